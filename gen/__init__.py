@@ -1,0 +1,184 @@
+"""Seeded synthetic inputs (graphs, initial forests, update batches).
+
+Thin ctypes wrapper over ``gen.c``.  Nothing here computes any part of the
+spanning-forest update: it draws random numbers, builds edge sets, converts
+them to CSR, runs a breadth-first search for the initial forest and samples
+update batches.  The CPU oracle and the GPU path both take these outputs.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gen.c")
+_LIB_PATH = os.path.join(_HERE, "libdrsfgen.so")
+_lib = None
+
+# purposes for seed derivation
+P_GRAPH, P_FOREST, P_INSERT, P_DELETE, P_STREAM = 1, 2, 3, 4, 5
+
+
+def build(force: bool = True) -> str:
+    """Compile the generator library in-tree with gcc."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-Wall", "-Wno-unused-function", _SRC, "-o", tmp])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build(force=False)
+    lib = ctypes.CDLL(_LIB_PATH)
+    u64, i64, i32, vp, dbl = (ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32,
+                              ctypes.c_void_p, ctypes.c_double)
+    lib.drsfgen_seed.restype = u64
+    lib.drsfgen_seed.argtypes = [u64, u64, u64]
+    lib.drsfgen_splitmix64.restype = u64
+    lib.drsfgen_splitmix64.argtypes = [u64]
+    lib.drsfgen_gnm.restype = i64
+    lib.drsfgen_gnm.argtypes = [i32, i64, u64, vp]
+    lib.drsfgen_rmat.restype = i64
+    lib.drsfgen_rmat.argtypes = [ctypes.c_int, i64, dbl, dbl, dbl, u64, vp]
+    lib.drsfgen_grid.restype = i64
+    lib.drsfgen_grid.argtypes = [i32, i32, i64, u64, vp]
+    lib.drsfgen_keys_to_csr.restype = None
+    lib.drsfgen_keys_to_csr.argtypes = [i32, vp, i64, vp, vp]
+    lib.drsfgen_bfs_forest.restype = None
+    lib.drsfgen_bfs_forest.argtypes = [i32, vp, vp, vp]
+    lib.drsfgen_insert_batches.restype = i64
+    lib.drsfgen_insert_batches.argtypes = [i32, vp, i64, i64, i64, u64, vp]
+    lib.drsfgen_delete_batches.restype = i64
+    lib.drsfgen_delete_batches.argtypes = [i32, vp, i64, vp, i64, i64, i64, u64, vp]
+    lib.drsfgen_uniform.restype = None
+    lib.drsfgen_uniform.argtypes = [u64, i64, vp]
+    lib.drsfgen_below.restype = None
+    lib.drsfgen_below.argtypes = [u64, i64, u64, vp]
+    lib.drsfgen_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _p(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def seed(config_id: int, instance: int, purpose: int) -> int:
+    return int(_load().drsfgen_seed(config_id, instance, purpose))
+
+
+def splitmix64(x: int) -> int:
+    return int(_load().drsfgen_splitmix64(x & (2**64 - 1)))
+
+
+def uniform(s: int, count: int) -> np.ndarray:
+    out = np.empty(count, dtype=np.float64)
+    _load().drsfgen_uniform(s, count, _p(out))
+    return out
+
+
+def below(s: int, count: int, bound: int) -> np.ndarray:
+    out = np.empty(count, dtype=np.uint64)
+    _load().drsfgen_below(s, count, bound, _p(out))
+    return out
+
+
+def gnm(n: int, m: int, s: int) -> np.ndarray:
+    keys = np.empty(max(m, 1), dtype=np.uint64)
+    got = _load().drsfgen_gnm(n, m, s, _p(keys))
+    if got < 0:
+        raise ValueError(f"G(n={n}, m={m}) infeasible")
+    return keys[:got]
+
+
+def rmat(scale: int, edge_factor: int, a: float, b: float, c: float, s: int) -> np.ndarray:
+    samples = edge_factor << scale
+    keys = np.empty(samples, dtype=np.uint64)
+    got = _load().drsfgen_rmat(scale, samples, a, b, c, s, _p(keys))
+    if got < 0:
+        raise ValueError("bad R-MAT parameters")
+    return keys[:got].copy()
+
+
+def grid(rows: int, cols: int, n_remove: int, s: int) -> np.ndarray:
+    total = rows * (cols - 1) + (rows - 1) * cols
+    keys = np.empty(total, dtype=np.uint64)
+    got = _load().drsfgen_grid(rows, cols, n_remove, s, _p(keys))
+    if got < 0:
+        raise ValueError("bad grid parameters")
+    return keys[:got].copy()
+
+
+def keys_to_csr(n: int, keys: np.ndarray):
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    row_ptr = np.empty(n + 1, dtype=np.int64)
+    col = np.empty(max(2 * len(keys), 1), dtype=np.int32)
+    _load().drsfgen_keys_to_csr(n, _p(keys), len(keys), _p(row_ptr), _p(col))
+    return row_ptr, col[: 2 * len(keys)]
+
+
+def bfs_forest(n: int, row_ptr: np.ndarray, col: np.ndarray) -> np.ndarray:
+    parent = np.empty(n, dtype=np.int32)
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    _load().drsfgen_bfs_forest(n, _p(row_ptr), _p(col), _p(parent))
+    return parent
+
+
+def insert_batches(n: int, keys: np.ndarray, nb: int, b: int, s: int) -> np.ndarray:
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    out = np.empty((nb, b, 2), dtype=np.int32)
+    if nb * b and _load().drsfgen_insert_batches(n, _p(keys), len(keys), nb, b, s, _p(out)) < 0:
+        raise ValueError("not enough non-edges")
+    return out
+
+
+def delete_batches(n: int, keys: np.ndarray, parent: np.ndarray, nb: int, b: int,
+                   n_tree: int, s: int) -> np.ndarray:
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    parent = np.ascontiguousarray(parent, dtype=np.int32)
+    out = np.empty((nb, b, 2), dtype=np.int32)
+    if nb * b and _load().drsfgen_delete_batches(n, _p(keys), len(keys), _p(parent), nb, b,
+                                                 n_tree, s, _p(out)) < 0:
+        raise ValueError("not enough edges to delete")
+    return out
+
+
+@dataclass
+class Graph:
+    """An undirected simple graph with its canonical initial forest."""
+    name: str
+    n: int
+    keys: np.ndarray              # sorted unique uint64 keys (u << 32 | v, u < v)
+    row_ptr: np.ndarray           # int64[n + 1], symmetric CSR
+    col: np.ndarray               # int32[2m], ascending rows
+    parent: np.ndarray            # int32[n], BFS forest, roots point to themselves
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def m(self) -> int:
+        return len(self.keys)
+
+
+def make_graph(name: str, n: int, keys: np.ndarray, **meta) -> Graph:
+    row_ptr, col = keys_to_csr(n, keys)
+    parent = bfs_forest(n, row_ptr, col)
+    return Graph(name, n, keys, row_ptr, col, parent, dict(meta))
+
+
+def keys_of_edges(edges: np.ndarray) -> np.ndarray:
+    """Normalised uint64 keys of an int32 [..., 2] pair array."""
+    e = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
+    lo = np.minimum(e[:, 0], e[:, 1]).astype(np.uint64)
+    hi = np.maximum(e[:, 0], e[:, 1]).astype(np.uint64)
+    return (lo << np.uint64(32)) | hi
