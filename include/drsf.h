@@ -1,0 +1,179 @@
+/*
+ * drsf.h — batch-dynamic rooted spanning forest (D-RSF) on AMD MI355X (gfx950).
+ *
+ * C ABI of libdrsf.so.  Plain pointers and sizes only.
+ *
+ * The problem (D-RSF box, Sec. I of "Fully Dynamic Rooted Spanning Tree on
+ * GPU"): given an undirected graph G, a rooted spanning forest F of G, a
+ * batch B of edges and op in {insert, delete}, produce a rooted spanning
+ * forest F' of G' = G + B (insert) or G - B (delete).  The library keeps G
+ * and F resident in device memory across calls and repairs F instead of
+ * rebuilding it (Algorithm 1): every tree edge that survives the batch stays
+ * in F' (Theorem 1).
+ *
+ * Deterministic rules, so that results are reproducible bit for bit:
+ *   - replacement edges: among the cross edges (Sec. II-A) the lowest key
+ *     (min(u,v), max(u,v)) hooks two trees, i.e. the replacement edges are
+ *     the Kruskal choice in increasing key order on top of F - B;
+ *   - roots: every tree is rooted at the smallest vertex id of its
+ *     component, and a root is its own parent (parent[r] == r, as in the
+ *     cut step of Algorithm 1).
+ * label[v] is the root of v's tree, i.e. the smallest vertex of v's
+ * connected component; the same call therefore also maintains connected
+ * components under insertions and deletions (Sec. I, contributions).
+ *
+ * Conventions for every call:
+ *   - vertex ids are 0-based int32 in [0, n); n < 2^31;
+ *   - inputs are owned by the caller and copied; nothing is retained;
+ *   - "host" pointers are ordinary CPU memory, "device" pointers are HIP
+ *     device memory on the context's device; which one an input is follows
+ *     drsf_opts.inputs_on_device;
+ *   - outputs exposed through drsf_view are device memory owned by the
+ *     context, valid until the next drsf_apply / drsf_restore / drsf_destroy
+ *     on that context;
+ *   - all device work is queued on drsf_opts.stream (NULL: a stream owned by
+ *     the context);
+ *   - every call returns a drsf_status; on failure drsf_last_error() gives a
+ *     message, and a rejected batch leaves the state unchanged;
+ *   - one context must not be used from two host threads at once; distinct
+ *     contexts are independent.
+ */
+#ifndef DRSF_H
+#define DRSF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { DRSF_INSERT = 0, DRSF_DELETE = 1 } drsf_op;
+
+typedef enum {
+    DRSF_OK = 0,
+    DRSF_E_ARG = -1,      /* bad argument (null pointer, negative size, bad CSR) */
+    DRSF_E_NOMEM = -2,    /* device or host allocation failed */
+    DRSF_E_FOREST = -3,   /* create: parent[] is not a rooted spanning forest of G */
+    DRSF_E_BATCH = -4,    /* apply: invalid batch (self-loop, id out of range,
+                             repeated edge, insert of an existing edge, delete of a
+                             missing edge); nothing was changed */
+    DRSF_E_CAPACITY = -5, /* batch larger than drsf_opts.max_batch, or graph too large */
+    DRSF_E_DEVICE = -6,   /* HIP runtime error, or an internal bound was exceeded */
+    DRSF_E_STATE = -7     /* call not valid in the context's current state */
+} drsf_status;
+
+typedef struct drsf_ctx drsf_ctx;
+
+typedef struct {
+    void *stream;            /* hipStream_t for all device work; NULL = context-owned */
+    int inputs_on_device;    /* 0: CSR/parent/batch pointers are host memory;
+                                1: they are device memory */
+    int validate_forest;     /* create: 1 (default) checks that parent[] is a rooted
+                                spanning forest whose trees span G's components */
+    int profile;             /* 1: time each phase of apply with events
+                                (drsf_phase_times); adds synchronisation */
+    int64_t max_batch;       /* largest batch accepted by apply; 0 = 1 << 20 */
+    int64_t delta_capacity;  /* inserted edges held before the edge store is
+                                rebuilt; 0 = automatic */
+} drsf_opts;
+
+/* Fills *opts with the defaults described above. */
+void drsf_default_opts(drsf_opts *opts);
+
+/*
+ * Result of the last apply.  parent and label are DEVICE pointers owned by
+ * the context (int32[n]).  Counters describe the last batch: num_key_cross
+ * is the number of cross edges found among the key edges (Sec. II-A),
+ * num_replacement = |E_r| = k - l (Theorem 1), num_pieces the trees of
+ * F-hat that the batch touched, num_paths the reversed paths (Algorithm 1,
+ * ReversePaths).
+ */
+typedef struct {
+    const int32_t *parent;
+    const int32_t *label;
+    int32_t n;
+    int64_t num_edges;        /* |E(G')| */
+    int64_t num_key_cross;
+    int64_t num_replacement;
+    int64_t num_pieces;
+    int64_t num_paths;
+} drsf_view;
+
+/*
+ * Creates a context from G and F.
+ *   n        number of vertices (>= 1)
+ *   row_ptr  int64[n + 1], symmetric CSR offsets of G (row_ptr[0] == 0)
+ *   col      int32[row_ptr[n]], neighbours; every row strictly ascending,
+ *            no self-loops, and (u,v) present iff (v,u) present
+ *   parent   int32[n], a rooted spanning forest of G (parent[r] == r for
+ *            roots) whose trees span the connected components of G — the
+ *            precondition the insert path of Algorithm 1 relies on
+ *   opts     may be NULL (defaults)
+ * Trees whose root is not their smallest vertex are re-rooted there.
+ * Errors: DRSF_E_ARG (bad CSR), DRSF_E_FOREST (parent invalid; checked when
+ * validate_forest is set), DRSF_E_NOMEM, DRSF_E_DEVICE.  *out is NULL on error.
+ */
+int drsf_create(int32_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *parent,
+                const drsf_opts *opts, drsf_ctx **out);
+
+/*
+ * Applies one batch (Algorithm 1): edges holds b pairs (u, v) interleaved,
+ * int32[2b], in either orientation; op is DRSF_INSERT or DRSF_DELETE.
+ * Blocks until the result is final on the device and fills *out (may be
+ * NULL).  b == 0 is a no-op.  Errors: DRSF_E_BATCH (state unchanged),
+ * DRSF_E_CAPACITY (b > max_batch), DRSF_E_ARG, DRSF_E_DEVICE.
+ */
+int drsf_apply(drsf_ctx *ctx, const int32_t *edges, int64_t b, int op, drsf_view *out);
+
+/*
+ * Queues the same work as drsf_apply on the context's stream and returns
+ * without waiting.  The batch is copied into the context before return.
+ * Call drsf_wait before reading results or queueing host reads; device work
+ * queued later on the same stream is ordered after it.
+ */
+int drsf_apply_async(drsf_ctx *ctx, const int32_t *edges, int64_t b, int op);
+
+/* Waits for queued work and returns the status of the last queued apply. */
+int drsf_wait(drsf_ctx *ctx, drsf_view *out);
+
+/* Copies parent and/or label (either may be NULL) to host int32[n]. */
+int drsf_copy_out(drsf_ctx *ctx, int32_t *parent_host, int32_t *label_host);
+
+/* Current view without applying anything. */
+int drsf_get_view(drsf_ctx *ctx, drsf_view *out);
+
+/*
+ * Number of edges of the current graph, and its edges as sorted keys
+ * (min << 32 | max) in host memory (capacity >= drsf_num_edges).  Together
+ * with drsf_copy_out this is a checkpoint that drsf_create can resume from.
+ */
+int64_t drsf_num_edges(drsf_ctx *ctx);
+int drsf_export_edges(drsf_ctx *ctx, uint64_t *keys_host, int64_t capacity, int64_t *m_out);
+
+/* Device-side copy of the whole state; restore returns to it exactly. */
+typedef struct drsf_snapshot drsf_snapshot;
+int drsf_snapshot_take(drsf_ctx *ctx, drsf_snapshot **out);
+int drsf_snapshot_restore(drsf_ctx *ctx, const drsf_snapshot *snap);
+void drsf_snapshot_free(drsf_snapshot *snap);
+
+/*
+ * Per-phase device times of the last apply in milliseconds (needs
+ * opts.profile): validate, update-graph, cut+root-finding, key-edge sweep,
+ * replacement edges, super-forest rooting, path reversal, labels.  Returns
+ * the number of phases written (<= cap).
+ */
+int drsf_phase_times(drsf_ctx *ctx, float *ms, int cap);
+
+void drsf_destroy(drsf_ctx *ctx);
+
+/* Message for the last error on ctx (ctx may be NULL for create errors). */
+const char *drsf_last_error(const drsf_ctx *ctx);
+
+/* Library version string. */
+const char *drsf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DRSF_H */

@@ -1,0 +1,114 @@
+// Internal interface between the host API and the D-RSF kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "drsf_dev.h"
+
+namespace drsf {
+
+// All device pointers one apply needs; passed by value to every kernel.
+struct Dev {
+    int32_t n;
+    int32_t op;              // 0 insert, 1 delete
+    // edge store: upper-half base CSR (row u holds v > u, ascending; TOMB bit =
+    // deleted) plus a list of inserted edges with a hash index
+    const uint32_t *bptr;    // [n + 1]
+    int32_t *bcol;           // [eb]
+    int64_t eb;
+    const int32_t *tile_row; // [ntiles + 1] row holding the first edge of each sweep tile
+    int64_t ntiles;
+    uint64_t *dkey;          // [dcap] inserted edge keys, KEY_DEAD when deleted
+    int64_t dcap;
+    uint64_t *dhash;         // [dhmask + 1] key -> slot, HASH_TOMB_BIT marks a deleted key
+    int32_t *dhpos;          // [dhmask + 1] slot -> index in dkey
+    uint64_t dhmask;
+    // forest
+    int32_t *parent;         // [n]
+    int32_t *label;          // [n] root of the vertex's tree = smallest vertex of its component
+    int32_t *rep;            // [n] root of the vertex's tree in F-hat (delete scratch)
+    const int32_t *repv;     // rep (delete) or label (insert: F-hat = F)
+    uint64_t *obits;         // [ceil(n/64)] vertex lies in a piece cut off from its old root
+    // touched pieces (trees of F-hat incident to the batch), dense ids
+    int32_t *tidx;           // [n] piece root vertex -> dense id, NONE when idle
+    int32_t *prt;            // [pcap] dense id -> piece root vertex
+    int32_t *pmin;           // [pcap] smallest vertex of the piece
+    int32_t *comp;           // [pcap] current component (a dense piece id)
+    int32_t *hook;           // [pcap] component this one hooked onto in the current round
+    uint64_t *best;          // [pcap] lowest key of a cross edge leaving the component
+    uint64_t *srkey;         // [pcap] (smallest vertex << 32 | piece) of the component
+    int32_t *head;           // [pcap] first arc of the piece's super-forest arc list
+    int32_t *newlab;         // [pcap] new label of the component
+    int64_t pcap;
+    // batch
+    const int32_t *bedges;   // [2b]
+    int64_t b;
+    uint64_t *bkey;          // [b] normalised key
+    int64_t *bloc;           // [b] >= 0: position in bcol; < 0: -(hash slot + 1)
+    int32_t *bchild;         // [b] child endpoint of a deleted tree edge, NONE otherwise
+    int32_t *bslot;          // [b] slot claimed in the batch duplicate table
+    uint64_t *bhash;         // [bhmask + 1]
+    uint64_t bhmask;
+    // cross-edge lists (double-buffered between replacement-edge rounds)
+    Cross *x0, *x1;
+    int64_t xcap;
+    // replacement edges and super-forest arcs
+    int4 *er;                // [ercap] (x, y, piece of x, piece of y)
+    int64_t ercap;
+    int32_t *arc_nxt;        // [2 ercap]
+    int32_t *succ0, *succ1;  // [2 ercap]
+    int32_t *rank0, *rank1;  // [2 ercap]
+    PathReq *paths;          // [pathcap]
+    int64_t pathcap;
+    // control
+    int32_t *status;
+    unsigned long long *cnt; // [C_COUNT + 2 * MAX_ROUNDS]
+};
+
+constexpr int MAX_ROUNDS = 64;
+// extra counter slots: per-round activity flags
+constexpr int C_BOR_ROUND = C_COUNT;               // [MAX_ROUNDS]
+constexpr int C_LR_ROUND = C_COUNT + MAX_ROUNDS;   // [MAX_ROUNDS]
+constexpr int C_TOTAL = C_COUNT + 2 * MAX_ROUNDS;
+constexpr int C_LR_FINAL = 12;
+
+// launchers (drsf_kernels.hip)
+void launch_classify(const Dev &d, hipStream_t s);
+void launch_prepare(const Dev &d, hipStream_t s);
+void launch_insert_emit(const Dev &d, hipStream_t s);
+void launch_rep(const Dev &d, hipStream_t s);
+void launch_sweep(const Dev &d, int64_t ndelta_bound, hipStream_t s);
+void launch_boruvka(const Dev &d, int rounds, hipStream_t s);
+void launch_superforest(const Dev &d, int lr_rounds, hipStream_t s);
+void launch_reverse(const Dev &d, hipStream_t s);
+void launch_labels(const Dev &d, hipStream_t s);
+void launch_cleanup(const Dev &d, hipStream_t s);
+
+// create-time helpers
+void launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t s);
+void launch_fill_u64(uint64_t *p, int64_t count, uint64_t v, hipStream_t s);
+inline void launch_fill_u64(unsigned long long *p, int64_t count, uint64_t v, hipStream_t s) {
+    launch_fill_u64(reinterpret_cast<uint64_t *>(p), count, v, s);
+}
+void launch_csr_check(int32_t n, const int64_t *row_ptr, const int32_t *col, uint32_t *ucnt,
+                      int32_t *status, hipStream_t s);
+void launch_csr_symmetric(int32_t n, const int64_t *row_ptr, const int32_t *col,
+                          int32_t *status, hipStream_t s);
+// exclusive scan of n uint32 counts into out[n + 1] (uint64 total in out64, may overflow uint32)
+void launch_scan_u32(const uint32_t *in, uint32_t *out, unsigned long long *total, int64_t n,
+                     void *tmp, hipStream_t s);
+size_t scan_tmp_bytes(int64_t n);
+void launch_upper_fill(int32_t n, const int64_t *row_ptr, const int32_t *col,
+                       const uint32_t *bptr, int32_t *bcol, hipStream_t s);
+void launch_tile_rows(int32_t n, const uint32_t *bptr, int64_t eb, int32_t *tile_row,
+                      int64_t ntiles, hipStream_t s);
+void launch_forest_check(int32_t n, const uint32_t *bptr, const int32_t *bcol,
+                         const int32_t *parent, int32_t *status, int check_edges, hipStream_t s);
+void launch_pointer_jump(int32_t n, const int32_t *in, int32_t *out, hipStream_t s);
+void launch_roots_check(int32_t n, const int32_t *parent, const int32_t *root,
+                        int32_t *status, hipStream_t s);
+void launch_span_check(const Dev &d, const int32_t *root, hipStream_t s);
+void launch_tree_min(int32_t n, const int32_t *root, int32_t *label, hipStream_t s);
+void launch_reroot_requests(const Dev &d, const int32_t *root, hipStream_t s);
+void launch_count_live_delta(const Dev &d, int64_t ndelta_bound, hipStream_t s);
+
+}  // namespace drsf

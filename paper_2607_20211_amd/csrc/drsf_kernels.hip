@@ -1,0 +1,1064 @@
+// D-RSF kernels for gfx950 (CDNA4, wave64).  One batch update follows
+// Algorithm 1 of "Fully Dynamic Rooted Spanning Tree on GPU":
+//   classify/validate -> update the edge store and cut deleted tree edges ->
+//   root finding (delete) -> key-edge sweep -> replacement edges by
+//   hooking rounds (Alg. 2, phase 1) -> super-forest rooting by an Euler
+//   tour with list ranking (Alg. 2, phase 2) -> path reversal and new parents
+//   (ReversePaths, Algorithm 1) -> component labels.
+// All integer work; no MFMA.  Every loop over device-side counts is a
+// grid-stride loop, every pointer chase is bounded by n and reports
+// ST_WALK_BOUND instead of spinning, and every kernel after validation is a
+// no-op when the status word is non-zero, so a rejected batch changes nothing.
+#include "drsf_kernels.h"
+
+namespace drsf {
+
+static inline int grid_for(int64_t items, int64_t per_block, int cap = 8192) {
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+// ------------------------------------------------------------------ helpers
+
+// Reserve `count` output slots per thread with one atomic per workgroup.
+// Every thread of the block must call it.
+__device__ int64_t block_reserve(int count, unsigned long long *counter) {
+    __shared__ int wsum[BLOCK / WAVE];
+    __shared__ unsigned long long base;
+    const int lane = lane_id(), wid = threadIdx.x / WAVE;
+    int x = count;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == WAVE - 1) wsum[wid] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < BLOCK / WAVE; w++) {
+            int s = wsum[w];
+            wsum[w] = t;
+            t += s;
+        }
+        base = t ? atomicAdd(counter, (unsigned long long)t) : 0ull;
+    }
+    __syncthreads();
+    int64_t r = (int64_t)base + wsum[wid] + x - count;
+    __syncthreads();
+    return r;
+}
+
+// position of v in the ascending (masked) run bcol[lo, hi), or -1
+__device__ __forceinline__ int64_t find_in_row(const int32_t *bcol, uint32_t lo, uint32_t hi,
+                                               int32_t v) {
+    uint32_t a = lo, b = hi;
+    while (a < b) {
+        uint32_t mid = a + ((b - a) >> 1);
+        if ((bcol[mid] & COLMASK) < v) a = mid + 1; else b = mid;
+    }
+    return (a < hi && (bcol[a] & COLMASK) == v) ? (int64_t)a : -1;
+}
+
+// slot holding live key k in the inserted-edge index, or -1
+__device__ int64_t dhash_find(const Dev &d, uint64_t k) {
+    uint64_t h = hmix(k) & d.dhmask;
+    for (uint64_t probe = 0; probe <= d.dhmask; probe++) {
+        uint64_t s = d.dhash[h];
+        if (s == HASH_EMPTY) return -1;
+        if (s == k) return (int64_t)h;
+        h = (h + 1) & d.dhmask;
+    }
+    return -1;
+}
+
+// insert key k (not live in the index) pointing at list position pos
+__device__ void dhash_insert(const Dev &d, uint64_t k, int32_t pos) {
+    uint64_t h = hmix(k) & d.dhmask;
+    for (uint64_t probe = 0; probe <= 2 * d.dhmask + 2; probe++) {
+        uint64_t s = d.dhash[h];
+        if (s == HASH_EMPTY || s == (k | HASH_TOMB_BIT)) {
+            uint64_t old = atomicCAS((unsigned long long *)&d.dhash[h], (unsigned long long)s,
+                                     (unsigned long long)k);
+            if (old == s) {
+                d.dhpos[h] = pos;
+                return;
+            }
+            continue;  // lost a race for this slot: look at it again
+        }
+        h = (h + 1) & d.dhmask;
+    }
+    atomicOr(d.status, ST_CAPACITY);
+}
+
+__device__ __forceinline__ bool obit(const uint64_t *bits, int32_t v) {
+    return (bits[v >> 6] >> (v & 63)) & 1;
+}
+
+__device__ __forceinline__ void init_piece(const Dev &d, int64_t id, int32_t v) {
+    d.prt[id] = v;
+    d.pmin[id] = v;
+    d.comp[id] = (int32_t)id;
+    d.hook[id] = NONE;
+    d.best[id] = KEY_INF;
+    d.srkey[id] = KEY_INF;
+    d.head[id] = NONE;
+    d.newlab[id] = v;
+    __threadfence();
+    d.tidx[v] = (int32_t)id;
+}
+
+// Register the trees of F-hat rooted at a and b as touched pieces (dense ids).
+__device__ void claim_two(const Dev &d, bool want, int32_t a, int32_t b) {
+    bool ga = want && atomicCAS(&d.tidx[a], NONE, CLAIMING) == NONE;
+    bool gb = want && a != b && atomicCAS(&d.tidx[b], NONE, CLAIMING) == NONE;
+    int64_t ia = wave_append(ga, &d.cnt[C_NP]);
+    int64_t ib = wave_append(gb, &d.cnt[C_NP]);
+    if (ga) init_piece(d, ia, a);
+    if (gb) init_piece(d, ib, b);
+}
+
+// -------------------------------------------------- a1: validate + classify
+
+// Normalise each pair, reject self-loops, out-of-range ids and pairs
+// repeated inside the batch, check presence against the edge store (insert:
+// must be absent; delete: must be present) and, for deletes, find the child
+// endpoint of a tree edge (parent[u] == v or parent[v] == u; Algorithm 1,
+// the cut step).  Writes only batch scratch and the status word.
+__global__ __launch_bounds__(BLOCK) void k_classify(Dev d) {
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < d.b; i += stride) {
+        int32_t u = d.bedges[2 * i], v = d.bedges[2 * i + 1];
+        d.bslot[i] = NONE;
+        d.bchild[i] = NONE;
+        d.bloc[i] = 0;
+        if (u < 0 || v < 0 || u >= d.n || v >= d.n || u == v) {
+            atomicOr(d.status, ST_BAD_PAIR);
+            d.bkey[i] = 0;
+            continue;
+        }
+        const uint64_t k = mkkey((uint32_t)u, (uint32_t)v);
+        d.bkey[i] = k;
+        const int32_t lo = key_lo(k), hi = key_hi(k);
+        // repeated pair inside the batch
+        uint64_t h = hmix(k) & d.bhmask;
+        for (uint64_t probe = 0; probe <= d.bhmask; probe++) {
+            uint64_t s = d.bhash[h];
+            if (s == HASH_EMPTY) {
+                s = atomicCAS((unsigned long long *)&d.bhash[h], (unsigned long long)HASH_EMPTY,
+                              (unsigned long long)k);
+                if (s == HASH_EMPTY) { d.bslot[i] = (int32_t)h; break; }
+            }
+            if (s == k) { atomicOr(d.status, ST_DUPLICATE); break; }
+            h = (h + 1) & d.bhmask;
+        }
+        // presence
+        int64_t pos = find_in_row(d.bcol, d.bptr[lo], d.bptr[lo + 1], hi);
+        int64_t loc;
+        bool present;
+        if (pos >= 0 && d.bcol[pos] >= 0) {
+            present = true;
+            loc = pos;
+        } else {
+            int64_t slot = dhash_find(d, k);
+            present = slot >= 0;
+            loc = -(slot + 1);
+        }
+        if (d.op == 0) {
+            if (present) atomicOr(d.status, ST_EXISTS);
+        } else {
+            if (!present) {
+                atomicOr(d.status, ST_MISSING);
+            } else {
+                d.bloc[i] = loc;
+                int32_t c = d.parent[lo] == hi ? lo : (d.parent[hi] == lo ? hi : NONE);
+                d.bchild[i] = c;
+            }
+        }
+    }
+}
+
+// ---------------------------- a2 + a3: update the edge store, cut tree edges
+
+__global__ __launch_bounds__(BLOCK) void k_prepare(Dev d) {
+    if (*d.status) return;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < d.b; base += stride) {
+        const int64_t i = base + threadIdx.x;
+        const bool valid = i < d.b;
+        if (d.op == 1) {
+            int32_t c = NONE, lc = NONE;
+            if (valid) {
+                const int64_t loc = d.bloc[i];
+                if (loc >= 0) {
+                    d.bcol[loc] = d.bcol[loc] | TOMB;
+                } else {
+                    const int64_t slot = -loc - 1;
+                    d.dkey[d.dhpos[slot]] = KEY_DEAD;
+                    d.dhash[slot] = d.bkey[i] | HASH_TOMB_BIT;
+                }
+                c = d.bchild[i];
+                if (c != NONE) {
+                    d.parent[c] = c;  // Algorithm 1: parent[u] <- u
+                    lc = d.label[c];
+                }
+            }
+            // orphan piece rooted at c, and the piece that keeps the old root
+            claim_two(d, c != NONE, c, lc);
+        } else {
+            uint64_t k = valid ? d.bkey[i] : 0;
+            int64_t pos = wave_append(valid, &d.cnt[C_NDELTA]);
+            int32_t la = NONE, lb = NONE;
+            if (valid && pos >= d.dcap) {
+                atomicOr(d.status, ST_CAPACITY);
+            } else if (valid) {
+                d.dkey[pos] = k;
+                dhash_insert(d, k, (int32_t)pos);
+                la = d.label[key_lo(k)];
+                lb = d.label[key_hi(k)];
+            }
+            claim_two(d, valid && la != lb, la, lb);
+        }
+    }
+}
+
+// insert: key edges M = B; cross edges join two different trees (labels)
+__global__ __launch_bounds__(BLOCK) void k_insert_emit(Dev d) {
+    if (*d.status) return;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < d.b; base += stride) {
+        const int64_t i = base + threadIdx.x;
+        bool cross = false;
+        uint64_t k = 0;
+        int32_t la = 0, lb = 0;
+        if (i < d.b) {
+            k = d.bkey[i];
+            la = d.label[key_lo(k)];
+            lb = d.label[key_hi(k)];
+            cross = la != lb;
+        }
+        int64_t slot = wave_append(cross, &d.cnt[C_NX0]);
+        if (cross) {
+            Cross e;
+            e.key = k;
+            e.pa = d.tidx[la];
+            e.pb = d.tidx[lb];
+            d.x0[slot] = e;
+        }
+    }
+}
+
+// ----------------------------------------------- a4: root finding (delete)
+
+__global__ __launch_bounds__(BLOCK) void k_rep_init(Dev d) {
+    if (*d.status) return;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < d.n; v += stride)
+        d.rep[v] = d.parent[v];
+}
+
+// rep[v] <- root of v in F-hat.  Each thread chases rep[] upward; entries
+// already finished by other threads are roots, so chains shorten as the
+// sweep proceeds (pointer jumping, Algorithm 1).  Every value read is an
+// ancestor of the vertex, so stale reads only cost extra steps.  Also marks
+// vertices whose root is not their old root (they lie in a piece cut off by
+// the batch) in a bitmap, and the smallest vertex of each such piece.
+__global__ __launch_bounds__(BLOCK) void k_rep_chase(Dev d) {
+    if (*d.status) return;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < d.n; base += stride) {
+        const int64_t v = base + threadIdx.x;
+        bool orphan = false;
+        int32_t x = 0;
+        if (v < d.n) {
+            x = ld_relaxed(&d.rep[v]);
+            for (int64_t steps = 0;; steps++) {
+                int32_t y = ld_relaxed(&d.rep[x]);
+                if (y == x) break;
+                x = y;
+                if (steps > d.n) { atomicOr(d.status, ST_WALK_BOUND); break; }
+            }
+            d.rep[v] = x;
+            orphan = x != d.label[v];
+        }
+        uint64_t word = __ballot(orphan);
+        if (lane_id() == 0 && v < d.n) d.obits[v >> 6] = word;
+        if (orphan) {
+            const int32_t t = d.tidx[x];
+            if (t >= 0) min_i32(&d.pmin[t], (int32_t)v);
+            else atomicOr(d.status, ST_WALK_BOUND);
+        }
+    }
+}
+
+// ------------------------------------------- a5: key-edge sweep (delete)
+
+// Key edges of a delete are all surviving non-tree edges (Sec. II-A); an
+// edge is a cross edge iff rep differs at its ends.  An edge whose ends both
+// stay in their old root's piece has equal reps (its ends share a component
+// of G, hence a tree of F, hence that tree's root piece), so the rep gathers
+// are only made when the orphan bitmap flags an end.  One workgroup streams
+// TILE consecutive stored edges; rows are found from a per-tile start row.
+__global__ __launch_bounds__(BLOCK) void k_sweep_base(Dev d) {
+    if (*d.status) return;
+    const int64_t tile = blockIdx.x;
+    const int64_t e0 = tile * TILE + (int64_t)threadIdx.x * EPT;
+    uint32_t mask = 0;
+    int32_t c[EPT];
+    int32_t u0 = 0;
+    if (e0 < d.eb) {
+        // largest row r with bptr[r] <= e0, searched among the tile's rows
+        int32_t a = d.tile_row[tile], b = d.tile_row[tile + 1];
+        while (a < b) {
+            int32_t mid = a + ((b - a + 1) >> 1);
+            if ((int64_t)d.bptr[mid] <= e0) a = mid; else b = mid - 1;
+        }
+        u0 = a;
+        if (e0 + EPT <= d.eb) {
+            const int4 *p = reinterpret_cast<const int4 *>(d.bcol + e0);
+#pragma unroll
+            for (int q = 0; q < EPT / 4; q++) {
+                int4 t = p[q];
+                c[4 * q] = t.x; c[4 * q + 1] = t.y; c[4 * q + 2] = t.z; c[4 * q + 3] = t.w;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < EPT; j++) c[j] = (e0 + j < d.eb) ? d.bcol[e0 + j] : TOMB;
+        }
+        int32_t u = u0;
+        int64_t rend = d.bptr[u + 1];
+        bool ou = obit(d.obits, u);
+#pragma unroll
+        for (int j = 0; j < EPT; j++) {
+            const int64_t e = e0 + j;
+            if (e >= d.eb) break;
+            while (e >= rend) {
+                u++;
+                rend = d.bptr[u + 1];
+                ou = obit(d.obits, u);
+            }
+            const int32_t v = c[j];
+            if (v < 0) continue;  // deleted
+            if (ou || obit(d.obits, v)) {
+                if (d.rep[u] != d.rep[v]) mask |= 1u << j;
+            }
+        }
+    }
+    const int64_t out = block_reserve(__popc(mask), &d.cnt[C_NX0]);
+    if (mask) {
+        int32_t u = u0;
+        int64_t rend = d.bptr[u + 1];
+        int64_t w = out;
+#pragma unroll
+        for (int j = 0; j < EPT; j++) {
+            const int64_t e = e0 + j;
+            if (e >= d.eb) break;
+            while (e >= rend) { u++; rend = d.bptr[u + 1]; }
+            if (mask >> j & 1) {
+                const int32_t v = c[j];
+                Cross x;
+                x.key = ((uint64_t)(uint32_t)u << 32) | (uint32_t)v;
+                x.pa = d.tidx[d.rep[u]];
+                x.pb = d.tidx[d.rep[v]];
+                if (x.pa < 0 || x.pb < 0) atomicOr(d.status, ST_WALK_BOUND);
+                d.x0[w++] = x;
+            }
+        }
+    }
+}
+
+// the same test over the list of inserted edges
+__global__ __launch_bounds__(BLOCK) void k_sweep_delta(Dev d) {
+    if (*d.status) return;
+    const int64_t nd = (int64_t)d.cnt[C_NDELTA];
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < nd; base += stride) {
+        const int64_t i = base + threadIdx.x;
+        bool cross = false;
+        uint64_t k = 0;
+        int32_t ru = 0, rv = 0;
+        if (i < nd) {
+            k = d.dkey[i];
+            if (k != KEY_DEAD) {
+                const int32_t u = key_lo(k), v = key_hi(k);
+                if (obit(d.obits, u) || obit(d.obits, v)) {
+                    ru = d.rep[u];
+                    rv = d.rep[v];
+                    cross = ru != rv;
+                }
+            }
+        }
+        int64_t slot = wave_append(cross, &d.cnt[C_NX0]);
+        if (cross) {
+            Cross x;
+            x.key = k;
+            x.pa = d.tidx[ru];
+            x.pb = d.tidx[rv];
+            if (x.pa < 0 || x.pb < 0) atomicOr(d.status, ST_WALK_BOUND);
+            d.x0[slot] = x;
+        }
+    }
+}
+
+// ------------------------------- a6: replacement edges by hooking rounds
+
+// Round r, step 1: drop cross edges now inside one component; every
+// component takes the lowest key of the cross edges it touches (64-bit
+// atomic min).  Survivors are compacted into the other buffer.
+__global__ __launch_bounds__(BLOCK) void k_bor_select(Dev d, int r) {
+    if (*d.status || d.cnt[C_DONE_BOR]) return;
+    const Cross *in = (r & 1) ? d.x1 : d.x0;
+    Cross *out = (r & 1) ? d.x0 : d.x1;
+    const int64_t nin = (int64_t)d.cnt[C_NX0 + (r & 1)];
+    unsigned long long *cout = &d.cnt[C_NX0 + ((r + 1) & 1)];
+    const int64_t np = (int64_t)d.cnt[C_NP];
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    if (r == 0 && blockIdx.x == 0 && threadIdx.x == 0) d.cnt[C_NCROSS] = (unsigned long long)nin;
+    for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < np; p += stride)
+        d.hook[p] = NONE;
+    for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < nin; base += stride) {
+        const int64_t i = base + threadIdx.x;
+        bool live = false;
+        Cross e;
+        if (i < nin) {
+            e = in[i];
+            const int32_t ca = d.comp[e.pa], cb = d.comp[e.pb];
+            live = ca != cb;
+            if (live) {
+                min_key(&d.best[ca], e.key);
+                min_key(&d.best[cb], e.key);
+                e.pa = ca;
+                e.pb = cb;
+            }
+        }
+        const int64_t o = block_reserve(live ? 1 : 0, cout);
+        if (live) out[o] = e;
+    }
+}
+
+// Step 2: each component hooks onto the component across its lowest-key
+// edge; when two components pick the same edge the smaller id stays a root.
+// Distinct keys make the chosen edges a forest (Boruvka), and each is the
+// lowest key leaving its component, so the union equals the Kruskal choice.
+__global__ __launch_bounds__(BLOCK) void k_bor_hook(Dev d, int r) {
+    if (*d.status || d.cnt[C_DONE_BOR]) return;
+    const int64_t nout = (int64_t)d.cnt[C_NX0 + ((r + 1) & 1)];
+    if (nout == 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) d.cnt[C_DONE_BOR] = 1;
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.cnt[C_NX0 + (r & 1)] = 0;
+    const int64_t np = (int64_t)d.cnt[C_NP];
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < np; base += stride) {
+        const int64_t p = base + threadIdx.x;
+        bool rec = false;
+        int4 er;
+        if (p < np && d.comp[p] == (int32_t)p) {
+            const uint64_t k = d.best[p];
+            if (k != KEY_INF) {
+                const int32_t x = key_lo(k), y = key_hi(k);
+                const int32_t px = d.tidx[d.repv[x]], py = d.tidx[d.repv[y]];
+                if (px < 0 || py < 0) {
+                    atomicOr(d.status, ST_WALK_BOUND);
+                } else {
+                const int32_t cx = d.comp[px], cy = d.comp[py];
+                const int32_t other = (cx == (int32_t)p) ? cy : cx;
+                if (!(d.best[other] == k && (int32_t)p < other)) {
+                    d.hook[p] = other;
+                    rec = true;
+                    er = make_int4(x, y, px, py);
+                }
+                }
+            }
+        }
+        const int64_t slot = wave_append(rec, &d.cnt[C_NER]);
+        if (rec) d.er[slot] = er;
+    }
+}
+
+// Step 3: every piece follows the hooks of this round to its new component.
+__global__ __launch_bounds__(BLOCK) void k_bor_compress(Dev d, int r) {
+    if (*d.status || d.cnt[C_DONE_BOR]) return;
+    const int64_t np = (int64_t)d.cnt[C_NP];
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < np; p += stride) {
+        int32_t x = d.comp[p];
+        for (int64_t steps = 0;; steps++) {
+            const int32_t h = ld_relaxed(&d.hook[x]);
+            if (h == NONE) break;
+            x = h;
+            if (steps > np) { atomicOr(d.status, ST_WALK_BOUND); break; }
+        }
+        d.comp[p] = x;
+        d.best[p] = KEY_INF;
+    }
+}
+
+// ------------------------------------- a7: super-forest rooting (Euler tour)
+
+// Super-root of each merged component: the piece holding its smallest
+// vertex (insert: the tree with the smallest root; delete: the piece that
+// kept the old root when present, since that root is the component's
+// minimum).  Arc lists of the super-forest: every replacement edge between
+// pieces P and Q gives arcs P->Q (2i) and Q->P (2i+1).
+__global__ __launch_bounds__(BLOCK) void k_sf_init(Dev d) {
+    if (*d.status) return;
+    if (!d.cnt[C_DONE_BOR]) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(d.status, ST_ROUND_BOUND);
+        return;
+    }
+    const int64_t np = (int64_t)d.cnt[C_NP];
+    const int64_t ner = (int64_t)d.cnt[C_NER];
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < np; p += stride)
+        atomicMin((unsigned long long *)&d.srkey[d.comp[p]],
+                  (unsigned long long)(((uint64_t)(uint32_t)d.pmin[p] << 32) | (uint64_t)p));
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < ner; i += stride) {
+        const int4 e = d.er[i];
+        d.arc_nxt[2 * i] = atomicExch(&d.head[e.z], (int32_t)(2 * i));
+        d.arc_nxt[2 * i + 1] = atomicExch(&d.head[e.w], (int32_t)(2 * i + 1));
+    }
+}
+
+// Euler tour successor: after arc P->Q comes the arc following Q->P in Q's
+// cyclic arc list.  The tour of each component is cut open at its super-root.
+__global__ __launch_bounds__(BLOCK) void k_sf_succ(Dev d) {
+    if (*d.status) return;
+    const int64_t na = 2 * (int64_t)d.cnt[C_NER];
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t a = (int64_t)blockIdx.x * BLOCK + threadIdx.x; a < na; a += stride) {
+        const int4 e = d.er[a >> 1];
+        const int32_t q = (a & 1) ? e.z : e.w;  // target piece of arc a
+        int32_t s = d.arc_nxt[a ^ 1];
+        const int32_t hq = d.head[q];
+        if (s == NONE) s = hq;
+        const int32_t S = (int32_t)(uint32_t)d.srkey[d.comp[q]];
+        if (q == S && s == hq) s = NONE;
+        d.succ0[a] = s;
+        d.rank0[a] = s == NONE ? 0 : 1;
+    }
+}
+
+// List ranking by pointer jumping (Wyllie): rank = arcs left until the end
+// of the tour.  Double-buffered; round r reads buffer r&1.
+__global__ __launch_bounds__(BLOCK) void k_lr_round(Dev d, int r) {
+    if (*d.status || d.cnt[C_DONE_LR]) return;
+    if (r > 0 && d.cnt[C_LR_ROUND + r - 1] == 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            d.cnt[C_LR_FINAL] = (unsigned long long)(r & 1);
+            d.cnt[C_DONE_LR] = 1;
+        }
+        return;
+    }
+    const int32_t *si = (r & 1) ? d.succ1 : d.succ0;
+    const int32_t *ri = (r & 1) ? d.rank1 : d.rank0;
+    int32_t *so = (r & 1) ? d.succ0 : d.succ1;
+    int32_t *ro = (r & 1) ? d.rank0 : d.rank1;
+    const int64_t na = 2 * (int64_t)d.cnt[C_NER];
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    bool active = false;
+    for (int64_t a = (int64_t)blockIdx.x * BLOCK + threadIdx.x; a < na; a += stride) {
+        const int32_t s = si[a];
+        if (s != NONE) {
+            const int32_t s2 = si[s];
+            ro[a] = ri[a] + ri[s];
+            so[a] = s2;
+            active |= s2 != NONE;
+        } else {
+            ro[a] = ri[a];
+            so[a] = NONE;
+        }
+    }
+    if (__ballot(active) && lane_id() == 0) d.cnt[C_LR_ROUND + r] = 1;
+}
+
+// Orientation: of the two arcs of a replacement edge the one met first in the
+// tour (larger rank) points from parent piece to child piece.  The child
+// piece's path from the edge's endpoint to its root is reversed and the
+// endpoint takes the other end as parent (Algorithm 1, R and new parents).
+// A super-root piece whose root is not the component's smallest vertex m is
+// re-rooted at m.  The component's new label is m.
+__global__ __launch_bounds__(BLOCK) void k_orient(Dev d, int lr_rounds) {
+    if (*d.status) return;
+    const int64_t ner = (int64_t)d.cnt[C_NER];
+    const int64_t np = (int64_t)d.cnt[C_NP];
+    int fin;
+    if (d.cnt[C_DONE_LR]) {
+        fin = (int)d.cnt[C_LR_FINAL];
+    } else {
+        if (ner > 0 && d.cnt[C_LR_ROUND + lr_rounds - 1] != 0) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(d.status, ST_ROUND_BOUND);
+            return;
+        }
+        fin = lr_rounds & 1;
+    }
+    const int32_t *rk = fin ? d.rank1 : d.rank0;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    const int64_t total = ner + np;
+    for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < total; base += stride) {
+        const int64_t t = base + threadIdx.x;
+        bool emit = false;
+        PathReq q;
+        if (t < ner) {
+            const int4 e = d.er[t];
+            emit = true;
+            if (rk[2 * t] > rk[2 * t + 1]) {  // piece of x is the parent
+                q.start = e.y; q.newpar = e.x; q.stop = d.prt[e.w];
+            } else {
+                q.start = e.x; q.newpar = e.y; q.stop = d.prt[e.z];
+            }
+        } else if (t < total) {
+            const int64_t p = t - ner;
+            if (d.comp[p] == (int32_t)p) {
+                const uint64_t sk = d.srkey[p];
+                const int32_t S = (int32_t)(uint32_t)sk, m = (int32_t)(sk >> 32);
+                d.newlab[p] = m;
+                if (m != d.prt[S]) {
+                    emit = true;
+                    q.start = m; q.newpar = m; q.stop = d.prt[S];
+                }
+            }
+        }
+        const int64_t slot = wave_append(emit, &d.cnt[C_NR]);
+        if (emit) {
+            if (slot < d.pathcap) d.paths[slot] = q;
+            else atomicOr(d.status, ST_CAPACITY);
+        }
+    }
+}
+
+// ------------------------------------- a8: path reversal + new parents
+
+// One thread per path.  Paths lie in distinct pieces (at most one per piece:
+// the attach path of a non-root piece or the re-root path of a super-root
+// piece), so the walks touch disjoint vertices; each thread reads a parent
+// before overwriting it (the old orientation is read exactly once).
+__global__ __launch_bounds__(BLOCK) void k_reverse(Dev d) {
+    if (*d.status) return;
+    const int64_t nr = (int64_t)d.cnt[C_NR];
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < nr; i += stride) {
+        const PathReq q = d.paths[i];
+        int32_t prev = q.newpar, cur = q.start;
+        for (int64_t steps = 0;; steps++) {
+            const int32_t nxt = d.parent[cur];
+            d.parent[cur] = prev;
+            if (cur == q.stop) break;
+            prev = cur;
+            cur = nxt;
+            if (steps > d.n) { atomicOr(d.status, ST_WALK_BOUND); break; }
+        }
+    }
+}
+
+// ------------------------------------------------------------ a9: labels
+
+__global__ __launch_bounds__(BLOCK) void k_label_delete(Dev d) {
+    if (*d.status) return;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < d.n; v += stride) {
+        if (obit(d.obits, (int32_t)v)) {
+            const int32_t p = d.tidx[d.rep[v]];
+            if (p >= 0) d.label[v] = d.newlab[d.comp[p]];
+            else atomicOr(d.status, ST_WALK_BOUND);
+        }
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_label_insert(Dev d) {
+    if (*d.status || d.cnt[C_NP] == 0) return;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < d.n; v += stride) {
+        const int32_t t = d.tidx[d.label[v]];
+        if (t != NONE) d.label[v] = d.newlab[d.comp[t]];
+    }
+}
+
+// ------------------------------------------------------------- cleanup
+
+__global__ __launch_bounds__(BLOCK) void k_cleanup_slots(Dev d) {
+    const int64_t np = (int64_t)d.cnt[C_NP];
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < np; p += stride)
+        d.tidx[d.prt[p]] = NONE;
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < d.b; i += stride)
+        if (d.bslot[i] != NONE) d.bhash[d.bslot[i]] = HASH_EMPTY;
+}
+
+__global__ void k_cleanup_counters(Dev d) {
+    const int t = threadIdx.x;
+    if (t < C_TOTAL && t != C_NDELTA && t != C_NLIVE_DELTA) d.cnt[t] = 0;
+    if (t == 0) *d.status = 0;
+}
+
+// ------------------------------------------------------------ launchers
+
+void launch_classify(const Dev &d, hipStream_t s) {
+    hipLaunchKernelGGL(k_classify, dim3(grid_for(d.b, BLOCK)), dim3(BLOCK), 0, s, d);
+}
+void launch_prepare(const Dev &d, hipStream_t s) {
+    hipLaunchKernelGGL(k_prepare, dim3(grid_for(d.b, BLOCK)), dim3(BLOCK), 0, s, d);
+}
+void launch_insert_emit(const Dev &d, hipStream_t s) {
+    hipLaunchKernelGGL(k_insert_emit, dim3(grid_for(d.b, BLOCK)), dim3(BLOCK), 0, s, d);
+}
+void launch_rep(const Dev &d, hipStream_t s) {
+    hipLaunchKernelGGL(k_rep_init, dim3(grid_for(d.n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_rep_chase, dim3(grid_for(d.n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, d);
+}
+void launch_sweep(const Dev &d, int64_t ndelta_bound, hipStream_t s) {
+    if (d.ntiles > 0)
+        hipLaunchKernelGGL(k_sweep_base, dim3((unsigned)d.ntiles), dim3(BLOCK), 0, s, d);
+    if (ndelta_bound > 0)
+        hipLaunchKernelGGL(k_sweep_delta, dim3(grid_for(ndelta_bound, BLOCK)), dim3(BLOCK), 0, s, d);
+}
+void launch_boruvka(const Dev &d, int rounds, hipStream_t s) {
+    const int ge = grid_for(d.xcap, BLOCK, 4096);
+    const int gp = grid_for(d.pcap, BLOCK, 2048);
+    for (int r = 0; r < rounds; r++) {
+        hipLaunchKernelGGL(k_bor_select, dim3(ge), dim3(BLOCK), 0, s, d, r);
+        hipLaunchKernelGGL(k_bor_hook, dim3(gp), dim3(BLOCK), 0, s, d, r);
+        hipLaunchKernelGGL(k_bor_compress, dim3(gp), dim3(BLOCK), 0, s, d, r);
+    }
+}
+void launch_superforest(const Dev &d, int lr_rounds, hipStream_t s) {
+    const int gp = grid_for(d.pcap, BLOCK, 2048);
+    const int ga = grid_for(2 * d.ercap, BLOCK, 2048);
+    hipLaunchKernelGGL(k_sf_init, dim3(gp), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_sf_succ, dim3(ga), dim3(BLOCK), 0, s, d);
+    for (int r = 0; r < lr_rounds; r++)
+        hipLaunchKernelGGL(k_lr_round, dim3(ga), dim3(BLOCK), 0, s, d, r);
+    hipLaunchKernelGGL(k_orient, dim3(grid_for(d.ercap + d.pcap, BLOCK, 2048)), dim3(BLOCK), 0, s,
+                       d, lr_rounds);
+}
+void launch_reverse(const Dev &d, hipStream_t s) {
+    hipLaunchKernelGGL(k_reverse, dim3(grid_for(d.pathcap, BLOCK, 2048)), dim3(BLOCK), 0, s, d);
+}
+void launch_labels(const Dev &d, hipStream_t s) {
+    if (d.op == 1)
+        hipLaunchKernelGGL(k_label_delete, dim3(grid_for(d.n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, d);
+    else
+        hipLaunchKernelGGL(k_label_insert, dim3(grid_for(d.n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, d);
+}
+void launch_cleanup(const Dev &d, hipStream_t s) {
+    hipLaunchKernelGGL(k_cleanup_slots, dim3(grid_for(d.pcap > d.b ? d.pcap : d.b, BLOCK, 2048)),
+                       dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_cleanup_counters, dim3(1), dim3(256), 0, s, d);
+}
+
+// ======================================================= create-time kernels
+
+__global__ void k_fill_i32(int32_t *p, int64_t count, int32_t v) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
+}
+__global__ void k_fill_u64(uint64_t *p, int64_t count, uint64_t v) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
+}
+void launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t s) {
+    if (count > 0)
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(count, BLOCK, 1 << 16)), dim3(BLOCK), 0, s, p, count, v);
+}
+void launch_fill_u64(uint64_t *p, int64_t count, uint64_t v, hipStream_t s) {
+    if (count > 0)
+        hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(count, BLOCK, 1 << 16)), dim3(BLOCK), 0, s, p, count, v);
+}
+
+// One wave per row: ids in range, no self-loop, strictly ascending; count
+// the entries above the diagonal (the upper half keeps each edge once).
+__global__ __launch_bounds__(BLOCK) void k_csr_check(int32_t n, const int64_t *row_ptr,
+                                                     const int32_t *col, uint32_t *ucnt,
+                                                     int32_t *status) {
+    const int64_t nw = (int64_t)gridDim.x * (BLOCK / WAVE);
+    const int lane = lane_id();
+    for (int64_t u = (int64_t)blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE; u < n; u += nw) {
+        const int64_t s = row_ptr[u], e = row_ptr[u + 1];
+        if (e < s) { if (lane == 0) atomicOr(status, 1); continue; }
+        int bad = 0;
+        int64_t above = 0;
+        for (int64_t j = s + lane; j < e; j += WAVE) {
+            const int32_t c = col[j];
+            if (c < 0 || c >= n || c == u) bad = 1;
+            if (j + 1 < e && col[j + 1] <= c) bad = 1;
+            above += c > u;
+        }
+        for (int o = WAVE / 2; o > 0; o >>= 1) {
+            above += __shfl_xor(above, o);
+            bad |= __shfl_xor(bad, o);
+        }
+        if (lane == 0) {
+            if (bad) atomicOr(status, 1);
+            ucnt[u] = (uint32_t)above;
+        }
+    }
+}
+void launch_csr_check(int32_t n, const int64_t *row_ptr, const int32_t *col, uint32_t *ucnt,
+                      int32_t *status, hipStream_t s) {
+    hipLaunchKernelGGL(k_csr_check, dim3(grid_for((int64_t)n * WAVE, BLOCK, 1 << 20)), dim3(BLOCK),
+                       0, s, n, row_ptr, col, ucnt, status);
+}
+
+// Every entry (u, c) must have its mirror (c, u).
+__global__ __launch_bounds__(BLOCK) void k_csr_symmetric(int32_t n, const int64_t *row_ptr,
+                                                         const int32_t *col, int32_t *status) {
+    const int64_t nw = (int64_t)gridDim.x * (BLOCK / WAVE);
+    const int lane = lane_id();
+    for (int64_t u = (int64_t)blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE; u < n; u += nw) {
+        const int64_t s = row_ptr[u], e = row_ptr[u + 1];
+        for (int64_t j = s + lane; j < e; j += WAVE) {
+            const int32_t c = col[j];
+            if (c < 0 || c >= n) continue;  // reported by k_csr_check
+            int64_t a = row_ptr[c], b = row_ptr[c + 1];
+            while (a < b) {
+                int64_t mid = a + ((b - a) >> 1);
+                if (col[mid] < u) a = mid + 1; else b = mid;
+            }
+            if (!(a < row_ptr[c + 1] && col[a] == u)) atomicOr(status, 2);
+        }
+    }
+}
+void launch_csr_symmetric(int32_t n, const int64_t *row_ptr, const int32_t *col, int32_t *status,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_csr_symmetric, dim3(grid_for((int64_t)n * WAVE, BLOCK, 1 << 20)),
+                       dim3(BLOCK), 0, s, n, row_ptr, col, status);
+}
+
+// ---- exclusive scan of uint32 counts (three passes), with a 64-bit total
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_CHUNK = BLOCK * SCAN_ITEMS;
+
+size_t scan_tmp_bytes(int64_t n) {
+    return sizeof(unsigned long long) * (size_t)((n + SCAN_CHUNK - 1) / SCAN_CHUNK + 1);
+}
+
+__device__ unsigned long long block_scan_excl(unsigned long long x, unsigned long long *total) {
+    __shared__ unsigned long long ws[BLOCK / WAVE];
+    const int lane = lane_id(), wid = threadIdx.x / WAVE;
+    unsigned long long inc = x;
+    for (int o = 1; o < WAVE; o <<= 1) {
+        unsigned long long y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (lane == WAVE - 1) ws[wid] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < BLOCK / WAVE; w++) { unsigned long long s2 = ws[w]; ws[w] = t; t += s2; }
+        *total = t;
+    }
+    __syncthreads();
+    unsigned long long r = ws[wid] + inc - x;
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_sums(const uint32_t *in, int64_t n,
+                                                     unsigned long long *bsum) {
+    const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_ITEMS;
+    unsigned long long s = 0;
+    for (int j = 0; j < SCAN_ITEMS; j++)
+        if (base + j < n) s += in[base + j];
+    __shared__ unsigned long long tot;
+    block_scan_excl(s, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+__global__ __launch_bounds__(BLOCK) void k_scan_top(unsigned long long *bsum, int64_t nb,
+                                                    unsigned long long *total) {
+    __shared__ unsigned long long tot;
+    unsigned long long carry = 0;
+    for (int64_t base = 0; base < nb; base += BLOCK) {
+        const int64_t i = base + threadIdx.x;
+        unsigned long long x = i < nb ? bsum[i] : 0;
+        unsigned long long ex = block_scan_excl(x, &tot);
+        if (i < nb) bsum[i] = carry + ex;
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+__global__ __launch_bounds__(BLOCK) void k_scan_apply(const uint32_t *in, uint32_t *out, int64_t n,
+                                                      const unsigned long long *bsum,
+                                                      const unsigned long long *total) {
+    const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_ITEMS;
+    unsigned long long s = 0;
+    uint32_t v[SCAN_ITEMS];
+    for (int j = 0; j < SCAN_ITEMS; j++) {
+        v[j] = base + j < n ? in[base + j] : 0;
+        s += v[j];
+    }
+    __shared__ unsigned long long tot;
+    unsigned long long off = bsum[blockIdx.x] + block_scan_excl(s, &tot);
+    for (int j = 0; j < SCAN_ITEMS; j++) {
+        if (base + j < n) out[base + j] = (uint32_t)off;
+        off += v[j];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = (uint32_t)*total;
+}
+void launch_scan_u32(const uint32_t *in, uint32_t *out, unsigned long long *total, int64_t n,
+                     void *tmp, hipStream_t s) {
+    const int64_t nb = (n + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    unsigned long long *bsum = (unsigned long long *)tmp;
+    if (nb > 0) hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(BLOCK), 0, s, in, n, bsum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, s, bsum, nb, total);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(BLOCK), 0, s, in, out,
+                       n, bsum, total);
+}
+
+// copy the upper-half suffix of every (ascending) row
+__global__ __launch_bounds__(BLOCK) void k_upper_fill(int32_t n, const int64_t *row_ptr,
+                                                      const int32_t *col, const uint32_t *bptr,
+                                                      int32_t *bcol) {
+    const int64_t nw = (int64_t)gridDim.x * (BLOCK / WAVE);
+    const int lane = lane_id();
+    for (int64_t u = (int64_t)blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE; u < n; u += nw) {
+        const int64_t e = row_ptr[u + 1];
+        const int64_t cntu = (int64_t)bptr[u + 1] - bptr[u];
+        const int64_t s = e - cntu;
+        for (int64_t j = lane; j < cntu; j += WAVE) bcol[bptr[u] + j] = col[s + j];
+    }
+}
+void launch_upper_fill(int32_t n, const int64_t *row_ptr, const int32_t *col, const uint32_t *bptr,
+                       int32_t *bcol, hipStream_t s) {
+    hipLaunchKernelGGL(k_upper_fill, dim3(grid_for((int64_t)n * WAVE, BLOCK, 1 << 20)), dim3(BLOCK),
+                       0, s, n, row_ptr, col, bptr, bcol);
+}
+
+// tile_row[t] = largest row r with bptr[r] <= t * TILE; tile_row[ntiles] = n - 1
+__global__ void k_tile_rows(int32_t n, const uint32_t *bptr, int64_t eb, int32_t *tile_row,
+                            int64_t ntiles) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t <= ntiles; t += stride) {
+        if (t == ntiles) { tile_row[t] = n - 1; continue; }
+        const int64_t e = t * TILE;
+        int32_t a = 0, b = n - 1;
+        while (a < b) {
+            int32_t mid = a + ((b - a + 1) >> 1);
+            if ((int64_t)bptr[mid] <= e) a = mid; else b = mid - 1;
+        }
+        tile_row[t] = a;
+    }
+}
+void launch_tile_rows(int32_t n, const uint32_t *bptr, int64_t eb, int32_t *tile_row, int64_t ntiles,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_tile_rows, dim3(grid_for(ntiles + 1, BLOCK)), dim3(BLOCK), 0, s, n, bptr,
+                       eb, tile_row, ntiles);
+}
+
+// parent ids in range; every parent edge is an edge of G
+__global__ void k_forest_check(int32_t n, const uint32_t *bptr, const int32_t *bcol,
+                               const int32_t *parent, int32_t *status, int edges) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        const int32_t p = parent[v];
+        if (p < 0 || p >= n) { atomicOr(status, 1); continue; }
+        if (p == v || !edges) continue;
+        const int32_t lo = p < v ? p : (int32_t)v, hi = p < v ? (int32_t)v : p;
+        if (find_in_row(bcol, bptr[lo], bptr[lo + 1], hi) < 0) atomicOr(status, 2);
+    }
+}
+void launch_forest_check(int32_t n, const uint32_t *bptr, const int32_t *bcol, const int32_t *parent,
+                         int32_t *status, int check_edges, hipStream_t s) {
+    hipLaunchKernelGGL(k_forest_check, dim3(grid_for(n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, n, bptr,
+                       bcol, parent, status, check_edges);
+}
+
+__global__ void k_pointer_jump(int32_t n, const int32_t *in, int32_t *out) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+        out[v] = in[in[v]];
+}
+void launch_pointer_jump(int32_t n, const int32_t *in, int32_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_pointer_jump, dim3(grid_for(n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, n, in, out);
+}
+
+// after enough jumping rounds every vertex of a tree points at its root; a
+// vertex on or below a cycle does not
+__global__ void k_roots_check(int32_t n, const int32_t *parent, const int32_t *root,
+                              int32_t *status) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        const int32_t r = root[v];
+        if (parent[r] != r) atomicOr(status, 4);
+    }
+}
+void launch_roots_check(int32_t n, const int32_t *parent, const int32_t *root, int32_t *status,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_roots_check, dim3(grid_for(n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, n, parent,
+                       root, status);
+}
+
+// no edge of G may join two trees (trees span components)
+__global__ __launch_bounds__(BLOCK) void k_span_check(Dev d, const int32_t *root) {
+    const int64_t nw = (int64_t)gridDim.x * (BLOCK / WAVE);
+    const int lane = lane_id();
+    for (int64_t u = (int64_t)blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE; u < d.n; u += nw) {
+        const int32_t ru = root[u];
+        for (int64_t j = (int64_t)d.bptr[u] + lane; j < (int64_t)d.bptr[u + 1]; j += WAVE)
+            if (root[d.bcol[j]] != ru) atomicOr(d.status, 8);
+    }
+}
+void launch_span_check(const Dev &d, const int32_t *root, hipStream_t s) {
+    hipLaunchKernelGGL(k_span_check, dim3(grid_for((int64_t)d.n * WAVE, BLOCK, 1 << 20)), dim3(BLOCK),
+                       0, s, d, root);
+}
+
+// label[r] <- smallest vertex of r's tree (label pre-filled with INT32_MAX),
+// then every vertex copies its root's value
+__global__ void k_tree_min(int32_t n, const int32_t *root, int32_t *label) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+        min_i32(&label[root[v]], (int32_t)v);
+}
+__global__ void k_label_from_root(int32_t n, const int32_t *root, int32_t *label) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+        if (root[v] != v) label[v] = label[root[v]];
+}
+void launch_tree_min(int32_t n, const int32_t *root, int32_t *label, hipStream_t s) {
+    launch_fill_i32(label, n, 0x7fffffff, s);
+    hipLaunchKernelGGL(k_tree_min, dim3(grid_for(n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, n, root, label);
+    hipLaunchKernelGGL(k_label_from_root, dim3(grid_for(n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, n, root,
+                       label);
+}
+
+// a tree whose root r is not its smallest vertex m is re-rooted at m
+__global__ __launch_bounds__(BLOCK) void k_reroot_requests(Dev d, const int32_t *root) {
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < d.n; base += stride) {
+        const int64_t v = base + threadIdx.x;
+        bool emit = false;
+        PathReq q;
+        if (v < d.n && root[v] == v && d.label[v] != v) {
+            emit = true;
+            q.start = d.label[v]; q.newpar = d.label[v]; q.stop = (int32_t)v;
+        }
+        const int64_t slot = wave_append(emit, &d.cnt[C_NR]);
+        if (emit) {
+            if (slot < d.pathcap) d.paths[slot] = q;
+            else atomicOr(d.status, ST_CAPACITY);
+        }
+    }
+}
+void launch_reroot_requests(const Dev &d, const int32_t *root, hipStream_t s) {
+    hipLaunchKernelGGL(k_reroot_requests, dim3(grid_for(d.n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, d, root);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_count_live_delta(Dev d) {
+    const int64_t nd = (int64_t)d.cnt[C_NDELTA];
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    unsigned long long c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < nd; i += stride)
+        c += d.dkey[i] != KEY_DEAD;
+    for (int o = WAVE / 2; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if (lane_id() == 0 && c) atomicAdd(&d.cnt[C_NLIVE_DELTA], c);
+}
+void launch_count_live_delta(const Dev &d, int64_t ndelta_bound, hipStream_t s) {
+    hipLaunchKernelGGL(k_count_live_delta, dim3(grid_for(ndelta_bound, BLOCK, 2048)), dim3(BLOCK), 0,
+                       s, d);
+}
+
+}  // namespace drsf

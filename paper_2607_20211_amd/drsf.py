@@ -1,0 +1,286 @@
+"""ctypes binding of libdrsf.so (include/drsf.h).
+
+Argument marshalling only: every step of a batch update runs in the HIP
+kernels of libdrsf.so.  Inputs may be numpy arrays (host memory) or torch
+tensors on the GPU (device memory, ``inputs_on_device=1``).  There is no CPU
+fallback: if the library is missing or no GPU is present, calls fail.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("DRSF_LIB") or os.path.join(_HERE, "libdrsf.so")
+
+DRSF_INSERT, DRSF_DELETE = 0, 1
+DRSF_OK, DRSF_E_ARG, DRSF_E_NOMEM, DRSF_E_FOREST = 0, -1, -2, -3
+DRSF_E_BATCH, DRSF_E_CAPACITY, DRSF_E_DEVICE, DRSF_E_STATE = -4, -5, -6, -7
+PHASES = ("validate", "update_graph", "cut_and_roots", "key_edge_sweep",
+          "replacement_edges", "superforest_rooting", "path_reversal", "labels")
+
+
+class drsf_opts(ctypes.Structure):
+    _fields_ = [("stream", ctypes.c_void_p),
+                ("inputs_on_device", ctypes.c_int),
+                ("validate_forest", ctypes.c_int),
+                ("profile", ctypes.c_int),
+                ("max_batch", ctypes.c_int64),
+                ("delta_capacity", ctypes.c_int64)]
+
+
+class drsf_view(ctypes.Structure):
+    _fields_ = [("parent", ctypes.c_void_p),
+                ("label", ctypes.c_void_p),
+                ("n", ctypes.c_int32),
+                ("num_edges", ctypes.c_int64),
+                ("num_key_cross", ctypes.c_int64),
+                ("num_replacement", ctypes.c_int64),
+                ("num_pieces", ctypes.c_int64),
+                ("num_paths", ctypes.c_int64)]
+
+
+class DrsfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"drsf error {code}: {msg}")
+        self.code = code
+
+
+# every symbol include/drsf.h declares
+EXPORTS = ("drsf_default_opts", "drsf_create", "drsf_apply", "drsf_apply_async", "drsf_wait",
+           "drsf_copy_out", "drsf_get_view", "drsf_num_edges", "drsf_export_edges",
+           "drsf_snapshot_take", "drsf_snapshot_restore", "drsf_snapshot_free",
+           "drsf_phase_times", "drsf_destroy", "drsf_last_error", "drsf_version")
+
+_lib = None
+
+
+def load():
+    """Load libdrsf.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+    # One HIP runtime per process: torch's wheel ships its own libamdhip64
+    # with the same soname.  Loading torch first makes libdrsf.so bind to that
+    # copy; loading libdrsf.so first would let torch load a second runtime
+    # later, and two runtimes cannot share the device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, c_int = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int
+    lib.drsf_default_opts.argtypes = [ctypes.POINTER(drsf_opts)]
+    lib.drsf_default_opts.restype = None
+    lib.drsf_create.argtypes = [i32, vp, vp, vp, ctypes.POINTER(drsf_opts), ctypes.POINTER(vp)]
+    lib.drsf_create.restype = c_int
+    lib.drsf_apply.argtypes = [vp, vp, i64, c_int, ctypes.POINTER(drsf_view)]
+    lib.drsf_apply.restype = c_int
+    lib.drsf_apply_async.argtypes = [vp, vp, i64, c_int]
+    lib.drsf_apply_async.restype = c_int
+    lib.drsf_wait.argtypes = [vp, ctypes.POINTER(drsf_view)]
+    lib.drsf_wait.restype = c_int
+    lib.drsf_copy_out.argtypes = [vp, vp, vp]
+    lib.drsf_copy_out.restype = c_int
+    lib.drsf_get_view.argtypes = [vp, ctypes.POINTER(drsf_view)]
+    lib.drsf_get_view.restype = c_int
+    lib.drsf_num_edges.argtypes = [vp]
+    lib.drsf_num_edges.restype = i64
+    lib.drsf_export_edges.argtypes = [vp, vp, i64, ctypes.POINTER(i64)]
+    lib.drsf_export_edges.restype = c_int
+    lib.drsf_snapshot_take.argtypes = [vp, ctypes.POINTER(vp)]
+    lib.drsf_snapshot_take.restype = c_int
+    lib.drsf_snapshot_restore.argtypes = [vp, vp]
+    lib.drsf_snapshot_restore.restype = c_int
+    lib.drsf_snapshot_free.argtypes = [vp]
+    lib.drsf_snapshot_free.restype = None
+    lib.drsf_phase_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), c_int]
+    lib.drsf_phase_times.restype = c_int
+    lib.drsf_destroy.argtypes = [vp]
+    lib.drsf_destroy.restype = None
+    lib.drsf_last_error.argtypes = [vp]
+    lib.drsf_last_error.restype = ctypes.c_char_p
+    lib.drsf_version.argtypes = []
+    lib.drsf_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _ptr(x):
+    """Raw pointer of a numpy array (host) or a torch tensor (host or device)."""
+    if x is None:
+        return None
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    return x.ctypes.data
+
+
+def _check(rc: int, ctx=None):
+    if rc != DRSF_OK:
+        msg = load().drsf_last_error(ctx)
+        raise DrsfError(rc, msg.decode() if msg else "")
+
+
+# ---- functions with the names of the C ABI --------------------------------
+
+def drsf_default_opts() -> drsf_opts:
+    o = drsf_opts()
+    load().drsf_default_opts(ctypes.byref(o))
+    return o
+
+
+def drsf_create(n: int, row_ptr, col, parent, opts: drsf_opts | None = None):
+    o = opts if opts is not None else drsf_default_opts()
+    out = ctypes.c_void_p()
+    _check(load().drsf_create(n, _ptr(row_ptr), _ptr(col), _ptr(parent), ctypes.byref(o),
+                              ctypes.byref(out)))
+    return out
+
+
+def drsf_apply(ctx, edges, b: int, op: int) -> drsf_view:
+    v = drsf_view()
+    _check(load().drsf_apply(ctx, _ptr(edges), b, op, ctypes.byref(v)), ctx)
+    return v
+
+
+def drsf_apply_async(ctx, edges, b: int, op: int) -> None:
+    _check(load().drsf_apply_async(ctx, _ptr(edges), b, op), ctx)
+
+
+def drsf_wait(ctx) -> drsf_view:
+    v = drsf_view()
+    _check(load().drsf_wait(ctx, ctypes.byref(v)), ctx)
+    return v
+
+
+def drsf_copy_out(ctx, parent_host=None, label_host=None) -> None:
+    _check(load().drsf_copy_out(ctx, _ptr(parent_host), _ptr(label_host)), ctx)
+
+
+def drsf_num_edges(ctx) -> int:
+    return int(load().drsf_num_edges(ctx))
+
+
+def drsf_export_edges(ctx) -> np.ndarray:
+    m = drsf_num_edges(ctx)
+    keys = np.empty(max(m, 1), dtype=np.uint64)
+    got = ctypes.c_int64()
+    _check(load().drsf_export_edges(ctx, keys.ctypes.data, len(keys), ctypes.byref(got)), ctx)
+    return keys[: got.value]
+
+
+def drsf_snapshot_take(ctx):
+    s = ctypes.c_void_p()
+    _check(load().drsf_snapshot_take(ctx, ctypes.byref(s)), ctx)
+    return s
+
+
+def drsf_snapshot_restore(ctx, snap) -> None:
+    _check(load().drsf_snapshot_restore(ctx, snap), ctx)
+
+
+def drsf_snapshot_free(snap) -> None:
+    load().drsf_snapshot_free(snap)
+
+
+def drsf_phase_times(ctx) -> dict:
+    buf = (ctypes.c_float * len(PHASES))()
+    k = load().drsf_phase_times(ctx, buf, len(PHASES))
+    return {PHASES[i]: float(buf[i]) for i in range(k)}
+
+
+def drsf_destroy(ctx) -> None:
+    load().drsf_destroy(ctx)
+
+
+def drsf_version() -> str:
+    return load().drsf_version().decode()
+
+
+# ---- convenience wrapper -----------------------------------------------------
+
+class Forest:
+    """A graph and its rooted spanning forest resident on the GPU."""
+
+    def __init__(self, n: int, row_ptr, col, parent, *, max_batch: int = 1 << 20,
+                 stream=None, inputs_on_device: bool = False, validate: bool = True,
+                 profile: bool = False, delta_capacity: int = 0):
+        o = drsf_default_opts()
+        o.max_batch = max_batch
+        o.inputs_on_device = int(inputs_on_device)
+        o.validate_forest = int(validate)
+        o.profile = int(profile)
+        o.delta_capacity = delta_capacity
+        if stream is not None:
+            o.stream = stream
+        if not inputs_on_device:
+            row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+            col = np.ascontiguousarray(col, dtype=np.int32)
+            parent = np.ascontiguousarray(parent, dtype=np.int32)
+        self.n = n
+        self._keep = (row_ptr, col, parent)
+        self.ctx = drsf_create(n, row_ptr, col, parent, o)
+        self._keep = None
+
+    def apply(self, edges, op: int) -> dict:
+        if hasattr(edges, "data_ptr"):
+            b = edges.numel() // 2
+        else:
+            edges = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+            b = edges.shape[0]
+        v = drsf_apply(self.ctx, edges, b, op)
+        return self._stats(v)
+
+    def apply_async(self, edges, op: int) -> None:
+        if hasattr(edges, "data_ptr"):
+            b = edges.numel() // 2
+        else:
+            edges = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+            b = edges.shape[0]
+        drsf_apply_async(self.ctx, edges, b, op)
+
+    def wait(self) -> dict:
+        return self._stats(drsf_wait(self.ctx))
+
+    @staticmethod
+    def _stats(v: drsf_view) -> dict:
+        return {"num_edges": v.num_edges, "num_key_cross": v.num_key_cross,
+                "num_replacement": v.num_replacement, "num_pieces": v.num_pieces,
+                "num_paths": v.num_paths}
+
+    def parent(self) -> np.ndarray:
+        p = np.empty(self.n, dtype=np.int32)
+        drsf_copy_out(self.ctx, p, None)
+        return p
+
+    def label(self) -> np.ndarray:
+        lab = np.empty(self.n, dtype=np.int32)
+        drsf_copy_out(self.ctx, None, lab)
+        return lab
+
+    def edges(self) -> np.ndarray:
+        return drsf_export_edges(self.ctx)
+
+    def phase_times(self) -> dict:
+        return drsf_phase_times(self.ctx)
+
+    def snapshot(self):
+        return drsf_snapshot_take(self.ctx)
+
+    def restore(self, snap) -> None:
+        drsf_snapshot_restore(self.ctx, snap)
+
+    def close(self) -> None:
+        if self.ctx is not None:
+            drsf_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,321 @@
+"""GPU parity: libdrsf.so (through the C ABI) against the CPU oracle.
+
+Bar: parent and label arrays bit-exact with the oracle after every batch
+(integer work; the deterministic rules fix a unique answer), the forest
+checker passes, and the reported replacement-edge count equals the
+oracle's.  Inputs are seeded synthetic graphs from gen/.
+"""
+from __future__ import annotations
+
+import itertools
+import random
+import sys
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    from paper_2607_20211_amd import drsf
+    return drsf
+
+
+def _case(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+class Pair:
+    """The GPU forest and the oracle state, stepped together."""
+
+    def __init__(self, g: gen.Graph, **kw):
+        drsf = _lib()
+        self.n = g.n
+        self.keys = g.keys
+        self.gpu = drsf.Forest(g.n, g.row_ptr, g.col, g.parent, **kw)
+        # canonical starting point: the oracle roots each tree at its minimum
+        r = oracle.apply(g.n, g.keys, g.parent, np.zeros((0, 2), np.int32), oracle.DELETE)
+        self.parent, self.label = r.parent, r.label
+        self.check_equal("create")
+
+    def check_equal(self, what):
+        p, lab = self.gpu.parent(), self.gpu.label()
+        if not np.array_equal(lab, self.label):
+            bad = np.flatnonzero(lab != self.label)[:10]
+            raise AssertionError(f"{what}: label mismatch at {bad.tolist()} "
+                                 f"gpu={lab[bad].tolist()} oracle={self.label[bad].tolist()}")
+        if not np.array_equal(p, self.parent):
+            bad = np.flatnonzero(p != self.parent)[:10]
+            raise AssertionError(f"{what}: parent mismatch at {bad.tolist()} "
+                                 f"gpu={p[bad].tolist()} oracle={self.parent[bad].tolist()}")
+        rc, msg = oracle.check_forest(self.n, self.keys, p, lab)
+        assert rc == 0, f"{what}: checker: {msg}"
+
+    def step(self, batch, op, what=""):
+        drsf = _lib()
+        opc = oracle.INSERT if op == drsf.DRSF_INSERT else oracle.DELETE
+        r = oracle.apply(self.n, self.keys, self.parent, batch, opc, label=self.label)
+        st = self.gpu.apply(batch, op)
+        self.keys, self.parent, self.label = r.keys, r.parent, r.label
+        self.check_equal(what)
+        assert st["num_replacement"] == r.stats["n_repl"], (what, st, r.stats)
+        assert st["num_edges"] == len(self.keys)
+        return st, r.stats
+
+
+def _roots(parent):
+    r = parent.copy()
+    while True:
+        nr = r[r]
+        if np.array_equal(nr, r):
+            return r
+        r = nr
+
+
+def test_golden_fixtures_gpu():
+    drsf = _lib()
+    import test_oracle as T
+    import glob
+    import os
+    for path in sorted(glob.glob(os.path.join(T.GOLDEN, "*.txt"))):
+        _case(path)
+        lines = [l.strip() for l in open(path) if l.strip() and not l.startswith("#")]
+        n = int(lines[0].split()[1])
+        edges = [tuple(map(int, p.split())) for p in lines[1].partition(" ")[2].split(";") if p.strip()]
+        parent = np.array(list(map(int, lines[2].split()[1:])), np.int32)
+        keys = T.keys_np(edges)
+        row_ptr, col = gen.keys_to_csr(n, keys)
+        g = gen.Graph("golden", n, keys, row_ptr, col, parent)
+        pair = Pair(g, max_batch=64)
+        i = 3
+        while i < len(lines):
+            op = drsf.DRSF_INSERT if lines[i].split()[1] == "insert" else drsf.DRSF_DELETE
+            batch = np.array([tuple(map(int, p.split())) for p in lines[i + 1].partition(" ")[2].split(";")],
+                             np.int32)
+            pair.step(batch, op, path)
+            assert pair.gpu.parent().tolist() == list(map(int, lines[i + 2].split()[1:]))
+            assert pair.gpu.label().tolist() == list(map(int, lines[i + 3].split()[1:]))
+            i += 4
+        pair.gpu.close()
+
+
+def test_tiny_random_sequences():
+    drsf = _lib()
+    rng = random.Random(5)
+    for case in range(40):
+        n = rng.randint(2, 9)
+        pairs = list(itertools.combinations(range(n), 2))
+        p = rng.random()
+        edges = [e for e in pairs if rng.random() < p]
+        keys = np.array(sorted((u << 32) | v for u, v in edges), np.uint64)
+        g = gen.make_graph("tiny", n, keys)
+        _case(f"tiny {case} n={n} m={len(edges)}")
+        pair = Pair(g, max_batch=64)
+        for step in range(6):
+            op = rng.choice([drsf.DRSF_INSERT, drsf.DRSF_DELETE])
+            present = set(int(k) for k in pair.keys)
+            pool = [e for e in pairs if ((e[0] << 32) | e[1]) not in present]
+            if op == drsf.DRSF_DELETE:
+                pool = [e for e in pairs if ((e[0] << 32) | e[1]) in present]
+            if not pool:
+                continue
+            batch = rng.sample(pool, rng.randint(1, len(pool)))
+            batch = [(v, u) if rng.random() < 0.5 else (u, v) for u, v in batch]
+            pair.step(np.array(batch, np.int32), op, f"tiny {case} step {step}")
+        pair.gpu.close()
+
+
+def test_c1_small_gnm():
+    """G(n=10,000, m=50,000): insert 1,000 non-edges, then delete 1,000 edges
+    (500 tree edges of the post-insert forest, 500 non-tree edges)."""
+    drsf = _lib()
+    _case("C1")
+    g = gen.make_graph("c1", 10000, gen.gnm(10000, 50000, gen.seed(1, 0, gen.P_GRAPH)))
+    pair = Pair(g)
+    ins = gen.insert_batches(g.n, g.keys, 1, 1000, gen.seed(1, 0, gen.P_INSERT))[0]
+    pair.step(ins, drsf.DRSF_INSERT, "C1 insert")
+    dl = gen.delete_batches(g.n, pair.keys, pair.parent, 1, 1000, 500, gen.seed(1, 0, gen.P_DELETE))[0]
+    st, ost = pair.step(dl, drsf.DRSF_DELETE, "C1 delete")
+    assert st["num_replacement"] > 0
+    pair.gpu.close()
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_sparse_many_components(seed):
+    """Sparse graphs (many trees, several sweep tiles and a ragged tail):
+    alternating inserts and deletes, state carried over."""
+    drsf = _lib()
+    n = 30011
+    g = gen.make_graph("sparse", n, gen.gnm(n, 26000 + 977 * seed, gen.seed(10, seed, gen.P_GRAPH)))
+    _case(f"sparse seed={seed}")
+    pair = Pair(g, max_batch=8192)
+    for step in range(4):
+        ins = gen.insert_batches(n, pair.keys, 1, 3000 + 17 * step, gen.seed(10, seed * 16 + step, gen.P_INSERT))[0]
+        pair.step(ins, drsf.DRSF_INSERT, f"sparse {seed} insert {step}")
+        trees = int((pair.parent != np.arange(n)).sum())
+        nt = min(2000, trees)
+        nn = min(2001, len(pair.keys) - trees)
+        dl = gen.delete_batches(n, pair.keys, pair.parent, 1, nt + nn, nt,
+                                gen.seed(10, seed * 16 + step, gen.P_DELETE))[0]
+        pair.step(dl, drsf.DRSF_DELETE, f"sparse {seed} delete {step}")
+    pair.gpu.close()
+
+
+def test_noncanonical_input_forest_is_rerooted():
+    drsf = _lib()
+    _case("noncanonical")
+    rng = np.random.default_rng(3)
+    n = 5000
+    g = gen.make_graph("nc", n, gen.gnm(n, 4000, 77))
+    # re-root every tree at a random vertex
+    import test_oracle as T
+    edges = [(int(k >> np.uint64(32)), int(k & np.uint64(0xffffffff))) for k in g.keys]
+    forest = [(v, int(p)) for v, p in enumerate(g.parent) if p != v]
+    par = T.random_spanning_forest(n, forest, random.Random(4))
+    g2 = gen.Graph("nc", n, g.keys, g.row_ptr, g.col, np.array(par, np.int32))
+    pair = Pair(g2)
+    dl = gen.delete_batches(n, pair.keys, pair.parent, 1, 500, 400, 5)[0]
+    pair.step(dl, drsf.DRSF_DELETE, "nc delete")
+    pair.gpu.close()
+
+
+def test_deep_trees_path_and_grid():
+    """Long root paths: a path graph with chords and a 256 x 256 grid."""
+    drsf = _lib()
+    _case("path")
+    n = 200_000
+    path = [(i, i + 1) for i in range(n - 1)]
+    rng = np.random.default_rng(8)
+    chords = set()
+    while len(chords) < 3000:
+        u, v = sorted(rng.integers(0, n, 2).tolist())
+        if v - u > 1:
+            chords.add((u, v))
+    keys = np.array(sorted((u << 32) | v for u, v in path + list(chords)), np.uint64)
+    g = gen.make_graph("path", n, keys)
+    pair = Pair(g)
+    dl = gen.delete_batches(n, pair.keys, pair.parent, 1, 3000, 2000, 9)[0]
+    pair.step(dl, drsf.DRSF_DELETE, "path delete")
+    ins = gen.insert_batches(n, pair.keys, 1, 2000, 10)[0]
+    pair.step(ins, drsf.DRSF_INSERT, "path insert")
+    pair.gpu.close()
+    _case("grid")
+    keys = gen.grid(256, 256, 3276, gen.seed(3, 1, gen.P_GRAPH))
+    g = gen.make_graph("grid", 256 * 256, keys)
+    pair = Pair(g)
+    dl = gen.delete_batches(g.n, pair.keys, pair.parent, 1, 2000, 2000, 11)[0]
+    pair.step(dl, drsf.DRSF_DELETE, "grid delete")
+    ins = gen.insert_batches(g.n, pair.keys, 1, 2000, 12)[0]
+    pair.step(ins, drsf.DRSF_INSERT, "grid insert")
+    pair.gpu.close()
+
+
+def test_rmat_small():
+    drsf = _lib()
+    _case("rmat16")
+    keys = gen.rmat(16, 16, 0.57, 0.19, 0.19, gen.seed(2, 7, gen.P_GRAPH))
+    g = gen.make_graph("rmat16", 1 << 16, keys)
+    pair = Pair(g)
+    for step in range(2):
+        ins = gen.insert_batches(g.n, pair.keys, 1, 10000, gen.seed(2, 7 + step, gen.P_INSERT))[0]
+        pair.step(ins, drsf.DRSF_INSERT, f"rmat insert {step}")
+        dl = gen.delete_batches(g.n, pair.keys, pair.parent, 1, 10000, 5000,
+                                gen.seed(2, 7 + step, gen.P_DELETE))[0]
+        pair.step(dl, drsf.DRSF_DELETE, f"rmat delete {step}")
+    pair.gpu.close()
+
+
+def test_invalid_batches_leave_state_unchanged():
+    drsf = _lib()
+    _case("invalid")
+    n = 3000
+    g = gen.make_graph("inv", n, gen.gnm(n, 6000, 21))
+    f = drsf.Forest(g.n, g.row_ptr, g.col, g.parent, max_batch=16)
+    p0, l0, e0 = f.parent(), f.label(), f.edges()
+    k0 = g.keys[:1]
+    e_in = [int(k0[0] >> np.uint64(32)), int(k0[0] & np.uint64(0xffffffff))]
+    non = gen.insert_batches(n, g.keys, 1, 2, 1)[0].tolist()
+    bad = [([(3, 3)], drsf.DRSF_INSERT), ([(0, n)], drsf.DRSF_INSERT), ([(-1, 2)], drsf.DRSF_DELETE),
+           ([non[0], non[0][::-1]], drsf.DRSF_INSERT), ([non[1], e_in], drsf.DRSF_INSERT),
+           ([e_in, non[0]], drsf.DRSF_DELETE), ([e_in, e_in], drsf.DRSF_DELETE)]
+    for batch, op in bad:
+        with pytest.raises(drsf.DrsfError) as ei:
+            f.apply(np.array(batch, np.int32), op)
+        assert ei.value.code == drsf.DRSF_E_BATCH
+        assert np.array_equal(f.parent(), p0) and np.array_equal(f.label(), l0)
+        assert np.array_equal(f.edges(), e0)
+    with pytest.raises(drsf.DrsfError) as ei:
+        f.apply(np.zeros((17, 2), np.int32), drsf.DRSF_INSERT)
+    assert ei.value.code == drsf.DRSF_E_CAPACITY
+    # empty batch is a no-op; a valid batch still works after the rejections
+    f.apply(np.zeros((0, 2), np.int32), drsf.DRSF_DELETE)
+    f.apply(np.array(non, np.int32), drsf.DRSF_INSERT)
+    f.close()
+
+
+def test_create_rejects_bad_inputs():
+    drsf = _lib()
+    _case("create errors")
+    n = 100
+    g = gen.make_graph("c", n, gen.gnm(n, 150, 3))
+    bad_parent = g.parent.copy()
+    v = int(np.flatnonzero(bad_parent != np.arange(n))[0])
+    bad_parent[bad_parent[v]] = v  # 2-cycle
+    with pytest.raises(drsf.DrsfError) as ei:
+        drsf.Forest(n, g.row_ptr, g.col, bad_parent)
+    assert ei.value.code == drsf.DRSF_E_FOREST
+    cut = g.parent.copy()
+    cut[v] = v  # trees no longer span components
+    with pytest.raises(drsf.DrsfError) as ei:
+        drsf.Forest(n, g.row_ptr, g.col, cut)
+    assert ei.value.code == drsf.DRSF_E_FOREST
+    asym = g.col.copy()
+    asym[0] = (asym[0] + 1) % n
+    with pytest.raises(drsf.DrsfError):
+        drsf.Forest(n, g.row_ptr, asym, g.parent)
+
+
+def test_determinism_snapshot_restore_export():
+    drsf = _lib()
+    _case("determinism")
+    n = 40000
+    g = gen.make_graph("det", n, gen.gnm(n, 60000, 31))
+    f = drsf.Forest(g.n, g.row_ptr, g.col, g.parent, max_batch=20000)
+    snap = f.snapshot()
+    ins = gen.insert_batches(n, g.keys, 1, 15000, 32)[0]
+    outs = []
+    for rep in range(3):
+        f.restore(snap)
+        f.apply(ins, drsf.DRSF_INSERT)
+        dl = gen.delete_batches(n, np.union1d(g.keys, gen.keys_of_edges(ins)), g.parent, 1, 15000, 5000, 33)[0]
+        f.apply(dl, drsf.DRSF_DELETE)
+        outs.append((f.parent(), f.label(), f.edges()))
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+    f.restore(snap)
+    assert np.array_equal(f.edges(), g.keys)
+    drsf.drsf_snapshot_free(snap)
+    f.close()
+
+
+@pytest.mark.slow
+def test_rmat22_full_size_step():
+    """R-MAT scale 22 (the headline workload) at batch 1e5: one insert and one
+    delete step in the configuration the benchmark times, compared with the
+    oracle on the full parent and label arrays."""
+    drsf = _lib()
+    _case("rmat22 full")
+    keys = gen.rmat(22, 16, 0.57, 0.19, 0.19, gen.seed(2, 0, gen.P_GRAPH))
+    g = gen.make_graph("rmat22", 1 << 22, keys)
+    pair = Pair(g, max_batch=1 << 17)
+    ins = gen.insert_batches(g.n, g.keys, 1, 100000, gen.seed(2, 0, gen.P_INSERT))[0]
+    pair.step(ins, drsf.DRSF_INSERT, "rmat22 insert")
+    dl = gen.delete_batches(g.n, g.keys, g.parent, 1, 100000, 50000, gen.seed(2, 0, gen.P_DELETE))[0]
+    pair.step(dl, drsf.DRSF_DELETE, "rmat22 delete")
+    pair.gpu.close()
