@@ -159,8 +159,9 @@ void drsf_snapshot_free(drsf_snapshot *snap);
 
 /*
  * Per-phase device times of the last apply in milliseconds (needs
- * opts.profile): validate, update-graph, cut+root-finding, key-edge sweep,
- * replacement edges, super-forest rooting, path reversal, labels.  Returns
+ * opts.profile): validate, update-graph, cut+root-finding, key-edge sweep of
+ * the base edge store, key-edge sweep of the inserted-edge list, replacement
+ * edges, super-forest rooting, path reversal, labels.  Returns
  * the number of phases written (<= cap).
  */
 int drsf_phase_times(drsf_ctx *ctx, float *ms, int cap);

@@ -19,7 +19,10 @@ namespace {
 
 thread_local std::string g_create_error;
 
-enum Phase { PH_VALIDATE, PH_UPDATE, PH_ROOTS, PH_SWEEP, PH_REPL, PH_ROOTING, PH_REVERSE, PH_LABELS, PH_N };
+constexpr int BFS_CHUNK = 4;   // search levels per host check
+constexpr int BFS_MAX = 8;     // deeper super-trees use the Euler tour instead
+
+enum Phase { PH_VALIDATE, PH_UPDATE, PH_ROOTS, PH_SWEEP, PH_SWEEP_DELTA, PH_REPL, PH_ROOTING, PH_REVERSE, PH_LABELS, PH_N };
 
 int ceil_log2(int64_t x) {
     int r = 0;
@@ -49,7 +52,10 @@ struct drsf_ctx {
     uint32_t *bptr = nullptr;
     int32_t *bcol = nullptr;
     int64_t eb = 0;
-    int32_t *tile_row = nullptr;
+    int32_t *zrow = nullptr;
+    uint32_t *zptr = nullptr;
+    int64_t nz = 0;
+    int32_t *tile_k = nullptr;
     int64_t ntiles = 0;
     uint64_t *dkey = nullptr;
     int64_t dcap = 0;
@@ -61,8 +67,10 @@ struct drsf_ctx {
     int32_t *parent = nullptr, *label = nullptr, *rep = nullptr;
     uint64_t *obits = nullptr;
     // pieces
-    int32_t *tidx = nullptr, *prt = nullptr, *pmin = nullptr, *comp = nullptr, *hook = nullptr;
-    int32_t *head = nullptr, *newlab = nullptr;
+    int32_t *tidx = nullptr, *owner = nullptr, *prt = nullptr, *pmin = nullptr, *comp = nullptr,
+            *hook = nullptr;
+    uint8_t *pkeep = nullptr;
+    int32_t *head = nullptr, *newlab = nullptr, *level = nullptr, *parc = nullptr;
     uint64_t *best = nullptr, *srkey = nullptr;
     int64_t pcap = 0;
     // batch
@@ -74,6 +82,7 @@ struct drsf_ctx {
     // lists
     Cross *x0 = nullptr, *x1 = nullptr;
     int64_t xcap = 0;
+    unsigned long long *rcnt = nullptr;
     int4 *er = nullptr;
     int64_t ercap = 0;
     int32_t *arc_nxt = nullptr, *succ0 = nullptr, *succ1 = nullptr, *rank0 = nullptr, *rank1 = nullptr;
@@ -141,16 +150,19 @@ Dev make_dev(drsf_ctx *c, int op, int64_t b) {
     memset(&d, 0, sizeof d);
     d.n = c->n;
     d.op = op;
-    d.bptr = c->bptr; d.bcol = c->bcol; d.eb = c->eb; d.tile_row = c->tile_row; d.ntiles = c->ntiles;
+    d.bptr = c->bptr; d.bcol = c->bcol; d.eb = c->eb;
+    d.zrow = c->zrow; d.zptr = c->zptr; d.nz = c->nz; d.tile_k = c->tile_k; d.ntiles = c->ntiles;
     d.dkey = c->dkey; d.dcap = c->dcap; d.dhash = c->dhash; d.dhpos = c->dhpos; d.dhmask = c->dhmask;
     d.parent = c->parent; d.label = c->label; d.rep = c->rep;
     d.repv = op == DRSF_DELETE ? c->rep : c->label;
     d.obits = c->obits;
-    d.tidx = c->tidx; d.prt = c->prt; d.pmin = c->pmin; d.comp = c->comp; d.hook = c->hook;
-    d.best = c->best; d.srkey = c->srkey; d.head = c->head; d.newlab = c->newlab; d.pcap = c->pcap;
+    d.tidx = c->tidx; d.owner = c->owner; d.pkeep = c->pkeep; d.prt = c->prt; d.pmin = c->pmin; d.comp = c->comp; d.hook = c->hook;
+    d.best = c->best; d.srkey = c->srkey; d.head = c->head; d.newlab = c->newlab;
+    d.level = c->level; d.parc = c->parc; d.pcap = c->pcap;
     d.bedges = c->bedges; d.b = b; d.bkey = c->bkey; d.bloc = c->bloc; d.bchild = c->bchild;
     d.bslot = c->bslot; d.bhash = c->bhash; d.bhmask = c->bhmask;
-    d.x0 = c->x0; d.x1 = c->x1; d.xcap = c->xcap;
+    d.x0 = c->x0; d.x1 = c->x1; d.xcap = c->xcap; d.rcnt = c->rcnt;
+    d.nreg = op == DRSF_DELETE ? c->ntiles + delta_tiles(c->ndelta_bound) : insert_regions(b);
     d.er = c->er; d.ercap = c->ercap; d.arc_nxt = c->arc_nxt;
     d.succ0 = c->succ0; d.succ1 = c->succ1; d.rank0 = c->rank0; d.rank1 = c->rank1;
     d.paths = c->paths; d.pathcap = c->pathcap;
@@ -173,12 +185,16 @@ int alloc_state(drsf_ctx *c) {
     if ((rc = dalloc(c, &c->rep, n))) return rc;
     if ((rc = dalloc(c, &c->obits, (n + 63) / 64))) return rc;
     if ((rc = dalloc(c, &c->tidx, n))) return rc;
+    if ((rc = dalloc(c, &c->owner, n))) return rc;
     c->pcap = 2 * mb + 16;
+    if ((rc = dalloc(c, &c->pkeep, c->pcap))) return rc;
     if ((rc = dalloc(c, &c->prt, c->pcap))) return rc;
     if ((rc = dalloc(c, &c->pmin, c->pcap))) return rc;
     if ((rc = dalloc(c, &c->comp, c->pcap))) return rc;
     if ((rc = dalloc(c, &c->hook, c->pcap))) return rc;
     if ((rc = dalloc(c, &c->head, c->pcap))) return rc;
+    if ((rc = dalloc(c, &c->level, c->pcap))) return rc;
+    if ((rc = dalloc(c, &c->parc, c->pcap))) return rc;
     if ((rc = dalloc(c, &c->newlab, c->pcap))) return rc;
     if ((rc = dalloc(c, &c->best, c->pcap))) return rc;
     if ((rc = dalloc(c, &c->srkey, c->pcap))) return rc;
@@ -199,9 +215,14 @@ int alloc_state(drsf_ctx *c) {
     c->dhmask = dh - 1;
     if ((rc = dalloc(c, &c->dhash, (int64_t)dh))) return rc;
     if ((rc = dalloc(c, &c->dhpos, (int64_t)dh))) return rc;
-    c->xcap = c->eb + c->dcap + 16;
+    // x0: one region of TILE entries per producing workgroup (base-store tiles
+    // and inserted-edge tiles on delete, batch tiles on insert)
+    const int64_t nregmax = std::max<int64_t>(c->ntiles + delta_tiles(c->dcap), insert_regions(mb));
+    c->xcap = nregmax * TILE;
     if ((rc = dalloc(c, &c->x0, c->xcap))) return rc;
     if ((rc = dalloc(c, &c->x1, c->xcap))) return rc;
+    if ((rc = dalloc(c, &c->rcnt, nregmax))) return rc;
+    launch_fill_u64(c->rcnt, nregmax, 0, c->stream);
     c->ercap = c->pcap;
     if ((rc = dalloc(c, &c->er, c->ercap))) return rc;
     if ((rc = dalloc(c, &c->arc_nxt, 2 * c->ercap))) return rc;
@@ -275,10 +296,22 @@ int build_store(drsf_ctx *c, const int64_t *row_ptr_in, const int32_t *col_in, i
     c->eb = (int64_t)total;
     if ((rc = dalloc(c, &c->bcol, c->eb))) return rc;
     launch_upper_fill(n, drow, dcol, c->bptr, c->bcol, c->stream);
-    c->ntiles = (c->eb + TILE - 1) / TILE;
-    if ((rc = dalloc(c, &c->tile_row, c->ntiles + 1))) return rc;
-    launch_tile_rows(n, c->bptr, c->eb, c->tile_row, c->ntiles, c->stream);
+    // non-empty-row index for the sweep
+    launch_nonempty_flags(n, c->bptr, ucnt, c->stream);
+    uint32_t *zpos = nullptr;
+    if ((rc = dalloc(c, &zpos, (int64_t)n + 1))) return rc;
+    launch_scan_u32(ucnt, zpos, dtotal, n, tmp, c->stream);
+    HIPCHK(c, hipMemcpyAsync(c->h_ret, dtotal, sizeof total, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->nz = (int64_t)c->h_ret[0];
+    if ((rc = dalloc(c, &c->zrow, c->nz))) return rc;
+    if ((rc = dalloc(c, &c->zptr, c->nz + 1))) return rc;
+    launch_nonempty_fill(n, c->bptr, zpos, c->zrow, c->zptr, c->nz, c->stream);
+    c->ntiles = (c->eb + TILE - 1) / TILE;
+    if ((rc = dalloc(c, &c->tile_k, c->ntiles + 1))) return rc;
+    launch_tile_k(c->zptr, c->nz, c->eb, c->tile_k, c->ntiles, c->stream);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    dfree(c, zpos);
     dfree(c, ucnt);
     dfree(c, tmp);
     if (!dev_in) { dfree(c, drow); dfree(c, dcol); }
@@ -381,7 +414,7 @@ int drsf_create(int32_t n, const int64_t *row_ptr, const int32_t *col, const int
         }
         c->own_stream = true;
     }
-    if (hipHostMalloc((void **)&c->h_ret, sizeof(unsigned long long) * (C_TOTAL + 8)) != hipSuccess) {
+    if (hipHostMalloc((void **)&c->h_ret, sizeof(unsigned long long) * (C_TOTAL + 16)) != hipSuccess) {
         fail(c, DRSF_E_NOMEM, "pinned host allocation failed");
         return bail(DRSF_E_NOMEM);
     }
@@ -462,21 +495,76 @@ int drsf_apply_async(drsf_ctx *c, const int32_t *edges, int64_t b, int op) {
     const bool prof = c->opts.profile != 0;
     auto mark = [&](int i) { if (prof) (void)hipEventRecord(c->ev[i], s); };
     const int64_t np_max = std::min<int64_t>(2 * b, c->pcap);
-    const int bor_rounds = std::min(ceil_log2(np_max + 2) + 2, MAX_ROUNDS);
+    const int bor_bound = std::min(ceil_log2(np_max + 2) + 2, MAX_ROUNDS);
     const int lr_rounds = std::min(ceil_log2(2 * np_max + 2) + 2, MAX_ROUNDS);
     mark(PH_VALIDATE);
     launch_classify(d, s);
     mark(PH_UPDATE);
     launch_prepare(d, s);
+    launch_register(d, s);
     mark(PH_ROOTS);
     if (op == DRSF_DELETE) launch_rep(d, s);
     mark(PH_SWEEP);
-    if (op == DRSF_DELETE) launch_sweep(d, c->ndelta_bound, s);
+    if (op == DRSF_DELETE) launch_sweep_base(d, s);
     else launch_insert_emit(d, s);
+    mark(PH_SWEEP_DELTA);
+    if (op == DRSF_DELETE) launch_sweep_delta(d, c->ndelta_bound, s);
     mark(PH_REPL);
-    launch_boruvka(d, bor_rounds, s);
+    // Hooking rounds run in short chunks; the host reads the device's done
+    // flag between chunks instead of queueing the worst-case number of
+    // rounds.  The first chunk is followed by speculative super-root and
+    // search levels that only run if the rounds have finished.
+    int r = op == DRSF_DELETE ? 2 : 4;
+    r = std::min(r, bor_bound);
+    launch_boruvka(d, 0, r, s);
+    launch_sf_root(d, s);
+    launch_sf_bfs(d, 0, BFS_CHUNK, s);
+    int lv = BFS_CHUNK;
+    unsigned long long *ctl = c->h_ret + 1 + C_COUNT;  // [status, done, bfs flag]
+    auto read_ctl = [&](int bfs_level) -> int {
+        HIPCHK(c, hipMemcpyAsync(ctl, c->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(ctl + 1, c->cnt + C_DONE_BOR, sizeof(unsigned long long),
+                                 hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(ctl + 2, c->cnt + C_BFS_ROUND + bfs_level - 1,
+                                 sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        return DRSF_OK;
+    };
+    int rc2;
+    if ((rc2 = read_ctl(lv))) return rc2;
+    bool bad = *(int32_t *)ctl != 0;
+    bool done = ctl[1] != 0;
+    if (!bad && !done) {
+        while (!done && r < bor_bound) {
+            const int r1 = std::min(r + 3, bor_bound);
+            launch_boruvka(d, r, r1, s);
+            r = r1;
+            if ((rc2 = read_ctl(lv))) return rc2;
+            done = ctl[1] != 0;
+            bad = *(int32_t *)ctl != 0;
+            if (bad) break;
+        }
+        if (!bad && done) {
+            launch_sf_root(d, s);
+            launch_sf_bfs(d, 0, BFS_CHUNK, s);
+            if ((rc2 = read_ctl(lv))) return rc2;
+            bad = *(int32_t *)ctl != 0;
+        }
+    }
     mark(PH_ROOTING);
-    launch_superforest(d, lr_rounds, s);
+    if (!bad && !done) {
+        launch_fill_i32(c->status, 1, ST_ROUND_BOUND, s);  // hooking rounds did not finish
+    } else if (!bad) {
+        bool bfs_done = ctl[2] == 0;
+        while (!bfs_done && lv < BFS_MAX) {
+            launch_sf_bfs(d, lv, lv + BFS_CHUNK, s);
+            lv += BFS_CHUNK;
+            if ((rc2 = read_ctl(lv))) return rc2;
+            bfs_done = ctl[2] == 0;
+        }
+        if (bfs_done) launch_orient_bfs(d, s);
+        else launch_superforest_lr(d, lr_rounds, s);  // deep super-trees: Euler tour
+    }
     mark(PH_REVERSE);
     launch_reverse(d, s);
     mark(PH_LABELS);

@@ -14,7 +14,6 @@ constexpr uint64_t KEY_DEAD = ~0ull;       // deleted entry of the inserted-edge
 constexpr uint64_t HASH_EMPTY = ~0ull;
 constexpr uint64_t HASH_TOMB_BIT = 1ull << 63;
 constexpr int32_t NONE = -1;
-constexpr int32_t CLAIMING = -2;
 
 // Sweep tile: every thread of a 256-thread workgroup takes EPT consecutive
 // stored edges, so one workgroup covers TILE edges.
@@ -43,10 +42,8 @@ enum : int {
     C_NCROSS = 5,    // cross edges found by the key-edge scan (statistic)
     C_DONE_BOR = 6,  // replacement-edge rounds finished
     C_DONE_LR = 7,   // list ranking finished
-    C_LR_ACTIVE0 = 8,
-    C_LR_ACTIVE1 = 9,
     C_NDELTA = 10,   // inserted-edge list length (persistent)
-    C_NLIVE_DELTA = 11,
+    C_LR_FINAL = 12, // buffer holding the final list ranks
     C_COUNT = 16,
 };
 
@@ -90,17 +87,77 @@ __device__ __forceinline__ int64_t wave_append(bool pred, unsigned long long *co
     return pred ? (int64_t)(base + lanes_below(mask)) : -1;
 }
 
-// atomicMin on a 64-bit key, skipped when the current value is already lower
+// atomicMin on a 64-bit key, skipped when a plain (possibly stale) read of
+// the current value is already lower: values only decrease, so a stale read
+// can cost an extra atomic but never skips a needed one.
 __device__ __forceinline__ void min_key(uint64_t *addr, uint64_t k) {
-    if (__atomic_load_n(addr, __ATOMIC_RELAXED) > k)
-        atomicMin((unsigned long long *)addr, (unsigned long long)k);
+    if (*addr > k) atomicMin((unsigned long long *)addr, (unsigned long long)k);
 }
 __device__ __forceinline__ void min_i32(int32_t *addr, int32_t v) {
-    if (__atomic_load_n(addr, __ATOMIC_RELAXED) > v) atomicMin(addr, v);
+    if (*addr > v) atomicMin(addr, v);
 }
 
-__device__ __forceinline__ int32_t ld_relaxed(const int32_t *p) {
-    return __atomic_load_n(p, __ATOMIC_RELAXED);
+// Hot-address atomics.  On this part an atomic request to one address is
+// serialised at the memory side (about 12 ns per request, where a request is
+// one wave instruction), so lanes of a wave that target the same address are
+// merged first: up to GROUP_ROUNDS times the lowest pending lane's target is
+// taken, every lane with that target joins the group, and the group issues a
+// single request.  Lanes left over issue their own.
+constexpr int GROUP_ROUNDS = 4;
+
+__device__ __forceinline__ void group_min_u64(bool active, int32_t target, uint64_t val,
+                                              uint64_t *arr) {
+    uint64_t rem = __ballot(active);
+    for (int round = 0; round < GROUP_ROUNDS && rem; round++) {
+        const int leader = __ffsll((unsigned long long)rem) - 1;
+        const int32_t t0 = __shfl(target, leader);
+        const bool in = active && target == t0;
+        const uint64_t gm = __ballot(in);
+        uint64_t v = in ? val : ~0ull;
+        for (int o = WAVE / 2; o > 0; o >>= 1) {
+            uint64_t w = __shfl_xor(v, o);
+            v = w < v ? w : v;
+        }
+        if (lane_id() == leader && arr[t0] > v)
+            atomicMin((unsigned long long *)&arr[t0], (unsigned long long)v);
+        rem &= ~gm;
+        if (in) active = false;
+    }
+    if (active && arr[target] > val) atomicMin((unsigned long long *)&arr[target], (unsigned long long)val);
 }
+
+// Push `item` onto the singly linked list headed by head[target]
+// (nxt[item] = previous head).  Grouped lanes are chained among themselves
+// and spliced in with one exchange.
+__device__ __forceinline__ void group_push(bool active, int32_t target, int32_t item,
+                                           int32_t *head, int32_t *nxt) {
+    uint64_t rem = __ballot(active);
+    const int lane = lane_id();
+    for (int round = 0; round < GROUP_ROUNDS && rem; round++) {
+        const int leader = __ffsll((unsigned long long)rem) - 1;
+        const int32_t t0 = __shfl(target, leader);
+        const bool in = active && target == t0;
+        const uint64_t gm = __ballot(in);
+        // next group lane above this one (or -1)
+        const uint64_t above = lane == 63 ? 0ull : (gm & ~((2ull << lane) - 1ull));
+        const int nl = above ? __ffsll((unsigned long long)above) - 1 : lane;
+        const int32_t next_item = __shfl(item, nl);
+        const int last = 63 - __clzll((long long)gm);
+        const int32_t first_item = __shfl(item, leader);
+        if (in) {
+            if (lane == last) nxt[item] = atomicExch(&head[t0], first_item);
+            else nxt[item] = next_item;
+        }
+        rem &= ~gm;
+        if (in) active = false;
+    }
+    if (active) nxt[item] = atomicExch(&head[target], item);
+}
+
+// Plain load used by the monotone pointer chases: the value read may be
+// stale (another workgroup's write not yet visible), which only means an
+// ancestor closer to the starting vertex.  System-scope atomic loads would
+// bypass the caches on every step.
+__device__ __forceinline__ int32_t ld_relaxed(const int32_t *p) { return *p; }
 
 }  // namespace drsf

@@ -15,7 +15,13 @@ struct Dev {
     const uint32_t *bptr;    // [n + 1]
     int32_t *bcol;           // [eb]
     int64_t eb;
-    const int32_t *tile_row; // [ntiles + 1] row holding the first edge of each sweep tile
+    // the same rows without the empty ones (for the sweep): zrow[k] is the k-th
+    // non-empty row, its edges are bcol[zptr[k], zptr[k + 1]); tile_k[t] is the
+    // non-empty row holding edge t * TILE
+    const int32_t *zrow;     // [nz]
+    const uint32_t *zptr;    // [nz + 1]
+    int64_t nz;
+    const int32_t *tile_k;   // [ntiles + 1]
     int64_t ntiles;
     uint64_t *dkey;          // [dcap] inserted edge keys, KEY_DEAD when deleted
     int64_t dcap;
@@ -30,6 +36,8 @@ struct Dev {
     uint64_t *obits;         // [ceil(n/64)] vertex lies in a piece cut off from its old root
     // touched pieces (trees of F-hat incident to the batch), dense ids
     int32_t *tidx;           // [n] piece root vertex -> dense id, NONE when idle
+    int32_t *owner;          // [n] scratch for electing one registrant per piece
+    uint8_t *pkeep;          // [pcap] piece holds its component's old root (delete)
     int32_t *prt;            // [pcap] dense id -> piece root vertex
     int32_t *pmin;           // [pcap] smallest vertex of the piece
     int32_t *comp;           // [pcap] current component (a dense piece id)
@@ -37,6 +45,8 @@ struct Dev {
     uint64_t *best;          // [pcap] lowest key of a cross edge leaving the component
     uint64_t *srkey;         // [pcap] (smallest vertex << 32 | piece) of the component
     int32_t *head;           // [pcap] first arc of the piece's super-forest arc list
+    int32_t *level;          // [pcap] BFS level of the piece in its super-tree, -1 unreached
+    int32_t *parc;           // [pcap] arc from the parent piece (BFS rooting)
     int32_t *newlab;         // [pcap] new label of the component
     int64_t pcap;
     // batch
@@ -48,9 +58,16 @@ struct Dev {
     int32_t *bslot;          // [b] slot claimed in the batch duplicate table
     uint64_t *bhash;         // [bhmask + 1]
     uint64_t bhmask;
-    // cross-edge lists (double-buffered between replacement-edge rounds)
+    // cross-edge lists.  x0 is written in regions of TILE entries, one per
+    // producing workgroup: region t holds its cross edges at x0[t * TILE ..]
+    // and rcnt[t] their number (no global atomics).  Delete: regions
+    // [0, ntiles) come from the base-store tiles and [ntiles, nreg) from tiles
+    // of the inserted-edge list; insert: one region per TILE batch entries.
+    // Later hooking rounds use dense lists alternating between x1 and x0.
     Cross *x0, *x1;
     int64_t xcap;
+    unsigned long long *rcnt; // [regions]
+    int64_t nreg;
     // replacement edges and super-forest arcs
     int4 *er;                // [ercap] (x, y, piece of x, piece of y)
     int64_t ercap;
@@ -68,17 +85,24 @@ constexpr int MAX_ROUNDS = 64;
 // extra counter slots: per-round activity flags
 constexpr int C_BOR_ROUND = C_COUNT;               // [MAX_ROUNDS]
 constexpr int C_LR_ROUND = C_COUNT + MAX_ROUNDS;   // [MAX_ROUNDS]
-constexpr int C_TOTAL = C_COUNT + 2 * MAX_ROUNDS;
-constexpr int C_LR_FINAL = 12;
+constexpr int C_BFS_ROUND = C_COUNT + 2 * MAX_ROUNDS;  // [MAX_ROUNDS]
+constexpr int C_TOTAL = C_COUNT + 3 * MAX_ROUNDS;
 
 // launchers (drsf_kernels.hip)
 void launch_classify(const Dev &d, hipStream_t s);
 void launch_prepare(const Dev &d, hipStream_t s);
 void launch_insert_emit(const Dev &d, hipStream_t s);
 void launch_rep(const Dev &d, hipStream_t s);
-void launch_sweep(const Dev &d, int64_t ndelta_bound, hipStream_t s);
-void launch_boruvka(const Dev &d, int rounds, hipStream_t s);
-void launch_superforest(const Dev &d, int lr_rounds, hipStream_t s);
+void launch_register(const Dev &d, hipStream_t s);
+void launch_sweep_base(const Dev &d, hipStream_t s);
+void launch_sweep_delta(const Dev &d, int64_t ndelta_bound, hipStream_t s);
+int64_t delta_tiles(int64_t count);
+int64_t insert_regions(int64_t b);
+void launch_boruvka(const Dev &d, int r0, int r1, hipStream_t s);
+void launch_sf_root(const Dev &d, hipStream_t s);
+void launch_sf_bfs(const Dev &d, int l0, int l1, hipStream_t s);
+void launch_orient_bfs(const Dev &d, hipStream_t s);
+void launch_superforest_lr(const Dev &d, int lr_rounds, hipStream_t s);
 void launch_reverse(const Dev &d, hipStream_t s);
 void launch_labels(const Dev &d, hipStream_t s);
 void launch_cleanup(const Dev &d, hipStream_t s);
@@ -99,8 +123,12 @@ void launch_scan_u32(const uint32_t *in, uint32_t *out, unsigned long long *tota
 size_t scan_tmp_bytes(int64_t n);
 void launch_upper_fill(int32_t n, const int64_t *row_ptr, const int32_t *col,
                        const uint32_t *bptr, int32_t *bcol, hipStream_t s);
-void launch_tile_rows(int32_t n, const uint32_t *bptr, int64_t eb, int32_t *tile_row,
-                      int64_t ntiles, hipStream_t s);
+// non-empty row index: flags -> (scan) -> zrow/zptr, then tile_k
+void launch_nonempty_flags(int32_t n, const uint32_t *bptr, uint32_t *flag, hipStream_t s);
+void launch_nonempty_fill(int32_t n, const uint32_t *bptr, const uint32_t *zpos, int32_t *zrow,
+                          uint32_t *zptr, int64_t nz, hipStream_t s);
+void launch_tile_k(const uint32_t *zptr, int64_t nz, int64_t eb, int32_t *tile_k, int64_t ntiles,
+                   hipStream_t s);
 void launch_forest_check(int32_t n, const uint32_t *bptr, const int32_t *bcol,
                          const int32_t *parent, int32_t *status, int check_edges, hipStream_t s);
 void launch_pointer_jump(int32_t n, const int32_t *in, int32_t *out, hipStream_t s);
@@ -109,6 +137,5 @@ void launch_roots_check(int32_t n, const int32_t *parent, const int32_t *root,
 void launch_span_check(const Dev &d, const int32_t *root, hipStream_t s);
 void launch_tree_min(int32_t n, const int32_t *root, int32_t *label, hipStream_t s);
 void launch_reroot_requests(const Dev &d, const int32_t *root, hipStream_t s);
-void launch_count_live_delta(const Dev &d, int64_t ndelta_bound, hipStream_t s);
 
 }  // namespace drsf

@@ -22,35 +22,6 @@ static inline int grid_for(int64_t items, int64_t per_block, int cap = 8192) {
 
 // ------------------------------------------------------------------ helpers
 
-// Reserve `count` output slots per thread with one atomic per workgroup.
-// Every thread of the block must call it.
-__device__ int64_t block_reserve(int count, unsigned long long *counter) {
-    __shared__ int wsum[BLOCK / WAVE];
-    __shared__ unsigned long long base;
-    const int lane = lane_id(), wid = threadIdx.x / WAVE;
-    int x = count;
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-        int y = __shfl_up(x, o);
-        if (lane >= o) x += y;
-    }
-    if (lane == WAVE - 1) wsum[wid] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int t = 0;
-        for (int w = 0; w < BLOCK / WAVE; w++) {
-            int s = wsum[w];
-            wsum[w] = t;
-            t += s;
-        }
-        base = t ? atomicAdd(counter, (unsigned long long)t) : 0ull;
-    }
-    __syncthreads();
-    int64_t r = (int64_t)base + wsum[wid] + x - count;
-    __syncthreads();
-    return r;
-}
-
 // position of v in the ascending (masked) run bcol[lo, hi), or -1
 __device__ __forceinline__ int64_t find_in_row(const int32_t *bcol, uint32_t lo, uint32_t hi,
                                                int32_t v) {
@@ -97,7 +68,7 @@ __device__ __forceinline__ bool obit(const uint64_t *bits, int32_t v) {
     return (bits[v >> 6] >> (v & 63)) & 1;
 }
 
-__device__ __forceinline__ void init_piece(const Dev &d, int64_t id, int32_t v) {
+__device__ __forceinline__ void init_piece(const Dev &d, int64_t id, int32_t v, bool keep) {
     d.prt[id] = v;
     d.pmin[id] = v;
     d.comp[id] = (int32_t)id;
@@ -106,18 +77,32 @@ __device__ __forceinline__ void init_piece(const Dev &d, int64_t id, int32_t v) 
     d.srkey[id] = KEY_INF;
     d.head[id] = NONE;
     d.newlab[id] = v;
-    __threadfence();
-    d.tidx[v] = (int32_t)id;
+    d.pkeep[id] = keep ? 1 : 0;
+    d.tidx[v] = (int32_t)id;  // read by later kernels only
 }
 
-// Register the trees of F-hat rooted at a and b as touched pieces (dense ids).
-__device__ void claim_two(const Dev &d, bool want, int32_t a, int32_t b) {
-    bool ga = want && atomicCAS(&d.tidx[a], NONE, CLAIMING) == NONE;
-    bool gb = want && a != b && atomicCAS(&d.tidx[b], NONE, CLAIMING) == NONE;
-    int64_t ia = wave_append(ga, &d.cnt[C_NP]);
-    int64_t ib = wave_append(gb, &d.cnt[C_NP]);
-    if (ga) init_piece(d, ia, a);
-    if (gb) init_piece(d, ib, b);
+// Exclusive scan of one int per thread over the block; also returns the total.
+// Every thread of the block must call it.
+__device__ int block_excl_scan(int x, int *total) {
+    __shared__ int wsum[BLOCK / WAVE];
+    const int lane = lane_id(), wid = threadIdx.x / WAVE;
+    int inc = x;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        int y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (lane == WAVE - 1) wsum[wid] = inc;
+    __syncthreads();
+    int before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < BLOCK / WAVE; w++) {
+        before += w < wid ? wsum[w] : 0;
+        tot += wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return before + inc - x;
 }
 
 // -------------------------------------------------- a1: validate + classify
@@ -182,6 +167,10 @@ __global__ __launch_bounds__(BLOCK) void k_classify(Dev d) {
 
 // ---------------------------- a2 + a3: update the edge store, cut tree edges
 
+// Also nominates the trees of F-hat the batch touches: each touched piece
+// root gets owner[root] = (batch index, side) by plain stores; whichever
+// store lands last owns the registration in k_register (no contended atomics
+// on the roots of big trees).
 __global__ __launch_bounds__(BLOCK) void k_prepare(Dev d) {
     if (*d.status) return;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
@@ -189,7 +178,6 @@ __global__ __launch_bounds__(BLOCK) void k_prepare(Dev d) {
         const int64_t i = base + threadIdx.x;
         const bool valid = i < d.b;
         if (d.op == 1) {
-            int32_t c = NONE, lc = NONE;
             if (valid) {
                 const int64_t loc = d.bloc[i];
                 if (loc >= 0) {
@@ -199,54 +187,83 @@ __global__ __launch_bounds__(BLOCK) void k_prepare(Dev d) {
                     d.dkey[d.dhpos[slot]] = KEY_DEAD;
                     d.dhash[slot] = d.bkey[i] | HASH_TOMB_BIT;
                 }
-                c = d.bchild[i];
+                const int32_t c = d.bchild[i];
                 if (c != NONE) {
                     d.parent[c] = c;  // Algorithm 1: parent[u] <- u
-                    lc = d.label[c];
+                    // orphan piece rooted at c, and the piece keeping the old root
+                    d.owner[c] = (int32_t)(2 * i);
+                    d.owner[d.label[c]] = (int32_t)(2 * i + 1);
                 }
             }
-            // orphan piece rooted at c, and the piece that keeps the old root
-            claim_two(d, c != NONE, c, lc);
         } else {
-            uint64_t k = valid ? d.bkey[i] : 0;
-            int64_t pos = wave_append(valid, &d.cnt[C_NDELTA]);
-            int32_t la = NONE, lb = NONE;
+            const uint64_t k = valid ? d.bkey[i] : 0;
+            const int64_t pos = wave_append(valid, &d.cnt[C_NDELTA]);
             if (valid && pos >= d.dcap) {
                 atomicOr(d.status, ST_CAPACITY);
             } else if (valid) {
                 d.dkey[pos] = k;
                 dhash_insert(d, k, (int32_t)pos);
-                la = d.label[key_lo(k)];
-                lb = d.label[key_hi(k)];
+                const int32_t la = d.label[key_lo(k)], lb = d.label[key_hi(k)];
+                if (la != lb) {
+                    d.owner[la] = (int32_t)(2 * i);
+                    d.owner[lb] = (int32_t)(2 * i + 1);
+                }
             }
-            claim_two(d, valid && la != lb, la, lb);
         }
     }
 }
 
-// insert: key edges M = B; cross edges join two different trees (labels)
-__global__ __launch_bounds__(BLOCK) void k_insert_emit(Dev d) {
+// Dense ids for the nominated pieces: the owning batch entry registers.
+__global__ __launch_bounds__(BLOCK) void k_register(Dev d) {
     if (*d.status) return;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < d.b; base += stride) {
         const int64_t i = base + threadIdx.x;
-        bool cross = false;
-        uint64_t k = 0;
-        int32_t la = 0, lb = 0;
+        int32_t a = NONE, b = NONE;
         if (i < d.b) {
-            k = d.bkey[i];
-            la = d.label[key_lo(k)];
-            lb = d.label[key_hi(k)];
-            cross = la != lb;
+            if (d.op == 1) {
+                const int32_t c = d.bchild[i];
+                if (c != NONE) { a = c; b = d.label[c]; }
+            } else {
+                const uint64_t k = d.bkey[i];
+                const int32_t la = d.label[key_lo(k)], lb = d.label[key_hi(k)];
+                if (la != lb) { a = la; b = lb; }
+            }
         }
-        int64_t slot = wave_append(cross, &d.cnt[C_NX0]);
-        if (cross) {
-            Cross e;
-            e.key = k;
-            e.pa = d.tidx[la];
-            e.pb = d.tidx[lb];
-            d.x0[slot] = e;
-        }
+        const bool ga = a != NONE && d.owner[a] == (int32_t)(2 * i);
+        const bool gb = b != NONE && d.owner[b] == (int32_t)(2 * i + 1);
+        const int64_t ia = wave_append(ga, &d.cnt[C_NP]);
+        const int64_t ib = wave_append(gb, &d.cnt[C_NP]);
+        if (ga) init_piece(d, ia, a, false);
+        if (gb) init_piece(d, ib, b, d.op == 1);
+    }
+}
+
+// insert: key edges M = B; cross edges join two different trees (labels).
+// Workgroup t takes batch entries [t * BLOCK, (t + 1) * BLOCK) and writes
+// region t of x0.
+__global__ __launch_bounds__(BLOCK) void k_insert_emit(Dev d) {
+    if (*d.status) return;
+    const int64_t t = blockIdx.x;
+    const int64_t i = t * BLOCK + threadIdx.x;
+    bool cross = false;
+    uint64_t k = 0;
+    int32_t la = 0, lb = 0;
+    if (i < d.b) {
+        k = d.bkey[i];
+        la = d.label[key_lo(k)];
+        lb = d.label[key_hi(k)];
+        cross = la != lb;
+    }
+    int total;
+    const int off = block_excl_scan(cross ? 1 : 0, &total);
+    if (threadIdx.x == 0) d.rcnt[t] = (unsigned long long)total;
+    if (cross) {
+        Cross e;
+        e.key = k;
+        e.pa = d.tidx[la];
+        e.pb = d.tidx[lb];
+        d.x0[t * TILE + off] = e;
     }
 }
 
@@ -283,13 +300,26 @@ __global__ __launch_bounds__(BLOCK) void k_rep_chase(Dev d) {
             d.rep[v] = x;
             orphan = x != d.label[v];
         }
-        uint64_t word = __ballot(orphan);
+        const uint64_t word = __ballot(orphan);
         if (lane_id() == 0 && v < d.n) d.obits[v >> 6] = word;
+        int32_t t = NONE;
         if (orphan) {
-            const int32_t t = d.tidx[x];
-            if (t >= 0) min_i32(&d.pmin[t], (int32_t)v);
-            else atomicOr(d.status, ST_WALK_BOUND);
+            t = d.tidx[x];
+            if (t < 0) atomicOr(d.status, ST_WALK_BOUND);
         }
+        // smallest vertex of each orphan piece; consecutive ids often share a piece
+        const bool act = orphan && t >= 0;
+        uint64_t rem = __ballot(act);
+        bool pending = act;
+        for (int round = 0; round < GROUP_ROUNDS && rem; round++) {
+            const int leader = __ffsll((unsigned long long)rem) - 1;
+            const int32_t t0 = __shfl(t, leader);
+            const bool in = pending && t == t0;
+            rem &= ~__ballot(in);
+            if (in) pending = false;
+            if (lane_id() == leader) min_i32(&d.pmin[t0], (int32_t)v);  // leader is the group's smallest v
+        }
+        if (pending) min_i32(&d.pmin[t], (int32_t)v);
     }
 }
 
@@ -300,162 +330,245 @@ __global__ __launch_bounds__(BLOCK) void k_rep_chase(Dev d) {
 // stay in their old root's piece has equal reps (its ends share a component
 // of G, hence a tree of F, hence that tree's root piece), so the rep gathers
 // are only made when the orphan bitmap flags an end.  One workgroup streams
-// TILE consecutive stored edges; rows are found from a per-tile start row.
+// TILE consecutive stored edges (EPT per thread, 16-byte loads); the rows are
+// walked over the non-empty-row index, so a thread advances at most EPT rows.
+// Cross edges go to the tile's own region of x0: no global atomics.
 __global__ __launch_bounds__(BLOCK) void k_sweep_base(Dev d) {
     if (*d.status) return;
+    typedef int v4i __attribute__((ext_vector_type(4)));
     const int64_t tile = blockIdx.x;
     const int64_t e0 = tile * TILE + (int64_t)threadIdx.x * EPT;
     uint32_t mask = 0;
     int32_t c[EPT];
-    int32_t u0 = 0;
+    int32_t urow[EPT];
     if (e0 < d.eb) {
-        // largest row r with bptr[r] <= e0, searched among the tile's rows
-        int32_t a = d.tile_row[tile], b = d.tile_row[tile + 1];
+        // largest k with zptr[k] <= e0, among the tile's rows
+        int32_t a = d.tile_k[tile], b = d.tile_k[tile + 1];
         while (a < b) {
-            int32_t mid = a + ((b - a + 1) >> 1);
-            if ((int64_t)d.bptr[mid] <= e0) a = mid; else b = mid - 1;
+            const int32_t mid = a + ((b - a + 1) >> 1);
+            if ((int64_t)d.zptr[mid] <= e0) a = mid; else b = mid - 1;
         }
-        u0 = a;
+        // columns: streamed once, non-temporal so they do not evict the bitmap
         if (e0 + EPT <= d.eb) {
-            const int4 *p = reinterpret_cast<const int4 *>(d.bcol + e0);
+            const v4i *p = reinterpret_cast<const v4i *>(d.bcol + e0);
 #pragma unroll
             for (int q = 0; q < EPT / 4; q++) {
-                int4 t = p[q];
+                const v4i t = __builtin_nontemporal_load(p + q);
                 c[4 * q] = t.x; c[4 * q + 1] = t.y; c[4 * q + 2] = t.z; c[4 * q + 3] = t.w;
             }
         } else {
 #pragma unroll
             for (int j = 0; j < EPT; j++) c[j] = (e0 + j < d.eb) ? d.bcol[e0 + j] : TOMB;
         }
-        int32_t u = u0;
-        int64_t rend = d.bptr[u + 1];
-        bool ou = obit(d.obits, u);
+        // phase 1: the row of every edge (at most EPT row steps)
+        int32_t k = a;
+        int64_t rend = d.zptr[k + 1];
+        int32_t u = d.zrow[k];
+        uint32_t umask = obit(d.obits, u) ? 1u : 0u;  // bit j: row of edge j is flagged
+        bool ou = umask != 0;
+        umask = 0;
 #pragma unroll
         for (int j = 0; j < EPT; j++) {
             const int64_t e = e0 + j;
-            if (e >= d.eb) break;
-            while (e >= rend) {
-                u++;
-                rend = d.bptr[u + 1];
-                ou = obit(d.obits, u);
+            if (e < d.eb) {
+                while (e >= rend) {
+                    k++;
+                    rend = d.zptr[k + 1];
+                    u = d.zrow[k];
+                    ou = obit(d.obits, u);
+                }
             }
-            const int32_t v = c[j];
-            if (v < 0) continue;  // deleted
-            if (ou || obit(d.obits, v)) {
-                if (d.rep[u] != d.rep[v]) mask |= 1u << j;
-            }
+            urow[j] = u;
+            umask |= (ou ? 1u : 0u) << j;
         }
-    }
-    const int64_t out = block_reserve(__popc(mask), &d.cnt[C_NX0]);
-    if (mask) {
-        int32_t u = u0;
-        int64_t rend = d.bptr[u + 1];
-        int64_t w = out;
+        // phase 2: independent bitmap loads for all columns
+        uint32_t cand = 0;
 #pragma unroll
         for (int j = 0; j < EPT; j++) {
-            const int64_t e = e0 + j;
-            if (e >= d.eb) break;
-            while (e >= rend) { u++; rend = d.bptr[u + 1]; }
+            const int32_t v = c[j];
+            if (v >= 0 && ((umask >> j & 1) || obit(d.obits, v))) cand |= 1u << j;
+        }
+        // phase 3: rep gathers only for flagged edges
+#pragma unroll
+        for (int j = 0; j < EPT; j++)
+            if ((cand >> j & 1) && d.rep[urow[j]] != d.rep[c[j]]) mask |= 1u << j;
+    }
+    int total;
+    const int off = block_excl_scan(__popc(mask), &total);
+    if (threadIdx.x == 0) d.rcnt[tile] = (unsigned long long)total;
+    if (mask) {
+        Cross *out = d.x0 + tile * TILE + off;
+        int w = 0;
+#pragma unroll
+        for (int j = 0; j < EPT; j++) {
             if (mask >> j & 1) {
-                const int32_t v = c[j];
+                const int32_t u = urow[j], v = c[j];
                 Cross x;
                 x.key = ((uint64_t)(uint32_t)u << 32) | (uint32_t)v;
                 x.pa = d.tidx[d.rep[u]];
                 x.pb = d.tidx[d.rep[v]];
                 if (x.pa < 0 || x.pb < 0) atomicOr(d.status, ST_WALK_BOUND);
-                d.x0[w++] = x;
+                out[w++] = x;
             }
         }
     }
 }
 
-// the same test over the list of inserted edges
+// The same test over the list of inserted edges: workgroup t takes list
+// entries [t * TILE, (t + 1) * TILE) and writes region ntiles + t.
 __global__ __launch_bounds__(BLOCK) void k_sweep_delta(Dev d) {
     if (*d.status) return;
     const int64_t nd = (int64_t)d.cnt[C_NDELTA];
-    const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < nd; base += stride) {
-        const int64_t i = base + threadIdx.x;
-        bool cross = false;
-        uint64_t k = 0;
-        int32_t ru = 0, rv = 0;
-        if (i < nd) {
-            k = d.dkey[i];
-            if (k != KEY_DEAD) {
-                const int32_t u = key_lo(k), v = key_hi(k);
-                if (obit(d.obits, u) || obit(d.obits, v)) {
-                    ru = d.rep[u];
-                    rv = d.rep[v];
-                    cross = ru != rv;
+    const int64_t t = blockIdx.x;
+    const int64_t i0 = t * TILE + (int64_t)threadIdx.x * EPT;
+    uint32_t mask = 0;
+    if (t * TILE < nd) {
+#pragma unroll
+        for (int j = 0; j < EPT; j++) {
+            const int64_t i = i0 + j;
+            if (i < nd) {
+                const uint64_t k = d.dkey[i];
+                if (k != KEY_DEAD) {
+                    const int32_t u = key_lo(k), v = key_hi(k);
+                    if ((obit(d.obits, u) || obit(d.obits, v)) && d.rep[u] != d.rep[v]) mask |= 1u << j;
                 }
             }
         }
-        int64_t slot = wave_append(cross, &d.cnt[C_NX0]);
-        if (cross) {
+    }
+    int total;
+    const int off = block_excl_scan(__popc(mask), &total);
+    const int64_t reg = d.ntiles + t;
+    if (threadIdx.x == 0) d.rcnt[reg] = (unsigned long long)total;
+    Cross *out = d.x0 + reg * TILE + off;
+    int w = 0;
+#pragma unroll
+    for (int j = 0; j < EPT; j++) {
+        if (mask >> j & 1) {
+            const uint64_t k = d.dkey[i0 + j];
             Cross x;
             x.key = k;
-            x.pa = d.tidx[ru];
-            x.pb = d.tidx[rv];
+            x.pa = d.tidx[d.rep[key_lo(k)]];
+            x.pb = d.tidx[d.rep[key_hi(k)]];
             if (x.pa < 0 || x.pb < 0) atomicOr(d.status, ST_WALK_BOUND);
-            d.x0[slot] = x;
+            out[w++] = x;
         }
     }
 }
 
 // ------------------------------- a6: replacement edges by hooking rounds
 
-// Round r, step 1: drop cross edges now inside one component; every
-// component takes the lowest key of the cross edges it touches (64-bit
-// atomic min).  Survivors are compacted into the other buffer.
-__global__ __launch_bounds__(BLOCK) void k_bor_select(Dev d, int r) {
-    if (*d.status || d.cnt[C_DONE_BOR]) return;
-    const Cross *in = (r & 1) ? d.x1 : d.x0;
-    Cross *out = (r & 1) ? d.x0 : d.x1;
-    const int64_t nin = (int64_t)d.cnt[C_NX0 + (r & 1)];
-    unsigned long long *cout = &d.cnt[C_NX0 + ((r + 1) & 1)];
+// A component selects the lowest key among the cross edges it touches.  In a
+// delete, a component that holds an old root piece never selects: every cross
+// edge lies inside one old component, whose root piece is unique, so every
+// live edge touches a component without one, which selects; each selected
+// edge is the lowest key leaving its component (cut property), so the
+// chosen set is still the Kruskal one.
+__device__ __forceinline__ void select_edge(const Dev &d, bool live, const Cross &e, int32_t ca,
+                                            int32_t cb) {
+    const bool sa = live && !d.pkeep[ca], sb = live && !d.pkeep[cb];
+    group_min_u64(sa, ca, e.key, d.best);
+    group_min_u64(sb, cb, e.key, d.best);
+}
+
+// Round 0: every cross edge is live and every component is a single piece.
+// Workgroup t reads region t of x0.  Workgroup 0 also sums the region
+// lengths (the number of cross edges found).
+__global__ __launch_bounds__(BLOCK) void k_bor_round0(Dev d) {
+    if (*d.status) return;
     const int64_t np = (int64_t)d.cnt[C_NP];
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    if (r == 0 && blockIdx.x == 0 && threadIdx.x == 0) d.cnt[C_NCROSS] = (unsigned long long)nin;
     for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < np; p += stride)
         d.hook[p] = NONE;
-    for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < nin; base += stride) {
+    const int64_t t = blockIdx.x;
+    const int64_t cntr = (int64_t)d.rcnt[t];
+    const Cross *in = d.x0 + t * TILE;
+    for (int64_t base = 0; base < cntr; base += BLOCK) {
         const int64_t i = base + threadIdx.x;
-        bool live = false;
+        const bool live = i < cntr;
         Cross e;
-        if (i < nin) {
-            e = in[i];
-            const int32_t ca = d.comp[e.pa], cb = d.comp[e.pb];
-            live = ca != cb;
-            if (live) {
-                min_key(&d.best[ca], e.key);
-                min_key(&d.best[cb], e.key);
-                e.pa = ca;
-                e.pb = cb;
-            }
-        }
-        const int64_t o = block_reserve(live ? 1 : 0, cout);
-        if (live) out[o] = e;
+        e.pa = e.pb = 0;
+        e.key = 0;
+        if (live) e = in[i];
+        select_edge(d, live, e, e.pa, e.pb);
+    }
+    if (t == 0) {
+        unsigned long long s = 0;
+        for (int64_t r = threadIdx.x; r < d.nreg; r += BLOCK) s += d.rcnt[r];
+        for (int o = WAVE / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        if (lane_id() == 0 && s) atomicAdd(&d.cnt[C_NCROSS], s);
     }
 }
 
-// Step 2: each component hooks onto the component across its lowest-key
+// Round r >= 1: drop cross edges now inside one component, select again, and
+// compact the survivors into a dense list.  Round 1 reads the regions of x0;
+// later rounds alternate dense lists (out: x1 on odd rounds, x0 on even).
+__global__ __launch_bounds__(BLOCK) void k_bor_select(Dev d, int r) {
+    if (*d.status || d.cnt[C_DONE_BOR]) return;
+    Cross *out = (r & 1) ? d.x1 : d.x0;
+    unsigned long long *cout = &d.cnt[(r & 1) ? C_NX1 : C_NX0];
+    const int64_t np = (int64_t)d.cnt[C_NP];
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < np; p += stride)
+        d.hook[p] = NONE;
+    const Cross *in;
+    int64_t first, count, step;
+    if (r == 1) {  // one workgroup per region of x0
+        in = d.x0 + (int64_t)blockIdx.x * TILE;
+        count = (int64_t)d.rcnt[blockIdx.x];
+        first = 0;
+        step = BLOCK;
+    } else {
+        in = (r & 1) ? d.x0 : d.x1;
+        count = (int64_t)d.cnt[(r & 1) ? C_NX0 : C_NX1];
+        first = (int64_t)blockIdx.x * BLOCK;
+        step = stride;
+    }
+    for (int64_t base = first; base < count; base += step) {
+        const int64_t i = base + threadIdx.x;
+        bool live = false;
+        Cross e;
+        e.key = 0;
+        e.pa = e.pb = 0;
+        int32_t ca = 0, cb = 0;
+        if (i < count) {
+            e = in[i];
+            ca = d.comp[e.pa];
+            cb = d.comp[e.pb];
+            live = ca != cb;
+        }
+        select_edge(d, live, e, ca, cb);
+        e.pa = ca;
+        e.pb = cb;
+        int total;
+        const int off = block_excl_scan(live ? 1 : 0, &total);
+        __shared__ unsigned long long obase;
+        if (threadIdx.x == 0) obase = total ? atomicAdd(cout, (unsigned long long)total) : 0ull;
+        __syncthreads();
+        if (live) out[obase + off] = e;
+        __syncthreads();
+    }
+}
+
+// Each selecting component hooks onto the component across its lowest-key
 // edge; when two components pick the same edge the smaller id stays a root.
-// Distinct keys make the chosen edges a forest (Boruvka), and each is the
-// lowest key leaving its component, so the union equals the Kruskal choice.
+// Distinct keys make the chosen edges a forest (Boruvka).  Round r >= 1 ends
+// the rounds when its select found no live edge.
 __global__ __launch_bounds__(BLOCK) void k_bor_hook(Dev d, int r) {
     if (*d.status || d.cnt[C_DONE_BOR]) return;
-    const int64_t nout = (int64_t)d.cnt[C_NX0 + ((r + 1) & 1)];
-    if (nout == 0) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) d.cnt[C_DONE_BOR] = 1;
-        return;
+    if (r >= 1) {
+        const int64_t nout = (int64_t)d.cnt[(r & 1) ? C_NX1 : C_NX0];
+        if (nout == 0) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) d.cnt[C_DONE_BOR] = 1;
+            return;
+        }
+        if (r >= 2 && blockIdx.x == 0 && threadIdx.x == 0) d.cnt[(r & 1) ? C_NX0 : C_NX1] = 0;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) d.cnt[C_NX0 + (r & 1)] = 0;
     const int64_t np = (int64_t)d.cnt[C_NP];
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < np; base += stride) {
         const int64_t p = base + threadIdx.x;
         bool rec = false;
-        int4 er;
+        int4 er = make_int4(0, 0, 0, 0);
         if (p < np && d.comp[p] == (int32_t)p) {
             const uint64_t k = d.best[p];
             if (k != KEY_INF) {
@@ -464,13 +577,13 @@ __global__ __launch_bounds__(BLOCK) void k_bor_hook(Dev d, int r) {
                 if (px < 0 || py < 0) {
                     atomicOr(d.status, ST_WALK_BOUND);
                 } else {
-                const int32_t cx = d.comp[px], cy = d.comp[py];
-                const int32_t other = (cx == (int32_t)p) ? cy : cx;
-                if (!(d.best[other] == k && (int32_t)p < other)) {
-                    d.hook[p] = other;
-                    rec = true;
-                    er = make_int4(x, y, px, py);
-                }
+                    const int32_t cx = d.comp[px], cy = d.comp[py];
+                    const int32_t other = (cx == (int32_t)p) ? cy : cx;
+                    if (!(d.best[other] == k && (int32_t)p < other)) {
+                        d.hook[p] = other;
+                        rec = true;
+                        er = make_int4(x, y, px, py);
+                    }
                 }
             }
         }
@@ -479,7 +592,7 @@ __global__ __launch_bounds__(BLOCK) void k_bor_hook(Dev d, int r) {
     }
 }
 
-// Step 3: every piece follows the hooks of this round to its new component.
+// Every piece follows the hooks of this round to its new component.
 __global__ __launch_bounds__(BLOCK) void k_bor_compress(Dev d, int r) {
     if (*d.status || d.cnt[C_DONE_BOR]) return;
     const int64_t np = (int64_t)d.cnt[C_NP];
@@ -497,29 +610,115 @@ __global__ __launch_bounds__(BLOCK) void k_bor_compress(Dev d, int r) {
     }
 }
 
-// ------------------------------------- a7: super-forest rooting (Euler tour)
+// ------------------------------------------- a7: super-forest rooting
 
 // Super-root of each merged component: the piece holding its smallest
 // vertex (insert: the tree with the smallest root; delete: the piece that
 // kept the old root when present, since that root is the component's
-// minimum).  Arc lists of the super-forest: every replacement edge between
-// pieces P and Q gives arcs P->Q (2i) and Q->P (2i+1).
-__global__ __launch_bounds__(BLOCK) void k_sf_init(Dev d) {
-    if (*d.status) return;
-    if (!d.cnt[C_DONE_BOR]) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(d.status, ST_ROUND_BOUND);
-        return;
-    }
+// minimum).  Runs only once the hooking rounds have finished.
+__global__ __launch_bounds__(BLOCK) void k_sf_root(Dev d) {
+    if (*d.status || !d.cnt[C_DONE_BOR]) return;
     const int64_t np = (int64_t)d.cnt[C_NP];
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < np; base += stride) {
+        const int64_t p = base + threadIdx.x;
+        const bool act = p < np;
+        const int32_t c = act ? d.comp[p] : 0;
+        const uint64_t key = act ? (((uint64_t)(uint32_t)d.pmin[p] << 32) | (uint64_t)p) : KEY_INF;
+        group_min_u64(act, c, key, d.srkey);
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_sf_level_init(Dev d) {
+    if (*d.status || !d.cnt[C_DONE_BOR]) return;
+    const int64_t np = (int64_t)d.cnt[C_NP];
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < np; p += stride) {
+        const int32_t S = (int32_t)(uint32_t)d.srkey[d.comp[p]];
+        d.level[p] = S == (int32_t)p ? 0 : -1;
+        d.parc[p] = NONE;
+    }
+}
+
+// Level-synchronous breadth-first search over the replacement edges from the
+// super-roots (the super-forest of Algorithm 2 rooted at the super-roots):
+// arc i*2 goes from the piece of x to the piece of y, i*2+1 back.  In a tree
+// every piece has exactly one neighbour on the previous level, so each
+// piece's level and parent arc have a single writer.  A level that reaches no
+// new piece ends the search.
+__global__ __launch_bounds__(BLOCK) void k_sf_bfs(Dev d, int L) {
+    if (*d.status || !d.cnt[C_DONE_BOR]) return;
+    if (L > 0 && d.cnt[C_BFS_ROUND + L - 1] == 0) return;
+    const int64_t na = 2 * (int64_t)d.cnt[C_NER];
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    bool active = false;
+    for (int64_t a = (int64_t)blockIdx.x * BLOCK + threadIdx.x; a < na; a += stride) {
+        const int4 e = d.er[a >> 1];
+        const int32_t src = (a & 1) ? e.w : e.z, dst = (a & 1) ? e.z : e.w;
+        if (d.level[src] == L && d.level[dst] < 0) {
+            d.level[dst] = L + 1;
+            d.parc[dst] = (int32_t)a;
+            active = true;
+        }
+    }
+    if (__ballot(active) && lane_id() == 0) d.cnt[C_BFS_ROUND + L] = 1;
+}
+
+// Orientation from the search: a piece reached through arc a (from the
+// parent piece) reverses the path from a's endpoint in the piece to the
+// piece's root and hangs that endpoint below a's other endpoint (Algorithm 1,
+// R and new parents).  A super-root piece whose root is not the component's
+// smallest vertex m is re-rooted at m; m is the component's new label.
+__global__ __launch_bounds__(BLOCK) void k_orient_bfs(Dev d) {
+    if (*d.status) return;
+    const int64_t np = (int64_t)d.cnt[C_NP];
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < np; base += stride) {
+        const int64_t p = base + threadIdx.x;
+        bool e1 = false, e2 = false;
+        PathReq q1, q2;
+        q1.start = q1.newpar = q1.stop = q1.pad = 0;
+        q2 = q1;
+        if (p < np) {
+            const int32_t a = d.parc[p];
+            if (a >= 0) {
+                const int4 e = d.er[a >> 1];
+                e1 = true;
+                if ((a & 1) == 0) { q1.start = e.y; q1.newpar = e.x; q1.stop = d.prt[e.w]; }
+                else { q1.start = e.x; q1.newpar = e.y; q1.stop = d.prt[e.z]; }
+            } else if (d.level[p] < 0) {
+                atomicOr(d.status, ST_ROUND_BOUND);  // piece not reached: search incomplete
+            }
+            if (d.comp[p] == (int32_t)p) {
+                const uint64_t sk = d.srkey[p];
+                const int32_t S = (int32_t)(uint32_t)sk, m = (int32_t)(sk >> 32);
+                d.newlab[p] = m;
+                if (m != d.prt[S]) {
+                    e2 = true;
+                    q2.start = m; q2.newpar = m; q2.stop = d.prt[S];
+                }
+            }
+        }
+        const int64_t s1 = wave_append(e1, &d.cnt[C_NR]);
+        const int64_t s2 = wave_append(e2, &d.cnt[C_NR]);
+        if (e1) { if (s1 < d.pathcap) d.paths[s1] = q1; else atomicOr(d.status, ST_CAPACITY); }
+        if (e2) { if (s2 < d.pathcap) d.paths[s2] = q2; else atomicOr(d.status, ST_CAPACITY); }
+    }
+}
+
+// Fallback for deep super-trees: Euler tour of the super-forest and list
+// ranking (Alg. 2, Eulerian tour step).  Arc lists per piece:
+__global__ __launch_bounds__(BLOCK) void k_sf_arcs(Dev d) {
+    if (*d.status) return;
     const int64_t ner = (int64_t)d.cnt[C_NER];
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < np; p += stride)
-        atomicMin((unsigned long long *)&d.srkey[d.comp[p]],
-                  (unsigned long long)(((uint64_t)(uint32_t)d.pmin[p] << 32) | (uint64_t)p));
-    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < ner; i += stride) {
-        const int4 e = d.er[i];
-        d.arc_nxt[2 * i] = atomicExch(&d.head[e.z], (int32_t)(2 * i));
-        d.arc_nxt[2 * i + 1] = atomicExch(&d.head[e.w], (int32_t)(2 * i + 1));
+    for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < ner; base += stride) {
+        const int64_t i = base + threadIdx.x;
+        const bool act = i < ner;
+        int4 e = make_int4(0, 0, 0, 0);
+        if (act) e = d.er[i];
+        group_push(act, e.z, (int32_t)(2 * i), d.head, d.arc_nxt);
+        group_push(act, e.w, (int32_t)(2 * i + 1), d.head, d.arc_nxt);
     }
 }
 
@@ -581,7 +780,7 @@ __global__ __launch_bounds__(BLOCK) void k_lr_round(Dev d, int r) {
 // endpoint takes the other end as parent (Algorithm 1, R and new parents).
 // A super-root piece whose root is not the component's smallest vertex m is
 // re-rooted at m.  The component's new label is m.
-__global__ __launch_bounds__(BLOCK) void k_orient(Dev d, int lr_rounds) {
+__global__ __launch_bounds__(BLOCK) void k_orient_lr(Dev d, int lr_rounds) {
     if (*d.status) return;
     const int64_t ner = (int64_t)d.cnt[C_NER];
     const int64_t np = (int64_t)d.cnt[C_NP];
@@ -602,6 +801,7 @@ __global__ __launch_bounds__(BLOCK) void k_orient(Dev d, int lr_rounds) {
         const int64_t t = base + threadIdx.x;
         bool emit = false;
         PathReq q;
+        q.start = q.newpar = q.stop = q.pad = 0;
         if (t < ner) {
             const int4 e = d.er[t];
             emit = true;
@@ -686,11 +886,13 @@ __global__ __launch_bounds__(BLOCK) void k_cleanup_slots(Dev d) {
         d.tidx[d.prt[p]] = NONE;
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < d.b; i += stride)
         if (d.bslot[i] != NONE) d.bhash[d.bslot[i]] = HASH_EMPTY;
+    for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < d.nreg; t += stride)
+        d.rcnt[t] = 0;
 }
 
 __global__ void k_cleanup_counters(Dev d) {
     const int t = threadIdx.x;
-    if (t < C_TOTAL && t != C_NDELTA && t != C_NLIVE_DELTA) d.cnt[t] = 0;
+    if (t < C_TOTAL && t != C_NDELTA) d.cnt[t] = 0;
     if (t == 0) *d.status = 0;
 }
 
@@ -702,36 +904,60 @@ void launch_classify(const Dev &d, hipStream_t s) {
 void launch_prepare(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_prepare, dim3(grid_for(d.b, BLOCK)), dim3(BLOCK), 0, s, d);
 }
+void launch_register(const Dev &d, hipStream_t s) {
+    hipLaunchKernelGGL(k_register, dim3(grid_for(d.b, BLOCK)), dim3(BLOCK), 0, s, d);
+}
 void launch_insert_emit(const Dev &d, hipStream_t s) {
-    hipLaunchKernelGGL(k_insert_emit, dim3(grid_for(d.b, BLOCK)), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_insert_emit, dim3((unsigned)insert_regions(d.b)), dim3(BLOCK), 0, s, d);
 }
 void launch_rep(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_rep_init, dim3(grid_for(d.n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, d);
     hipLaunchKernelGGL(k_rep_chase, dim3(grid_for(d.n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, d);
 }
-void launch_sweep(const Dev &d, int64_t ndelta_bound, hipStream_t s) {
+void launch_sweep_base(const Dev &d, hipStream_t s) {
     if (d.ntiles > 0)
         hipLaunchKernelGGL(k_sweep_base, dim3((unsigned)d.ntiles), dim3(BLOCK), 0, s, d);
-    if (ndelta_bound > 0)
-        hipLaunchKernelGGL(k_sweep_delta, dim3(grid_for(ndelta_bound, BLOCK)), dim3(BLOCK), 0, s, d);
 }
-void launch_boruvka(const Dev &d, int rounds, hipStream_t s) {
+int64_t delta_tiles(int64_t count) { return (count + TILE - 1) / TILE; }
+int64_t insert_regions(int64_t b) { return (b + BLOCK - 1) / BLOCK; }
+void launch_sweep_delta(const Dev &d, int64_t ndelta_bound, hipStream_t s) {
+    if (ndelta_bound > 0)
+        hipLaunchKernelGGL(k_sweep_delta, dim3((unsigned)delta_tiles(ndelta_bound)), dim3(BLOCK), 0, s, d);
+}
+void launch_boruvka(const Dev &d, int r0, int r1, hipStream_t s) {
     const int ge = grid_for(d.xcap, BLOCK, 4096);
     const int gp = grid_for(d.pcap, BLOCK, 2048);
-    for (int r = 0; r < rounds; r++) {
-        hipLaunchKernelGGL(k_bor_select, dim3(ge), dim3(BLOCK), 0, s, d, r);
+    const unsigned gr = (unsigned)(d.nreg > 0 ? d.nreg : 1);
+    for (int r = r0; r < r1; r++) {
+        if (r == 0)
+            hipLaunchKernelGGL(k_bor_round0, dim3(gr), dim3(BLOCK), 0, s, d);
+        else if (r == 1)
+            hipLaunchKernelGGL(k_bor_select, dim3(gr), dim3(BLOCK), 0, s, d, r);
+        else
+            hipLaunchKernelGGL(k_bor_select, dim3(ge), dim3(BLOCK), 0, s, d, r);
         hipLaunchKernelGGL(k_bor_hook, dim3(gp), dim3(BLOCK), 0, s, d, r);
         hipLaunchKernelGGL(k_bor_compress, dim3(gp), dim3(BLOCK), 0, s, d, r);
     }
 }
-void launch_superforest(const Dev &d, int lr_rounds, hipStream_t s) {
+void launch_sf_root(const Dev &d, hipStream_t s) {
     const int gp = grid_for(d.pcap, BLOCK, 2048);
+    hipLaunchKernelGGL(k_sf_root, dim3(gp), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_sf_level_init, dim3(gp), dim3(BLOCK), 0, s, d);
+}
+void launch_sf_bfs(const Dev &d, int l0, int l1, hipStream_t s) {
     const int ga = grid_for(2 * d.ercap, BLOCK, 2048);
-    hipLaunchKernelGGL(k_sf_init, dim3(gp), dim3(BLOCK), 0, s, d);
+    for (int L = l0; L < l1; L++) hipLaunchKernelGGL(k_sf_bfs, dim3(ga), dim3(BLOCK), 0, s, d, L);
+}
+void launch_orient_bfs(const Dev &d, hipStream_t s) {
+    hipLaunchKernelGGL(k_orient_bfs, dim3(grid_for(d.pcap, BLOCK, 2048)), dim3(BLOCK), 0, s, d);
+}
+void launch_superforest_lr(const Dev &d, int lr_rounds, hipStream_t s) {
+    const int ga = grid_for(2 * d.ercap, BLOCK, 2048);
+    hipLaunchKernelGGL(k_sf_arcs, dim3(grid_for(d.ercap, BLOCK, 2048)), dim3(BLOCK), 0, s, d);
     hipLaunchKernelGGL(k_sf_succ, dim3(ga), dim3(BLOCK), 0, s, d);
     for (int r = 0; r < lr_rounds; r++)
         hipLaunchKernelGGL(k_lr_round, dim3(ga), dim3(BLOCK), 0, s, d, r);
-    hipLaunchKernelGGL(k_orient, dim3(grid_for(d.ercap + d.pcap, BLOCK, 2048)), dim3(BLOCK), 0, s,
+    hipLaunchKernelGGL(k_orient_lr, dim3(grid_for(d.ercap + d.pcap, BLOCK, 2048)), dim3(BLOCK), 0, s,
                        d, lr_rounds);
 }
 void launch_reverse(const Dev &d, hipStream_t s) {
@@ -744,8 +970,9 @@ void launch_labels(const Dev &d, hipStream_t s) {
         hipLaunchKernelGGL(k_label_insert, dim3(grid_for(d.n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, d);
 }
 void launch_cleanup(const Dev &d, hipStream_t s) {
-    hipLaunchKernelGGL(k_cleanup_slots, dim3(grid_for(d.pcap > d.b ? d.pcap : d.b, BLOCK, 2048)),
-                       dim3(BLOCK), 0, s, d);
+    int64_t m = d.pcap > d.b ? d.pcap : d.b;
+    if (d.nreg > m) m = d.nreg;
+    hipLaunchKernelGGL(k_cleanup_slots, dim3(grid_for(m, BLOCK, 2048)), dim3(BLOCK), 0, s, d);
     hipLaunchKernelGGL(k_cleanup_counters, dim3(1), dim3(256), 0, s, d);
 }
 
@@ -927,25 +1154,51 @@ void launch_upper_fill(int32_t n, const int64_t *row_ptr, const int32_t *col, co
                        0, s, n, row_ptr, col, bptr, bcol);
 }
 
-// tile_row[t] = largest row r with bptr[r] <= t * TILE; tile_row[ntiles] = n - 1
-__global__ void k_tile_rows(int32_t n, const uint32_t *bptr, int64_t eb, int32_t *tile_row,
-                            int64_t ntiles) {
+// Non-empty-row index of the upper-half store (used by the sweep).
+__global__ void k_nonempty_flags(int32_t n, const uint32_t *bptr, uint32_t *flag) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride)
+        flag[u] = bptr[u + 1] > bptr[u] ? 1u : 0u;
+}
+__global__ void k_nonempty_fill(int32_t n, const uint32_t *bptr, const uint32_t *zpos, int32_t *zrow,
+                                uint32_t *zptr, int64_t nz) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride)
+        if (bptr[u + 1] > bptr[u]) {
+            zrow[zpos[u]] = (int32_t)u;
+            zptr[zpos[u]] = bptr[u];
+        }
+    if (blockIdx.x == 0 && threadIdx.x == 0) zptr[nz] = bptr[n];
+}
+void launch_nonempty_flags(int32_t n, const uint32_t *bptr, uint32_t *flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_nonempty_flags, dim3(grid_for(n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, n, bptr,
+                       flag);
+}
+void launch_nonempty_fill(int32_t n, const uint32_t *bptr, const uint32_t *zpos, int32_t *zrow,
+                          uint32_t *zptr, int64_t nz, hipStream_t s) {
+    hipLaunchKernelGGL(k_nonempty_fill, dim3(grid_for(n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, n, bptr,
+                       zpos, zrow, zptr, nz);
+}
+
+// tile_k[t] = largest k with zptr[k] <= t * TILE; tile_k[ntiles] = nz - 1
+__global__ void k_tile_k(const uint32_t *zptr, int64_t nz, int64_t eb, int32_t *tile_k,
+                         int64_t ntiles) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t <= ntiles; t += stride) {
-        if (t == ntiles) { tile_row[t] = n - 1; continue; }
+        if (t == ntiles) { tile_k[t] = (int32_t)(nz - 1); continue; }
         const int64_t e = t * TILE;
-        int32_t a = 0, b = n - 1;
+        int64_t a = 0, b = nz - 1;
         while (a < b) {
-            int32_t mid = a + ((b - a + 1) >> 1);
-            if ((int64_t)bptr[mid] <= e) a = mid; else b = mid - 1;
+            const int64_t mid = a + ((b - a + 1) >> 1);
+            if ((int64_t)zptr[mid] <= e) a = mid; else b = mid - 1;
         }
-        tile_row[t] = a;
+        tile_k[t] = (int32_t)a;
     }
 }
-void launch_tile_rows(int32_t n, const uint32_t *bptr, int64_t eb, int32_t *tile_row, int64_t ntiles,
-                      hipStream_t s) {
-    hipLaunchKernelGGL(k_tile_rows, dim3(grid_for(ntiles + 1, BLOCK)), dim3(BLOCK), 0, s, n, bptr,
-                       eb, tile_row, ntiles);
+void launch_tile_k(const uint32_t *zptr, int64_t nz, int64_t eb, int32_t *tile_k, int64_t ntiles,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(k_tile_k, dim3(grid_for(ntiles + 1, BLOCK)), dim3(BLOCK), 0, s, zptr, nz, eb,
+                       tile_k, ntiles);
 }
 
 // parent ids in range; every parent edge is an edge of G
@@ -1045,20 +1298,6 @@ __global__ __launch_bounds__(BLOCK) void k_reroot_requests(Dev d, const int32_t 
 }
 void launch_reroot_requests(const Dev &d, const int32_t *root, hipStream_t s) {
     hipLaunchKernelGGL(k_reroot_requests, dim3(grid_for(d.n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, d, root);
-}
-
-__global__ __launch_bounds__(BLOCK) void k_count_live_delta(Dev d) {
-    const int64_t nd = (int64_t)d.cnt[C_NDELTA];
-    const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    unsigned long long c = 0;
-    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < nd; i += stride)
-        c += d.dkey[i] != KEY_DEAD;
-    for (int o = WAVE / 2; o > 0; o >>= 1) c += __shfl_xor(c, o);
-    if (lane_id() == 0 && c) atomicAdd(&d.cnt[C_NLIVE_DELTA], c);
-}
-void launch_count_live_delta(const Dev &d, int64_t ndelta_bound, hipStream_t s) {
-    hipLaunchKernelGGL(k_count_live_delta, dim3(grid_for(ndelta_bound, BLOCK, 2048)), dim3(BLOCK), 0,
-                       s, d);
 }
 
 }  // namespace drsf

@@ -19,7 +19,8 @@ DRSF_INSERT, DRSF_DELETE = 0, 1
 DRSF_OK, DRSF_E_ARG, DRSF_E_NOMEM, DRSF_E_FOREST = 0, -1, -2, -3
 DRSF_E_BATCH, DRSF_E_CAPACITY, DRSF_E_DEVICE, DRSF_E_STATE = -4, -5, -6, -7
 PHASES = ("validate", "update_graph", "cut_and_roots", "key_edge_sweep",
-          "replacement_edges", "superforest_rooting", "path_reversal", "labels")
+          "key_edge_sweep_inserted", "replacement_edges", "superforest_rooting",
+          "path_reversal", "labels")
 
 
 class drsf_opts(ctypes.Structure):

@@ -319,3 +319,25 @@ def test_rmat22_full_size_step():
     dl = gen.delete_batches(g.n, g.keys, g.parent, 1, 100000, 50000, gen.seed(2, 0, gen.P_DELETE))[0]
     pair.step(dl, drsf.DRSF_DELETE, "rmat22 delete")
     pair.gpu.close()
+
+
+def test_deep_super_tree_uses_euler_tour_fallback():
+    """A path with skip edges (i, i+2); deleting every 10th path edge leaves a
+    chain of pieces joined only through neighbouring pieces, so the
+    super-forest is a path ~100 pieces deep: deeper than the breadth-first
+    levels tried first, which exercises the Euler-tour and list-ranking path."""
+    drsf = _lib()
+    _case("deep super-tree")
+    n = 1000
+    edges = [(i, i + 1) for i in range(n - 1)] + [(i, i + 2) for i in range(n - 2)]
+    keys = np.array(sorted((u << 32) | v for u, v in edges), np.uint64)
+    row_ptr, col = gen.keys_to_csr(n, keys)
+    parent = np.array([0] + list(range(n - 1)), np.int32)  # the path rooted at 0
+    g = gen.Graph("chain", n, keys, row_ptr, col, parent)
+    pair = Pair(g, max_batch=256)
+    batch = np.array([(i, i + 1) for i in range(9, n - 1, 10)], np.int32)
+    st, ost = pair.step(batch, drsf.DRSF_DELETE, "chain delete")
+    assert ost["n_repl"] == len(batch)
+    # and the reverse direction: re-insert, then delete the skip edges' partners
+    pair.step(batch, drsf.DRSF_INSERT, "chain reinsert")
+    pair.gpu.close()
