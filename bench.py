@@ -12,9 +12,13 @@ every surviving forest edge.  Graph, forest and every batch are resident in
 device memory before the timed region starts.
 
 Prints one JSON line: value = edge updates per second of the whole timed
-job (insert + delete), plus per-phase device times, the roofline of the
-dominant kernel (the key-edge sweep of the base edge store) measured with
-events on its own stream, and the CPU oracle timed on a bounded sample.
+job (insert + delete) in the production configuration (each update replays
+the context's captured HIP graph); insert and delete latencies as seen by
+the host; per-phase device times and the roofline of the dominant kernel
+(the key-edge sweep of the base edge store) from a second pass over the
+same steps that launches the kernels one by one with events between the
+phases on the stream the kernels run on; and the CPU oracle timed on a
+bounded sample.
 """
 from __future__ import annotations
 
@@ -94,32 +98,50 @@ def main():
     d_ins = torch.from_numpy(ins).to(dev)
     d_del = torch.from_numpy(dl).to(dev)
     torch.cuda.synchronize()
-    f = drsf.Forest(g.n, d_row, d_col, d_par, max_batch=b, stream=stream.cuda_stream,
-                    inputs_on_device=True, profile=True,
-                    delta_capacity=max(nsteps * b + b, 1 << 20))
-    del d_row, d_col
+
+    def make(profile):
+        return drsf.Forest(g.n, d_row, d_col, d_par, max_batch=b, stream=stream.cuda_stream,
+                           inputs_on_device=True, profile=profile,
+                           delta_capacity=max(nsteps * b + b, 1 << 20))
+
+    # timed pass: the production configuration (captured update graph, no events)
+    f = make(0)
     torch.cuda.synchronize()
     log(f"context created ({time.time() - t0:.1f}s)")
-
-    phases_ins, phases_del = [], []
-
-    def step(i, record):
-        f.apply(d_ins[i], drsf.DRSF_INSERT)
-        if record:
-            phases_ins.append(f.phase_times())
-        f.apply(d_del[i], drsf.DRSF_DELETE)
-        if record:
-            phases_del.append(f.phase_times())
-
     for i in range(W):
-        step(i, False)
+        f.apply(d_ins[i], drsf.DRSF_INSERT)
+        f.apply(d_del[i], drsf.DRSF_DELETE)
     torch.cuda.synchronize()
+    lat_ins, lat_del = [], []
     t_start = time.perf_counter()
     for i in range(W, W + K):
-        step(i, True)
+        ta = time.perf_counter()
+        f.apply(d_ins[i], drsf.DRSF_INSERT)
+        tb = time.perf_counter()
+        f.apply(d_del[i], drsf.DRSF_DELETE)
+        tc = time.perf_counter()
+        lat_ins.append(tb - ta)
+        lat_del.append(tc - tb)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
+    f.close()
     log(f"timed {K} steps in {wall * 1e3:.2f} ms")
+
+    # profiled pass: the same steps on a fresh context that launches the same
+    # kernels one by one with an event between phases, on the stream the
+    # kernels run on
+    fp = make(1)
+    phases_ins, phases_del = [], []
+    for i in range(W + K):
+        fp.apply(d_ins[i], drsf.DRSF_INSERT)
+        if i >= W:
+            phases_ins.append(fp.phase_times())
+        fp.apply(d_del[i], drsf.DRSF_DELETE)
+        if i >= W:
+            phases_del.append(fp.phase_times())
+    torch.cuda.synchronize()
+    fp.close()
+    del d_row, d_col
 
     def mean_phases(lst):
         return {k: float(np.mean([p[k] for p in lst])) for k in lst[0]}
@@ -178,10 +200,16 @@ def main():
                    "scale": scale, "edge_factor": 16, "abcd": [0.57, 0.19, 0.19, 0.05],
                    "n": g.n, "m": g.m, "batch": b,
                    "step": "one insert batch then one delete batch (50% tree edges)"},
-        "insert_updates_per_s": round(b / t_ins_dev, 1),
-        "delete_updates_per_s": round(b / t_del_dev, 1),
-        "insert_device_ms": round(t_ins_dev * 1e3, 4),
-        "delete_device_ms": round(t_del_dev * 1e3, 4),
+        "insert_updates_per_s": round(b / float(np.mean(lat_ins)), 1),
+        "delete_updates_per_s": round(b / float(np.mean(lat_del)), 1),
+        "insert_ms": {"mean": round(float(np.mean(lat_ins)) * 1e3, 4),
+                      "p50": round(float(np.median(lat_ins)) * 1e3, 4),
+                      "max": round(float(np.max(lat_ins)) * 1e3, 4)},
+        "delete_ms": {"mean": round(float(np.mean(lat_del)) * 1e3, 4),
+                      "p50": round(float(np.median(lat_del)) * 1e3, 4),
+                      "max": round(float(np.max(lat_del)) * 1e3, 4)},
+        "insert_device_ms_profiled": round(t_ins_dev * 1e3, 4),
+        "delete_device_ms_profiled": round(t_del_dev * 1e3, 4),
         "phase_ms_insert": {k: round(v, 4) for k, v in pi.items()},
         "phase_ms_delete": {k: round(v, 4) for k, v in pd.items()},
         "roofline": roofline,

@@ -182,3 +182,81 @@ def keys_of_edges(edges: np.ndarray) -> np.ndarray:
     lo = np.minimum(e[:, 0], e[:, 1]).astype(np.uint64)
     hi = np.maximum(e[:, 0], e[:, 1]).astype(np.uint64)
     return (lo << np.uint64(32)) | hi
+
+
+# ---- several independent graphs in one vertex space ---------------------------
+
+@dataclass
+class MultiGraph:
+    """Independent graphs side by side: graph g owns global vertex ids
+    n_off[g] .. n_off[g + 1] - 1.  ``graphs`` hold the local (0-based) views."""
+    n_off: np.ndarray             # int32[G + 1]
+    graphs: list                  # [Graph] with local ids
+    row_ptr: np.ndarray           # int64[N + 1], symmetric CSR over global ids
+    col: np.ndarray               # int32[2 sum m]
+    parent: np.ndarray            # int32[N], global ids
+
+    @property
+    def G(self) -> int:
+        return len(self.graphs)
+
+    @property
+    def n(self) -> int:
+        return int(self.n_off[-1])
+
+
+def shift_keys(keys: np.ndarray, off: int) -> np.ndarray:
+    k = np.asarray(keys, dtype=np.uint64)
+    o = np.uint64(off)
+    return (((k >> np.uint64(32)) + o) << np.uint64(32)) | ((k & np.uint64(0xffffffff)) + o)
+
+
+def multi_graph(graphs: list) -> MultiGraph:
+    """Concatenate local graphs into one global CSR and forest."""
+    ns = [g.n for g in graphs]
+    n_off = np.zeros(len(graphs) + 1, dtype=np.int64)
+    n_off[1:] = np.cumsum(ns)
+    if n_off[-1] >= 2**31:
+        raise ValueError("more than 2^31 - 1 vertices in total")
+    keys = np.concatenate([shift_keys(g.keys, int(o)) for g, o in zip(graphs, n_off)]
+                          + [np.zeros(0, np.uint64)])
+    row_ptr, col = keys_to_csr(int(n_off[-1]), keys)
+    parent = np.concatenate([g.parent.astype(np.int64) + o for g, o in zip(graphs, n_off)]
+                            + [np.zeros(0, np.int64)]).astype(np.int32)
+    return MultiGraph(n_off.astype(np.int32), list(graphs), row_ptr, col, parent)
+
+
+def batched_sizes(G: int, s: int, log_n=(3.0, 6.0), log_b=(1.0, 4.0)):
+    """Per-graph recipe of the batched workload: n_g = round(10^U(log_n)),
+    m_g = 4 n_g, op_g ~ Bernoulli(1/2) (1 = delete), b_g = round(10^U(log_b))."""
+    u = uniform(s, 3 * G).reshape(3, G)
+    ns = np.rint(10.0 ** (log_n[0] + (log_n[1] - log_n[0]) * u[0])).astype(np.int64)
+    ops = (u[1] < 0.5).astype(np.int8)
+    bs = np.rint(10.0 ** (log_b[0] + (log_b[1] - log_b[0]) * u[2])).astype(np.int64)
+    return ns, 4 * ns, ops, bs
+
+
+def multi_step_batches(graph_state: list, ops, bs, s: int):
+    """One batch per graph in local ids: inserts of uniform non-edges, deletes
+    of half tree and half non-tree edges (capped by what the graph has).
+    graph_state[g] = (n, keys, parent).  Returns (list of int32[b_g, 2], ops)."""
+    out, ops_out = [], []
+    for g, (n, keys, parent) in enumerate(graph_state):
+        op, b = int(ops[g]), int(bs[g])
+        sg = splitmix64(s ^ (g * 0x9E3779B97F4A7C15))
+        if op == 1:
+            trees = int((np.asarray(parent) != np.arange(n)).sum())
+            nontree = len(keys) - trees
+            b = min(b, len(keys))
+            nt = min(b // 2, trees)
+            nn = min(b - nt, nontree)
+            nt = min(b - nn, trees)
+            batch = delete_batches(n, keys, parent, 1, nt + nn, nt, sg)[0] if nt + nn else \
+                np.zeros((0, 2), np.int32)
+        else:
+            free = n * (n - 1) // 2 - len(keys)
+            b = min(b, free // 2)  # rejection sampling stays fast
+            batch = insert_batches(n, keys, 1, b, sg)[0] if b else np.zeros((0, 2), np.int32)
+        out.append(batch)
+        ops_out.append(op)
+    return out, np.array(ops_out, np.int8)

@@ -71,8 +71,9 @@ typedef struct {
                                 1: they are device memory */
     int validate_forest;     /* create: 1 (default) checks that parent[] is a rooted
                                 spanning forest whose trees span G's components */
-    int profile;             /* 1: time each phase of apply with events
-                                (drsf_phase_times); adds synchronisation */
+    int profile;             /* 1: launch the update's kernels one by one with an
+                                event between phases (drsf_phase_times) instead of
+                                replaying the captured update graph */
     int64_t max_batch;       /* largest batch accepted by apply; 0 = 1 << 20 */
     int64_t delta_capacity;  /* inserted edges held before the edge store is
                                 rebuilt; 0 = automatic */
@@ -137,6 +138,48 @@ int drsf_apply_async(drsf_ctx *ctx, const int32_t *edges, int64_t b, int op);
 /* Waits for queued work and returns the status of the last queued apply. */
 int drsf_wait(drsf_ctx *ctx, drsf_view *out);
 
+/*
+ * Several independent graphs in one context, each updated by its own batch
+ * and op in a single pass of the update path.  The paper runs one graph at a
+ * time (Sec. V, experimental setup); the per-graph result is exactly what
+ * drsf_apply computes for that graph alone: components never span two
+ * graphs, so every step of Algorithm 1 restricted to one graph's vertices is
+ * the single-graph step.
+ *
+ * drsf_multi_create:
+ *   G        number of graphs (>= 1)
+ *   n_off    host int32[G + 1], vertex offsets: graph g owns global ids
+ *            [n_off[g], n_off[g + 1]); n_off[0] == 0, non-decreasing; n =
+ *            n_off[G]
+ *   row_ptr, col, parent, opts: as drsf_create over the n global ids; every
+ *            neighbour of a vertex lies in the vertex's graph (else
+ *            DRSF_E_ARG)
+ * Labels are global ids (the smallest global id of the component).
+ *
+ * drsf_multi_apply(_async):
+ *   edges    int32[2 * b_off[G]] global-id pairs, graph g's batch at
+ *            [b_off[g], b_off[g + 1]) (host or device per inputs_on_device)
+ *   b_off    host int64[G + 1], b_off[0] == 0, non-decreasing; b_off[G] <=
+ *            max_batch
+ *   op       host int8[G], DRSF_INSERT or DRSF_DELETE per graph
+ *   status   host int32[G] (may be NULL): DRSF_OK, or DRSF_E_BATCH when graph
+ *            g's batch was invalid (that graph is left unchanged; the others
+ *            are updated)
+ * drsf_apply on a context with G > 1 returns DRSF_E_STATE.
+ */
+int drsf_multi_create(int32_t G, const int32_t *n_off, const int64_t *row_ptr, const int32_t *col,
+                      const int32_t *parent, const drsf_opts *opts, drsf_ctx **out);
+int drsf_multi_apply(drsf_ctx *ctx, const int32_t *edges, const int64_t *b_off, const int8_t *op,
+                     int32_t *status);
+int drsf_multi_apply_async(drsf_ctx *ctx, const int32_t *edges, const int64_t *b_off,
+                           const int8_t *op);
+/* Waits like drsf_wait and fills the per-graph status of the last multi apply. */
+int drsf_multi_wait(drsf_ctx *ctx, int32_t *status);
+/* Live edges per graph, host int64[G]. */
+int drsf_multi_num_edges(drsf_ctx *ctx, int64_t *m);
+/* Number of graphs in the context (1 for drsf_create). */
+int drsf_num_graphs(const drsf_ctx *ctx);
+
 /* Copies parent and/or label (either may be NULL) to host int32[n]. */
 int drsf_copy_out(drsf_ctx *ctx, int32_t *parent_host, int32_t *label_host);
 
@@ -159,10 +202,12 @@ void drsf_snapshot_free(drsf_snapshot *snap);
 
 /*
  * Per-phase device times of the last apply in milliseconds (needs
- * opts.profile): validate, update-graph, cut+root-finding, key-edge sweep of
- * the base edge store, key-edge sweep of the inserted-edge list, replacement
- * edges, super-forest rooting, path reversal, labels.  Returns
- * the number of phases written (<= cap).
+ * opts.profile): validate, update-graph (cut, store update, piece
+ * registration), root finding, key-edge sweep of the base edge store,
+ * cross edges of the batch and of the inserted-edge list, replacement edges
+ * (the hooking rounds queued with the update), super-forest rooting, path
+ * reversal, labels.  Work that an update finishes on the host (extra rounds)
+ * is not in these times.  Returns the number of phases written (<= cap).
  */
 int drsf_phase_times(drsf_ctx *ctx, float *ms, int cap);
 

@@ -1,5 +1,15 @@
-// C ABI of libdrsf.so (declared in include/drsf.h): context management,
-// create-time build of the device edge store, and the batch update pipeline.
+// C ABI of libdrsf.so (declared in include/drsf.h): contexts, the create-time
+// build of the device edge store, and the host driver of the update path.
+//
+// One update is a fixed kernel sequence (drsf_kernels.hip) whose batch shape
+// lives in a small device control block, so the sequence is captured once
+// per context into a HIP graph and replayed for every batch.  The graph
+// queues a few hooking rounds and search levels; when a batch needs more,
+// the kernels after them skip themselves and drsf_wait finishes the update
+// with direct launches (further rounds in short chunks, deeper search or the
+// Euler tour).  With opts.profile the same sequence is launched directly,
+// with events between the phases (events recorded inside a captured graph
+// cannot be timed on this runtime).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,10 +29,13 @@ namespace {
 
 thread_local std::string g_create_error;
 
-constexpr int BFS_CHUNK = 4;   // search levels per host check
-constexpr int BFS_MAX = 8;     // deeper super-trees use the Euler tour instead
+constexpr int BOR_FAST = 4;    // hooking rounds queued in the captured sequence
+constexpr int BFS_FAST = 4;    // search levels queued in the captured sequence
+constexpr int BFS_MAX = 12;    // deeper super-trees use the Euler tour instead
+constexpr int BOR_CHUNK = 3;   // rounds per host check in the continuation
 
-enum Phase { PH_VALIDATE, PH_UPDATE, PH_ROOTS, PH_SWEEP, PH_SWEEP_DELTA, PH_REPL, PH_ROOTING, PH_REVERSE, PH_LABELS, PH_N };
+enum Phase { PH_VALIDATE, PH_UPDATE, PH_ROOTS, PH_SWEEP, PH_SWEEP_DELTA, PH_REPL, PH_ROOTING,
+             PH_REVERSE, PH_LABELS, PH_N };
 
 int ceil_log2(int64_t x) {
     int r = 0;
@@ -33,12 +46,13 @@ int ceil_log2(int64_t x) {
 }  // namespace
 
 struct drsf_snapshot {
-    int32_t n;
-    int64_t eb, dcap, ndelta_bound, m_live;
-    uint64_t dhmask;
-    unsigned long long ndelta;
-    int32_t *parent, *label, *bcol, *dhpos;
-    uint64_t *dkey, *dhash;
+    int32_t n = 0;
+    int64_t eb = 0, dcap = 0, ndelta_bound = 0, m_live = 0;
+    uint64_t dhmask = 0;
+    unsigned long long ndelta = 0;
+    std::vector<int64_t> gm;
+    int32_t *parent = nullptr, *label = nullptr, *bcol = nullptr, *dhpos = nullptr;
+    uint64_t *dkey = nullptr, *dhash = nullptr;
 };
 
 struct drsf_ctx {
@@ -48,6 +62,13 @@ struct drsf_ctx {
     bool own_stream = false;
     int32_t n = 0;
     int64_t m_live = 0;
+    // graphs sharing the context (disjoint vertex ranges)
+    int32_t ngraph = 1;
+    std::vector<int32_t> goff_h;   // [ngraph + 1] vertex offsets
+    std::vector<int64_t> gedge_h;  // [ngraph + 1] base-store offsets of each graph's rows
+    std::vector<int64_t> gm_h;     // live edges per graph
+    int32_t *goff = nullptr;
+    int32_t *gstat = nullptr;
     // edge store
     uint32_t *bptr = nullptr;
     int32_t *bcol = nullptr;
@@ -58,7 +79,7 @@ struct drsf_ctx {
     int32_t *tile_k = nullptr;
     int64_t ntiles = 0;
     uint64_t *dkey = nullptr;
-    int64_t dcap = 0;
+    int64_t dcap = 0, dtmax = 0;
     int64_t ndelta_bound = 0;
     uint64_t *dhash = nullptr;
     int32_t *dhpos = nullptr;
@@ -75,10 +96,13 @@ struct drsf_ctx {
     int64_t pcap = 0;
     // batch
     int64_t max_batch = 0;
-    int32_t *bedges = nullptr, *bchild = nullptr, *bslot = nullptr;
+    int32_t *bedges = nullptr, *bchild = nullptr, *bslot = nullptr, *bgid = nullptr;
+    int8_t *bop = nullptr;
     uint64_t *bkey = nullptr, *bhash = nullptr;
     int64_t *bloc = nullptr;
     uint64_t bhmask = 0;
+    int32_t *lists = nullptr;      // vlist | ilist | tlist (several graphs)
+    int64_t nvblk = 0;
     // lists
     Cross *x0 = nullptr, *x1 = nullptr;
     int64_t xcap = 0;
@@ -90,11 +114,23 @@ struct drsf_ctx {
     int64_t pathcap = 0;
     int32_t *status = nullptr;
     unsigned long long *cnt = nullptr;
+    Ctl *ctl = nullptr;
     // pinned host staging
-    int32_t *h_edges = nullptr;
-    unsigned long long *h_ret = nullptr;  // [0] status, [1..] counters
+    int32_t *h_edges = nullptr;           // [2 max_batch]
+    int8_t *h_bop = nullptr;              // [max_batch]
+    int32_t *h_bgid = nullptr;            // [max_batch]
+    int32_t *h_lists = nullptr;           // vlist | ilist | tlist
+    Ctl *h_ctl = nullptr;
+    unsigned long long *h_ret = nullptr;  // [0] status, [1, 1 + C_COUNT) counters, then scratch
+    int32_t *h_gstat = nullptr;           // [ngraph]
+    // captured update sequence
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
     // last apply
     bool pending = false;
+    bool multi_last = false;
+    std::vector<int64_t> last_bg;  // per-graph batch sizes of the last apply
+    std::vector<int8_t> last_opg;  // per-graph op of the last apply
     int64_t last_b = 0;
     int last_op = 0;
     int last_rc = DRSF_OK;
@@ -118,16 +154,16 @@ int fail(drsf_ctx *c, int code, const char *fmt, ...) {
     return code;
 }
 
-#define HIPCHK(ctx, call)                                                                  \
-    do {                                                                                   \
-        hipError_t e_ = (call);                                                            \
-        if (e_ != hipSuccess)                                                              \
-            return fail((ctx), DRSF_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+#define HIPCHK(ctx, call)                                                                      \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail((ctx), DRSF_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_));  \
     } while (0)
 
 template <class T>
 int dalloc(drsf_ctx *c, T **p, int64_t count) {
-    size_t bytes = sizeof(T) * (size_t)(count > 0 ? count : 1);
+    const size_t bytes = sizeof(T) * (size_t)(count > 0 ? count : 1);
     void *q = nullptr;
     if (hipMalloc(&q, bytes) != hipSuccess) {
         (void)hipGetLastError();
@@ -138,6 +174,16 @@ int dalloc(drsf_ctx *c, T **p, int64_t count) {
     return DRSF_OK;
 }
 
+template <class T>
+int halloc(drsf_ctx *c, T **p, int64_t count) {
+    if (hipHostMalloc((void **)p, sizeof(T) * (size_t)(count > 0 ? count : 1)) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(c, DRSF_E_NOMEM, "pinned host allocation failed");
+    }
+    return DRSF_OK;
+}
+
 void dfree(drsf_ctx *c, void *p) {
     if (!p) return;
     auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
@@ -145,24 +191,31 @@ void dfree(drsf_ctx *c, void *p) {
     (void)hipFree(p);
 }
 
-Dev make_dev(drsf_ctx *c, int op, int64_t b) {
+Dev make_dev(drsf_ctx *c) {
     Dev d;
     memset(&d, 0, sizeof d);
     d.n = c->n;
-    d.op = op;
+    d.ctl = c->ctl;
     d.bptr = c->bptr; d.bcol = c->bcol; d.eb = c->eb;
     d.zrow = c->zrow; d.zptr = c->zptr; d.nz = c->nz; d.tile_k = c->tile_k; d.ntiles = c->ntiles;
+    d.dtmax = c->dtmax;
     d.dkey = c->dkey; d.dcap = c->dcap; d.dhash = c->dhash; d.dhpos = c->dhpos; d.dhmask = c->dhmask;
     d.parent = c->parent; d.label = c->label; d.rep = c->rep;
-    d.repv = op == DRSF_DELETE ? c->rep : c->label;
     d.obits = c->obits;
-    d.tidx = c->tidx; d.owner = c->owner; d.pkeep = c->pkeep; d.prt = c->prt; d.pmin = c->pmin; d.comp = c->comp; d.hook = c->hook;
+    d.tidx = c->tidx; d.owner = c->owner; d.pkeep = c->pkeep; d.prt = c->prt; d.pmin = c->pmin;
+    d.comp = c->comp; d.hook = c->hook;
     d.best = c->best; d.srkey = c->srkey; d.head = c->head; d.newlab = c->newlab;
     d.level = c->level; d.parc = c->parc; d.pcap = c->pcap;
-    d.bedges = c->bedges; d.b = b; d.bkey = c->bkey; d.bloc = c->bloc; d.bchild = c->bchild;
+    d.bedges = c->bedges; d.bop = c->bop;
+    d.bgid = c->ngraph > 1 ? c->bgid : nullptr;
+    d.goff = c->ngraph > 1 ? c->goff : nullptr;
+    d.gstat = c->gstat; d.max_b = c->max_batch;
+    d.bkey = c->bkey; d.bloc = c->bloc; d.bchild = c->bchild;
     d.bslot = c->bslot; d.bhash = c->bhash; d.bhmask = c->bhmask;
+    d.vlist = c->lists;
+    d.ilist = c->lists ? c->lists + c->nvblk : nullptr;
+    d.tlist = c->lists ? c->lists + 2 * c->nvblk : nullptr;
     d.x0 = c->x0; d.x1 = c->x1; d.xcap = c->xcap; d.rcnt = c->rcnt;
-    d.nreg = op == DRSF_DELETE ? c->ntiles + delta_tiles(c->ndelta_bound) : insert_regions(b);
     d.er = c->er; d.ercap = c->ercap; d.arc_nxt = c->arc_nxt;
     d.succ0 = c->succ0; d.succ1 = c->succ1; d.rank0 = c->rank0; d.rank1 = c->rank1;
     d.paths = c->paths; d.pathcap = c->pathcap;
@@ -181,12 +234,13 @@ int alloc_state(drsf_ctx *c) {
     int rc;
     const int32_t n = c->n;
     const int64_t mb = c->max_batch;
+    hipStream_t s = c->stream;
     if ((rc = dalloc(c, &c->label, n))) return rc;
     if ((rc = dalloc(c, &c->rep, n))) return rc;
     if ((rc = dalloc(c, &c->obits, (n + 63) / 64))) return rc;
     if ((rc = dalloc(c, &c->tidx, n))) return rc;
     if ((rc = dalloc(c, &c->owner, n))) return rc;
-    c->pcap = 2 * mb + 16;
+    c->pcap = 2 * mb + 16;  // a batch edge registers at most two pieces
     if ((rc = dalloc(c, &c->pkeep, c->pcap))) return rc;
     if ((rc = dalloc(c, &c->prt, c->pcap))) return rc;
     if ((rc = dalloc(c, &c->pmin, c->pcap))) return rc;
@@ -199,6 +253,8 @@ int alloc_state(drsf_ctx *c) {
     if ((rc = dalloc(c, &c->best, c->pcap))) return rc;
     if ((rc = dalloc(c, &c->srkey, c->pcap))) return rc;
     if ((rc = dalloc(c, &c->bedges, 2 * mb))) return rc;
+    if ((rc = dalloc(c, &c->bop, mb))) return rc;
+    if ((rc = dalloc(c, &c->bgid, mb))) return rc;
     if ((rc = dalloc(c, &c->bkey, mb))) return rc;
     if ((rc = dalloc(c, &c->bloc, mb))) return rc;
     if ((rc = dalloc(c, &c->bchild, mb))) return rc;
@@ -209,20 +265,19 @@ int alloc_state(drsf_ctx *c) {
     if ((rc = dalloc(c, &c->bhash, (int64_t)bh))) return rc;
     c->dcap = c->opts.delta_capacity > 0 ? c->opts.delta_capacity
                                          : std::max<int64_t>({4 * mb, c->eb / 8, 1 << 20});
+    c->dtmax = delta_tiles(c->dcap);
     if ((rc = dalloc(c, &c->dkey, c->dcap))) return rc;
     uint64_t dh = 16;
     while (dh < (uint64_t)(2 * c->dcap)) dh <<= 1;
     c->dhmask = dh - 1;
     if ((rc = dalloc(c, &c->dhash, (int64_t)dh))) return rc;
     if ((rc = dalloc(c, &c->dhpos, (int64_t)dh))) return rc;
-    // x0: one region of TILE entries per producing workgroup (base-store tiles
-    // and inserted-edge tiles on delete, batch tiles on insert)
-    const int64_t nregmax = std::max<int64_t>(c->ntiles + delta_tiles(c->dcap), insert_regions(mb));
+    // x0 regions: base-store tiles, inserted-edge tiles, then batch regions
+    const int64_t nregmax = c->ntiles + c->dtmax + insert_regions(mb);
     c->xcap = nregmax * TILE;
     if ((rc = dalloc(c, &c->x0, c->xcap))) return rc;
     if ((rc = dalloc(c, &c->x1, c->xcap))) return rc;
     if ((rc = dalloc(c, &c->rcnt, nregmax))) return rc;
-    launch_fill_u64(c->rcnt, nregmax, 0, c->stream);
     c->ercap = c->pcap;
     if ((rc = dalloc(c, &c->er, c->ercap))) return rc;
     if ((rc = dalloc(c, &c->arc_nxt, 2 * c->ercap))) return rc;
@@ -232,32 +287,50 @@ int alloc_state(drsf_ctx *c) {
     if ((rc = dalloc(c, &c->rank1, 2 * c->ercap))) return rc;
     c->pathcap = std::max<int64_t>(c->ercap + c->pcap, n);
     if ((rc = dalloc(c, &c->paths, c->pathcap))) return rc;
-    if (hipHostMalloc((void **)&c->h_edges, sizeof(int32_t) * 2 * (size_t)mb) != hipSuccess)
-        return fail(c, DRSF_E_NOMEM, "pinned host allocation failed");
-    launch_fill_i32(c->tidx, n, NONE, c->stream);
-    launch_fill_u64(c->bhash, (int64_t)bh, HASH_EMPTY, c->stream);
-    launch_fill_u64(c->dhash, (int64_t)dh, HASH_EMPTY, c->stream);
-    launch_fill_u64(c->obits, (n + 63) / 64, 0, c->stream);
+    if ((rc = dalloc(c, &c->ctl, 1))) return rc;
+    if ((rc = dalloc(c, &c->gstat, c->ngraph))) return rc;
+    if (c->ngraph > 1) {
+        // every vertex block and every tile appears at most once per list
+        c->nvblk = (n + BLOCK - 1) / BLOCK;
+        const int64_t nl = 2 * c->nvblk + c->ntiles + 1;
+        if ((rc = dalloc(c, &c->lists, nl))) return rc;
+        if ((rc = halloc(c, &c->h_lists, nl))) return rc;
+    }
+    if ((rc = halloc(c, &c->h_edges, 2 * mb))) return rc;
+    if ((rc = halloc(c, &c->h_bop, mb))) return rc;
+    if ((rc = halloc(c, &c->h_bgid, mb))) return rc;
+    if ((rc = halloc(c, &c->h_ctl, 1))) return rc;
+    if ((rc = halloc(c, &c->h_gstat, c->ngraph))) return rc;
+    launch_fill_i32(c->tidx, n, NONE, s);
+    launch_fill_u64(c->bhash, (int64_t)bh, HASH_EMPTY, s);
+    launch_fill_u64(c->dhash, (int64_t)dh, HASH_EMPTY, s);
+    launch_fill_u64(c->obits, (n + 63) / 64, 0, s);
+    launch_fill_u64(c->rcnt, nregmax, 0, s);
+    launch_fill_i32(c->gstat, c->ngraph, 0, s);
     return DRSF_OK;
 }
 
 void destroy_ctx(drsf_ctx *c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
     for (void *p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
-    if (c->h_edges) (void)hipHostFree(c->h_edges);
-    if (c->h_ret) (void)hipHostFree(c->h_ret);
+    void *hosts[] = {c->h_edges, c->h_bop, c->h_bgid, c->h_lists, c->h_ctl, c->h_ret, c->h_gstat};
+    for (void *p : hosts)
+        if (p) (void)hipHostFree(p);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
 
-// Build the device edge store from a symmetric CSR with ascending rows.
+// Builds the device edge store from a symmetric CSR with ascending rows.
 int build_store(drsf_ctx *c, const int64_t *row_ptr_in, const int32_t *col_in, int64_t nnz) {
     int rc;
     const int32_t n = c->n;
+    hipStream_t s = c->stream;
     const bool dev_in = c->opts.inputs_on_device != 0;
     int64_t *drow = nullptr;
     int32_t *dcol = nullptr;
@@ -268,49 +341,56 @@ int build_store(drsf_ctx *c, const int64_t *row_ptr_in, const int32_t *col_in, i
         if ((rc = dalloc(c, &drow, (int64_t)n + 1))) return rc;
         if ((rc = dalloc(c, &dcol, nnz))) return rc;
         HIPCHK(c, hipMemcpyAsync(drow, row_ptr_in, sizeof(int64_t) * ((size_t)n + 1),
-                                 hipMemcpyHostToDevice, c->stream));
+                                 hipMemcpyHostToDevice, s));
         if (nnz > 0)
             HIPCHK(c, hipMemcpyAsync(dcol, col_in, sizeof(int32_t) * (size_t)nnz,
-                                     hipMemcpyHostToDevice, c->stream));
+                                     hipMemcpyHostToDevice, s));
     }
     uint32_t *ucnt = nullptr;
-    void *tmp = nullptr;
+    char *tmp = nullptr;
     if ((rc = dalloc(c, &ucnt, n))) return rc;
-    if ((rc = dalloc(c, (char **)&tmp, (int64_t)scan_tmp_bytes(n) + 64))) return rc;
+    if ((rc = dalloc(c, &tmp, (int64_t)scan_tmp_bytes(n) + 64))) return rc;
     if ((rc = dalloc(c, &c->bptr, (int64_t)n + 1))) return rc;
-    unsigned long long *dtotal = (unsigned long long *)((char *)tmp + scan_tmp_bytes(n));
-    launch_fill_i32(c->status, 1, 0, c->stream);
-    launch_csr_check(n, drow, dcol, ucnt, c->status, c->stream);
-    launch_csr_symmetric(n, drow, dcol, c->status, c->stream);
-    launch_scan_u32(ucnt, c->bptr, dtotal, n, tmp, c->stream);
-    unsigned long long total = 0;
-    HIPCHK(c, hipMemcpyAsync(c->h_ret, dtotal, sizeof total, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->h_ret + 1, c->status, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    total = c->h_ret[0];
-    int32_t st = *(int32_t *)(c->h_ret + 1);
-    if (st & 1) return fail(c, DRSF_E_ARG, "CSR rows must be ascending, without self-loops, ids in [0,n)");
-    if (st & 2) return fail(c, DRSF_E_ARG, "CSR is not symmetric");
-    if (2 * (int64_t)total != nnz) return fail(c, DRSF_E_ARG, "CSR is not symmetric");
+    unsigned long long *dtotal = (unsigned long long *)(tmp + scan_tmp_bytes(n));
+    launch_fill_i32(c->status, 1, 0, s);
+    launch_csr_check(n, drow, dcol, ucnt, c->status, c->ngraph > 1 ? c->goff : nullptr, c->ngraph, s);
+    launch_csr_symmetric(n, drow, dcol, c->status, s);
+    launch_scan_u32(ucnt, c->bptr, dtotal, n, tmp, s);
+    HIPCHK(c, hipMemcpyAsync(c->h_ret, dtotal, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_ret + 1, c->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    const unsigned long long total = c->h_ret[0];
+    const int32_t st = *(int32_t *)(c->h_ret + 1);
+    if (st & 1)
+        return fail(c, DRSF_E_ARG, "CSR rows must be strictly ascending, without self-loops, with ids in range%s",
+                    c->ngraph > 1 ? " of the row's graph" : "");
+    if ((st & 2) || 2 * (int64_t)total != nnz) return fail(c, DRSF_E_ARG, "CSR is not symmetric");
     if (total >= 0xffffffffull) return fail(c, DRSF_E_CAPACITY, "more than 2^32-1 undirected edges");
     c->eb = (int64_t)total;
     if ((rc = dalloc(c, &c->bcol, c->eb))) return rc;
-    launch_upper_fill(n, drow, dcol, c->bptr, c->bcol, c->stream);
+    launch_upper_fill(n, drow, dcol, c->bptr, c->bcol, s);
     // non-empty-row index for the sweep
-    launch_nonempty_flags(n, c->bptr, ucnt, c->stream);
+    launch_nonempty_flags(n, c->bptr, ucnt, s);
     uint32_t *zpos = nullptr;
     if ((rc = dalloc(c, &zpos, (int64_t)n + 1))) return rc;
-    launch_scan_u32(ucnt, zpos, dtotal, n, tmp, c->stream);
-    HIPCHK(c, hipMemcpyAsync(c->h_ret, dtotal, sizeof total, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    launch_scan_u32(ucnt, zpos, dtotal, n, tmp, s);
+    HIPCHK(c, hipMemcpyAsync(c->h_ret, dtotal, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
     c->nz = (int64_t)c->h_ret[0];
     if ((rc = dalloc(c, &c->zrow, c->nz))) return rc;
     if ((rc = dalloc(c, &c->zptr, c->nz + 1))) return rc;
-    launch_nonempty_fill(n, c->bptr, zpos, c->zrow, c->zptr, c->nz, c->stream);
+    launch_nonempty_fill(n, c->bptr, zpos, c->zrow, c->zptr, c->nz, s);
     c->ntiles = (c->eb + TILE - 1) / TILE;
     if ((rc = dalloc(c, &c->tile_k, c->ntiles + 1))) return rc;
-    launch_tile_k(c->zptr, c->nz, c->eb, c->tile_k, c->ntiles, c->stream);
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    launch_tile_k(c->zptr, c->nz, c->eb, c->tile_k, c->ntiles, s);
+    // base-store offsets of each graph's rows (host copy, for the tile lists)
+    std::vector<uint32_t> bp((size_t)n + 1);
+    HIPCHK(c, hipMemcpyAsync(bp.data(), c->bptr, sizeof(uint32_t) * bp.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    c->gedge_h.assign((size_t)c->ngraph + 1, 0);
+    c->gm_h.assign((size_t)c->ngraph, 0);
+    for (int32_t g = 0; g <= c->ngraph; g++) c->gedge_h[g] = bp[c->goff_h[g]];
+    for (int32_t g = 0; g < c->ngraph; g++) c->gm_h[g] = c->gedge_h[g + 1] - c->gedge_h[g];
     dfree(c, zpos);
     dfree(c, ucnt);
     dfree(c, tmp);
@@ -319,11 +399,10 @@ int build_store(drsf_ctx *c, const int64_t *row_ptr_in, const int32_t *col_in, i
     return DRSF_OK;
 }
 
-// Check the forest (optional) and root every tree at its smallest vertex.
+// Checks the forest (optional) and roots every tree at its smallest vertex.
 int canonicalise_forest(drsf_ctx *c) {
     const int32_t n = c->n;
     hipStream_t s = c->stream;
-    Dev d = make_dev(c, DRSF_INSERT, 0);
     launch_fill_i32(c->status, 1, 0, s);
     launch_fill_u64(c->cnt, C_TOTAL, 0, s);
     launch_forest_check(n, c->bptr, c->bcol, c->parent, c->status, c->opts.validate_forest, s);
@@ -341,35 +420,207 @@ int canonicalise_forest(drsf_ctx *c) {
         std::swap(a, b);
     }
     int32_t *root = a;
-    int32_t *other = b;
-    launch_roots_check(n, c->parent, root, c->status, s);
-    if (c->opts.validate_forest) launch_span_check(d, root, s);
-    if ((rc = read_status(c, &st))) return rc;
-    if (st & 4) return fail(c, DRSF_E_FOREST, "parent[] contains a cycle");
-    if (st & 8) return fail(c, DRSF_E_FOREST, "a tree does not span its connected component");
-    // label <- smallest vertex of each tree; re-root where it is not the root
-    int32_t *lab = c->label;
     if (root == c->label) {  // keep roots in rep, labels in label
         HIPCHK(c, hipMemcpyAsync(c->rep, root, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
         root = c->rep;
     }
-    (void)other;
-    launch_tree_min(n, root, lab, s);
-    d = make_dev(c, DRSF_INSERT, 0);
+    launch_roots_check(n, c->parent, root, c->status, s);
+    const Dev d = make_dev(c);
+    if (c->opts.validate_forest) launch_span_check(d, root, s);
+    if ((rc = read_status(c, &st))) return rc;
+    if (st & 4) return fail(c, DRSF_E_FOREST, "parent[] contains a cycle");
+    if (st & 8) return fail(c, DRSF_E_FOREST, "a tree does not span its connected component");
+    // label <- smallest vertex of each tree; re-root where that is not the root
+    launch_tree_min(n, root, c->label, s);
     launch_reroot_requests(d, root, s);
-    launch_reverse(d, s);
+    launch_reverse_all(d, s);
     if ((rc = read_status(c, &st))) return rc;
     if (st) return fail(c, DRSF_E_DEVICE, "re-rooting failed (status %d)", st);
     launch_fill_u64(c->cnt, C_TOTAL, 0, s);
+    // invariant between updates: rep == label
+    HIPCHK(c, hipMemcpyAsync(c->rep, c->label, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
     HIPCHK(c, hipStreamSynchronize(s));
     return DRSF_OK;
+}
+
+void enqueue_results_copy(drsf_ctx *c) {
+    hipStream_t s = c->stream;
+    (void)hipMemcpyAsync(c->h_ret, c->status, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(c->h_ret + 1, c->cnt, sizeof(unsigned long long) * C_COUNT,
+                         hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(c->h_gstat, c->gstat, sizeof(int32_t) * (size_t)c->ngraph,
+                         hipMemcpyDeviceToHost, s);
+}
+
+// The update sequence (see the file comment); with events when profiling.
+void enqueue_update(drsf_ctx *c, bool profile) {
+    const Dev d = make_dev(c);
+    hipStream_t s = c->stream;
+    auto mark = [&](int i) {
+        if (profile) (void)hipEventRecord(c->ev[i], s);
+    };
+    mark(PH_VALIDATE);
+    launch_classify(d, s);
+    mark(PH_UPDATE);
+    launch_prepare(d, s);
+    launch_register(d, s);
+    mark(PH_ROOTS);
+    launch_rep(d, s);
+    mark(PH_SWEEP);
+    launch_sweep_base(d, s);
+    mark(PH_SWEEP_DELTA);
+    launch_insert_emit(d, s);
+    launch_sweep_delta(d, s);
+    mark(PH_REPL);
+    launch_boruvka(d, 0, BOR_FAST, s);
+    mark(PH_ROOTING);
+    launch_sf_root(d, s);
+    launch_sf_bfs(d, 0, BFS_FAST, s);
+    launch_orient_bfs(d, BFS_FAST, s);
+    mark(PH_REVERSE);
+    launch_reverse(d, s);
+    mark(PH_LABELS);
+    launch_labels(d, s);
+    mark(PH_N);
+    enqueue_results_copy(c);
+    launch_cleanup(d, s);
+}
+
+int capture_graph(drsf_ctx *c) {
+    if (c->gexec) return DRSF_OK;
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    enqueue_update(c, false);
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamEndCapture(c->stream, &g));
+    c->graph = g;
+    HIPCHK(c, hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0));
+    return DRSF_OK;
+}
+
+// Finishes an update that the captured sequence left unfinished: more
+// hooking rounds in short chunks, deeper search or the Euler tour, then
+// reversal, labels and cleanup.
+int continue_update(drsf_ctx *c) {
+    const Dev d = make_dev(c);
+    hipStream_t s = c->stream;
+    unsigned long long *f = c->h_ret + 1 + C_COUNT;  // [0] status, [1] rounds done, [2] level active
+    auto read_flags = [&](int levels) -> int {
+        HIPCHK(c, hipMemcpyAsync(f, c->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(f + 1, c->cnt + C_DONE_BOR, sizeof(unsigned long long),
+                                 hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(f + 2, c->cnt + C_BFS_ROUND + levels - 1, sizeof(unsigned long long),
+                                 hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        return DRSF_OK;
+    };
+    const int64_t np_max = c->pcap;
+    // each round at least halves the components that still have a live edge
+    const int bor_bound = std::min(ceil_log2(np_max + 2) + 2, MAX_ROUNDS);
+    const int lr_rounds = std::min(ceil_log2(2 * np_max + 2) + 2, MAX_ROUNDS);
+    int rc;
+    if ((rc = read_flags(BFS_FAST))) return rc;
+    bool bad = *(int32_t *)f != 0, done = f[1] != 0, bfs_done = f[2] == 0;
+    int r = BOR_FAST, lv = BFS_FAST;
+    if (!bad && !done) {
+        while (!done && !bad && r < bor_bound) {
+            const int r1 = std::min(r + BOR_CHUNK, bor_bound);
+            launch_boruvka(d, r, r1, s);
+            r = r1;
+            if ((rc = read_flags(lv))) return rc;
+            bad = *(int32_t *)f != 0;
+            done = f[1] != 0;
+        }
+        if (!bad && !done) {
+            launch_fill_i32(c->status, 1, ST_ROUND_BOUND, s);
+            bad = true;
+        }
+        if (!bad) {
+            launch_sf_root(d, s);
+            launch_sf_bfs(d, 0, BFS_FAST, s);
+            if ((rc = read_flags(lv))) return rc;
+            bad = *(int32_t *)f != 0;
+            bfs_done = f[2] == 0;
+        }
+    }
+    if (!bad) {
+        while (!bfs_done && lv < BFS_MAX) {
+            launch_sf_bfs(d, lv, lv + BFS_FAST, s);
+            lv += BFS_FAST;
+            if ((rc = read_flags(lv))) return rc;
+            bfs_done = f[2] == 0;
+        }
+        if (bfs_done) launch_orient_bfs(d, lv, s);
+        else launch_superforest_lr(d, lr_rounds, s);  // deep super-trees: Euler tour
+        launch_reverse(d, s);
+        launch_labels(d, s);
+    }
+    enqueue_results_copy(c);
+    launch_cleanup(d, s);
+    HIPCHK(c, hipStreamSynchronize(s));
+    return DRSF_OK;
+}
+
+// Queues one update whose batch is in the device batch buffers and whose
+// control block is in h_ctl.
+int launch_update(drsf_ctx *c) {
+    hipStream_t s = c->stream;
+    HIPCHK(c, hipMemcpyAsync(c->ctl, c->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, s));
+    const bool prof = c->opts.profile != 0;
+    if (prof) {
+        enqueue_update(c, true);
+    } else {
+        int rc;
+        if ((rc = capture_graph(c))) return rc;
+        HIPCHK(c, hipGraphLaunch(c->gexec, s));
+    }
+    HIPCHK(c, hipGetLastError());
+    c->pending = true;
+    c->have_phases = prof;
+    return DRSF_OK;
+}
+
+// Regions of x0 the first hooking rounds read (see Dev::x0).
+void set_regions(drsf_ctx *c, Ctl &k) {
+    k.ibase = c->ntiles + c->dtmax;
+    const int64_t dreg = c->ntiles + delta_tiles(c->ndelta_bound);
+    if (k.has_ins && k.has_del) {
+        k.rlo = 0;
+        k.rhi = k.ibase + insert_regions(k.b);
+    } else if (k.has_del) {
+        k.rlo = 0;
+        k.rhi = dreg;
+    } else {
+        k.rlo = k.ibase;
+        k.rhi = k.ibase + insert_regions(k.b);
+    }
+}
+
+int stage_edges(drsf_ctx *c, const int32_t *edges, int64_t b) {
+    if (b == 0) return DRSF_OK;
+    hipStream_t s = c->stream;
+    if (c->opts.inputs_on_device) {
+        HIPCHK(c, hipMemcpyAsync(c->bedges, edges, sizeof(int32_t) * 2 * (size_t)b,
+                                 hipMemcpyDeviceToDevice, s));
+    } else {
+        // the previous update has completed, so the pinned staging is free
+        memcpy(c->h_edges, edges, sizeof(int32_t) * 2 * (size_t)b);
+        HIPCHK(c, hipMemcpyAsync(c->bedges, c->h_edges, sizeof(int32_t) * 2 * (size_t)b,
+                                 hipMemcpyHostToDevice, s));
+    }
+    return DRSF_OK;
+}
+
+int finish_pending(drsf_ctx *c) {
+    if (!c->pending) return DRSF_OK;
+    const int rc = drsf_wait(c, nullptr);
+    return (rc == DRSF_OK || rc == DRSF_E_BATCH) ? DRSF_OK : rc;
 }
 
 }  // namespace
 
 extern "C" {
 
-const char *drsf_version(void) { return "drsf 0.1 (gfx950)"; }
+const char *drsf_version(void) { return "drsf 0.2 (gfx950)"; }
 
 void drsf_default_opts(drsf_opts *o) {
     if (!o) return;
@@ -382,24 +633,33 @@ const char *drsf_last_error(const drsf_ctx *c) {
     return c ? c->err.c_str() : g_create_error.c_str();
 }
 
-int drsf_create(int32_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *parent,
-                const drsf_opts *opts, drsf_ctx **out) {
-    if (!out) return fail(nullptr, DRSF_E_ARG, "out is NULL");
+static int create_impl(int32_t G, const int32_t *n_off, int32_t n, const int64_t *row_ptr,
+                       const int32_t *col, const int32_t *parent, const drsf_opts *opts,
+                       drsf_ctx **out) {
     *out = nullptr;
-    if (n < 1 || !row_ptr || !parent) return fail(nullptr, DRSF_E_ARG, "bad arguments");
+    if (n < 1 || !row_ptr || !parent) return fail(nullptr, DRSF_E_ARG, "n must be >= 1; row_ptr and parent non-NULL");
     drsf_ctx *c = new drsf_ctx();
     if (opts) c->opts = *opts; else drsf_default_opts(&c->opts);
     if (c->opts.max_batch <= 0) c->opts.max_batch = 1 << 20;
     c->max_batch = c->opts.max_batch;
     c->n = n;
+    c->ngraph = G;
+    c->goff_h.assign((size_t)G + 1, 0);
+    if (n_off) for (int32_t g = 0; g <= G; g++) c->goff_h[g] = n_off[g];
+    else c->goff_h[1] = n;
     int rc = DRSF_OK;
     auto bail = [&](int code) {
         g_create_error = c->err;
         destroy_ctx(c);
         return code;
     };
+    for (int32_t g = 0; g < G; g++)
+        if (c->goff_h[g + 1] < c->goff_h[g]) {
+            fail(c, DRSF_E_ARG, "graph vertex offsets must be non-decreasing");
+            return bail(DRSF_E_ARG);
+        }
     {
-        hipError_t e = hipGetDevice(&c->dev);
+        const hipError_t e = hipGetDevice(&c->dev);
         if (e != hipSuccess) {
             fail(c, DRSF_E_DEVICE, "no HIP device: %s", hipGetErrorString(e));
             return bail(DRSF_E_DEVICE);
@@ -414,14 +674,20 @@ int drsf_create(int32_t n, const int64_t *row_ptr, const int32_t *col, const int
         }
         c->own_stream = true;
     }
-    if (hipHostMalloc((void **)&c->h_ret, sizeof(unsigned long long) * (C_TOTAL + 16)) != hipSuccess) {
-        fail(c, DRSF_E_NOMEM, "pinned host allocation failed");
-        return bail(DRSF_E_NOMEM);
-    }
+    if ((rc = halloc(c, &c->h_ret, C_TOTAL + 16))) return bail(rc);
     for (auto &e : c->ev)
-        if (hipEventCreate(&e) != hipSuccess) { fail(c, DRSF_E_DEVICE, "event creation failed"); return bail(DRSF_E_DEVICE); }
+        if (hipEventCreate(&e) != hipSuccess) {
+            fail(c, DRSF_E_DEVICE, "event creation failed");
+            return bail(DRSF_E_DEVICE);
+        }
     if ((rc = dalloc(c, &c->status, 4))) return bail(rc);
     if ((rc = dalloc(c, &c->cnt, C_TOTAL))) return bail(rc);
+    if ((rc = dalloc(c, &c->goff, (int64_t)G + 1))) return bail(rc);
+    if (hipMemcpy(c->goff, c->goff_h.data(), sizeof(int32_t) * ((size_t)G + 1), hipMemcpyHostToDevice) !=
+        hipSuccess) {
+        fail(c, DRSF_E_DEVICE, "cannot copy graph offsets");
+        return bail(DRSF_E_DEVICE);
+    }
     launch_fill_u64(c->cnt, C_TOTAL, 0, c->stream);
     // row offsets are checked on the host before any kernel reads through them
     std::vector<int64_t> hrow;
@@ -435,11 +701,20 @@ int drsf_create(int32_t n, const int64_t *row_ptr, const int32_t *col, const int
         }
         rp = hrow.data();
     }
-    if (rp[0] != 0) { fail(c, DRSF_E_ARG, "row_ptr[0] must be 0"); return bail(DRSF_E_ARG); }
+    if (rp[0] != 0) {
+        fail(c, DRSF_E_ARG, "row_ptr[0] must be 0");
+        return bail(DRSF_E_ARG);
+    }
     for (int32_t u = 0; u < n; u++)
-        if (rp[u + 1] < rp[u]) { fail(c, DRSF_E_ARG, "row_ptr must be non-decreasing"); return bail(DRSF_E_ARG); }
+        if (rp[u + 1] < rp[u]) {
+            fail(c, DRSF_E_ARG, "row_ptr must be non-decreasing");
+            return bail(DRSF_E_ARG);
+        }
     const int64_t nnz = rp[n];
-    if (nnz > 0 && !col) { fail(c, DRSF_E_ARG, "col is NULL"); return bail(DRSF_E_ARG); }
+    if (nnz > 0 && !col) {
+        fail(c, DRSF_E_ARG, "col is NULL");
+        return bail(DRSF_E_ARG);
+    }
     if ((rc = build_store(c, row_ptr, col, nnz))) return bail(rc);
     if ((rc = dalloc(c, &c->parent, n))) return bail(rc);
     if (hipMemcpyAsync(c->parent, parent, sizeof(int32_t) * (size_t)n,
@@ -458,21 +733,36 @@ int drsf_create(int32_t n, const int64_t *row_ptr, const int32_t *col, const int
     return DRSF_OK;
 }
 
+int drsf_create(int32_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *parent,
+                const drsf_opts *opts, drsf_ctx **out) {
+    if (!out) return fail(nullptr, DRSF_E_ARG, "out is NULL");
+    return create_impl(1, nullptr, n, row_ptr, col, parent, opts, out);
+}
+
+int drsf_multi_create(int32_t G, const int32_t *n_off, const int64_t *row_ptr, const int32_t *col,
+                      const int32_t *parent, const drsf_opts *opts, drsf_ctx **out) {
+    if (!out) return fail(nullptr, DRSF_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (G < 1 || !n_off) return fail(nullptr, DRSF_E_ARG, "G must be >= 1 and n_off non-NULL");
+    if (n_off[0] != 0) return fail(nullptr, DRSF_E_ARG, "n_off[0] must be 0");
+    return create_impl(G, n_off, n_off[G], row_ptr, col, parent, opts, out);
+}
+
+int drsf_num_graphs(const drsf_ctx *c) { return c ? c->ngraph : 0; }
+
 int drsf_apply_async(drsf_ctx *c, const int32_t *edges, int64_t b, int op) {
     if (!c) return DRSF_E_ARG;
-    if (c->pending) {
-        int rc = drsf_wait(c, nullptr);
-        if (rc != DRSF_OK && rc != DRSF_E_BATCH) return rc;
-    }
+    int rc;
+    if ((rc = finish_pending(c))) return rc;
+    if (c->ngraph != 1) return fail(c, DRSF_E_STATE, "the context holds several graphs: use drsf_multi_apply");
     if (op != DRSF_INSERT && op != DRSF_DELETE) return fail(c, DRSF_E_ARG, "op must be insert or delete");
     if (b < 0 || (b > 0 && !edges)) return fail(c, DRSF_E_ARG, "bad batch");
-    if (b > c->max_batch) return fail(c, DRSF_E_CAPACITY, "batch of %lld exceeds max_batch %lld",
-                                      (long long)b, (long long)c->max_batch);
-    c->last_b = b;
-    c->last_op = op;
+    if (b > c->max_batch)
+        return fail(c, DRSF_E_CAPACITY, "batch of %lld exceeds max_batch %lld", (long long)b,
+                    (long long)c->max_batch);
     c->have_phases = false;
+    c->multi_last = false;
     if (b == 0) {
-        c->pending = false;
         c->last_rc = DRSF_OK;
         c->view.num_key_cross = c->view.num_replacement = c->view.num_pieces = c->view.num_paths = 0;
         return DRSF_OK;
@@ -480,105 +770,103 @@ int drsf_apply_async(drsf_ctx *c, const int32_t *edges, int64_t b, int op) {
     if (op == DRSF_INSERT && c->ndelta_bound + b > c->dcap)
         return fail(c, DRSF_E_CAPACITY, "inserted-edge store full (%lld of %lld)",
                     (long long)c->ndelta_bound, (long long)c->dcap);
-    hipStream_t s = c->stream;
-    if (c->opts.inputs_on_device) {
-        HIPCHK(c, hipMemcpyAsync(c->bedges, edges, sizeof(int32_t) * 2 * (size_t)b,
-                                 hipMemcpyDeviceToDevice, s));
-    } else {
-        // the previous apply has completed (pending was cleared), so the
-        // pinned staging buffer is free
-        memcpy(c->h_edges, edges, sizeof(int32_t) * 2 * (size_t)b);
-        HIPCHK(c, hipMemcpyAsync(c->bedges, c->h_edges, sizeof(int32_t) * 2 * (size_t)b,
-                                 hipMemcpyHostToDevice, s));
-    }
-    const Dev d = make_dev(c, op, b);
-    const bool prof = c->opts.profile != 0;
-    auto mark = [&](int i) { if (prof) (void)hipEventRecord(c->ev[i], s); };
-    const int64_t np_max = std::min<int64_t>(2 * b, c->pcap);
-    const int bor_bound = std::min(ceil_log2(np_max + 2) + 2, MAX_ROUNDS);
-    const int lr_rounds = std::min(ceil_log2(2 * np_max + 2) + 2, MAX_ROUNDS);
-    mark(PH_VALIDATE);
-    launch_classify(d, s);
-    mark(PH_UPDATE);
-    launch_prepare(d, s);
-    launch_register(d, s);
-    mark(PH_ROOTS);
-    if (op == DRSF_DELETE) launch_rep(d, s);
-    mark(PH_SWEEP);
-    if (op == DRSF_DELETE) launch_sweep_base(d, s);
-    else launch_insert_emit(d, s);
-    mark(PH_SWEEP_DELTA);
-    if (op == DRSF_DELETE) launch_sweep_delta(d, c->ndelta_bound, s);
-    mark(PH_REPL);
-    // Hooking rounds run in short chunks; the host reads the device's done
-    // flag between chunks instead of queueing the worst-case number of
-    // rounds.  The first chunk is followed by speculative super-root and
-    // search levels that only run if the rounds have finished.
-    int r = op == DRSF_DELETE ? 2 : 4;
-    r = std::min(r, bor_bound);
-    launch_boruvka(d, 0, r, s);
-    launch_sf_root(d, s);
-    launch_sf_bfs(d, 0, BFS_CHUNK, s);
-    int lv = BFS_CHUNK;
-    unsigned long long *ctl = c->h_ret + 1 + C_COUNT;  // [status, done, bfs flag]
-    auto read_ctl = [&](int bfs_level) -> int {
-        HIPCHK(c, hipMemcpyAsync(ctl, c->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIPCHK(c, hipMemcpyAsync(ctl + 1, c->cnt + C_DONE_BOR, sizeof(unsigned long long),
-                                 hipMemcpyDeviceToHost, s));
-        HIPCHK(c, hipMemcpyAsync(ctl + 2, c->cnt + C_BFS_ROUND + bfs_level - 1,
-                                 sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-        HIPCHK(c, hipStreamSynchronize(s));
-        return DRSF_OK;
-    };
-    int rc2;
-    if ((rc2 = read_ctl(lv))) return rc2;
-    bool bad = *(int32_t *)ctl != 0;
-    bool done = ctl[1] != 0;
-    if (!bad && !done) {
-        while (!done && r < bor_bound) {
-            const int r1 = std::min(r + 3, bor_bound);
-            launch_boruvka(d, r, r1, s);
-            r = r1;
-            if ((rc2 = read_ctl(lv))) return rc2;
-            done = ctl[1] != 0;
-            bad = *(int32_t *)ctl != 0;
-            if (bad) break;
-        }
-        if (!bad && done) {
-            launch_sf_root(d, s);
-            launch_sf_bfs(d, 0, BFS_CHUNK, s);
-            if ((rc2 = read_ctl(lv))) return rc2;
-            bad = *(int32_t *)ctl != 0;
-        }
-    }
-    mark(PH_ROOTING);
-    if (!bad && !done) {
-        launch_fill_i32(c->status, 1, ST_ROUND_BOUND, s);  // hooking rounds did not finish
-    } else if (!bad) {
-        bool bfs_done = ctl[2] == 0;
-        while (!bfs_done && lv < BFS_MAX) {
-            launch_sf_bfs(d, lv, lv + BFS_CHUNK, s);
-            lv += BFS_CHUNK;
-            if ((rc2 = read_ctl(lv))) return rc2;
-            bfs_done = ctl[2] == 0;
-        }
-        if (bfs_done) launch_orient_bfs(d, s);
-        else launch_superforest_lr(d, lr_rounds, s);  // deep super-trees: Euler tour
-    }
-    mark(PH_REVERSE);
-    launch_reverse(d, s);
-    mark(PH_LABELS);
-    launch_labels(d, s);
-    mark(PH_N);
-    HIPCHK(c, hipMemcpyAsync(c->h_ret, c->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(c->h_ret + 1, c->cnt, sizeof(unsigned long long) * C_COUNT,
-                             hipMemcpyDeviceToHost, s));
-    launch_cleanup(d, s);
-    HIPCHK(c, hipGetLastError());
+    if ((rc = stage_edges(c, edges, b))) return rc;
+    c->last_b = b;
+    c->last_op = op;
+    Ctl &k = *c->h_ctl;
+    memset(&k, 0, sizeof k);
+    k.b = b;
+    k.op = op;
+    k.has_ins = op == DRSF_INSERT;
+    k.has_del = op == DRSF_DELETE;
+    k.ngraph = 1;
+    k.lfast = BFS_FAST;
+    k.nvl = k.nil = k.ntl = -1;
     if (op == DRSF_INSERT) c->ndelta_bound += b;
-    c->pending = true;
-    c->have_phases = prof;
-    return DRSF_OK;
+    set_regions(c, k);
+    return launch_update(c);
+}
+
+int drsf_multi_apply_async(drsf_ctx *c, const int32_t *edges, const int64_t *b_off, const int8_t *op) {
+    if (!c) return DRSF_E_ARG;
+    int rc;
+    if ((rc = finish_pending(c))) return rc;
+    if (!b_off || !op) return fail(c, DRSF_E_ARG, "b_off and op must be non-NULL");
+    const int32_t G = c->ngraph;
+    const int64_t b = b_off[G];
+    if (b_off[0] != 0 || b < 0 || (b > 0 && !edges)) return fail(c, DRSF_E_ARG, "bad batch offsets");
+    for (int32_t g = 0; g < G; g++)
+        if (b_off[g + 1] < b_off[g] || (op[g] != DRSF_INSERT && op[g] != DRSF_DELETE))
+            return fail(c, DRSF_E_ARG, "bad batch offsets or op for graph %d", g);
+    if (b > c->max_batch)
+        return fail(c, DRSF_E_CAPACITY, "batch of %lld exceeds max_batch %lld", (long long)b,
+                    (long long)c->max_batch);
+    int64_t nins = 0;
+    for (int32_t g = 0; g < G; g++)
+        if (op[g] == DRSF_INSERT) nins += b_off[g + 1] - b_off[g];
+    if (c->ndelta_bound + nins > c->dcap)
+        return fail(c, DRSF_E_CAPACITY, "inserted-edge store full (%lld of %lld)",
+                    (long long)c->ndelta_bound, (long long)c->dcap);
+    c->have_phases = false;
+    c->multi_last = true;
+    c->last_b = b;
+    c->last_bg.assign((size_t)G, 0);
+    c->last_opg.assign(op, op + G);
+    for (int32_t g = 0; g < G; g++) c->last_bg[g] = b_off[g + 1] - b_off[g];
+    if (b == 0) {
+        c->last_rc = DRSF_OK;
+        for (int32_t g = 0; g < G; g++) c->h_gstat[g] = 0;
+        c->view.num_key_cross = c->view.num_replacement = c->view.num_pieces = c->view.num_paths = 0;
+        return DRSF_OK;
+    }
+    // per-edge op and graph; vertex-block lists of the deleting and the
+    // inserting graphs and the base-store tiles of the deleting ones
+    bool any_ins = false, any_del = false;
+    for (int32_t g = 0; g < G; g++)
+        for (int64_t i = b_off[g]; i < b_off[g + 1]; i++) {
+            c->h_bop[i] = op[g];
+            c->h_bgid[i] = g;
+        }
+    int32_t *vl = c->h_lists, *il = c->h_lists + c->nvblk, *tl = c->h_lists + 2 * c->nvblk;
+    int64_t nvl = 0, nil = 0, ntl = 0, lastv = -1, lasti = -1, lastt = -1;
+    for (int32_t g = 0; g < G; g++) {
+        if (b_off[g + 1] == b_off[g] || c->goff_h[g + 1] == c->goff_h[g]) continue;
+        const int64_t v0 = c->goff_h[g] / BLOCK, v1 = (c->goff_h[g + 1] - 1) / BLOCK;
+        if (op[g] == DRSF_DELETE) {
+            any_del = true;
+            for (int64_t j = std::max(v0, lastv + 1); j <= v1; j++) vl[nvl++] = (int32_t)j;
+            lastv = std::max(lastv, v1);
+            if (c->gedge_h[g + 1] > c->gedge_h[g]) {
+                const int64_t t0 = c->gedge_h[g] / TILE, t1 = (c->gedge_h[g + 1] - 1) / TILE;
+                for (int64_t t = std::max(t0, lastt + 1); t <= t1; t++) tl[ntl++] = (int32_t)t;
+                lastt = std::max(lastt, t1);
+            }
+        } else {
+            any_ins = true;
+            for (int64_t j = std::max(v0, lasti + 1); j <= v1; j++) il[nil++] = (int32_t)j;
+            lasti = std::max(lasti, v1);
+        }
+    }
+    hipStream_t s = c->stream;
+    HIPCHK(c, hipMemcpyAsync(c->lists, c->h_lists, sizeof(int32_t) * (size_t)(2 * c->nvblk + c->ntiles + 1),
+                             hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->bop, c->h_bop, (size_t)b, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->bgid, c->h_bgid, sizeof(int32_t) * (size_t)b, hipMemcpyHostToDevice, s));
+    if ((rc = stage_edges(c, edges, b))) return rc;
+    Ctl &k = *c->h_ctl;
+    memset(&k, 0, sizeof k);
+    k.b = b;
+    k.op = 2;
+    k.has_ins = any_ins;
+    k.has_del = any_del;
+    k.ngraph = G;
+    k.lfast = BFS_FAST;
+    k.nvl = nvl;
+    k.nil = nil;
+    k.ntl = ntl;
+    c->ndelta_bound += nins;
+    set_regions(c, k);
+    return launch_update(c);
 }
 
 int drsf_wait(drsf_ctx *c, drsf_view *out) {
@@ -586,28 +874,51 @@ int drsf_wait(drsf_ctx *c, drsf_view *out) {
     if (c->pending) {
         c->pending = false;
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        const int32_t st = *(int32_t *)c->h_ret;
         const unsigned long long *k = c->h_ret + 1;
-        if (st == 0) {
-            c->m_live += c->last_op == DRSF_INSERT ? c->last_b : -c->last_b;
+        int32_t st = *(int32_t *)c->h_ret;
+        if (st == 0 && !k[C_ORIENTED]) {  // the captured rounds did not finish it
+            const int rc = continue_update(c);
+            if (rc) return c->last_rc = rc;
+            st = *(int32_t *)c->h_ret;
+        }
+        if (c->have_phases)
+            for (int i = 0; i < PH_N; i++)
+                if (hipEventElapsedTime(&c->phase_ms[i], c->ev[i], c->ev[i + 1]) != hipSuccess) {
+                    (void)hipGetLastError();
+                    c->have_phases = false;
+                }
+        if (st != 0) {
+            c->last_rc = fail(c, DRSF_E_DEVICE, "internal bound exceeded (status %d)", st);
+        } else {
             c->view.num_key_cross = (int64_t)k[C_NCROSS];
             c->view.num_replacement = (int64_t)k[C_NER];
             c->view.num_pieces = (int64_t)k[C_NP];
             c->view.num_paths = (int64_t)k[C_NR];
             c->last_rc = DRSF_OK;
-        } else if (st & ST_BATCH_MASK) {
-            if (c->last_op == DRSF_INSERT) c->ndelta_bound -= c->last_b;
-            c->last_rc = fail(c, DRSF_E_BATCH, "invalid batch:%s%s%s%s",
-                              st & ST_BAD_PAIR ? " self-loop or id out of range;" : "",
-                              st & ST_DUPLICATE ? " repeated edge;" : "",
-                              st & ST_EXISTS ? " insert of an existing edge;" : "",
-                              st & ST_MISSING ? " delete of a missing edge;" : "");
-        } else {
-            c->last_rc = fail(c, DRSF_E_DEVICE, "internal bound exceeded (status %d)", st);
-        }
-        if (c->have_phases) {
-            for (int i = 0; i < PH_N; i++)
-                (void)hipEventElapsedTime(&c->phase_ms[i], c->ev[i], c->ev[i + 1]);
+            if (c->multi_last) {
+                for (int32_t g = 0; g < c->ngraph; g++) {
+                    const int64_t bg = c->last_bg[g];
+                    if (c->h_gstat[g]) {
+                        if (c->last_opg[g] == DRSF_INSERT) c->ndelta_bound -= bg;
+                    } else {
+                        const int64_t dm = c->last_opg[g] == DRSF_INSERT ? bg : -bg;
+                        c->gm_h[g] += dm;
+                        c->m_live += dm;
+                    }
+                }
+            } else if (c->h_gstat[0]) {
+                const int32_t bs = c->h_gstat[0];
+                if (c->last_op == DRSF_INSERT) c->ndelta_bound -= c->last_b;
+                c->last_rc = fail(c, DRSF_E_BATCH, "invalid batch:%s%s%s%s",
+                                  bs & ST_BAD_PAIR ? " self-loop or id out of range;" : "",
+                                  bs & ST_DUPLICATE ? " repeated edge;" : "",
+                                  bs & ST_EXISTS ? " insert of an existing edge;" : "",
+                                  bs & ST_MISSING ? " delete of a missing edge;" : "");
+            } else {
+                const int64_t dm = c->last_op == DRSF_INSERT ? c->last_b : -c->last_b;
+                c->m_live += dm;
+                c->gm_h[0] += dm;
+            }
         }
     }
     c->view.parent = c->parent;
@@ -618,22 +929,48 @@ int drsf_wait(drsf_ctx *c, drsf_view *out) {
     return c->last_rc;
 }
 
+int drsf_multi_wait(drsf_ctx *c, int32_t *status) {
+    if (!c) return DRSF_E_ARG;
+    const int rc = drsf_wait(c, nullptr);
+    if (rc != DRSF_OK) return rc;
+    if (status)
+        for (int32_t g = 0; g < c->ngraph; g++) status[g] = c->h_gstat[g] ? DRSF_E_BATCH : DRSF_OK;
+    return DRSF_OK;
+}
+
+int drsf_multi_apply(drsf_ctx *c, const int32_t *edges, const int64_t *b_off, const int8_t *op,
+                     int32_t *status) {
+    const int rc = drsf_multi_apply_async(c, edges, b_off, op);
+    if (rc != DRSF_OK) return rc;
+    return drsf_multi_wait(c, status);
+}
+
+int drsf_multi_num_edges(drsf_ctx *c, int64_t *m) {
+    if (!c || !m) return DRSF_E_ARG;
+    const int rc = finish_pending(c);
+    if (rc) return rc;
+    for (int32_t g = 0; g < c->ngraph; g++) m[g] = c->gm_h[g];
+    return DRSF_OK;
+}
+
 int drsf_apply(drsf_ctx *c, const int32_t *edges, int64_t b, int op, drsf_view *out) {
-    int rc = drsf_apply_async(c, edges, b, op);
+    const int rc = drsf_apply_async(c, edges, b, op);
     if (rc != DRSF_OK) return rc;
     return drsf_wait(c, out);
 }
 
 int drsf_get_view(drsf_ctx *c, drsf_view *out) {
     if (!c || !out) return DRSF_E_ARG;
-    if (c->pending) drsf_wait(c, nullptr);
+    const int rc = finish_pending(c);
+    if (rc) return rc;
     *out = c->view;
     return DRSF_OK;
 }
 
 int drsf_copy_out(drsf_ctx *c, int32_t *parent_host, int32_t *label_host) {
     if (!c) return DRSF_E_ARG;
-    if (c->pending) drsf_wait(c, nullptr);
+    const int rc = finish_pending(c);
+    if (rc) return rc;
     if (parent_host)
         HIPCHK(c, hipMemcpyAsync(parent_host, c->parent, sizeof(int32_t) * (size_t)c->n,
                                  hipMemcpyDeviceToHost, c->stream));
@@ -646,24 +983,29 @@ int drsf_copy_out(drsf_ctx *c, int32_t *parent_host, int32_t *label_host) {
 
 int64_t drsf_num_edges(drsf_ctx *c) {
     if (!c) return -1;
-    if (c->pending) drsf_wait(c, nullptr);
+    if (finish_pending(c)) return -1;
     return c->m_live;
 }
 
 int drsf_export_edges(drsf_ctx *c, uint64_t *keys, int64_t capacity, int64_t *m_out) {
     if (!c || !keys || !m_out) return DRSF_E_ARG;
-    if (c->pending) drsf_wait(c, nullptr);
+    int rc = finish_pending(c);
+    if (rc) return rc;
     std::vector<uint32_t> bptr((size_t)c->n + 1);
     std::vector<int32_t> bcol((size_t)c->eb);
     unsigned long long nd = 0;
-    HIPCHK(c, hipMemcpyAsync(&nd, c->cnt + C_NDELTA, sizeof nd, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(bptr.data(), c->bptr, sizeof(uint32_t) * bptr.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->h_ret, c->cnt + C_NDELTA, sizeof nd, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(bptr.data(), c->bptr, sizeof(uint32_t) * bptr.size(), hipMemcpyDeviceToHost,
+                             c->stream));
     if (c->eb)
-        HIPCHK(c, hipMemcpyAsync(bcol.data(), c->bcol, sizeof(int32_t) * bcol.size(), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(bcol.data(), c->bcol, sizeof(int32_t) * bcol.size(),
+                                 hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    nd = c->h_ret[0];
     std::vector<uint64_t> dk((size_t)nd);
     if (nd) {
-        HIPCHK(c, hipMemcpy(dk.data(), c->dkey, sizeof(uint64_t) * nd, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpyAsync(dk.data(), c->dkey, sizeof(uint64_t) * nd, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
     }
     int64_t w = 0;
     for (int32_t u = 0; u < c->n; u++)
@@ -682,21 +1024,28 @@ int drsf_export_edges(drsf_ctx *c, uint64_t *keys, int64_t capacity, int64_t *m_
     return DRSF_OK;
 }
 
+void drsf_snapshot_free(drsf_snapshot *s);
+
 int drsf_snapshot_take(drsf_ctx *c, drsf_snapshot **out) {
     if (!c || !out) return DRSF_E_ARG;
-    if (c->pending) drsf_wait(c, nullptr);
+    int rc = finish_pending(c);
+    if (rc) return rc;
     drsf_snapshot *s = new drsf_snapshot();
-    memset(s, 0, sizeof *s);
     s->n = c->n; s->eb = c->eb; s->dcap = c->dcap; s->dhmask = c->dhmask;
     s->ndelta_bound = c->ndelta_bound; s->m_live = c->m_live;
+    s->gm = c->gm_h;
     const size_t dh = (size_t)c->dhmask + 1;
-    bool ok = hipMalloc(&s->parent, 4 * (size_t)c->n) == hipSuccess &&
-              hipMalloc(&s->label, 4 * (size_t)c->n) == hipSuccess &&
-              hipMalloc(&s->bcol, 4 * (size_t)std::max<int64_t>(c->eb, 1)) == hipSuccess &&
-              hipMalloc(&s->dkey, 8 * (size_t)c->dcap) == hipSuccess &&
-              hipMalloc(&s->dhash, 8 * dh) == hipSuccess &&
-              hipMalloc(&s->dhpos, 4 * dh) == hipSuccess;
-    if (!ok) { drsf_snapshot_free(s); return fail(c, DRSF_E_NOMEM, "snapshot allocation failed"); }
+    const bool ok = hipMalloc(&s->parent, 4 * (size_t)c->n) == hipSuccess &&
+                    hipMalloc(&s->label, 4 * (size_t)c->n) == hipSuccess &&
+                    hipMalloc(&s->bcol, 4 * (size_t)std::max<int64_t>(c->eb, 1)) == hipSuccess &&
+                    hipMalloc(&s->dkey, 8 * (size_t)c->dcap) == hipSuccess &&
+                    hipMalloc(&s->dhash, 8 * dh) == hipSuccess &&
+                    hipMalloc(&s->dhpos, 4 * dh) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        drsf_snapshot_free(s);
+        return fail(c, DRSF_E_NOMEM, "snapshot allocation failed");
+    }
     hipStream_t st = c->stream;
     HIPCHK(c, hipMemcpyAsync(s->parent, c->parent, 4 * (size_t)c->n, hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipMemcpyAsync(s->label, c->label, 4 * (size_t)c->n, hipMemcpyDeviceToDevice, st));
@@ -704,21 +1053,25 @@ int drsf_snapshot_take(drsf_ctx *c, drsf_snapshot **out) {
     HIPCHK(c, hipMemcpyAsync(s->dkey, c->dkey, 8 * (size_t)c->dcap, hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipMemcpyAsync(s->dhash, c->dhash, 8 * dh, hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipMemcpyAsync(s->dhpos, c->dhpos, 4 * dh, hipMemcpyDeviceToDevice, st));
-    HIPCHK(c, hipMemcpyAsync(&s->ndelta, c->cnt + C_NDELTA, sizeof s->ndelta, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(c->h_ret, c->cnt + C_NDELTA, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
+    s->ndelta = c->h_ret[0];
     *out = s;
     return DRSF_OK;
 }
 
 int drsf_snapshot_restore(drsf_ctx *c, const drsf_snapshot *s) {
     if (!c || !s) return DRSF_E_ARG;
-    if (c->pending) drsf_wait(c, nullptr);
-    if (s->n != c->n || s->eb != c->eb || s->dcap != c->dcap || s->dhmask != c->dhmask)
+    int rc = finish_pending(c);
+    if (rc) return rc;
+    if (s->n != c->n || s->eb != c->eb || s->dcap != c->dcap || s->dhmask != c->dhmask ||
+        s->gm.size() != c->gm_h.size())
         return fail(c, DRSF_E_STATE, "snapshot does not match the context's layout");
     hipStream_t st = c->stream;
     const size_t dh = (size_t)c->dhmask + 1;
     HIPCHK(c, hipMemcpyAsync(c->parent, s->parent, 4 * (size_t)c->n, hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipMemcpyAsync(c->label, s->label, 4 * (size_t)c->n, hipMemcpyDeviceToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(c->rep, s->label, 4 * (size_t)c->n, hipMemcpyDeviceToDevice, st));
     if (c->eb) HIPCHK(c, hipMemcpyAsync(c->bcol, s->bcol, 4 * (size_t)c->eb, hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipMemcpyAsync(c->dkey, s->dkey, 8 * (size_t)c->dcap, hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipMemcpyAsync(c->dhash, s->dhash, 8 * dh, hipMemcpyDeviceToDevice, st));
@@ -728,22 +1081,27 @@ int drsf_snapshot_restore(drsf_ctx *c, const drsf_snapshot *s) {
     HIPCHK(c, hipStreamSynchronize(st));
     c->ndelta_bound = s->ndelta_bound;
     c->m_live = s->m_live;
+    c->gm_h = s->gm;
     c->view.num_edges = c->m_live;
     return DRSF_OK;
 }
 
 void drsf_snapshot_free(drsf_snapshot *s) {
     if (!s) return;
-    (void)hipFree(s->parent); (void)hipFree(s->label); (void)hipFree(s->bcol);
-    (void)hipFree(s->dkey); (void)hipFree(s->dhash); (void)hipFree(s->dhpos);
+    (void)hipFree(s->parent);
+    (void)hipFree(s->label);
+    (void)hipFree(s->bcol);
+    (void)hipFree(s->dkey);
+    (void)hipFree(s->dhash);
+    (void)hipFree(s->dhpos);
     delete s;
 }
 
 int drsf_phase_times(drsf_ctx *c, float *ms, int cap) {
     if (!c || !ms) return 0;
-    if (c->pending) drsf_wait(c, nullptr);
+    if (finish_pending(c)) return 0;
     if (!c->have_phases) return 0;
-    int k = std::min(cap, (int)PH_N);
+    const int k = std::min(cap, (int)PH_N);
     for (int i = 0; i < k; i++) ms[i] = c->phase_ms[i];
     return k;
 }

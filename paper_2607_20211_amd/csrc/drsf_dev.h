@@ -42,6 +42,7 @@ enum : int {
     C_NCROSS = 5,    // cross edges found by the key-edge scan (statistic)
     C_DONE_BOR = 6,  // replacement-edge rounds finished
     C_DONE_LR = 7,   // list ranking finished
+    C_ORIENTED = 8,  // orientation done: the rest of the update may run
     C_NDELTA = 10,   // inserted-edge list length (persistent)
     C_LR_FINAL = 12, // buffer holding the final list ranks
     C_COUNT = 16,

@@ -1,4 +1,4 @@
-// Internal interface between the host API and the D-RSF kernels.
+// Internal interface between the host driver and the D-RSF kernels.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -6,10 +6,27 @@
 
 namespace drsf {
 
+// Shape of one update, read by the kernels from device memory so that one
+// captured kernel sequence serves every batch up to the context's maximum.
+struct Ctl {
+    int64_t b;        // batch entries
+    int64_t rlo, rhi; // regions of x0 read by the first two hooking rounds
+    int64_t ibase;    // first region written by the insert emitter
+    int64_t nvl;      // vertex blocks in vlist (root finding, delete labels); < 0: all
+    int64_t nil;      // vertex blocks in ilist (insert labels); < 0: all
+    int64_t ntl;      // tiles in tlist (base-store sweep); < 0: all
+    int32_t op;       // 0 insert, 1 delete, 2 per-edge op in bop
+    int32_t has_ins;  // some edge inserts
+    int32_t has_del;  // some edge deletes
+    int32_t ngraph;   // graphs in this context (per-graph batch status)
+    int32_t lfast;    // search levels queued before the orientation step
+    int32_t pad;
+};
+
 // All device pointers one apply needs; passed by value to every kernel.
 struct Dev {
     int32_t n;
-    int32_t op;              // 0 insert, 1 delete
+    const Ctl *ctl;
     // edge store: upper-half base CSR (row u holds v > u, ascending; TOMB bit =
     // deleted) plus a list of inserted edges with a hash index
     const uint32_t *bptr;    // [n + 1]
@@ -23,16 +40,17 @@ struct Dev {
     int64_t nz;
     const int32_t *tile_k;   // [ntiles + 1]
     int64_t ntiles;
+    int64_t dtmax;           // tiles of the inserted-edge list at capacity
     uint64_t *dkey;          // [dcap] inserted edge keys, KEY_DEAD when deleted
     int64_t dcap;
     uint64_t *dhash;         // [dhmask + 1] key -> slot, HASH_TOMB_BIT marks a deleted key
     int32_t *dhpos;          // [dhmask + 1] slot -> index in dkey
     uint64_t dhmask;
-    // forest
+    // forest.  Between updates rep[v] == label[v]; a delete recomputes rep as
+    // the root of v in F-hat.
     int32_t *parent;         // [n]
     int32_t *label;          // [n] root of the vertex's tree = smallest vertex of its component
-    int32_t *rep;            // [n] root of the vertex's tree in F-hat (delete scratch)
-    const int32_t *repv;     // rep (delete) or label (insert: F-hat = F)
+    int32_t *rep;            // [n]
     uint64_t *obits;         // [ceil(n/64)] vertex lies in a piece cut off from its old root
     // touched pieces (trees of F-hat incident to the batch), dense ids
     int32_t *tidx;           // [n] piece root vertex -> dense id, NONE when idle
@@ -45,29 +63,35 @@ struct Dev {
     uint64_t *best;          // [pcap] lowest key of a cross edge leaving the component
     uint64_t *srkey;         // [pcap] (smallest vertex << 32 | piece) of the component
     int32_t *head;           // [pcap] first arc of the piece's super-forest arc list
-    int32_t *level;          // [pcap] BFS level of the piece in its super-tree, -1 unreached
-    int32_t *parc;           // [pcap] arc from the parent piece (BFS rooting)
+    int32_t *level;          // [pcap] search level of the piece in its super-tree, -1 unreached
+    int32_t *parc;           // [pcap] arc from the parent piece (search rooting)
     int32_t *newlab;         // [pcap] new label of the component
     int64_t pcap;
     // batch
-    const int32_t *bedges;   // [2b]
-    int64_t b;
-    uint64_t *bkey;          // [b] normalised key
-    int64_t *bloc;           // [b] >= 0: position in bcol; < 0: -(hash slot + 1)
-    int32_t *bchild;         // [b] child endpoint of a deleted tree edge, NONE otherwise
-    int32_t *bslot;          // [b] slot claimed in the batch duplicate table
+    const int32_t *bedges;   // [2 max_b]
+    const int8_t *bop;       // [max_b] per-edge op when ctl->op == 2
+    const int32_t *bgid;     // [max_b] graph of each edge (several graphs), or null
+    const int32_t *goff;     // [ngraph + 1] vertex range of each graph, or null
+    int32_t *gstat;          // [ngraph] batch status bits per graph
+    int64_t max_b;
+    uint64_t *bkey;          // [max_b] normalised key
+    int64_t *bloc;           // [max_b] >= 0: position in bcol; < 0: -(hash slot + 1)
+    int32_t *bchild;         // [max_b] child endpoint of a deleted tree edge, NONE otherwise
+    int32_t *bslot;          // [max_b] slot claimed in the batch duplicate table
     uint64_t *bhash;         // [bhmask + 1]
     uint64_t bhmask;
+    // vertex-block and tile lists restricting per-vertex and sweep kernels to
+    // the graphs that delete or insert (several graphs); see Ctl
+    const int32_t *vlist, *ilist, *tlist;
     // cross-edge lists.  x0 is written in regions of TILE entries, one per
     // producing workgroup: region t holds its cross edges at x0[t * TILE ..]
-    // and rcnt[t] their number (no global atomics).  Delete: regions
-    // [0, ntiles) come from the base-store tiles and [ntiles, nreg) from tiles
-    // of the inserted-edge list; insert: one region per TILE batch entries.
-    // Later hooking rounds use dense lists alternating between x1 and x0.
+    // and rcnt[t] their number (no global atomics).  Regions [0, ntiles) come
+    // from base-store tiles, [ntiles, ntiles + dtmax) from tiles of the
+    // inserted-edge list, [ctl->ibase, ...) from the batch.  Later hooking
+    // rounds use dense lists alternating between x1 and x0.
     Cross *x0, *x1;
     int64_t xcap;
-    unsigned long long *rcnt; // [regions]
-    int64_t nreg;
+    unsigned long long *rcnt;  // [regions]
     // replacement edges and super-forest arcs
     int4 *er;                // [ercap] (x, y, piece of x, piece of y)
     int64_t ercap;
@@ -77,31 +101,34 @@ struct Dev {
     PathReq *paths;          // [pathcap]
     int64_t pathcap;
     // control
-    int32_t *status;
-    unsigned long long *cnt; // [C_COUNT + 2 * MAX_ROUNDS]
+    int32_t *status;         // internal errors (bounds exceeded)
+    unsigned long long *cnt; // [C_TOTAL]
 };
 
 constexpr int MAX_ROUNDS = 64;
 // extra counter slots: per-round activity flags
-constexpr int C_BOR_ROUND = C_COUNT;               // [MAX_ROUNDS]
-constexpr int C_LR_ROUND = C_COUNT + MAX_ROUNDS;   // [MAX_ROUNDS]
+constexpr int C_LR_ROUND = C_COUNT + MAX_ROUNDS;       // [MAX_ROUNDS]
 constexpr int C_BFS_ROUND = C_COUNT + 2 * MAX_ROUNDS;  // [MAX_ROUNDS]
 constexpr int C_TOTAL = C_COUNT + 3 * MAX_ROUNDS;
 
-// launchers (drsf_kernels.hip)
-void launch_classify(const Dev &d, hipStream_t s);
-void launch_prepare(const Dev &d, hipStream_t s);
-void launch_insert_emit(const Dev &d, hipStream_t s);
-void launch_rep(const Dev &d, hipStream_t s);
-void launch_register(const Dev &d, hipStream_t s);
-void launch_sweep_base(const Dev &d, hipStream_t s);
-void launch_sweep_delta(const Dev &d, int64_t ndelta_bound, hipStream_t s);
+// grid sizes
+int grid_for(int64_t items, int64_t per_block, int cap = 8192);
 int64_t delta_tiles(int64_t count);
 int64_t insert_regions(int64_t b);
+
+// launchers of the update path (drsf_kernels.hip); grids are sized from the
+// context's maxima so that a captured sequence fits every batch
+void launch_classify(const Dev &d, hipStream_t s);
+void launch_prepare(const Dev &d, hipStream_t s);
+void launch_register(const Dev &d, hipStream_t s);
+void launch_insert_emit(const Dev &d, hipStream_t s);
+void launch_rep(const Dev &d, hipStream_t s);
+void launch_sweep_base(const Dev &d, hipStream_t s);
+void launch_sweep_delta(const Dev &d, hipStream_t s);
 void launch_boruvka(const Dev &d, int r0, int r1, hipStream_t s);
 void launch_sf_root(const Dev &d, hipStream_t s);
 void launch_sf_bfs(const Dev &d, int l0, int l1, hipStream_t s);
-void launch_orient_bfs(const Dev &d, hipStream_t s);
+void launch_orient_bfs(const Dev &d, int levels, hipStream_t s);
 void launch_superforest_lr(const Dev &d, int lr_rounds, hipStream_t s);
 void launch_reverse(const Dev &d, hipStream_t s);
 void launch_labels(const Dev &d, hipStream_t s);
@@ -114,10 +141,10 @@ inline void launch_fill_u64(unsigned long long *p, int64_t count, uint64_t v, hi
     launch_fill_u64(reinterpret_cast<uint64_t *>(p), count, v, s);
 }
 void launch_csr_check(int32_t n, const int64_t *row_ptr, const int32_t *col, uint32_t *ucnt,
-                      int32_t *status, hipStream_t s);
+                      int32_t *status, const int32_t *goff, int32_t ngraph, hipStream_t s);
 void launch_csr_symmetric(int32_t n, const int64_t *row_ptr, const int32_t *col,
                           int32_t *status, hipStream_t s);
-// exclusive scan of n uint32 counts into out[n + 1] (uint64 total in out64, may overflow uint32)
+// exclusive scan of n uint32 counts into out[n + 1] (64-bit total in *total)
 void launch_scan_u32(const uint32_t *in, uint32_t *out, unsigned long long *total, int64_t n,
                      void *tmp, hipStream_t s);
 size_t scan_tmp_bytes(int64_t n);
@@ -137,5 +164,6 @@ void launch_roots_check(int32_t n, const int32_t *parent, const int32_t *root,
 void launch_span_check(const Dev &d, const int32_t *root, hipStream_t s);
 void launch_tree_min(int32_t n, const int32_t *root, int32_t *label, hipStream_t s);
 void launch_reroot_requests(const Dev &d, const int32_t *root, hipStream_t s);
+void launch_reverse_all(const Dev &d, hipStream_t s);
 
 }  // namespace drsf

@@ -13,7 +13,7 @@
 
 namespace drsf {
 
-static inline int grid_for(int64_t items, int64_t per_block, int cap = 8192) {
+int grid_for(int64_t items, int64_t per_block, int cap) {
     int64_t g = (items + per_block - 1) / per_block;
     if (g < 1) g = 1;
     if (g > cap) g = cap;
@@ -105,22 +105,43 @@ __device__ int block_excl_scan(int x, int *total) {
     return before + inc - x;
 }
 
+__device__ __forceinline__ int edge_op(const Dev &d, int64_t i) {
+    return d.ctl->op == 2 ? (int)d.bop[i] : d.ctl->op;
+}
+__device__ __forceinline__ int32_t edge_graph(const Dev &d, int64_t i) {
+    return d.bgid ? d.bgid[i] : 0;
+}
+// the edge's graph accepted its batch
+__device__ __forceinline__ bool edge_ok(const Dev &d, int64_t i) {
+    return d.gstat[edge_graph(d, i)] == 0;
+}
+// vertex block (BLOCK vertices) handled by the j-th slot of a list, or -1
+__device__ __forceinline__ int64_t list_block(const int32_t *list, int64_t cnt, int64_t j,
+                                              int64_t all) {
+    if (cnt < 0) return j < all ? j : -1;
+    return j < cnt ? list[j] : -1;
+}
+
 // -------------------------------------------------- a1: validate + classify
 
-// Normalise each pair, reject self-loops, out-of-range ids and pairs
-// repeated inside the batch, check presence against the edge store (insert:
-// must be absent; delete: must be present) and, for deletes, find the child
-// endpoint of a tree edge (parent[u] == v or parent[v] == u; Algorithm 1,
-// the cut step).  Writes only batch scratch and the status word.
+// Normalise each pair, reject self-loops, ids outside the edge's graph and
+// pairs repeated inside the batch, check presence against the edge store
+// (insert: must be absent; delete: must be present) and, for deletes, find
+// the child endpoint of a tree edge (parent[u] == v or parent[v] == u;
+// Algorithm 1, the cut step).  Errors mark the edge's graph as rejected;
+// nothing but batch scratch is written.
 __global__ __launch_bounds__(BLOCK) void k_classify(Dev d) {
+    const int64_t b = d.ctl->b;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < d.b; i += stride) {
-        int32_t u = d.bedges[2 * i], v = d.bedges[2 * i + 1];
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < b; i += stride) {
+        const int32_t u = d.bedges[2 * i], v = d.bedges[2 * i + 1];
+        const int32_t g = edge_graph(d, i);
+        const int32_t lo_ok = d.goff ? d.goff[g] : 0, hi_ok = d.goff ? d.goff[g + 1] : d.n;
         d.bslot[i] = NONE;
         d.bchild[i] = NONE;
         d.bloc[i] = 0;
-        if (u < 0 || v < 0 || u >= d.n || v >= d.n || u == v) {
-            atomicOr(d.status, ST_BAD_PAIR);
+        if (u < lo_ok || v < lo_ok || u >= hi_ok || v >= hi_ok || u == v) {
+            atomicOr(&d.gstat[g], ST_BAD_PAIR);
             d.bkey[i] = 0;
             continue;
         }
@@ -136,30 +157,29 @@ __global__ __launch_bounds__(BLOCK) void k_classify(Dev d) {
                               (unsigned long long)k);
                 if (s == HASH_EMPTY) { d.bslot[i] = (int32_t)h; break; }
             }
-            if (s == k) { atomicOr(d.status, ST_DUPLICATE); break; }
+            if (s == k) { atomicOr(&d.gstat[g], ST_DUPLICATE); break; }
             h = (h + 1) & d.bhmask;
         }
         // presence
-        int64_t pos = find_in_row(d.bcol, d.bptr[lo], d.bptr[lo + 1], hi);
+        const int64_t pos = find_in_row(d.bcol, d.bptr[lo], d.bptr[lo + 1], hi);
         int64_t loc;
         bool present;
         if (pos >= 0 && d.bcol[pos] >= 0) {
             present = true;
             loc = pos;
         } else {
-            int64_t slot = dhash_find(d, k);
+            const int64_t slot = dhash_find(d, k);
             present = slot >= 0;
             loc = -(slot + 1);
         }
-        if (d.op == 0) {
-            if (present) atomicOr(d.status, ST_EXISTS);
+        if (edge_op(d, i) == 0) {
+            if (present) atomicOr(&d.gstat[g], ST_EXISTS);
         } else {
             if (!present) {
-                atomicOr(d.status, ST_MISSING);
+                atomicOr(&d.gstat[g], ST_MISSING);
             } else {
                 d.bloc[i] = loc;
-                int32_t c = d.parent[lo] == hi ? lo : (d.parent[hi] == lo ? hi : NONE);
-                d.bchild[i] = c;
+                d.bchild[i] = d.parent[lo] == hi ? lo : (d.parent[hi] == lo ? hi : NONE);
             }
         }
     }
@@ -173,34 +193,35 @@ __global__ __launch_bounds__(BLOCK) void k_classify(Dev d) {
 // on the roots of big trees).
 __global__ __launch_bounds__(BLOCK) void k_prepare(Dev d) {
     if (*d.status) return;
+    const int64_t b = d.ctl->b;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < d.b; base += stride) {
+    for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < b; base += stride) {
         const int64_t i = base + threadIdx.x;
-        const bool valid = i < d.b;
-        if (d.op == 1) {
-            if (valid) {
-                const int64_t loc = d.bloc[i];
-                if (loc >= 0) {
-                    d.bcol[loc] = d.bcol[loc] | TOMB;
-                } else {
-                    const int64_t slot = -loc - 1;
-                    d.dkey[d.dhpos[slot]] = KEY_DEAD;
-                    d.dhash[slot] = d.bkey[i] | HASH_TOMB_BIT;
-                }
-                const int32_t c = d.bchild[i];
-                if (c != NONE) {
-                    d.parent[c] = c;  // Algorithm 1: parent[u] <- u
-                    // orphan piece rooted at c, and the piece keeping the old root
-                    d.owner[c] = (int32_t)(2 * i);
-                    d.owner[d.label[c]] = (int32_t)(2 * i + 1);
-                }
+        const bool valid = i < b && edge_ok(d, i);
+        const int op = valid ? edge_op(d, i) : -1;
+        if (op == 1) {
+            const int64_t loc = d.bloc[i];
+            if (loc >= 0) {
+                d.bcol[loc] = d.bcol[loc] | TOMB;
+            } else {
+                const int64_t slot = -loc - 1;
+                d.dkey[d.dhpos[slot]] = KEY_DEAD;
+                d.dhash[slot] = d.bkey[i] | HASH_TOMB_BIT;
             }
-        } else {
-            const uint64_t k = valid ? d.bkey[i] : 0;
-            const int64_t pos = wave_append(valid, &d.cnt[C_NDELTA]);
-            if (valid && pos >= d.dcap) {
+            const int32_t c = d.bchild[i];
+            if (c != NONE) {
+                d.parent[c] = c;  // Algorithm 1: parent[u] <- u
+                // orphan piece rooted at c, and the piece keeping the old root
+                d.owner[c] = (int32_t)(2 * i);
+                d.owner[d.label[c]] = (int32_t)(2 * i + 1);
+            }
+        }
+        const int64_t pos = wave_append(op == 0, &d.cnt[C_NDELTA]);
+        if (op == 0) {
+            const uint64_t k = d.bkey[i];
+            if (pos >= d.dcap) {
                 atomicOr(d.status, ST_CAPACITY);
-            } else if (valid) {
+            } else {
                 d.dkey[pos] = k;
                 dhash_insert(d, k, (int32_t)pos);
                 const int32_t la = d.label[key_lo(k)], lb = d.label[key_hi(k)];
@@ -216,40 +237,45 @@ __global__ __launch_bounds__(BLOCK) void k_prepare(Dev d) {
 // Dense ids for the nominated pieces: the owning batch entry registers.
 __global__ __launch_bounds__(BLOCK) void k_register(Dev d) {
     if (*d.status) return;
+    const int64_t b = d.ctl->b;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < d.b; base += stride) {
+    for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < b; base += stride) {
         const int64_t i = base + threadIdx.x;
-        int32_t a = NONE, b = NONE;
-        if (i < d.b) {
-            if (d.op == 1) {
+        int32_t a = NONE, c2 = NONE;
+        bool del = false;
+        if (i < b && edge_ok(d, i)) {
+            del = edge_op(d, i) == 1;
+            if (del) {
                 const int32_t c = d.bchild[i];
-                if (c != NONE) { a = c; b = d.label[c]; }
+                if (c != NONE) { a = c; c2 = d.label[c]; }
             } else {
                 const uint64_t k = d.bkey[i];
                 const int32_t la = d.label[key_lo(k)], lb = d.label[key_hi(k)];
-                if (la != lb) { a = la; b = lb; }
+                if (la != lb) { a = la; c2 = lb; }
             }
         }
         const bool ga = a != NONE && d.owner[a] == (int32_t)(2 * i);
-        const bool gb = b != NONE && d.owner[b] == (int32_t)(2 * i + 1);
+        const bool gb = c2 != NONE && d.owner[c2] == (int32_t)(2 * i + 1);
         const int64_t ia = wave_append(ga, &d.cnt[C_NP]);
         const int64_t ib = wave_append(gb, &d.cnt[C_NP]);
         if (ga) init_piece(d, ia, a, false);
-        if (gb) init_piece(d, ib, b, d.op == 1);
+        if (gb) init_piece(d, ib, c2, del);
     }
 }
 
 // insert: key edges M = B; cross edges join two different trees (labels).
 // Workgroup t takes batch entries [t * BLOCK, (t + 1) * BLOCK) and writes
-// region t of x0.
+// region ibase + t of x0.
 __global__ __launch_bounds__(BLOCK) void k_insert_emit(Dev d) {
-    if (*d.status) return;
+    if (*d.status || !d.ctl->has_ins) return;
+    const int64_t b = d.ctl->b;
     const int64_t t = blockIdx.x;
+    if (t * BLOCK >= b) return;
     const int64_t i = t * BLOCK + threadIdx.x;
     bool cross = false;
     uint64_t k = 0;
     int32_t la = 0, lb = 0;
-    if (i < d.b) {
+    if (i < b && edge_ok(d, i) && edge_op(d, i) == 0) {
         k = d.bkey[i];
         la = d.label[key_lo(k)];
         lb = d.label[key_hi(k)];
@@ -257,23 +283,28 @@ __global__ __launch_bounds__(BLOCK) void k_insert_emit(Dev d) {
     }
     int total;
     const int off = block_excl_scan(cross ? 1 : 0, &total);
-    if (threadIdx.x == 0) d.rcnt[t] = (unsigned long long)total;
+    const int64_t reg = d.ctl->ibase + t;
+    if (threadIdx.x == 0) d.rcnt[reg] = (unsigned long long)total;
     if (cross) {
         Cross e;
         e.key = k;
         e.pa = d.tidx[la];
         e.pb = d.tidx[lb];
-        d.x0[t * TILE + off] = e;
+        d.x0[reg * TILE + off] = e;
     }
 }
 
 // ----------------------------------------------- a4: root finding (delete)
 
 __global__ __launch_bounds__(BLOCK) void k_rep_init(Dev d) {
-    if (*d.status) return;
-    const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < d.n; v += stride)
-        d.rep[v] = d.parent[v];
+    if (*d.status || !d.ctl->has_del) return;
+    const int64_t nb = (d.n + BLOCK - 1) / BLOCK;
+    for (int64_t j = blockIdx.x;; j += gridDim.x) {
+        const int64_t blk = list_block(d.vlist, d.ctl->nvl, j, nb);
+        if (blk < 0) break;
+        const int64_t v = blk * BLOCK + threadIdx.x;
+        if (v < d.n) d.rep[v] = d.parent[v];
+    }
 }
 
 // rep[v] <- root of v in F-hat.  Each thread chases rep[] upward; entries
@@ -283,16 +314,18 @@ __global__ __launch_bounds__(BLOCK) void k_rep_init(Dev d) {
 // vertices whose root is not their old root (they lie in a piece cut off by
 // the batch) in a bitmap, and the smallest vertex of each such piece.
 __global__ __launch_bounds__(BLOCK) void k_rep_chase(Dev d) {
-    if (*d.status) return;
-    const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < d.n; base += stride) {
-        const int64_t v = base + threadIdx.x;
+    if (*d.status || !d.ctl->has_del) return;
+    const int64_t nb = (d.n + BLOCK - 1) / BLOCK;
+    for (int64_t j = blockIdx.x;; j += gridDim.x) {
+        const int64_t blk = list_block(d.vlist, d.ctl->nvl, j, nb);
+        if (blk < 0) break;
+        const int64_t v = blk * BLOCK + threadIdx.x;
         bool orphan = false;
         int32_t x = 0;
         if (v < d.n) {
             x = ld_relaxed(&d.rep[v]);
             for (int64_t steps = 0;; steps++) {
-                int32_t y = ld_relaxed(&d.rep[x]);
+                const int32_t y = ld_relaxed(&d.rep[x]);
                 if (y == x) break;
                 x = y;
                 if (steps > d.n) { atomicOr(d.status, ST_WALK_BOUND); break; }
@@ -317,7 +350,7 @@ __global__ __launch_bounds__(BLOCK) void k_rep_chase(Dev d) {
             const bool in = pending && t == t0;
             rem &= ~__ballot(in);
             if (in) pending = false;
-            if (lane_id() == leader) min_i32(&d.pmin[t0], (int32_t)v);  // leader is the group's smallest v
+            if (lane_id() == leader) min_i32(&d.pmin[t0], (int32_t)v);  // leader: smallest v of the group
         }
         if (pending) min_i32(&d.pmin[t], (int32_t)v);
     }
@@ -330,25 +363,26 @@ __global__ __launch_bounds__(BLOCK) void k_rep_chase(Dev d) {
 // stay in their old root's piece has equal reps (its ends share a component
 // of G, hence a tree of F, hence that tree's root piece), so the rep gathers
 // are only made when the orphan bitmap flags an end.  One workgroup streams
-// TILE consecutive stored edges (EPT per thread, 16-byte loads); the rows are
-// walked over the non-empty-row index, so a thread advances at most EPT rows.
-// Cross edges go to the tile's own region of x0: no global atomics.
+// TILE consecutive stored edges (EPT per thread, 16-byte non-temporal loads);
+// rows are walked over the non-empty-row index, so a thread advances at most
+// EPT rows; the bitmap and rep gathers of a thread's edges are issued
+// together.  Cross edges go to the tile's own region of x0.
 __global__ __launch_bounds__(BLOCK) void k_sweep_base(Dev d) {
-    if (*d.status) return;
+    if (*d.status || !d.ctl->has_del) return;
+    const int64_t tile = list_block(d.tlist, d.ctl->ntl, blockIdx.x, d.ntiles);
+    if (tile < 0) return;
     typedef int v4i __attribute__((ext_vector_type(4)));
-    const int64_t tile = blockIdx.x;
     const int64_t e0 = tile * TILE + (int64_t)threadIdx.x * EPT;
     uint32_t mask = 0;
     int32_t c[EPT];
     int32_t urow[EPT];
     if (e0 < d.eb) {
         // largest k with zptr[k] <= e0, among the tile's rows
-        int32_t a = d.tile_k[tile], b = d.tile_k[tile + 1];
-        while (a < b) {
-            const int32_t mid = a + ((b - a + 1) >> 1);
-            if ((int64_t)d.zptr[mid] <= e0) a = mid; else b = mid - 1;
+        int32_t a = d.tile_k[tile], bk = d.tile_k[tile + 1];
+        while (a < bk) {
+            const int32_t mid = a + ((bk - a + 1) >> 1);
+            if ((int64_t)d.zptr[mid] <= e0) a = mid; else bk = mid - 1;
         }
-        // columns: streamed once, non-temporal so they do not evict the bitmap
         if (e0 + EPT <= d.eb) {
             const v4i *p = reinterpret_cast<const v4i *>(d.bcol + e0);
 #pragma unroll
@@ -360,13 +394,12 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_base(Dev d) {
 #pragma unroll
             for (int j = 0; j < EPT; j++) c[j] = (e0 + j < d.eb) ? d.bcol[e0 + j] : TOMB;
         }
-        // phase 1: the row of every edge (at most EPT row steps)
+        // phase 1: the row of every edge
         int32_t k = a;
         int64_t rend = d.zptr[k + 1];
         int32_t u = d.zrow[k];
-        uint32_t umask = obit(d.obits, u) ? 1u : 0u;  // bit j: row of edge j is flagged
-        bool ou = umask != 0;
-        umask = 0;
+        bool ou = obit(d.obits, u);
+        uint32_t umask = 0;
 #pragma unroll
         for (int j = 0; j < EPT; j++) {
             const int64_t e = e0 + j;
@@ -402,10 +435,10 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_base(Dev d) {
 #pragma unroll
         for (int j = 0; j < EPT; j++) {
             if (mask >> j & 1) {
-                const int32_t u = urow[j], v = c[j];
+                const int32_t uu = urow[j], v = c[j];
                 Cross x;
-                x.key = ((uint64_t)(uint32_t)u << 32) | (uint32_t)v;
-                x.pa = d.tidx[d.rep[u]];
+                x.key = ((uint64_t)(uint32_t)uu << 32) | (uint32_t)v;
+                x.pa = d.tidx[d.rep[uu]];
                 x.pb = d.tidx[d.rep[v]];
                 if (x.pa < 0 || x.pb < 0) atomicOr(d.status, ST_WALK_BOUND);
                 out[w++] = x;
@@ -417,21 +450,20 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_base(Dev d) {
 // The same test over the list of inserted edges: workgroup t takes list
 // entries [t * TILE, (t + 1) * TILE) and writes region ntiles + t.
 __global__ __launch_bounds__(BLOCK) void k_sweep_delta(Dev d) {
-    if (*d.status) return;
+    if (*d.status || !d.ctl->has_del) return;
     const int64_t nd = (int64_t)d.cnt[C_NDELTA];
     const int64_t t = blockIdx.x;
+    if (t * TILE >= nd) return;
     const int64_t i0 = t * TILE + (int64_t)threadIdx.x * EPT;
     uint32_t mask = 0;
-    if (t * TILE < nd) {
 #pragma unroll
-        for (int j = 0; j < EPT; j++) {
-            const int64_t i = i0 + j;
-            if (i < nd) {
-                const uint64_t k = d.dkey[i];
-                if (k != KEY_DEAD) {
-                    const int32_t u = key_lo(k), v = key_hi(k);
-                    if ((obit(d.obits, u) || obit(d.obits, v)) && d.rep[u] != d.rep[v]) mask |= 1u << j;
-                }
+    for (int j = 0; j < EPT; j++) {
+        const int64_t i = i0 + j;
+        if (i < nd) {
+            const uint64_t k = d.dkey[i];
+            if (k != KEY_DEAD) {
+                const int32_t u = key_lo(k), v = key_hi(k);
+                if ((obit(d.obits, u) || obit(d.obits, v)) && d.rep[u] != d.rep[v]) mask |= 1u << j;
             }
         }
     }
@@ -471,29 +503,31 @@ __device__ __forceinline__ void select_edge(const Dev &d, bool live, const Cross
 }
 
 // Round 0: every cross edge is live and every component is a single piece.
-// Workgroup t reads region t of x0.  Workgroup 0 also sums the region
-// lengths (the number of cross edges found).
+// Workgroups take the regions [rlo, rhi) of x0 in turn.  Workgroup 0 also
+// sums the region lengths (the number of cross edges found).
 __global__ __launch_bounds__(BLOCK) void k_bor_round0(Dev d) {
     if (*d.status) return;
     const int64_t np = (int64_t)d.cnt[C_NP];
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < np; p += stride)
         d.hook[p] = NONE;
-    const int64_t t = blockIdx.x;
-    const int64_t cntr = (int64_t)d.rcnt[t];
-    const Cross *in = d.x0 + t * TILE;
-    for (int64_t base = 0; base < cntr; base += BLOCK) {
-        const int64_t i = base + threadIdx.x;
-        const bool live = i < cntr;
-        Cross e;
-        e.pa = e.pb = 0;
-        e.key = 0;
-        if (live) e = in[i];
-        select_edge(d, live, e, e.pa, e.pb);
+    const int64_t rlo = d.ctl->rlo, rhi = d.ctl->rhi;
+    for (int64_t t = rlo + blockIdx.x; t < rhi; t += gridDim.x) {
+        const int64_t cntr = (int64_t)d.rcnt[t];
+        const Cross *in = d.x0 + t * TILE;
+        for (int64_t base = 0; base < cntr; base += BLOCK) {
+            const int64_t i = base + threadIdx.x;
+            const bool live = i < cntr;
+            Cross e;
+            e.pa = e.pb = 0;
+            e.key = 0;
+            if (live) e = in[i];
+            select_edge(d, live, e, e.pa, e.pb);
+        }
     }
-    if (t == 0) {
+    if (blockIdx.x == 0) {
         unsigned long long s = 0;
-        for (int64_t r = threadIdx.x; r < d.nreg; r += BLOCK) s += d.rcnt[r];
+        for (int64_t r = rlo + threadIdx.x; r < rhi; r += BLOCK) s += d.rcnt[r];
         for (int o = WAVE / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
         if (lane_id() == 0 && s) atomicAdd(&d.cnt[C_NCROSS], s);
     }
@@ -510,42 +544,52 @@ __global__ __launch_bounds__(BLOCK) void k_bor_select(Dev d, int r) {
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < np; p += stride)
         d.hook[p] = NONE;
-    const Cross *in;
-    int64_t first, count, step;
-    if (r == 1) {  // one workgroup per region of x0
-        in = d.x0 + (int64_t)blockIdx.x * TILE;
-        count = (int64_t)d.rcnt[blockIdx.x];
-        first = 0;
-        step = BLOCK;
+    __shared__ unsigned long long obase;
+    // work units: regions of x0 (round 1) or BLOCK-sized chunks of a dense list
+    int64_t u0, u1;
+    const Cross *dense = (r & 1) ? d.x0 : d.x1;
+    int64_t dcount = 0;
+    if (r == 1) {
+        u0 = d.ctl->rlo;
+        u1 = d.ctl->rhi;
     } else {
-        in = (r & 1) ? d.x0 : d.x1;
-        count = (int64_t)d.cnt[(r & 1) ? C_NX0 : C_NX1];
-        first = (int64_t)blockIdx.x * BLOCK;
-        step = stride;
+        dcount = (int64_t)d.cnt[(r & 1) ? C_NX0 : C_NX1];
+        u0 = 0;
+        u1 = (dcount + BLOCK - 1) / BLOCK;
     }
-    for (int64_t base = first; base < count; base += step) {
-        const int64_t i = base + threadIdx.x;
-        bool live = false;
-        Cross e;
-        e.key = 0;
-        e.pa = e.pb = 0;
-        int32_t ca = 0, cb = 0;
-        if (i < count) {
-            e = in[i];
-            ca = d.comp[e.pa];
-            cb = d.comp[e.pb];
-            live = ca != cb;
+    for (int64_t unit = u0 + blockIdx.x; unit < u1; unit += gridDim.x) {
+        const Cross *in;
+        int64_t count;
+        if (r == 1) {
+            in = d.x0 + unit * TILE;
+            count = (int64_t)d.rcnt[unit];
+        } else {
+            in = dense + unit * BLOCK;
+            count = dcount - unit * BLOCK < BLOCK ? dcount - unit * BLOCK : BLOCK;
         }
-        select_edge(d, live, e, ca, cb);
-        e.pa = ca;
-        e.pb = cb;
-        int total;
-        const int off = block_excl_scan(live ? 1 : 0, &total);
-        __shared__ unsigned long long obase;
-        if (threadIdx.x == 0) obase = total ? atomicAdd(cout, (unsigned long long)total) : 0ull;
-        __syncthreads();
-        if (live) out[obase + off] = e;
-        __syncthreads();
+        for (int64_t base = 0; base < count; base += BLOCK) {
+            const int64_t i = base + threadIdx.x;
+            bool live = false;
+            Cross e;
+            e.key = 0;
+            e.pa = e.pb = 0;
+            int32_t ca = 0, cb = 0;
+            if (i < count) {
+                e = in[i];
+                ca = d.comp[e.pa];
+                cb = d.comp[e.pb];
+                live = ca != cb;
+            }
+            select_edge(d, live, e, ca, cb);
+            e.pa = ca;
+            e.pb = cb;
+            int total;
+            const int off = block_excl_scan(live ? 1 : 0, &total);
+            if (threadIdx.x == 0) obase = total ? atomicAdd(cout, (unsigned long long)total) : 0ull;
+            __syncthreads();
+            if (live) out[obase + off] = e;
+            __syncthreads();
+        }
     }
 }
 
@@ -573,7 +617,7 @@ __global__ __launch_bounds__(BLOCK) void k_bor_hook(Dev d, int r) {
             const uint64_t k = d.best[p];
             if (k != KEY_INF) {
                 const int32_t x = key_lo(k), y = key_hi(k);
-                const int32_t px = d.tidx[d.repv[x]], py = d.tidx[d.repv[y]];
+                const int32_t px = d.tidx[d.rep[x]], py = d.tidx[d.rep[y]];
                 if (px < 0 || py < 0) {
                     atomicOr(d.status, ST_WALK_BOUND);
                 } else {
@@ -664,15 +708,17 @@ __global__ __launch_bounds__(BLOCK) void k_sf_bfs(Dev d, int L) {
     if (__ballot(active) && lane_id() == 0) d.cnt[C_BFS_ROUND + L] = 1;
 }
 
-// Orientation from the search: a piece reached through arc a (from the
+// Orientation from the search, once the rounds have finished and the last
+// queued level reached nothing new: a piece reached through arc a (from the
 // parent piece) reverses the path from a's endpoint in the piece to the
 // piece's root and hangs that endpoint below a's other endpoint (Algorithm 1,
 // R and new parents).  A super-root piece whose root is not the component's
 // smallest vertex m is re-rooted at m; m is the component's new label.
-__global__ __launch_bounds__(BLOCK) void k_orient_bfs(Dev d) {
-    if (*d.status) return;
+__global__ __launch_bounds__(BLOCK) void k_orient_bfs(Dev d, int levels) {
+    if (*d.status || !d.cnt[C_DONE_BOR] || d.cnt[C_BFS_ROUND + levels - 1] != 0) return;
     const int64_t np = (int64_t)d.cnt[C_NP];
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.cnt[C_ORIENTED] = 1;
     for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < np; base += stride) {
         const int64_t p = base + threadIdx.x;
         bool e1 = false, e2 = false;
@@ -774,12 +820,9 @@ __global__ __launch_bounds__(BLOCK) void k_lr_round(Dev d, int r) {
     if (__ballot(active) && lane_id() == 0) d.cnt[C_LR_ROUND + r] = 1;
 }
 
-// Orientation: of the two arcs of a replacement edge the one met first in the
-// tour (larger rank) points from parent piece to child piece.  The child
-// piece's path from the edge's endpoint to its root is reversed and the
-// endpoint takes the other end as parent (Algorithm 1, R and new parents).
-// A super-root piece whose root is not the component's smallest vertex m is
-// re-rooted at m.  The component's new label is m.
+// Orientation from the tour: of the two arcs of a replacement edge the one
+// met first (larger rank) points from parent piece to child piece; the rest
+// as in k_orient_bfs.
 __global__ __launch_bounds__(BLOCK) void k_orient_lr(Dev d, int lr_rounds) {
     if (*d.status) return;
     const int64_t ner = (int64_t)d.cnt[C_NER];
@@ -794,6 +837,7 @@ __global__ __launch_bounds__(BLOCK) void k_orient_lr(Dev d, int lr_rounds) {
         }
         fin = lr_rounds & 1;
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.cnt[C_ORIENTED] = 1;
     const int32_t *rk = fin ? d.rank1 : d.rank0;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     const int64_t total = ner + np;
@@ -836,8 +880,7 @@ __global__ __launch_bounds__(BLOCK) void k_orient_lr(Dev d, int lr_rounds) {
 // the attach path of a non-root piece or the re-root path of a super-root
 // piece), so the walks touch disjoint vertices; each thread reads a parent
 // before overwriting it (the old orientation is read exactly once).
-__global__ __launch_bounds__(BLOCK) void k_reverse(Dev d) {
-    if (*d.status) return;
+__device__ void reverse_paths(const Dev &d) {
     const int64_t nr = (int64_t)d.cnt[C_NR];
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < nr; i += stride) {
@@ -853,44 +896,87 @@ __global__ __launch_bounds__(BLOCK) void k_reverse(Dev d) {
         }
     }
 }
+__global__ __launch_bounds__(BLOCK) void k_reverse(Dev d) {
+    if (*d.status || !d.cnt[C_ORIENTED]) return;
+    reverse_paths(d);
+}
+__global__ __launch_bounds__(BLOCK) void k_reverse_all(Dev d) {
+    if (*d.status) return;
+    reverse_paths(d);
+}
 
 // ------------------------------------------------------------ a9: labels
 
+// Deletes: a vertex cut off from its old root takes its new component's
+// label.  Runs before the insert labels (mixed batches).  Restores
+// rep == label for the next update.
 __global__ __launch_bounds__(BLOCK) void k_label_delete(Dev d) {
-    if (*d.status) return;
-    const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < d.n; v += stride) {
-        if (obit(d.obits, (int32_t)v)) {
+    if (*d.status || !d.cnt[C_ORIENTED] || !d.ctl->has_del) return;
+    const int64_t nb = (d.n + BLOCK - 1) / BLOCK;
+    for (int64_t j = blockIdx.x;; j += gridDim.x) {
+        const int64_t blk = list_block(d.vlist, d.ctl->nvl, j, nb);
+        if (blk < 0) break;
+        const int64_t v = blk * BLOCK + threadIdx.x;
+        uint64_t w = 0;
+        if (v < d.n) w = d.obits[v >> 6];
+        // the bitmap is all zero between updates (the sweeps read it for any
+        // vertex); the store depends on the loaded word, so it lands after
+        // every lane's read
+        if (lane_id() == 0 && w != 0) d.obits[v >> 6] = 0;
+        if (v < d.n && ((w >> (v & 63)) & 1)) {
             const int32_t p = d.tidx[d.rep[v]];
-            if (p >= 0) d.label[v] = d.newlab[d.comp[p]];
-            else atomicOr(d.status, ST_WALK_BOUND);
+            if (p >= 0) {
+                const int32_t l = d.newlab[d.comp[p]];
+                d.label[v] = l;
+                d.rep[v] = l;
+            } else {
+                atomicOr(d.status, ST_WALK_BOUND);
+            }
         }
     }
 }
 
+// Inserts: every vertex of a tree that merged into another takes the new
+// component's label (the tree is found through its old label, its root).
 __global__ __launch_bounds__(BLOCK) void k_label_insert(Dev d) {
-    if (*d.status || d.cnt[C_NP] == 0) return;
-    const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < d.n; v += stride) {
-        const int32_t t = d.tidx[d.label[v]];
-        if (t != NONE) d.label[v] = d.newlab[d.comp[t]];
+    if (*d.status || !d.cnt[C_ORIENTED] || !d.ctl->has_ins || d.cnt[C_NP] == 0) return;
+    const int64_t nb = (d.n + BLOCK - 1) / BLOCK;
+    for (int64_t j = blockIdx.x;; j += gridDim.x) {
+        const int64_t blk = list_block(d.ilist, d.ctl->nil, j, nb);
+        if (blk < 0) break;
+        const int64_t v = blk * BLOCK + threadIdx.x;
+        if (v < d.n) {
+            const int32_t t = d.tidx[d.label[v]];
+            if (t != NONE) {
+                const int32_t l = d.newlab[d.comp[t]];
+                d.label[v] = l;
+                d.rep[v] = l;
+            }
+        }
     }
 }
 
 // ------------------------------------------------------------- cleanup
 
+// Resets the per-update scratch once the update has finished (or failed).
 __global__ __launch_bounds__(BLOCK) void k_cleanup_slots(Dev d) {
+    if (!d.cnt[C_ORIENTED] && !*d.status) return;  // unfinished: the host continues
     const int64_t np = (int64_t)d.cnt[C_NP];
+    const int64_t b = d.ctl->b;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < np; p += stride)
         d.tidx[d.prt[p]] = NONE;
-    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < d.b; i += stride)
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < b; i += stride)
         if (d.bslot[i] != NONE) d.bhash[d.bslot[i]] = HASH_EMPTY;
-    for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < d.nreg; t += stride)
+    for (int64_t t = d.ctl->rlo + (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < d.ctl->rhi; t += stride)
         d.rcnt[t] = 0;
+    for (int64_t g = (int64_t)blockIdx.x * BLOCK + threadIdx.x; g < d.ctl->ngraph; g += stride)
+        d.gstat[g] = 0;
 }
 
 __global__ void k_cleanup_counters(Dev d) {
+    if (!d.cnt[C_ORIENTED] && !*d.status) return;
+    __syncthreads();  // every thread has read the flags before any reset
     const int t = threadIdx.x;
     if (t < C_TOTAL && t != C_NDELTA) d.cnt[t] = 0;
     if (t == 0) *d.status = 0;
@@ -898,41 +984,40 @@ __global__ void k_cleanup_counters(Dev d) {
 
 // ------------------------------------------------------------ launchers
 
+int64_t delta_tiles(int64_t count) { return (count + TILE - 1) / TILE; }
+int64_t insert_regions(int64_t b) { return (b + BLOCK - 1) / BLOCK; }
+
 void launch_classify(const Dev &d, hipStream_t s) {
-    hipLaunchKernelGGL(k_classify, dim3(grid_for(d.b, BLOCK)), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_classify, dim3(grid_for(d.max_b, BLOCK)), dim3(BLOCK), 0, s, d);
 }
 void launch_prepare(const Dev &d, hipStream_t s) {
-    hipLaunchKernelGGL(k_prepare, dim3(grid_for(d.b, BLOCK)), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_prepare, dim3(grid_for(d.max_b, BLOCK)), dim3(BLOCK), 0, s, d);
 }
 void launch_register(const Dev &d, hipStream_t s) {
-    hipLaunchKernelGGL(k_register, dim3(grid_for(d.b, BLOCK)), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_register, dim3(grid_for(d.max_b, BLOCK)), dim3(BLOCK), 0, s, d);
 }
 void launch_insert_emit(const Dev &d, hipStream_t s) {
-    hipLaunchKernelGGL(k_insert_emit, dim3((unsigned)insert_regions(d.b)), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_insert_emit, dim3((unsigned)insert_regions(d.max_b)), dim3(BLOCK), 0, s, d);
 }
 void launch_rep(const Dev &d, hipStream_t s) {
-    hipLaunchKernelGGL(k_rep_init, dim3(grid_for(d.n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, d);
-    hipLaunchKernelGGL(k_rep_chase, dim3(grid_for(d.n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, d);
+    const int g = grid_for(d.n, BLOCK, 1 << 20);
+    hipLaunchKernelGGL(k_rep_init, dim3(g), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_rep_chase, dim3(g), dim3(BLOCK), 0, s, d);
 }
 void launch_sweep_base(const Dev &d, hipStream_t s) {
     if (d.ntiles > 0)
         hipLaunchKernelGGL(k_sweep_base, dim3((unsigned)d.ntiles), dim3(BLOCK), 0, s, d);
 }
-int64_t delta_tiles(int64_t count) { return (count + TILE - 1) / TILE; }
-int64_t insert_regions(int64_t b) { return (b + BLOCK - 1) / BLOCK; }
-void launch_sweep_delta(const Dev &d, int64_t ndelta_bound, hipStream_t s) {
-    if (ndelta_bound > 0)
-        hipLaunchKernelGGL(k_sweep_delta, dim3((unsigned)delta_tiles(ndelta_bound)), dim3(BLOCK), 0, s, d);
+void launch_sweep_delta(const Dev &d, hipStream_t s) {
+    if (d.dtmax > 0)
+        hipLaunchKernelGGL(k_sweep_delta, dim3((unsigned)d.dtmax), dim3(BLOCK), 0, s, d);
 }
 void launch_boruvka(const Dev &d, int r0, int r1, hipStream_t s) {
     const int ge = grid_for(d.xcap, BLOCK, 4096);
     const int gp = grid_for(d.pcap, BLOCK, 2048);
-    const unsigned gr = (unsigned)(d.nreg > 0 ? d.nreg : 1);
     for (int r = r0; r < r1; r++) {
         if (r == 0)
-            hipLaunchKernelGGL(k_bor_round0, dim3(gr), dim3(BLOCK), 0, s, d);
-        else if (r == 1)
-            hipLaunchKernelGGL(k_bor_select, dim3(gr), dim3(BLOCK), 0, s, d, r);
+            hipLaunchKernelGGL(k_bor_round0, dim3(ge), dim3(BLOCK), 0, s, d);
         else
             hipLaunchKernelGGL(k_bor_select, dim3(ge), dim3(BLOCK), 0, s, d, r);
         hipLaunchKernelGGL(k_bor_hook, dim3(gp), dim3(BLOCK), 0, s, d, r);
@@ -948,8 +1033,8 @@ void launch_sf_bfs(const Dev &d, int l0, int l1, hipStream_t s) {
     const int ga = grid_for(2 * d.ercap, BLOCK, 2048);
     for (int L = l0; L < l1; L++) hipLaunchKernelGGL(k_sf_bfs, dim3(ga), dim3(BLOCK), 0, s, d, L);
 }
-void launch_orient_bfs(const Dev &d, hipStream_t s) {
-    hipLaunchKernelGGL(k_orient_bfs, dim3(grid_for(d.pcap, BLOCK, 2048)), dim3(BLOCK), 0, s, d);
+void launch_orient_bfs(const Dev &d, int levels, hipStream_t s) {
+    hipLaunchKernelGGL(k_orient_bfs, dim3(grid_for(d.pcap, BLOCK, 2048)), dim3(BLOCK), 0, s, d, levels);
 }
 void launch_superforest_lr(const Dev &d, int lr_rounds, hipStream_t s) {
     const int ga = grid_for(2 * d.ercap, BLOCK, 2048);
@@ -963,15 +1048,16 @@ void launch_superforest_lr(const Dev &d, int lr_rounds, hipStream_t s) {
 void launch_reverse(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_reverse, dim3(grid_for(d.pathcap, BLOCK, 2048)), dim3(BLOCK), 0, s, d);
 }
+void launch_reverse_all(const Dev &d, hipStream_t s) {
+    hipLaunchKernelGGL(k_reverse_all, dim3(grid_for(d.pathcap, BLOCK, 2048)), dim3(BLOCK), 0, s, d);
+}
 void launch_labels(const Dev &d, hipStream_t s) {
-    if (d.op == 1)
-        hipLaunchKernelGGL(k_label_delete, dim3(grid_for(d.n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, d);
-    else
-        hipLaunchKernelGGL(k_label_insert, dim3(grid_for(d.n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, d);
+    const int g = grid_for(d.n, BLOCK, 1 << 20);
+    hipLaunchKernelGGL(k_label_delete, dim3(g), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_label_insert, dim3(g), dim3(BLOCK), 0, s, d);
 }
 void launch_cleanup(const Dev &d, hipStream_t s) {
-    int64_t m = d.pcap > d.b ? d.pcap : d.b;
-    if (d.nreg > m) m = d.nreg;
+    int64_t m = d.pcap > d.max_b ? d.pcap : d.max_b;
     hipLaunchKernelGGL(k_cleanup_slots, dim3(grid_for(m, BLOCK, 2048)), dim3(BLOCK), 0, s, d);
     hipLaunchKernelGGL(k_cleanup_counters, dim3(1), dim3(256), 0, s, d);
 }
@@ -995,21 +1081,32 @@ void launch_fill_u64(uint64_t *p, int64_t count, uint64_t v, hipStream_t s) {
         hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(count, BLOCK, 1 << 16)), dim3(BLOCK), 0, s, p, count, v);
 }
 
-// One wave per row: ids in range, no self-loop, strictly ascending; count
-// the entries above the diagonal (the upper half keeps each edge once).
+// One wave per row: ids in range (inside the row's graph when several graphs
+// share the context), no self-loop, strictly ascending; count the entries
+// above the diagonal (the upper half keeps each edge once).
 __global__ __launch_bounds__(BLOCK) void k_csr_check(int32_t n, const int64_t *row_ptr,
                                                      const int32_t *col, uint32_t *ucnt,
-                                                     int32_t *status) {
+                                                     int32_t *status, const int32_t *goff,
+                                                     int32_t ngraph) {
     const int64_t nw = (int64_t)gridDim.x * (BLOCK / WAVE);
     const int lane = lane_id();
     for (int64_t u = (int64_t)blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE; u < n; u += nw) {
         const int64_t s = row_ptr[u], e = row_ptr[u + 1];
-        if (e < s) { if (lane == 0) atomicOr(status, 1); continue; }
+        int32_t lo = 0, hi = n;
+        if (goff) {  // graph of row u: largest g with goff[g] <= u
+            int32_t a = 0, b = ngraph - 1;
+            while (a < b) {
+                const int32_t mid = a + ((b - a + 1) >> 1);
+                if (goff[mid] <= u) a = mid; else b = mid - 1;
+            }
+            lo = goff[a];
+            hi = goff[a + 1];
+        }
         int bad = 0;
         int64_t above = 0;
         for (int64_t j = s + lane; j < e; j += WAVE) {
             const int32_t c = col[j];
-            if (c < 0 || c >= n || c == u) bad = 1;
+            if (c < lo || c >= hi || c == u) bad = 1;
             if (j + 1 < e && col[j + 1] <= c) bad = 1;
             above += c > u;
         }
@@ -1024,9 +1121,9 @@ __global__ __launch_bounds__(BLOCK) void k_csr_check(int32_t n, const int64_t *r
     }
 }
 void launch_csr_check(int32_t n, const int64_t *row_ptr, const int32_t *col, uint32_t *ucnt,
-                      int32_t *status, hipStream_t s) {
+                      int32_t *status, const int32_t *goff, int32_t ngraph, hipStream_t s) {
     hipLaunchKernelGGL(k_csr_check, dim3(grid_for((int64_t)n * WAVE, BLOCK, 1 << 20)), dim3(BLOCK),
-                       0, s, n, row_ptr, col, ucnt, status);
+                       0, s, n, row_ptr, col, ucnt, status, goff, ngraph);
 }
 
 // Every entry (u, c) must have its mirror (c, u).

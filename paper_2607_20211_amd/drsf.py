@@ -18,7 +18,7 @@ LIB_PATH = os.environ.get("DRSF_LIB") or os.path.join(_HERE, "libdrsf.so")
 DRSF_INSERT, DRSF_DELETE = 0, 1
 DRSF_OK, DRSF_E_ARG, DRSF_E_NOMEM, DRSF_E_FOREST = 0, -1, -2, -3
 DRSF_E_BATCH, DRSF_E_CAPACITY, DRSF_E_DEVICE, DRSF_E_STATE = -4, -5, -6, -7
-PHASES = ("validate", "update_graph", "cut_and_roots", "key_edge_sweep",
+PHASES = ("validate", "update_graph", "root_finding", "key_edge_sweep",
           "key_edge_sweep_inserted", "replacement_edges", "superforest_rooting",
           "path_reversal", "labels")
 
@@ -53,7 +53,9 @@ class DrsfError(RuntimeError):
 EXPORTS = ("drsf_default_opts", "drsf_create", "drsf_apply", "drsf_apply_async", "drsf_wait",
            "drsf_copy_out", "drsf_get_view", "drsf_num_edges", "drsf_export_edges",
            "drsf_snapshot_take", "drsf_snapshot_restore", "drsf_snapshot_free",
-           "drsf_phase_times", "drsf_destroy", "drsf_last_error", "drsf_version")
+           "drsf_phase_times", "drsf_destroy", "drsf_last_error", "drsf_version",
+           "drsf_multi_create", "drsf_multi_apply", "drsf_multi_apply_async", "drsf_multi_wait",
+           "drsf_multi_num_edges", "drsf_num_graphs")
 
 _lib = None
 
@@ -107,6 +109,18 @@ def load():
     lib.drsf_last_error.restype = ctypes.c_char_p
     lib.drsf_version.argtypes = []
     lib.drsf_version.restype = ctypes.c_char_p
+    lib.drsf_multi_create.argtypes = [i32, vp, vp, vp, vp, ctypes.POINTER(drsf_opts), ctypes.POINTER(vp)]
+    lib.drsf_multi_create.restype = c_int
+    lib.drsf_multi_apply.argtypes = [vp, vp, vp, vp, vp]
+    lib.drsf_multi_apply.restype = c_int
+    lib.drsf_multi_apply_async.argtypes = [vp, vp, vp, vp]
+    lib.drsf_multi_apply_async.restype = c_int
+    lib.drsf_multi_wait.argtypes = [vp, vp]
+    lib.drsf_multi_wait.restype = c_int
+    lib.drsf_multi_num_edges.argtypes = [vp, vp]
+    lib.drsf_multi_num_edges.restype = c_int
+    lib.drsf_num_graphs.argtypes = [vp]
+    lib.drsf_num_graphs.restype = c_int
     _lib = lib
     return lib
 
@@ -192,6 +206,45 @@ def drsf_phase_times(ctx) -> dict:
     buf = (ctypes.c_float * len(PHASES))()
     k = load().drsf_phase_times(ctx, buf, len(PHASES))
     return {PHASES[i]: float(buf[i]) for i in range(k)}
+
+
+def drsf_multi_create(G: int, n_off, row_ptr, col, parent, opts: drsf_opts | None = None):
+    o = opts if opts is not None else drsf_default_opts()
+    n_off = np.ascontiguousarray(n_off, dtype=np.int32)
+    out = ctypes.c_void_p()
+    _check(load().drsf_multi_create(G, _ptr(n_off), _ptr(row_ptr), _ptr(col), _ptr(parent),
+                                    ctypes.byref(o), ctypes.byref(out)))
+    return out
+
+
+def drsf_multi_apply_async(ctx, edges, b_off, op) -> None:
+    b_off = np.ascontiguousarray(b_off, dtype=np.int64)
+    op = np.ascontiguousarray(op, dtype=np.int8)
+    _check(load().drsf_multi_apply_async(ctx, _ptr(edges), _ptr(b_off), _ptr(op)), ctx)
+
+
+def drsf_multi_wait(ctx, G: int) -> np.ndarray:
+    st = np.zeros(G, dtype=np.int32)
+    _check(load().drsf_multi_wait(ctx, _ptr(st)), ctx)
+    return st
+
+
+def drsf_multi_apply(ctx, edges, b_off, op) -> np.ndarray:
+    b_off = np.ascontiguousarray(b_off, dtype=np.int64)
+    op = np.ascontiguousarray(op, dtype=np.int8)
+    st = np.zeros(len(op), dtype=np.int32)
+    _check(load().drsf_multi_apply(ctx, _ptr(edges), _ptr(b_off), _ptr(op), _ptr(st)), ctx)
+    return st
+
+
+def drsf_multi_num_edges(ctx, G: int) -> np.ndarray:
+    m = np.zeros(G, dtype=np.int64)
+    _check(load().drsf_multi_num_edges(ctx, _ptr(m)), ctx)
+    return m
+
+
+def drsf_num_graphs(ctx) -> int:
+    return int(load().drsf_num_graphs(ctx))
 
 
 def drsf_destroy(ctx) -> None:
@@ -285,3 +338,49 @@ class Forest:
             self.close()
         except Exception:
             pass
+
+
+class MultiForest(Forest):
+    """Several independent graphs in one context (global vertex ids
+    n_off[g] .. n_off[g + 1] - 1 belong to graph g), updated together: one
+    batch and op per graph per call."""
+
+    def __init__(self, n_off, row_ptr, col, parent, *, max_batch: int = 1 << 20,
+                 stream=None, inputs_on_device: bool = False, validate: bool = True,
+                 profile: bool = False, delta_capacity: int = 0):
+        o = drsf_default_opts()
+        o.max_batch = max_batch
+        o.inputs_on_device = int(inputs_on_device)
+        o.validate_forest = int(validate)
+        o.profile = int(profile)
+        o.delta_capacity = delta_capacity
+        if stream is not None:
+            o.stream = stream
+        if not inputs_on_device:
+            row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+            col = np.ascontiguousarray(col, dtype=np.int32)
+            parent = np.ascontiguousarray(parent, dtype=np.int32)
+        self.n_off = np.ascontiguousarray(n_off, dtype=np.int32)
+        self.G = len(self.n_off) - 1
+        self.n = int(self.n_off[-1])
+        self.ctx = drsf_multi_create(self.G, self.n_off, row_ptr, col, parent, o)
+
+    def apply_multi(self, edges, b_off, op) -> np.ndarray:
+        """Per-graph status (DRSF_OK or DRSF_E_BATCH)."""
+        if not hasattr(edges, "data_ptr"):
+            edges = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+        return drsf_multi_apply(self.ctx, edges, b_off, op)
+
+    def apply_multi_async(self, edges, b_off, op) -> None:
+        if not hasattr(edges, "data_ptr"):
+            edges = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+        self._pending_edges = edges
+        drsf_multi_apply_async(self.ctx, edges, b_off, op)
+
+    def wait_multi(self) -> np.ndarray:
+        st = drsf_multi_wait(self.ctx, self.G)
+        self._pending_edges = None
+        return st
+
+    def num_edges(self) -> np.ndarray:
+        return drsf_multi_num_edges(self.ctx, self.G)

@@ -341,3 +341,41 @@ def test_deep_super_tree_uses_euler_tour_fallback():
     # and the reverse direction: re-insert, then delete the skip edges' partners
     pair.step(batch, drsf.DRSF_INSERT, "chain reinsert")
     pair.gpu.close()
+
+
+def test_long_hooking_and_deep_search_continue_on_host():
+    """An edgeless graph receiving a large random batch: the hooking rounds
+    run past the few queued in the captured update sequence and the
+    super-trees are deep, so the host finishes the update with further
+    rounds and the Euler tour.  Then a delete of half tree, half non-tree
+    edges on the result."""
+    drsf = _lib()
+    _case("continuation")
+    n = 100_000
+    g = gen.make_graph("empty", n, np.zeros(0, np.uint64))
+    pair = Pair(g, max_batch=1 << 18)
+    ins = gen.insert_batches(n, g.keys, 1, 200_000, gen.seed(4, 1, gen.P_INSERT))[0]
+    st, ost = pair.step(ins, drsf.DRSF_INSERT, "continuation insert")
+    assert ost["n_repl"] > n // 2
+    dl = gen.delete_batches(n, pair.keys, pair.parent, 1, 100_000, 50_000, gen.seed(4, 1, gen.P_DELETE))[0]
+    pair.step(dl, drsf.DRSF_DELETE, "continuation delete")
+    pair.gpu.close()
+
+
+def test_profile_mode_direct_launches():
+    """opts.profile launches the same kernels directly with events between
+    the phases; the results are the same and every phase has a time."""
+    drsf = _lib()
+    _case("profile mode")
+    n = 20000
+    g = gen.make_graph("prof", n, gen.gnm(n, 30000, gen.seed(5, 0, gen.P_GRAPH)))
+    pair = Pair(g, profile=True, max_batch=8192)
+    for step in range(3):
+        ins = gen.insert_batches(n, pair.keys, 1, 4000, gen.seed(5, step, gen.P_INSERT))[0]
+        pair.step(ins, drsf.DRSF_INSERT, f"profile insert {step}")
+        assert len(pair.gpu.phase_times()) == len(drsf.PHASES)
+        dl = gen.delete_batches(n, pair.keys, pair.parent, 1, 4000, 2000, gen.seed(5, step, gen.P_DELETE))[0]
+        pair.step(dl, drsf.DRSF_DELETE, f"profile delete {step}")
+        t = pair.gpu.phase_times()
+        assert all(v >= 0 for v in t.values())
+    pair.gpu.close()
