@@ -55,6 +55,200 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def served_workload(scale, ntenants, nreq, seed):
+    """Serving workload: a resident R-MAT graph plus tenants G(n_t, 4 n_t),
+    n_t = round(10^U(5,6)), arriving staggered over the stream and leaving
+    after their last request.  Requests: target uniform over the graphs live
+    at the request's (unit-rate) arrival time, op ~ Bernoulli(1/2), size
+    round(10^U(2,5)); inserts are initial non-edges and deletes initial edges
+    of the target, distinct across requests, so every request is valid in
+    any interleaving of graphs.  Arrival gaps are unit-mean exponentials,
+    scaled per offered load."""
+    import gen
+    keys = gen.rmat(scale, 16, 0.57, 0.19, 0.19, gen.seed(5, 0, gen.P_GRAPH))
+    graphs = [gen.make_graph(f"rmat{scale}", 1 << scale, keys)]
+    u = gen.uniform(gen.seed(5, 1, gen.P_GRAPH), ntenants)
+    for t in range(ntenants):
+        n = int(round(10 ** (5 + u[t])))
+        graphs.append(gen.make_graph(f"t{t}", n, gen.gnm(n, 4 * n, gen.seed(5, 2 + t, gen.P_GRAPH))))
+    r = gen.uniform(gen.seed(5, 0, gen.P_STREAM), 4 * nreq).reshape(4, nreq)
+    gaps = -np.log1p(-r[0])                  # unit-mean exponential gaps
+    t_arr = np.cumsum(gaps)
+    span = t_arr[-1]
+    # tenant k is live on [k, k + 4) eighths of the stream (staggered, finite)
+    win = [(0.0, np.inf)] + [(span * t / (ntenants + 4), span * (t + 4) / (ntenants + 4))
+                             for t in range(ntenants)]
+    pools = []
+    sizes = np.rint(10 ** (2 + 3 * r[2])).astype(np.int64)
+    ops = (r[3] < 0.5).astype(np.int64)
+    live_idx = [[g for g, (a, b) in enumerate(win) if a <= t < b] for t in t_arr]
+    demand = np.zeros((len(graphs), 2), np.int64)
+    target = np.zeros(nreq, np.int64)
+    for k in range(nreq):
+        lv = live_idx[k]
+        target[k] = lv[min(int(r[1][k] * len(lv)), len(lv) - 1)]
+        demand[target[k], ops[k]] += sizes[k]
+    for g, gr in enumerate(graphs):
+        ni = int(min(demand[g, 0], gr.n * 2))
+        nd = int(min(demand[g, 1], gr.m))
+        trees = int((gr.parent != np.arange(gr.n)).sum())
+        nt = min(trees, nd // 2)
+        nn = min(nd - nt, gr.m - trees)
+        nt = min(trees, nd - nn)
+        ins = gen.insert_batches(gr.n, gr.keys, 1, ni, gen.seed(5, g, gen.P_INSERT))[0] if ni else \
+            np.zeros((0, 2), np.int32)
+        dl = gen.delete_batches(gr.n, gr.keys, gr.parent, 1, nt + nn, nt,
+                                gen.seed(5, g, gen.P_DELETE))[0] if nt + nn else np.zeros((0, 2), np.int32)
+        # tree and non-tree edges interleaved so every request mixes both
+        dl = dl[np.argsort(gen.uniform(gen.seed(5, g, gen.P_STREAM), len(dl)), kind="stable")]
+        pools.append([ins, 0, dl, 0])
+    reqs = []
+    for k in range(nreq):
+        g, op, b = int(target[k]), int(ops[k]), int(sizes[k])
+        pool = pools[g]
+        src, at = (pool[0], 1) if op == 0 else (pool[2], 3)
+        e = src[pool[at]:pool[at] + b]
+        pool[at] += len(e)
+        if len(e) == 0:
+            continue
+        reqs.append((g, np.ascontiguousarray(e), op, float(t_arr[k])))
+    last = {}
+    for i, (g, _, _, _) in enumerate(reqs):
+        last[g] = i
+    return graphs, reqs, win, last
+
+
+def run_served(scale, nreq, loads, log):
+    """Served pattern against the plain path (one request at a time in
+    arrival order, same server code in serial mode)."""
+    from paper_2607_20211_amd import drsf
+    t0 = time.time()
+    graphs, reqs, win, last = served_workload(scale, 8, nreq, 0)
+    ups = sum(len(e) for _, e, _, _ in reqs)
+    log(f"served workload: {len(graphs)} graphs, {len(reqs)} requests, {ups} updates "
+        f"({time.time() - t0:.1f}s)")
+    opts = drsf.drsf_default_opts()
+    opts.max_batch = 100_000
+    fps = [drsf.drsf_footprint(g.n, len(g.col), opts) for g in graphs]
+    budget = fps[0] + sum(sorted(fps[1:])[-3:])
+
+    def serve(serial, rate):
+        srv = drsf.Server(budget, max_batch=100_000, serial=serial)
+        scale_ns = 1e9 / rate if rate else 0.0
+        tids = []
+        for g, gr in enumerate(graphs):
+            a = 0 if g == 0 or not rate else int(win[g][0] * scale_ns)
+            tids.append(srv.admit(gr.n, gr.row_ptr, gr.col, gr.parent, arrive_ns=a))
+        for i, (g, e, op, t) in enumerate(reqs):
+            srv.submit(tids[g], e, op, arrive_ns=int(t * scale_ns) if rate else 0)
+        for g in range(1, len(graphs)):
+            srv.release(tids[g])
+        srv.start()
+        srv.wait_all()
+        st = srv.stats()
+        srv.close()
+        return st
+
+    sat = serve(True, None)  # plain path, every request queued at once: its service rate
+    mu = sat["completed"] / (sat["completed"] and (ups / sat["updates_per_s"]))
+    log(f"plain path service rate {mu:.1f} requests/s ({sat['updates_per_s']:.3e} updates/s)")
+    out = []
+    for lam in loads:
+        rate = lam * mu
+        a = serve(False, rate)
+        b = serve(True, rate)
+        log(f"load {lam}: served p50 {a['p50_ms']:.3f} p99 {a['p99_ms']:.3f} ms; "
+            f"plain p50 {b['p50_ms']:.3f} p99 {b['p99_ms']:.3f} ms")
+        out.append({"load": lam, "offered_requests_per_s": round(rate, 1),
+                    "served_p50_ms": round(a["p50_ms"], 4), "served_p99_ms": round(a["p99_ms"], 4),
+                    "served_updates_per_s": round(a["updates_per_s"], 1),
+                    "plain_p50_ms": round(b["p50_ms"], 4), "plain_p99_ms": round(b["p99_ms"], 4),
+                    "plain_updates_per_s": round(b["updates_per_s"], 1),
+                    "peak_bytes": a["peak_bytes"]})
+    return {"workload": f"resident R-MAT scale {scale} + 8 tenants G(n, 4n), n = 10^U(5,6), "
+                        f"staggered; {len(reqs)} requests of 10^U(2,5) edges, Poisson arrivals",
+            "requests": len(reqs), "updates": ups, "budget_bytes": budget,
+            "plain_service_requests_per_s": round(mu, 1),
+            "plain_saturated_updates_per_s": round(sat["updates_per_s"], 1),
+            "loads": out}
+
+
+def run_batched(nsteps, dev, stream, log, tune):
+    """Batched pattern: 256 independent G(n, 4n) graphs (n = 10^U(3,6)) with
+    one batch per graph per step (op and size per graph), all graphs updated
+    by one multi-graph apply per step; against the same batches applied one
+    graph at a time through 256 single-graph contexts."""
+    import torch
+    import gen
+    from paper_2607_20211_amd import drsf
+    t0 = time.time()
+    wl = gen.batched_workload(256, 2 + nsteps, gen.seed(4, 0, gen.P_GRAPH))
+    mg = wl.mg
+    ups = int(wl.steps[0][1][-1])
+    log(f"batched workload: {mg.G} graphs, n={mg.n} m={len(mg.col) // 2}, {ups} updates/step "
+        f"({time.time() - t0:.1f}s)")
+    d_row = torch.from_numpy(mg.row_ptr).to(dev)
+    d_col = torch.from_numpy(mg.col).to(dev)
+    d_par = torch.from_numpy(mg.parent).to(dev)
+    d_steps = [torch.from_numpy(e).to(dev) for e, _, _ in wl.steps]
+    torch.cuda.synchronize()
+    f = drsf.MultiForest(mg.n_off, d_row, d_col, d_par, max_batch=ups, stream=stream.cuda_stream,
+                         inputs_on_device=True, delta_capacity=(2 + nsteps) * ups + (1 << 20))
+    del d_row, d_col
+    tuning = None
+    if tune:
+        from paper_2607_20211_amd import autotune
+
+        def sample(fr):
+            fr.apply_multi(d_steps[0], wl.steps[0][1], wl.steps[0][2])
+        tuning = autotune.tune(f, sample, "batched_256_gnm", use_cache=False)
+        log(f"batched tuning: {tuning}")
+    for i in range(2):
+        st = f.apply_multi(d_steps[i], wl.steps[i][1], wl.steps[i][2])
+        assert (st == 0).all()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i in range(2, 2 + nsteps):
+        f.apply_multi(d_steps[i], wl.steps[i][1], wl.steps[i][2])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    f.close()
+    # the same batches one graph at a time (the plain path), on the first steps
+    plain_steps = min(nsteps, 2)
+    singles = []
+    for g, gr in enumerate(mg.graphs):
+        singles.append(drsf.Forest(gr.n, gr.row_ptr, gr.col, gr.parent, max_batch=max(int(wl.b[g]), 1),
+                                   stream=stream.cuda_stream,
+                                   delta_capacity=(2 + nsteps) * max(int(wl.b[g]), 1) + (1 << 16)))
+    local = []
+    for i in range(2 + plain_steps):
+        e, b_off, ops = wl.steps[i]
+        local.append([(np.ascontiguousarray(e[b_off[g]:b_off[g + 1]] - mg.n_off[g]), int(ops[g]))
+                      for g in range(mg.G)])
+    for i in range(2):
+        for g, fs in enumerate(singles):
+            fs.apply(*local[i][g])
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for i in range(2, 2 + plain_steps):
+        for g, fs in enumerate(singles):
+            fs.apply(*local[i][g])
+    torch.cuda.synchronize()
+    wall_plain = (time.perf_counter() - t2) / plain_steps * nsteps
+    for fs in singles:
+        fs.close()
+    log(f"batched: {nsteps} steps in {wall * 1e3:.2f} ms; plain {wall_plain / nsteps * 1e3:.2f} ms/step")
+    return {"workload": "256 graphs G(n, 4n), n = 10^U(3,6), b = 10^U(1,4) per graph, op per graph "
+                        "and step",
+            "graphs": mg.G, "n_total": mg.n, "m_total": int(len(mg.col) // 2),
+            "updates_per_step": ups, "steps": nsteps,
+            "value": round(ups * nsteps / wall, 1), "unit": "edge updates/s",
+            "ms_per_step": round(wall / nsteps * 1e3, 4),
+            "plain_ms_per_step": round(wall_plain / nsteps * 1e3, 4),
+            "plain_value": round(ups * nsteps / wall_plain, 1),
+            "speedup_vs_plain": round(wall_plain / wall, 2), "tuning": tuning}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +257,15 @@ def main():
     ap.add_argument("--scale", type=int, default=22)
     ap.add_argument("--batch", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-pattern measurement (256 graphs per launch)")
+    ap.add_argument("--batched-steps", type=int, default=6)
+    ap.add_argument("--no-served", action="store_true",
+                    help="skip the served-pattern measurement")
+    ap.add_argument("--served-scale", type=int, default=24)
+    ap.add_argument("--served-requests", type=int, default=2000)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default launch schedule instead of autotuning it first")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, run a plain 512 MiB device copy three times (a known "
                          "byte count for scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -108,17 +311,26 @@ def main():
     f = make(0)
     torch.cuda.synchronize()
     log(f"context created ({time.time() - t0:.1f}s)")
+    tuning = None
+    if not args.no_tune:
+        from paper_2607_20211_amd import autotune
+
+        def sample(fr):
+            fr.apply(d_ins[0], drsf.DRSF_INSERT)
+            fr.apply(d_del[0], drsf.DRSF_DELETE)
+        tuning = autotune.tune(f, sample, f"rmat{scale}_insert{b}_delete{b}", use_cache=False)
+        log(f"tuning: {tuning}")
     for i in range(W):
         f.apply(d_ins[i], drsf.DRSF_INSERT)
         f.apply(d_del[i], drsf.DRSF_DELETE)
     torch.cuda.synchronize()
-    lat_ins, lat_del = [], []
+    lat_ins, lat_del, st_ins, st_del = [], [], [], []
     t_start = time.perf_counter()
     for i in range(W, W + K):
         ta = time.perf_counter()
-        f.apply(d_ins[i], drsf.DRSF_INSERT)
+        st_ins.append(f.apply(d_ins[i], drsf.DRSF_INSERT))
         tb = time.perf_counter()
-        f.apply(d_del[i], drsf.DRSF_DELETE)
+        st_del.append(f.apply(d_del[i], drsf.DRSF_DELETE))
         tc = time.perf_counter()
         lat_ins.append(tb - ta)
         lat_del.append(tc - tb)
@@ -182,6 +394,12 @@ def main():
                          f"scale {scale} graph (insert {t2 - t1:.2f}s, delete {t3 - t2:.2f}s), "
                          f"single-threaded C oracle"}
 
+    batched = None if args.no_batched else run_batched(args.batched_steps, dev, stream, log,
+                                                       not args.no_tune)
+
+    served = None if args.no_served else run_served(args.served_scale, args.served_requests,
+                                                     (0.5, 0.95, 1.5), log)
+
     total_updates = 2 * b * K
     out = {
         "metric": "edge updates/sec (insert, delete) RMAT-22 1e5 batch; served p50/p99 latency",
@@ -210,9 +428,14 @@ def main():
                       "max": round(float(np.max(lat_del)) * 1e3, 4)},
         "insert_device_ms_profiled": round(t_ins_dev * 1e3, 4),
         "delete_device_ms_profiled": round(t_del_dev * 1e3, 4),
+        "batch_stats_insert": {k: float(np.mean([x[k] for x in st_ins])) for k in st_ins[0]},
+        "batch_stats_delete": {k: float(np.mean([x[k] for x in st_del])) for k in st_del[0]},
         "phase_ms_insert": {k: round(v, 4) for k, v in pi.items()},
         "phase_ms_delete": {k: round(v, 4) for k, v in pd.items()},
+        "tuning": tuning,
         "roofline": roofline,
+        "batched": batched,
+        "served": served,
         "cpu_baseline": cpu,
     }
     f.close()

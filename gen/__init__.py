@@ -260,3 +260,70 @@ def multi_step_batches(graph_state: list, ops, bs, s: int):
         out.append(batch)
         ops_out.append(op)
     return out, np.array(ops_out, np.int8)
+
+
+@dataclass
+class BatchedWorkload:
+    """Several graphs side by side with a batch per graph per step (global ids).
+    steps[s] = (edges int32[b, 2], b_off int64[G + 1], ops int8[G])."""
+    mg: MultiGraph
+    steps: list
+    b: np.ndarray                 # int64[G] batch size per graph
+
+
+def batched_workload(G: int, nsteps: int, s: int, log_n=(3.0, 6.0), log_b=(1.0, 4.0)):
+    """The batched workload: G independent G(n_g, 4 n_g) graphs with n_g =
+    round(10^U(log_n)), canonical BFS forests, and per step one batch per
+    graph: op ~ Bernoulli(1/2) per graph and step, size b_g = round(10^U(log_b))
+    per graph.  All batches are drawn from the initial state: inserts are
+    non-edges distinct across steps, deletes are initial edges distinct across
+    steps with half of each batch initial tree edges (they stay tree edges
+    until deleted, since an update keeps every surviving forest edge), so
+    every batch stays valid in sequence.  b_g is capped so that all of a
+    graph's delete steps fit."""
+    ns, ms, _, bs = batched_sizes(G, s, log_n, log_b)
+    ops = (uniform(splitmix64(s ^ 0x5151), G * nsteps).reshape(nsteps, G) < 0.5).astype(np.int8)
+    graphs = []
+    for g in range(G):
+        n, m = int(ns[g]), int(ms[g])
+        m = min(m, n * (n - 1) // 4)
+        keys = gnm(n, m, splitmix64(s + 1 + g)) if m > 0 else np.zeros(0, np.uint64)
+        graphs.append(make_graph(f"g{g}", n, keys))
+    mg = multi_graph(graphs)
+    per_graph = []
+    b_eff = np.zeros(G, np.int64)
+    for g, gr in enumerate(graphs):
+        nd = int((ops[:, g] == 1).sum())
+        ni = nsteps - nd
+        trees = int((gr.parent != np.arange(gr.n)).sum())
+        nontree = gr.m - trees
+        b = int(bs[g])
+        if nd:
+            b = min(b, 2 * (trees // nd), 2 * (nontree // nd) + 1)
+        free = gr.n * (gr.n - 1) // 2 - gr.m
+        if ni:
+            b = min(b, free // (2 * ni))
+        b = max(b, 0)
+        b_eff[g] = b
+        seed_g = splitmix64(s ^ (0xC4 << 40) ^ g)
+        dels = delete_batches(gr.n, gr.keys, gr.parent, nd, b, b // 2, seed_g) if nd and b else None
+        inss = insert_batches(gr.n, gr.keys, ni, b, seed_g ^ 1) if ni and b else None
+        per_graph.append((dels, inss))
+    steps = []
+    used = [[0, 0] for _ in range(G)]
+    for st in range(nsteps):
+        parts, b_off = [], [0]
+        for g in range(G):
+            dels, inss = per_graph[g]
+            o = int(mg.n_off[g])
+            if ops[st, g] == 1:
+                bt = dels[used[g][0]] if dels is not None else np.zeros((0, 2), np.int32)
+                used[g][0] += 1
+            else:
+                bt = inss[used[g][1]] if inss is not None else np.zeros((0, 2), np.int32)
+                used[g][1] += 1
+            parts.append(bt.astype(np.int32) + o)
+            b_off.append(b_off[-1] + len(bt))
+        steps.append((np.concatenate(parts).astype(np.int32), np.array(b_off, np.int64),
+                      ops[st].copy()))
+    return BatchedWorkload(mg, steps, b_eff)

@@ -60,7 +60,8 @@ typedef enum {
                              missing edge); nothing was changed */
     DRSF_E_CAPACITY = -5, /* batch larger than drsf_opts.max_batch, or graph too large */
     DRSF_E_DEVICE = -6,   /* HIP runtime error, or an internal bound was exceeded */
-    DRSF_E_STATE = -7     /* call not valid in the context's current state */
+    DRSF_E_STATE = -7,    /* call not valid in the context's current state */
+    DRSF_E_BUDGET = -8    /* server: the graph does not fit the memory budget */
 } drsf_status;
 
 typedef struct drsf_ctx drsf_ctx;
@@ -77,6 +78,16 @@ typedef struct {
     int64_t max_batch;       /* largest batch accepted by apply; 0 = 1 << 20 */
     int64_t delta_capacity;  /* inserted edges held before the edge store is
                                 rebuilt; 0 = automatic */
+    int sweep_mode;          /* delete key-edge scan: 0 (default) per batch, the
+                                orphans' adjacency when it is at most half the
+                                store, else the whole store; 1: always the whole
+                                store (Sec. II-A as written) */
+    int rounds_queued;       /* hooking rounds (Alg. 2, phase 1) placed in the
+                                captured update graph; an update needing more
+                                finishes them with host-driven launches;
+                                0 = 4 */
+    int levels_queued;       /* super-forest search levels placed in the graph;
+                                0 = 4 (max 12) */
 } drsf_opts;
 
 /* Fills *opts with the defaults described above. */
@@ -180,6 +191,32 @@ int drsf_multi_num_edges(drsf_ctx *ctx, int64_t *m);
 /* Number of graphs in the context (1 for drsf_create). */
 int drsf_num_graphs(const drsf_ctx *ctx);
 
+/*
+ * Digests of the current parent and label arrays (out[0], out[1], host):
+ * order-independent 64-bit sums of a mix of (vertex, value).  Equal arrays
+ * give equal digests; used to compare runs without copying the arrays.
+ */
+int drsf_digest(drsf_ctx *ctx, uint64_t *out);
+
+/* Device bytes the context holds (its own allocations). */
+int64_t drsf_device_bytes(const drsf_ctx *ctx);
+
+/*
+ * Upper estimate of the device bytes drsf_create would hold at its peak for
+ * n vertices and nnz CSR entries (2 |E|) with these options (NULL: defaults);
+ * used for admission against a memory budget.
+ */
+int64_t drsf_footprint(int32_t n, int64_t nnz, const drsf_opts *opts);
+
+/*
+ * Changes the tunables of drsf_opts (rounds_queued, levels_queued,
+ * sweep_mode; 0 = default for the first two) on a live context; the next
+ * apply captures its update graph again.  Results do not depend on them
+ * (only the split between captured and host-driven work does).  Used by the
+ * autotuner.  Errors: DRSF_E_ARG.
+ */
+int drsf_set_tuning(drsf_ctx *ctx, int rounds_queued, int levels_queued, int sweep_mode);
+
 /* Copies parent and/or label (either may be NULL) to host int32[n]. */
 int drsf_copy_out(drsf_ctx *ctx, int32_t *parent_host, int32_t *label_host);
 
@@ -218,6 +255,58 @@ const char *drsf_last_error(const drsf_ctx *ctx);
 
 /* Library version string. */
 const char *drsf_version(void);
+
+/*
+ * Serving: several graphs ("tenants") resident on the GPU under a device
+ * memory budget, updated by a stream of requests (the paper's setting
+ * applied to many graphs at once; no counterpart in its experiments).
+ * A scheduler thread admits tenants in arrival order while their estimated
+ * footprint (drsf_footprint) fits the budget, keeps one FIFO per tenant and
+ * starts the head request of every ready tenant on that tenant's stream, so
+ * updates of different graphs overlap on the device.  Requests of one tenant
+ * are applied one at a time in arrival order (never merged), so each
+ * request's result is the one drsf_apply would give on that graph.
+ *
+ * Times are nanoseconds from drsf_server_start.  arrive_ns >= 0 schedules an
+ * admission or request at that time (a pre-generated arrival stream); < 0
+ * means now.  Requests submitted before their tenant is admitted wait for
+ * it.  Flags: DRSF_SERVER_DIGESTS computes drsf_digest-equal digests of
+ * parent and label after every request; DRSF_SERVER_SERIAL keeps at most one
+ * request in flight over all tenants, in arrival order (the plain path).
+ * All inputs are host memory and are copied.  One thread at a time may call
+ * a server's functions, besides its own scheduler thread.
+ */
+typedef struct drsf_server drsf_server;
+#define DRSF_SERVER_DIGESTS 1
+#define DRSF_SERVER_SERIAL 2
+int drsf_server_create(int64_t budget_bytes, const drsf_opts *opts, int flags, drsf_server **out);
+/* Errors: DRSF_E_BUDGET when the estimate exceeds the whole budget. */
+int drsf_server_admit(drsf_server *srv, int32_t n, const int64_t *row_ptr, const int32_t *col,
+                      const int32_t *parent, int64_t arrive_ns, int32_t *tenant);
+int drsf_server_submit(drsf_server *srv, int32_t tenant, const int32_t *edges, int64_t b, int op,
+                       int64_t arrive_ns, int64_t *req);
+/* The tenant leaves once its submitted requests are done; its memory is freed. */
+int drsf_server_release(drsf_server *srv, int32_t tenant);
+int drsf_server_start(drsf_server *srv);
+/* Blocks until every submitted request is done. */
+int drsf_server_wait_all(drsf_server *srv);
+/*
+ * Blocks until request req is done: status (drsf_status of its update),
+ * t_ns[3] = arrival, start and completion times, digest[2] (with
+ * DRSF_SERVER_DIGESTS).  Any output may be NULL.
+ */
+int drsf_server_result(drsf_server *srv, int64_t req, int32_t *status, uint64_t *t_ns, uint64_t *digest);
+/*
+ * out[6]: completed requests, p50 and p99 of (completion - arrival) in ms,
+ * edge updates per second from the first arrival to the last completion,
+ * peak device bytes of the admitted tenants, the budget.
+ */
+int drsf_server_stats(drsf_server *srv, double *out);
+/* 0 waiting to arrive, 1 queued for admission, 2 live, 3 released, 4 failed. */
+int32_t drsf_server_tenant_state(drsf_server *srv, int32_t tenant);
+const char *drsf_server_error(const drsf_server *srv);
+/* Waits for submitted requests, then frees everything. */
+void drsf_server_destroy(drsf_server *srv);
 
 #ifdef __cplusplus
 }

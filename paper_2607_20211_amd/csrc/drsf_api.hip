@@ -29,8 +29,8 @@ namespace {
 
 thread_local std::string g_create_error;
 
-constexpr int BOR_FAST = 4;    // hooking rounds queued in the captured sequence
-constexpr int BFS_FAST = 4;    // search levels queued in the captured sequence
+constexpr int BOR_FAST = 4;    // default hooking rounds queued in the captured sequence
+constexpr int BFS_FAST = 4;    // default search levels queued in the captured sequence
 constexpr int BFS_MAX = 12;    // deeper super-trees use the Euler tour instead
 constexpr int BOR_CHUNK = 3;   // rounds per host check in the continuation
 
@@ -51,7 +51,7 @@ struct drsf_snapshot {
     uint64_t dhmask = 0;
     unsigned long long ndelta = 0;
     std::vector<int64_t> gm;
-    int32_t *parent = nullptr, *label = nullptr, *bcol = nullptr, *dhpos = nullptr;
+    int32_t *parent = nullptr, *label = nullptr, *bcol = nullptr, *lcol = nullptr, *dhpos = nullptr;
     uint64_t *dkey = nullptr, *dhash = nullptr;
 };
 
@@ -70,8 +70,8 @@ struct drsf_ctx {
     int32_t *goff = nullptr;
     int32_t *gstat = nullptr;
     // edge store
-    uint32_t *bptr = nullptr;
-    int32_t *bcol = nullptr;
+    uint32_t *bptr = nullptr, *lptr = nullptr;
+    int32_t *bcol = nullptr, *lcol = nullptr;
     int64_t eb = 0;
     int32_t *zrow = nullptr;
     uint32_t *zptr = nullptr;
@@ -100,7 +100,15 @@ struct drsf_ctx {
     int8_t *bop = nullptr;
     uint64_t *bkey = nullptr, *bhash = nullptr;
     int64_t *bloc = nullptr;
+    uint32_t *twin = nullptr;
     uint64_t bhmask = 0;
+    // orphan scan
+    int64_t nvb = 0;
+    int64_t *bvol = nullptr, *bpre = nullptr;
+    unsigned long long *gsum = nullptr, *gpre = nullptr;
+    int32_t *bcnt = nullptr, *opre = nullptr, *rstart = nullptr;
+    OrphEnt *olist = nullptr, *ostage = nullptr;
+    unsigned long long *xcnt = nullptr;
     int32_t *lists = nullptr;      // vlist | ilist | tlist (several graphs)
     int64_t nvblk = 0;
     // lists
@@ -112,6 +120,11 @@ struct drsf_ctx {
     int32_t *arc_nxt = nullptr, *succ0 = nullptr, *succ1 = nullptr, *rank0 = nullptr, *rank1 = nullptr;
     PathReq *paths = nullptr;
     int64_t pathcap = 0;
+    // status word, counters and per-graph batch status share one allocation
+    // so that one copy returns them: status at word 0, counters from word 1,
+    // gstat after the counters
+    unsigned long long *ctlmem = nullptr;
+    int64_t ret_words = 0;
     int32_t *status = nullptr;
     unsigned long long *cnt = nullptr;
     Ctl *ctl = nullptr;
@@ -121,11 +134,13 @@ struct drsf_ctx {
     int32_t *h_bgid = nullptr;            // [max_batch]
     int32_t *h_lists = nullptr;           // vlist | ilist | tlist
     Ctl *h_ctl = nullptr;
-    unsigned long long *h_ret = nullptr;  // [0] status, [1, 1 + C_COUNT) counters, then scratch
-    int32_t *h_gstat = nullptr;           // [ngraph]
-    // captured update sequence
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    unsigned long long *h_ret = nullptr;  // copy of ctlmem, then scratch words
+    int32_t *h_gstat = nullptr;           // [ngraph] inside h_ret
+    // captured update sequences, by kind (1 inserts, 2 deletes, 3 both)
+    hipGraph_t graph[4] = {};
+    hipGraphExec_t gexec[4] = {};
+    int kind = 0;  // of the pending update
+    int bor_fast = BOR_FAST, bfs_fast = BFS_FAST;
     // last apply
     bool pending = false;
     bool multi_last = false;
@@ -140,6 +155,8 @@ struct drsf_ctx {
     bool have_phases = false;
     std::string err;
     std::vector<void *> allocs;
+    std::vector<size_t> alloc_bytes;
+    int64_t bytes = 0, peak_bytes = 0;  // device bytes held now / at most
 };
 
 namespace {
@@ -170,6 +187,9 @@ int dalloc(drsf_ctx *c, T **p, int64_t count) {
         return fail(c, DRSF_E_NOMEM, "device allocation of %zu bytes failed", bytes);
     }
     c->allocs.push_back(q);
+    c->alloc_bytes.push_back(bytes);
+    c->bytes += (int64_t)bytes;
+    c->peak_bytes = std::max(c->peak_bytes, c->bytes);
     *p = (T *)q;
     return DRSF_OK;
 }
@@ -187,7 +207,12 @@ int halloc(drsf_ctx *c, T **p, int64_t count) {
 void dfree(drsf_ctx *c, void *p) {
     if (!p) return;
     auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
-    if (it != c->allocs.end()) c->allocs.erase(it);
+    if (it != c->allocs.end()) {
+        const size_t k = (size_t)(it - c->allocs.begin());
+        c->bytes -= (int64_t)c->alloc_bytes[k];
+        c->alloc_bytes.erase(c->alloc_bytes.begin() + (std::ptrdiff_t)k);
+        c->allocs.erase(it);
+    }
     (void)hipFree(p);
 }
 
@@ -197,6 +222,10 @@ Dev make_dev(drsf_ctx *c) {
     d.n = c->n;
     d.ctl = c->ctl;
     d.bptr = c->bptr; d.bcol = c->bcol; d.eb = c->eb;
+    d.lptr = c->lptr; d.lcol = c->lcol; d.twin = c->twin;
+    d.nvb = c->nvb; d.bvol = c->bvol; d.bcnt = c->bcnt; d.bpre = c->bpre; d.opre = c->opre;
+    d.olist = c->olist; d.rstart = c->rstart; d.xcnt = c->xcnt;
+    d.gsum = c->gsum; d.gpre = c->gpre; d.ostage = c->ostage;
     d.zrow = c->zrow; d.zptr = c->zptr; d.nz = c->nz; d.tile_k = c->tile_k; d.ntiles = c->ntiles;
     d.dtmax = c->dtmax;
     d.dkey = c->dkey; d.dcap = c->dcap; d.dhash = c->dhash; d.dhpos = c->dhpos; d.dhmask = c->dhmask;
@@ -288,7 +317,20 @@ int alloc_state(drsf_ctx *c) {
     c->pathcap = std::max<int64_t>(c->ercap + c->pcap, n);
     if ((rc = dalloc(c, &c->paths, c->pathcap))) return rc;
     if ((rc = dalloc(c, &c->ctl, 1))) return rc;
-    if ((rc = dalloc(c, &c->gstat, c->ngraph))) return rc;
+    // orphan scan: per-block figures (zero between updates), list, ranges
+    c->nvb = (n + BLOCK - 1) / BLOCK;
+    if ((rc = dalloc(c, &c->bvol, c->nvb))) return rc;
+    if ((rc = dalloc(c, &c->bcnt, c->nvb))) return rc;
+    if ((rc = dalloc(c, &c->bpre, c->nvb))) return rc;
+    if ((rc = dalloc(c, &c->opre, c->nvb))) return rc;
+    if ((rc = dalloc(c, &c->gsum, (c->nvb + BLOCK - 1) / BLOCK))) return rc;
+    if ((rc = dalloc(c, &c->gpre, (c->nvb + BLOCK - 1) / BLOCK))) return rc;
+    if ((rc = dalloc(c, &c->olist, n))) return rc;
+    if ((rc = dalloc(c, &c->ostage, c->nvb * BLOCK))) return rc;
+    if ((rc = dalloc(c, &c->rstart, c->ntiles + 1))) return rc;
+    if ((rc = dalloc(c, &c->xcnt, c->ntiles + 1))) return rc;
+    launch_fill_u64(reinterpret_cast<uint64_t *>(c->bvol), c->nvb, 0, s);
+    launch_fill_i32(c->bcnt, c->nvb, 0, s);
     if (c->ngraph > 1) {
         // every vertex block and every tile appears at most once per list
         c->nvblk = (n + BLOCK - 1) / BLOCK;
@@ -300,24 +342,24 @@ int alloc_state(drsf_ctx *c) {
     if ((rc = halloc(c, &c->h_bop, mb))) return rc;
     if ((rc = halloc(c, &c->h_bgid, mb))) return rc;
     if ((rc = halloc(c, &c->h_ctl, 1))) return rc;
-    if ((rc = halloc(c, &c->h_gstat, c->ngraph))) return rc;
     launch_fill_i32(c->tidx, n, NONE, s);
     launch_fill_u64(c->bhash, (int64_t)bh, HASH_EMPTY, s);
     launch_fill_u64(c->dhash, (int64_t)dh, HASH_EMPTY, s);
     launch_fill_u64(c->obits, (n + 63) / 64, 0, s);
     launch_fill_u64(c->rcnt, nregmax, 0, s);
-    launch_fill_i32(c->gstat, c->ngraph, 0, s);
     return DRSF_OK;
 }
 
 void destroy_ctx(drsf_ctx *c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-    if (c->graph) (void)hipGraphDestroy(c->graph);
+    for (int k = 0; k < 4; k++) {
+        if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+        if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+    }
     for (void *p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
-    void *hosts[] = {c->h_edges, c->h_bop, c->h_bgid, c->h_lists, c->h_ctl, c->h_ret, c->h_gstat};
+    void *hosts[] = {c->h_edges, c->h_bop, c->h_bgid, c->h_lists, c->h_ctl, c->h_ret};
     for (void *p : hosts)
         if (p) (void)hipHostFree(p);
     for (auto &e : c->ev)
@@ -354,7 +396,6 @@ int build_store(drsf_ctx *c, const int64_t *row_ptr_in, const int32_t *col_in, i
     unsigned long long *dtotal = (unsigned long long *)(tmp + scan_tmp_bytes(n));
     launch_fill_i32(c->status, 1, 0, s);
     launch_csr_check(n, drow, dcol, ucnt, c->status, c->ngraph > 1 ? c->goff : nullptr, c->ngraph, s);
-    launch_csr_symmetric(n, drow, dcol, c->status, s);
     launch_scan_u32(ucnt, c->bptr, dtotal, n, tmp, s);
     HIPCHK(c, hipMemcpyAsync(c->h_ret, dtotal, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(c->h_ret + 1, c->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -364,11 +405,29 @@ int build_store(drsf_ctx *c, const int64_t *row_ptr_in, const int32_t *col_in, i
     if (st & 1)
         return fail(c, DRSF_E_ARG, "CSR rows must be strictly ascending, without self-loops, with ids in range%s",
                     c->ngraph > 1 ? " of the row's graph" : "");
-    if ((st & 2) || 2 * (int64_t)total != nnz) return fail(c, DRSF_E_ARG, "CSR is not symmetric");
+    if (2 * (int64_t)total != nnz) return fail(c, DRSF_E_ARG, "CSR is not symmetric");
     if (total >= 0xffffffffull) return fail(c, DRSF_E_CAPACITY, "more than 2^32-1 undirected edges");
     c->eb = (int64_t)total;
-    if ((rc = dalloc(c, &c->bcol, c->eb))) return rc;
+    c->ntiles = (c->eb + TILE - 1) / TILE;
+    // padded to whole sweep tiles with deleted entries
+    if ((rc = dalloc(c, &c->bcol, c->ntiles * TILE))) return rc;
+    launch_fill_i32(c->bcol + c->eb, c->ntiles * TILE - c->eb, TOMB, s);
     launch_upper_fill(n, drow, dcol, c->bptr, c->bcol, s);
+    // lower half (row v holds u < v), for the orphan scan
+    launch_lower_counts(n, drow, c->bptr, ucnt, s);
+    if ((rc = dalloc(c, &c->lptr, (int64_t)n + 1))) return rc;
+    launch_scan_u32(ucnt, c->lptr, dtotal, n, tmp, s);
+    if ((rc = dalloc(c, &c->lcol, c->eb))) return rc;
+    launch_lower_fill(n, drow, dcol, c->lptr, c->lcol, s);
+    if ((rc = dalloc(c, &c->twin, c->eb))) return rc;
+    // every lower entry finds its mirror in the upper half: with equal halves
+    // this is the symmetry check
+    launch_twin(n, c->bptr, c->bcol, c->lptr, c->lcol, c->twin, c->status, s);
+    {
+        int32_t st2;
+        if ((rc = read_status(c, &st2))) return rc;
+        if (st2 & 2) return fail(c, DRSF_E_ARG, "CSR is not symmetric");
+    }
     // non-empty-row index for the sweep
     launch_nonempty_flags(n, c->bptr, ucnt, s);
     uint32_t *zpos = nullptr;
@@ -380,7 +439,6 @@ int build_store(drsf_ctx *c, const int64_t *row_ptr_in, const int32_t *col_in, i
     if ((rc = dalloc(c, &c->zrow, c->nz))) return rc;
     if ((rc = dalloc(c, &c->zptr, c->nz + 1))) return rc;
     launch_nonempty_fill(n, c->bptr, zpos, c->zrow, c->zptr, c->nz, s);
-    c->ntiles = (c->eb + TILE - 1) / TILE;
     if ((rc = dalloc(c, &c->tile_k, c->ntiles + 1))) return rc;
     launch_tile_k(c->zptr, c->nz, c->eb, c->tile_k, c->ntiles, s);
     // base-store offsets of each graph's rows (host copy, for the tile lists)
@@ -445,17 +503,16 @@ int canonicalise_forest(drsf_ctx *c) {
 
 void enqueue_results_copy(drsf_ctx *c) {
     hipStream_t s = c->stream;
-    (void)hipMemcpyAsync(c->h_ret, c->status, sizeof(int32_t), hipMemcpyDeviceToHost, s);
-    (void)hipMemcpyAsync(c->h_ret + 1, c->cnt, sizeof(unsigned long long) * C_COUNT,
-                         hipMemcpyDeviceToHost, s);
-    (void)hipMemcpyAsync(c->h_gstat, c->gstat, sizeof(int32_t) * (size_t)c->ngraph,
+    (void)hipMemcpyAsync(c->h_ret, c->ctlmem, sizeof(unsigned long long) * (size_t)c->ret_words,
                          hipMemcpyDeviceToHost, s);
 }
 
-// The update sequence (see the file comment); with events when profiling.
-void enqueue_update(drsf_ctx *c, bool profile) {
+// The update sequence (see the file comment) for batches with inserts
+// (kind bit 1) and/or deletes (kind bit 2); with events when profiling.
+void enqueue_update(drsf_ctx *c, int kind, bool profile) {
     const Dev d = make_dev(c);
     hipStream_t s = c->stream;
+    const bool ins = kind & 1, del = kind & 2;
     auto mark = [&](int i) {
         if (profile) (void)hipEventRecord(c->ev[i], s);
     };
@@ -465,35 +522,38 @@ void enqueue_update(drsf_ctx *c, bool profile) {
     launch_prepare(d, s);
     launch_register(d, s);
     mark(PH_ROOTS);
-    launch_rep(d, s);
+    if (del) launch_rep(d, s);
     mark(PH_SWEEP);
-    launch_sweep_base(d, s);
+    if (del) {
+        launch_orphan_scan(d, s);
+        launch_sweep_base(d, s);
+    }
     mark(PH_SWEEP_DELTA);
-    launch_insert_emit(d, s);
-    launch_sweep_delta(d, s);
+    if (ins) launch_insert_emit(d, s);
+    if (del) launch_sweep_delta(d, s);
     mark(PH_REPL);
-    launch_boruvka(d, 0, BOR_FAST, s);
+    launch_boruvka(d, 0, c->bor_fast, s);
     mark(PH_ROOTING);
     launch_sf_root(d, s);
-    launch_sf_bfs(d, 0, BFS_FAST, s);
-    launch_orient_bfs(d, BFS_FAST, s);
+    launch_sf_bfs(d, 0, c->bfs_fast, s);
+    launch_orient_bfs(d, c->bfs_fast, s);
     mark(PH_REVERSE);
     launch_reverse(d, s);
     mark(PH_LABELS);
-    launch_labels(d, s);
+    launch_labels(d, ins, del, s);
     mark(PH_N);
     enqueue_results_copy(c);
     launch_cleanup(d, s);
 }
 
-int capture_graph(drsf_ctx *c) {
-    if (c->gexec) return DRSF_OK;
+int capture_graph(drsf_ctx *c, int kind) {
+    if (c->gexec[kind]) return DRSF_OK;
     HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    enqueue_update(c, false);
+    enqueue_update(c, kind, false);
     hipGraph_t g = nullptr;
     HIPCHK(c, hipStreamEndCapture(c->stream, &g));
-    c->graph = g;
-    HIPCHK(c, hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0));
+    c->graph[kind] = g;
+    HIPCHK(c, hipGraphInstantiate(&c->gexec[kind], g, nullptr, nullptr, 0));
     return DRSF_OK;
 }
 
@@ -503,7 +563,7 @@ int capture_graph(drsf_ctx *c) {
 int continue_update(drsf_ctx *c) {
     const Dev d = make_dev(c);
     hipStream_t s = c->stream;
-    unsigned long long *f = c->h_ret + 1 + C_COUNT;  // [0] status, [1] rounds done, [2] level active
+    unsigned long long *f = c->h_ret + c->ret_words;  // [0] status, [1] rounds done, [2] level active
     auto read_flags = [&](int levels) -> int {
         HIPCHK(c, hipMemcpyAsync(f, c->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipMemcpyAsync(f + 1, c->cnt + C_DONE_BOR, sizeof(unsigned long long),
@@ -518,9 +578,9 @@ int continue_update(drsf_ctx *c) {
     const int bor_bound = std::min(ceil_log2(np_max + 2) + 2, MAX_ROUNDS);
     const int lr_rounds = std::min(ceil_log2(2 * np_max + 2) + 2, MAX_ROUNDS);
     int rc;
-    if ((rc = read_flags(BFS_FAST))) return rc;
+    if ((rc = read_flags(c->bfs_fast))) return rc;
     bool bad = *(int32_t *)f != 0, done = f[1] != 0, bfs_done = f[2] == 0;
-    int r = BOR_FAST, lv = BFS_FAST;
+    int r = c->bor_fast, lv = c->bfs_fast;
     if (!bad && !done) {
         while (!done && !bad && r < bor_bound) {
             const int r1 = std::min(r + BOR_CHUNK, bor_bound);
@@ -536,7 +596,7 @@ int continue_update(drsf_ctx *c) {
         }
         if (!bad) {
             launch_sf_root(d, s);
-            launch_sf_bfs(d, 0, BFS_FAST, s);
+            launch_sf_bfs(d, 0, c->bfs_fast, s);
             if ((rc = read_flags(lv))) return rc;
             bad = *(int32_t *)f != 0;
             bfs_done = f[2] == 0;
@@ -544,15 +604,15 @@ int continue_update(drsf_ctx *c) {
     }
     if (!bad) {
         while (!bfs_done && lv < BFS_MAX) {
-            launch_sf_bfs(d, lv, lv + BFS_FAST, s);
-            lv += BFS_FAST;
+            launch_sf_bfs(d, lv, lv + 4, s);
+            lv += 4;
             if ((rc = read_flags(lv))) return rc;
             bfs_done = f[2] == 0;
         }
         if (bfs_done) launch_orient_bfs(d, lv, s);
         else launch_superforest_lr(d, lr_rounds, s);  // deep super-trees: Euler tour
         launch_reverse(d, s);
-        launch_labels(d, s);
+        launch_labels(d, c->kind & 1, c->kind & 2, s);
     }
     enqueue_results_copy(c);
     launch_cleanup(d, s);
@@ -566,12 +626,14 @@ int launch_update(drsf_ctx *c) {
     hipStream_t s = c->stream;
     HIPCHK(c, hipMemcpyAsync(c->ctl, c->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, s));
     const bool prof = c->opts.profile != 0;
+    c->kind = (c->h_ctl->has_ins ? 1 : 0) | (c->h_ctl->has_del ? 2 : 0);
+    if (c->kind == 0) c->kind = 3;  // nothing but rejected or empty batches: run everything
     if (prof) {
-        enqueue_update(c, true);
+        enqueue_update(c, c->kind, true);
     } else {
         int rc;
-        if ((rc = capture_graph(c))) return rc;
-        HIPCHK(c, hipGraphLaunch(c->gexec, s));
+        if ((rc = capture_graph(c, c->kind))) return rc;
+        HIPCHK(c, hipGraphLaunch(c->gexec[c->kind], s));
     }
     HIPCHK(c, hipGetLastError());
     c->pending = true;
@@ -642,6 +704,8 @@ static int create_impl(int32_t G, const int32_t *n_off, int32_t n, const int64_t
     if (opts) c->opts = *opts; else drsf_default_opts(&c->opts);
     if (c->opts.max_batch <= 0) c->opts.max_batch = 1 << 20;
     c->max_batch = c->opts.max_batch;
+    if (c->opts.rounds_queued > 0) c->bor_fast = std::min(c->opts.rounds_queued, MAX_ROUNDS - 1);
+    if (c->opts.levels_queued > 0) c->bfs_fast = std::min(c->opts.levels_queued, BFS_MAX);
     c->n = n;
     c->ngraph = G;
     c->goff_h.assign((size_t)G + 1, 0);
@@ -674,14 +738,19 @@ static int create_impl(int32_t G, const int32_t *n_off, int32_t n, const int64_t
         }
         c->own_stream = true;
     }
-    if ((rc = halloc(c, &c->h_ret, C_TOTAL + 16))) return bail(rc);
+    c->ret_words = 1 + C_TOTAL + (G + 1) / 2;
+    if ((rc = halloc(c, &c->h_ret, c->ret_words + 8))) return bail(rc);
+    c->h_gstat = reinterpret_cast<int32_t *>(c->h_ret + 1 + C_TOTAL);
     for (auto &e : c->ev)
         if (hipEventCreate(&e) != hipSuccess) {
             fail(c, DRSF_E_DEVICE, "event creation failed");
             return bail(DRSF_E_DEVICE);
         }
-    if ((rc = dalloc(c, &c->status, 4))) return bail(rc);
-    if ((rc = dalloc(c, &c->cnt, C_TOTAL))) return bail(rc);
+    if ((rc = dalloc(c, &c->ctlmem, c->ret_words))) return bail(rc);
+    c->status = reinterpret_cast<int32_t *>(c->ctlmem);
+    c->cnt = c->ctlmem + 1;
+    c->gstat = reinterpret_cast<int32_t *>(c->ctlmem + 1 + C_TOTAL);
+    launch_fill_u64(c->ctlmem, c->ret_words, 0, c->stream);
     if ((rc = dalloc(c, &c->goff, (int64_t)G + 1))) return bail(rc);
     if (hipMemcpy(c->goff, c->goff_h.data(), sizeof(int32_t) * ((size_t)G + 1), hipMemcpyHostToDevice) !=
         hipSuccess) {
@@ -750,6 +819,69 @@ int drsf_multi_create(int32_t G, const int32_t *n_off, const int64_t *row_ptr, c
 
 int drsf_num_graphs(const drsf_ctx *c) { return c ? c->ngraph : 0; }
 
+int64_t drsf_device_bytes(const drsf_ctx *c) { return c ? c->bytes : -1; }
+
+int drsf_digest(drsf_ctx *c, uint64_t *out) {
+    if (!c || !out) return DRSF_E_ARG;
+    const int rc = finish_pending(c);
+    if (rc) return rc;
+    unsigned long long *dd = c->cnt + C_COUNT;  // two spare counter words
+    launch_digest(c->n, c->parent, c->label, dd, c->stream);
+    HIPCHK(c, hipMemcpyAsync(c->h_ret, dd, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    out[0] = c->h_ret[0];
+    out[1] = c->h_ret[1];
+    launch_fill_u64(dd, 2, 0, c->stream);
+    return DRSF_OK;
+}
+
+int64_t drsf_footprint(int32_t n, int64_t nnz, const drsf_opts *opts) {
+    // the allocations of create (peak, with the host-input staging) and of
+    // the per-context state, as sized in build_store and alloc_state
+    drsf_opts o;
+    if (opts) o = *opts; else drsf_default_opts(&o);
+    const int64_t mb = o.max_batch > 0 ? o.max_batch : (1 << 20);
+    const int64_t eb = nnz / 2, N = n;
+    const int64_t ntiles = (eb + TILE - 1) / TILE;
+    const int64_t nvb = (N + BLOCK - 1) / BLOCK;
+    const int64_t pcap = 2 * mb + 16;
+    const int64_t dcap = o.delta_capacity > 0 ? o.delta_capacity : std::max<int64_t>({4 * mb, eb / 8, 1 << 20});
+    auto pow2 = [](int64_t x) { int64_t p = 16; while (p < x) p <<= 1; return p; };
+    const int64_t bh = pow2(2 * mb), dh = pow2(2 * dcap);
+    const int64_t xcap = (ntiles + (dcap + TILE - 1) / TILE + (mb + BLOCK - 1) / BLOCK) * TILE;
+    int64_t b = 0;
+    b += o.inputs_on_device ? 0 : 8 * (N + 1) + 4 * nnz;                 // staged input
+    b += 4 * (N + 1) * 3 + 4 * ntiles * TILE + 8 * eb + 4 * (ntiles + 1);  // bptr, lptr, zptr; bcol; lcol, twin
+    b += 4 * N * 2;                                                       // zrow, parent
+    b += 16 * N + (N + 63) / 64 * 8;                                      // label, rep, tidx, owner; bitmap
+    b += 49 * pcap + 40 * pcap + 16 * pcap + 16 * std::max(2 * pcap, N);  // pieces, tour, er, paths
+    b += 37 * mb + 8 * bh + 8 * dcap + 12 * dh;                           // batch, tables, inserted list
+    b += 32 * xcap + 8 * (xcap / TILE);                                   // cross lists
+    b += 24 * nvb + 40 * N + 40 * nvb * BLOCK + 16 * (ntiles + 1);       // orphan scan
+    return b + (1 << 20);
+}
+
+int drsf_set_tuning(drsf_ctx *c, int rounds_queued, int levels_queued, int sweep_mode) {
+    if (!c) return DRSF_E_ARG;
+    if (sweep_mode < 0 || sweep_mode > 1) return fail(c, DRSF_E_ARG, "sweep_mode must be 0 or 1");
+    const int rc = finish_pending(c);
+    if (rc) return rc;
+    c->bor_fast = rounds_queued > 0 ? std::min(rounds_queued, MAX_ROUNDS - 1) : BOR_FAST;
+    c->bfs_fast = levels_queued > 0 ? std::min(levels_queued, BFS_MAX) : BFS_FAST;
+    c->opts.rounds_queued = rounds_queued;
+    c->opts.levels_queued = levels_queued;
+    c->opts.sweep_mode = sweep_mode;
+    // the captured sequences hold the old round counts
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < 4; k++) {
+        if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+        if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+        c->gexec[k] = nullptr;
+        c->graph[k] = nullptr;
+    }
+    return DRSF_OK;
+}
+
 int drsf_apply_async(drsf_ctx *c, const int32_t *edges, int64_t b, int op) {
     if (!c) return DRSF_E_ARG;
     int rc;
@@ -780,7 +912,8 @@ int drsf_apply_async(drsf_ctx *c, const int32_t *edges, int64_t b, int op) {
     k.has_ins = op == DRSF_INSERT;
     k.has_del = op == DRSF_DELETE;
     k.ngraph = 1;
-    k.lfast = BFS_FAST;
+    k.lfast = c->bfs_fast;
+    k.smode = c->opts.sweep_mode;
     k.nvl = k.nil = k.ntl = -1;
     if (op == DRSF_INSERT) c->ndelta_bound += b;
     set_regions(c, k);
@@ -860,7 +993,8 @@ int drsf_multi_apply_async(drsf_ctx *c, const int32_t *edges, const int64_t *b_o
     k.has_ins = any_ins;
     k.has_del = any_del;
     k.ngraph = G;
-    k.lfast = BFS_FAST;
+    k.lfast = c->bfs_fast;
+    k.smode = c->opts.sweep_mode;
     k.nvl = nvl;
     k.nil = nil;
     k.ntl = ntl;
@@ -1038,6 +1172,7 @@ int drsf_snapshot_take(drsf_ctx *c, drsf_snapshot **out) {
     const bool ok = hipMalloc(&s->parent, 4 * (size_t)c->n) == hipSuccess &&
                     hipMalloc(&s->label, 4 * (size_t)c->n) == hipSuccess &&
                     hipMalloc(&s->bcol, 4 * (size_t)std::max<int64_t>(c->eb, 1)) == hipSuccess &&
+                    hipMalloc(&s->lcol, 4 * (size_t)std::max<int64_t>(c->eb, 1)) == hipSuccess &&
                     hipMalloc(&s->dkey, 8 * (size_t)c->dcap) == hipSuccess &&
                     hipMalloc(&s->dhash, 8 * dh) == hipSuccess &&
                     hipMalloc(&s->dhpos, 4 * dh) == hipSuccess;
@@ -1050,6 +1185,7 @@ int drsf_snapshot_take(drsf_ctx *c, drsf_snapshot **out) {
     HIPCHK(c, hipMemcpyAsync(s->parent, c->parent, 4 * (size_t)c->n, hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipMemcpyAsync(s->label, c->label, 4 * (size_t)c->n, hipMemcpyDeviceToDevice, st));
     if (c->eb) HIPCHK(c, hipMemcpyAsync(s->bcol, c->bcol, 4 * (size_t)c->eb, hipMemcpyDeviceToDevice, st));
+    if (c->eb) HIPCHK(c, hipMemcpyAsync(s->lcol, c->lcol, 4 * (size_t)c->eb, hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipMemcpyAsync(s->dkey, c->dkey, 8 * (size_t)c->dcap, hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipMemcpyAsync(s->dhash, c->dhash, 8 * dh, hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipMemcpyAsync(s->dhpos, c->dhpos, 4 * dh, hipMemcpyDeviceToDevice, st));
@@ -1073,6 +1209,7 @@ int drsf_snapshot_restore(drsf_ctx *c, const drsf_snapshot *s) {
     HIPCHK(c, hipMemcpyAsync(c->label, s->label, 4 * (size_t)c->n, hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipMemcpyAsync(c->rep, s->label, 4 * (size_t)c->n, hipMemcpyDeviceToDevice, st));
     if (c->eb) HIPCHK(c, hipMemcpyAsync(c->bcol, s->bcol, 4 * (size_t)c->eb, hipMemcpyDeviceToDevice, st));
+    if (c->eb) HIPCHK(c, hipMemcpyAsync(c->lcol, s->lcol, 4 * (size_t)c->eb, hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipMemcpyAsync(c->dkey, s->dkey, 8 * (size_t)c->dcap, hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipMemcpyAsync(c->dhash, s->dhash, 8 * dh, hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipMemcpyAsync(c->dhpos, s->dhpos, 4 * dh, hipMemcpyDeviceToDevice, st));
@@ -1091,6 +1228,7 @@ void drsf_snapshot_free(drsf_snapshot *s) {
     (void)hipFree(s->parent);
     (void)hipFree(s->label);
     (void)hipFree(s->bcol);
+    (void)hipFree(s->lcol);
     (void)hipFree(s->dkey);
     (void)hipFree(s->dhash);
     (void)hipFree(s->dhpos);

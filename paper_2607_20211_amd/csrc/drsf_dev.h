@@ -43,7 +43,10 @@ enum : int {
     C_DONE_BOR = 6,  // replacement-edge rounds finished
     C_DONE_LR = 7,   // list ranking finished
     C_ORIENTED = 8,  // orientation done: the rest of the update may run
+    C_OMODE = 9,     // delete sweep restricted to the orphans' adjacency
     C_NDELTA = 10,   // inserted-edge list length (persistent)
+    C_OVOL = 11,     // adjacency slots of the listed orphan vertices
+    C_NORPH = 13,    // listed orphan vertices (orphans with at least one slot)
     C_LR_FINAL = 12, // buffer holding the final list ranks
     C_COUNT = 16,
 };
@@ -55,6 +58,19 @@ struct Cross {      // one cross edge between pieces (dense piece ids)
 
 struct PathReq {    // reverse the path start -> ... -> stop, then parent[start] = newpar
     int32_t start, newpar, stop, pad;
+};
+
+// One orphan vertex (a vertex cut off from its old root) with adjacency to
+// scan: slots [pre, pre + du + dl) of the concatenated orphan adjacency are
+// its du upper-store entries from ustart, then its dl lower-store entries
+// from lstart (followed by padding slots that hold no work).
+struct OrphEnt {
+    int64_t pre;
+    uint32_t ustart, lstart;
+    int32_t v, du, dl;
+    int32_t pu;     // dense id of the vertex's piece
+    int32_t ru;     // root of that piece (rep of the vertex)
+    int32_t pad;
 };
 
 __device__ __forceinline__ uint64_t mkkey(uint32_t a, uint32_t b) {

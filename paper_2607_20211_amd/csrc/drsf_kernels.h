@@ -20,7 +20,7 @@ struct Ctl {
     int32_t has_del;  // some edge deletes
     int32_t ngraph;   // graphs in this context (per-graph batch status)
     int32_t lfast;    // search levels queued before the orientation step
-    int32_t pad;
+    int32_t smode;    // delete sweep: 0 chosen per batch, 1 always the full store
 };
 
 // All device pointers one apply needs; passed by value to every kernel.
@@ -46,6 +46,26 @@ struct Dev {
     uint64_t *dhash;         // [dhmask + 1] key -> slot, HASH_TOMB_BIT marks a deleted key
     int32_t *dhpos;          // [dhmask + 1] slot -> index in dkey
     uint64_t dhmask;
+    // lower half of the same store (row v holds u < v, ascending; TOMB kept
+    // in step with the upper copy), so that a vertex's whole adjacency is
+    // two contiguous runs
+    const uint32_t *lptr;    // [n + 1]
+    int32_t *lcol;           // [eb]
+    const uint32_t *twin;    // [eb] position in lcol of the mirror of each bcol entry
+    // orphan adjacency scan (delete): per vertex block of BLOCK vertices the
+    // listed orphans and their slots, prefixes, the compacted list and, per
+    // range of OR_W slots, the list index holding its first slot
+    int64_t nvb;             // vertex blocks
+    int64_t *bvol;           // [nvb] slots of the block's orphans (zero between updates)
+    int32_t *bcnt;           // [nvb] listed orphans of the block (zero between updates)
+    int64_t *bpre;           // [nvb] slots before the block within its group of BLOCK blocks
+    int32_t *opre;           // [nvb] orphans before the block within its group
+    unsigned long long *gsum;  // [ngroups] packed (slots, orphans) per group
+    unsigned long long *gpre;  // [ngroups] packed prefix over the groups
+    OrphEnt *olist;          // [n] every orphan, vertex order
+    OrphEnt *ostage;         // [nvb * BLOCK] each block's orphans, compacted at the block's start
+    int32_t *rstart;         // [ntiles + 1]
+    unsigned long long *xcnt;  // [ntiles] cross edges found per range
     // forest.  Between updates rep[v] == label[v]; a delete recomputes rep as
     // the root of v in F-hat.
     int32_t *parent;         // [n]
@@ -105,6 +125,17 @@ struct Dev {
     unsigned long long *cnt; // [C_TOTAL]
 };
 
+// slots per range of the orphan adjacency scan; a range's cross edges go to
+// the region of x0 with the range's index, so ranges must not outnumber the
+// base-store tiles: the orphan scan is used only when its slots are at most
+// eb / OR_MAX_FRAC (and OR_W * OR_MAX_FRAC <= TILE)
+constexpr int OR_W = 2048;
+constexpr int OR_MAX_FRAC = 2;
+constexpr int OR_K = OR_W / BLOCK;  // slots per thread per range
+// every orphan also owns OR_PAD empty slots after its adjacency, so a range
+// meets at most about OR_W / OR_PAD orphans: one LDS window of BLOCK
+constexpr int OR_PAD = OR_W / BLOCK;
+
 constexpr int MAX_ROUNDS = 64;
 // extra counter slots: per-round activity flags
 constexpr int C_LR_ROUND = C_COUNT + MAX_ROUNDS;       // [MAX_ROUNDS]
@@ -124,6 +155,7 @@ void launch_register(const Dev &d, hipStream_t s);
 void launch_insert_emit(const Dev &d, hipStream_t s);
 void launch_rep(const Dev &d, hipStream_t s);
 void launch_sweep_base(const Dev &d, hipStream_t s);
+void launch_orphan_scan(const Dev &d, hipStream_t s);  // plan, list, scan
 void launch_sweep_delta(const Dev &d, hipStream_t s);
 void launch_boruvka(const Dev &d, int r0, int r1, hipStream_t s);
 void launch_sf_root(const Dev &d, hipStream_t s);
@@ -131,8 +163,13 @@ void launch_sf_bfs(const Dev &d, int l0, int l1, hipStream_t s);
 void launch_orient_bfs(const Dev &d, int levels, hipStream_t s);
 void launch_superforest_lr(const Dev &d, int lr_rounds, hipStream_t s);
 void launch_reverse(const Dev &d, hipStream_t s);
-void launch_labels(const Dev &d, hipStream_t s);
+// label kernels of the ops present (delete labels run first)
+void launch_labels(const Dev &d, bool ins, bool del, hipStream_t s);
 void launch_cleanup(const Dev &d, hipStream_t s);
+
+// digests of parent and label (out: two device words)
+void launch_digest(int32_t n, const int32_t *parent, const int32_t *label, unsigned long long *out,
+                   hipStream_t s);
 
 // create-time helpers
 void launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t s);
@@ -150,6 +187,13 @@ void launch_scan_u32(const uint32_t *in, uint32_t *out, unsigned long long *tota
 size_t scan_tmp_bytes(int64_t n);
 void launch_upper_fill(int32_t n, const int64_t *row_ptr, const int32_t *col,
                        const uint32_t *bptr, int32_t *bcol, hipStream_t s);
+// lower half: counts (row length minus upper count), then the row prefixes
+void launch_lower_counts(int32_t n, const int64_t *row_ptr, const uint32_t *bptr, uint32_t *lcnt,
+                         hipStream_t s);
+void launch_lower_fill(int32_t n, const int64_t *row_ptr, const int32_t *col,
+                       const uint32_t *lptr, int32_t *lcol, hipStream_t s);
+void launch_twin(int32_t n, const uint32_t *bptr, const int32_t *bcol, const uint32_t *lptr,
+                 const int32_t *lcol, uint32_t *twin, int32_t *status, hipStream_t s);
 // non-empty row index: flags -> (scan) -> zrow/zptr, then tile_k
 void launch_nonempty_flags(int32_t n, const uint32_t *bptr, uint32_t *flag, hipStream_t s);
 void launch_nonempty_fill(int32_t n, const uint32_t *bptr, const uint32_t *zpos, int32_t *zrow,

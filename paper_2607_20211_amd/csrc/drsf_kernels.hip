@@ -105,6 +105,66 @@ __device__ int block_excl_scan(int x, int *total) {
     return before + inc - x;
 }
 
+// 64-bit exclusive scan over the block; also returns the total.  Every
+// thread of the block must call it.
+__device__ unsigned long long block_excl_scan64(unsigned long long x, unsigned long long *total) {
+    __shared__ unsigned long long wsum[BLOCK / WAVE];
+    const int lane = lane_id(), wid = threadIdx.x / WAVE;
+    unsigned long long inc = x;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const unsigned long long y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (lane == WAVE - 1) wsum[wid] = inc;
+    __syncthreads();
+    unsigned long long before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < BLOCK / WAVE; w++) {
+        before += w < wid ? wsum[w] : 0;
+        tot += wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return before + inc - x;
+}
+
+// Sum over the block (one barrier pair).  Every thread must call it.
+__device__ unsigned long long block_sum64(unsigned long long x) {
+    __shared__ unsigned long long wsum[BLOCK / WAVE];
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    if (lane_id() == 0) wsum[threadIdx.x / WAVE] = x;
+    __syncthreads();
+    unsigned long long t = 0;
+#pragma unroll
+    for (int w = 0; w < BLOCK / WAVE; w++) t += wsum[w];
+    __syncthreads();
+    return t;
+}
+
+// (slots, orphans) packed into one word so that one sum or scan carries both:
+// slots below 2^44, orphans in the bits above
+__device__ __forceinline__ unsigned long long opack(unsigned long long vol, unsigned long long c) {
+    return (c << 44) | vol;
+}
+__device__ __forceinline__ unsigned long long ovol(unsigned long long p) { return p & ((1ull << 44) - 1); }
+__device__ __forceinline__ unsigned long long ocnt(unsigned long long p) { return p >> 44; }
+
+// Block-aggregated append: each thread reserves k consecutive slots of
+// *counter and gets the first; one atomic per workgroup (a counter shared by
+// the whole grid is a hot address).  Every thread of the block must call it.
+__device__ int64_t block_append(int k, unsigned long long *counter) {
+    __shared__ unsigned long long s_base;
+    int total;
+    const int off = block_excl_scan(k, &total);
+    if (threadIdx.x == 0 && total) s_base = atomicAdd(counter, (unsigned long long)total);
+    __syncthreads();
+    const int64_t r = (int64_t)s_base + off;
+    __syncthreads();  // s_base is reused by the next call
+    return r;
+}
+
 __device__ __forceinline__ int edge_op(const Dev &d, int64_t i) {
     return d.ctl->op == 2 ? (int)d.bop[i] : d.ctl->op;
 }
@@ -203,6 +263,8 @@ __global__ __launch_bounds__(BLOCK) void k_prepare(Dev d) {
             const int64_t loc = d.bloc[i];
             if (loc >= 0) {
                 d.bcol[loc] = d.bcol[loc] | TOMB;
+                const uint32_t l2 = d.twin[loc];
+                d.lcol[l2] = d.lcol[l2] | TOMB;
             } else {
                 const int64_t slot = -loc - 1;
                 d.dkey[d.dhpos[slot]] = KEY_DEAD;
@@ -216,7 +278,7 @@ __global__ __launch_bounds__(BLOCK) void k_prepare(Dev d) {
                 d.owner[d.label[c]] = (int32_t)(2 * i + 1);
             }
         }
-        const int64_t pos = wave_append(op == 0, &d.cnt[C_NDELTA]);
+        const int64_t pos = block_append(op == 0 ? 1 : 0, &d.cnt[C_NDELTA]);
         if (op == 0) {
             const uint64_t k = d.bkey[i];
             if (pos >= d.dcap) {
@@ -256,8 +318,8 @@ __global__ __launch_bounds__(BLOCK) void k_register(Dev d) {
         }
         const bool ga = a != NONE && d.owner[a] == (int32_t)(2 * i);
         const bool gb = c2 != NONE && d.owner[c2] == (int32_t)(2 * i + 1);
-        const int64_t ia = wave_append(ga, &d.cnt[C_NP]);
-        const int64_t ib = wave_append(gb, &d.cnt[C_NP]);
+        const int64_t ia = block_append((ga ? 1 : 0) + (gb ? 1 : 0), &d.cnt[C_NP]);
+        const int64_t ib = ia + (ga ? 1 : 0);
         if (ga) init_piece(d, ia, a, false);
         if (gb) init_piece(d, ib, c2, del);
     }
@@ -336,9 +398,38 @@ __global__ __launch_bounds__(BLOCK) void k_rep_chase(Dev d) {
         const uint64_t word = __ballot(orphan);
         if (lane_id() == 0 && v < d.n) d.obits[v >> 6] = word;
         int32_t t = NONE;
+        uint32_t us = 0, ls = 0;
+        int32_t du = 0, dl = 0;
         if (orphan) {
             t = d.tidx[x];
             if (t < 0) atomicOr(d.status, ST_WALK_BOUND);
+            us = d.bptr[v];
+            ls = d.lptr[v];
+            du = (int32_t)(d.bptr[v + 1] - us);
+            dl = (int32_t)(d.lptr[v + 1] - ls);
+        }
+        // the block's orphans with their adjacency runs (plus padding),
+        // compacted at the block's start of the staging array for the orphan
+        // scan, and the block's totals
+        unsigned long long tot;
+        const unsigned long long off =
+            block_excl_scan64(orphan ? opack((unsigned long long)(du + dl + OR_PAD), 1) : 0, &tot);
+        if (orphan) {
+            OrphEnt o;
+            o.pre = (int64_t)ovol(off);
+            o.ustart = us;
+            o.lstart = ls;
+            o.v = (int32_t)v;
+            o.du = du;
+            o.dl = dl;
+            o.pu = t;
+            o.ru = x;
+            o.pad = 0;
+            d.ostage[blk * BLOCK + (int64_t)ocnt(off)] = o;
+        }
+        if (threadIdx.x == 0) {
+            d.bvol[blk] = (int64_t)ovol(tot);
+            d.bcnt[blk] = (int32_t)ocnt(tot);
         }
         // smallest vertex of each orphan piece; consecutive ids often share a piece
         const bool act = orphan && t >= 0;
@@ -362,84 +453,222 @@ __global__ __launch_bounds__(BLOCK) void k_rep_chase(Dev d) {
 // edge is a cross edge iff rep differs at its ends.  An edge whose ends both
 // stay in their old root's piece has equal reps (its ends share a component
 // of G, hence a tree of F, hence that tree's root piece), so the rep gathers
-// are only made when the orphan bitmap flags an end.  One workgroup streams
-// TILE consecutive stored edges (EPT per thread, 16-byte non-temporal loads);
-// rows are walked over the non-empty-row index, so a thread advances at most
-// EPT rows; the bitmap and rep gathers of a thread's edges are issued
-// together.  Cross edges go to the tile's own region of x0.
+// are only made when the orphan bitmap flags an end.
+//
+// One workgroup streams TILE consecutive stored edges.  Each wave reads its
+// quarter of the tile with 16-byte non-temporal loads, every instruction
+// covering 1 KB of contiguous columns.  The row of each edge comes from a
+// map built in LDS: every row starting inside the tile marks its first
+// position with its local index, and a max-scan over the tile fills the
+// rest; the row vertices sit in LDS beside it.  So the only global gathers
+// are the orphan bits of both ends (all of a thread's issued together) and
+// rep for the flagged edges.  Cross edges go to the
+// tile's own region of x0.
 __global__ __launch_bounds__(BLOCK) void k_sweep_base(Dev d) {
-    if (*d.status || !d.ctl->has_del) return;
-    const int64_t tile = list_block(d.tlist, d.ctl->ntl, blockIdx.x, d.ntiles);
-    if (tile < 0) return;
+    if (*d.status || !d.ctl->has_del || d.cnt[C_OMODE]) return;
     typedef int v4i __attribute__((ext_vector_type(4)));
-    const int64_t e0 = tile * TILE + (int64_t)threadIdx.x * EPT;
-    uint32_t mask = 0;
-    int32_t c[EPT];
-    int32_t urow[EPT];
-    if (e0 < d.eb) {
-        // largest k with zptr[k] <= e0, among the tile's rows
-        int32_t a = d.tile_k[tile], bk = d.tile_k[tile + 1];
-        while (a < bk) {
-            const int32_t mid = a + ((bk - a + 1) >> 1);
-            if ((int64_t)d.zptr[mid] <= e0) a = mid; else bk = mid - 1;
-        }
-        if (e0 + EPT <= d.eb) {
-            const v4i *p = reinterpret_cast<const v4i *>(d.bcol + e0);
+    typedef short v4s __attribute__((ext_vector_type(4)));
+    __shared__ v4i s_rowv[TILE / 8];      // int16 local row index per edge
+    __shared__ int32_t s_u[TILE + 1];     // row vertex per local row
+    __shared__ int16_t s_wmax[BLOCK / WAVE];
+    int16_t *s_row = reinterpret_cast<int16_t *>(s_rowv);
+    for (int64_t jt = blockIdx.x;; jt += gridDim.x) {
+        const int64_t tile = list_block(d.tlist, d.ctl->ntl, jt, d.ntiles);
+        if (tile < 0) break;
+        __syncthreads();  // the previous tile is finished with the LDS
+        const int64_t base = tile * TILE;
+        const int64_t cnt = d.eb - base < TILE ? d.eb - base : TILE;
+        const int lane = lane_id(), wid = threadIdx.x / WAVE;
+        // thread's edges: local positions pbase + q * 256 + j, q, j < 4
+        const int pbase = wid * (TILE / 4) + lane * 4;
+        // the store is padded with deleted entries to whole tiles
+        int32_t c[EPT];
+        {
+            const v4i *p = reinterpret_cast<const v4i *>(d.bcol + base + pbase);
 #pragma unroll
-            for (int q = 0; q < EPT / 4; q++) {
-                const v4i t = __builtin_nontemporal_load(p + q);
+            for (int q = 0; q < 4; q++) {
+                const v4i t = __builtin_nontemporal_load(p + q * 64);
                 c[4 * q] = t.x; c[4 * q + 1] = t.y; c[4 * q + 2] = t.z; c[4 * q + 3] = t.w;
             }
-        } else {
-#pragma unroll
-            for (int j = 0; j < EPT; j++) c[j] = (e0 + j < d.eb) ? d.bcol[e0 + j] : TOMB;
         }
-        // phase 1: the row of every edge
-        int32_t k = a;
-        int64_t rend = d.zptr[k + 1];
-        int32_t u = d.zrow[k];
-        bool ou = obit(d.obits, u);
-        uint32_t umask = 0;
+        // row map: mark row starts
+        const v4i zero = {0, 0, 0, 0};
+        s_rowv[threadIdx.x] = zero;
+        s_rowv[threadIdx.x + BLOCK] = zero;
+        __syncthreads();
+        // rows in chunks of 4 * BLOCK: all loads of a chunk are issued before use
+        const int32_t ka = d.tile_k[tile], kb = d.tile_k[tile + 1];
+        for (int32_t k0 = ka; k0 <= kb; k0 += 4 * BLOCK) {
+            int32_t zp[4], zr[4];
 #pragma unroll
-        for (int j = 0; j < EPT; j++) {
-            const int64_t e = e0 + j;
-            if (e < d.eb) {
-                while (e >= rend) {
-                    k++;
-                    rend = d.zptr[k + 1];
-                    u = d.zrow[k];
-                    ou = obit(d.obits, u);
+            for (int i = 0; i < 4; i++) {
+                int32_t k = k0 + i * BLOCK + (int32_t)threadIdx.x;
+                k = k < kb ? k : kb;
+                zp[i] = (int32_t)d.zptr[k];
+                zr[i] = d.zrow[k];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int32_t k = k0 + i * BLOCK + (int32_t)threadIdx.x;
+                if (k <= kb) {
+                    const int64_t p = (int64_t)(uint32_t)zp[i] - base;
+                    if (p > 0 && p < cnt) s_row[p] = (int16_t)(k - ka);
+                    s_u[k - ka] = zr[i];
                 }
             }
-            urow[j] = u;
-            umask |= (ou ? 1u : 0u) << j;
         }
-        // phase 2: independent bitmap loads for all columns
-        uint32_t cand = 0;
+        __syncthreads();
+        // inclusive max-scan of the marks: thread t owns positions [16 t, 16 t + 16)
+        {
+            v4s m[4];
+            const v4s *src = reinterpret_cast<const v4s *>(s_row + 16 * threadIdx.x);
+            int16_t run = 0;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                m[q] = src[q];
+                run = m[q].x > run ? m[q].x : run; m[q].x = run;
+                run = m[q].y > run ? m[q].y : run; m[q].y = run;
+                run = m[q].z > run ? m[q].z : run; m[q].z = run;
+                run = m[q].w > run ? m[q].w : run; m[q].w = run;
+            }
+            int32_t inc = run;
+#pragma unroll
+            for (int o = 1; o < WAVE; o <<= 1) {
+                const int32_t y = __shfl_up(inc, o);
+                if (lane >= o && y > inc) inc = y;
+            }
+            if (lane == WAVE - 1) s_wmax[wid] = (int16_t)inc;
+            int32_t before = __shfl_up(inc, 1);
+            if (lane == 0) before = 0;
+            __syncthreads();
+#pragma unroll
+            for (int w = 0; w < BLOCK / WAVE; w++)
+                if (w < wid && s_wmax[w] > before) before = s_wmax[w];
+            const int16_t pre = (int16_t)before;
+            v4s *dst = reinterpret_cast<v4s *>(s_row + 16 * threadIdx.x);
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                v4s x = m[q];
+                x.x = x.x > pre ? x.x : pre; x.y = x.y > pre ? x.y : pre;
+                x.z = x.z > pre ? x.z : pre; x.w = x.w > pre ? x.w : pre;
+                dst[q] = x;
+            }
+        }
+        __syncthreads();
+        // row vertex of each of the thread's edges
+        int32_t urow[EPT];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const v4s r = *reinterpret_cast<const v4s *>(s_row + pbase + q * 256);
+            urow[4 * q] = s_u[r.x]; urow[4 * q + 1] = s_u[r.y];
+            urow[4 * q + 2] = s_u[r.z]; urow[4 * q + 3] = s_u[r.w];
+        }
+        // every gather of a thread is issued before any result is used: the
+        // bitmap words of both ends unconditionally (a deleted entry's masked id
+        // is still a vertex; edges of one row share the row's word), then rep
+        // only for flagged edges, the others pointed at rep[0]
+        uint64_t bu[EPT], bv[EPT];
 #pragma unroll
         for (int j = 0; j < EPT; j++) {
-            const int32_t v = c[j];
-            if (v >= 0 && ((umask >> j & 1) || obit(d.obits, v))) cand |= 1u << j;
+            bu[j] = d.obits[urow[j] >> 6];
+            bv[j] = d.obits[(c[j] & COLMASK) >> 6];
         }
-        // phase 3: rep gathers only for flagged edges
+        uint32_t cand = 0;
 #pragma unroll
         for (int j = 0; j < EPT; j++)
-            if ((cand >> j & 1) && d.rep[urow[j]] != d.rep[c[j]]) mask |= 1u << j;
+            if (c[j] >= 0 && (((bu[j] >> (urow[j] & 63)) | (bv[j] >> (c[j] & 63))) & 1)) cand |= 1u << j;
+        int32_t ra[EPT], rb[EPT];
+        uint32_t mask = 0;
+        if (__ballot(cand != 0)) {
+#pragma unroll
+            for (int j = 0; j < EPT; j++) {
+                const bool k = cand >> j & 1;
+                ra[j] = d.rep[k ? urow[j] : 0];
+                rb[j] = d.rep[k ? c[j] : 0];
+            }
+#pragma unroll
+            for (int j = 0; j < EPT; j++)
+                if ((cand >> j & 1) && ra[j] != rb[j]) mask |= 1u << j;
+        }
+        int total;
+        const int off = block_excl_scan(__popc(mask), &total);
+        if (threadIdx.x == 0) d.rcnt[tile] = (unsigned long long)total;
+        if (mask) {
+            Cross *out = d.x0 + tile * TILE + off;
+            int w = 0;
+#pragma unroll
+            for (int j = 0; j < EPT; j++) {
+                if (mask >> j & 1) {
+                    Cross x;
+                    x.key = ((uint64_t)(uint32_t)urow[j] << 32) | (uint32_t)c[j];
+                    x.pa = d.tidx[ra[j]];
+                    x.pb = d.tidx[rb[j]];
+                    if (x.pa < 0 || x.pb < 0) atomicOr(d.status, ST_WALK_BOUND);
+                    out[w++] = x;
+                }
+            }
+        }
+    }
+}
+
+// The same test over the list of inserted edges: workgroup t takes list
+// entries [t * TILE, (t + 1) * TILE) and writes region ntiles + t.  Lane
+// layout and gathers as in k_sweep_base.
+__global__ __launch_bounds__(BLOCK) void k_sweep_delta(Dev d) {
+    if (*d.status || !d.ctl->has_del) return;
+    const int64_t nd = (int64_t)d.cnt[C_NDELTA];
+    const int64_t t = blockIdx.x;
+    if (t * TILE >= nd) return;
+    const int lane = lane_id(), wid = threadIdx.x / WAVE;
+    const int64_t i0 = t * TILE + wid * (TILE / 4) + lane * 4;  // + q * 256 + j
+    uint64_t k[EPT];
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int64_t i = i0 + q * 256 + j;
+            k[4 * q + j] = i < nd ? d.dkey[i] : KEY_DEAD;
+        }
+    uint64_t wu[EPT], wv[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; j++) {
+        const bool live = k[j] != KEY_DEAD;
+        wu[j] = d.obits[live ? key_lo(k[j]) >> 6 : 0];
+        wv[j] = d.obits[live ? key_hi(k[j]) >> 6 : 0];
+    }
+    uint32_t cand = 0;
+#pragma unroll
+    for (int j = 0; j < EPT; j++)
+        if (k[j] != KEY_DEAD &&
+            (((wu[j] >> (key_lo(k[j]) & 63)) | (wv[j] >> (key_hi(k[j]) & 63))) & 1))
+            cand |= 1u << j;
+    int32_t ra[EPT], rb[EPT];
+    uint32_t mask = 0;
+    if (__ballot(cand != 0)) {
+#pragma unroll
+        for (int j = 0; j < EPT; j++) {
+            const bool c = cand >> j & 1;
+            ra[j] = d.rep[c ? key_lo(k[j]) : 0];
+            rb[j] = d.rep[c ? key_hi(k[j]) : 0];
+        }
+#pragma unroll
+        for (int j = 0; j < EPT; j++)
+            if ((cand >> j & 1) && ra[j] != rb[j]) mask |= 1u << j;
     }
     int total;
     const int off = block_excl_scan(__popc(mask), &total);
-    if (threadIdx.x == 0) d.rcnt[tile] = (unsigned long long)total;
+    const int64_t reg = d.ntiles + t;
+    if (threadIdx.x == 0) d.rcnt[reg] = (unsigned long long)total;
     if (mask) {
-        Cross *out = d.x0 + tile * TILE + off;
+        Cross *out = d.x0 + reg * TILE + off;
         int w = 0;
 #pragma unroll
         for (int j = 0; j < EPT; j++) {
             if (mask >> j & 1) {
-                const int32_t uu = urow[j], v = c[j];
                 Cross x;
-                x.key = ((uint64_t)(uint32_t)uu << 32) | (uint32_t)v;
-                x.pa = d.tidx[d.rep[uu]];
-                x.pb = d.tidx[d.rep[v]];
+                x.key = k[j];
+                x.pa = d.tidx[ra[j]];
+                x.pb = d.tidx[rb[j]];
                 if (x.pa < 0 || x.pb < 0) atomicOr(d.status, ST_WALK_BOUND);
                 out[w++] = x;
             }
@@ -447,42 +676,236 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_base(Dev d) {
     }
 }
 
-// The same test over the list of inserted edges: workgroup t takes list
-// entries [t * TILE, (t + 1) * TILE) and writes region ntiles + t.
-__global__ __launch_bounds__(BLOCK) void k_sweep_delta(Dev d) {
+// ------------------ f4: key-edge scan restricted to the orphans (delete)
+
+// Every cross edge of a delete has an orphan end (ends that both kept their
+// old root have equal reps), so scanning the whole adjacency of the orphan
+// vertices finds every cross edge of the base store; when the orphans hold
+// few slots this replaces the sweep of the whole store.  Root finding left,
+// per vertex block, the block's orphans and their slots.  Prefixes over the
+// blocks are taken in two levels: within groups of BLOCK blocks here, then
+// over the groups in k_orph_total.
+__global__ __launch_bounds__(BLOCK) void k_orph_plan(Dev d) {
     if (*d.status || !d.ctl->has_del) return;
-    const int64_t nd = (int64_t)d.cnt[C_NDELTA];
-    const int64_t t = blockIdx.x;
-    if (t * TILE >= nd) return;
-    const int64_t i0 = t * TILE + (int64_t)threadIdx.x * EPT;
-    uint32_t mask = 0;
-#pragma unroll
-    for (int j = 0; j < EPT; j++) {
-        const int64_t i = i0 + j;
-        if (i < nd) {
-            const uint64_t k = d.dkey[i];
-            if (k != KEY_DEAD) {
-                const int32_t u = key_lo(k), v = key_hi(k);
-                if ((obit(d.obits, u) || obit(d.obits, v)) && d.rep[u] != d.rep[v]) mask |= 1u << j;
-            }
-        }
+    const int64_t b = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const unsigned long long x =
+        b < d.nvb ? opack((unsigned long long)d.bvol[b], (unsigned long long)d.bcnt[b]) : 0;
+    unsigned long long tot;
+    const unsigned long long pre = block_excl_scan64(x, &tot);
+    if (b < d.nvb) {
+        d.bpre[b] = (int64_t)ovol(pre);
+        d.opre[b] = (int32_t)ocnt(pre);
     }
-    int total;
-    const int off = block_excl_scan(__popc(mask), &total);
-    const int64_t reg = d.ntiles + t;
-    if (threadIdx.x == 0) d.rcnt[reg] = (unsigned long long)total;
-    Cross *out = d.x0 + reg * TILE + off;
-    int w = 0;
+    if (threadIdx.x == 0) d.gsum[blockIdx.x] = tot;
+}
+
+// Prefix over the groups, the totals and the choice of scan.
+__global__ __launch_bounds__(BLOCK) void k_orph_total(Dev d) {
+    if (*d.status || !d.ctl->has_del) return;
+    const int64_t ng = (d.nvb + BLOCK - 1) / BLOCK;
+    const int64_t per = (ng + BLOCK - 1) / BLOCK;
+    const int64_t g0 = (int64_t)threadIdx.x * per;
+    const int64_t g1 = g0 + per < ng ? g0 + per : ng;
+    unsigned long long sum = 0;
+    for (int64_t g = g0; g < g1; g++) sum += d.gsum[g];
+    unsigned long long tot;
+    unsigned long long pre = block_excl_scan64(sum, &tot);
+    for (int64_t g = g0; g < g1; g++) {
+        const unsigned long long x = d.gsum[g];
+        d.gpre[g] = pre;
+        pre += x;
+    }
+    if (threadIdx.x == 0) {
+        const int64_t V = (int64_t)ovol(tot);
+        d.cnt[C_OVOL] = (unsigned long long)V;
+        d.cnt[C_NORPH] = ocnt(tot);
+        d.cnt[C_OMODE] = (d.ctl->smode != 1 && V * OR_MAX_FRAC <= d.eb) ? 1ull : 0ull;
+    }
+}
+
+// Compacted list of all orphans in vertex order (copied from the blocks'
+// staging with global prefixes), and for each range of OR_W slots the list
+// index of the orphan holding its first slot.
+__global__ __launch_bounds__(BLOCK) void k_orph_fill(Dev d) {
+    if (*d.status || !d.ctl->has_del || !d.cnt[C_OMODE]) return;
+    for (int64_t j = blockIdx.x;; j += gridDim.x) {
+        const int64_t blk = list_block(d.vlist, d.ctl->nvl, j, d.nvb);
+        if (blk < 0) break;
+        const int32_t nc = d.bcnt[blk];
+        if ((int32_t)threadIdx.x >= nc) continue;
+        const unsigned long long gp = d.gpre[blk / BLOCK];
+        OrphEnt o = d.ostage[blk * BLOCK + threadIdx.x];
+        const int64_t idx = (int64_t)ocnt(gp) + d.opre[blk] + threadIdx.x;
+        o.pre += (int64_t)ovol(gp) + d.bpre[blk];
+        d.olist[idx] = o;
+        const int64_t end = o.pre + o.du + o.dl + OR_PAD;
+        for (int64_t w = (o.pre + OR_W - 1) / OR_W; w * OR_W < end; w++) d.rstart[w] = (int32_t)idx;
+    }
+}
+
+// One workgroup per range of OR_W consecutive slots.  The orphans covering
+// the range are staged in LDS; each thread takes OR_K consecutive slots
+// (one binary search, then a walk), loads their columns from the upper or
+// lower run and tests rep at both ends.  A cross edge (u, v) takes part in
+// the first hooking round's selection for u's piece (an orphan piece, which
+// never holds an old root), and within the thread's run of slots only the
+// lowest key per pair of pieces is kept for the later rounds: a parallel
+// edge with a higher key closes a cycle on which it is the largest, so the
+// lowest-key forest never contains it.  Edges between two orphan pieces are
+// seen from both ends; they are counted once (from the smaller end).
+__global__ __launch_bounds__(BLOCK) void k_orph_scan(Dev d) {
+    if (*d.status || !d.ctl->has_del || !d.cnt[C_OMODE]) return;
+    const int64_t V = (int64_t)d.cnt[C_OVOL];
+    const int64_t no = (int64_t)d.cnt[C_NORPH];
+    const int64_t nr = (V + OR_W - 1) / OR_W;
+    __shared__ OrphEnt s_o[BLOCK];
+    __shared__ int64_t s_pre[BLOCK];
+    __shared__ unsigned long long s_min[BLOCK];  // lowest cross key per staged orphan
+    for (int64_t w = blockIdx.x; w < nr; w += gridDim.x) {
+        const int64_t S1 = (w + 1) * OR_W < V ? (w + 1) * OR_W : V;
+        int64_t pos = w * OR_W;
+        int64_t i0 = d.rstart[w];
+        int64_t emitted = 0;
+        int ncross = 0;
+        while (pos < S1) {  // windows of BLOCK orphans; uniform over the block
+            __syncthreads();  // the LDS is free
+            const int64_t ii = i0 + threadIdx.x;
+            if (ii < no) {
+                s_o[threadIdx.x] = d.olist[ii];
+                s_pre[threadIdx.x] = s_o[threadIdx.x].pre;
+            }
+            s_min[threadIdx.x] = KEY_INF;
+            __syncthreads();
+            const int wn = no - i0 < BLOCK ? (int)(no - i0) : BLOCK;
+            int64_t we = S1;
+            if (wn > 0) {
+                const OrphEnt &last = s_o[wn - 1];
+                const int64_t e = last.pre + last.du + last.dl + OR_PAD;
+                we = e < S1 ? e : S1;
+            }
+            if (wn <= 0 || we <= pos || s_pre[0] > pos) {  // inconsistent plan
+                if (threadIdx.x == 0) atomicOr(d.status, ST_WALK_BOUND);
+                break;
+            }
+            // this thread's slots [s0, s0 + cnt)
+            const int64_t s0 = pos + (int64_t)threadIdx.x * OR_K;
+            const int cnt = s0 >= we ? 0 : (we - s0 < OR_K ? (int)(we - s0) : OR_K);
+            int a = 0;
+            if (cnt > 0) {
+                int b = wn - 1;
+                while (a < b) {
+                    const int mid = (a + b + 1) >> 1;
+                    if (s_pre[mid] <= s0) a = mid; else b = mid - 1;
+                }
+            }
+            int64_t e = cnt > 0 ? s0 - s_pre[a] : 0;
+            int32_t col[OR_K], oi[OR_K];
 #pragma unroll
-    for (int j = 0; j < EPT; j++) {
-        if (mask >> j & 1) {
-            const uint64_t k = d.dkey[i0 + j];
-            Cross x;
-            x.key = k;
-            x.pa = d.tidx[d.rep[key_lo(k)]];
-            x.pb = d.tidx[d.rep[key_hi(k)]];
-            if (x.pa < 0 || x.pb < 0) atomicOr(d.status, ST_WALK_BOUND);
-            out[w++] = x;
+            for (int k = 0; k < OR_K; k++) {
+                const int32_t *src = d.bcol;
+                bool real = false;
+                if (k < cnt) {
+                    while (e >= (int64_t)s_o[a].du + s_o[a].dl + OR_PAD && a < wn - 1) {
+                        e -= (int64_t)s_o[a].du + s_o[a].dl + OR_PAD;
+                        a++;
+                    }
+                    const OrphEnt &o = s_o[a];
+                    real = e < (int64_t)o.du + o.dl;  // else a padding slot
+                    if (real) src = e < o.du ? d.bcol + o.ustart + e : d.lcol + o.lstart + (e - o.du);
+                    e++;
+                }
+                oi[k] = a;
+                col[k] = *src;
+                if (!real) col[k] = TOMB;
+            }
+            int32_t rv[OR_K];
+#pragma unroll
+            for (int k = 0; k < OR_K; k++) rv[k] = d.rep[col[k] & COLMASK];
+            uint32_t cross = 0;
+#pragma unroll
+            for (int k = 0; k < OR_K; k++)
+                if (col[k] >= 0 && rv[k] != s_o[oi[k]].ru) cross |= 1u << k;
+            int32_t pv[OR_K];
+            uint64_t vw[OR_K];
+#pragma unroll
+            for (int k = 0; k < OR_K; k++) {
+                const bool x = cross >> k & 1;
+                pv[k] = d.tidx[x ? rv[k] : 0];
+                vw[k] = d.obits[x ? (col[k] >> 6) : 0];
+            }
+            // count, and the runs of equal piece pairs
+            int runs = 0;
+            {
+                uint64_t cur = ~0ull;
+#pragma unroll
+                for (int k = 0; k < OR_K; k++) {
+                    if (!(cross >> k & 1)) continue;
+                    const OrphEnt &o = s_o[oi[k]];
+                    if (pv[k] < 0 || o.pu < 0) atomicOr(d.status, ST_WALK_BOUND);
+                    if (!((vw[k] >> (col[k] & 63)) & 1) || o.v < col[k]) ncross++;
+                    const uint64_t pair = ((uint64_t)(uint32_t)o.pu << 32) | (uint32_t)pv[k];
+                    if (pair != cur) { runs++; cur = pair; }
+                }
+            }
+            int rtot;
+            const int roff = block_excl_scan(runs, &rtot);
+            // lowest key of each run: output, and the run's orphan's minimum
+            // in LDS (several threads' runs of one orphan meet there; one
+            // global atomic per orphan and window follows)
+            {
+                Cross *out = d.x0 + w * TILE + emitted + roff;
+                int r = 0;
+                uint64_t cur = ~0ull, mk = 0;
+                int32_t cpu = 0, cpv = 0, ca = 0;
+#pragma unroll
+                for (int k = 0; k <= OR_K; k++) {
+                    bool flush = k == OR_K;
+                    uint64_t pair = 0, key = 0;
+                    if (!flush && (cross >> k & 1)) {
+                        const OrphEnt &o = s_o[oi[k]];
+                        pair = ((uint64_t)(uint32_t)o.pu << 32) | (uint32_t)pv[k];
+                        key = mkkey((uint32_t)o.v, (uint32_t)col[k]);
+                        if (pair == cur) {
+                            mk = key < mk ? key : mk;
+                            continue;
+                        }
+                        flush = true;
+                    } else if (!flush) {
+                        continue;
+                    }
+                    if (cur != ~0ull) {
+                        Cross xo;
+                        xo.key = mk;
+                        xo.pa = cpu;
+                        xo.pb = cpv;
+                        out[r++] = xo;
+                        if (s_min[ca] > mk) atomicMin(&s_min[ca], (unsigned long long)mk);
+                    }
+                    if (k < OR_K) {
+                        cur = pair;
+                        mk = key;
+                        cpu = (int32_t)(pair >> 32);
+                        cpv = (int32_t)(uint32_t)pair;
+                        ca = oi[k];
+                    }
+                }
+            }
+            __syncthreads();
+            if (threadIdx.x < wn) {
+                const unsigned long long m = s_min[threadIdx.x];
+                const int32_t pu = s_o[threadIdx.x].pu;
+                if (m != KEY_INF && pu >= 0 && d.best[pu] > m)
+                    atomicMin((unsigned long long *)&d.best[pu], m);
+            }
+            emitted += rtot;
+            pos = we;
+            i0 += wn;
+        }
+        int ct;
+        block_excl_scan(ncross, &ct);
+        if (threadIdx.x == 0) {
+            d.rcnt[w] = (unsigned long long)emitted;
+            d.xcnt[w] = (unsigned long long)ct;
         }
     }
 }
@@ -511,7 +934,11 @@ __global__ __launch_bounds__(BLOCK) void k_bor_round0(Dev d) {
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < np; p += stride)
         d.hook[p] = NONE;
-    const int64_t rlo = d.ctl->rlo, rhi = d.ctl->rhi;
+    // regions below ntiles hold the orphan scan's output when it ran: those
+    // edges took part in this round's selection already
+    const bool om = d.cnt[C_OMODE] != 0;
+    const int64_t rhi = d.ctl->rhi;
+    const int64_t rlo = om ? (d.ctl->rlo > d.ntiles ? d.ctl->rlo : d.ntiles) : d.ctl->rlo;
     for (int64_t t = rlo + blockIdx.x; t < rhi; t += gridDim.x) {
         const int64_t cntr = (int64_t)d.rcnt[t];
         const Cross *in = d.x0 + t * TILE;
@@ -528,6 +955,10 @@ __global__ __launch_bounds__(BLOCK) void k_bor_round0(Dev d) {
     if (blockIdx.x == 0) {
         unsigned long long s = 0;
         for (int64_t r = rlo + threadIdx.x; r < rhi; r += BLOCK) s += d.rcnt[r];
+        if (om) {
+            const int64_t nr = ((int64_t)d.cnt[C_OVOL] + OR_W - 1) / OR_W;
+            for (int64_t r = threadIdx.x; r < nr; r += BLOCK) s += d.xcnt[r];
+        }
         for (int o = WAVE / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
         if (lane_id() == 0 && s) atomicAdd(&d.cnt[C_NCROSS], s);
     }
@@ -631,7 +1062,7 @@ __global__ __launch_bounds__(BLOCK) void k_bor_hook(Dev d, int r) {
                 }
             }
         }
-        const int64_t slot = wave_append(rec, &d.cnt[C_NER]);
+        const int64_t slot = block_append(rec ? 1 : 0, &d.cnt[C_NER]);
         if (rec) d.er[slot] = er;
     }
 }
@@ -745,8 +1176,8 @@ __global__ __launch_bounds__(BLOCK) void k_orient_bfs(Dev d, int levels) {
                 }
             }
         }
-        const int64_t s1 = wave_append(e1, &d.cnt[C_NR]);
-        const int64_t s2 = wave_append(e2, &d.cnt[C_NR]);
+        const int64_t s1 = block_append((e1 ? 1 : 0) + (e2 ? 1 : 0), &d.cnt[C_NR]);
+        const int64_t s2 = s1 + (e1 ? 1 : 0);
         if (e1) { if (s1 < d.pathcap) d.paths[s1] = q1; else atomicOr(d.status, ST_CAPACITY); }
         if (e2) { if (s2 < d.pathcap) d.paths[s2] = q2; else atomicOr(d.status, ST_CAPACITY); }
     }
@@ -866,7 +1297,7 @@ __global__ __launch_bounds__(BLOCK) void k_orient_lr(Dev d, int lr_rounds) {
                 }
             }
         }
-        const int64_t slot = wave_append(emit, &d.cnt[C_NR]);
+        const int64_t slot = block_append(emit ? 1 : 0, &d.cnt[C_NR]);
         if (emit) {
             if (slot < d.pathcap) d.paths[slot] = q;
             else atomicOr(d.status, ST_CAPACITY);
@@ -912,6 +1343,27 @@ __global__ __launch_bounds__(BLOCK) void k_reverse_all(Dev d) {
 // rep == label for the next update.
 __global__ __launch_bounds__(BLOCK) void k_label_delete(Dev d) {
     if (*d.status || !d.cnt[C_ORIENTED] || !d.ctl->has_del) return;
+    if (d.cnt[C_OMODE]) {
+        // the orphan list holds every orphan: relabel them, clear their
+        // bitmap words and their blocks' figures (idempotent stores)
+        const int64_t no = (int64_t)d.cnt[C_NORPH];
+        const int64_t stride = (int64_t)gridDim.x * BLOCK;
+        for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < no; i += stride) {
+            const int32_t v = d.olist[i].v;
+            const int32_t p = d.tidx[d.rep[v]];
+            if (p >= 0) {
+                const int32_t l = d.newlab[d.comp[p]];
+                d.label[v] = l;
+                d.rep[v] = l;
+            } else {
+                atomicOr(d.status, ST_WALK_BOUND);
+            }
+            d.obits[v >> 6] = 0;
+            d.bvol[v / BLOCK] = 0;
+            d.bcnt[v / BLOCK] = 0;
+        }
+        return;
+    }
     const int64_t nb = (d.n + BLOCK - 1) / BLOCK;
     for (int64_t j = blockIdx.x;; j += gridDim.x) {
         const int64_t blk = list_block(d.vlist, d.ctl->nvl, j, nb);
@@ -923,6 +1375,10 @@ __global__ __launch_bounds__(BLOCK) void k_label_delete(Dev d) {
         // vertex); the store depends on the loaded word, so it lands after
         // every lane's read
         if (lane_id() == 0 && w != 0) d.obits[v >> 6] = 0;
+        if (threadIdx.x == 0) {  // read only by this update's orphan scan
+            d.bvol[blk] = 0;
+            d.bcnt[blk] = 0;
+        }
         if (v < d.n && ((w >> (v & 63)) & 1)) {
             const int32_t p = d.tidx[d.rep[v]];
             if (p >= 0) {
@@ -1005,8 +1461,16 @@ void launch_rep(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_rep_chase, dim3(g), dim3(BLOCK), 0, s, d);
 }
 void launch_sweep_base(const Dev &d, hipStream_t s) {
+    // persistent: about as many workgroups as fit at once (24 KB of LDS each)
     if (d.ntiles > 0)
-        hipLaunchKernelGGL(k_sweep_base, dim3((unsigned)d.ntiles), dim3(BLOCK), 0, s, d);
+        hipLaunchKernelGGL(k_sweep_base, dim3(grid_for(d.ntiles, 1, 6 * 256)), dim3(BLOCK), 0, s, d);
+}
+void launch_orphan_scan(const Dev &d, hipStream_t s) {
+    hipLaunchKernelGGL(k_orph_plan, dim3(grid_for(d.nvb, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_orph_total, dim3(1), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_orph_fill, dim3(grid_for(d.n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_orph_scan, dim3(grid_for((d.ntiles * TILE) / OR_MAX_FRAC, OR_W, 4096)),
+                       dim3(BLOCK), 0, s, d);
 }
 void launch_sweep_delta(const Dev &d, hipStream_t s) {
     if (d.dtmax > 0)
@@ -1051,15 +1515,40 @@ void launch_reverse(const Dev &d, hipStream_t s) {
 void launch_reverse_all(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_reverse_all, dim3(grid_for(d.pathcap, BLOCK, 2048)), dim3(BLOCK), 0, s, d);
 }
-void launch_labels(const Dev &d, hipStream_t s) {
+void launch_labels(const Dev &d, bool ins, bool del, hipStream_t s) {
     const int g = grid_for(d.n, BLOCK, 1 << 20);
-    hipLaunchKernelGGL(k_label_delete, dim3(g), dim3(BLOCK), 0, s, d);
-    hipLaunchKernelGGL(k_label_insert, dim3(g), dim3(BLOCK), 0, s, d);
+    if (del) hipLaunchKernelGGL(k_label_delete, dim3(g), dim3(BLOCK), 0, s, d);
+    if (ins) hipLaunchKernelGGL(k_label_insert, dim3(g), dim3(BLOCK), 0, s, d);
 }
 void launch_cleanup(const Dev &d, hipStream_t s) {
     int64_t m = d.pcap > d.max_b ? d.pcap : d.max_b;
     hipLaunchKernelGGL(k_cleanup_slots, dim3(grid_for(m, BLOCK, 2048)), dim3(BLOCK), 0, s, d);
     hipLaunchKernelGGL(k_cleanup_counters, dim3(1), dim3(256), 0, s, d);
+}
+
+// ------------------------------------------------------------ digests
+
+// Order-independent 64-bit digests of parent and label: wrap-around sums of
+// a mix of (index, value) over the vertices.  out[0..1] must be zero.
+__global__ __launch_bounds__(BLOCK) void k_digest(int32_t n, const int32_t *parent,
+                                                  const int32_t *label, unsigned long long *out) {
+    unsigned long long a = 0, b = 0;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += stride) {
+        a += hmix(((uint64_t)i << 32) | (uint32_t)parent[i]);
+        b += hmix(((uint64_t)i << 32) | (uint32_t)label[i]) ^ 0x9E3779B97F4A7C15ull;
+    }
+    a = block_sum64(a);
+    b = block_sum64(b);
+    if (threadIdx.x == 0) {
+        atomicAdd(&out[0], a);
+        atomicAdd(&out[1], b);
+    }
+}
+void launch_digest(int32_t n, const int32_t *parent, const int32_t *label, unsigned long long *out,
+                   hipStream_t s) {
+    launch_fill_u64(out, 2, 0, s);
+    hipLaunchKernelGGL(k_digest, dim3(grid_for(n, BLOCK, 512)), dim3(BLOCK), 0, s, n, parent, label, out);
 }
 
 // ======================================================= create-time kernels
@@ -1251,6 +1740,56 @@ void launch_upper_fill(int32_t n, const int64_t *row_ptr, const int32_t *col, co
                        0, s, n, row_ptr, col, bptr, bcol);
 }
 
+// lower half: the prefix of every ascending row below the diagonal
+__global__ void k_lower_counts(int32_t n, const int64_t *row_ptr, const uint32_t *bptr,
+                               uint32_t *lcnt) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride)
+        lcnt[u] = (uint32_t)((row_ptr[u + 1] - row_ptr[u]) - (int64_t)(bptr[u + 1] - bptr[u]));
+}
+void launch_lower_counts(int32_t n, const int64_t *row_ptr, const uint32_t *bptr, uint32_t *lcnt,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_lower_counts, dim3(grid_for(n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, n, row_ptr,
+                       bptr, lcnt);
+}
+__global__ __launch_bounds__(BLOCK) void k_lower_fill(int32_t n, const int64_t *row_ptr,
+                                                      const int32_t *col, const uint32_t *lptr,
+                                                      int32_t *lcol) {
+    const int64_t nw = (int64_t)gridDim.x * (BLOCK / WAVE);
+    const int lane = lane_id();
+    for (int64_t u = (int64_t)blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE; u < n; u += nw) {
+        const int64_t s = row_ptr[u];
+        const int64_t cntu = (int64_t)lptr[u + 1] - lptr[u];
+        for (int64_t j = lane; j < cntu; j += WAVE) lcol[lptr[u] + j] = col[s + j];
+    }
+}
+void launch_lower_fill(int32_t n, const int64_t *row_ptr, const int32_t *col, const uint32_t *lptr,
+                       int32_t *lcol, hipStream_t s) {
+    hipLaunchKernelGGL(k_lower_fill, dim3(grid_for((int64_t)n * WAVE, BLOCK, 1 << 20)), dim3(BLOCK),
+                       0, s, n, row_ptr, col, lptr, lcol);
+}
+// twin[p]: position in the lower half of the mirror of upper entry p (one
+// wave per row v walks its lower entries u and finds v in upper row u)
+__global__ __launch_bounds__(BLOCK) void k_twin(int32_t n, const uint32_t *bptr, const int32_t *bcol,
+                                                const uint32_t *lptr, const int32_t *lcol,
+                                                uint32_t *twin, int32_t *status) {
+    const int64_t nw = (int64_t)gridDim.x * (BLOCK / WAVE);
+    const int lane = lane_id();
+    for (int64_t v = (int64_t)blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE; v < n; v += nw) {
+        for (int64_t q = (int64_t)lptr[v] + lane; q < (int64_t)lptr[v + 1]; q += WAVE) {
+            const int32_t u = lcol[q];
+            const int64_t p = find_in_row(bcol, bptr[u], bptr[u + 1], (int32_t)v);
+            if (p < 0) atomicOr(status, 2);
+            else twin[p] = (uint32_t)q;
+        }
+    }
+}
+void launch_twin(int32_t n, const uint32_t *bptr, const int32_t *bcol, const uint32_t *lptr,
+                 const int32_t *lcol, uint32_t *twin, int32_t *status, hipStream_t s) {
+    hipLaunchKernelGGL(k_twin, dim3(grid_for((int64_t)n * WAVE, BLOCK, 1 << 20)), dim3(BLOCK), 0, s,
+                       n, bptr, bcol, lptr, lcol, twin, status);
+}
+
 // Non-empty-row index of the upper-half store (used by the sweep).
 __global__ void k_nonempty_flags(int32_t n, const uint32_t *bptr, uint32_t *flag) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -1386,7 +1925,7 @@ __global__ __launch_bounds__(BLOCK) void k_reroot_requests(Dev d, const int32_t 
             emit = true;
             q.start = d.label[v]; q.newpar = d.label[v]; q.stop = (int32_t)v;
         }
-        const int64_t slot = wave_append(emit, &d.cnt[C_NR]);
+        const int64_t slot = block_append(emit ? 1 : 0, &d.cnt[C_NR]);
         if (emit) {
             if (slot < d.pathcap) d.paths[slot] = q;
             else atomicOr(d.status, ST_CAPACITY);

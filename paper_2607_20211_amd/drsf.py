@@ -18,6 +18,8 @@ LIB_PATH = os.environ.get("DRSF_LIB") or os.path.join(_HERE, "libdrsf.so")
 DRSF_INSERT, DRSF_DELETE = 0, 1
 DRSF_OK, DRSF_E_ARG, DRSF_E_NOMEM, DRSF_E_FOREST = 0, -1, -2, -3
 DRSF_E_BATCH, DRSF_E_CAPACITY, DRSF_E_DEVICE, DRSF_E_STATE = -4, -5, -6, -7
+DRSF_E_BUDGET = -8
+DRSF_SERVER_DIGESTS, DRSF_SERVER_SERIAL = 1, 2
 PHASES = ("validate", "update_graph", "root_finding", "key_edge_sweep",
           "key_edge_sweep_inserted", "replacement_edges", "superforest_rooting",
           "path_reversal", "labels")
@@ -29,7 +31,10 @@ class drsf_opts(ctypes.Structure):
                 ("validate_forest", ctypes.c_int),
                 ("profile", ctypes.c_int),
                 ("max_batch", ctypes.c_int64),
-                ("delta_capacity", ctypes.c_int64)]
+                ("delta_capacity", ctypes.c_int64),
+                ("sweep_mode", ctypes.c_int),
+                ("rounds_queued", ctypes.c_int),
+                ("levels_queued", ctypes.c_int)]
 
 
 class drsf_view(ctypes.Structure):
@@ -55,7 +60,11 @@ EXPORTS = ("drsf_default_opts", "drsf_create", "drsf_apply", "drsf_apply_async",
            "drsf_snapshot_take", "drsf_snapshot_restore", "drsf_snapshot_free",
            "drsf_phase_times", "drsf_destroy", "drsf_last_error", "drsf_version",
            "drsf_multi_create", "drsf_multi_apply", "drsf_multi_apply_async", "drsf_multi_wait",
-           "drsf_multi_num_edges", "drsf_num_graphs")
+           "drsf_multi_num_edges", "drsf_num_graphs", "drsf_set_tuning", "drsf_digest",
+           "drsf_device_bytes", "drsf_footprint", "drsf_server_create", "drsf_server_admit",
+           "drsf_server_submit", "drsf_server_release", "drsf_server_start",
+           "drsf_server_wait_all", "drsf_server_result", "drsf_server_stats",
+           "drsf_server_tenant_state", "drsf_server_error", "drsf_server_destroy")
 
 _lib = None
 
@@ -121,6 +130,36 @@ def load():
     lib.drsf_multi_num_edges.restype = c_int
     lib.drsf_num_graphs.argtypes = [vp]
     lib.drsf_num_graphs.restype = c_int
+    lib.drsf_set_tuning.argtypes = [vp, c_int, c_int, c_int]
+    lib.drsf_set_tuning.restype = c_int
+    lib.drsf_digest.argtypes = [vp, vp]
+    lib.drsf_digest.restype = c_int
+    lib.drsf_device_bytes.argtypes = [vp]
+    lib.drsf_device_bytes.restype = i64
+    lib.drsf_footprint.argtypes = [i32, i64, ctypes.POINTER(drsf_opts)]
+    lib.drsf_footprint.restype = i64
+    lib.drsf_server_create.argtypes = [i64, ctypes.POINTER(drsf_opts), c_int, ctypes.POINTER(vp)]
+    lib.drsf_server_create.restype = c_int
+    lib.drsf_server_admit.argtypes = [vp, i32, vp, vp, vp, i64, ctypes.POINTER(i32)]
+    lib.drsf_server_admit.restype = c_int
+    lib.drsf_server_submit.argtypes = [vp, i32, vp, i64, c_int, i64, ctypes.POINTER(i64)]
+    lib.drsf_server_submit.restype = c_int
+    lib.drsf_server_release.argtypes = [vp, i32]
+    lib.drsf_server_release.restype = c_int
+    lib.drsf_server_start.argtypes = [vp]
+    lib.drsf_server_start.restype = c_int
+    lib.drsf_server_wait_all.argtypes = [vp]
+    lib.drsf_server_wait_all.restype = c_int
+    lib.drsf_server_result.argtypes = [vp, i64, ctypes.POINTER(i32), vp, vp]
+    lib.drsf_server_result.restype = c_int
+    lib.drsf_server_stats.argtypes = [vp, vp]
+    lib.drsf_server_stats.restype = c_int
+    lib.drsf_server_tenant_state.argtypes = [vp, i32]
+    lib.drsf_server_tenant_state.restype = i32
+    lib.drsf_server_error.argtypes = [vp]
+    lib.drsf_server_error.restype = ctypes.c_char_p
+    lib.drsf_server_destroy.argtypes = [vp]
+    lib.drsf_server_destroy.restype = None
     _lib = lib
     return lib
 
@@ -247,6 +286,25 @@ def drsf_num_graphs(ctx) -> int:
     return int(load().drsf_num_graphs(ctx))
 
 
+def drsf_set_tuning(ctx, rounds_queued: int = 0, levels_queued: int = 0, sweep_mode: int = 0) -> None:
+    _check(load().drsf_set_tuning(ctx, rounds_queued, levels_queued, sweep_mode), ctx)
+
+
+def drsf_digest(ctx) -> tuple:
+    out = np.zeros(2, dtype=np.uint64)
+    _check(load().drsf_digest(ctx, out.ctypes.data), ctx)
+    return int(out[0]), int(out[1])
+
+
+def drsf_device_bytes(ctx) -> int:
+    return int(load().drsf_device_bytes(ctx))
+
+
+def drsf_footprint(n: int, nnz: int, opts: drsf_opts | None = None) -> int:
+    o = opts if opts is not None else drsf_default_opts()
+    return int(load().drsf_footprint(n, nnz, ctypes.byref(o)))
+
+
 def drsf_destroy(ctx) -> None:
     load().drsf_destroy(ctx)
 
@@ -262,13 +320,17 @@ class Forest:
 
     def __init__(self, n: int, row_ptr, col, parent, *, max_batch: int = 1 << 20,
                  stream=None, inputs_on_device: bool = False, validate: bool = True,
-                 profile: bool = False, delta_capacity: int = 0):
+                 profile: bool = False, delta_capacity: int = 0, sweep_mode: int = 0,
+                 rounds_queued: int = 0, levels_queued: int = 0):
         o = drsf_default_opts()
         o.max_batch = max_batch
         o.inputs_on_device = int(inputs_on_device)
         o.validate_forest = int(validate)
         o.profile = int(profile)
         o.delta_capacity = delta_capacity
+        o.sweep_mode = sweep_mode
+        o.rounds_queued = rounds_queued
+        o.levels_queued = levels_queued
         if stream is not None:
             o.stream = stream
         if not inputs_on_device:
@@ -322,6 +384,15 @@ class Forest:
     def phase_times(self) -> dict:
         return drsf_phase_times(self.ctx)
 
+    def digest(self) -> tuple:
+        return drsf_digest(self.ctx)
+
+    def device_bytes(self) -> int:
+        return drsf_device_bytes(self.ctx)
+
+    def set_tuning(self, rounds_queued: int = 0, levels_queued: int = 0, sweep_mode: int = 0) -> None:
+        drsf_set_tuning(self.ctx, rounds_queued, levels_queued, sweep_mode)
+
     def snapshot(self):
         return drsf_snapshot_take(self.ctx)
 
@@ -347,13 +418,17 @@ class MultiForest(Forest):
 
     def __init__(self, n_off, row_ptr, col, parent, *, max_batch: int = 1 << 20,
                  stream=None, inputs_on_device: bool = False, validate: bool = True,
-                 profile: bool = False, delta_capacity: int = 0):
+                 profile: bool = False, delta_capacity: int = 0, sweep_mode: int = 0,
+                 rounds_queued: int = 0, levels_queued: int = 0):
         o = drsf_default_opts()
         o.max_batch = max_batch
         o.inputs_on_device = int(inputs_on_device)
         o.validate_forest = int(validate)
         o.profile = int(profile)
         o.delta_capacity = delta_capacity
+        o.sweep_mode = sweep_mode
+        o.rounds_queued = rounds_queued
+        o.levels_queued = levels_queued
         if stream is not None:
             o.stream = stream
         if not inputs_on_device:
@@ -384,3 +459,81 @@ class MultiForest(Forest):
 
     def num_edges(self) -> np.ndarray:
         return drsf_multi_num_edges(self.ctx, self.G)
+
+
+# ---- serving ------------------------------------------------------------------
+
+def _scheck(rc: int, srv):
+    if rc != DRSF_OK:
+        msg = load().drsf_server_error(srv) if srv else b""
+        raise DrsfError(rc, msg.decode() if msg else "")
+
+
+class Server:
+    """Several graphs resident under a device memory budget, served by the
+    library's scheduler thread (drsf_server_* in include/drsf.h)."""
+
+    def __init__(self, budget_bytes: int, *, max_batch: int = 1 << 17, digests: bool = False,
+                 serial: bool = False, sweep_mode: int = 0):
+        o = drsf_default_opts()
+        o.max_batch = max_batch
+        o.sweep_mode = sweep_mode
+        flags = (DRSF_SERVER_DIGESTS if digests else 0) | (DRSF_SERVER_SERIAL if serial else 0)
+        out = ctypes.c_void_p()
+        _scheck(load().drsf_server_create(int(budget_bytes), ctypes.byref(o), flags, ctypes.byref(out)),
+                None)
+        self.srv = out
+
+    def admit(self, n: int, row_ptr, col, parent, arrive_ns: int = -1) -> int:
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        parent = np.ascontiguousarray(parent, dtype=np.int32)
+        t = ctypes.c_int32()
+        _scheck(load().drsf_server_admit(self.srv, n, _ptr(row_ptr), _ptr(col), _ptr(parent),
+                                         int(arrive_ns), ctypes.byref(t)), self.srv)
+        return t.value
+
+    def submit(self, tenant: int, edges, op: int, arrive_ns: int = -1) -> int:
+        edges = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+        r = ctypes.c_int64()
+        _scheck(load().drsf_server_submit(self.srv, tenant, _ptr(edges), edges.shape[0], op,
+                                          int(arrive_ns), ctypes.byref(r)), self.srv)
+        return r.value
+
+    def release(self, tenant: int) -> None:
+        _scheck(load().drsf_server_release(self.srv, tenant), self.srv)
+
+    def start(self) -> None:
+        _scheck(load().drsf_server_start(self.srv), self.srv)
+
+    def wait_all(self) -> None:
+        _scheck(load().drsf_server_wait_all(self.srv), self.srv)
+
+    def result(self, req: int) -> dict:
+        st = ctypes.c_int32()
+        t = np.zeros(3, dtype=np.uint64)
+        dg = np.zeros(2, dtype=np.uint64)
+        _scheck(load().drsf_server_result(self.srv, req, ctypes.byref(st), t.ctypes.data,
+                                          dg.ctypes.data), self.srv)
+        return {"status": st.value, "t_arrive": int(t[0]), "t_start": int(t[1]), "t_done": int(t[2]),
+                "digest": (int(dg[0]), int(dg[1]))}
+
+    def stats(self) -> dict:
+        out = np.zeros(6, dtype=np.float64)
+        _scheck(load().drsf_server_stats(self.srv, out.ctypes.data), self.srv)
+        return {"completed": int(out[0]), "p50_ms": float(out[1]), "p99_ms": float(out[2]),
+                "updates_per_s": float(out[3]), "peak_bytes": int(out[4]), "budget": int(out[5])}
+
+    def tenant_state(self, tenant: int) -> int:
+        return int(load().drsf_server_tenant_state(self.srv, tenant))
+
+    def close(self) -> None:
+        if self.srv is not None:
+            load().drsf_server_destroy(self.srv)
+            self.srv = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -145,15 +145,16 @@ def test_c1_small_gnm():
     pair.gpu.close()
 
 
-@pytest.mark.parametrize("seed", range(3))
-def test_sparse_many_components(seed):
+@pytest.mark.parametrize("seed,sweep_mode", [(0, 0), (1, 0), (2, 0), (0, 1), (1, 1)])
+def test_sparse_many_components(seed, sweep_mode):
     """Sparse graphs (many trees, several sweep tiles and a ragged tail):
-    alternating inserts and deletes, state carried over."""
+    alternating inserts and deletes, state carried over; the delete scan
+    chosen per batch (0) or always over the whole store (1)."""
     drsf = _lib()
     n = 30011
     g = gen.make_graph("sparse", n, gen.gnm(n, 26000 + 977 * seed, gen.seed(10, seed, gen.P_GRAPH)))
-    _case(f"sparse seed={seed}")
-    pair = Pair(g, max_batch=8192)
+    _case(f"sparse seed={seed} sweep_mode={sweep_mode}")
+    pair = Pair(g, max_batch=8192, sweep_mode=sweep_mode)
     for step in range(4):
         ins = gen.insert_batches(n, pair.keys, 1, 3000 + 17 * step, gen.seed(10, seed * 16 + step, gen.P_INSERT))[0]
         pair.step(ins, drsf.DRSF_INSERT, f"sparse {seed} insert {step}")
@@ -215,12 +216,13 @@ def test_deep_trees_path_and_grid():
     pair.gpu.close()
 
 
-def test_rmat_small():
+@pytest.mark.parametrize("sweep_mode", [0, 1])
+def test_rmat_small(sweep_mode):
     drsf = _lib()
-    _case("rmat16")
+    _case(f"rmat16 sweep_mode={sweep_mode}")
     keys = gen.rmat(16, 16, 0.57, 0.19, 0.19, gen.seed(2, 7, gen.P_GRAPH))
     g = gen.make_graph("rmat16", 1 << 16, keys)
-    pair = Pair(g)
+    pair = Pair(g, sweep_mode=sweep_mode)
     for step in range(2):
         ins = gen.insert_batches(g.n, pair.keys, 1, 10000, gen.seed(2, 7 + step, gen.P_INSERT))[0]
         pair.step(ins, drsf.DRSF_INSERT, f"rmat insert {step}")
@@ -305,15 +307,16 @@ def test_determinism_snapshot_restore_export():
 
 
 @pytest.mark.slow
-def test_rmat22_full_size_step():
+@pytest.mark.parametrize("sweep_mode", [0, 1])
+def test_rmat22_full_size_step(sweep_mode):
     """R-MAT scale 22 (the headline workload) at batch 1e5: one insert and one
     delete step in the configuration the benchmark times, compared with the
     oracle on the full parent and label arrays."""
     drsf = _lib()
-    _case("rmat22 full")
+    _case(f"rmat22 full sweep_mode={sweep_mode}")
     keys = gen.rmat(22, 16, 0.57, 0.19, 0.19, gen.seed(2, 0, gen.P_GRAPH))
     g = gen.make_graph("rmat22", 1 << 22, keys)
-    pair = Pair(g, max_batch=1 << 17)
+    pair = Pair(g, max_batch=1 << 17, sweep_mode=sweep_mode)
     ins = gen.insert_batches(g.n, g.keys, 1, 100000, gen.seed(2, 0, gen.P_INSERT))[0]
     pair.step(ins, drsf.DRSF_INSERT, "rmat22 insert")
     dl = gen.delete_batches(g.n, g.keys, g.parent, 1, 100000, 50000, gen.seed(2, 0, gen.P_DELETE))[0]
@@ -378,4 +381,25 @@ def test_profile_mode_direct_launches():
         pair.step(dl, drsf.DRSF_DELETE, f"profile delete {step}")
         t = pair.gpu.phase_times()
         assert all(v >= 0 for v in t.values())
+    pair.gpu.close()
+
+
+@pytest.mark.parametrize("tuning", [(1, 1, 0), (2, 2, 1), (6, 6, 0)])
+def test_launch_schedule_does_not_change_results(tuning):
+    """Few or many queued hooking rounds / search levels, either delete scan:
+    the same bit-exact results (only the split of work between the captured
+    graph and host-driven launches changes)."""
+    drsf = _lib()
+    _case(f"tuning {tuning}")
+    n = 50000
+    g = gen.make_graph("tune", n, gen.gnm(n, 45000, gen.seed(6, 0, gen.P_GRAPH)))
+    pair = Pair(g, max_batch=16384)
+    pair.gpu.set_tuning(*tuning)
+    for step in range(3):
+        ins = gen.insert_batches(n, pair.keys, 1, 12000, gen.seed(6, step, gen.P_INSERT))[0]
+        pair.step(ins, drsf.DRSF_INSERT, f"tuning {tuning} insert {step}")
+        trees = int((pair.parent != np.arange(n)).sum())
+        dl = gen.delete_batches(n, pair.keys, pair.parent, 1, 8000, min(4000, trees),
+                                gen.seed(6, step, gen.P_DELETE))[0]
+        pair.step(dl, drsf.DRSF_DELETE, f"tuning {tuning} delete {step}")
     pair.gpu.close()

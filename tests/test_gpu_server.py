@@ -1,0 +1,161 @@
+"""Serving: several graphs under a memory budget, updated by a stream of
+requests through the library's scheduler.  Every request's digests of parent
+and label must equal the oracle's arrays after the same requests, both when
+requests of different graphs overlap on the device and in the serial
+(one-at-a-time) mode; a budget that holds only some graphs at once delays
+admission without changing results."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def _lib():
+    from paper_2607_20211_amd import drsf
+    return drsf
+
+
+def _case(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _fmix(k):
+    k = k ^ (k >> np.uint64(33))
+    k = k * np.uint64(0xFF51AFD7ED558CCD)
+    k = k ^ (k >> np.uint64(33))
+    k = k * np.uint64(0xC4CEB9FE1A85EC53)
+    return k ^ (k >> np.uint64(33))
+
+
+def digest(parent, label):
+    """The digest the library computes: wrap-around sums of a 64-bit mix of
+    (vertex, value), label words xor-ed with a constant."""
+    i = np.arange(len(parent), dtype=np.uint64) << np.uint64(32)
+    with np.errstate(over="ignore"):
+        a = _fmix(i | parent.astype(np.uint32).astype(np.uint64))
+        b = _fmix(i | label.astype(np.uint32).astype(np.uint64)) ^ np.uint64(0x9E3779B97F4A7C15)
+        return int(a.sum(dtype=np.uint64)), int(b.sum(dtype=np.uint64))
+
+
+def _tenants(k, seed):
+    out = []
+    for t in range(k):
+        n = 2000 + 1500 * t
+        out.append(gen.make_graph(f"t{t}", n, gen.gnm(n, 3 * n, gen.seed(50, seed * 16 + t, gen.P_GRAPH))))
+    return out
+
+
+def _stream(graphs, nreq, seed, bad=()):
+    """Requests (tenant, edges, op, arrive_ns), valid in order per tenant:
+    inserts of initial non-edges, deletes of initial edges, distinct across
+    requests.  Requests with index in `bad` repeat a pair (invalid)."""
+    rng = np.random.default_rng(seed)
+    pools = []
+    for t, g in enumerate(graphs):
+        ins = gen.insert_batches(g.n, g.keys, 1, g.n, gen.seed(51, seed * 16 + t, gen.P_INSERT))[0]
+        trees = int((g.parent != np.arange(g.n)).sum())
+        dl = gen.delete_batches(g.n, g.keys, g.parent, 1, min(g.m, 2 * trees) // 2 * 2,
+                                min(g.m, 2 * trees) // 4, gen.seed(51, seed * 16 + t, gen.P_DELETE))[0]
+        rng.shuffle(dl)
+        pools.append([ins, 0, dl, 0])
+    reqs, t_ns = [], 0
+    for r in range(nreq):
+        t = int(rng.integers(len(graphs)))
+        op = int(rng.integers(2))
+        b = int(rng.integers(1, 200))
+        pool = pools[t]
+        if op == 0:
+            e = pool[0][pool[1]:pool[1] + b]
+            pool[1] += len(e)
+        else:
+            e = pool[2][pool[3]:pool[3] + b]
+            pool[3] += len(e)
+        if len(e) == 0:
+            op, e = 0, pool[0][pool[1]:pool[1] + 1]
+            pool[1] += 1
+        if r in bad:
+            e = np.concatenate([e, e[:1]])
+        t_ns += int(rng.exponential(40_000))
+        reqs.append((t, np.ascontiguousarray(e, np.int32), op, t_ns))
+    return reqs
+
+
+def _oracle_digests(graphs, reqs):
+    """Per request: (valid, digest) after applying it with the oracle."""
+    st = []
+    for g in graphs:
+        r = oracle.apply(g.n, g.keys, g.parent, np.zeros((0, 2), np.int32), oracle.DELETE)
+        st.append([g.keys, r.parent, r.label])
+    out = []
+    for t, e, op, _ in reqs:
+        keys, par, lab = st[t]
+        try:
+            r = oracle.apply(graphs[t].n, keys, par, e, oracle.INSERT if op == 0 else oracle.DELETE,
+                             label=lab)
+        except oracle.OracleError:
+            out.append((False, digest(par, lab)))
+            continue
+        st[t] = [r.keys, r.parent, r.label]
+        out.append((True, digest(r.parent, r.label)))
+    return out
+
+
+def _serve(graphs, reqs, *, serial, budget, stagger_ns=0):
+    drsf = _lib()
+    srv = drsf.Server(budget, max_batch=512, digests=True, serial=serial)
+    ids = [srv.admit(g.n, g.row_ptr, g.col, g.parent, arrive_ns=i * stagger_ns)
+           for i, g in enumerate(graphs)]
+    rids = [srv.submit(ids[t], e, op, arrive_ns=a) for t, e, op, a in reqs]
+    for tid in ids:
+        srv.release(tid)
+    srv.start()
+    srv.wait_all()
+    res = [srv.result(r) for r in rids]
+    stats = srv.stats()
+    srv.close()
+    return res, stats
+
+
+@pytest.mark.parametrize("serial", [False, True])
+def test_served_requests_match_oracle(serial):
+    drsf = _lib()
+    _case(f"server serial={serial}")
+    graphs = _tenants(4, 0)
+    reqs = _stream(graphs, 160, 3, bad={17, 90})
+    ref = _oracle_digests(graphs, reqs)
+    res, stats = _serve(graphs, reqs, serial=serial, budget=1 << 40)
+    for k, (r, (valid, dg)) in enumerate(zip(res, ref)):
+        if valid:
+            assert r["status"] == drsf.DRSF_OK, (k, r)
+            assert r["digest"] == dg, f"request {k}: digest differs from the oracle"
+        else:
+            assert r["status"] == drsf.DRSF_E_BATCH, (k, r)
+        assert r["t_arrive"] <= r["t_start"] <= r["t_done"]
+    assert stats["completed"] == len(reqs)
+    assert stats["p50_ms"] <= stats["p99_ms"]
+
+
+def test_budget_delays_admission_only():
+    """A budget that holds two of the four graphs: the later graphs wait
+    for earlier ones to leave; every request still ends as the oracle says."""
+    drsf = _lib()
+    _case("server budget")
+    graphs = _tenants(4, 1)
+    fp = [drsf.drsf_footprint(g.n, len(g.col), None) for g in graphs]
+    budget = fp[2] + fp[3] + 1
+    reqs = _stream(graphs, 80, 4)
+    ref = _oracle_digests(graphs, reqs)
+    res, stats = _serve(graphs, reqs, serial=False, budget=budget, stagger_ns=200_000)
+    for k, (r, (valid, dg)) in enumerate(zip(res, ref)):
+        assert r["status"] == drsf.DRSF_OK and r["digest"] == dg, k
+    assert stats["peak_bytes"] <= budget
