@@ -110,6 +110,10 @@ typedef struct {
     int64_t num_replacement;
     int64_t num_pieces;
     int64_t num_paths;
+    int64_t num_orphans;      /* delete: vertices cut off from their old root */
+    int64_t orphan_slots;     /* delete: adjacency entries of those vertices */
+    int32_t scan_orphans;     /* delete: 1 if the key-edge scan covered only the
+                                 orphans' adjacency, 0 if the whole store */
 } drsf_view;
 
 /*
@@ -239,12 +243,14 @@ void drsf_snapshot_free(drsf_snapshot *snap);
 
 /*
  * Per-phase device times of the last apply in milliseconds (needs
- * opts.profile): validate, update-graph (cut, store update, piece
- * registration), root finding, key-edge sweep of the base edge store,
- * cross edges of the batch and of the inserted-edge list, replacement edges
- * (the hooking rounds queued with the update), super-forest rooting, path
- * reversal, labels.  Work that an update finishes on the host (extra rounds)
- * is not in these times.  Returns the number of phases written (<= cap).
+ * opts.profile), 12 phases: validate; update-graph (cut, store update, piece
+ * registration); root-finding start (rep = parent); root finding (pointer
+ * chase, orphan bitmap); orphan list; orphan adjacency scan; whole-store
+ * sweep; cross edges of the batch and of the inserted-edge list; replacement
+ * edges (the hooking rounds queued with the update); super-forest rooting;
+ * path reversal; labels.  Work that an update finishes on the host (extra
+ * rounds) is not in these times.  Returns the number of phases written
+ * (<= cap).
  */
 int drsf_phase_times(drsf_ctx *ctx, float *ms, int cap);
 
@@ -297,9 +303,12 @@ int drsf_server_wait_all(drsf_server *srv);
  */
 int drsf_server_result(drsf_server *srv, int64_t req, int32_t *status, uint64_t *t_ns, uint64_t *digest);
 /*
- * out[6]: completed requests, p50 and p99 of (completion - arrival) in ms,
+ * out[8]: completed requests, p50 and p99 of (completion - arrival) in ms,
  * edge updates per second from the first arrival to the last completion,
- * peak device bytes of the admitted tenants, the budget.
+ * peak device bytes of the admitted tenants, the budget, p50 and p99 of
+ * (completion - max(arrival, the tenant's admission)) in ms.  Graphs
+ * admitted at time 0 are made resident by drsf_server_start, before the
+ * clock starts.
  */
 int drsf_server_stats(drsf_server *srv, double *out);
 /* 0 waiting to arrive, 1 queued for admission, 2 live, 3 released, 4 failed. */

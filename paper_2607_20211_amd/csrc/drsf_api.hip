@@ -34,8 +34,8 @@ constexpr int BFS_FAST = 4;    // default search levels queued in the captured s
 constexpr int BFS_MAX = 12;    // deeper super-trees use the Euler tour instead
 constexpr int BOR_CHUNK = 3;   // rounds per host check in the continuation
 
-enum Phase { PH_VALIDATE, PH_UPDATE, PH_ROOTS, PH_SWEEP, PH_SWEEP_DELTA, PH_REPL, PH_ROOTING,
-             PH_REVERSE, PH_LABELS, PH_N };
+enum Phase { PH_VALIDATE, PH_UPDATE, PH_ROOT_INIT, PH_ROOT_CHASE, PH_ORPH_LIST, PH_ORPH_SCAN,
+             PH_SWEEP, PH_SWEEP_DELTA, PH_REPL, PH_ROOTING, PH_REVERSE, PH_LABELS, PH_N };
 
 int ceil_log2(int64_t x) {
     int r = 0;
@@ -100,7 +100,7 @@ struct drsf_ctx {
     int8_t *bop = nullptr;
     uint64_t *bkey = nullptr, *bhash = nullptr;
     int64_t *bloc = nullptr;
-    uint32_t *twin = nullptr;
+    uint32_t *twin = nullptr, *ltwin = nullptr;
     uint64_t bhmask = 0;
     // orphan scan
     int64_t nvb = 0;
@@ -221,8 +221,13 @@ Dev make_dev(drsf_ctx *c) {
     memset(&d, 0, sizeof d);
     d.n = c->n;
     d.ctl = c->ctl;
+    d.ctlw = c->ctl;
+    d.hctl = c->h_ctl;
+    d.ctlmem = c->ctlmem;
+    d.hret = c->h_ret;
+    d.ret_words = c->ret_words;
     d.bptr = c->bptr; d.bcol = c->bcol; d.eb = c->eb;
-    d.lptr = c->lptr; d.lcol = c->lcol; d.twin = c->twin;
+    d.lptr = c->lptr; d.lcol = c->lcol; d.twin = c->twin; d.ltwin = c->ltwin;
     d.nvb = c->nvb; d.bvol = c->bvol; d.bcnt = c->bcnt; d.bpre = c->bpre; d.opre = c->opre;
     d.olist = c->olist; d.rstart = c->rstart; d.xcnt = c->xcnt;
     d.gsum = c->gsum; d.gpre = c->gpre; d.ostage = c->ostage;
@@ -420,9 +425,10 @@ int build_store(drsf_ctx *c, const int64_t *row_ptr_in, const int32_t *col_in, i
     if ((rc = dalloc(c, &c->lcol, c->eb))) return rc;
     launch_lower_fill(n, drow, dcol, c->lptr, c->lcol, s);
     if ((rc = dalloc(c, &c->twin, c->eb))) return rc;
+    if ((rc = dalloc(c, &c->ltwin, c->eb))) return rc;
     // every lower entry finds its mirror in the upper half: with equal halves
     // this is the symmetry check
-    launch_twin(n, c->bptr, c->bcol, c->lptr, c->lcol, c->twin, c->status, s);
+    launch_twin(n, c->bptr, c->bcol, c->lptr, c->lcol, c->twin, c->ltwin, c->status, s);
     {
         int32_t st2;
         if ((rc = read_status(c, &st2))) return rc;
@@ -501,11 +507,6 @@ int canonicalise_forest(drsf_ctx *c) {
     return DRSF_OK;
 }
 
-void enqueue_results_copy(drsf_ctx *c) {
-    hipStream_t s = c->stream;
-    (void)hipMemcpyAsync(c->h_ret, c->ctlmem, sizeof(unsigned long long) * (size_t)c->ret_words,
-                         hipMemcpyDeviceToHost, s);
-}
 
 // The update sequence (see the file comment) for batches with inserts
 // (kind bit 1) and/or deletes (kind bit 2); with events when profiling.
@@ -521,18 +522,22 @@ void enqueue_update(drsf_ctx *c, int kind, bool profile) {
     mark(PH_UPDATE);
     launch_prepare(d, s);
     launch_register(d, s);
-    mark(PH_ROOTS);
-    if (del) launch_rep(d, s);
+    mark(PH_ROOT_INIT);
+    if (del) launch_rep_init(d, s);
+    mark(PH_ROOT_CHASE);
+    if (del) launch_rep_chase(d, s);
+    mark(PH_ORPH_LIST);
+    if (del) launch_orphan_list(d, s);
+    mark(PH_ORPH_SCAN);
+    if (del) launch_orphan_scan(d, s);
     mark(PH_SWEEP);
-    if (del) {
-        launch_orphan_scan(d, s);
-        launch_sweep_base(d, s);
-    }
+    if (del) launch_sweep_base(d, s);
     mark(PH_SWEEP_DELTA);
     if (ins) launch_insert_emit(d, s);
     if (del) launch_sweep_delta(d, s);
     mark(PH_REPL);
-    launch_boruvka(d, 0, c->bor_fast, s);
+    const int64_t units = (ins ? insert_regions(c->max_batch) : 0) + (del ? c->ntiles + c->dtmax : 0);
+    launch_boruvka(d, 0, c->bor_fast, units, s);
     mark(PH_ROOTING);
     launch_sf_root(d, s);
     launch_sf_bfs(d, 0, c->bfs_fast, s);
@@ -542,8 +547,7 @@ void enqueue_update(drsf_ctx *c, int kind, bool profile) {
     mark(PH_LABELS);
     launch_labels(d, ins, del, s);
     mark(PH_N);
-    enqueue_results_copy(c);
-    launch_cleanup(d, s);
+    launch_cleanup(d, s);  // also hands the results to the host
 }
 
 int capture_graph(drsf_ctx *c, int kind) {
@@ -584,7 +588,7 @@ int continue_update(drsf_ctx *c) {
     if (!bad && !done) {
         while (!done && !bad && r < bor_bound) {
             const int r1 = std::min(r + BOR_CHUNK, bor_bound);
-            launch_boruvka(d, r, r1, s);
+            launch_boruvka(d, r, r1, 4096, s);
             r = r1;
             if ((rc = read_flags(lv))) return rc;
             bad = *(int32_t *)f != 0;
@@ -614,8 +618,7 @@ int continue_update(drsf_ctx *c) {
         launch_reverse(d, s);
         launch_labels(d, c->kind & 1, c->kind & 2, s);
     }
-    enqueue_results_copy(c);
-    launch_cleanup(d, s);
+    launch_cleanup(d, s);  // hands the results to the host, then resets
     HIPCHK(c, hipStreamSynchronize(s));
     return DRSF_OK;
 }
@@ -624,7 +627,7 @@ int continue_update(drsf_ctx *c) {
 // control block is in h_ctl.
 int launch_update(drsf_ctx *c) {
     hipStream_t s = c->stream;
-    HIPCHK(c, hipMemcpyAsync(c->ctl, c->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, s));
+    // the control block is read from h_ctl by the first kernel (no copy)
     const bool prof = c->opts.profile != 0;
     c->kind = (c->h_ctl->has_ins ? 1 : 0) | (c->h_ctl->has_del ? 2 : 0);
     if (c->kind == 0) c->kind = 3;  // nothing but rejected or empty batches: run everything
@@ -897,6 +900,8 @@ int drsf_apply_async(drsf_ctx *c, const int32_t *edges, int64_t b, int op) {
     if (b == 0) {
         c->last_rc = DRSF_OK;
         c->view.num_key_cross = c->view.num_replacement = c->view.num_pieces = c->view.num_paths = 0;
+        c->view.num_orphans = c->view.orphan_slots = 0;
+        c->view.scan_orphans = 0;
         return DRSF_OK;
     }
     if (op == DRSF_INSERT && c->ndelta_bound + b > c->dcap)
@@ -950,6 +955,8 @@ int drsf_multi_apply_async(drsf_ctx *c, const int32_t *edges, const int64_t *b_o
         c->last_rc = DRSF_OK;
         for (int32_t g = 0; g < G; g++) c->h_gstat[g] = 0;
         c->view.num_key_cross = c->view.num_replacement = c->view.num_pieces = c->view.num_paths = 0;
+        c->view.num_orphans = c->view.orphan_slots = 0;
+        c->view.scan_orphans = 0;
         return DRSF_OK;
     }
     // per-edge op and graph; vertex-block lists of the deleting and the
@@ -1028,6 +1035,9 @@ int drsf_wait(drsf_ctx *c, drsf_view *out) {
             c->view.num_replacement = (int64_t)k[C_NER];
             c->view.num_pieces = (int64_t)k[C_NP];
             c->view.num_paths = (int64_t)k[C_NR];
+            c->view.scan_orphans = (int32_t)k[C_OMODE];
+            c->view.num_orphans = (int64_t)k[C_NORPH];
+            c->view.orphan_slots = (int64_t)k[C_OVOL] - (int64_t)OR_PAD * (int64_t)k[C_NORPH];
             c->last_rc = DRSF_OK;
             if (c->multi_last) {
                 for (int32_t g = 0; g < c->ngraph; g++) {

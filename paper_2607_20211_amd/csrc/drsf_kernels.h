@@ -26,7 +26,12 @@ struct Ctl {
 // All device pointers one apply needs; passed by value to every kernel.
 struct Dev {
     int32_t n;
-    const Ctl *ctl;
+    const Ctl *ctl;          // device copy, written by the first kernel of an update
+    Ctl *ctlw;               // the same, writable
+    const Ctl *hctl;         // host copy (pinned), read by the first kernel only
+    unsigned long long *ctlmem;  // status word, counters, per-graph status (ret_words words)
+    unsigned long long *hret;    // pinned host copy of ctlmem, written by the last kernel
+    int64_t ret_words;
     // edge store: upper-half base CSR (row u holds v > u, ascending; TOMB bit =
     // deleted) plus a list of inserted edges with a hash index
     const uint32_t *bptr;    // [n + 1]
@@ -52,6 +57,7 @@ struct Dev {
     const uint32_t *lptr;    // [n + 1]
     int32_t *lcol;           // [eb]
     const uint32_t *twin;    // [eb] position in lcol of the mirror of each bcol entry
+    const uint32_t *ltwin;   // [eb] position in bcol of the mirror of each lcol entry
     // orphan adjacency scan (delete): per vertex block of BLOCK vertices the
     // listed orphans and their slots, prefixes, the compacted list and, per
     // range of OR_W slots, the list index holding its first slot
@@ -153,11 +159,14 @@ void launch_classify(const Dev &d, hipStream_t s);
 void launch_prepare(const Dev &d, hipStream_t s);
 void launch_register(const Dev &d, hipStream_t s);
 void launch_insert_emit(const Dev &d, hipStream_t s);
-void launch_rep(const Dev &d, hipStream_t s);
+void launch_rep_init(const Dev &d, hipStream_t s);
+void launch_rep_chase(const Dev &d, hipStream_t s);
 void launch_sweep_base(const Dev &d, hipStream_t s);
-void launch_orphan_scan(const Dev &d, hipStream_t s);  // plan, list, scan
+void launch_orphan_list(const Dev &d, hipStream_t s);  // plan, totals and mode, list
+void launch_orphan_scan(const Dev &d, hipStream_t s);
 void launch_sweep_delta(const Dev &d, hipStream_t s);
-void launch_boruvka(const Dev &d, int r0, int r1, hipStream_t s);
+// units: regions of x0 the first two rounds may read (sizes their grids)
+void launch_boruvka(const Dev &d, int r0, int r1, int64_t units, hipStream_t s);
 void launch_sf_root(const Dev &d, hipStream_t s);
 void launch_sf_bfs(const Dev &d, int l0, int l1, hipStream_t s);
 void launch_orient_bfs(const Dev &d, int levels, hipStream_t s);
@@ -193,7 +202,7 @@ void launch_lower_counts(int32_t n, const int64_t *row_ptr, const uint32_t *bptr
 void launch_lower_fill(int32_t n, const int64_t *row_ptr, const int32_t *col,
                        const uint32_t *lptr, int32_t *lcol, hipStream_t s);
 void launch_twin(int32_t n, const uint32_t *bptr, const int32_t *bcol, const uint32_t *lptr,
-                 const int32_t *lcol, uint32_t *twin, int32_t *status, hipStream_t s);
+                 const int32_t *lcol, uint32_t *twin, uint32_t *ltwin, int32_t *status, hipStream_t s);
 // non-empty row index: flags -> (scan) -> zrow/zptr, then tile_k
 void launch_nonempty_flags(int32_t n, const uint32_t *bptr, uint32_t *flag, hipStream_t s);
 void launch_nonempty_fill(int32_t n, const uint32_t *bptr, const uint32_t *zpos, int32_t *zrow,

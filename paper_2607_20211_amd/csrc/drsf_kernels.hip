@@ -191,7 +191,14 @@ __device__ __forceinline__ int64_t list_block(const int32_t *list, int64_t cnt, 
 // Algorithm 1, the cut step).  Errors mark the edge's graph as rejected;
 // nothing but batch scratch is written.
 __global__ __launch_bounds__(BLOCK) void k_classify(Dev d) {
-    const int64_t b = d.ctl->b;
+    // the update's control block comes from pinned host memory; the first
+    // workgroup publishes it for the later kernels, which read the device copy
+    const Ctl *hc = d.hctl;
+    if (blockIdx.x == 0 && threadIdx.x < sizeof(Ctl) / 8)
+        reinterpret_cast<uint64_t *>(d.ctlw)[threadIdx.x] =
+            reinterpret_cast<const uint64_t *>(hc)[threadIdx.x];
+    const int64_t b = hc->b;
+    const int opm = hc->op;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < b; i += stride) {
         const int32_t u = d.bedges[2 * i], v = d.bedges[2 * i + 1];
@@ -220,8 +227,16 @@ __global__ __launch_bounds__(BLOCK) void k_classify(Dev d) {
             if (s == k) { atomicOr(&d.gstat[g], ST_DUPLICATE); break; }
             h = (h + 1) & d.bhmask;
         }
-        // presence
-        const int64_t pos = find_in_row(d.bcol, d.bptr[lo], d.bptr[lo + 1], hi);
+        // presence: the edge sits in upper row lo and in lower row hi (with
+        // mirrored tombstones); search the shorter and map a lower hit up
+        const uint32_t ua = d.bptr[lo], ub = d.bptr[lo + 1], la = d.lptr[hi], lb = d.lptr[hi + 1];
+        int64_t pos;
+        if (ub - ua <= lb - la) {
+            pos = find_in_row(d.bcol, ua, ub, hi);
+        } else {
+            const int64_t q = find_in_row(d.lcol, la, lb, lo);
+            pos = q >= 0 ? (int64_t)d.ltwin[q] : -1;
+        }
         int64_t loc;
         bool present;
         if (pos >= 0 && d.bcol[pos] >= 0) {
@@ -232,7 +247,7 @@ __global__ __launch_bounds__(BLOCK) void k_classify(Dev d) {
             present = slot >= 0;
             loc = -(slot + 1);
         }
-        if (edge_op(d, i) == 0) {
+        if ((opm == 2 ? (int)d.bop[i] : opm) == 0) {
             if (present) atomicOr(&d.gstat[g], ST_EXISTS);
         } else {
             if (!present) {
@@ -358,14 +373,21 @@ __global__ __launch_bounds__(BLOCK) void k_insert_emit(Dev d) {
 
 // ----------------------------------------------- a4: root finding (delete)
 
+// One wave per vertex block, four vertices per lane (16-byte accesses).
 __global__ __launch_bounds__(BLOCK) void k_rep_init(Dev d) {
     if (*d.status || !d.ctl->has_del) return;
+    typedef int v4i __attribute__((ext_vector_type(4)));
     const int64_t nb = (d.n + BLOCK - 1) / BLOCK;
-    for (int64_t j = blockIdx.x;; j += gridDim.x) {
+    const int w = threadIdx.x / WAVE;
+    for (int64_t j = (int64_t)blockIdx.x * (BLOCK / WAVE) + w;; j += (int64_t)gridDim.x * (BLOCK / WAVE)) {
         const int64_t blk = list_block(d.vlist, d.ctl->nvl, j, nb);
         if (blk < 0) break;
-        const int64_t v = blk * BLOCK + threadIdx.x;
-        if (v < d.n) d.rep[v] = d.parent[v];
+        const int64_t v = blk * BLOCK + lane_id() * 4;
+        if (v + 4 <= d.n) {
+            *reinterpret_cast<v4i *>(d.rep + v) = *reinterpret_cast<const v4i *>(d.parent + v);
+        } else {
+            for (int64_t u = v; u < d.n && u < v + 4; u++) d.rep[u] = d.parent[u];
+        }
     }
 }
 
@@ -728,18 +750,24 @@ __global__ __launch_bounds__(BLOCK) void k_orph_total(Dev d) {
 // index of the orphan holding its first slot.
 __global__ __launch_bounds__(BLOCK) void k_orph_fill(Dev d) {
     if (*d.status || !d.ctl->has_del || !d.cnt[C_OMODE]) return;
-    for (int64_t j = blockIdx.x;; j += gridDim.x) {
+    const int wv = threadIdx.x / WAVE;
+    // one wave per vertex block (blocks hold few orphans)
+    for (int64_t j = (int64_t)blockIdx.x * (BLOCK / WAVE) + wv;; j += (int64_t)gridDim.x * (BLOCK / WAVE)) {
         const int64_t blk = list_block(d.vlist, d.ctl->nvl, j, d.nvb);
         if (blk < 0) break;
         const int32_t nc = d.bcnt[blk];
-        if ((int32_t)threadIdx.x >= nc) continue;
+        if (nc == 0) continue;
         const unsigned long long gp = d.gpre[blk / BLOCK];
-        OrphEnt o = d.ostage[blk * BLOCK + threadIdx.x];
-        const int64_t idx = (int64_t)ocnt(gp) + d.opre[blk] + threadIdx.x;
-        o.pre += (int64_t)ovol(gp) + d.bpre[blk];
-        d.olist[idx] = o;
-        const int64_t end = o.pre + o.du + o.dl + OR_PAD;
-        for (int64_t w = (o.pre + OR_W - 1) / OR_W; w * OR_W < end; w++) d.rstart[w] = (int32_t)idx;
+        const int64_t ob = (int64_t)ocnt(gp) + d.opre[blk];
+        const int64_t vb = (int64_t)ovol(gp) + d.bpre[blk];
+        for (int32_t i = lane_id(); i < nc; i += WAVE) {
+            OrphEnt o = d.ostage[blk * BLOCK + i];
+            const int64_t idx = ob + i;
+            o.pre += vb;
+            d.olist[idx] = o;
+            const int64_t end = o.pre + o.du + o.dl + OR_PAD;
+            for (int64_t w = (o.pre + OR_W - 1) / OR_W; w * OR_W < end; w++) d.rstart[w] = (int32_t)idx;
+        }
     }
 }
 
@@ -1396,17 +1424,32 @@ __global__ __launch_bounds__(BLOCK) void k_label_delete(Dev d) {
 // component's label (the tree is found through its old label, its root).
 __global__ __launch_bounds__(BLOCK) void k_label_insert(Dev d) {
     if (*d.status || !d.cnt[C_ORIENTED] || !d.ctl->has_ins || d.cnt[C_NP] == 0) return;
+    typedef int v4i __attribute__((ext_vector_type(4)));
     const int64_t nb = (d.n + BLOCK - 1) / BLOCK;
-    for (int64_t j = blockIdx.x;; j += gridDim.x) {
+    const int w = threadIdx.x / WAVE;
+    // one wave per vertex block, four vertices per lane
+    for (int64_t j = (int64_t)blockIdx.x * (BLOCK / WAVE) + w;; j += (int64_t)gridDim.x * (BLOCK / WAVE)) {
         const int64_t blk = list_block(d.ilist, d.ctl->nil, j, nb);
         if (blk < 0) break;
-        const int64_t v = blk * BLOCK + threadIdx.x;
-        if (v < d.n) {
-            const int32_t t = d.tidx[d.label[v]];
-            if (t != NONE) {
-                const int32_t l = d.newlab[d.comp[t]];
-                d.label[v] = l;
-                d.rep[v] = l;
+        const int64_t v = blk * BLOCK + lane_id() * 4;
+        int32_t lab[4];
+        if (v + 4 <= d.n) {
+            const v4i x = *reinterpret_cast<const v4i *>(d.label + v);
+            lab[0] = x.x; lab[1] = x.y; lab[2] = x.z; lab[3] = x.w;
+        } else {
+            for (int k = 0; k < 4; k++) lab[k] = v + k < d.n ? d.label[v + k] : 0;
+        }
+        int32_t t[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) t[k] = d.tidx[lab[k]];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            if (v + k < d.n && t[k] != NONE) {
+                const int32_t l = d.newlab[d.comp[t[k]]];
+                if (l != lab[k]) {  // the super-root's tree keeps its label
+                    d.label[v + k] = l;
+                    d.rep[v + k] = l;
+                }
             }
         }
     }
@@ -1426,15 +1469,19 @@ __global__ __launch_bounds__(BLOCK) void k_cleanup_slots(Dev d) {
         if (d.bslot[i] != NONE) d.bhash[d.bslot[i]] = HASH_EMPTY;
     for (int64_t t = d.ctl->rlo + (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < d.ctl->rhi; t += stride)
         d.rcnt[t] = 0;
-    for (int64_t g = (int64_t)blockIdx.x * BLOCK + threadIdx.x; g < d.ctl->ngraph; g += stride)
-        d.gstat[g] = 0;
 }
 
+// Hands status, counters and per-graph batch status to the host (pinned
+// memory, also when the update is unfinished and the host continues it),
+// then resets them once the update has finished.
 __global__ void k_cleanup_counters(Dev d) {
+    for (int64_t t = threadIdx.x; t < d.ret_words; t += blockDim.x) d.hret[t] = d.ctlmem[t];
+    __threadfence_system();
     if (!d.cnt[C_ORIENTED] && !*d.status) return;
-    __syncthreads();  // every thread has read the flags before any reset
+    __syncthreads();  // every thread has copied and read the flags before any reset
     const int t = threadIdx.x;
     if (t < C_TOTAL && t != C_NDELTA) d.cnt[t] = 0;
+    for (int64_t g = threadIdx.x; g < d.ctl->ngraph; g += blockDim.x) d.gstat[g] = 0;
     if (t == 0) *d.status = 0;
 }
 
@@ -1455,20 +1502,23 @@ void launch_register(const Dev &d, hipStream_t s) {
 void launch_insert_emit(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_insert_emit, dim3((unsigned)insert_regions(d.max_b)), dim3(BLOCK), 0, s, d);
 }
-void launch_rep(const Dev &d, hipStream_t s) {
-    const int g = grid_for(d.n, BLOCK, 1 << 20);
-    hipLaunchKernelGGL(k_rep_init, dim3(g), dim3(BLOCK), 0, s, d);
-    hipLaunchKernelGGL(k_rep_chase, dim3(g), dim3(BLOCK), 0, s, d);
+void launch_rep_init(const Dev &d, hipStream_t s) {
+    hipLaunchKernelGGL(k_rep_init, dim3(grid_for(d.nvb, BLOCK / WAVE, 1 << 20)), dim3(BLOCK), 0, s, d);
+}
+void launch_rep_chase(const Dev &d, hipStream_t s) {
+    hipLaunchKernelGGL(k_rep_chase, dim3(grid_for(d.n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, d);
 }
 void launch_sweep_base(const Dev &d, hipStream_t s) {
     // persistent: about as many workgroups as fit at once (24 KB of LDS each)
     if (d.ntiles > 0)
         hipLaunchKernelGGL(k_sweep_base, dim3(grid_for(d.ntiles, 1, 6 * 256)), dim3(BLOCK), 0, s, d);
 }
-void launch_orphan_scan(const Dev &d, hipStream_t s) {
+void launch_orphan_list(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_orph_plan, dim3(grid_for(d.nvb, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, d);
     hipLaunchKernelGGL(k_orph_total, dim3(1), dim3(BLOCK), 0, s, d);
-    hipLaunchKernelGGL(k_orph_fill, dim3(grid_for(d.n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_orph_fill, dim3(grid_for(d.nvb, BLOCK / WAVE, 1 << 20)), dim3(BLOCK), 0, s, d);
+}
+void launch_orphan_scan(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_orph_scan, dim3(grid_for((d.ntiles * TILE) / OR_MAX_FRAC, OR_W, 4096)),
                        dim3(BLOCK), 0, s, d);
 }
@@ -1476,8 +1526,8 @@ void launch_sweep_delta(const Dev &d, hipStream_t s) {
     if (d.dtmax > 0)
         hipLaunchKernelGGL(k_sweep_delta, dim3((unsigned)d.dtmax), dim3(BLOCK), 0, s, d);
 }
-void launch_boruvka(const Dev &d, int r0, int r1, hipStream_t s) {
-    const int ge = grid_for(d.xcap, BLOCK, 4096);
+void launch_boruvka(const Dev &d, int r0, int r1, int64_t units, hipStream_t s) {
+    const int ge = grid_for(units, 1, 4096);
     const int gp = grid_for(d.pcap, BLOCK, 2048);
     for (int r = r0; r < r1; r++) {
         if (r == 0)
@@ -1518,7 +1568,9 @@ void launch_reverse_all(const Dev &d, hipStream_t s) {
 void launch_labels(const Dev &d, bool ins, bool del, hipStream_t s) {
     const int g = grid_for(d.n, BLOCK, 1 << 20);
     if (del) hipLaunchKernelGGL(k_label_delete, dim3(g), dim3(BLOCK), 0, s, d);
-    if (ins) hipLaunchKernelGGL(k_label_insert, dim3(g), dim3(BLOCK), 0, s, d);
+    if (ins)
+        hipLaunchKernelGGL(k_label_insert, dim3(grid_for(d.nvb, BLOCK / WAVE, 1 << 20)), dim3(BLOCK), 0,
+                           s, d);
 }
 void launch_cleanup(const Dev &d, hipStream_t s) {
     int64_t m = d.pcap > d.max_b ? d.pcap : d.max_b;
@@ -1772,22 +1824,26 @@ void launch_lower_fill(int32_t n, const int64_t *row_ptr, const int32_t *col, co
 // wave per row v walks its lower entries u and finds v in upper row u)
 __global__ __launch_bounds__(BLOCK) void k_twin(int32_t n, const uint32_t *bptr, const int32_t *bcol,
                                                 const uint32_t *lptr, const int32_t *lcol,
-                                                uint32_t *twin, int32_t *status) {
+                                                uint32_t *twin, uint32_t *ltwin, int32_t *status) {
     const int64_t nw = (int64_t)gridDim.x * (BLOCK / WAVE);
     const int lane = lane_id();
     for (int64_t v = (int64_t)blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE; v < n; v += nw) {
         for (int64_t q = (int64_t)lptr[v] + lane; q < (int64_t)lptr[v + 1]; q += WAVE) {
             const int32_t u = lcol[q];
             const int64_t p = find_in_row(bcol, bptr[u], bptr[u + 1], (int32_t)v);
-            if (p < 0) atomicOr(status, 2);
-            else twin[p] = (uint32_t)q;
+            if (p < 0) {
+                atomicOr(status, 2);
+            } else {
+                twin[p] = (uint32_t)q;
+                ltwin[q] = (uint32_t)p;
+            }
         }
     }
 }
 void launch_twin(int32_t n, const uint32_t *bptr, const int32_t *bcol, const uint32_t *lptr,
-                 const int32_t *lcol, uint32_t *twin, int32_t *status, hipStream_t s) {
+                 const int32_t *lcol, uint32_t *twin, uint32_t *ltwin, int32_t *status, hipStream_t s) {
     hipLaunchKernelGGL(k_twin, dim3(grid_for((int64_t)n * WAVE, BLOCK, 1 << 20)), dim3(BLOCK), 0, s,
-                       n, bptr, bcol, lptr, lcol, twin, status);
+                       n, bptr, bcol, lptr, lcol, twin, ltwin, status);
 }
 
 // Non-empty-row index of the upper-half store (used by the sweep).

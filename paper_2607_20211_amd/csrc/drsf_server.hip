@@ -55,6 +55,7 @@ struct Tenant {
     int32_t id = 0;
     TState state = T_WAITING;
     uint64_t t_arrive = 0;
+    uint64_t t_live = 0;  // admitted (context created)
     // host copy of the graph until admission
     int32_t n = 0;
     std::vector<int64_t> row_ptr;
@@ -91,8 +92,9 @@ struct drsf_server {
     bool started = false, stop = false;
     std::thread th;
     std::string err;
-    // statistics of completed requests
-    std::vector<double> lat_ms;
+    // statistics of completed requests: latency from arrival, and from the
+    // later of arrival and the tenant's admission (service latency)
+    std::vector<double> lat_ms, svc_ms;
     int64_t updates = 0;
     uint64_t first_arrive = ~0ull, last_done = 0;
 };
@@ -110,6 +112,8 @@ void complete(drsf_server *s, Req &r, int status, uint64_t t) {
     r.done = true;
     s->outstanding--;
     s->lat_ms.push_back((double)(r.t_done - r.t_arrive) * 1e-6);
+    const uint64_t ready = std::max(r.t_arrive, s->tenants[r.tenant].t_live);
+    s->svc_ms.push_back((double)(r.t_done - std::min(ready, r.t_done)) * 1e-6);
     if (status == DRSF_OK) s->updates += (int64_t)(r.edges.size() / 2);
     s->first_arrive = std::min(s->first_arrive, r.t_arrive);
     s->last_done = std::max(s->last_done, r.t_done);
@@ -195,6 +199,7 @@ void scheduler(drsf_server *s) {
                 continue;
             }
             tn.state = T_LIVE;
+            tn.t_live = now_ns() - s->t0;
             tn.row_ptr.clear(); tn.row_ptr.shrink_to_fit();
             tn.col.clear(); tn.col.shrink_to_fit();
             tn.parent.clear(); tn.parent.shrink_to_fit();
@@ -390,6 +395,25 @@ int drsf_server_start(drsf_server *s) {
     if (!s) return DRSF_E_ARG;
     std::lock_guard<std::mutex> g(s->mu);
     if (s->started) return sfail(s, DRSF_E_STATE, "already started");
+    // graphs present from the start are made resident before the clock runs
+    for (Tenant &tn : s->tenants) {
+        if (tn.t_arrive != 0 || tn.state != T_WAITING) continue;
+        if (s->used + tn.estimate > s->budget && s->used > 0) break;
+        const int rc = admit_one(s, tn);
+        if (rc != DRSF_OK) {
+            destroy_tenant(tn);
+            tn.state = T_FAILED;
+        } else {
+            tn.state = T_LIVE;
+            tn.row_ptr.clear(); tn.row_ptr.shrink_to_fit();
+            tn.col.clear(); tn.col.shrink_to_fit();
+            tn.parent.clear(); tn.parent.shrink_to_fit();
+            s->used += tn.bytes;
+            s->peak_used = std::max(s->peak_used, s->used);
+        }
+        for (auto it = s->future_admits.begin(); it != s->future_admits.end(); ++it)
+            if (it->second == tn.id) { s->future_admits.erase(it); break; }
+    }
     s->t0 = now_ns();
     s->started = true;
     s->th = std::thread(scheduler, s);
@@ -441,6 +465,10 @@ int drsf_server_stats(drsf_server *s, double *out) {
     out[3] = span > 0 ? (double)s->updates / span : 0.0;
     out[4] = (double)s->peak_used;
     out[5] = (double)s->budget;
+    l = s->svc_ms;
+    std::sort(l.begin(), l.end());
+    out[6] = q(0.5);
+    out[7] = q(0.99);
     return DRSF_OK;
 }
 

@@ -20,8 +20,8 @@ DRSF_OK, DRSF_E_ARG, DRSF_E_NOMEM, DRSF_E_FOREST = 0, -1, -2, -3
 DRSF_E_BATCH, DRSF_E_CAPACITY, DRSF_E_DEVICE, DRSF_E_STATE = -4, -5, -6, -7
 DRSF_E_BUDGET = -8
 DRSF_SERVER_DIGESTS, DRSF_SERVER_SERIAL = 1, 2
-PHASES = ("validate", "update_graph", "root_finding", "key_edge_sweep",
-          "key_edge_sweep_inserted", "replacement_edges", "superforest_rooting",
+PHASES = ("validate", "update_graph", "root_init", "root_chase", "orphan_list", "orphan_scan",
+          "store_sweep", "batch_and_inserted_scan", "replacement_edges", "superforest_rooting",
           "path_reversal", "labels")
 
 
@@ -45,7 +45,10 @@ class drsf_view(ctypes.Structure):
                 ("num_key_cross", ctypes.c_int64),
                 ("num_replacement", ctypes.c_int64),
                 ("num_pieces", ctypes.c_int64),
-                ("num_paths", ctypes.c_int64)]
+                ("num_paths", ctypes.c_int64),
+                ("num_orphans", ctypes.c_int64),
+                ("orphan_slots", ctypes.c_int64),
+                ("scan_orphans", ctypes.c_int32)]
 
 
 class DrsfError(RuntimeError):
@@ -366,7 +369,8 @@ class Forest:
     def _stats(v: drsf_view) -> dict:
         return {"num_edges": v.num_edges, "num_key_cross": v.num_key_cross,
                 "num_replacement": v.num_replacement, "num_pieces": v.num_pieces,
-                "num_paths": v.num_paths}
+                "num_paths": v.num_paths, "num_orphans": v.num_orphans,
+                "orphan_slots": v.orphan_slots, "scan_orphans": v.scan_orphans}
 
     def parent(self) -> np.ndarray:
         p = np.empty(self.n, dtype=np.int32)
@@ -519,10 +523,11 @@ class Server:
                 "digest": (int(dg[0]), int(dg[1]))}
 
     def stats(self) -> dict:
-        out = np.zeros(6, dtype=np.float64)
+        out = np.zeros(8, dtype=np.float64)
         _scheck(load().drsf_server_stats(self.srv, out.ctypes.data), self.srv)
         return {"completed": int(out[0]), "p50_ms": float(out[1]), "p99_ms": float(out[2]),
-                "updates_per_s": float(out[3]), "peak_bytes": int(out[4]), "budget": int(out[5])}
+                "updates_per_s": float(out[3]), "peak_bytes": int(out[4]), "budget": int(out[5]),
+                "service_p50_ms": float(out[6]), "service_p99_ms": float(out[7])}
 
     def tenant_state(self, tenant: int) -> int:
         return int(load().drsf_server_tenant_state(self.srv, tenant))
