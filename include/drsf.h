@@ -76,8 +76,11 @@ typedef struct {
                                 event between phases (drsf_phase_times) instead of
                                 replaying the captured update graph */
     int64_t max_batch;       /* largest batch accepted by apply; 0 = 1 << 20 */
-    int64_t delta_capacity;  /* inserted edges held before the edge store is
-                                rebuilt; 0 = automatic */
+    int64_t delta_capacity;  /* inserted edges held in the inserted-edge list; an
+                                insert that would overflow it first merges the list
+                                into the base store (and drops deleted entries):
+                                O(|E|) work, amortised over the list; 0 = automatic
+                                (max(4 max_batch, |E| / 8, 2^20)) */
     int sweep_mode;          /* delete key-edge scan: 0 (default) per batch, the
                                 orphans' adjacency when it is at most half the
                                 store, else the whole store; 1: always the whole
@@ -235,7 +238,9 @@ int drsf_get_view(drsf_ctx *ctx, drsf_view *out);
 int64_t drsf_num_edges(drsf_ctx *ctx);
 int drsf_export_edges(drsf_ctx *ctx, uint64_t *keys_host, int64_t capacity, int64_t *m_out);
 
-/* Device-side copy of the whole state; restore returns to it exactly. */
+/* Device-side copy of the whole state; restore returns to it exactly.  A
+ * snapshot taken before a store rebuild cannot be restored after it
+ * (DRSF_E_STATE). */
 typedef struct drsf_snapshot drsf_snapshot;
 int drsf_snapshot_take(drsf_ctx *ctx, drsf_snapshot **out);
 int drsf_snapshot_restore(drsf_ctx *ctx, const drsf_snapshot *snap);

@@ -47,7 +47,7 @@ int ceil_log2(int64_t x) {
 
 struct drsf_snapshot {
     int32_t n = 0;
-    int64_t eb = 0, dcap = 0, ndelta_bound = 0, m_live = 0;
+    int64_t eb = 0, dcap = 0, ndelta_bound = 0, m_live = 0, rebuilds = 0;
     uint64_t dhmask = 0;
     unsigned long long ndelta = 0;
     std::vector<int64_t> gm;
@@ -157,6 +157,7 @@ struct drsf_ctx {
     std::vector<void *> allocs;
     std::vector<size_t> alloc_bytes;
     int64_t bytes = 0, peak_bytes = 0;  // device bytes held now / at most
+    int64_t rebuilds = 0;               // store rebuilds so far
 };
 
 namespace {
@@ -264,6 +265,33 @@ int read_status(drsf_ctx *c, int32_t *st) {
     return DRSF_OK;
 }
 
+// Arrays sized by the base store's tiles: cross-edge regions (base-store
+// tiles, inserted-edge tiles, batch regions), orphan-scan ranges and, with
+// several graphs, the block and tile lists.  Called again after a rebuild.
+int alloc_tiles(drsf_ctx *c) {
+    int rc;
+    dfree(c, c->x0); dfree(c, c->x1); dfree(c, c->rcnt); dfree(c, c->rstart); dfree(c, c->xcnt);
+    dfree(c, c->lists);
+    if (c->h_lists) (void)hipHostFree(c->h_lists);
+    c->h_lists = nullptr;
+    const int64_t nregmax = c->ntiles + c->dtmax + insert_regions(c->max_batch);
+    c->xcap = nregmax * TILE;
+    if ((rc = dalloc(c, &c->x0, c->xcap))) return rc;
+    if ((rc = dalloc(c, &c->x1, c->xcap))) return rc;
+    if ((rc = dalloc(c, &c->rcnt, nregmax))) return rc;
+    if ((rc = dalloc(c, &c->rstart, c->ntiles + 1))) return rc;
+    if ((rc = dalloc(c, &c->xcnt, c->ntiles + 1))) return rc;
+    launch_fill_u64(c->rcnt, nregmax, 0, c->stream);
+    if (c->ngraph > 1) {
+        // every vertex block and every tile appears at most once per list
+        c->nvblk = (c->n + BLOCK - 1) / BLOCK;
+        const int64_t nl = 2 * c->nvblk + c->ntiles + 1;
+        if ((rc = dalloc(c, &c->lists, nl))) return rc;
+        if ((rc = halloc(c, &c->h_lists, nl))) return rc;
+    }
+    return DRSF_OK;
+}
+
 int alloc_state(drsf_ctx *c) {
     int rc;
     const int32_t n = c->n;
@@ -306,12 +334,7 @@ int alloc_state(drsf_ctx *c) {
     c->dhmask = dh - 1;
     if ((rc = dalloc(c, &c->dhash, (int64_t)dh))) return rc;
     if ((rc = dalloc(c, &c->dhpos, (int64_t)dh))) return rc;
-    // x0 regions: base-store tiles, inserted-edge tiles, then batch regions
-    const int64_t nregmax = c->ntiles + c->dtmax + insert_regions(mb);
-    c->xcap = nregmax * TILE;
-    if ((rc = dalloc(c, &c->x0, c->xcap))) return rc;
-    if ((rc = dalloc(c, &c->x1, c->xcap))) return rc;
-    if ((rc = dalloc(c, &c->rcnt, nregmax))) return rc;
+    if ((rc = alloc_tiles(c))) return rc;
     c->ercap = c->pcap;
     if ((rc = dalloc(c, &c->er, c->ercap))) return rc;
     if ((rc = dalloc(c, &c->arc_nxt, 2 * c->ercap))) return rc;
@@ -332,17 +355,8 @@ int alloc_state(drsf_ctx *c) {
     if ((rc = dalloc(c, &c->gpre, (c->nvb + BLOCK - 1) / BLOCK))) return rc;
     if ((rc = dalloc(c, &c->olist, n))) return rc;
     if ((rc = dalloc(c, &c->ostage, c->nvb * BLOCK))) return rc;
-    if ((rc = dalloc(c, &c->rstart, c->ntiles + 1))) return rc;
-    if ((rc = dalloc(c, &c->xcnt, c->ntiles + 1))) return rc;
     launch_fill_u64(reinterpret_cast<uint64_t *>(c->bvol), c->nvb, 0, s);
     launch_fill_i32(c->bcnt, c->nvb, 0, s);
-    if (c->ngraph > 1) {
-        // every vertex block and every tile appears at most once per list
-        c->nvblk = (n + BLOCK - 1) / BLOCK;
-        const int64_t nl = 2 * c->nvblk + c->ntiles + 1;
-        if ((rc = dalloc(c, &c->lists, nl))) return rc;
-        if ((rc = halloc(c, &c->h_lists, nl))) return rc;
-    }
     if ((rc = halloc(c, &c->h_edges, 2 * mb))) return rc;
     if ((rc = halloc(c, &c->h_bop, mb))) return rc;
     if ((rc = halloc(c, &c->h_bgid, mb))) return rc;
@@ -351,7 +365,6 @@ int alloc_state(drsf_ctx *c) {
     launch_fill_u64(c->bhash, (int64_t)bh, HASH_EMPTY, s);
     launch_fill_u64(c->dhash, (int64_t)dh, HASH_EMPTY, s);
     launch_fill_u64(c->obits, (n + 63) / 64, 0, s);
-    launch_fill_u64(c->rcnt, nregmax, 0, s);
     return DRSF_OK;
 }
 
@@ -374,11 +387,10 @@ void destroy_ctx(drsf_ctx *c) {
 }
 
 // Builds the device edge store from a symmetric CSR with ascending rows.
-int build_store(drsf_ctx *c, const int64_t *row_ptr_in, const int32_t *col_in, int64_t nnz) {
+int build_store(drsf_ctx *c, const int64_t *row_ptr_in, const int32_t *col_in, int64_t nnz, bool dev_in) {
     int rc;
     const int32_t n = c->n;
     hipStream_t s = c->stream;
-    const bool dev_in = c->opts.inputs_on_device != 0;
     int64_t *drow = nullptr;
     int32_t *dcol = nullptr;
     if (dev_in) {
@@ -507,6 +519,86 @@ int canonicalise_forest(drsf_ctx *c) {
     return DRSF_OK;
 }
 
+
+// Merges the inserted-edge list into the base store and drops deleted
+// entries: the live edges become one symmetric CSR (rows of live base
+// entries merged with the sorted inserted pairs), from which the store is
+// built as at create.  The forest is untouched.  Captured update graphs
+// hold the old arrays and are dropped.
+int rebuild_store(drsf_ctx *c) {
+    int rc;
+    hipStream_t s = c->stream;
+    const int32_t n = c->n;
+    HIPCHK(c, hipStreamSynchronize(s));
+    HIPCHK(c, hipMemcpy(c->h_ret, c->cnt + C_NDELTA, sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    const int64_t nd = (int64_t)c->h_ret[0];
+    const int64_t pcap2 = 2 * nd + 2;
+    uint64_t *pairs = nullptr, *sorted = nullptr;
+    unsigned long long *npairs = nullptr, *dtot = nullptr;
+    uint32_t *ddeg = nullptr, *dstart = nullptr, *bdeg = nullptr, *rowp32 = nullptr;
+    char *stmp = nullptr, *ctmp = nullptr;
+    int64_t *rowp = nullptr;
+    int32_t *col = nullptr;
+    const size_t sbytes = sort_u64_tmp_bytes(pcap2) + 256;
+    if ((rc = dalloc(c, &pairs, pcap2)) || (rc = dalloc(c, &sorted, pcap2)) || (rc = dalloc(c, &npairs, 2)) ||
+        (rc = dalloc(c, &stmp, (int64_t)sbytes)) || (rc = dalloc(c, &ddeg, n)) ||
+        (rc = dalloc(c, &dstart, (int64_t)n + 1)) || (rc = dalloc(c, &bdeg, n)) ||
+        (rc = dalloc(c, &rowp32, (int64_t)n + 1)) || (rc = dalloc(c, &rowp, (int64_t)n + 1)) ||
+        (rc = dalloc(c, &ctmp, (int64_t)scan_tmp_bytes(n) + 64)))
+        return rc;
+    dtot = npairs + 1;
+    launch_fill_u64(npairs, 2, 0, s);
+    launch_rb_pairs(c->dkey, c->cnt + C_NDELTA, pairs, npairs, pcap2, s);
+    HIPCHK(c, hipMemcpyAsync(c->h_ret, npairs, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    const int64_t np = (int64_t)c->h_ret[0];
+    if (np > 0 && launch_sort_u64(pairs, sorted, np, stmp, sbytes, s) != 0)
+        return fail(c, DRSF_E_DEVICE, "sort failed during the store rebuild");
+    launch_fill_i32(reinterpret_cast<int32_t *>(ddeg), n, 0, s);
+    launch_rb_pair_deg(sorted, npairs, ddeg, pcap2, s);
+    launch_scan_u32(ddeg, dstart, dtot, n, ctmp, s);
+    launch_rb_counts(n, c->bptr, c->bcol, c->lptr, c->lcol, bdeg, s);
+    launch_add_u32(bdeg, ddeg, bdeg, n, s);
+    launch_scan_u32(bdeg, rowp32, dtot, n, ctmp, s);
+    HIPCHK(c, hipMemcpyAsync(c->h_ret, dtot, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    const int64_t nnz = (int64_t)c->h_ret[0];
+    if (nnz != 2 * c->m_live)
+        return fail(c, DRSF_E_DEVICE, "store rebuild counted %lld entries, expected %lld", (long long)nnz,
+                    (long long)(2 * c->m_live));
+    if ((rc = dalloc(c, &col, nnz))) return rc;
+    launch_u32_to_i64(rowp32, rowp, (int64_t)n + 1, s);
+    launch_rb_fill(n, c->bptr, c->bcol, c->lptr, c->lcol, sorted, dstart, ddeg, rowp, col, s);
+    HIPCHK(c, hipStreamSynchronize(s));
+    for (void *p : {(void *)pairs, (void *)sorted, (void *)npairs, (void *)stmp, (void *)ddeg, (void *)dstart,
+                    (void *)bdeg, (void *)rowp32, (void *)ctmp})
+        dfree(c, p);
+    for (void *p : {(void *)c->bptr, (void *)c->bcol, (void *)c->lptr, (void *)c->lcol, (void *)c->twin,
+                    (void *)c->ltwin, (void *)c->zrow, (void *)c->zptr, (void *)c->tile_k})
+        dfree(c, p);
+    c->bptr = c->lptr = nullptr;
+    c->bcol = c->lcol = c->zrow = c->tile_k = nullptr;
+    c->twin = c->ltwin = c->zptr = nullptr;
+    const int64_t old_tiles = c->ntiles;
+    rc = build_store(c, rowp, col, nnz, true);
+    dfree(c, rowp);
+    dfree(c, col);
+    if (rc) return rc;
+    if (c->ntiles > old_tiles && (rc = alloc_tiles(c))) return rc;
+    // empty inserted-edge list
+    launch_fill_u64(c->cnt + C_NDELTA, 1, 0, s);
+    launch_fill_u64(c->dhash, (int64_t)c->dhmask + 1, HASH_EMPTY, s);
+    c->ndelta_bound = 0;
+    c->rebuilds++;
+    HIPCHK(c, hipStreamSynchronize(s));
+    for (int k = 0; k < 4; k++) {
+        if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+        if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+        c->gexec[k] = nullptr;
+        c->graph[k] = nullptr;
+    }
+    return DRSF_OK;
+}
 
 // The update sequence (see the file comment) for batches with inserts
 // (kind bit 1) and/or deletes (kind bit 2); with events when profiling.
@@ -787,7 +879,7 @@ static int create_impl(int32_t G, const int32_t *n_off, int32_t n, const int64_t
         fail(c, DRSF_E_ARG, "col is NULL");
         return bail(DRSF_E_ARG);
     }
-    if ((rc = build_store(c, row_ptr, col, nnz))) return bail(rc);
+    if ((rc = build_store(c, row_ptr, col, nnz, c->opts.inputs_on_device != 0))) return bail(rc);
     if ((rc = dalloc(c, &c->parent, n))) return bail(rc);
     if (hipMemcpyAsync(c->parent, parent, sizeof(int32_t) * (size_t)n,
                        c->opts.inputs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
@@ -904,9 +996,12 @@ int drsf_apply_async(drsf_ctx *c, const int32_t *edges, int64_t b, int op) {
         c->view.scan_orphans = 0;
         return DRSF_OK;
     }
-    if (op == DRSF_INSERT && c->ndelta_bound + b > c->dcap)
-        return fail(c, DRSF_E_CAPACITY, "inserted-edge store full (%lld of %lld)",
-                    (long long)c->ndelta_bound, (long long)c->dcap);
+    if (op == DRSF_INSERT && c->ndelta_bound + b > c->dcap) {
+        if (b > c->dcap)
+            return fail(c, DRSF_E_CAPACITY, "batch of %lld inserts exceeds delta_capacity %lld",
+                        (long long)b, (long long)c->dcap);
+        if ((rc = rebuild_store(c))) return rc;
+    }
     if ((rc = stage_edges(c, edges, b))) return rc;
     c->last_b = b;
     c->last_op = op;
@@ -942,9 +1037,12 @@ int drsf_multi_apply_async(drsf_ctx *c, const int32_t *edges, const int64_t *b_o
     int64_t nins = 0;
     for (int32_t g = 0; g < G; g++)
         if (op[g] == DRSF_INSERT) nins += b_off[g + 1] - b_off[g];
-    if (c->ndelta_bound + nins > c->dcap)
-        return fail(c, DRSF_E_CAPACITY, "inserted-edge store full (%lld of %lld)",
-                    (long long)c->ndelta_bound, (long long)c->dcap);
+    if (c->ndelta_bound + nins > c->dcap) {
+        if (nins > c->dcap)
+            return fail(c, DRSF_E_CAPACITY, "batch of %lld inserts exceeds delta_capacity %lld",
+                        (long long)nins, (long long)c->dcap);
+        if ((rc = rebuild_store(c))) return rc;
+    }
     c->have_phases = false;
     c->multi_last = true;
     c->last_b = b;
@@ -1176,7 +1274,7 @@ int drsf_snapshot_take(drsf_ctx *c, drsf_snapshot **out) {
     if (rc) return rc;
     drsf_snapshot *s = new drsf_snapshot();
     s->n = c->n; s->eb = c->eb; s->dcap = c->dcap; s->dhmask = c->dhmask;
-    s->ndelta_bound = c->ndelta_bound; s->m_live = c->m_live;
+    s->ndelta_bound = c->ndelta_bound; s->m_live = c->m_live; s->rebuilds = c->rebuilds;
     s->gm = c->gm_h;
     const size_t dh = (size_t)c->dhmask + 1;
     const bool ok = hipMalloc(&s->parent, 4 * (size_t)c->n) == hipSuccess &&
@@ -1211,8 +1309,9 @@ int drsf_snapshot_restore(drsf_ctx *c, const drsf_snapshot *s) {
     int rc = finish_pending(c);
     if (rc) return rc;
     if (s->n != c->n || s->eb != c->eb || s->dcap != c->dcap || s->dhmask != c->dhmask ||
-        s->gm.size() != c->gm_h.size())
-        return fail(c, DRSF_E_STATE, "snapshot does not match the context's layout");
+        s->gm.size() != c->gm_h.size() || s->rebuilds != c->rebuilds)
+        return fail(c, DRSF_E_STATE, "snapshot does not match the context's layout (taken before a "
+                                     "store rebuild?)");
     hipStream_t st = c->stream;
     const size_t dh = (size_t)c->dhmask + 1;
     HIPCHK(c, hipMemcpyAsync(c->parent, s->parent, 4 * (size_t)c->n, hipMemcpyDeviceToDevice, st));

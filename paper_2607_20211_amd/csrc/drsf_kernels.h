@@ -176,6 +176,24 @@ void launch_reverse(const Dev &d, hipStream_t s);
 void launch_labels(const Dev &d, bool ins, bool del, hipStream_t s);
 void launch_cleanup(const Dev &d, hipStream_t s);
 
+// store rebuild: live degrees of the base store, the inserted edges as
+// directed pairs (x << 32 | y, both directions), their per-row counts, and
+// the merged symmetric CSR
+void launch_rb_counts(int32_t n, const uint32_t *bptr, const int32_t *bcol, const uint32_t *lptr,
+                      const int32_t *lcol, uint32_t *deg, hipStream_t s);
+void launch_rb_pairs(const uint64_t *dkey, const unsigned long long *ndelta, uint64_t *pairs,
+                     unsigned long long *npairs, int64_t cap, hipStream_t s);
+void launch_rb_pair_deg(const uint64_t *pairs, const unsigned long long *npairs, uint32_t *ddeg,
+                        int64_t cap, hipStream_t s);
+void launch_add_u32(const uint32_t *a, const uint32_t *b, uint32_t *out, int64_t count, hipStream_t s);
+void launch_u32_to_i64(const uint32_t *in, int64_t *out, int64_t count, hipStream_t s);
+void launch_rb_fill(int32_t n, const uint32_t *bptr, const int32_t *bcol, const uint32_t *lptr,
+                    const int32_t *lcol, const uint64_t *pairs, const uint32_t *dstart,
+                    const uint32_t *ddeg, const int64_t *row_ptr, int32_t *col, hipStream_t s);
+size_t sort_u64_tmp_bytes(int64_t count);
+int launch_sort_u64(const uint64_t *in, uint64_t *out, int64_t count, void *tmp, size_t tmp_bytes,
+                    hipStream_t s);
+
 // digests of parent and label (out: two device words)
 void launch_digest(int32_t n, const int32_t *parent, const int32_t *label, unsigned long long *out,
                    hipStream_t s);

@@ -1578,6 +1578,123 @@ void launch_cleanup(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_cleanup_counters, dim3(1), dim3(256), 0, s, d);
 }
 
+// ------------------------------------------------------ store rebuild
+
+// live entries of each row (upper and lower halves), one wave per row
+__global__ __launch_bounds__(BLOCK) void k_rb_counts(int32_t n, const uint32_t *bptr, const int32_t *bcol,
+                                                     const uint32_t *lptr, const int32_t *lcol,
+                                                     uint32_t *deg) {
+    const int64_t nw = (int64_t)gridDim.x * (BLOCK / WAVE);
+    const int lane = lane_id();
+    for (int64_t u = (int64_t)blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE; u < n; u += nw) {
+        uint32_t c = 0;
+        for (int64_t j = (int64_t)bptr[u] + lane; j < (int64_t)bptr[u + 1]; j += WAVE) c += bcol[j] >= 0;
+        for (int64_t j = (int64_t)lptr[u] + lane; j < (int64_t)lptr[u + 1]; j += WAVE) c += lcol[j] >= 0;
+        for (int o = WAVE / 2; o > 0; o >>= 1) c += __shfl_xor(c, o);
+        if (lane == 0) deg[u] = c;
+    }
+}
+void launch_rb_counts(int32_t n, const uint32_t *bptr, const int32_t *bcol, const uint32_t *lptr,
+                      const int32_t *lcol, uint32_t *deg, hipStream_t s) {
+    hipLaunchKernelGGL(k_rb_counts, dim3(grid_for((int64_t)n * WAVE, BLOCK, 1 << 20)), dim3(BLOCK), 0, s,
+                       n, bptr, bcol, lptr, lcol, deg);
+}
+
+// live inserted edges as directed pairs in both directions
+__global__ __launch_bounds__(BLOCK) void k_rb_pairs(const uint64_t *dkey, const unsigned long long *ndelta,
+                                                    uint64_t *pairs, unsigned long long *npairs,
+                                                    int64_t cap) {
+    const int64_t nd = (int64_t)*ndelta;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < nd; base += stride) {
+        const int64_t i = base + threadIdx.x;
+        const uint64_t k = i < nd ? dkey[i] : KEY_DEAD;
+        const bool live = k != KEY_DEAD;
+        const int64_t pos = block_append(live ? 2 : 0, npairs);
+        if (live && pos + 1 < cap) {
+            const uint64_t lo = k >> 32, hi = k & 0xffffffffull;
+            pairs[pos] = k;
+            pairs[pos + 1] = (hi << 32) | lo;
+        }
+    }
+}
+void launch_rb_pairs(const uint64_t *dkey, const unsigned long long *ndelta, uint64_t *pairs,
+                     unsigned long long *npairs, int64_t cap, hipStream_t s) {
+    hipLaunchKernelGGL(k_rb_pairs, dim3(grid_for(cap / 2 + 1, BLOCK, 4096)), dim3(BLOCK), 0, s, dkey, ndelta,
+                       pairs, npairs, cap);
+}
+__global__ void k_rb_pair_deg(const uint64_t *pairs, const unsigned long long *npairs, uint32_t *ddeg,
+                              int64_t cap) {
+    const int64_t np = (int64_t)*npairs < cap ? (int64_t)*npairs : cap;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += stride)
+        atomicAdd(&ddeg[pairs[i] >> 32], 1u);
+}
+void launch_rb_pair_deg(const uint64_t *pairs, const unsigned long long *npairs, uint32_t *ddeg,
+                        int64_t cap, hipStream_t s) {
+    hipLaunchKernelGGL(k_rb_pair_deg, dim3(grid_for(cap, BLOCK, 4096)), dim3(BLOCK), 0, s, pairs, npairs,
+                       ddeg, cap);
+}
+__global__ void k_add_u32(const uint32_t *a, const uint32_t *b, uint32_t *out, int64_t count) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+        out[i] = a[i] + b[i];
+}
+void launch_add_u32(const uint32_t *a, const uint32_t *b, uint32_t *out, int64_t count, hipStream_t s) {
+    hipLaunchKernelGGL(k_add_u32, dim3(grid_for(count, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, a, b, out, count);
+}
+__global__ void k_u32_to_i64(const uint32_t *in, int64_t *out, int64_t count) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+        out[i] = (int64_t)in[i];
+}
+void launch_u32_to_i64(const uint32_t *in, int64_t *out, int64_t count, hipStream_t s) {
+    hipLaunchKernelGGL(k_u32_to_i64, dim3(grid_for(count, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, in, out, count);
+}
+
+// Row u of the merged symmetric CSR: its live lower entries, then its live
+// upper entries (together ascending), merged with its inserted neighbours
+// (ascending in the sorted pairs).  One thread per row.
+__global__ void k_rb_fill(int32_t n, const uint32_t *bptr, const int32_t *bcol, const uint32_t *lptr,
+                          const int32_t *lcol, const uint64_t *pairs, const uint32_t *dstart,
+                          const uint32_t *ddeg, const int64_t *row_ptr, int32_t *col) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
+        int64_t w = row_ptr[u];
+        uint64_t a = lptr[u];
+        const uint64_t ae = lptr[u + 1], bs = bptr[u], be = bptr[u + 1];
+        uint64_t b = bs;
+        uint64_t q = dstart[u];
+        const uint64_t qe = q + ddeg[u];
+        while (true) {
+            // next live base entry (lower run first, then upper run)
+            int32_t x = -1;
+            while (a < ae && lcol[a] < 0) a++;
+            if (a < ae) {
+                x = lcol[a];
+            } else {
+                while (b < be && bcol[b] < 0) b++;
+                if (b < be) x = bcol[b];
+            }
+            const int32_t y = q < qe ? (int32_t)(uint32_t)pairs[q] : -1;
+            if (x < 0 && y < 0) break;
+            if (y < 0 || (x >= 0 && x < y)) {
+                col[w++] = x;
+                if (a < ae) a++; else b++;
+            } else {
+                col[w++] = y;
+                q++;
+            }
+        }
+    }
+}
+void launch_rb_fill(int32_t n, const uint32_t *bptr, const int32_t *bcol, const uint32_t *lptr,
+                    const int32_t *lcol, const uint64_t *pairs, const uint32_t *dstart,
+                    const uint32_t *ddeg, const int64_t *row_ptr, int32_t *col, hipStream_t s) {
+    hipLaunchKernelGGL(k_rb_fill, dim3(grid_for(n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, n, bptr, bcol, lptr,
+                       lcol, pairs, dstart, ddeg, row_ptr, col);
+}
+
 // ------------------------------------------------------------ digests
 
 // Order-independent 64-bit digests of parent and label: wrap-around sums of

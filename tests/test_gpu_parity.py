@@ -403,3 +403,23 @@ def test_launch_schedule_does_not_change_results(tuning):
                                 gen.seed(6, step, gen.P_DELETE))[0]
         pair.step(dl, drsf.DRSF_DELETE, f"tuning {tuning} delete {step}")
     pair.gpu.close()
+
+
+def test_store_rebuild_when_inserted_list_fills():
+    """A small inserted-edge list: inserts overflow it every few batches, the
+    list is merged into the base store, and updates go on bit-exact (deletes
+    of merged edges included)."""
+    drsf = _lib()
+    _case("store rebuild")
+    n = 20000
+    g = gen.make_graph("rb", n, gen.gnm(n, 30000, gen.seed(7, 0, gen.P_GRAPH)))
+    pair = Pair(g, max_batch=4096, delta_capacity=5000)
+    for step in range(6):
+        ins = gen.insert_batches(n, pair.keys, 1, 3000, gen.seed(7, step, gen.P_INSERT))[0]
+        pair.step(ins, drsf.DRSF_INSERT, f"rebuild insert {step}")
+        trees = int((pair.parent != np.arange(n)).sum())
+        dl = gen.delete_batches(n, pair.keys, pair.parent, 1, 2000, min(1000, trees),
+                                gen.seed(7, step, gen.P_DELETE))[0]
+        pair.step(dl, drsf.DRSF_DELETE, f"rebuild delete {step}")
+        assert np.array_equal(pair.gpu.edges(), pair.keys)
+    pair.gpu.close()
