@@ -179,6 +179,88 @@ def run_served(scale, nreq, loads, log):
             "loads": out}
 
 
+def time_op(f, snap, batch, op, reps, drsf):
+    """Median seconds of one apply of `batch` from the snapshot's state."""
+    ts = []
+    for _ in range(reps):
+        f.restore(snap)
+        t0 = time.perf_counter()
+        f.apply(batch, op)
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def run_configs(g, dev, stream, log, reps=3):
+    """Per-op rates from the initial state: R-MAT 22 at b = 1e4, 1e5, 1e6
+    (inserts of uniform non-edges; deletes half tree edges), and the deep
+    4096 x 4096 grid (5% of edges removed): 1e5 tree-edge deletes, then 1e5
+    inserts of uniform vertex pairs that are not edges."""
+    import torch
+    import gen
+    from paper_2607_20211_amd import drsf
+    out = {}
+    d_row = torch.from_numpy(g.row_ptr).to(dev)
+    d_col = torch.from_numpy(g.col).to(dev)
+    d_par = torch.from_numpy(g.parent).to(dev)
+    f = drsf.Forest(g.n, d_row, d_col, d_par, max_batch=1_000_000, stream=stream.cuda_stream,
+                    inputs_on_device=True, delta_capacity=4_000_000)
+    del d_row, d_col, d_par
+    snap = f.snapshot()
+    sweep = []
+    for b in (10_000, 100_000, 1_000_000):
+        ins = torch.from_numpy(gen.insert_batches(g.n, g.keys, 1, b, gen.seed(2, 1, gen.P_INSERT))[0]).to(dev)
+        dl = torch.from_numpy(gen.delete_batches(g.n, g.keys, g.parent, 1, b, b // 2,
+                                                 gen.seed(2, 1, gen.P_DELETE))[0]).to(dev)
+        f.apply(ins, drsf.DRSF_INSERT)  # warm (captures the graphs)
+        f.restore(snap)
+        f.apply(dl, drsf.DRSF_DELETE)
+        ti = time_op(f, snap, ins, drsf.DRSF_INSERT, reps, drsf)
+        td = time_op(f, snap, dl, drsf.DRSF_DELETE, reps, drsf)
+        sweep.append({"batch": b, "insert_updates_per_s": round(b / ti, 1),
+                      "delete_updates_per_s": round(b / td, 1),
+                      "insert_ms": round(ti * 1e3, 4), "delete_ms": round(td * 1e3, 4)})
+        log(f"rmat22 b={b}: insert {ti * 1e3:.3f} ms, delete {td * 1e3:.3f} ms")
+    drsf.drsf_snapshot_free(snap)
+    f.close()
+    out["rmat22_from_initial_state"] = sweep
+    # deep trees
+    t0 = time.time()
+    side = 4096
+    total = side * (side - 1) * 2
+    keys = gen.grid(side, side, total // 20, gen.seed(3, 0, gen.P_GRAPH))
+    gg = gen.make_graph("grid4096", side * side, keys)
+    trees = int((gg.parent != np.arange(gg.n)).sum())
+    dl = gen.delete_batches(gg.n, gg.keys, gg.parent, 1, 100_000, 100_000, gen.seed(3, 0, gen.P_DELETE))[0]
+    ins = gen.insert_batches(gg.n, gg.keys, 1, 100_000, gen.seed(3, 0, gen.P_INSERT))[0]
+    log(f"grid {side}x{side}: n={gg.n} m={gg.m} tree edges {trees} ({time.time() - t0:.1f}s)")
+    f = drsf.Forest(gg.n, torch.from_numpy(gg.row_ptr).to(dev), torch.from_numpy(gg.col).to(dev),
+                    torch.from_numpy(gg.parent).to(dev), max_batch=100_000, stream=stream.cuda_stream,
+                    inputs_on_device=True)
+    d_dl, d_ins = torch.from_numpy(dl).to(dev), torch.from_numpy(ins).to(dev)
+    snap = f.snapshot()
+    f.apply(d_dl, drsf.DRSF_DELETE)
+    f.apply(d_ins, drsf.DRSF_INSERT)
+    td, ti = [], []
+    for _ in range(reps):
+        f.restore(snap)
+        t1 = time.perf_counter()
+        st_d = f.apply(d_dl, drsf.DRSF_DELETE)
+        t2 = time.perf_counter()
+        st_i = f.apply(d_ins, drsf.DRSF_INSERT)
+        t3 = time.perf_counter()
+        td.append(t2 - t1)
+        ti.append(t3 - t2)
+    drsf.drsf_snapshot_free(snap)
+    f.close()
+    td, ti = float(np.median(td)), float(np.median(ti))
+    log(f"grid: delete {td * 1e3:.3f} ms, insert {ti * 1e3:.3f} ms")
+    out["grid4096_deep"] = {"n": gg.n, "m": gg.m, "delete_tree_edges": 100_000, "insert_pairs": 100_000,
+                            "delete_updates_per_s": round(1e5 / td, 1), "delete_ms": round(td * 1e3, 4),
+                            "insert_updates_per_s": round(1e5 / ti, 1), "insert_ms": round(ti * 1e3, 4),
+                            "delete_stats": st_d, "insert_stats": st_i}
+    return out
+
+
 def run_batched(nsteps, dev, stream, log, tune):
     """Batched pattern: 256 independent G(n, 4n) graphs (n = 10^U(3,6)) with
     one batch per graph per step (op and size per graph), all graphs updated
@@ -266,6 +348,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-pattern measurement (256 graphs per launch)")
     ap.add_argument("--batched-steps", type=int, default=6)
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the per-op rates at other batch sizes and the deep grid")
     ap.add_argument("--no-served", action="store_true",
                     help="skip the served-pattern measurement")
     ap.add_argument("--served-scale", type=int, default=24)
@@ -415,6 +499,7 @@ def main():
                          f"scale {scale} graph (insert {t2 - t1:.2f}s, delete {t3 - t2:.2f}s), "
                          f"single-threaded C oracle"}
 
+    configs = None if args.no_configs else run_configs(g, dev, stream, log)
     batched = None if args.no_batched else run_batched(args.batched_steps, dev, stream, log,
                                                        not args.no_tune)
 
@@ -456,6 +541,7 @@ def main():
         "tuning": tuning,
         "roofline": roofline,
         "rooflines": rooflines,
+        "configs": configs,
         "batched": batched,
         "served": served,
         "cpu_baseline": cpu,

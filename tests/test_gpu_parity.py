@@ -423,3 +423,21 @@ def test_store_rebuild_when_inserted_list_fills():
         pair.step(dl, drsf.DRSF_DELETE, f"rebuild delete {step}")
         assert np.array_equal(pair.gpu.edges(), pair.keys)
     pair.gpu.close()
+
+
+@pytest.mark.slow
+def test_grid4096_deep_full_size():
+    """The deep-tree workload at full size: a 4096 x 4096 grid with 5% of its
+    edges removed, 1e5 tree-edge deletes, then 1e5 inserts, compared with the
+    oracle on the full parent and label arrays."""
+    drsf = _lib()
+    _case("grid4096 full")
+    side = 4096
+    keys = gen.grid(side, side, side * (side - 1) * 2 // 20, gen.seed(3, 0, gen.P_GRAPH))
+    g = gen.make_graph("grid4096", side * side, keys)
+    pair = Pair(g, max_batch=100_000)
+    dl = gen.delete_batches(g.n, g.keys, g.parent, 1, 100_000, 100_000, gen.seed(3, 0, gen.P_DELETE))[0]
+    pair.step(dl, drsf.DRSF_DELETE, "grid4096 delete")
+    ins = gen.insert_batches(g.n, pair.keys, 1, 100_000, gen.seed(3, 0, gen.P_INSERT))[0]
+    pair.step(ins, drsf.DRSF_INSERT, "grid4096 insert")
+    pair.gpu.close()
