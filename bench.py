@@ -36,17 +36,33 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
+def kernel_source_sha(kernel: str) -> str:
+    """sha256[:16] of the kernel's own definition in drsf_kernels.hip (from
+    its __global__ line to its closing brace)."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2607_20211_amd", "csrc", "drsf_kernels.hip")).read()
+    i = src.find(f" void {kernel}(")
+    if i < 0:
+        return ""
+    i = src.rfind("\n", 0, i) + 1
+    j = src.index("{", i)
+    depth = 0
+    for k in range(j, len(src)):
+        depth += {"{": 1, "}": -1}.get(src[k], 0)
+        if depth == 0:
+            return hashlib.sha256(src[i:k + 1].encode()).hexdigest()[:16]
+    return ""
+
+
 def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    runs (profiles/*.counters.json), or None when the kernel source has
-    changed since the counters were taken."""
+    runs (profiles/*.counters.json), or None when the kernel's definition
+    has changed since the counters were taken."""
     import glob
-    import hashlib
-    src = os.path.join(ROOT, "paper_2607_20211_amd", "csrc", "drsf_kernels.hip")
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    h = kernel_source_sha(kernel)
     for path in glob.glob(os.path.join(ROOT, "profiles", "*.counters.json")):
         c = json.load(open(path))
-        if c.get("kernel") == kernel and c.get("workload") == workload and c.get("source_sha256_16") == h:
+        if c.get("kernel") == kernel and c.get("workload") == workload and c.get("kernel_sha256_16") == h:
             return c["traffic_bytes_per_launch"]
     return None
 
@@ -449,22 +465,25 @@ def main():
         return {k: float(np.mean([p[k] for p in lst])) for k in lst[0]}
 
     pi, pd = mean_phases(phases_ins), mean_phases(phases_del)
+    # every phase time holds one event record's cost: the empty bracket
+    ev_ins, ev_del = pi.pop(drsf.EVENT_BRACKET, 0.0), pd.pop(drsf.EVENT_BRACKET, 0.0)
     t_ins_dev = sum(pi.values()) * 1e-3
     t_del_dev = sum(pd.values()) * 1e-3
     # rooflines of the single-kernel phases with a defined algorithmic byte
     # count; the dominant one (largest time) is "roofline"
     sd = {k: float(np.mean([x[k] for x in st_del])) for k in st_del[0]}
     eb = g.m  # undirected edges, held once in the upper-half store
+    # one-kernel phases: the kernel's time is the phase time less the bracket
     kernels = {
-        "k_rep_chase": (pd["root_chase"], 12 * g.n + g.n // 8,
+        "k_rep_chase": (pd["root_chase"] - ev_del, 12 * g.n + g.n // 8,
                         "root finding: read rep and label, write rep (4 B each per vertex), "
                         "orphan bitmap (1 bit per vertex)"),
-        "k_orph_scan": (pd["orphan_scan"], int(8 * sd["orphan_slots"] + 40 * sd["num_orphans"]),
+        "k_orph_scan": (pd["orphan_scan"] - ev_del, int(8 * sd["orphan_slots"] + 40 * sd["num_orphans"]),
                         "orphan scan: column and the neighbour's rep per adjacency slot "
                         "(4 + 4 B), one 40-B list entry per orphan"),
     }
     if sd["scan_orphans"] < 0.5:
-        kernels["k_sweep_base"] = (pd["store_sweep"], 4 * eb + 4 * (g.n + 1),
+        kernels["k_sweep_base"] = (pd["store_sweep"] - ev_del, 4 * eb + 4 * (g.n + 1),
                                    "store sweep: 4 B per stored edge slot + 4 B per row offset")
     rooflines = {}
     for name, (ms, nbytes, what) in kernels.items():
@@ -473,7 +492,9 @@ def main():
                            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                            "traffic": measured_traffic(name, f"rmat{scale}_insert{b}_delete{b}"),
                            "kernel": name, "algorithmic_bytes_per_launch": int(nbytes),
-                           "avg_launch_ms": round(ms, 4), "bytes": what}
+                           "avg_launch_ms": round(ms, 4), "bytes": what,
+                           "timing": "HIP events around the kernel on its stream, mean over the "
+                                     "profiled steps, less an empty two-event bracket"}
     dom = max(rooflines, key=lambda k: rooflines[k]["avg_launch_ms"])
     roofline = rooflines[dom]
 
@@ -538,6 +559,7 @@ def main():
         "batch_stats_delete": {k: float(np.mean([x[k] for x in st_del])) for k in st_del[0]},
         "phase_ms_insert": {k: round(v, 4) for k, v in pi.items()},
         "phase_ms_delete": {k: round(v, 4) for k, v in pd.items()},
+        "event_bracket_ms": {"insert": round(ev_ins, 4), "delete": round(ev_del, 4)},
         "tuning": tuning,
         "roofline": roofline,
         "rooflines": rooflines,

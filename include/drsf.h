@@ -254,8 +254,12 @@ void drsf_snapshot_free(drsf_snapshot *snap);
  * sweep; cross edges of the batch and of the inserted-edge list; replacement
  * edges (the hooking rounds queued with the update); super-forest rooting;
  * path reversal; labels.  Work that an update finishes on the host (extra
- * rounds) is not in these times.  Returns the number of phases written
- * (<= cap).
+ * rounds) is not in these times; a phase that launches nothing for the
+ * batch's kind (the delete-only phases of an insert batch) reads 0.  Each
+ * phase time includes the fixed cost of one event record; a 13th entry
+ * (written when cap > 12) is the time of an empty bracket, two events
+ * recorded back to back before the update, which measures that cost.
+ * Returns the number of entries written (<= cap).
  */
 int drsf_phase_times(drsf_ctx *ctx, float *ms, int cap);
 

@@ -150,8 +150,9 @@ struct drsf_ctx {
     int last_op = 0;
     int last_rc = DRSF_OK;
     drsf_view view{};
-    hipEvent_t ev[PH_N + 1]{};
-    float phase_ms[PH_N]{};
+    hipEvent_t ev[PH_N + 3]{};  // phase boundaries, then an empty bracket
+    bool ph_on[PH_N + 1]{};     // the phase recorded its event in the last enqueued update
+    float phase_ms[PH_N + 1]{}; // phases, then the empty bracket
     bool have_phases = false;
     std::string err;
     std::vector<void *> allocs;
@@ -606,23 +607,30 @@ void enqueue_update(drsf_ctx *c, int kind, bool profile) {
     const Dev d = make_dev(c);
     hipStream_t s = c->stream;
     const bool ins = kind & 1, del = kind & 2;
-    auto mark = [&](int i) {
-        if (profile) (void)hipEventRecord(c->ev[i], s);
+    // a phase that launches nothing for this kind records no event (an
+    // event record costs a few microseconds of its own) and reads zero
+    auto mark = [&](int i, bool on = true) {
+        c->ph_on[i] = on;
+        if (profile && on) (void)hipEventRecord(c->ev[i], s);
     };
+    if (profile) {  // two events back to back: the fixed cost a phase time includes
+        (void)hipEventRecord(c->ev[PH_N + 1], s);
+        (void)hipEventRecord(c->ev[PH_N + 2], s);
+    }
     mark(PH_VALIDATE);
     launch_classify(d, s);
     mark(PH_UPDATE);
     launch_prepare(d, s);
     launch_register(d, s);
-    mark(PH_ROOT_INIT);
+    mark(PH_ROOT_INIT, del);
     if (del) launch_rep_init(d, s);
-    mark(PH_ROOT_CHASE);
+    mark(PH_ROOT_CHASE, del);
     if (del) launch_rep_chase(d, s);
-    mark(PH_ORPH_LIST);
+    mark(PH_ORPH_LIST, del);
     if (del) launch_orphan_list(d, s);
-    mark(PH_ORPH_SCAN);
+    mark(PH_ORPH_SCAN, del);
     if (del) launch_orphan_scan(d, s);
-    mark(PH_SWEEP);
+    mark(PH_SWEEP, del);
     if (del) launch_sweep_base(d, s);
     mark(PH_SWEEP_DELTA);
     if (ins) launch_insert_emit(d, s);
@@ -1120,12 +1128,22 @@ int drsf_wait(drsf_ctx *c, drsf_view *out) {
             if (rc) return c->last_rc = rc;
             st = *(int32_t *)c->h_ret;
         }
+        if (c->have_phases &&
+            hipEventElapsedTime(&c->phase_ms[PH_N], c->ev[PH_N + 1], c->ev[PH_N + 2]) != hipSuccess) {
+            (void)hipGetLastError();
+            c->have_phases = false;
+        }
         if (c->have_phases)
-            for (int i = 0; i < PH_N; i++)
-                if (hipEventElapsedTime(&c->phase_ms[i], c->ev[i], c->ev[i + 1]) != hipSuccess) {
+            for (int i = 0; i < PH_N; i++) {
+                c->phase_ms[i] = 0.f;
+                if (!c->ph_on[i]) continue;
+                int j = i + 1;
+                while (j < PH_N && !c->ph_on[j]) j++;
+                if (hipEventElapsedTime(&c->phase_ms[i], c->ev[i], c->ev[j]) != hipSuccess) {
                     (void)hipGetLastError();
                     c->have_phases = false;
                 }
+            }
         if (st != 0) {
             c->last_rc = fail(c, DRSF_E_DEVICE, "internal bound exceeded (status %d)", st);
         } else {
@@ -1348,7 +1366,7 @@ int drsf_phase_times(drsf_ctx *c, float *ms, int cap) {
     if (!c || !ms) return 0;
     if (finish_pending(c)) return 0;
     if (!c->have_phases) return 0;
-    const int k = std::min(cap, (int)PH_N);
+    const int k = std::min(cap, (int)PH_N + 1);
     for (int i = 0; i < k; i++) ms[i] = c->phase_ms[i];
     return k;
 }

@@ -148,8 +148,22 @@ constexpr int C_LR_ROUND = C_COUNT + MAX_ROUNDS;       // [MAX_ROUNDS]
 constexpr int C_BFS_ROUND = C_COUNT + 2 * MAX_ROUNDS;  // [MAX_ROUNDS]
 constexpr int C_TOTAL = C_COUNT + 3 * MAX_ROUNDS;
 
-// grid sizes
-int grid_for(int64_t items, int64_t per_block, int cap = 8192);
+// Grid sizes.  Workgroups are dispatched at about 200-270 per microsecond
+// across the chip, so a kernel of many short workgroups is bound by
+// dispatch: grid-stride kernels over vertices are capped near one full wave
+// of residency (8 workgroups of 256 threads per CU on 256 CUs).  Kernels
+// over pieces, arcs and paths, and the first hooking selections (one
+// region per workgroup), have their own caps, set by measurement.
+constexpr int GRID_CAP = 2048;
+#ifndef DRSF_SMALL_CAP
+#define DRSF_SMALL_CAP 2048
+#endif
+#ifndef DRSF_EDGE_CAP
+#define DRSF_EDGE_CAP 4096
+#endif
+constexpr int SMALL_CAP = DRSF_SMALL_CAP;  // kernels over pieces, arcs and paths
+constexpr int EDGE_CAP = DRSF_EDGE_CAP;    // first hooking selections
+int grid_for(int64_t items, int64_t per_block, int cap = GRID_CAP);
 int64_t delta_tiles(int64_t count);
 int64_t insert_regions(int64_t b);
 

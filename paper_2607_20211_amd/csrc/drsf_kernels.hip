@@ -23,14 +23,53 @@ int grid_for(int64_t items, int64_t per_block, int cap) {
 // ------------------------------------------------------------------ helpers
 
 // position of v in the ascending (masked) run bcol[lo, hi), or -1
-__device__ __forceinline__ int64_t find_in_row(const int32_t *bcol, uint32_t lo, uint32_t hi,
-                                               int32_t v) {
+// Position of column v in the ascending run col[lo, hi) (tombstone bits
+// ignored), or -1; *raw receives the stored entry.  Each step loads
+// SEARCH_FAN evenly spaced entries at once and keeps the part of the run
+// that can hold v, so a run of length L takes about log_{FAN+1}(L)
+// dependent loads.
+#ifndef DRSF_SEARCH_FAN
+#define DRSF_SEARCH_FAN 4
+#endif
+constexpr int SEARCH_FAN = DRSF_SEARCH_FAN;
+__device__ __forceinline__ int64_t find_in_row(const int32_t *col, uint32_t lo, uint32_t hi,
+                                               int32_t v, int32_t *raw) {
+    constexpr int F = SEARCH_FAN;
+    // the first entry >= v lies in [a, b]; cb is col[b] when b < hi
     uint32_t a = lo, b = hi;
-    while (a < b) {
-        uint32_t mid = a + ((b - a) >> 1);
-        if ((bcol[mid] & COLMASK) < v) a = mid + 1; else b = mid;
+    int32_t cb = 0;
+    while (b - a > (uint32_t)F) {
+        const uint32_t w = (b - a) / (F + 1);
+        int32_t c[F];
+#pragma unroll
+        for (int j = 0; j < F; j++) c[j] = col[a + (uint32_t)(j + 1) * w];
+        int cnt = 0;
+#pragma unroll
+        for (int j = 0; j < F; j++) cnt += (c[j] & COLMASK) < v;
+        if (cnt < F) {
+#pragma unroll
+            for (int j = 0; j < F; j++)
+                if (j == cnt) cb = c[j];
+            b = a + (uint32_t)(cnt + 1) * w;
+        }
+        if (cnt > 0) a += (uint32_t)cnt * w + 1;
     }
-    return (a < hi && (bcol[a] & COLMASK) == v) ? (int64_t)a : -1;
+    int64_t pos = -1;
+#pragma unroll
+    for (int j = 0; j < F; j++) {
+        if (a + (uint32_t)j < b) {
+            const int32_t c = col[a + j];
+            if ((c & COLMASK) == v) {
+                pos = a + j;
+                *raw = c;
+            }
+        }
+    }
+    if (pos < 0 && b < hi && (cb & COLMASK) == v) {
+        pos = b;
+        *raw = cb;
+    }
+    return pos;
 }
 
 // slot holding live key k in the inserted-edge index, or -1
@@ -215,6 +254,15 @@ __global__ __launch_bounds__(BLOCK) void k_classify(Dev d) {
         const uint64_t k = mkkey((uint32_t)u, (uint32_t)v);
         d.bkey[i] = k;
         const int32_t lo = key_lo(k), hi = key_hi(k);
+        // loads that do not depend on the probes below, issued first (the
+        // parents only where the batch holds deletes)
+        const uint32_t ua = d.bptr[lo], ub = d.bptr[lo + 1], la = d.lptr[hi], lb = d.lptr[hi + 1];
+        const int opi = opm == 2 ? (int)d.bop[i] : opm;
+        int32_t plo = NONE, phi = NONE;
+        if (opm != 0) {
+            plo = d.parent[lo];
+            phi = d.parent[hi];
+        }
         // repeated pair inside the batch
         uint64_t h = hmix(k) & d.bhmask;
         for (uint64_t probe = 0; probe <= d.bhmask; probe++) {
@@ -229,17 +277,17 @@ __global__ __launch_bounds__(BLOCK) void k_classify(Dev d) {
         }
         // presence: the edge sits in upper row lo and in lower row hi (with
         // mirrored tombstones); search the shorter and map a lower hit up
-        const uint32_t ua = d.bptr[lo], ub = d.bptr[lo + 1], la = d.lptr[hi], lb = d.lptr[hi + 1];
         int64_t pos;
+        int32_t raw = TOMB;
         if (ub - ua <= lb - la) {
-            pos = find_in_row(d.bcol, ua, ub, hi);
+            pos = find_in_row(d.bcol, ua, ub, hi, &raw);
         } else {
-            const int64_t q = find_in_row(d.lcol, la, lb, lo);
+            const int64_t q = find_in_row(d.lcol, la, lb, lo, &raw);
             pos = q >= 0 ? (int64_t)d.ltwin[q] : -1;
         }
         int64_t loc;
         bool present;
-        if (pos >= 0 && d.bcol[pos] >= 0) {
+        if (pos >= 0 && raw >= 0) {
             present = true;
             loc = pos;
         } else {
@@ -247,14 +295,14 @@ __global__ __launch_bounds__(BLOCK) void k_classify(Dev d) {
             present = slot >= 0;
             loc = -(slot + 1);
         }
-        if ((opm == 2 ? (int)d.bop[i] : opm) == 0) {
+        if (opi == 0) {
             if (present) atomicOr(&d.gstat[g], ST_EXISTS);
         } else {
             if (!present) {
                 atomicOr(&d.gstat[g], ST_MISSING);
             } else {
                 d.bloc[i] = loc;
-                d.bchild[i] = d.parent[lo] == hi ? lo : (d.parent[hi] == lo ? hi : NONE);
+                d.bchild[i] = plo == hi ? lo : (phi == lo ? hi : NONE);
             }
         }
     }
@@ -397,75 +445,123 @@ __global__ __launch_bounds__(BLOCK) void k_rep_init(Dev d) {
 // ancestor of the vertex, so stale reads only cost extra steps.  Also marks
 // vertices whose root is not their old root (they lie in a piece cut off by
 // the batch) in a bitmap, and the smallest vertex of each such piece.
+// rep[v] <- root of v in F-hat.  Each thread chases rep[] upward; entries
+// already finished by other threads are roots, so chains shorten as the
+// sweep proceeds (pointer jumping, Algorithm 1).  Every value read is an
+// ancestor of the vertex, so stale reads only cost extra steps.  A thread
+// can take REP_CH vertex blocks at a time and interleave their chases and
+// the loads that follow (on gfx950 one block at a time measures fastest:
+// the whole grid is resident, so more chains per thread add no overlap).
+// Marks vertices whose root is not their old root (they lie in a
+// piece cut off by the batch), stages each block's such orphans, compacted
+// at the block's start, with their adjacency runs for the orphan scan, and
+// lowers each orphan piece's smallest vertex.
+#ifndef DRSF_REP_CH
+#define DRSF_REP_CH 1
+#endif
+constexpr int REP_CH = DRSF_REP_CH;
 __global__ __launch_bounds__(BLOCK) void k_rep_chase(Dev d) {
     if (*d.status || !d.ctl->has_del) return;
     const int64_t nb = (d.n + BLOCK - 1) / BLOCK;
-    for (int64_t j = blockIdx.x;; j += gridDim.x) {
-        const int64_t blk = list_block(d.vlist, d.ctl->nvl, j, nb);
-        if (blk < 0) break;
-        const int64_t v = blk * BLOCK + threadIdx.x;
-        bool orphan = false;
-        int32_t x = 0;
-        if (v < d.n) {
-            x = ld_relaxed(&d.rep[v]);
-            for (int64_t steps = 0;; steps++) {
-                const int32_t y = ld_relaxed(&d.rep[x]);
-                if (y == x) break;
-                x = y;
-                if (steps > d.n) { atomicOr(d.status, ST_WALK_BOUND); break; }
+    for (int64_t j0 = (int64_t)blockIdx.x * REP_CH;; j0 += (int64_t)gridDim.x * REP_CH) {
+        int64_t blk[REP_CH], v[REP_CH];
+        int32_t x[REP_CH], lab[REP_CH];
+        bool live[REP_CH], act[REP_CH];
+#pragma unroll
+        for (int k = 0; k < REP_CH; k++) {
+            blk[k] = list_block(d.vlist, d.ctl->nvl, j0 + k, nb);
+            v[k] = blk[k] >= 0 ? blk[k] * BLOCK + threadIdx.x : d.n;
+            live[k] = act[k] = v[k] < d.n;
+        }
+        if (blk[0] < 0) break;  // the list is exhausted (uniform over the block)
+#pragma unroll
+        for (int k = 0; k < REP_CH; k++) {
+            x[k] = live[k] ? ld_relaxed(&d.rep[v[k]]) : 0;
+            lab[k] = live[k] ? d.label[v[k]] : 0;
+        }
+        for (int64_t steps = 0;; steps++) {
+            int32_t y[REP_CH];
+#pragma unroll
+            for (int k = 0; k < REP_CH; k++) y[k] = act[k] ? ld_relaxed(&d.rep[x[k]]) : x[k];
+            bool more = false;
+#pragma unroll
+            for (int k = 0; k < REP_CH; k++) {
+                act[k] = act[k] && y[k] != x[k];
+                x[k] = y[k];
+                more |= act[k];
             }
-            d.rep[v] = x;
-            orphan = x != d.label[v];
+            if (!more) break;
+            if (steps > d.n) {
+                atomicOr(d.status, ST_WALK_BOUND);
+                break;
+            }
         }
-        const uint64_t word = __ballot(orphan);
-        if (lane_id() == 0 && v < d.n) d.obits[v >> 6] = word;
-        int32_t t = NONE;
-        uint32_t us = 0, ls = 0;
-        int32_t du = 0, dl = 0;
-        if (orphan) {
-            t = d.tidx[x];
-            if (t < 0) atomicOr(d.status, ST_WALK_BOUND);
-            us = d.bptr[v];
-            ls = d.lptr[v];
-            du = (int32_t)(d.bptr[v + 1] - us);
-            dl = (int32_t)(d.lptr[v + 1] - ls);
+        bool orphan[REP_CH];
+        int32_t t[REP_CH];
+        uint32_t us[REP_CH], ls[REP_CH];
+        int32_t du[REP_CH], dl[REP_CH];
+#pragma unroll
+        for (int k = 0; k < REP_CH; k++) {
+            orphan[k] = live[k] && x[k] != lab[k];
+            if (live[k]) d.rep[v[k]] = x[k];
+            const uint64_t word = __ballot(orphan[k]);
+            if (lane_id() == 0 && live[k]) d.obits[v[k] >> 6] = word;
+            t[k] = NONE;
+            us[k] = ls[k] = 0;
+            du[k] = dl[k] = 0;
+            if (orphan[k]) {
+                t[k] = d.tidx[x[k]];
+                us[k] = d.bptr[v[k]];
+                ls[k] = d.lptr[v[k]];
+                du[k] = (int32_t)d.bptr[v[k] + 1];
+                dl[k] = (int32_t)d.lptr[v[k] + 1];
+            }
         }
-        // the block's orphans with their adjacency runs (plus padding),
-        // compacted at the block's start of the staging array for the orphan
-        // scan, and the block's totals
-        unsigned long long tot;
-        const unsigned long long off =
-            block_excl_scan64(orphan ? opack((unsigned long long)(du + dl + OR_PAD), 1) : 0, &tot);
-        if (orphan) {
-            OrphEnt o;
-            o.pre = (int64_t)ovol(off);
-            o.ustart = us;
-            o.lstart = ls;
-            o.v = (int32_t)v;
-            o.du = du;
-            o.dl = dl;
-            o.pu = t;
-            o.ru = x;
-            o.pad = 0;
-            d.ostage[blk * BLOCK + (int64_t)ocnt(off)] = o;
+#pragma unroll
+        for (int k = 0; k < REP_CH; k++) {
+            if (blk[k] < 0) continue;  // uniform over the block
+            if (orphan[k]) {
+                if (t[k] < 0) atomicOr(d.status, ST_WALK_BOUND);
+                du[k] -= (int32_t)us[k];
+                dl[k] -= (int32_t)ls[k];
+            }
+            // the block's orphans with their adjacency runs (plus padding)
+            // and the block's totals
+            unsigned long long tot;
+            const unsigned long long off = block_excl_scan64(
+                orphan[k] ? opack((unsigned long long)(du[k] + dl[k] + OR_PAD), 1) : 0, &tot);
+            if (orphan[k]) {
+                OrphEnt o;
+                o.pre = (int64_t)ovol(off);
+                o.ustart = us[k];
+                o.lstart = ls[k];
+                o.v = (int32_t)v[k];
+                o.du = du[k];
+                o.dl = dl[k];
+                o.pu = t[k];
+                o.ru = x[k];
+                o.pad = 0;
+                d.ostage[blk[k] * BLOCK + (int64_t)ocnt(off)] = o;
+            }
+            if (threadIdx.x == 0) {
+                d.bvol[blk[k]] = (int64_t)ovol(tot);
+                d.bcnt[blk[k]] = (int32_t)ocnt(tot);
+            }
+            // smallest vertex of each orphan piece; consecutive ids often
+            // share a piece
+            const bool grp = orphan[k] && t[k] >= 0;
+            uint64_t rem = __ballot(grp);
+            bool pending = grp;
+            for (int round = 0; round < GROUP_ROUNDS && rem; round++) {
+                const int leader = __ffsll((unsigned long long)rem) - 1;
+                const int32_t t0 = __shfl(t[k], leader);
+                const bool in = pending && t[k] == t0;
+                rem &= ~__ballot(in);
+                if (in) pending = false;
+                if (lane_id() == leader) min_i32(&d.pmin[t0], (int32_t)v[k]);  // smallest v of the group
+            }
+            if (pending) min_i32(&d.pmin[t[k]], (int32_t)v[k]);
         }
-        if (threadIdx.x == 0) {
-            d.bvol[blk] = (int64_t)ovol(tot);
-            d.bcnt[blk] = (int32_t)ocnt(tot);
-        }
-        // smallest vertex of each orphan piece; consecutive ids often share a piece
-        const bool act = orphan && t >= 0;
-        uint64_t rem = __ballot(act);
-        bool pending = act;
-        for (int round = 0; round < GROUP_ROUNDS && rem; round++) {
-            const int leader = __ffsll((unsigned long long)rem) - 1;
-            const int32_t t0 = __shfl(t, leader);
-            const bool in = pending && t == t0;
-            rem &= ~__ballot(in);
-            if (in) pending = false;
-            if (lane_id() == leader) min_i32(&d.pmin[t0], (int32_t)v);  // leader: smallest v of the group
-        }
-        if (pending) min_i32(&d.pmin[t], (int32_t)v);
     }
 }
 
@@ -1503,10 +1599,10 @@ void launch_insert_emit(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_insert_emit, dim3((unsigned)insert_regions(d.max_b)), dim3(BLOCK), 0, s, d);
 }
 void launch_rep_init(const Dev &d, hipStream_t s) {
-    hipLaunchKernelGGL(k_rep_init, dim3(grid_for(d.nvb, BLOCK / WAVE, 1 << 20)), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_rep_init, dim3(grid_for(d.nvb, BLOCK / WAVE, GRID_CAP)), dim3(BLOCK), 0, s, d);
 }
 void launch_rep_chase(const Dev &d, hipStream_t s) {
-    hipLaunchKernelGGL(k_rep_chase, dim3(grid_for(d.n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_rep_chase, dim3(grid_for(d.nvb, REP_CH, GRID_CAP)), dim3(BLOCK), 0, s, d);
 }
 void launch_sweep_base(const Dev &d, hipStream_t s) {
     // persistent: about as many workgroups as fit at once (24 KB of LDS each)
@@ -1514,67 +1610,70 @@ void launch_sweep_base(const Dev &d, hipStream_t s) {
         hipLaunchKernelGGL(k_sweep_base, dim3(grid_for(d.ntiles, 1, 6 * 256)), dim3(BLOCK), 0, s, d);
 }
 void launch_orphan_list(const Dev &d, hipStream_t s) {
-    hipLaunchKernelGGL(k_orph_plan, dim3(grid_for(d.nvb, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_orph_plan, dim3(grid_for(d.nvb, BLOCK, 1 << 30)), dim3(BLOCK), 0, s, d);
     hipLaunchKernelGGL(k_orph_total, dim3(1), dim3(BLOCK), 0, s, d);
-    hipLaunchKernelGGL(k_orph_fill, dim3(grid_for(d.nvb, BLOCK / WAVE, 1 << 20)), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_orph_fill, dim3(grid_for(d.nvb, BLOCK / WAVE, GRID_CAP)), dim3(BLOCK), 0, s, d);
 }
 void launch_orphan_scan(const Dev &d, hipStream_t s) {
-    hipLaunchKernelGGL(k_orph_scan, dim3(grid_for((d.ntiles * TILE) / OR_MAX_FRAC, OR_W, 4096)),
+    hipLaunchKernelGGL(k_orph_scan, dim3(grid_for((d.ntiles * TILE) / OR_MAX_FRAC, OR_W, GRID_CAP)),
                        dim3(BLOCK), 0, s, d);
 }
 void launch_sweep_delta(const Dev &d, hipStream_t s) {
     if (d.dtmax > 0)
         hipLaunchKernelGGL(k_sweep_delta, dim3((unsigned)d.dtmax), dim3(BLOCK), 0, s, d);
 }
+// The hooking, rooting and reversal kernels index pieces, arcs and paths
+// (at most 2 max_batch): grids of one workgroup per CU, grid-stride, so a
+// round that finds nothing to do costs little dispatch.
 void launch_boruvka(const Dev &d, int r0, int r1, int64_t units, hipStream_t s) {
-    const int ge = grid_for(units, 1, 4096);
-    const int gp = grid_for(d.pcap, BLOCK, 2048);
+    const int ge = grid_for(units, 1, EDGE_CAP);
+    const int gp = grid_for(d.pcap, BLOCK, SMALL_CAP);
     for (int r = r0; r < r1; r++) {
         if (r == 0)
             hipLaunchKernelGGL(k_bor_round0, dim3(ge), dim3(BLOCK), 0, s, d);
         else
-            hipLaunchKernelGGL(k_bor_select, dim3(ge), dim3(BLOCK), 0, s, d, r);
+            hipLaunchKernelGGL(k_bor_select, dim3(r == 1 ? ge : gp), dim3(BLOCK), 0, s, d, r);
         hipLaunchKernelGGL(k_bor_hook, dim3(gp), dim3(BLOCK), 0, s, d, r);
         hipLaunchKernelGGL(k_bor_compress, dim3(gp), dim3(BLOCK), 0, s, d, r);
     }
 }
 void launch_sf_root(const Dev &d, hipStream_t s) {
-    const int gp = grid_for(d.pcap, BLOCK, 2048);
+    const int gp = grid_for(d.pcap, BLOCK, SMALL_CAP);
     hipLaunchKernelGGL(k_sf_root, dim3(gp), dim3(BLOCK), 0, s, d);
     hipLaunchKernelGGL(k_sf_level_init, dim3(gp), dim3(BLOCK), 0, s, d);
 }
 void launch_sf_bfs(const Dev &d, int l0, int l1, hipStream_t s) {
-    const int ga = grid_for(2 * d.ercap, BLOCK, 2048);
+    const int ga = grid_for(2 * d.ercap, BLOCK, SMALL_CAP);
     for (int L = l0; L < l1; L++) hipLaunchKernelGGL(k_sf_bfs, dim3(ga), dim3(BLOCK), 0, s, d, L);
 }
 void launch_orient_bfs(const Dev &d, int levels, hipStream_t s) {
-    hipLaunchKernelGGL(k_orient_bfs, dim3(grid_for(d.pcap, BLOCK, 2048)), dim3(BLOCK), 0, s, d, levels);
+    hipLaunchKernelGGL(k_orient_bfs, dim3(grid_for(d.pcap, BLOCK, SMALL_CAP)), dim3(BLOCK), 0, s, d, levels);
 }
 void launch_superforest_lr(const Dev &d, int lr_rounds, hipStream_t s) {
-    const int ga = grid_for(2 * d.ercap, BLOCK, 2048);
-    hipLaunchKernelGGL(k_sf_arcs, dim3(grid_for(d.ercap, BLOCK, 2048)), dim3(BLOCK), 0, s, d);
+    const int ga = grid_for(2 * d.ercap, BLOCK, SMALL_CAP);
+    hipLaunchKernelGGL(k_sf_arcs, dim3(grid_for(d.ercap, BLOCK, SMALL_CAP)), dim3(BLOCK), 0, s, d);
     hipLaunchKernelGGL(k_sf_succ, dim3(ga), dim3(BLOCK), 0, s, d);
     for (int r = 0; r < lr_rounds; r++)
         hipLaunchKernelGGL(k_lr_round, dim3(ga), dim3(BLOCK), 0, s, d, r);
-    hipLaunchKernelGGL(k_orient_lr, dim3(grid_for(d.ercap + d.pcap, BLOCK, 2048)), dim3(BLOCK), 0, s,
+    hipLaunchKernelGGL(k_orient_lr, dim3(grid_for(d.ercap + d.pcap, BLOCK, SMALL_CAP)), dim3(BLOCK), 0, s,
                        d, lr_rounds);
 }
 void launch_reverse(const Dev &d, hipStream_t s) {
-    hipLaunchKernelGGL(k_reverse, dim3(grid_for(d.pathcap, BLOCK, 2048)), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_reverse, dim3(grid_for(d.pathcap, BLOCK, SMALL_CAP)), dim3(BLOCK), 0, s, d);
 }
 void launch_reverse_all(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_reverse_all, dim3(grid_for(d.pathcap, BLOCK, 2048)), dim3(BLOCK), 0, s, d);
 }
 void launch_labels(const Dev &d, bool ins, bool del, hipStream_t s) {
-    const int g = grid_for(d.n, BLOCK, 1 << 20);
+    const int g = grid_for(d.n, BLOCK, GRID_CAP);
     if (del) hipLaunchKernelGGL(k_label_delete, dim3(g), dim3(BLOCK), 0, s, d);
     if (ins)
-        hipLaunchKernelGGL(k_label_insert, dim3(grid_for(d.nvb, BLOCK / WAVE, 1 << 20)), dim3(BLOCK), 0,
+        hipLaunchKernelGGL(k_label_insert, dim3(grid_for(d.nvb, BLOCK / WAVE, GRID_CAP)), dim3(BLOCK), 0,
                            s, d);
 }
 void launch_cleanup(const Dev &d, hipStream_t s) {
     int64_t m = d.pcap > d.max_b ? d.pcap : d.max_b;
-    hipLaunchKernelGGL(k_cleanup_slots, dim3(grid_for(m, BLOCK, 2048)), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_cleanup_slots, dim3(grid_for(m, BLOCK, SMALL_CAP)), dim3(BLOCK), 0, s, d);
     hipLaunchKernelGGL(k_cleanup_counters, dim3(1), dim3(256), 0, s, d);
 }
 
@@ -1596,7 +1695,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_counts(int32_t n, const uint32_t *
 }
 void launch_rb_counts(int32_t n, const uint32_t *bptr, const int32_t *bcol, const uint32_t *lptr,
                       const int32_t *lcol, uint32_t *deg, hipStream_t s) {
-    hipLaunchKernelGGL(k_rb_counts, dim3(grid_for((int64_t)n * WAVE, BLOCK, 1 << 20)), dim3(BLOCK), 0, s,
+    hipLaunchKernelGGL(k_rb_counts, dim3(grid_for((int64_t)n * WAVE, BLOCK, GRID_CAP)), dim3(BLOCK), 0, s,
                        n, bptr, bcol, lptr, lcol, deg);
 }
 
@@ -1641,7 +1740,7 @@ __global__ void k_add_u32(const uint32_t *a, const uint32_t *b, uint32_t *out, i
         out[i] = a[i] + b[i];
 }
 void launch_add_u32(const uint32_t *a, const uint32_t *b, uint32_t *out, int64_t count, hipStream_t s) {
-    hipLaunchKernelGGL(k_add_u32, dim3(grid_for(count, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, a, b, out, count);
+    hipLaunchKernelGGL(k_add_u32, dim3(grid_for(count, BLOCK, GRID_CAP)), dim3(BLOCK), 0, s, a, b, out, count);
 }
 __global__ void k_u32_to_i64(const uint32_t *in, int64_t *out, int64_t count) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -1649,7 +1748,7 @@ __global__ void k_u32_to_i64(const uint32_t *in, int64_t *out, int64_t count) {
         out[i] = (int64_t)in[i];
 }
 void launch_u32_to_i64(const uint32_t *in, int64_t *out, int64_t count, hipStream_t s) {
-    hipLaunchKernelGGL(k_u32_to_i64, dim3(grid_for(count, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, in, out, count);
+    hipLaunchKernelGGL(k_u32_to_i64, dim3(grid_for(count, BLOCK, GRID_CAP)), dim3(BLOCK), 0, s, in, out, count);
 }
 
 // Row u of the merged symmetric CSR: its live lower entries, then its live
@@ -1691,7 +1790,7 @@ __global__ void k_rb_fill(int32_t n, const uint32_t *bptr, const int32_t *bcol, 
 void launch_rb_fill(int32_t n, const uint32_t *bptr, const int32_t *bcol, const uint32_t *lptr,
                     const int32_t *lcol, const uint64_t *pairs, const uint32_t *dstart,
                     const uint32_t *ddeg, const int64_t *row_ptr, int32_t *col, hipStream_t s) {
-    hipLaunchKernelGGL(k_rb_fill, dim3(grid_for(n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, n, bptr, bcol, lptr,
+    hipLaunchKernelGGL(k_rb_fill, dim3(grid_for(n, BLOCK, GRID_CAP)), dim3(BLOCK), 0, s, n, bptr, bcol, lptr,
                        lcol, pairs, dstart, ddeg, row_ptr, col);
 }
 
@@ -1732,11 +1831,11 @@ __global__ void k_fill_u64(uint64_t *p, int64_t count, uint64_t v) {
 }
 void launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t s) {
     if (count > 0)
-        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(count, BLOCK, 1 << 16)), dim3(BLOCK), 0, s, p, count, v);
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(count, BLOCK, GRID_CAP)), dim3(BLOCK), 0, s, p, count, v);
 }
 void launch_fill_u64(uint64_t *p, int64_t count, uint64_t v, hipStream_t s) {
     if (count > 0)
-        hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(count, BLOCK, 1 << 16)), dim3(BLOCK), 0, s, p, count, v);
+        hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(count, BLOCK, GRID_CAP)), dim3(BLOCK), 0, s, p, count, v);
 }
 
 // One wave per row: ids in range (inside the row's graph when several graphs
@@ -1780,7 +1879,7 @@ __global__ __launch_bounds__(BLOCK) void k_csr_check(int32_t n, const int64_t *r
 }
 void launch_csr_check(int32_t n, const int64_t *row_ptr, const int32_t *col, uint32_t *ucnt,
                       int32_t *status, const int32_t *goff, int32_t ngraph, hipStream_t s) {
-    hipLaunchKernelGGL(k_csr_check, dim3(grid_for((int64_t)n * WAVE, BLOCK, 1 << 20)), dim3(BLOCK),
+    hipLaunchKernelGGL(k_csr_check, dim3(grid_for((int64_t)n * WAVE, BLOCK, GRID_CAP)), dim3(BLOCK),
                        0, s, n, row_ptr, col, ucnt, status, goff, ngraph);
 }
 
@@ -1805,7 +1904,7 @@ __global__ __launch_bounds__(BLOCK) void k_csr_symmetric(int32_t n, const int64_
 }
 void launch_csr_symmetric(int32_t n, const int64_t *row_ptr, const int32_t *col, int32_t *status,
                           hipStream_t s) {
-    hipLaunchKernelGGL(k_csr_symmetric, dim3(grid_for((int64_t)n * WAVE, BLOCK, 1 << 20)),
+    hipLaunchKernelGGL(k_csr_symmetric, dim3(grid_for((int64_t)n * WAVE, BLOCK, GRID_CAP)),
                        dim3(BLOCK), 0, s, n, row_ptr, col, status);
 }
 
@@ -1905,7 +2004,7 @@ __global__ __launch_bounds__(BLOCK) void k_upper_fill(int32_t n, const int64_t *
 }
 void launch_upper_fill(int32_t n, const int64_t *row_ptr, const int32_t *col, const uint32_t *bptr,
                        int32_t *bcol, hipStream_t s) {
-    hipLaunchKernelGGL(k_upper_fill, dim3(grid_for((int64_t)n * WAVE, BLOCK, 1 << 20)), dim3(BLOCK),
+    hipLaunchKernelGGL(k_upper_fill, dim3(grid_for((int64_t)n * WAVE, BLOCK, GRID_CAP)), dim3(BLOCK),
                        0, s, n, row_ptr, col, bptr, bcol);
 }
 
@@ -1918,7 +2017,7 @@ __global__ void k_lower_counts(int32_t n, const int64_t *row_ptr, const uint32_t
 }
 void launch_lower_counts(int32_t n, const int64_t *row_ptr, const uint32_t *bptr, uint32_t *lcnt,
                          hipStream_t s) {
-    hipLaunchKernelGGL(k_lower_counts, dim3(grid_for(n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, n, row_ptr,
+    hipLaunchKernelGGL(k_lower_counts, dim3(grid_for(n, BLOCK, GRID_CAP)), dim3(BLOCK), 0, s, n, row_ptr,
                        bptr, lcnt);
 }
 __global__ __launch_bounds__(BLOCK) void k_lower_fill(int32_t n, const int64_t *row_ptr,
@@ -1934,7 +2033,7 @@ __global__ __launch_bounds__(BLOCK) void k_lower_fill(int32_t n, const int64_t *
 }
 void launch_lower_fill(int32_t n, const int64_t *row_ptr, const int32_t *col, const uint32_t *lptr,
                        int32_t *lcol, hipStream_t s) {
-    hipLaunchKernelGGL(k_lower_fill, dim3(grid_for((int64_t)n * WAVE, BLOCK, 1 << 20)), dim3(BLOCK),
+    hipLaunchKernelGGL(k_lower_fill, dim3(grid_for((int64_t)n * WAVE, BLOCK, GRID_CAP)), dim3(BLOCK),
                        0, s, n, row_ptr, col, lptr, lcol);
 }
 // twin[p]: position in the lower half of the mirror of upper entry p (one
@@ -1947,7 +2046,8 @@ __global__ __launch_bounds__(BLOCK) void k_twin(int32_t n, const uint32_t *bptr,
     for (int64_t v = (int64_t)blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE; v < n; v += nw) {
         for (int64_t q = (int64_t)lptr[v] + lane; q < (int64_t)lptr[v + 1]; q += WAVE) {
             const int32_t u = lcol[q];
-            const int64_t p = find_in_row(bcol, bptr[u], bptr[u + 1], (int32_t)v);
+            int32_t raw;
+            const int64_t p = find_in_row(bcol, bptr[u], bptr[u + 1], (int32_t)v, &raw);
             if (p < 0) {
                 atomicOr(status, 2);
             } else {
@@ -1959,7 +2059,7 @@ __global__ __launch_bounds__(BLOCK) void k_twin(int32_t n, const uint32_t *bptr,
 }
 void launch_twin(int32_t n, const uint32_t *bptr, const int32_t *bcol, const uint32_t *lptr,
                  const int32_t *lcol, uint32_t *twin, uint32_t *ltwin, int32_t *status, hipStream_t s) {
-    hipLaunchKernelGGL(k_twin, dim3(grid_for((int64_t)n * WAVE, BLOCK, 1 << 20)), dim3(BLOCK), 0, s,
+    hipLaunchKernelGGL(k_twin, dim3(grid_for((int64_t)n * WAVE, BLOCK, GRID_CAP)), dim3(BLOCK), 0, s,
                        n, bptr, bcol, lptr, lcol, twin, ltwin, status);
 }
 
@@ -1980,12 +2080,12 @@ __global__ void k_nonempty_fill(int32_t n, const uint32_t *bptr, const uint32_t 
     if (blockIdx.x == 0 && threadIdx.x == 0) zptr[nz] = bptr[n];
 }
 void launch_nonempty_flags(int32_t n, const uint32_t *bptr, uint32_t *flag, hipStream_t s) {
-    hipLaunchKernelGGL(k_nonempty_flags, dim3(grid_for(n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, n, bptr,
+    hipLaunchKernelGGL(k_nonempty_flags, dim3(grid_for(n, BLOCK, GRID_CAP)), dim3(BLOCK), 0, s, n, bptr,
                        flag);
 }
 void launch_nonempty_fill(int32_t n, const uint32_t *bptr, const uint32_t *zpos, int32_t *zrow,
                           uint32_t *zptr, int64_t nz, hipStream_t s) {
-    hipLaunchKernelGGL(k_nonempty_fill, dim3(grid_for(n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, n, bptr,
+    hipLaunchKernelGGL(k_nonempty_fill, dim3(grid_for(n, BLOCK, GRID_CAP)), dim3(BLOCK), 0, s, n, bptr,
                        zpos, zrow, zptr, nz);
 }
 
@@ -2019,12 +2119,13 @@ __global__ void k_forest_check(int32_t n, const uint32_t *bptr, const int32_t *b
         if (p < 0 || p >= n) { atomicOr(status, 1); continue; }
         if (p == v || !edges) continue;
         const int32_t lo = p < v ? p : (int32_t)v, hi = p < v ? (int32_t)v : p;
-        if (find_in_row(bcol, bptr[lo], bptr[lo + 1], hi) < 0) atomicOr(status, 2);
+        int32_t raw;
+        if (find_in_row(bcol, bptr[lo], bptr[lo + 1], hi, &raw) < 0) atomicOr(status, 2);
     }
 }
 void launch_forest_check(int32_t n, const uint32_t *bptr, const int32_t *bcol, const int32_t *parent,
                          int32_t *status, int check_edges, hipStream_t s) {
-    hipLaunchKernelGGL(k_forest_check, dim3(grid_for(n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, n, bptr,
+    hipLaunchKernelGGL(k_forest_check, dim3(grid_for(n, BLOCK, GRID_CAP)), dim3(BLOCK), 0, s, n, bptr,
                        bcol, parent, status, check_edges);
 }
 
@@ -2034,7 +2135,7 @@ __global__ void k_pointer_jump(int32_t n, const int32_t *in, int32_t *out) {
         out[v] = in[in[v]];
 }
 void launch_pointer_jump(int32_t n, const int32_t *in, int32_t *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_pointer_jump, dim3(grid_for(n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, n, in, out);
+    hipLaunchKernelGGL(k_pointer_jump, dim3(grid_for(n, BLOCK, GRID_CAP)), dim3(BLOCK), 0, s, n, in, out);
 }
 
 // after enough jumping rounds every vertex of a tree points at its root; a
@@ -2049,7 +2150,7 @@ __global__ void k_roots_check(int32_t n, const int32_t *parent, const int32_t *r
 }
 void launch_roots_check(int32_t n, const int32_t *parent, const int32_t *root, int32_t *status,
                         hipStream_t s) {
-    hipLaunchKernelGGL(k_roots_check, dim3(grid_for(n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, n, parent,
+    hipLaunchKernelGGL(k_roots_check, dim3(grid_for(n, BLOCK, GRID_CAP)), dim3(BLOCK), 0, s, n, parent,
                        root, status);
 }
 
@@ -2064,7 +2165,7 @@ __global__ __launch_bounds__(BLOCK) void k_span_check(Dev d, const int32_t *root
     }
 }
 void launch_span_check(const Dev &d, const int32_t *root, hipStream_t s) {
-    hipLaunchKernelGGL(k_span_check, dim3(grid_for((int64_t)d.n * WAVE, BLOCK, 1 << 20)), dim3(BLOCK),
+    hipLaunchKernelGGL(k_span_check, dim3(grid_for((int64_t)d.n * WAVE, BLOCK, GRID_CAP)), dim3(BLOCK),
                        0, s, d, root);
 }
 
@@ -2082,8 +2183,8 @@ __global__ void k_label_from_root(int32_t n, const int32_t *root, int32_t *label
 }
 void launch_tree_min(int32_t n, const int32_t *root, int32_t *label, hipStream_t s) {
     launch_fill_i32(label, n, 0x7fffffff, s);
-    hipLaunchKernelGGL(k_tree_min, dim3(grid_for(n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, n, root, label);
-    hipLaunchKernelGGL(k_label_from_root, dim3(grid_for(n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, n, root,
+    hipLaunchKernelGGL(k_tree_min, dim3(grid_for(n, BLOCK, GRID_CAP)), dim3(BLOCK), 0, s, n, root, label);
+    hipLaunchKernelGGL(k_label_from_root, dim3(grid_for(n, BLOCK, GRID_CAP)), dim3(BLOCK), 0, s, n, root,
                        label);
 }
 
@@ -2106,7 +2207,7 @@ __global__ __launch_bounds__(BLOCK) void k_reroot_requests(Dev d, const int32_t 
     }
 }
 void launch_reroot_requests(const Dev &d, const int32_t *root, hipStream_t s) {
-    hipLaunchKernelGGL(k_reroot_requests, dim3(grid_for(d.n, BLOCK, 1 << 20)), dim3(BLOCK), 0, s, d, root);
+    hipLaunchKernelGGL(k_reroot_requests, dim3(grid_for(d.n, BLOCK, GRID_CAP)), dim3(BLOCK), 0, s, d, root);
 }
 
 }  // namespace drsf

@@ -23,6 +23,9 @@ DRSF_SERVER_DIGESTS, DRSF_SERVER_SERIAL = 1, 2
 PHASES = ("validate", "update_graph", "root_init", "root_chase", "orphan_list", "orphan_scan",
           "store_sweep", "batch_and_inserted_scan", "replacement_edges", "superforest_rooting",
           "path_reversal", "labels")
+# the 13th entry of drsf_phase_times: two events back to back (the fixed cost
+# of the event record that every phase time includes)
+EVENT_BRACKET = "event_bracket"
 
 
 class drsf_opts(ctypes.Structure):
@@ -245,9 +248,10 @@ def drsf_snapshot_free(snap) -> None:
 
 
 def drsf_phase_times(ctx) -> dict:
-    buf = (ctypes.c_float * len(PHASES))()
-    k = load().drsf_phase_times(ctx, buf, len(PHASES))
-    return {PHASES[i]: float(buf[i]) for i in range(k)}
+    names = PHASES + (EVENT_BRACKET,)
+    buf = (ctypes.c_float * len(names))()
+    k = load().drsf_phase_times(ctx, buf, len(names))
+    return {names[i]: float(buf[i]) for i in range(k)}
 
 
 def drsf_multi_create(G: int, n_off, row_ptr, col, parent, opts: drsf_opts | None = None):

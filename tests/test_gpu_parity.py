@@ -376,7 +376,12 @@ def test_profile_mode_direct_launches():
     for step in range(3):
         ins = gen.insert_batches(n, pair.keys, 1, 4000, gen.seed(5, step, gen.P_INSERT))[0]
         pair.step(ins, drsf.DRSF_INSERT, f"profile insert {step}")
-        assert len(pair.gpu.phase_times()) == len(drsf.PHASES)
+        t = pair.gpu.phase_times()
+        assert list(t) == list(drsf.PHASES) + [drsf.EVENT_BRACKET]
+        # an insert batch launches nothing in the delete-only phases
+        assert all(t[k] == 0.0 for k in ("root_init", "root_chase", "orphan_list",
+                                          "orphan_scan", "store_sweep"))
+        assert t["validate"] > 0 and t[drsf.EVENT_BRACKET] >= 0
         dl = gen.delete_batches(n, pair.keys, pair.parent, 1, 4000, 2000, gen.seed(5, step, gen.P_DELETE))[0]
         pair.step(dl, drsf.DRSF_DELETE, f"profile delete {step}")
         t = pair.gpu.phase_times()
