@@ -475,7 +475,7 @@ def main():
     eb = g.m  # undirected edges, held once in the upper-half store
     # one-kernel phases: the kernel's time is the phase time less the bracket
     kernels = {
-        "k_rep_chase": (pd["root_chase"] - ev_del, 12 * g.n + g.n // 8,
+        "k_rep_chase": (pd["root_finding"] - ev_del, 12 * g.n + g.n // 8,
                         "root finding: read rep and label, write rep (4 B each per vertex), "
                         "orphan bitmap (1 bit per vertex)"),
         "k_orph_scan": (pd["orphan_scan"] - ev_del, int(8 * sd["orphan_slots"] + 40 * sd["num_orphans"]),

@@ -248,18 +248,19 @@ void drsf_snapshot_free(drsf_snapshot *snap);
 
 /*
  * Per-phase device times of the last apply in milliseconds (needs
- * opts.profile), 12 phases: validate; update-graph (cut, store update, piece
- * registration); root-finding start (rep = parent); root finding (pointer
- * chase, orphan bitmap); orphan list; orphan adjacency scan; whole-store
- * sweep; cross edges of the batch and of the inserted-edge list; replacement
- * edges (the hooking rounds queued with the update); super-forest rooting;
- * path reversal; labels.  Work that an update finishes on the host (extra
- * rounds) is not in these times; a phase that launches nothing for the
- * batch's kind (the delete-only phases of an insert batch) reads 0.  Each
- * phase time includes the fixed cost of one event record; a 13th entry
- * (written when cap > 12) is the time of an empty bracket, two events
- * recorded back to back before the update, which measures that cost.
- * Returns the number of entries written (<= cap).
+ * opts.profile), 10 phases: validate; update-graph (cut, store update, piece
+ * registration, and for deletes the start of root finding, rep = parent);
+ * root finding (pointer chase, orphan bitmap, orphan staging); orphan list;
+ * orphan adjacency scan; whole-store sweep; cross edges of the batch and of
+ * the inserted-edge list; replacement edges (the hooking rounds queued with
+ * the update); super-forest rooting; path reversal with the new labels (one
+ * launch).  Work that an update finishes on the host (extra rounds) is not
+ * in these times; a phase that launches nothing for the batch's kind (the
+ * delete-only phases of an insert batch) reads 0.  Each phase time includes
+ * the fixed cost of one event record; an 11th entry (written when cap > 10)
+ * is the time of an empty bracket, two events recorded back to back before
+ * the update, which measures that cost.  Returns the number of entries
+ * written (<= cap).
  */
 int drsf_phase_times(drsf_ctx *ctx, float *ms, int cap);
 

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -34,8 +35,8 @@ constexpr int BFS_FAST = 4;    // default search levels queued in the captured s
 constexpr int BFS_MAX = 12;    // deeper super-trees use the Euler tour instead
 constexpr int BOR_CHUNK = 3;   // rounds per host check in the continuation
 
-enum Phase { PH_VALIDATE, PH_UPDATE, PH_ROOT_INIT, PH_ROOT_CHASE, PH_ORPH_LIST, PH_ORPH_SCAN,
-             PH_SWEEP, PH_SWEEP_DELTA, PH_REPL, PH_ROOTING, PH_REVERSE, PH_LABELS, PH_N };
+enum Phase { PH_VALIDATE, PH_UPDATE, PH_ROOT, PH_ORPH_LIST, PH_ORPH_SCAN, PH_SWEEP, PH_SWEEP_DELTA,
+             PH_REPL, PH_ROOTING, PH_FINISH, PH_N };
 
 int ceil_log2(int64_t x) {
     int r = 0;
@@ -134,7 +135,9 @@ struct drsf_ctx {
     int32_t *h_bgid = nullptr;            // [max_batch]
     int32_t *h_lists = nullptr;           // vlist | ilist | tlist
     Ctl *h_ctl = nullptr;
-    unsigned long long *h_ret = nullptr;  // copy of ctlmem, then scratch words
+    unsigned long long *h_ret = nullptr;  // copy of ctlmem, then scratch words; the last is the
+                                          // completion word (seq of the finished update)
+    uint64_t seq = 0;                     // updates launched
     int32_t *h_gstat = nullptr;           // [ngraph] inside h_ret
     // captured update sequences, by kind (1 inserts, 2 deletes, 3 both)
     hipGraph_t graph[4] = {};
@@ -227,6 +230,7 @@ Dev make_dev(drsf_ctx *c) {
     d.hctl = c->h_ctl;
     d.ctlmem = c->ctlmem;
     d.hret = c->h_ret;
+    d.hdone = c->h_ret + c->ret_words + 7;
     d.ret_words = c->ret_words;
     d.bptr = c->bptr; d.bcol = c->bcol; d.eb = c->eb;
     d.lptr = c->lptr; d.lcol = c->lcol; d.twin = c->twin; d.ltwin = c->ltwin;
@@ -363,6 +367,8 @@ int alloc_state(drsf_ctx *c) {
     if ((rc = halloc(c, &c->h_bgid, mb))) return rc;
     if ((rc = halloc(c, &c->h_ctl, 1))) return rc;
     launch_fill_i32(c->tidx, n, NONE, s);
+    launch_fill_i32(c->level, c->pcap, -1, s);  // the search state is reset by each update's cleanup
+    launch_fill_i32(c->parc, c->pcap, NONE, s);
     launch_fill_u64(c->bhash, (int64_t)bh, HASH_EMPTY, s);
     launch_fill_u64(c->dhash, (int64_t)dh, HASH_EMPTY, s);
     launch_fill_u64(c->obits, (n + 63) / 64, 0, s);
@@ -620,11 +626,9 @@ void enqueue_update(drsf_ctx *c, int kind, bool profile) {
     mark(PH_VALIDATE);
     launch_classify(d, s);
     mark(PH_UPDATE);
-    launch_prepare(d, s);
+    launch_prepare(d, del, s);
     launch_register(d, s);
-    mark(PH_ROOT_INIT, del);
-    if (del) launch_rep_init(d, s);
-    mark(PH_ROOT_CHASE, del);
+    mark(PH_ROOT, del);
     if (del) launch_rep_chase(d, s);
     mark(PH_ORPH_LIST, del);
     if (del) launch_orphan_list(d, s);
@@ -642,10 +646,8 @@ void enqueue_update(drsf_ctx *c, int kind, bool profile) {
     launch_sf_root(d, s);
     launch_sf_bfs(d, 0, c->bfs_fast, s);
     launch_orient_bfs(d, c->bfs_fast, s);
-    mark(PH_REVERSE);
-    launch_reverse(d, s);
-    mark(PH_LABELS);
-    launch_labels(d, ins, del, s);
+    mark(PH_FINISH);
+    launch_finish(d, ins, del, s);
     mark(PH_N);
     launch_cleanup(d, s);  // also hands the results to the host
 }
@@ -715,8 +717,7 @@ int continue_update(drsf_ctx *c) {
         }
         if (bfs_done) launch_orient_bfs(d, lv, s);
         else launch_superforest_lr(d, lr_rounds, s);  // deep super-trees: Euler tour
-        launch_reverse(d, s);
-        launch_labels(d, c->kind & 1, c->kind & 2, s);
+        launch_finish(d, c->kind & 1, c->kind & 2, s);
     }
     launch_cleanup(d, s);  // hands the results to the host, then resets
     HIPCHK(c, hipStreamSynchronize(s));
@@ -729,6 +730,10 @@ int launch_update(drsf_ctx *c) {
     hipStream_t s = c->stream;
     // the control block is read from h_ctl by the first kernel (no copy)
     const bool prof = c->opts.profile != 0;
+    c->h_ctl->seq = ++c->seq;
+    // clear the completion word: pinned memory may hold any value (a freed
+    // context's, or scratch), and the wait must only see this update's
+    *(volatile unsigned long long *)(c->h_ret + c->ret_words + 7) = 0;
     c->kind = (c->h_ctl->has_ins ? 1 : 0) | (c->h_ctl->has_del ? 2 : 0);
     if (c->kind == 0) c->kind = 3;  // nothing but rejected or empty batches: run everything
     if (prof) {
@@ -1010,11 +1015,14 @@ int drsf_apply_async(drsf_ctx *c, const int32_t *edges, int64_t b, int op) {
                         (long long)b, (long long)c->dcap);
         if ((rc = rebuild_store(c))) return rc;
     }
-    if ((rc = stage_edges(c, edges, b))) return rc;
+    // a device batch is read in place by the first kernel (the stream orders
+    // it before later work the caller queues there); a host batch is staged
+    if (!c->opts.inputs_on_device && (rc = stage_edges(c, edges, b))) return rc;
     c->last_b = b;
     c->last_op = op;
     Ctl &k = *c->h_ctl;
     memset(&k, 0, sizeof k);
+    if (c->opts.inputs_on_device) k.edges = edges;
     k.b = b;
     k.op = op;
     k.has_ins = op == DRSF_INSERT;
@@ -1120,7 +1128,23 @@ int drsf_wait(drsf_ctx *c, drsf_view *out) {
     if (!c) return DRSF_E_ARG;
     if (c->pending) {
         c->pending = false;
-        HIPCHK(c, hipStreamSynchronize(c->stream));
+        // the last kernel writes the completion word once the results in
+        // h_ret are final: poll it (a stream synchronisation wakes up later),
+        // asking the stream now and then so that a failed or idle stream ends
+        // the wait; profiling waits for the stream (its events)
+        const volatile unsigned long long *done = c->h_ret + c->ret_words + 7;
+        bool seen = false;
+        if (!c->have_phases) {
+            for (uint32_t it = 1;; it++) {
+                if (*done == c->seq) {
+                    seen = true;
+                    break;
+                }
+                if ((it & 1023) == 0 && hipStreamQuery(c->stream) != hipErrorNotReady) break;
+            }
+            std::atomic_thread_fence(std::memory_order_acquire);
+        }
+        if (!seen || *done != c->seq) HIPCHK(c, hipStreamSynchronize(c->stream));
         const unsigned long long *k = c->h_ret + 1;
         int32_t st = *(int32_t *)c->h_ret;
         if (st == 0 && !k[C_ORIENTED]) {  // the captured rounds did not finish it

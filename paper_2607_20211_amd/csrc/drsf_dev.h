@@ -47,6 +47,7 @@ enum : int {
     C_NDELTA = 10,   // inserted-edge list length (persistent)
     C_OVOL = 11,     // adjacency slots of the listed orphan vertices
     C_NORPH = 13,    // listed orphan vertices (orphans with at least one slot)
+    C_ARRIVE = 14,   // workgroups of the running kernel that have finished (zero between kernels)
     C_LR_FINAL = 12, // buffer holding the final list ranks
     C_COUNT = 16,
 };

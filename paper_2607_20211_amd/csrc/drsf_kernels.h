@@ -21,6 +21,8 @@ struct Ctl {
     int32_t ngraph;   // graphs in this context (per-graph batch status)
     int32_t lfast;    // search levels queued before the orientation step
     int32_t smode;    // delete sweep: 0 chosen per batch, 1 always the full store
+    const int32_t *edges;  // the batch in the caller's device memory, or null: staged copy
+    uint64_t seq;          // update number, written to the completion word when done
 };
 
 // All device pointers one apply needs; passed by value to every kernel.
@@ -31,6 +33,7 @@ struct Dev {
     const Ctl *hctl;         // host copy (pinned), read by the first kernel only
     unsigned long long *ctlmem;  // status word, counters, per-graph status (ret_words words)
     unsigned long long *hret;    // pinned host copy of ctlmem, written by the last kernel
+    unsigned long long *hdone;   // pinned completion word: the update's seq once hret is final
     int64_t ret_words;
     // edge store: upper-half base CSR (row u holds v > u, ascending; TOMB bit =
     // deleted) plus a list of inserted edges with a hash index
@@ -170,10 +173,9 @@ int64_t insert_regions(int64_t b);
 // launchers of the update path (drsf_kernels.hip); grids are sized from the
 // context's maxima so that a captured sequence fits every batch
 void launch_classify(const Dev &d, hipStream_t s);
-void launch_prepare(const Dev &d, hipStream_t s);
+void launch_prepare(const Dev &d, bool del, hipStream_t s);  // with rep <- parent when del
 void launch_register(const Dev &d, hipStream_t s);
 void launch_insert_emit(const Dev &d, hipStream_t s);
-void launch_rep_init(const Dev &d, hipStream_t s);
 void launch_rep_chase(const Dev &d, hipStream_t s);
 void launch_sweep_base(const Dev &d, hipStream_t s);
 void launch_orphan_list(const Dev &d, hipStream_t s);  // plan, totals and mode, list
@@ -185,9 +187,8 @@ void launch_sf_root(const Dev &d, hipStream_t s);
 void launch_sf_bfs(const Dev &d, int l0, int l1, hipStream_t s);
 void launch_orient_bfs(const Dev &d, int levels, hipStream_t s);
 void launch_superforest_lr(const Dev &d, int lr_rounds, hipStream_t s);
-void launch_reverse(const Dev &d, hipStream_t s);
 // label kernels of the ops present (delete labels run first)
-void launch_labels(const Dev &d, bool ins, bool del, hipStream_t s);
+void launch_finish(const Dev &d, bool ins, bool del, hipStream_t s);  // path reversal and labels
 void launch_cleanup(const Dev &d, hipStream_t s);
 
 // store rebuild: live degrees of the base store, the inserted edges as

@@ -204,6 +204,23 @@ __device__ int64_t block_append(int k, unsigned long long *counter) {
     return r;
 }
 
+// True in the workgroup that arrives last among the kernel's gridDim.x
+// workgroups (every workgroup calls it once, with all its threads); that
+// workgroup also resets the counter.  No fence: it orders the workgroups'
+// earlier reads (all consumed before the barrier) before the last one's
+// writes, and publishes no data between workgroups (a device-wide fence
+// writes back the L2 and costs microseconds per workgroup).
+__device__ bool last_block_arrives(unsigned long long *arrive) {
+    __shared__ bool s_last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s_last = atomicAdd(arrive, 1ull) == (unsigned long long)gridDim.x - 1;
+        if (s_last) atomicExch(arrive, 0ull);
+    }
+    __syncthreads();
+    return s_last;
+}
+
 __device__ __forceinline__ int edge_op(const Dev &d, int64_t i) {
     return d.ctl->op == 2 ? (int)d.bop[i] : d.ctl->op;
 }
@@ -238,9 +255,10 @@ __global__ __launch_bounds__(BLOCK) void k_classify(Dev d) {
             reinterpret_cast<const uint64_t *>(hc)[threadIdx.x];
     const int64_t b = hc->b;
     const int opm = hc->op;
+    const int32_t *be = hc->edges ? hc->edges : d.bedges;  // caller's device batch, or the staged one
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < b; i += stride) {
-        const int32_t u = d.bedges[2 * i], v = d.bedges[2 * i + 1];
+        const int32_t u = be[2 * i], v = be[2 * i + 1];
         const int32_t g = edge_graph(d, i);
         const int32_t lo_ok = d.goff ? d.goff[g] : 0, hi_ok = d.goff ? d.goff[g + 1] : d.n;
         d.bslot[i] = NONE;
@@ -314,10 +332,34 @@ __global__ __launch_bounds__(BLOCK) void k_classify(Dev d) {
 // root gets owner[root] = (batch index, side) by plain stores; whichever
 // store lands last owns the registration in k_register (no contended atomics
 // on the roots of big trees).
-__global__ __launch_bounds__(BLOCK) void k_prepare(Dev d) {
+// Workgroups from gb on (launched for batches with deletes) start root
+// finding instead: rep <- parent over the listed vertex blocks, one wave per
+// block, four vertices per lane (16-byte accesses).  A cut child may be
+// copied before or after its cut; k_register then sets rep[c] = c.
+__device__ void rep_init(const Dev &d, int64_t bid, int64_t nblk) {
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    const int64_t nb = (d.n + BLOCK - 1) / BLOCK;
+    const int w = threadIdx.x / WAVE;
+    for (int64_t j = bid * (BLOCK / WAVE) + w;; j += nblk * (BLOCK / WAVE)) {
+        const int64_t blk = list_block(d.vlist, d.ctl->nvl, j, nb);
+        if (blk < 0) break;
+        const int64_t v = blk * BLOCK + lane_id() * 4;
+        if (v + 4 <= d.n) {
+            *reinterpret_cast<v4i *>(d.rep + v) = *reinterpret_cast<const v4i *>(d.parent + v);
+        } else {
+            for (int64_t u = v; u < d.n && u < v + 4; u++) d.rep[u] = d.parent[u];
+        }
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_prepare(Dev d, int gb) {
     if (*d.status) return;
+    if ((int)blockIdx.x >= gb) {
+        if (d.ctl->has_del) rep_init(d, (int64_t)blockIdx.x - gb, (int64_t)gridDim.x - gb);
+        return;
+    }
     const int64_t b = d.ctl->b;
-    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    const int64_t stride = (int64_t)gb * BLOCK;
     for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < b; base += stride) {
         const int64_t i = base + threadIdx.x;
         const bool valid = i < b && edge_ok(d, i);
@@ -372,7 +414,11 @@ __global__ __launch_bounds__(BLOCK) void k_register(Dev d) {
             del = edge_op(d, i) == 1;
             if (del) {
                 const int32_t c = d.bchild[i];
-                if (c != NONE) { a = c; c2 = d.label[c]; }
+                if (c != NONE) {
+                    a = c;
+                    c2 = d.label[c];
+                    d.rep[c] = c;  // the cut child roots its piece of F-hat
+                }
             } else {
                 const uint64_t k = d.bkey[i];
                 const int32_t la = d.label[key_lo(k)], lb = d.label[key_hi(k)];
@@ -421,23 +467,6 @@ __global__ __launch_bounds__(BLOCK) void k_insert_emit(Dev d) {
 
 // ----------------------------------------------- a4: root finding (delete)
 
-// One wave per vertex block, four vertices per lane (16-byte accesses).
-__global__ __launch_bounds__(BLOCK) void k_rep_init(Dev d) {
-    if (*d.status || !d.ctl->has_del) return;
-    typedef int v4i __attribute__((ext_vector_type(4)));
-    const int64_t nb = (d.n + BLOCK - 1) / BLOCK;
-    const int w = threadIdx.x / WAVE;
-    for (int64_t j = (int64_t)blockIdx.x * (BLOCK / WAVE) + w;; j += (int64_t)gridDim.x * (BLOCK / WAVE)) {
-        const int64_t blk = list_block(d.vlist, d.ctl->nvl, j, nb);
-        if (blk < 0) break;
-        const int64_t v = blk * BLOCK + lane_id() * 4;
-        if (v + 4 <= d.n) {
-            *reinterpret_cast<v4i *>(d.rep + v) = *reinterpret_cast<const v4i *>(d.parent + v);
-        } else {
-            for (int64_t u = v; u < d.n && u < v + 4; u++) d.rep[u] = d.parent[u];
-        }
-    }
-}
 
 // rep[v] <- root of v in F-hat.  Each thread chases rep[] upward; entries
 // already finished by other threads are roots, so chains shorten as the
@@ -1228,19 +1257,11 @@ __global__ __launch_bounds__(BLOCK) void k_sf_root(Dev d) {
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_sf_level_init(Dev d) {
-    if (*d.status || !d.cnt[C_DONE_BOR]) return;
-    const int64_t np = (int64_t)d.cnt[C_NP];
-    const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < np; p += stride) {
-        const int32_t S = (int32_t)(uint32_t)d.srkey[d.comp[p]];
-        d.level[p] = S == (int32_t)p ? 0 : -1;
-        d.parc[p] = NONE;
-    }
+// The super-root piece of p's component (after k_sf_root).
+__device__ __forceinline__ bool is_super_root(const Dev &d, int32_t p) {
+    return (int32_t)(uint32_t)d.srkey[d.comp[p]] == p;
 }
 
-// Level-synchronous breadth-first search over the replacement edges from the
-// super-roots (the super-forest of Algorithm 2 rooted at the super-roots):
 // arc i*2 goes from the piece of x to the piece of y, i*2+1 back.  In a tree
 // every piece has exactly one neighbour on the previous level, so each
 // piece's level and parent arc have a single writer.  A level that reaches no
@@ -1251,10 +1272,21 @@ __global__ __launch_bounds__(BLOCK) void k_sf_bfs(Dev d, int L) {
     const int64_t na = 2 * (int64_t)d.cnt[C_NER];
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     bool active = false;
+    // every level starts at -1 (cleanup of the previous update); level 0 is
+    // the super-roots, recognised here and marked on the first level
     for (int64_t a = (int64_t)blockIdx.x * BLOCK + threadIdx.x; a < na; a += stride) {
         const int4 e = d.er[a >> 1];
         const int32_t src = (a & 1) ? e.w : e.z, dst = (a & 1) ? e.z : e.w;
-        if (d.level[src] == L && d.level[dst] < 0) {
+        bool from;
+        if (L == 0) {
+            from = is_super_root(d, src);
+            if (from) d.level[src] = 0;  // same value from every arc of src
+        } else {
+            from = d.level[src] == L;
+        }
+        // a super-root's neighbours are on level 1, so level 0 reaches no
+        // super-root; later levels never see one at -1 (marked on level 0)
+        if (from && d.level[dst] < 0) {
             d.level[dst] = L + 1;
             d.parc[dst] = (int32_t)a;
             active = true;
@@ -1287,7 +1319,7 @@ __global__ __launch_bounds__(BLOCK) void k_orient_bfs(Dev d, int levels) {
                 e1 = true;
                 if ((a & 1) == 0) { q1.start = e.y; q1.newpar = e.x; q1.stop = d.prt[e.w]; }
                 else { q1.start = e.x; q1.newpar = e.y; q1.stop = d.prt[e.z]; }
-            } else if (d.level[p] < 0) {
+            } else if (d.level[p] < 0 && !is_super_root(d, (int32_t)p)) {
                 atomicOr(d.status, ST_ROUND_BOUND);  // piece not reached: search incomplete
             }
             if (d.comp[p] == (int32_t)p) {
@@ -1435,10 +1467,10 @@ __global__ __launch_bounds__(BLOCK) void k_orient_lr(Dev d, int lr_rounds) {
 // the attach path of a non-root piece or the re-root path of a super-root
 // piece), so the walks touch disjoint vertices; each thread reads a parent
 // before overwriting it (the old orientation is read exactly once).
-__device__ void reverse_paths(const Dev &d) {
+__device__ void reverse_paths(const Dev &d, int64_t bid, int64_t nblk) {
     const int64_t nr = (int64_t)d.cnt[C_NR];
-    const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < nr; i += stride) {
+    const int64_t stride = nblk * BLOCK;
+    for (int64_t i = bid * BLOCK + threadIdx.x; i < nr; i += stride) {
         const PathReq q = d.paths[i];
         int32_t prev = q.newpar, cur = q.start;
         for (int64_t steps = 0;; steps++) {
@@ -1451,13 +1483,9 @@ __device__ void reverse_paths(const Dev &d) {
         }
     }
 }
-__global__ __launch_bounds__(BLOCK) void k_reverse(Dev d) {
-    if (*d.status || !d.cnt[C_ORIENTED]) return;
-    reverse_paths(d);
-}
 __global__ __launch_bounds__(BLOCK) void k_reverse_all(Dev d) {
     if (*d.status) return;
-    reverse_paths(d);
+    reverse_paths(d, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------------------ a9: labels
@@ -1465,14 +1493,13 @@ __global__ __launch_bounds__(BLOCK) void k_reverse_all(Dev d) {
 // Deletes: a vertex cut off from its old root takes its new component's
 // label.  Runs before the insert labels (mixed batches).  Restores
 // rep == label for the next update.
-__global__ __launch_bounds__(BLOCK) void k_label_delete(Dev d) {
-    if (*d.status || !d.cnt[C_ORIENTED] || !d.ctl->has_del) return;
+__device__ void label_delete(const Dev &d, int64_t bid, int64_t nblk) {
     if (d.cnt[C_OMODE]) {
         // the orphan list holds every orphan: relabel them, clear their
         // bitmap words and their blocks' figures (idempotent stores)
         const int64_t no = (int64_t)d.cnt[C_NORPH];
-        const int64_t stride = (int64_t)gridDim.x * BLOCK;
-        for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < no; i += stride) {
+        const int64_t stride = nblk * BLOCK;
+        for (int64_t i = bid * BLOCK + threadIdx.x; i < no; i += stride) {
             const int32_t v = d.olist[i].v;
             const int32_t p = d.tidx[d.rep[v]];
             if (p >= 0) {
@@ -1489,7 +1516,7 @@ __global__ __launch_bounds__(BLOCK) void k_label_delete(Dev d) {
         return;
     }
     const int64_t nb = (d.n + BLOCK - 1) / BLOCK;
-    for (int64_t j = blockIdx.x;; j += gridDim.x) {
+    for (int64_t j = bid;; j += nblk) {
         const int64_t blk = list_block(d.vlist, d.ctl->nvl, j, nb);
         if (blk < 0) break;
         const int64_t v = blk * BLOCK + threadIdx.x;
@@ -1518,13 +1545,13 @@ __global__ __launch_bounds__(BLOCK) void k_label_delete(Dev d) {
 
 // Inserts: every vertex of a tree that merged into another takes the new
 // component's label (the tree is found through its old label, its root).
-__global__ __launch_bounds__(BLOCK) void k_label_insert(Dev d) {
-    if (*d.status || !d.cnt[C_ORIENTED] || !d.ctl->has_ins || d.cnt[C_NP] == 0) return;
+__device__ void label_insert(const Dev &d, int64_t bid, int64_t nblk) {
+    if (d.cnt[C_NP] == 0) return;
     typedef int v4i __attribute__((ext_vector_type(4)));
     const int64_t nb = (d.n + BLOCK - 1) / BLOCK;
     const int w = threadIdx.x / WAVE;
     // one wave per vertex block, four vertices per lane
-    for (int64_t j = (int64_t)blockIdx.x * (BLOCK / WAVE) + w;; j += (int64_t)gridDim.x * (BLOCK / WAVE)) {
+    for (int64_t j = bid * (BLOCK / WAVE) + w;; j += nblk * (BLOCK / WAVE)) {
         const int64_t blk = list_block(d.ilist, d.ctl->nil, j, nb);
         if (blk < 0) break;
         const int64_t v = blk * BLOCK + lane_id() * 4;
@@ -1551,33 +1578,61 @@ __global__ __launch_bounds__(BLOCK) void k_label_insert(Dev d) {
     }
 }
 
-// ------------------------------------------------------------- cleanup
-
-// Resets the per-update scratch once the update has finished (or failed).
-__global__ __launch_bounds__(BLOCK) void k_cleanup_slots(Dev d) {
-    if (!d.cnt[C_ORIENTED] && !*d.status) return;  // unfinished: the host continues
-    const int64_t np = (int64_t)d.cnt[C_NP];
-    const int64_t b = d.ctl->b;
-    const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < np; p += stride)
-        d.tidx[d.prt[p]] = NONE;
-    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < b; i += stride)
-        if (d.bslot[i] != NONE) d.bhash[d.bslot[i]] = HASH_EMPTY;
-    for (int64_t t = d.ctl->rlo + (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < d.ctl->rhi; t += stride)
-        d.rcnt[t] = 0;
+// Path reversal and labels touch disjoint data (parent and the paths; label,
+// rep and the orphan scratch), so one launch does both: workgroups below
+// grev reverse paths, the rest relabel (lab: 1 inserts, 2 deletes).
+__global__ __launch_bounds__(BLOCK) void k_finish(Dev d, int lab, int grev) {
+    if (*d.status || !d.cnt[C_ORIENTED]) return;
+    if ((int)blockIdx.x < grev) {
+        reverse_paths(d, blockIdx.x, grev);
+    } else {
+        const int64_t bid = (int64_t)blockIdx.x - grev, nblk = (int64_t)gridDim.x - grev;
+        if (lab == 2 && d.ctl->has_del) label_delete(d, bid, nblk);
+        if (lab == 1 && d.ctl->has_ins) label_insert(d, bid, nblk);
+    }
 }
 
-// Hands status, counters and per-graph batch status to the host (pinned
-// memory, also when the update is unfinished and the host continues it),
-// then resets them once the update has finished.
-__global__ void k_cleanup_counters(Dev d) {
-    for (int64_t t = threadIdx.x; t < d.ret_words; t += blockDim.x) d.hret[t] = d.ctlmem[t];
+// The insert labels of a mixed batch, after the delete labels.
+__global__ __launch_bounds__(BLOCK) void k_label_insert(Dev d) {
+    if (*d.status || !d.cnt[C_ORIENTED] || !d.ctl->has_ins) return;
+    label_insert(d, blockIdx.x, gridDim.x);
+}
+
+// ------------------------------------------------------------- cleanup
+
+// Resets the per-update scratch once the update has finished (or failed);
+// the workgroup that finishes last then hands status, counters and per-graph
+// batch status to the host (pinned memory, also when the update is
+// unfinished and the host continues it) and resets them once the update has
+// finished.
+__global__ __launch_bounds__(BLOCK) void k_cleanup(Dev d) {
+    const bool fin = d.cnt[C_ORIENTED] || *d.status;  // else unfinished: the host continues
+    if (fin) {
+        const int64_t np = (int64_t)d.cnt[C_NP];
+        const int64_t b = d.ctl->b;
+        const int64_t stride = (int64_t)gridDim.x * BLOCK;
+        for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < np; p += stride) {
+            d.tidx[d.prt[p]] = NONE;
+            d.level[p] = -1;  // the super-forest search starts from all -1
+            d.parc[p] = NONE;
+        }
+        for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < b; i += stride)
+            if (d.bslot[i] != NONE) d.bhash[d.bslot[i]] = HASH_EMPTY;
+        for (int64_t t = d.ctl->rlo + (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < d.ctl->rhi;
+             t += stride)
+            d.rcnt[t] = 0;
+    }
+    if (!last_block_arrives(&d.cnt[C_ARRIVE])) return;
+    for (int64_t t = threadIdx.x; t < d.ret_words; t += BLOCK) d.hret[t] = d.ctlmem[t];
     __threadfence_system();
-    if (!d.cnt[C_ORIENTED] && !*d.status) return;
-    __syncthreads();  // every thread has copied and read the flags before any reset
+    __syncthreads();  // every thread has copied before the completion word and any reset
+    if (threadIdx.x == 0)
+        __hip_atomic_store(d.hdone, (unsigned long long)d.ctl->seq, __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+    if (!fin) return;
     const int t = threadIdx.x;
     if (t < C_TOTAL && t != C_NDELTA) d.cnt[t] = 0;
-    for (int64_t g = threadIdx.x; g < d.ctl->ngraph; g += blockDim.x) d.gstat[g] = 0;
+    for (int64_t g = threadIdx.x; g < d.ctl->ngraph; g += BLOCK) d.gstat[g] = 0;
     if (t == 0) *d.status = 0;
 }
 
@@ -1589,17 +1644,16 @@ int64_t insert_regions(int64_t b) { return (b + BLOCK - 1) / BLOCK; }
 void launch_classify(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_classify, dim3(grid_for(d.max_b, BLOCK)), dim3(BLOCK), 0, s, d);
 }
-void launch_prepare(const Dev &d, hipStream_t s) {
-    hipLaunchKernelGGL(k_prepare, dim3(grid_for(d.max_b, BLOCK)), dim3(BLOCK), 0, s, d);
+void launch_prepare(const Dev &d, bool del, hipStream_t s) {
+    const int gb = grid_for(d.max_b, BLOCK);
+    const int gi = del ? grid_for(d.nvb, BLOCK / WAVE, GRID_CAP) : 0;
+    hipLaunchKernelGGL(k_prepare, dim3(gb + gi), dim3(BLOCK), 0, s, d, gb);
 }
 void launch_register(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_register, dim3(grid_for(d.max_b, BLOCK)), dim3(BLOCK), 0, s, d);
 }
 void launch_insert_emit(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_insert_emit, dim3((unsigned)insert_regions(d.max_b)), dim3(BLOCK), 0, s, d);
-}
-void launch_rep_init(const Dev &d, hipStream_t s) {
-    hipLaunchKernelGGL(k_rep_init, dim3(grid_for(d.nvb, BLOCK / WAVE, GRID_CAP)), dim3(BLOCK), 0, s, d);
 }
 void launch_rep_chase(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_rep_chase, dim3(grid_for(d.nvb, REP_CH, GRID_CAP)), dim3(BLOCK), 0, s, d);
@@ -1640,7 +1694,6 @@ void launch_boruvka(const Dev &d, int r0, int r1, int64_t units, hipStream_t s) 
 void launch_sf_root(const Dev &d, hipStream_t s) {
     const int gp = grid_for(d.pcap, BLOCK, SMALL_CAP);
     hipLaunchKernelGGL(k_sf_root, dim3(gp), dim3(BLOCK), 0, s, d);
-    hipLaunchKernelGGL(k_sf_level_init, dim3(gp), dim3(BLOCK), 0, s, d);
 }
 void launch_sf_bfs(const Dev &d, int l0, int l1, hipStream_t s) {
     const int ga = grid_for(2 * d.ercap, BLOCK, SMALL_CAP);
@@ -1658,23 +1711,22 @@ void launch_superforest_lr(const Dev &d, int lr_rounds, hipStream_t s) {
     hipLaunchKernelGGL(k_orient_lr, dim3(grid_for(d.ercap + d.pcap, BLOCK, SMALL_CAP)), dim3(BLOCK), 0, s,
                        d, lr_rounds);
 }
-void launch_reverse(const Dev &d, hipStream_t s) {
-    hipLaunchKernelGGL(k_reverse, dim3(grid_for(d.pathcap, BLOCK, SMALL_CAP)), dim3(BLOCK), 0, s, d);
-}
 void launch_reverse_all(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_reverse_all, dim3(grid_for(d.pathcap, BLOCK, 2048)), dim3(BLOCK), 0, s, d);
 }
-void launch_labels(const Dev &d, bool ins, bool del, hipStream_t s) {
-    const int g = grid_for(d.n, BLOCK, GRID_CAP);
-    if (del) hipLaunchKernelGGL(k_label_delete, dim3(g), dim3(BLOCK), 0, s, d);
-    if (ins)
+void launch_finish(const Dev &d, bool ins, bool del, hipStream_t s) {
+    const int grev = grid_for(d.pathcap, BLOCK, SMALL_CAP);
+    // deletes relabel per vertex block or per listed orphan, inserts one wave
+    // per vertex block
+    const int glab = del ? grid_for(d.n, BLOCK, GRID_CAP) : grid_for(d.nvb, BLOCK / WAVE, GRID_CAP);
+    hipLaunchKernelGGL(k_finish, dim3(grev + glab), dim3(BLOCK), 0, s, d, del ? 2 : 1, grev);
+    if (ins && del)
         hipLaunchKernelGGL(k_label_insert, dim3(grid_for(d.nvb, BLOCK / WAVE, GRID_CAP)), dim3(BLOCK), 0,
                            s, d);
 }
 void launch_cleanup(const Dev &d, hipStream_t s) {
     int64_t m = d.pcap > d.max_b ? d.pcap : d.max_b;
-    hipLaunchKernelGGL(k_cleanup_slots, dim3(grid_for(m, BLOCK, SMALL_CAP)), dim3(BLOCK), 0, s, d);
-    hipLaunchKernelGGL(k_cleanup_counters, dim3(1), dim3(256), 0, s, d);
+    hipLaunchKernelGGL(k_cleanup, dim3(grid_for(m, BLOCK, SMALL_CAP)), dim3(BLOCK), 0, s, d);
 }
 
 // ------------------------------------------------------ store rebuild

@@ -20,10 +20,10 @@ DRSF_OK, DRSF_E_ARG, DRSF_E_NOMEM, DRSF_E_FOREST = 0, -1, -2, -3
 DRSF_E_BATCH, DRSF_E_CAPACITY, DRSF_E_DEVICE, DRSF_E_STATE = -4, -5, -6, -7
 DRSF_E_BUDGET = -8
 DRSF_SERVER_DIGESTS, DRSF_SERVER_SERIAL = 1, 2
-PHASES = ("validate", "update_graph", "root_init", "root_chase", "orphan_list", "orphan_scan",
+PHASES = ("validate", "update_graph", "root_finding", "orphan_list", "orphan_scan",
           "store_sweep", "batch_and_inserted_scan", "replacement_edges", "superforest_rooting",
-          "path_reversal", "labels")
-# the 13th entry of drsf_phase_times: two events back to back (the fixed cost
+          "reversal_and_labels")
+# the entry after the phases in drsf_phase_times: two events back to back (the fixed cost
 # of the event record that every phase time includes)
 EVENT_BRACKET = "event_bracket"
 

@@ -379,8 +379,8 @@ def test_profile_mode_direct_launches():
         t = pair.gpu.phase_times()
         assert list(t) == list(drsf.PHASES) + [drsf.EVENT_BRACKET]
         # an insert batch launches nothing in the delete-only phases
-        assert all(t[k] == 0.0 for k in ("root_init", "root_chase", "orphan_list",
-                                          "orphan_scan", "store_sweep"))
+        assert all(t[k] == 0.0 for k in ("root_finding", "orphan_list", "orphan_scan",
+                                          "store_sweep"))
         assert t["validate"] > 0 and t[drsf.EVENT_BRACKET] >= 0
         dl = gen.delete_batches(n, pair.keys, pair.parent, 1, 4000, 2000, gen.seed(5, step, gen.P_DELETE))[0]
         pair.step(dl, drsf.DRSF_DELETE, f"profile delete {step}")
