@@ -166,6 +166,14 @@ constexpr int GRID_CAP = 2048;
 #endif
 constexpr int SMALL_CAP = DRSF_SMALL_CAP;  // kernels over pieces, arcs and paths
 constexpr int EDGE_CAP = DRSF_EDGE_CAP;    // first hooking selections
+#ifndef DRSF_FINISH_CAP
+#define DRSF_FINISH_CAP 2048
+#endif
+#ifndef DRSF_COPY_CAP
+#define DRSF_COPY_CAP 2048
+#endif
+constexpr int FINISH_CAP = DRSF_FINISH_CAP;  // each part of path reversal + labels
+constexpr int COPY_CAP = DRSF_COPY_CAP;      // rep <- parent beside the store update
 int grid_for(int64_t items, int64_t per_block, int cap = GRID_CAP);
 int64_t delta_tiles(int64_t count);
 int64_t insert_regions(int64_t b);

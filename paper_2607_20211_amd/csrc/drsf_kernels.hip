@@ -875,9 +875,13 @@ __global__ __launch_bounds__(BLOCK) void k_orph_total(Dev d) {
 // index of the orphan holding its first slot.
 __global__ __launch_bounds__(BLOCK) void k_orph_fill(Dev d) {
     if (*d.status || !d.ctl->has_del || !d.cnt[C_OMODE]) return;
-    const int wv = threadIdx.x / WAVE;
-    // one wave per vertex block (blocks hold few orphans)
-    for (int64_t j = (int64_t)blockIdx.x * (BLOCK / WAVE) + wv;; j += (int64_t)gridDim.x * (BLOCK / WAVE)) {
+    // FILL_LANES lanes per vertex block (blocks hold few orphans), so one
+    // wave covers WAVE / FILL_LANES blocks with all its loads in flight
+    constexpr int FILL_LANES = 8;
+    const int64_t per_block = BLOCK / FILL_LANES;
+    const int sub = threadIdx.x % FILL_LANES;
+    for (int64_t j = (int64_t)blockIdx.x * per_block + threadIdx.x / FILL_LANES;;
+         j += (int64_t)gridDim.x * per_block) {
         const int64_t blk = list_block(d.vlist, d.ctl->nvl, j, d.nvb);
         if (blk < 0) break;
         const int32_t nc = d.bcnt[blk];
@@ -885,7 +889,7 @@ __global__ __launch_bounds__(BLOCK) void k_orph_fill(Dev d) {
         const unsigned long long gp = d.gpre[blk / BLOCK];
         const int64_t ob = (int64_t)ocnt(gp) + d.opre[blk];
         const int64_t vb = (int64_t)ovol(gp) + d.bpre[blk];
-        for (int32_t i = lane_id(); i < nc; i += WAVE) {
+        for (int32_t i = sub; i < nc; i += FILL_LANES) {
             OrphEnt o = d.ostage[blk * BLOCK + i];
             const int64_t idx = ob + i;
             o.pre += vb;
@@ -1646,7 +1650,7 @@ void launch_classify(const Dev &d, hipStream_t s) {
 }
 void launch_prepare(const Dev &d, bool del, hipStream_t s) {
     const int gb = grid_for(d.max_b, BLOCK);
-    const int gi = del ? grid_for(d.nvb, BLOCK / WAVE, GRID_CAP) : 0;
+    const int gi = del ? grid_for(d.nvb, BLOCK / WAVE, COPY_CAP) : 0;
     hipLaunchKernelGGL(k_prepare, dim3(gb + gi), dim3(BLOCK), 0, s, d, gb);
 }
 void launch_register(const Dev &d, hipStream_t s) {
@@ -1666,7 +1670,7 @@ void launch_sweep_base(const Dev &d, hipStream_t s) {
 void launch_orphan_list(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_orph_plan, dim3(grid_for(d.nvb, BLOCK, 1 << 30)), dim3(BLOCK), 0, s, d);
     hipLaunchKernelGGL(k_orph_total, dim3(1), dim3(BLOCK), 0, s, d);
-    hipLaunchKernelGGL(k_orph_fill, dim3(grid_for(d.nvb, BLOCK / WAVE, GRID_CAP)), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_orph_fill, dim3(grid_for(d.nvb, BLOCK / 8, GRID_CAP)), dim3(BLOCK), 0, s, d);
 }
 void launch_orphan_scan(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_orph_scan, dim3(grid_for((d.ntiles * TILE) / OR_MAX_FRAC, OR_W, GRID_CAP)),
@@ -1715,10 +1719,11 @@ void launch_reverse_all(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_reverse_all, dim3(grid_for(d.pathcap, BLOCK, 2048)), dim3(BLOCK), 0, s, d);
 }
 void launch_finish(const Dev &d, bool ins, bool del, hipStream_t s) {
-    const int grev = grid_for(d.pathcap, BLOCK, SMALL_CAP);
+    // an update reverses at most one path per piece and per replacement edge
+    const int grev = grid_for(d.ercap + d.pcap, BLOCK, FINISH_CAP);
     // deletes relabel per vertex block or per listed orphan, inserts one wave
     // per vertex block
-    const int glab = del ? grid_for(d.n, BLOCK, GRID_CAP) : grid_for(d.nvb, BLOCK / WAVE, GRID_CAP);
+    const int glab = del ? grid_for(d.n, BLOCK, FINISH_CAP) : grid_for(d.nvb, BLOCK / WAVE, FINISH_CAP);
     hipLaunchKernelGGL(k_finish, dim3(grev + glab), dim3(BLOCK), 0, s, d, del ? 2 : 1, grev);
     if (ins && del)
         hipLaunchKernelGGL(k_label_insert, dim3(grid_for(d.nvb, BLOCK / WAVE, GRID_CAP)), dim3(BLOCK), 0,
