@@ -89,11 +89,10 @@ struct drsf_ctx {
     int32_t *parent = nullptr, *label = nullptr, *rep = nullptr;
     uint64_t *obits = nullptr;
     // pieces
-    int32_t *tidx = nullptr, *owner = nullptr, *prt = nullptr, *pmin = nullptr, *comp = nullptr,
-            *hook = nullptr;
+    int32_t *tidx = nullptr, *owner = nullptr, *prt = nullptr, *pmin = nullptr, *comp = nullptr;
     uint8_t *pkeep = nullptr;
     int32_t *head = nullptr, *newlab = nullptr, *level = nullptr, *parc = nullptr;
-    uint64_t *best = nullptr, *srkey = nullptr;
+    uint64_t *hook = nullptr, *best = nullptr, *srkey = nullptr;
     int64_t pcap = 0;
     // batch
     int64_t max_batch = 0;
@@ -312,12 +311,12 @@ int alloc_state(drsf_ctx *c) {
     if ((rc = dalloc(c, &c->prt, c->pcap))) return rc;
     if ((rc = dalloc(c, &c->pmin, c->pcap))) return rc;
     if ((rc = dalloc(c, &c->comp, c->pcap))) return rc;
-    if ((rc = dalloc(c, &c->hook, c->pcap))) return rc;
+    if ((rc = dalloc(c, &c->hook, c->pcap))) return rc;  // set per piece at registration
     if ((rc = dalloc(c, &c->head, c->pcap))) return rc;
     if ((rc = dalloc(c, &c->level, c->pcap))) return rc;
     if ((rc = dalloc(c, &c->parc, c->pcap))) return rc;
     if ((rc = dalloc(c, &c->newlab, c->pcap))) return rc;
-    if ((rc = dalloc(c, &c->best, c->pcap))) return rc;
+    if ((rc = dalloc(c, &c->best, 2 * c->pcap))) return rc;
     if ((rc = dalloc(c, &c->srkey, c->pcap))) return rc;
     if ((rc = dalloc(c, &c->bedges, 2 * mb))) return rc;
     if ((rc = dalloc(c, &c->bop, mb))) return rc;

@@ -14,6 +14,7 @@ constexpr uint64_t KEY_DEAD = ~0ull;       // deleted entry of the inserted-edge
 constexpr uint64_t HASH_EMPTY = ~0ull;
 constexpr uint64_t HASH_TOMB_BIT = 1ull << 63;
 constexpr int32_t NONE = -1;
+constexpr uint64_t HOOK_NONE = ~0ull;  // a component that has not hooked (largest round tag)
 
 // Sweep tile: every thread of a 256-thread workgroup takes EPT consecutive
 // stored edges, so one workgroup covers TILE edges.

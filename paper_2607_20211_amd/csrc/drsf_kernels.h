@@ -88,8 +88,10 @@ struct Dev {
     int32_t *prt;            // [pcap] dense id -> piece root vertex
     int32_t *pmin;           // [pcap] smallest vertex of the piece
     int32_t *comp;           // [pcap] current component (a dense piece id)
-    int32_t *hook;           // [pcap] component this one hooked onto in the current round
-    uint64_t *best;          // [pcap] lowest key of a cross edge leaving the component
+    uint64_t *hook;          // [pcap] (round << 32 | component) the component hooked onto; ~0 before
+    uint64_t *best;          // [2 pcap] lowest key of a cross edge leaving the component, in
+                             // two buffers by round parity (one is selected into while the
+                             // other is cleared)
     uint64_t *srkey;         // [pcap] (smallest vertex << 32 | piece) of the component
     int32_t *head;           // [pcap] first arc of the piece's super-forest arc list
     int32_t *level;          // [pcap] search level of the piece in its super-tree, -1 unreached

@@ -111,8 +111,9 @@ __device__ __forceinline__ void init_piece(const Dev &d, int64_t id, int32_t v, 
     d.prt[id] = v;
     d.pmin[id] = v;
     d.comp[id] = (int32_t)id;
-    d.hook[id] = NONE;
+    d.hook[id] = HOOK_NONE;
     d.best[id] = KEY_INF;
+    d.best[d.pcap + id] = KEY_INF;
     d.srkey[id] = KEY_INF;
     d.head[id] = NONE;
     d.newlab[id] = v;
@@ -1069,6 +1070,28 @@ __global__ __launch_bounds__(BLOCK) void k_orph_scan(Dev d) {
 
 // ------------------------------- a6: replacement edges by hooking rounds
 
+// Hooks.  A component hooks at most once per update, so hook[] is written
+// once per component and tagged with its round; the components are never
+// compressed between rounds.  The root of x's component at the start of
+// round r follows the hooks made before round r (a round's own hooks, being
+// written meanwhile, are skipped by their tag).
+__device__ __forceinline__ uint64_t hook_pack(int r, int32_t other) {
+    return ((uint64_t)(uint32_t)r << 32) | (uint32_t)other;
+}
+__device__ int32_t comp_root(const Dev &d, int32_t x, uint32_t r, int64_t np) {
+    for (int64_t steps = 0;; steps++) {
+        const uint64_t h = d.hook[x];
+        if ((uint32_t)(h >> 32) >= r) return x;  // a root then (HOOK_NONE has the largest tag)
+        x = (int32_t)(uint32_t)h;
+        if (steps > np) {
+            atomicOr(d.status, ST_WALK_BOUND);
+            return x;
+        }
+    }
+}
+// the buffer of best[] that round r selects into
+__device__ __forceinline__ uint64_t *best_of(const Dev &d, int r) { return d.best + (r & 1) * d.pcap; }
+
 // A component selects the lowest key among the cross edges it touches.  In a
 // delete, a component that holds an old root piece never selects: every cross
 // edge lies inside one old component, whose root piece is unique, so every
@@ -1076,10 +1099,10 @@ __global__ __launch_bounds__(BLOCK) void k_orph_scan(Dev d) {
 // edge is the lowest key leaving its component (cut property), so the
 // chosen set is still the Kruskal one.
 __device__ __forceinline__ void select_edge(const Dev &d, bool live, const Cross &e, int32_t ca,
-                                            int32_t cb) {
+                                            int32_t cb, uint64_t *best) {
     const bool sa = live && !d.pkeep[ca], sb = live && !d.pkeep[cb];
-    group_min_u64(sa, ca, e.key, d.best);
-    group_min_u64(sb, cb, e.key, d.best);
+    group_min_u64(sa, ca, e.key, best);
+    group_min_u64(sb, cb, e.key, best);
 }
 
 // Round 0: every cross edge is live and every component is a single piece.
@@ -1087,10 +1110,6 @@ __device__ __forceinline__ void select_edge(const Dev &d, bool live, const Cross
 // sums the region lengths (the number of cross edges found).
 __global__ __launch_bounds__(BLOCK) void k_bor_round0(Dev d) {
     if (*d.status) return;
-    const int64_t np = (int64_t)d.cnt[C_NP];
-    const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < np; p += stride)
-        d.hook[p] = NONE;
     // regions below ntiles hold the orphan scan's output when it ran: those
     // edges took part in this round's selection already
     const bool om = d.cnt[C_OMODE] != 0;
@@ -1106,7 +1125,7 @@ __global__ __launch_bounds__(BLOCK) void k_bor_round0(Dev d) {
             e.pa = e.pb = 0;
             e.key = 0;
             if (live) e = in[i];
-            select_edge(d, live, e, e.pa, e.pb);
+            select_edge(d, live, e, e.pa, e.pb, d.best);
         }
     }
     if (blockIdx.x == 0) {
@@ -1129,9 +1148,7 @@ __global__ __launch_bounds__(BLOCK) void k_bor_select(Dev d, int r) {
     Cross *out = (r & 1) ? d.x1 : d.x0;
     unsigned long long *cout = &d.cnt[(r & 1) ? C_NX1 : C_NX0];
     const int64_t np = (int64_t)d.cnt[C_NP];
-    const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < np; p += stride)
-        d.hook[p] = NONE;
+    uint64_t *best = best_of(d, r);
     __shared__ unsigned long long obase;
     // work units: regions of x0 (round 1) or BLOCK-sized chunks of a dense list
     int64_t u0, u1;
@@ -1163,12 +1180,12 @@ __global__ __launch_bounds__(BLOCK) void k_bor_select(Dev d, int r) {
             e.pa = e.pb = 0;
             int32_t ca = 0, cb = 0;
             if (i < count) {
-                e = in[i];
-                ca = d.comp[e.pa];
-                cb = d.comp[e.pb];
+                e = in[i];  // ends: pieces (round 1) or components at the last round's start
+                ca = comp_root(d, e.pa, (uint32_t)r, np);
+                cb = comp_root(d, e.pb, (uint32_t)r, np);
                 live = ca != cb;
             }
-            select_edge(d, live, e, ca, cb);
+            select_edge(d, live, e, ca, cb, best);
             e.pa = ca;
             e.pb = cb;
             int total;
@@ -1184,7 +1201,8 @@ __global__ __launch_bounds__(BLOCK) void k_bor_select(Dev d, int r) {
 // Each selecting component hooks onto the component across its lowest-key
 // edge; when two components pick the same edge the smaller id stays a root.
 // Distinct keys make the chosen edges a forest (Boruvka).  Round r >= 1 ends
-// the rounds when its select found no live edge.
+// the rounds when its select found no live edge.  Also clears the other
+// buffer of best[] for the next round's selection.
 __global__ __launch_bounds__(BLOCK) void k_bor_hook(Dev d, int r) {
     if (*d.status || d.cnt[C_DONE_BOR]) return;
     if (r >= 1) {
@@ -1196,23 +1214,28 @@ __global__ __launch_bounds__(BLOCK) void k_bor_hook(Dev d, int r) {
         if (r >= 2 && blockIdx.x == 0 && threadIdx.x == 0) d.cnt[(r & 1) ? C_NX0 : C_NX1] = 0;
     }
     const int64_t np = (int64_t)d.cnt[C_NP];
+    const uint64_t *best = best_of(d, r);
+    uint64_t *next = best_of(d, r + 1);
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < np; base += stride) {
         const int64_t p = base + threadIdx.x;
         bool rec = false;
         int4 er = make_int4(0, 0, 0, 0);
-        if (p < np && d.comp[p] == (int32_t)p) {
-            const uint64_t k = d.best[p];
+        if (p < np) {
+            next[p] = KEY_INF;
+            // a root at this round's start (only p's own thread writes hook[p])
+            const uint64_t k = d.hook[p] == HOOK_NONE ? best[p] : KEY_INF;
             if (k != KEY_INF) {
                 const int32_t x = key_lo(k), y = key_hi(k);
                 const int32_t px = d.tidx[d.rep[x]], py = d.tidx[d.rep[y]];
                 if (px < 0 || py < 0) {
                     atomicOr(d.status, ST_WALK_BOUND);
                 } else {
-                    const int32_t cx = d.comp[px], cy = d.comp[py];
+                    const int32_t cx = comp_root(d, px, (uint32_t)r, np);
+                    const int32_t cy = comp_root(d, py, (uint32_t)r, np);
                     const int32_t other = (cx == (int32_t)p) ? cy : cx;
-                    if (!(d.best[other] == k && (int32_t)p < other)) {
-                        d.hook[p] = other;
+                    if (!(best[other] == k && (int32_t)p < other)) {
+                        d.hook[p] = hook_pack(r, other);
                         rec = true;
                         er = make_int4(x, y, px, py);
                     }
@@ -1221,24 +1244,6 @@ __global__ __launch_bounds__(BLOCK) void k_bor_hook(Dev d, int r) {
         }
         const int64_t slot = block_append(rec ? 1 : 0, &d.cnt[C_NER]);
         if (rec) d.er[slot] = er;
-    }
-}
-
-// Every piece follows the hooks of this round to its new component.
-__global__ __launch_bounds__(BLOCK) void k_bor_compress(Dev d, int r) {
-    if (*d.status || d.cnt[C_DONE_BOR]) return;
-    const int64_t np = (int64_t)d.cnt[C_NP];
-    const int64_t stride = (int64_t)gridDim.x * BLOCK;
-    for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < np; p += stride) {
-        int32_t x = d.comp[p];
-        for (int64_t steps = 0;; steps++) {
-            const int32_t h = ld_relaxed(&d.hook[x]);
-            if (h == NONE) break;
-            x = h;
-            if (steps > np) { atomicOr(d.status, ST_WALK_BOUND); break; }
-        }
-        d.comp[p] = x;
-        d.best[p] = KEY_INF;
     }
 }
 
@@ -1255,7 +1260,9 @@ __global__ __launch_bounds__(BLOCK) void k_sf_root(Dev d) {
     for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < np; base += stride) {
         const int64_t p = base + threadIdx.x;
         const bool act = p < np;
-        const int32_t c = act ? d.comp[p] : 0;
+        // the final component: every hook of every round
+        const int32_t c = act ? comp_root(d, (int32_t)p, ~0u, np) : 0;
+        if (act) d.comp[p] = c;
         const uint64_t key = act ? (((uint64_t)(uint32_t)d.pmin[p] << 32) | (uint64_t)p) : KEY_INF;
         group_min_u64(act, c, key, d.srkey);
     }
@@ -1692,7 +1699,6 @@ void launch_boruvka(const Dev &d, int r0, int r1, int64_t units, hipStream_t s) 
         else
             hipLaunchKernelGGL(k_bor_select, dim3(r == 1 ? ge : gp), dim3(BLOCK), 0, s, d, r);
         hipLaunchKernelGGL(k_bor_hook, dim3(gp), dim3(BLOCK), 0, s, d, r);
-        hipLaunchKernelGGL(k_bor_compress, dim3(gp), dim3(BLOCK), 0, s, d, r);
     }
 }
 void launch_sf_root(const Dev &d, hipStream_t s) {
