@@ -102,6 +102,8 @@ struct drsf_ctx {
     int64_t *bloc = nullptr;
     uint32_t *twin = nullptr, *ltwin = nullptr;
     uint64_t bhmask = 0;
+    int32_t *dslot = nullptr;
+    uint64_t dsmask = 0;
     // orphan scan
     int64_t nvb = 0;
     int64_t *bvol = nullptr, *bpre = nullptr;
@@ -251,6 +253,7 @@ Dev make_dev(drsf_ctx *c) {
     d.gstat = c->gstat; d.max_b = c->max_batch;
     d.bkey = c->bkey; d.bloc = c->bloc; d.bchild = c->bchild;
     d.bslot = c->bslot; d.bhash = c->bhash; d.bhmask = c->bhmask;
+    d.dslot = c->dslot; d.dsmask = c->dsmask;
     d.vlist = c->lists;
     d.ilist = c->lists ? c->lists + c->nvblk : nullptr;
     d.tlist = c->lists ? c->lists + 2 * c->nvblk : nullptr;
@@ -329,6 +332,12 @@ int alloc_state(drsf_ctx *c) {
     while (bh < (uint64_t)(2 * mb)) bh <<= 1;
     c->bhmask = bh - 1;
     if ((rc = dalloc(c, &c->bhash, (int64_t)bh))) return rc;
+    // slot table at load <= 1/8: about 1 edge in 16 collides and takes the
+    // claim table; never cleared (only slots written by the batch are read)
+    uint64_t ds = 16;
+    while (ds < (uint64_t)(8 * mb)) ds <<= 1;
+    c->dsmask = ds - 1;
+    if ((rc = dalloc(c, &c->dslot, (int64_t)ds))) return rc;
     c->dcap = c->opts.delta_capacity > 0 ? c->opts.delta_capacity
                                          : std::max<int64_t>({4 * mb, c->eb / 8, 1 << 20});
     c->dtmax = delta_tiles(c->dcap);
@@ -624,6 +633,7 @@ void enqueue_update(drsf_ctx *c, int kind, bool profile) {
     }
     mark(PH_VALIDATE);
     launch_classify(d, s);
+    launch_dedupe(d, s);
     mark(PH_UPDATE);
     launch_prepare(d, del, s);
     launch_register(d, s);

@@ -109,8 +109,10 @@ struct Dev {
     int64_t *bloc;           // [max_b] >= 0: position in bcol; < 0: -(hash slot + 1)
     int32_t *bchild;         // [max_b] child endpoint of a deleted tree edge, NONE otherwise
     int32_t *bslot;          // [max_b] slot claimed in the batch duplicate table
-    uint64_t *bhash;         // [bhmask + 1]
+    uint64_t *bhash;         // [bhmask + 1] keys claimed by edges whose slot below collided
     uint64_t bhmask;
+    int32_t *dslot;          // [dsmask + 1] batch index of the last edge hashed to the slot
+    uint64_t dsmask;         // (plain stores; only slots of the current batch are read)
     // vertex-block and tile lists restricting per-vertex and sweep kernels to
     // the graphs that delete or insert (several graphs); see Ctl
     const int32_t *vlist, *ilist, *tlist;
@@ -183,6 +185,7 @@ int64_t insert_regions(int64_t b);
 // launchers of the update path (drsf_kernels.hip); grids are sized from the
 // context's maxima so that a captured sequence fits every batch
 void launch_classify(const Dev &d, hipStream_t s);
+void launch_dedupe(const Dev &d, hipStream_t s);  // repeated pairs inside the batch
 void launch_prepare(const Dev &d, bool del, hipStream_t s);  // with rep <- parent when del
 void launch_register(const Dev &d, hipStream_t s);
 void launch_insert_emit(const Dev &d, hipStream_t s);

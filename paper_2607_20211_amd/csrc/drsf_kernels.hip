@@ -282,18 +282,8 @@ __global__ __launch_bounds__(BLOCK) void k_classify(Dev d) {
             plo = d.parent[lo];
             phi = d.parent[hi];
         }
-        // repeated pair inside the batch
-        uint64_t h = hmix(k) & d.bhmask;
-        for (uint64_t probe = 0; probe <= d.bhmask; probe++) {
-            uint64_t s = d.bhash[h];
-            if (s == HASH_EMPTY) {
-                s = atomicCAS((unsigned long long *)&d.bhash[h], (unsigned long long)HASH_EMPTY,
-                              (unsigned long long)k);
-                if (s == HASH_EMPTY) { d.bslot[i] = (int32_t)h; break; }
-            }
-            if (s == k) { atomicOr(&d.gstat[g], ST_DUPLICATE); break; }
-            h = (h + 1) & d.bhmask;
-        }
+        // repeated pairs: every edge stamps its slot (checked by k_dedupe)
+        d.dslot[hmix(k) & d.dsmask] = (int32_t)i;
         // presence: the edge sits in upper row lo and in lower row hi (with
         // mirrored tombstones); search the shorter and map a lower hit up
         int64_t pos;
@@ -323,6 +313,41 @@ __global__ __launch_bounds__(BLOCK) void k_classify(Dev d) {
                 d.bloc[i] = loc;
                 d.bchild[i] = plo == hi ? lo : (phi == lo ? hi : NONE);
             }
+        }
+    }
+}
+
+// Repeated pairs inside the batch.  Equal keys hash to one slot and exactly
+// one of their stamps survives, so an edge that finds another edge's stamp
+// compares keys: equal is a repeat; different is a collision, and such edges
+// claim their key in a table with compare-and-swap, where repeats among them
+// meet.  Only the colliding edges (about 1 in 16) pay for an atomic.
+__global__ __launch_bounds__(BLOCK) void k_dedupe(Dev d) {
+    const int64_t b = d.ctl->b;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < b; i += stride) {
+        const uint64_t k = d.bkey[i];
+        if (k == 0) continue;  // rejected pair (its graph is marked already)
+        const int32_t j = d.dslot[hmix(k) & d.dsmask];
+        if (j == (int32_t)i) continue;
+        const int32_t g = edge_graph(d, i);
+        if (d.bkey[j] == k) {
+            atomicOr(&d.gstat[g], ST_DUPLICATE);
+            continue;
+        }
+        uint64_t h = hmix(k) & d.bhmask;
+        for (uint64_t probe = 0; probe <= d.bhmask; probe++) {
+            const uint64_t prev = atomicCAS((unsigned long long *)&d.bhash[h],
+                                            (unsigned long long)HASH_EMPTY, (unsigned long long)k);
+            if (prev == HASH_EMPTY) {
+                d.bslot[i] = (int32_t)h;
+                break;
+            }
+            if (prev == k) {
+                atomicOr(&d.gstat[g], ST_DUPLICATE);
+                break;
+            }
+            h = (h + 1) & d.bhmask;
         }
     }
 }
@@ -1654,6 +1679,9 @@ int64_t insert_regions(int64_t b) { return (b + BLOCK - 1) / BLOCK; }
 
 void launch_classify(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_classify, dim3(grid_for(d.max_b, BLOCK)), dim3(BLOCK), 0, s, d);
+}
+void launch_dedupe(const Dev &d, hipStream_t s) {
+    hipLaunchKernelGGL(k_dedupe, dim3(grid_for(d.max_b, BLOCK)), dim3(BLOCK), 0, s, d);
 }
 void launch_prepare(const Dev &d, bool del, hipStream_t s) {
     const int gb = grid_for(d.max_b, BLOCK);

@@ -260,6 +260,45 @@ def test_invalid_batches_leave_state_unchanged():
     f.close()
 
 
+def test_repeated_pairs_in_large_batches():
+    """A pair repeated anywhere in a large batch (either orientation) is
+    rejected and leaves the state unchanged; the same batches without the
+    repeat go through.  Large batches make many keys share a slot of the
+    repeat check's stamp table, so repeats are caught both by the stamp and by
+    the claim table that colliding edges fall back to."""
+    drsf = _lib()
+    _case("repeated pairs")
+    rng = np.random.default_rng(12)
+    n = 20000
+    g = gen.make_graph("rep", n, gen.gnm(n, 60000, gen.seed(12, 0, gen.P_GRAPH)))
+    f = drsf.Forest(g.n, g.row_ptr, g.col, g.parent, max_batch=4096)
+    p0, l0 = f.parent(), f.label()
+    ins_all = gen.insert_batches(n, g.keys, 1, 3000 * 24, gen.seed(12, 1, gen.P_INSERT))[0]
+    for t in range(24):
+        op = drsf.DRSF_INSERT if t % 2 == 0 else drsf.DRSF_DELETE
+        if op == drsf.DRSF_INSERT:
+            base = ins_all[3000 * t:3000 * (t + 1)]
+        else:
+            sel = rng.choice(len(g.keys), 3000, replace=False)
+            k = g.keys[sel]
+            base = np.stack([(k >> np.uint64(32)).astype(np.int32),
+                             (k & np.uint64(0xffffffff)).astype(np.int32)], 1)
+        reps = 1 + t % 3
+        extra = base[rng.choice(len(base), reps, replace=False)].copy()
+        if t % 4 < 2:
+            extra = extra[:, ::-1]
+        batch = np.concatenate([base, extra])
+        batch = batch[rng.permutation(len(batch))]
+        with pytest.raises(drsf.DrsfError) as ei:
+            f.apply(np.ascontiguousarray(batch, np.int32), op)
+        assert ei.value.code == drsf.DRSF_E_BATCH, t
+        if t % 6 == 0:
+            assert np.array_equal(f.parent(), p0) and np.array_equal(f.label(), l0)
+    # without the repeats the same kind of batch is accepted
+    f.apply(np.ascontiguousarray(ins_all[:3000], np.int32), drsf.DRSF_INSERT)
+    f.close()
+
+
 def test_create_rejects_bad_inputs():
     drsf = _lib()
     _case("create errors")
