@@ -206,6 +206,37 @@ def time_op(f, snap, batch, op, reps, drsf):
     return float(np.median(ts))
 
 
+def reversal_ab(n, row, col, par, batches, max_batch, stream, drsf):
+    """The same updates with each path reversal (reverse_mode 0: one thread
+    walks each path; 1: Euler tour of F-hat with list ranking, Alg. 3), both
+    launched kernel by kernel (the Euler tour's library sort is never
+    captured): per step the host-observed update time, the reversal-and-labels
+    phase (less the event bracket), and whether the two modes end in the same
+    forest (digest)."""
+    res = {}
+    for mode in (0, 1):
+        f = drsf.Forest(n, row, col, par, max_batch=max_batch, stream=stream.cuda_stream,
+                        inputs_on_device=True, profile=True, reverse_mode=mode)
+        steps = []
+        for edges, op in batches:
+            t0 = time.perf_counter()
+            st = f.apply(edges, op)
+            wall = time.perf_counter() - t0
+            t = f.phase_times()
+            br = t.pop(drsf.EVENT_BRACKET, 0.0)
+            # an update that needed more hooking rounds or search levels than
+            # queued finishes on the host: its reversal is then outside the
+            # phases, but inside the wall time
+            steps.append({"op": "insert" if op == drsf.DRSF_INSERT else "delete",
+                          "paths": st["num_paths"],
+                          "reversal_and_labels_phase_ms": round(t["reversal_and_labels"] - br, 4),
+                          "update_wall_ms": round(wall * 1e3, 4)})
+        res[f"reverse_mode_{mode}"] = {"steps": steps, "digest": [int(x) for x in f.digest()]}
+        f.close()
+    res["same_result"] = res["reverse_mode_0"]["digest"] == res["reverse_mode_1"]["digest"]
+    return res
+
+
 def run_configs(g, dev, stream, log, reps=3):
     """Per-op rates from the initial state: R-MAT 22 at b = 1e4, 1e5, 1e6
     (inserts of uniform non-edges; deletes half tree edges), and the deep
@@ -239,6 +270,15 @@ def run_configs(g, dev, stream, log, reps=3):
     drsf.drsf_snapshot_free(snap)
     f.close()
     out["rmat22_from_initial_state"] = sweep
+    # path reversal A/B (row f1) on the headline workload: insert then delete 1e5
+    ins = torch.from_numpy(gen.insert_batches(g.n, g.keys, 1, 100_000, gen.seed(2, 2, gen.P_INSERT))[0]).to(dev)
+    dl = torch.from_numpy(gen.delete_batches(g.n, g.keys, g.parent, 1, 100_000, 50_000,
+                                             gen.seed(2, 2, gen.P_DELETE))[0]).to(dev)
+    out["reversal_ab_rmat22_b1e5"] = reversal_ab(
+        g.n, torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col).to(dev),
+        torch.from_numpy(g.parent).to(dev), [(ins, drsf.DRSF_INSERT), (dl, drsf.DRSF_DELETE)],
+        100_000, stream, drsf)
+    log(f"reversal A/B rmat22: {out['reversal_ab_rmat22_b1e5']}")
     # deep trees
     t0 = time.time()
     side = 4096
@@ -274,6 +314,11 @@ def run_configs(g, dev, stream, log, reps=3):
                             "delete_updates_per_s": round(1e5 / td, 1), "delete_ms": round(td * 1e3, 4),
                             "insert_updates_per_s": round(1e5 / ti, 1), "insert_ms": round(ti * 1e3, 4),
                             "delete_stats": st_d, "insert_stats": st_i}
+    out["reversal_ab_grid4096"] = reversal_ab(
+        gg.n, torch.from_numpy(gg.row_ptr).to(dev), torch.from_numpy(gg.col).to(dev),
+        torch.from_numpy(gg.parent).to(dev), [(d_dl, drsf.DRSF_DELETE), (d_ins, drsf.DRSF_INSERT)],
+        100_000, stream, drsf)
+    log(f"reversal A/B grid: {out['reversal_ab_grid4096']}")
     return out
 
 

@@ -91,6 +91,14 @@ typedef struct {
                                 0 = 4 */
     int levels_queued;       /* super-forest search levels placed in the graph;
                                 0 = 4 (max 12) */
+    int reverse_mode;        /* path reversal: 0 (default) one thread walks each
+                                path; 1: Euler tour of F-hat with list ranking,
+                                start/finish times and the interval test
+                                (Alg. 3, ReversePathsEulerTour), launched kernel
+                                by kernel (it sorts F-hat's child lists with a
+                                library radix sort, kept out of captured graphs);
+                                needs about 56 bytes per vertex more device
+                                memory.  Results are identical. */
 } drsf_opts;
 
 /* Fills *opts with the defaults described above. */

@@ -122,6 +122,13 @@ struct drsf_ctx {
     int32_t *arc_nxt = nullptr, *succ0 = nullptr, *succ1 = nullptr, *rank0 = nullptr, *rank1 = nullptr;
     PathReq *paths = nullptr;
     int64_t pathcap = 0;
+    // path reversal by Euler tour (reverse_mode 1)
+    uint64_t *et_keys = nullptr, *et_sorted = nullptr;
+    int32_t *et_fc = nullptr, *et_ns = nullptr, *et_opar = nullptr, *et_nxt0 = nullptr,
+            *et_nxt1 = nullptr, *et_dst0 = nullptr, *et_dst1 = nullptr, *et_start = nullptr,
+            *et_finish = nullptr, *et_support = nullptr;
+    uint8_t *et_tmp = nullptr;
+    size_t et_tmp_bytes = 0;
     // status word, counters and per-graph batch status share one allocation
     // so that one copy returns them: status at word 0, counters from word 1,
     // gstat after the counters
@@ -261,6 +268,10 @@ Dev make_dev(drsf_ctx *c) {
     d.er = c->er; d.ercap = c->ercap; d.arc_nxt = c->arc_nxt;
     d.succ0 = c->succ0; d.succ1 = c->succ1; d.rank0 = c->rank0; d.rank1 = c->rank1;
     d.paths = c->paths; d.pathcap = c->pathcap;
+    d.et_keys = c->et_keys; d.et_sorted = c->et_sorted; d.et_fc = c->et_fc; d.et_ns = c->et_ns;
+    d.et_opar = c->et_opar; d.et_nxt0 = c->et_nxt0; d.et_nxt1 = c->et_nxt1;
+    d.et_dst0 = c->et_dst0; d.et_dst1 = c->et_dst1; d.et_start = c->et_start;
+    d.et_finish = c->et_finish; d.et_support = c->et_support;
     d.status = c->status; d.cnt = c->cnt;
     return d;
 }
@@ -357,6 +368,23 @@ int alloc_state(drsf_ctx *c) {
     if ((rc = dalloc(c, &c->rank1, 2 * c->ercap))) return rc;
     c->pathcap = std::max<int64_t>(c->ercap + c->pcap, n);
     if ((rc = dalloc(c, &c->paths, c->pathcap))) return rc;
+    if (c->opts.reverse_mode == 1) {  // path reversal by Euler tour
+        if ((rc = dalloc(c, &c->et_keys, n))) return rc;
+        if ((rc = dalloc(c, &c->et_sorted, n))) return rc;
+        if ((rc = dalloc(c, &c->et_fc, n))) return rc;
+        if ((rc = dalloc(c, &c->et_ns, n))) return rc;
+        if ((rc = dalloc(c, &c->et_opar, n))) return rc;
+        if ((rc = dalloc(c, &c->et_nxt0, 2 * (int64_t)n))) return rc;
+        if ((rc = dalloc(c, &c->et_nxt1, 2 * (int64_t)n))) return rc;
+        if ((rc = dalloc(c, &c->et_dst0, 2 * (int64_t)n))) return rc;
+        if ((rc = dalloc(c, &c->et_dst1, 2 * (int64_t)n))) return rc;
+        if ((rc = dalloc(c, &c->et_start, n))) return rc;
+        if ((rc = dalloc(c, &c->et_finish, n))) return rc;
+        if ((rc = dalloc(c, &c->et_support, n))) return rc;
+        c->et_tmp_bytes = sort_u64_tmp_bytes(n) + 256;
+        if ((rc = dalloc(c, &c->et_tmp, (int64_t)c->et_tmp_bytes))) return rc;
+        launch_fill_i32(c->et_support, n, NONE, s);
+    }
     if ((rc = dalloc(c, &c->ctl, 1))) return rc;
     // orphan scan: per-block figures (zero between updates), list, ranges
     c->nvb = (n + BLOCK - 1) / BLOCK;
@@ -656,7 +684,10 @@ void enqueue_update(drsf_ctx *c, int kind, bool profile) {
     launch_sf_bfs(d, 0, c->bfs_fast, s);
     launch_orient_bfs(d, c->bfs_fast, s);
     mark(PH_FINISH);
-    launch_finish(d, ins, del, s);
+    const bool et = c->opts.reverse_mode == 1;
+    if (et && launch_et_reverse(d, c->et_tmp, c->et_tmp_bytes, s))
+        launch_fill_i32(c->status, 1, ST_ROUND_BOUND, s);  // the library sort failed
+    launch_finish(d, ins, del, !et, s);
     mark(PH_N);
     launch_cleanup(d, s);  // also hands the results to the host
 }
@@ -726,7 +757,10 @@ int continue_update(drsf_ctx *c) {
         }
         if (bfs_done) launch_orient_bfs(d, lv, s);
         else launch_superforest_lr(d, lr_rounds, s);  // deep super-trees: Euler tour
-        launch_finish(d, c->kind & 1, c->kind & 2, s);
+        const bool et = c->opts.reverse_mode == 1;
+        if (et && launch_et_reverse(d, c->et_tmp, c->et_tmp_bytes, s))
+            launch_fill_i32(c->status, 1, ST_ROUND_BOUND, s);
+        launch_finish(d, c->kind & 1, c->kind & 2, !et, s);
     }
     launch_cleanup(d, s);  // hands the results to the host, then resets
     HIPCHK(c, hipStreamSynchronize(s));
@@ -745,8 +779,8 @@ int launch_update(drsf_ctx *c) {
     *(volatile unsigned long long *)(c->h_ret + c->ret_words + 7) = 0;
     c->kind = (c->h_ctl->has_ins ? 1 : 0) | (c->h_ctl->has_del ? 2 : 0);
     if (c->kind == 0) c->kind = 3;  // nothing but rejected or empty batches: run everything
-    if (prof) {
-        enqueue_update(c, c->kind, true);
+    if (prof || c->opts.reverse_mode == 1) {  // the Euler-tour reversal's sort is not captured
+        enqueue_update(c, c->kind, prof);
     } else {
         int rc;
         if ((rc = capture_graph(c, c->kind))) return rc;
@@ -839,6 +873,10 @@ static int create_impl(int32_t G, const int32_t *n_off, int32_t n, const int64_t
             fail(c, DRSF_E_ARG, "graph vertex offsets must be non-decreasing");
             return bail(DRSF_E_ARG);
         }
+    if (c->opts.reverse_mode < 0 || c->opts.reverse_mode > 1) {
+        fail(c, DRSF_E_ARG, "reverse_mode must be 0 or 1");
+        return bail(DRSF_E_ARG);
+    }
     {
         const hipError_t e = hipGetDevice(&c->dev);
         if (e != hipSuccess) {

@@ -133,6 +133,15 @@ struct Dev {
     int32_t *rank0, *rank1;  // [2 ercap]
     PathReq *paths;          // [pathcap]
     int64_t pathcap;
+    // path reversal by Euler tour (reverse_mode 1, else null): arc 2v is the
+    // down arc from v's parent into v, arc 2v + 1 the up arc back
+    uint64_t *et_keys, *et_sorted;  // [n] (F-hat parent << 32 | child), sorted
+    int32_t *et_fc, *et_ns;         // [n] first child / next sibling in F-hat (NONE)
+    int32_t *et_opar;               // [n] F-hat parents (read before any reversal)
+    int32_t *et_nxt0, *et_nxt1;     // [2n] list-ranking successor (NONE past the end)
+    int32_t *et_dst0, *et_dst1;     // [2n] arcs after this one in its tour
+    int32_t *et_start, *et_finish;  // [n] Euler-tour times of each vertex
+    int32_t *et_support;            // [n] support[r] = x for a path (x, r), else NONE
     // control
     int32_t *status;         // internal errors (bounds exceeded)
     unsigned long long *cnt; // [C_TOTAL]
@@ -201,7 +210,9 @@ void launch_sf_bfs(const Dev &d, int l0, int l1, hipStream_t s);
 void launch_orient_bfs(const Dev &d, int levels, hipStream_t s);
 void launch_superforest_lr(const Dev &d, int lr_rounds, hipStream_t s);
 // label kernels of the ops present (delete labels run first)
-void launch_finish(const Dev &d, bool ins, bool del, hipStream_t s);  // path reversal and labels
+void launch_finish(const Dev &d, bool ins, bool del, bool rev, hipStream_t s);  // path reversal and labels
+// path reversal by Euler tour (Alg. 3); tmp/tmp_bytes: radix-sort scratch
+int launch_et_reverse(const Dev &d, void *tmp, size_t tmp_bytes, hipStream_t s);
 void launch_cleanup(const Dev &d, hipStream_t s);
 
 // store rebuild: live degrees of the base store, the inserted edges as

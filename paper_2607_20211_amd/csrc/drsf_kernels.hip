@@ -11,6 +11,8 @@
 // no-op when the status word is non-zero, so a rejected batch changes nothing.
 #include "drsf_kernels.h"
 
+#include <utility>
+
 namespace drsf {
 
 int grid_for(int64_t items, int64_t per_block, int cap) {
@@ -1634,6 +1636,147 @@ __global__ __launch_bounds__(BLOCK) void k_label_insert(Dev d) {
     label_insert(d, blockIdx.x, gridDim.x);
 }
 
+// -------------------------- f1: path reversal by Euler tour (Alg. 3)
+//
+// F-hat is the forest of the parents as they are before any reversal.  Its
+// child lists come from sorting (parent << 32 | child) keys, so siblings are
+// in increasing id order.  Euler tour of each tree (EulerianTour, first step
+// of Alg. 3): the tour enters a child c through its down arc 2c, walks c's
+// subtree, leaves through the up arc 2c + 1, then goes down to c's next
+// sibling, or else up from c's parent (the tour of a root ends there).  List
+// ranking by pointer jumping gives every arc the number of arcs after it in
+// its tour; its rank is the tour length - 1 - that number.
+
+// keys for the child lists, and the F-hat parents
+__global__ __launch_bounds__(BLOCK) void k_et_keys(Dev d) {
+    if (*d.status || !d.cnt[C_ORIENTED]) return;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < d.n; v += stride) {
+        const int32_t p = d.parent[v];
+        d.et_opar[v] = p;
+        // roots sort after every child entry and are skipped
+        const uint64_t hi = p == (int32_t)v ? 0xffffffffull : (uint64_t)(uint32_t)p;
+        d.et_keys[v] = (hi << 32) | (uint32_t)v;
+    }
+}
+
+// first child and next sibling from the sorted keys
+__global__ __launch_bounds__(BLOCK) void k_et_links(Dev d) {
+    if (*d.status || !d.cnt[C_ORIENTED]) return;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j < d.n; j += stride) {
+        const uint64_t k = d.et_sorted[j];
+        const uint32_t p = (uint32_t)(k >> 32);
+        if (p == 0xffffffffu) continue;
+        const int32_t c = (int32_t)(uint32_t)k;
+        if (j == 0 || (uint32_t)(d.et_sorted[j - 1] >> 32) != p) d.et_fc[p] = c;
+        const uint64_t nk = j + 1 < d.n ? d.et_sorted[j + 1] : ~0ull;
+        d.et_ns[c] = (uint32_t)(nk >> 32) == p ? (int32_t)(uint32_t)nk : NONE;
+    }
+}
+
+// successor of every arc, and the ranking's start (1 arc after, or 0 at the end)
+__global__ __launch_bounds__(BLOCK) void k_et_succ(Dev d) {
+    if (*d.status || !d.cnt[C_ORIENTED]) return;
+    const int64_t na = 2 * (int64_t)d.n;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t a = (int64_t)blockIdx.x * BLOCK + threadIdx.x; a < na; a += stride) {
+        const int32_t v = (int32_t)(a >> 1), pv = d.et_opar[v];
+        int32_t nx = NONE;  // a root has no arcs
+        if (pv != v) {
+            if ((a & 1) == 0) {
+                const int32_t c = d.et_fc[v];
+                nx = c != NONE ? 2 * c : 2 * v + 1;
+            } else {
+                const int32_t sb = d.et_ns[v];
+                nx = sb != NONE ? 2 * sb : (d.et_opar[pv] == pv ? NONE : 2 * pv + 1);
+            }
+        }
+        d.et_nxt0[a] = nx;
+        d.et_dst0[a] = nx == NONE ? 0 : 1;
+    }
+}
+
+// one pointer-jumping round: every arc adds the count of its successor and
+// jumps past it
+__global__ __launch_bounds__(BLOCK) void k_et_round(Dev d, const int32_t *nin, const int32_t *din,
+                                                    int32_t *nout, int32_t *dout) {
+    if (*d.status || !d.cnt[C_ORIENTED]) return;
+    const int64_t na = 2 * (int64_t)d.n;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t a = (int64_t)blockIdx.x * BLOCK + threadIdx.x; a < na; a += stride) {
+        const int32_t nx = nin[a];
+        int32_t dn = din[a], nn = NONE;
+        if (nx != NONE) {
+            dn += din[nx];
+            nn = nin[nx];
+        }
+        nout[a] = nn;
+        dout[a] = dn;
+    }
+}
+
+// start and finish times (Alg. 3): a leaf takes its up arc's rank for both;
+// a root the rank of its first arc and its tour's length; any other vertex
+// the rank of the down arc to its first child and of its own up arc
+__global__ __launch_bounds__(BLOCK) void k_et_times(Dev d, const int32_t *dst) {
+    if (*d.status || !d.cnt[C_ORIENTED]) return;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < d.n; v += stride) {
+        const int32_t r = d.rep[v];  // root of v's tree of F-hat
+        const int32_t fr = d.et_fc[r];
+        const int32_t L = fr != NONE ? dst[2 * fr] + 1 : 0;  // arcs in r's tour
+        const int32_t fc = d.et_fc[v];
+        int32_t st, fi;
+        if (d.et_opar[v] == (int32_t)v) {
+            st = 0;
+            fi = L;
+        } else if (fc == NONE) {
+            st = fi = L - 1 - dst[2 * v + 1];
+        } else {
+            st = L - 1 - dst[2 * fc];
+            fi = L - 1 - dst[2 * v + 1];
+        }
+        d.et_start[v] = st;
+        d.et_finish[v] = fi;
+    }
+}
+
+// support[r] = x for each path (x, r) of R (at most one path per tree of F-hat)
+__global__ __launch_bounds__(BLOCK) void k_et_support(Dev d) {
+    if (*d.status || !d.cnt[C_ORIENTED]) return;
+    const int64_t nr = (int64_t)d.cnt[C_NR];
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < nr; i += stride) {
+        const PathReq q = d.paths[i];
+        d.et_support[q.stop] = q.start;
+    }
+}
+
+// Every tree edge (u, parent[u]) whose u lies on the path from x = support[r]
+// up to its root r (excluding r: the interval test of Alg. 3) turns around:
+// parent[old parent of u] = u.  Then each path's start hangs below its new
+// parent (its own parent edge is not on any path, so no write collides).
+__global__ __launch_bounds__(BLOCK) void k_et_reverse(Dev d) {
+    if (*d.status || !d.cnt[C_ORIENTED]) return;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t u = (int64_t)blockIdx.x * BLOCK + threadIdx.x; u < d.n; u += stride) {
+        const int32_t pu = d.et_opar[u];
+        if (pu == (int32_t)u) continue;
+        const int32_t r = d.rep[u];
+        const int32_t x = d.et_support[r];
+        if (x == NONE) continue;
+        const int32_t su = d.et_start[u], fu = d.et_finish[u];
+        if (d.et_start[r] < su && su <= d.et_start[x] && d.et_finish[r] > fu && fu >= d.et_finish[x])
+            d.parent[pu] = (int32_t)u;
+    }
+    const int64_t nr = (int64_t)d.cnt[C_NR];
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < nr; i += stride) {
+        const PathReq q = d.paths[i];
+        d.parent[q.start] = q.newpar;
+    }
+}
+
 // ------------------------------------------------------------- cleanup
 
 // Resets the per-update scratch once the update has finished (or failed);
@@ -1651,6 +1794,7 @@ __global__ __launch_bounds__(BLOCK) void k_cleanup(Dev d) {
             d.tidx[d.prt[p]] = NONE;
             d.level[p] = -1;  // the super-forest search starts from all -1
             d.parc[p] = NONE;
+            if (d.et_support) d.et_support[d.prt[p]] = NONE;  // path ends are piece roots
         }
         for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < b; i += stride)
             if (d.bslot[i] != NONE) d.bhash[d.bslot[i]] = HASH_EMPTY;
@@ -1752,9 +1896,9 @@ void launch_superforest_lr(const Dev &d, int lr_rounds, hipStream_t s) {
 void launch_reverse_all(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_reverse_all, dim3(grid_for(d.pathcap, BLOCK, 2048)), dim3(BLOCK), 0, s, d);
 }
-void launch_finish(const Dev &d, bool ins, bool del, hipStream_t s) {
+void launch_finish(const Dev &d, bool ins, bool del, bool rev, hipStream_t s) {
     // an update reverses at most one path per piece and per replacement edge
-    const int grev = grid_for(d.ercap + d.pcap, BLOCK, FINISH_CAP);
+    const int grev = rev ? grid_for(d.ercap + d.pcap, BLOCK, FINISH_CAP) : 0;
     // deletes relabel per vertex block or per listed orphan, inserts one wave
     // per vertex block
     const int glab = del ? grid_for(d.n, BLOCK, FINISH_CAP) : grid_for(d.nvb, BLOCK / WAVE, FINISH_CAP);
@@ -1762,6 +1906,28 @@ void launch_finish(const Dev &d, bool ins, bool del, hipStream_t s) {
     if (ins && del)
         hipLaunchKernelGGL(k_label_insert, dim3(grid_for(d.nvb, BLOCK / WAVE, GRID_CAP)), dim3(BLOCK), 0,
                            s, d);
+}
+int launch_et_reverse(const Dev &d, void *tmp, size_t tmp_bytes, hipStream_t s) {
+    const int gv = grid_for(d.n, BLOCK, GRID_CAP), ga = grid_for(2 * (int64_t)d.n, BLOCK, GRID_CAP);
+    hipLaunchKernelGGL(k_et_keys, dim3(gv), dim3(BLOCK), 0, s, d);
+    if (launch_sort_u64(d.et_keys, d.et_sorted, d.n, tmp, tmp_bytes, s)) return -1;
+    launch_fill_i32(d.et_fc, d.n, NONE, s);
+    hipLaunchKernelGGL(k_et_links, dim3(gv), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_et_succ, dim3(ga), dim3(BLOCK), 0, s, d);
+    // 2^rounds >= 2n: every arc has jumped past the end of its tour
+    int rounds = 0;
+    while ((int64_t)1 << rounds < 2 * (int64_t)d.n) rounds++;
+    int32_t *n0 = d.et_nxt0, *d0 = d.et_dst0, *n1 = d.et_nxt1, *d1 = d.et_dst1;
+    for (int r = 0; r < rounds; r++) {
+        hipLaunchKernelGGL(k_et_round, dim3(ga), dim3(BLOCK), 0, s, d, n0, d0, n1, d1);
+        std::swap(n0, n1);
+        std::swap(d0, d1);
+    }
+    hipLaunchKernelGGL(k_et_times, dim3(gv), dim3(BLOCK), 0, s, d, d0);
+    hipLaunchKernelGGL(k_et_support, dim3(grid_for(d.ercap + d.pcap, BLOCK, GRID_CAP)), dim3(BLOCK), 0,
+                       s, d);
+    hipLaunchKernelGGL(k_et_reverse, dim3(gv), dim3(BLOCK), 0, s, d);
+    return 0;
 }
 void launch_cleanup(const Dev &d, hipStream_t s) {
     int64_t m = d.pcap > d.max_b ? d.pcap : d.max_b;

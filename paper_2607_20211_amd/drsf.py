@@ -37,7 +37,8 @@ class drsf_opts(ctypes.Structure):
                 ("delta_capacity", ctypes.c_int64),
                 ("sweep_mode", ctypes.c_int),
                 ("rounds_queued", ctypes.c_int),
-                ("levels_queued", ctypes.c_int)]
+                ("levels_queued", ctypes.c_int),
+                ("reverse_mode", ctypes.c_int)]
 
 
 class drsf_view(ctypes.Structure):
@@ -328,7 +329,7 @@ class Forest:
     def __init__(self, n: int, row_ptr, col, parent, *, max_batch: int = 1 << 20,
                  stream=None, inputs_on_device: bool = False, validate: bool = True,
                  profile: bool = False, delta_capacity: int = 0, sweep_mode: int = 0,
-                 rounds_queued: int = 0, levels_queued: int = 0):
+                 rounds_queued: int = 0, levels_queued: int = 0, reverse_mode: int = 0):
         o = drsf_default_opts()
         o.max_batch = max_batch
         o.inputs_on_device = int(inputs_on_device)
@@ -338,6 +339,7 @@ class Forest:
         o.sweep_mode = sweep_mode
         o.rounds_queued = rounds_queued
         o.levels_queued = levels_queued
+        o.reverse_mode = reverse_mode
         if stream is not None:
             o.stream = stream
         if not inputs_on_device:
@@ -427,7 +429,7 @@ class MultiForest(Forest):
     def __init__(self, n_off, row_ptr, col, parent, *, max_batch: int = 1 << 20,
                  stream=None, inputs_on_device: bool = False, validate: bool = True,
                  profile: bool = False, delta_capacity: int = 0, sweep_mode: int = 0,
-                 rounds_queued: int = 0, levels_queued: int = 0):
+                 rounds_queued: int = 0, levels_queued: int = 0, reverse_mode: int = 0):
         o = drsf_default_opts()
         o.max_batch = max_batch
         o.inputs_on_device = int(inputs_on_device)

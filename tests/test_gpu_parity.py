@@ -232,6 +232,76 @@ def test_rmat_small(sweep_mode):
     pair.gpu.close()
 
 
+@pytest.mark.parametrize("workload", ["gnm", "rmat16", "grid", "path", "continuation"])
+def test_euler_tour_reversal(workload):
+    """Path reversal by Euler tour (reverse_mode 1, the paper's
+    ReversePathsEulerTour: tour of F-hat, list ranking, start/finish times,
+    support and the interval test) gives bit-exact the same forest as the
+    oracle: many trees with short paths, a power-law graph, deep grid and path
+    trees with long paths, and an update finished on the host."""
+    drsf = _lib()
+    _case(f"euler tour reversal {workload}")
+    if workload == "gnm":
+        n = 30011
+        g = gen.make_graph("sparse", n, gen.gnm(n, 27000, gen.seed(14, 0, gen.P_GRAPH)))
+        pair = Pair(g, max_batch=8192, reverse_mode=1)
+        for step in range(3):
+            ins = gen.insert_batches(n, pair.keys, 1, 3000, gen.seed(14, step, gen.P_INSERT))[0]
+            pair.step(ins, drsf.DRSF_INSERT, f"gnm insert {step}")
+            dl = gen.delete_batches(n, pair.keys, pair.parent, 1, 3000, 1500,
+                                    gen.seed(14, step, gen.P_DELETE))[0]
+            pair.step(dl, drsf.DRSF_DELETE, f"gnm delete {step}")
+    elif workload == "rmat16":
+        keys = gen.rmat(16, 16, 0.57, 0.19, 0.19, gen.seed(14, 1, gen.P_GRAPH))
+        g = gen.make_graph("rmat16", 1 << 16, keys)
+        pair = Pair(g, reverse_mode=1)
+        ins = gen.insert_batches(g.n, pair.keys, 1, 10000, gen.seed(14, 1, gen.P_INSERT))[0]
+        pair.step(ins, drsf.DRSF_INSERT, "rmat insert")
+        dl = gen.delete_batches(g.n, pair.keys, pair.parent, 1, 10000, 5000, gen.seed(14, 1, gen.P_DELETE))[0]
+        pair.step(dl, drsf.DRSF_DELETE, "rmat delete")
+    elif workload == "grid":
+        keys = gen.grid(256, 256, 3276, gen.seed(14, 2, gen.P_GRAPH))
+        g = gen.make_graph("grid", 256 * 256, keys)
+        pair = Pair(g, reverse_mode=1)
+        dl = gen.delete_batches(g.n, pair.keys, pair.parent, 1, 2000, 2000, gen.seed(14, 2, gen.P_DELETE))[0]
+        pair.step(dl, drsf.DRSF_DELETE, "grid delete")
+        ins = gen.insert_batches(g.n, pair.keys, 1, 2000, gen.seed(14, 2, gen.P_INSERT))[0]
+        pair.step(ins, drsf.DRSF_INSERT, "grid insert")
+    elif workload == "path":
+        n = 50_000
+        path = [(i, i + 1) for i in range(n - 1)]
+        rng = np.random.default_rng(15)
+        chords = set()
+        while len(chords) < 800:
+            u, v = sorted(rng.integers(0, n, 2).tolist())
+            if v - u > 1:
+                chords.add((u, v))
+        keys = np.array(sorted((u << 32) | v for u, v in path + list(chords)), np.uint64)
+        g = gen.make_graph("path", n, keys)
+        pair = Pair(g, reverse_mode=1)
+        dl = gen.delete_batches(n, pair.keys, pair.parent, 1, 800, 600, gen.seed(14, 3, gen.P_DELETE))[0]
+        pair.step(dl, drsf.DRSF_DELETE, "path delete")
+        ins = gen.insert_batches(n, pair.keys, 1, 800, gen.seed(14, 3, gen.P_INSERT))[0]
+        pair.step(ins, drsf.DRSF_INSERT, "path insert")
+    else:
+        n = 20_000
+        g = gen.make_graph("empty", n, np.zeros(0, np.uint64))
+        pair = Pair(g, max_batch=1 << 16, reverse_mode=1)
+        ins = gen.insert_batches(n, g.keys, 1, 40_000, gen.seed(14, 4, gen.P_INSERT))[0]
+        pair.step(ins, drsf.DRSF_INSERT, "continuation insert")
+        dl = gen.delete_batches(n, pair.keys, pair.parent, 1, 20_000, 10_000, gen.seed(14, 4, gen.P_DELETE))[0]
+        pair.step(dl, drsf.DRSF_DELETE, "continuation delete")
+    pair.gpu.close()
+
+
+def test_reverse_mode_rejects_unknown_value():
+    drsf = _lib()
+    g = gen.make_graph("tiny", 10, gen.gnm(10, 12, 3))
+    with pytest.raises(drsf.DrsfError) as ei:
+        drsf.Forest(g.n, g.row_ptr, g.col, g.parent, reverse_mode=2)
+    assert ei.value.code == drsf.DRSF_E_ARG
+
+
 def test_invalid_batches_leave_state_unchanged():
     drsf = _lib()
     _case("invalid")
