@@ -237,6 +237,31 @@ def reversal_ab(n, row, col, par, batches, max_batch, stream, drsf):
     return res
 
 
+def static_rebuild(n, keys, dev, stream, drsf, reps=3):
+    """The static baseline (row f3): a rooted spanning forest of the graph
+    with these keys from scratch on the GPU (components by hooking, then a
+    breadth-first forest from each component's smallest vertex); median wall
+    time of reps runs with the CSR already in device memory."""
+    import torch
+    import gen
+    row_ptr, col = gen.keys_to_csr(n, keys)
+    d_row, d_col = torch.from_numpy(row_ptr).to(dev), torch.from_numpy(col).to(dev)
+    par = torch.empty(n, dtype=torch.int32, device=dev)
+    lab = torch.empty_like(par)
+    times, levels = [], 0
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        levels = drsf.drsf_static_forest(n, d_row, d_col, par, lab, stream.cuda_stream)
+        times.append(time.perf_counter() - t0)
+    return {"ms": round(float(np.median(times)) * 1e3, 3), "levels": levels}
+
+
+def edge_keys(batch):
+    u, v = batch[:, 0].astype(np.uint64), batch[:, 1].astype(np.uint64)
+    return (np.minimum(u, v) << np.uint64(32)) | np.maximum(u, v)
+
+
 def run_configs(g, dev, stream, log, reps=3):
     """Per-op rates from the initial state: R-MAT 22 at b = 1e4, 1e5, 1e6
     (inserts of uniform non-edges; deletes half tree edges), and the deep
@@ -279,6 +304,14 @@ def run_configs(g, dev, stream, log, reps=3):
         torch.from_numpy(g.parent).to(dev), [(ins, drsf.DRSF_INSERT), (dl, drsf.DRSF_DELETE)],
         100_000, stream, drsf)
     log(f"reversal A/B rmat22: {out['reversal_ab_rmat22_b1e5']}")
+    # static rebuild of the graph after the 1e5-insert batch (row f3), against
+    # the dynamic updates at b = 1e5
+    st = static_rebuild(g.n, np.union1d(g.keys, edge_keys(ins.cpu().numpy())), dev, stream, drsf)
+    b5 = [x for x in sweep if x["batch"] == 100_000][0]
+    st["speedup_insert"] = round(st["ms"] / b5["insert_ms"], 1)
+    st["speedup_delete"] = round(st["ms"] / b5["delete_ms"], 1)
+    out["static_rebuild_rmat22"] = st
+    log(f"static rebuild rmat22: {st}")
     # deep trees
     t0 = time.time()
     side = 4096
@@ -319,6 +352,12 @@ def run_configs(g, dev, stream, log, reps=3):
         torch.from_numpy(gg.parent).to(dev), [(d_dl, drsf.DRSF_DELETE), (d_ins, drsf.DRSF_INSERT)],
         100_000, stream, drsf)
     log(f"reversal A/B grid: {out['reversal_ab_grid4096']}")
+    keep = np.ones(len(gg.keys), bool)
+    keep[np.searchsorted(gg.keys, edge_keys(dl))] = False
+    st = static_rebuild(gg.n, gg.keys[keep], dev, stream, drsf, reps=1)
+    st["speedup_delete"] = round(st["ms"] / (td * 1e3), 1)
+    out["static_rebuild_grid4096"] = st
+    log(f"static rebuild grid: {st}")
     return out
 
 

@@ -213,6 +213,29 @@ int drsf_num_graphs(const drsf_ctx *ctx);
  */
 int drsf_digest(drsf_ctx *ctx, uint64_t *out);
 
+/*
+ * Static rebuild (the baseline of the dynamic update, Sec. V's static GPU
+ * forest; no context): a rooted spanning forest of G from scratch.
+ * Connected components by hooking (the larger root of an edge's two
+ * components takes the smaller as its root, repeated with pointer jumping
+ * until no edge joins two roots), so each component is rooted at its
+ * smallest vertex, then a breadth-first forest from all roots at once
+ * (a level is expanded from its frontier's rows when the frontier is small,
+ * else by one pass over all rows).
+ * row_ptr: DEVICE int64[n + 1]; col: DEVICE int32[row_ptr[n]] (may be NULL
+ * when row_ptr[n] == 0), a symmetric CSR without self-loops (not checked
+ * here).  parent_out, label_out: DEVICE
+ * int32[n], written: parent[root] = root, label = the component's smallest
+ * vertex.  The breadth-first parent is one of several valid choices (ties
+ * between frontier vertices are decided by the hardware).  stream: hipStream_t
+ * or NULL.  levels_out (host, may be NULL): breadth-first levels.  Allocates
+ * and frees its own scratch (about 12 bytes per vertex and 4 per CSR entry)
+ * and returns when the result is final.  Errors: DRSF_E_ARG, DRSF_E_NOMEM,
+ * DRSF_E_DEVICE.
+ */
+int drsf_static_forest(int32_t n, const int64_t *row_ptr, const int32_t *col, int32_t *parent_out,
+                       int32_t *label_out, void *stream, int32_t *levels_out);
+
 /* Device bytes the context holds (its own allocations). */
 int64_t drsf_device_bytes(const drsf_ctx *ctx);
 

@@ -71,7 +71,8 @@ EXPORTS = ("drsf_default_opts", "drsf_create", "drsf_apply", "drsf_apply_async",
            "drsf_device_bytes", "drsf_footprint", "drsf_server_create", "drsf_server_admit",
            "drsf_server_submit", "drsf_server_release", "drsf_server_start",
            "drsf_server_wait_all", "drsf_server_result", "drsf_server_stats",
-           "drsf_server_tenant_state", "drsf_server_error", "drsf_server_destroy")
+           "drsf_server_tenant_state", "drsf_server_error", "drsf_server_destroy",
+           "drsf_static_forest")
 
 _lib = None
 
@@ -145,6 +146,8 @@ def load():
     lib.drsf_device_bytes.restype = i64
     lib.drsf_footprint.argtypes = [i32, i64, ctypes.POINTER(drsf_opts)]
     lib.drsf_footprint.restype = i64
+    lib.drsf_static_forest.argtypes = [i32, vp, vp, vp, vp, vp, ctypes.POINTER(i32)]
+    lib.drsf_static_forest.restype = c_int
     lib.drsf_server_create.argtypes = [i64, ctypes.POINTER(drsf_opts), c_int, ctypes.POINTER(vp)]
     lib.drsf_server_create.restype = c_int
     lib.drsf_server_admit.argtypes = [vp, i32, vp, vp, vp, i64, ctypes.POINTER(i32)]
@@ -306,6 +309,16 @@ def drsf_digest(ctx) -> tuple:
 
 def drsf_device_bytes(ctx) -> int:
     return int(load().drsf_device_bytes(ctx))
+
+
+def drsf_static_forest(n: int, row_ptr, col, parent_out, label_out, stream=None) -> int:
+    """Static rebuild (no context): device CSR in, device parent and label
+    out (torch tensors or raw pointers); returns the breadth-first levels."""
+    lv = ctypes.c_int32(0)
+    rc = load().drsf_static_forest(n, _ptr(row_ptr), _ptr(col), _ptr(parent_out), _ptr(label_out),
+                                   stream, ctypes.byref(lv))
+    _check(rc)
+    return int(lv.value)
 
 
 def drsf_footprint(n: int, nnz: int, opts: drsf_opts | None = None) -> int:
