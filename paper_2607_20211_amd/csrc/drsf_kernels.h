@@ -187,6 +187,10 @@ constexpr int EDGE_CAP = DRSF_EDGE_CAP;    // first hooking selections
 #endif
 constexpr int FINISH_CAP = DRSF_FINISH_CAP;  // each part of path reversal + labels
 constexpr int COPY_CAP = DRSF_COPY_CAP;      // rep <- parent beside the store update
+#ifndef DRSF_CLEANUP_CAP
+#define DRSF_CLEANUP_CAP 128
+#endif
+constexpr int CLEANUP_CAP = DRSF_CLEANUP_CAP;  // cleanup (its workgroups share one arrival counter)
 int grid_for(int64_t items, int64_t per_block, int cap = GRID_CAP);
 int64_t delta_tiles(int64_t count);
 int64_t insert_regions(int64_t b);

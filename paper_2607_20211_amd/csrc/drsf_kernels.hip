@@ -1931,7 +1931,8 @@ int launch_et_reverse(const Dev &d, void *tmp, size_t tmp_bytes, hipStream_t s) 
 }
 void launch_cleanup(const Dev &d, hipStream_t s) {
     int64_t m = d.pcap > d.max_b ? d.pcap : d.max_b;
-    hipLaunchKernelGGL(k_cleanup, dim3(grid_for(m, BLOCK, SMALL_CAP)), dim3(BLOCK), 0, s, d);
+    // few workgroups: each arrives once on one counter (serialised atomics)
+    hipLaunchKernelGGL(k_cleanup, dim3(grid_for(m, BLOCK, CLEANUP_CAP)), dim3(BLOCK), 0, s, d);
 }
 
 // ------------------------------------------------------ store rebuild
