@@ -206,17 +206,22 @@ def time_op(f, snap, batch, op, reps, drsf):
     return float(np.median(ts))
 
 
-def reversal_ab(n, row, col, par, batches, max_batch, stream, drsf):
-    """The same updates with each path reversal (reverse_mode 0: one thread
-    walks each path; 1: Euler tour of F-hat with list ranking, Alg. 3), both
-    launched kernel by kernel (the Euler tour's library sort is never
-    captured): per step the host-observed update time, the reversal-and-labels
-    phase (less the event bracket), and whether the two modes end in the same
-    forest (digest)."""
+# replacement_mode (0: hooking on every cross edge, HS; 1: supergraph, SG) x
+# reverse_mode (0: a thread per path; 1: Euler tour, ET)
+METHODS = {"hs_paths": (0, 0), "hs_et": (0, 1), "sg_paths": (1, 0), "sg_et": (1, 1)}
+
+
+def methods_ab(n, row, col, par, batches, max_batch, stream, drsf):
+    """The same updates with each replacement-edge method and each path
+    reversal (the paper's SG/HS x ET variants beside this build's defaults),
+    all launched kernel by kernel (the library sorts of SG and ET are never
+    captured): per step the host-observed update time and the replacement
+    and reversal phases (less the event bracket), and whether every method
+    ends in the same forest (digest)."""
     res = {}
-    for mode in (0, 1):
+    for name, (rm, vm) in METHODS.items():
         f = drsf.Forest(n, row, col, par, max_batch=max_batch, stream=stream.cuda_stream,
-                        inputs_on_device=True, profile=True, reverse_mode=mode)
+                        inputs_on_device=True, profile=True, replacement_mode=rm, reverse_mode=vm)
         steps = []
         for edges, op in batches:
             t0 = time.perf_counter()
@@ -225,15 +230,16 @@ def reversal_ab(n, row, col, par, batches, max_batch, stream, drsf):
             t = f.phase_times()
             br = t.pop(drsf.EVENT_BRACKET, 0.0)
             # an update that needed more hooking rounds or search levels than
-            # queued finishes on the host: its reversal is then outside the
-            # phases, but inside the wall time
+            # queued finishes on the host: that work is outside the phases,
+            # but inside the wall time
             steps.append({"op": "insert" if op == drsf.DRSF_INSERT else "delete",
-                          "paths": st["num_paths"],
+                          "cross_edges": st["num_key_cross"], "paths": st["num_paths"],
+                          "replacement_phase_ms": round(t["replacement_edges"] - br, 4),
                           "reversal_and_labels_phase_ms": round(t["reversal_and_labels"] - br, 4),
                           "update_wall_ms": round(wall * 1e3, 4)})
-        res[f"reverse_mode_{mode}"] = {"steps": steps, "digest": [int(x) for x in f.digest()]}
+        res[name] = {"steps": steps, "digest": [int(x) for x in f.digest()]}
         f.close()
-    res["same_result"] = res["reverse_mode_0"]["digest"] == res["reverse_mode_1"]["digest"]
+    res["same_result"] = len({tuple(v["digest"]) for v in res.values()}) == 1
     return res
 
 
@@ -295,15 +301,16 @@ def run_configs(g, dev, stream, log, reps=3):
     drsf.drsf_snapshot_free(snap)
     f.close()
     out["rmat22_from_initial_state"] = sweep
-    # path reversal A/B (row f1) on the headline workload: insert then delete 1e5
+    # replacement-edge and path-reversal methods (rows f1, f2) on the headline
+    # workload: insert then delete 1e5
     ins = torch.from_numpy(gen.insert_batches(g.n, g.keys, 1, 100_000, gen.seed(2, 2, gen.P_INSERT))[0]).to(dev)
     dl = torch.from_numpy(gen.delete_batches(g.n, g.keys, g.parent, 1, 100_000, 50_000,
                                              gen.seed(2, 2, gen.P_DELETE))[0]).to(dev)
-    out["reversal_ab_rmat22_b1e5"] = reversal_ab(
+    out["methods_ab_rmat22_b1e5"] = methods_ab(
         g.n, torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col).to(dev),
         torch.from_numpy(g.parent).to(dev), [(ins, drsf.DRSF_INSERT), (dl, drsf.DRSF_DELETE)],
         100_000, stream, drsf)
-    log(f"reversal A/B rmat22: {out['reversal_ab_rmat22_b1e5']}")
+    log(f"methods A/B rmat22: {out['methods_ab_rmat22_b1e5']}")
     # static rebuild of the graph after the 1e5-insert batch (row f3), against
     # the dynamic updates at b = 1e5
     st = static_rebuild(g.n, np.union1d(g.keys, edge_keys(ins.cpu().numpy())), dev, stream, drsf)
@@ -347,11 +354,11 @@ def run_configs(g, dev, stream, log, reps=3):
                             "delete_updates_per_s": round(1e5 / td, 1), "delete_ms": round(td * 1e3, 4),
                             "insert_updates_per_s": round(1e5 / ti, 1), "insert_ms": round(ti * 1e3, 4),
                             "delete_stats": st_d, "insert_stats": st_i}
-    out["reversal_ab_grid4096"] = reversal_ab(
+    out["methods_ab_grid4096"] = methods_ab(
         gg.n, torch.from_numpy(gg.row_ptr).to(dev), torch.from_numpy(gg.col).to(dev),
         torch.from_numpy(gg.parent).to(dev), [(d_dl, drsf.DRSF_DELETE), (d_ins, drsf.DRSF_INSERT)],
         100_000, stream, drsf)
-    log(f"reversal A/B grid: {out['reversal_ab_grid4096']}")
+    log(f"methods A/B grid: {out['methods_ab_grid4096']}")
     keep = np.ones(len(gg.keys), bool)
     keep[np.searchsorted(gg.keys, edge_keys(dl))] = False
     st = static_rebuild(gg.n, gg.keys[keep], dev, stream, drsf, reps=1)

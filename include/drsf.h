@@ -99,6 +99,14 @@ typedef struct {
                                 library radix sort, kept out of captured graphs);
                                 needs about 56 bytes per vertex more device
                                 memory.  Results are identical. */
+    int replacement_mode;    /* replacement edges: 0 (default) hooking rounds on
+                                every cross edge (Alg. 2); 1: on the supergraph
+                                (Sec. III-A): the cross edges reduced to the
+                                lowest key per pair of trees of F-hat by a radix
+                                sort, then the hooking rounds on those; launched
+                                kernel by kernel with two host reads of sizes;
+                                needs about 24 bytes per cross-edge slot more
+                                device memory.  Results are identical. */
 } drsf_opts;
 
 /* Fills *opts with the defaults described above. */

@@ -129,6 +129,13 @@ struct drsf_ctx {
             *et_finish = nullptr, *et_support = nullptr;
     uint8_t *et_tmp = nullptr;
     size_t et_tmp_bytes = 0;
+    // supergraph replacement edges (replacement_mode 1)
+    uint32_t *sg_rcount = nullptr, *sg_rpos = nullptr, *sg_flag = nullptr, *sg_segid = nullptr;
+    uint64_t *sg_skeys = nullptr, *sg_svals = nullptr;
+    unsigned long long *sg_totals = nullptr;
+    uint8_t *sg_scan_tmp = nullptr, *sg_sort_tmp = nullptr;
+    size_t sg_sort_bytes = 0;
+    int round_base = 0;  // index of the first hooking round of the last update
     // status word, counters and per-graph batch status share one allocation
     // so that one copy returns them: status at word 0, counters from word 1,
     // gstat after the counters
@@ -289,6 +296,9 @@ int read_status(drsf_ctx *c, int32_t *st) {
 int alloc_tiles(drsf_ctx *c) {
     int rc;
     dfree(c, c->x0); dfree(c, c->x1); dfree(c, c->rcnt); dfree(c, c->rstart); dfree(c, c->xcnt);
+    dfree(c, c->sg_rcount); dfree(c, c->sg_rpos); dfree(c, c->sg_flag); dfree(c, c->sg_segid);
+    dfree(c, c->sg_skeys); dfree(c, c->sg_svals); dfree(c, c->sg_totals); dfree(c, c->sg_scan_tmp);
+    dfree(c, c->sg_sort_tmp);
     dfree(c, c->lists);
     if (c->h_lists) (void)hipHostFree(c->h_lists);
     c->h_lists = nullptr;
@@ -300,6 +310,16 @@ int alloc_tiles(drsf_ctx *c) {
     if ((rc = dalloc(c, &c->rstart, c->ntiles + 1))) return rc;
     if ((rc = dalloc(c, &c->xcnt, c->ntiles + 1))) return rc;
     launch_fill_u64(c->rcnt, nregmax, 0, c->stream);
+    if (c->opts.replacement_mode == 1) {  // supergraph scratch, sized by the cross-edge slots
+        if ((rc = dalloc(c, &c->sg_rcount, nregmax)) || (rc = dalloc(c, &c->sg_rpos, nregmax)) ||
+            (rc = dalloc(c, &c->sg_flag, c->xcap)) || (rc = dalloc(c, &c->sg_segid, c->xcap)) ||
+            (rc = dalloc(c, &c->sg_skeys, c->xcap)) || (rc = dalloc(c, &c->sg_svals, c->xcap)) ||
+            (rc = dalloc(c, &c->sg_totals, 2)) ||
+            (rc = dalloc(c, &c->sg_scan_tmp, (int64_t)scan_tmp_bytes(c->xcap) + 64)))
+            return rc;
+        c->sg_sort_bytes = sort_pairs_u64_tmp_bytes(c->xcap) + 256;
+        if ((rc = dalloc(c, &c->sg_sort_tmp, (int64_t)c->sg_sort_bytes))) return rc;
+    }
     if (c->ngraph > 1) {
         // every vertex block and every tile appears at most once per list
         c->nvblk = (c->n + BLOCK - 1) / BLOCK;
@@ -643,6 +663,42 @@ int rebuild_store(drsf_ctx *c) {
     return DRSF_OK;
 }
 
+// Supergraph mode: reads the orphan-scan mode and the region sizes back,
+// then queues the reduction of the first round's cross edges to one per pair
+// of pieces (dense in x0 for the rounds from SG_ROUND0).
+int sg_reduce(drsf_ctx *c, const Dev &d, hipStream_t s) {
+    unsigned long long *f = c->h_ret + c->ret_words + 3;  // [0] status, [1] scan mode, [2] slots
+    HIPCHK(c, hipMemcpyAsync(f, c->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(f + 1, c->cnt + C_OMODE, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(f + 2, c->cnt + C_OVOL, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (*(int32_t *)f != 0) return DRSF_OK;  // failed already: the rounds skip themselves
+    const bool om = f[1] != 0;
+    const int64_t nr_om = om ? ((int64_t)f[2] + OR_W - 1) / OR_W : 0;
+    const Ctl &k = *c->h_ctl;
+    const int64_t rlo2 = om ? std::max<int64_t>(k.rlo, c->ntiles) : k.rlo;
+    const int64_t nreg = nr_om + std::max<int64_t>(k.rhi - rlo2, 0);
+    SgScratch g;
+    g.rcount = c->sg_rcount;
+    g.rpos = c->sg_rpos;
+    g.flag = c->sg_flag;
+    g.segid = c->sg_segid;
+    g.skeys = c->sg_skeys;
+    g.svals = c->sg_svals;
+    g.totals = c->sg_totals;
+    g.scan_tmp = c->sg_scan_tmp;
+    g.sort_tmp = c->sg_sort_tmp;
+    g.sort_tmp_bytes = c->sg_sort_bytes;
+    launch_sg_regions(d, nr_om, rlo2, nreg, g, s);
+    HIPCHK(c, hipMemcpyAsync(f, c->sg_totals, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    const int64_t total = (int64_t)f[0];
+    if (total > c->xcap) return fail(c, DRSF_E_DEVICE, "supergraph: %lld cross edges", (long long)total);
+    if (launch_sg_reduce(d, nr_om, rlo2, nreg, total, g, s))
+        return fail(c, DRSF_E_DEVICE, "supergraph: radix sort failed");
+    return DRSF_OK;
+}
+
 // The update sequence (see the file comment) for batches with inserts
 // (kind bit 1) and/or deletes (kind bit 2); with events when profiling.
 void enqueue_update(drsf_ctx *c, int kind, bool profile) {
@@ -678,7 +734,14 @@ void enqueue_update(drsf_ctx *c, int kind, bool profile) {
     if (del) launch_sweep_delta(d, s);
     mark(PH_REPL);
     const int64_t units = (ins ? insert_regions(c->max_batch) : 0) + (del ? c->ntiles + c->dtmax : 0);
-    launch_boruvka(d, 0, c->bor_fast, units, s);
+    if (c->opts.replacement_mode == 1) {  // supergraph, then its rounds
+        c->round_base = SG_ROUND0;
+        if (sg_reduce(c, d, s)) launch_fill_i32(c->status, 1, ST_ROUND_BOUND, s);
+        launch_boruvka(d, SG_ROUND0, SG_ROUND0 + c->bor_fast, units, s);
+    } else {
+        c->round_base = 0;
+        launch_boruvka(d, 0, c->bor_fast, units, s);
+    }
     mark(PH_ROOTING);
     launch_sf_root(d, s);
     launch_sf_bfs(d, 0, c->bfs_fast, s);
@@ -721,12 +784,12 @@ int continue_update(drsf_ctx *c) {
     };
     const int64_t np_max = c->pcap;
     // each round at least halves the components that still have a live edge
-    const int bor_bound = std::min(ceil_log2(np_max + 2) + 2, MAX_ROUNDS);
+    const int bor_bound = std::min(c->round_base + ceil_log2(np_max + 2) + 2, MAX_ROUNDS);
     const int lr_rounds = std::min(ceil_log2(2 * np_max + 2) + 2, MAX_ROUNDS);
     int rc;
     if ((rc = read_flags(c->bfs_fast))) return rc;
     bool bad = *(int32_t *)f != 0, done = f[1] != 0, bfs_done = f[2] == 0;
-    int r = c->bor_fast, lv = c->bfs_fast;
+    int r = c->round_base + c->bor_fast, lv = c->bfs_fast;
     if (!bad && !done) {
         while (!done && !bad && r < bor_bound) {
             const int r1 = std::min(r + BOR_CHUNK, bor_bound);
@@ -779,7 +842,9 @@ int launch_update(drsf_ctx *c) {
     *(volatile unsigned long long *)(c->h_ret + c->ret_words + 7) = 0;
     c->kind = (c->h_ctl->has_ins ? 1 : 0) | (c->h_ctl->has_del ? 2 : 0);
     if (c->kind == 0) c->kind = 3;  // nothing but rejected or empty batches: run everything
-    if (prof || c->opts.reverse_mode == 1) {  // the Euler-tour reversal's sort is not captured
+    // the library sorts of the Euler-tour reversal and of the supergraph are
+    // not captured; the supergraph also reads sizes back
+    if (prof || c->opts.reverse_mode == 1 || c->opts.replacement_mode == 1) {
         enqueue_update(c, c->kind, prof);
     } else {
         int rc;
@@ -875,6 +940,10 @@ static int create_impl(int32_t G, const int32_t *n_off, int32_t n, const int64_t
         }
     if (c->opts.reverse_mode < 0 || c->opts.reverse_mode > 1) {
         fail(c, DRSF_E_ARG, "reverse_mode must be 0 or 1");
+        return bail(DRSF_E_ARG);
+    }
+    if (c->opts.replacement_mode < 0 || c->opts.replacement_mode > 1) {
+        fail(c, DRSF_E_ARG, "replacement_mode must be 0 or 1");
         return bail(DRSF_E_ARG);
     }
     {

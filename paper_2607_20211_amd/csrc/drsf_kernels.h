@@ -217,6 +217,23 @@ void launch_superforest_lr(const Dev &d, int lr_rounds, hipStream_t s);
 void launch_finish(const Dev &d, bool ins, bool del, bool rev, hipStream_t s);  // path reversal and labels
 // path reversal by Euler tour (Alg. 3); tmp/tmp_bytes: radix-sort scratch
 int launch_et_reverse(const Dev &d, void *tmp, size_t tmp_bytes, hipStream_t s);
+// Supergraph (Sec. III-A): the first round's cross edges reduced to one per
+// pair of pieces (the lowest key), written densely to x0 with its count in
+// C_NX0, ready for hooking rounds started at SG_ROUND0.
+constexpr int SG_ROUND0 = 3;
+struct SgScratch {
+    uint32_t *rcount, *rpos;     // [nregmax] cross edges per region, prefix
+    uint32_t *flag, *segid;      // [xcap] segment heads, segment index
+    uint64_t *skeys, *svals;     // [xcap] sorted (piece pair, edge key)
+    unsigned long long *totals;  // [2] device totals (edges, segments)
+    void *scan_tmp;              // scan scratch (for xcap items)
+    void *sort_tmp;
+    size_t sort_tmp_bytes;
+};
+void launch_sg_regions(const Dev &d, int64_t nr_om, int64_t rlo2, int64_t nreg, const SgScratch &g,
+                       hipStream_t s);
+int launch_sg_reduce(const Dev &d, int64_t nr_om, int64_t rlo2, int64_t nreg, int64_t total,
+                     const SgScratch &g, hipStream_t s);
 void launch_cleanup(const Dev &d, hipStream_t s);
 
 // store rebuild: live degrees of the base store, the inserted edges as
@@ -234,6 +251,9 @@ void launch_rb_fill(int32_t n, const uint32_t *bptr, const int32_t *bcol, const 
                     const int32_t *lcol, const uint64_t *pairs, const uint32_t *dstart,
                     const uint32_t *ddeg, const int64_t *row_ptr, int32_t *col, hipStream_t s);
 size_t sort_u64_tmp_bytes(int64_t count);
+size_t sort_pairs_u64_tmp_bytes(int64_t count);
+int launch_sort_pairs_u64(const uint64_t *kin, uint64_t *kout, const uint64_t *vin, uint64_t *vout,
+                          int64_t count, void *tmp, size_t tmp_bytes, hipStream_t s);
 int launch_sort_u64(const uint64_t *in, uint64_t *out, int64_t count, void *tmp, size_t tmp_bytes,
                     hipStream_t s);
 

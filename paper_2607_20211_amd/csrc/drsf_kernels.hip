@@ -1636,6 +1636,90 @@ __global__ __launch_bounds__(BLOCK) void k_label_insert(Dev d) {
     label_insert(d, blockIdx.x, gridDim.x);
 }
 
+// ---------------- f2: replacement edges on the supergraph (Sec. III-A)
+//
+// The supergraph has a vertex per piece and an edge per pair of pieces that
+// a cross edge joins.  Its edges are taken from the cross edges of the first
+// round by a radix sort on the piece pair and a minimum per run of equal
+// pairs (the lowest key of the pair, where the paper keeps whichever edge a
+// racy hash write leaves); the hooking rounds then run on these edges only.
+// Regions holding the first round's cross edges: the orphan scan's ranges
+// [0, nr_om) when it ran, then regions from rlo2.
+__device__ __forceinline__ int64_t sg_region(int64_t i, int64_t nr_om, int64_t rlo2) {
+    return i < nr_om ? i : rlo2 + (i - nr_om);
+}
+
+// cross edges per region, and the cross-edge count statistic (as round 0)
+__global__ __launch_bounds__(BLOCK) void k_sg_count(Dev d, int64_t nr_om, int64_t rlo2, int64_t nreg,
+                                                    uint32_t *rcount) {
+    if (*d.status) return;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    unsigned long long st = 0;
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < nreg; i += stride) {
+        const unsigned long long c = d.rcnt[sg_region(i, nr_om, rlo2)];
+        rcount[i] = (uint32_t)c;
+        st += i < nr_om ? d.xcnt[i] : c;  // the orphan scan counted its edges before merging runs
+    }
+    for (int o = WAVE / 2; o > 0; o >>= 1) st += __shfl_xor(st, o);
+    if (lane_id() == 0 && st) atomicAdd(&d.cnt[C_NCROSS], st);
+}
+
+// (smaller piece << 32 | larger piece) and the edge key of every cross edge,
+// densely (one workgroup per region)
+__global__ __launch_bounds__(BLOCK) void k_sg_gather(Dev d, int64_t nr_om, int64_t rlo2, int64_t nreg,
+                                                     const uint32_t *rpos, uint64_t *keys, uint64_t *vals) {
+    if (*d.status) return;
+    for (int64_t i = blockIdx.x; i < nreg; i += gridDim.x) {
+        const int64_t t = sg_region(i, nr_om, rlo2);
+        const int64_t c = (int64_t)d.rcnt[t], base = rpos[i];
+        const Cross *in = d.x0 + t * TILE;
+        for (int64_t j = threadIdx.x; j < c; j += BLOCK) {
+            const Cross e = in[j];
+            const uint32_t lo = (uint32_t)(e.pa < e.pb ? e.pa : e.pb), hi = (uint32_t)(e.pa < e.pb ? e.pb : e.pa);
+            keys[base + j] = ((uint64_t)lo << 32) | hi;
+            vals[base + j] = e.key;
+        }
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_sg_heads(int64_t total, const uint64_t *skeys, uint32_t *flag) {
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j < total; j += stride)
+        flag[j] = (j == 0 || skeys[j] != skeys[j - 1]) ? 1u : 0u;
+}
+
+// lowest key per run of equal pairs (segid: exclusive count of heads)
+__global__ __launch_bounds__(BLOCK) void k_sg_min(int64_t total, const uint32_t *flag, const uint32_t *segid,
+                                                  const uint64_t *svals, uint64_t *smin) {
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j < total; j += stride) {
+        const int64_t seg = (int64_t)segid[j] + flag[j] - 1;
+        const uint64_t v = svals[j];
+        if (smin[seg] > v) atomicMin((unsigned long long *)&smin[seg], (unsigned long long)v);
+    }
+}
+
+// the supergraph's edges, densely in x0, with their count in C_NX0
+__global__ __launch_bounds__(BLOCK) void k_sg_emit(Dev d, int64_t total, const uint64_t *skeys,
+                                                   const uint32_t *flag, const uint32_t *segid,
+                                                   const uint64_t *smin, const unsigned long long *nseg) {
+    if (*d.status) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        d.cnt[C_NX0] = *nseg;
+        d.cnt[C_NX1] = 0;
+    }
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j < total; j += stride) {
+        if (!flag[j]) continue;
+        const int64_t seg = segid[j];
+        Cross e;
+        e.key = smin[seg];
+        e.pa = (int32_t)(skeys[j] >> 32);
+        e.pb = (int32_t)(uint32_t)skeys[j];
+        d.x0[seg] = e;
+    }
+}
+
 // -------------------------- f1: path reversal by Euler tour (Alg. 3)
 //
 // F-hat is the forest of the parents as they are before any reversal.  Its
@@ -1907,6 +1991,32 @@ void launch_finish(const Dev &d, bool ins, bool del, bool rev, hipStream_t s) {
         hipLaunchKernelGGL(k_label_insert, dim3(grid_for(d.nvb, BLOCK / WAVE, GRID_CAP)), dim3(BLOCK), 0,
                            s, d);
 }
+void launch_sg_regions(const Dev &d, int64_t nr_om, int64_t rlo2, int64_t nreg, const SgScratch &g,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_sg_count, dim3(grid_for(nreg, BLOCK)), dim3(BLOCK), 0, s, d, nr_om, rlo2, nreg,
+                       g.rcount);
+    launch_scan_u32(g.rcount, g.rpos, g.totals, nreg, g.scan_tmp, s);
+}
+int launch_sg_reduce(const Dev &d, int64_t nr_om, int64_t rlo2, int64_t nreg, int64_t total,
+                     const SgScratch &g, hipStream_t s) {
+    // the dense (pair, key) lists use x1, which the rounds overwrite later
+    uint64_t *keys = reinterpret_cast<uint64_t *>(d.x1), *vals = keys + d.xcap;
+    hipLaunchKernelGGL(k_sg_gather, dim3(grid_for(nreg, 1)), dim3(BLOCK), 0, s, d, nr_om, rlo2, nreg, g.rpos,
+                       keys, vals);
+    if (total > 0 &&
+        launch_sort_pairs_u64(keys, g.skeys, vals, g.svals, total, g.sort_tmp, g.sort_tmp_bytes, s))
+        return -1;
+    const int gt = grid_for(total, BLOCK);
+    hipLaunchKernelGGL(k_sg_heads, dim3(gt), dim3(BLOCK), 0, s, total, g.skeys, g.flag);
+    launch_scan_u32(g.flag, g.segid, g.totals + 1, total, g.scan_tmp, s);
+    uint64_t *smin = keys;  // the unsorted keys are no longer needed
+    launch_fill_u64(smin, total > 0 ? total : 1, KEY_INF, s);
+    hipLaunchKernelGGL(k_sg_min, dim3(gt), dim3(BLOCK), 0, s, total, g.flag, g.segid, g.svals, smin);
+    hipLaunchKernelGGL(k_sg_emit, dim3(gt), dim3(BLOCK), 0, s, d, total, g.skeys, g.flag, g.segid, smin,
+                       g.totals + 1);
+    return 0;
+}
+
 int launch_et_reverse(const Dev &d, void *tmp, size_t tmp_bytes, hipStream_t s) {
     const int gv = grid_for(d.n, BLOCK, GRID_CAP), ga = grid_for(2 * (int64_t)d.n, BLOCK, GRID_CAP);
     hipLaunchKernelGGL(k_et_keys, dim3(gv), dim3(BLOCK), 0, s, d);

@@ -19,4 +19,21 @@ int launch_sort_u64(const uint64_t *in, uint64_t *out, int64_t count, void *tmp,
     return hipcub::DeviceRadixSort::SortKeys(tmp, bytes, in, out, (int)count, 0, 64, s) == hipSuccess ? 0 : -1;
 }
 
+size_t sort_pairs_u64_tmp_bytes(int64_t count) {
+    size_t bytes = 0;
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint64_t *)nullptr, (uint64_t *)nullptr,
+                                             (const uint64_t *)nullptr, (uint64_t *)nullptr, (int)count, 0, 64,
+                                             (hipStream_t)0);
+    return bytes;
+}
+
+int launch_sort_pairs_u64(const uint64_t *kin, uint64_t *kout, const uint64_t *vin, uint64_t *vout,
+                          int64_t count, void *tmp, size_t tmp_bytes, hipStream_t s) {
+    size_t bytes = tmp_bytes;
+    return hipcub::DeviceRadixSort::SortPairs(tmp, bytes, kin, kout, vin, vout, (int)count, 0, 64, s) ==
+                   hipSuccess
+               ? 0
+               : -1;
+}
+
 }  // namespace drsf

@@ -38,7 +38,8 @@ class drsf_opts(ctypes.Structure):
                 ("sweep_mode", ctypes.c_int),
                 ("rounds_queued", ctypes.c_int),
                 ("levels_queued", ctypes.c_int),
-                ("reverse_mode", ctypes.c_int)]
+                ("reverse_mode", ctypes.c_int),
+                ("replacement_mode", ctypes.c_int)]
 
 
 class drsf_view(ctypes.Structure):
@@ -342,7 +343,8 @@ class Forest:
     def __init__(self, n: int, row_ptr, col, parent, *, max_batch: int = 1 << 20,
                  stream=None, inputs_on_device: bool = False, validate: bool = True,
                  profile: bool = False, delta_capacity: int = 0, sweep_mode: int = 0,
-                 rounds_queued: int = 0, levels_queued: int = 0, reverse_mode: int = 0):
+                 rounds_queued: int = 0, levels_queued: int = 0, reverse_mode: int = 0,
+                 replacement_mode: int = 0):
         o = drsf_default_opts()
         o.max_batch = max_batch
         o.inputs_on_device = int(inputs_on_device)
@@ -353,6 +355,7 @@ class Forest:
         o.rounds_queued = rounds_queued
         o.levels_queued = levels_queued
         o.reverse_mode = reverse_mode
+        o.replacement_mode = replacement_mode
         if stream is not None:
             o.stream = stream
         if not inputs_on_device:
@@ -442,7 +445,8 @@ class MultiForest(Forest):
     def __init__(self, n_off, row_ptr, col, parent, *, max_batch: int = 1 << 20,
                  stream=None, inputs_on_device: bool = False, validate: bool = True,
                  profile: bool = False, delta_capacity: int = 0, sweep_mode: int = 0,
-                 rounds_queued: int = 0, levels_queued: int = 0, reverse_mode: int = 0):
+                 rounds_queued: int = 0, levels_queued: int = 0, reverse_mode: int = 0,
+                 replacement_mode: int = 0):
         o = drsf_default_opts()
         o.max_batch = max_batch
         o.inputs_on_device = int(inputs_on_device)

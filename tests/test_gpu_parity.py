@@ -294,11 +294,63 @@ def test_euler_tour_reversal(workload):
     pair.gpu.close()
 
 
+@pytest.mark.parametrize("workload,reverse_mode", [("gnm", 0), ("rmat16", 0), ("grid", 0),
+                                                   ("continuation", 0), ("gnm", 1), ("grid", 1)])
+def test_supergraph_replacement_edges(workload, reverse_mode):
+    """Replacement edges on the supergraph (replacement_mode 1: cross edges
+    reduced to the lowest key per pair of trees, Sec. III-A), alone and with
+    the Euler-tour reversal (the paper's SG-ET): bit-exact with the oracle."""
+    drsf = _lib()
+    _case(f"supergraph {workload} reverse_mode={reverse_mode}")
+    kw = dict(replacement_mode=1, reverse_mode=reverse_mode)
+    if workload == "gnm":
+        n = 30011
+        g = gen.make_graph("sparse", n, gen.gnm(n, 27000, gen.seed(17, 0, gen.P_GRAPH)))
+        pair = Pair(g, max_batch=8192, **kw)
+        for step in range(3):
+            ins = gen.insert_batches(n, pair.keys, 1, 3000, gen.seed(17, step, gen.P_INSERT))[0]
+            pair.step(ins, drsf.DRSF_INSERT, f"gnm insert {step}")
+            dl = gen.delete_batches(n, pair.keys, pair.parent, 1, 3000, 1500,
+                                    gen.seed(17, step, gen.P_DELETE))[0]
+            pair.step(dl, drsf.DRSF_DELETE, f"gnm delete {step}")
+    elif workload == "rmat16":
+        for sweep_mode in (0, 1):
+            keys = gen.rmat(16, 16, 0.57, 0.19, 0.19, gen.seed(17, 1, gen.P_GRAPH))
+            g = gen.make_graph("rmat16", 1 << 16, keys)
+            pair = Pair(g, sweep_mode=sweep_mode, **kw)
+            ins = gen.insert_batches(g.n, pair.keys, 1, 10000, gen.seed(17, 1, gen.P_INSERT))[0]
+            pair.step(ins, drsf.DRSF_INSERT, "rmat insert")
+            dl = gen.delete_batches(g.n, pair.keys, pair.parent, 1, 10000, 5000, gen.seed(17, 1, gen.P_DELETE))[0]
+            pair.step(dl, drsf.DRSF_DELETE, "rmat delete")
+            pair.gpu.close()
+        return
+    elif workload == "grid":
+        keys = gen.grid(256, 256, 3276, gen.seed(17, 2, gen.P_GRAPH))
+        g = gen.make_graph("grid", 256 * 256, keys)
+        pair = Pair(g, **kw)
+        dl = gen.delete_batches(g.n, pair.keys, pair.parent, 1, 2000, 2000, gen.seed(17, 2, gen.P_DELETE))[0]
+        pair.step(dl, drsf.DRSF_DELETE, "grid delete")
+        ins = gen.insert_batches(g.n, pair.keys, 1, 2000, gen.seed(17, 2, gen.P_INSERT))[0]
+        pair.step(ins, drsf.DRSF_INSERT, "grid insert")
+    else:
+        n = 20_000
+        g = gen.make_graph("empty", n, np.zeros(0, np.uint64))
+        pair = Pair(g, max_batch=1 << 16, **kw)
+        ins = gen.insert_batches(n, g.keys, 1, 40_000, gen.seed(17, 4, gen.P_INSERT))[0]
+        pair.step(ins, drsf.DRSF_INSERT, "continuation insert")
+        dl = gen.delete_batches(n, pair.keys, pair.parent, 1, 20_000, 10_000, gen.seed(17, 4, gen.P_DELETE))[0]
+        pair.step(dl, drsf.DRSF_DELETE, "continuation delete")
+    pair.gpu.close()
+
+
 def test_reverse_mode_rejects_unknown_value():
     drsf = _lib()
     g = gen.make_graph("tiny", 10, gen.gnm(10, 12, 3))
     with pytest.raises(drsf.DrsfError) as ei:
         drsf.Forest(g.n, g.row_ptr, g.col, g.parent, reverse_mode=2)
+    assert ei.value.code == drsf.DRSF_E_ARG
+    with pytest.raises(drsf.DrsfError) as ei:
+        drsf.Forest(g.n, g.row_ptr, g.col, g.parent, replacement_mode=-1)
     assert ei.value.code == drsf.DRSF_E_ARG
 
 
