@@ -512,9 +512,10 @@ def main():
     if not args.no_tune:
         from paper_2607_20211_amd import autotune
 
-        def sample(fr):
-            fr.apply(d_ins[0], drsf.DRSF_INSERT)
-            fr.apply(d_del[0], drsf.DRSF_DELETE)
+        def sample(fr):  # the warm-up steps' batches (never the timed ones)
+            for i in range(max(1, min(W, 3))):
+                fr.apply(d_ins[i], drsf.DRSF_INSERT)
+                fr.apply(d_del[i], drsf.DRSF_DELETE)
         tuning = autotune.tune(f, sample, f"rmat{scale}_insert{b}_delete{b}", use_cache=False)
         log(f"tuning: {tuning}")
     for i in range(W):
@@ -646,6 +647,8 @@ def main():
                       "max": round(float(np.max(lat_del)) * 1e3, 4)},
         "insert_device_ms_profiled": round(t_ins_dev * 1e3, 4),
         "delete_device_ms_profiled": round(t_del_dev * 1e3, 4),
+        "steps_ms": {"insert": [round(x * 1e3, 4) for x in lat_ins],
+                     "delete": [round(x * 1e3, 4) for x in lat_del]},
         "batch_stats_insert": {k: float(np.mean([x[k] for x in st_ins])) for k in st_ins[0]},
         "batch_stats_delete": {k: float(np.mean([x[k] for x in st_del])) for k in st_del[0]},
         "phase_ms_insert": {k: round(v, 4) for k, v in pi.items()},

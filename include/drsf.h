@@ -133,6 +133,9 @@ typedef struct {
     int64_t orphan_slots;     /* delete: adjacency entries of those vertices */
     int32_t scan_orphans;     /* delete: 1 if the key-edge scan covered only the
                                  orphans' adjacency, 0 if the whole store */
+    int32_t host_finished;    /* 1 if the update needed more hooking rounds or
+                                 search levels than queued and was finished by
+                                 host-driven launches */
 } drsf_view;
 
 /*

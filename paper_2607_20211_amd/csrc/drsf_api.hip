@@ -1263,7 +1263,9 @@ int drsf_wait(drsf_ctx *c, drsf_view *out) {
         if (!seen || *done != c->seq) HIPCHK(c, hipStreamSynchronize(c->stream));
         const unsigned long long *k = c->h_ret + 1;
         int32_t st = *(int32_t *)c->h_ret;
+        c->view.host_finished = 0;
         if (st == 0 && !k[C_ORIENTED]) {  // the captured rounds did not finish it
+            c->view.host_finished = 1;
             const int rc = continue_update(c);
             if (rc) return c->last_rc = rc;
             st = *(int32_t *)c->h_ret;

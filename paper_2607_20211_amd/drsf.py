@@ -53,7 +53,8 @@ class drsf_view(ctypes.Structure):
                 ("num_paths", ctypes.c_int64),
                 ("num_orphans", ctypes.c_int64),
                 ("orphan_slots", ctypes.c_int64),
-                ("scan_orphans", ctypes.c_int32)]
+                ("scan_orphans", ctypes.c_int32),
+                ("host_finished", ctypes.c_int32)]
 
 
 class DrsfError(RuntimeError):
@@ -392,7 +393,8 @@ class Forest:
         return {"num_edges": v.num_edges, "num_key_cross": v.num_key_cross,
                 "num_replacement": v.num_replacement, "num_pieces": v.num_pieces,
                 "num_paths": v.num_paths, "num_orphans": v.num_orphans,
-                "orphan_slots": v.orphan_slots, "scan_orphans": v.scan_orphans}
+                "orphan_slots": v.orphan_slots, "scan_orphans": v.scan_orphans,
+                "host_finished": v.host_finished}
 
     def parent(self) -> np.ndarray:
         p = np.empty(self.n, dtype=np.int32)
