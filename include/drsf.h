@@ -231,8 +231,9 @@ int drsf_digest(drsf_ctx *ctx, uint64_t *out);
  * components takes the smaller as its root, repeated with pointer jumping
  * until no edge joins two roots), so each component is rooted at its
  * smallest vertex, then a breadth-first forest from all roots at once
- * (a level is expanded from its frontier's rows when the frontier is small,
- * else by one pass over all rows).
+ * (a level is expanded top-down from its frontier's rows when they are few
+ * and short, else bottom-up: every unvisited vertex takes the first
+ * neighbour on the frontier in its row).
  * row_ptr: DEVICE int64[n + 1]; col: DEVICE int32[row_ptr[n]] (may be NULL
  * when row_ptr[n] == 0), a symmetric CSR without self-loops (not checked
  * here).  parent_out, label_out: DEVICE

@@ -14,11 +14,23 @@
 namespace drsf {
 namespace {
 
-// row of every CSR slot (one wave per row)
-__global__ __launch_bounds__(BLOCK) void k_st_rows(int32_t n, const int64_t *row_ptr, int32_t *erow) {
-    const int64_t nw = (int64_t)gridDim.x * (BLOCK / WAVE);
-    for (int64_t u = (int64_t)blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE; u < n; u += nw)
-        for (int64_t s = row_ptr[u] + lane_id(); s < row_ptr[u + 1]; s += WAVE) erow[s] = (int32_t)u;
+// Row of every CSR slot: the number of rows u >= 1 whose first slot is at
+// or before it.  Each row u >= 1 counts 1 at its first slot (k_st_marks;
+// empty rows share the next row's first slot), an exclusive sum over the
+// slots follows, and the row of slot s is that sum plus its own count.
+__global__ __launch_bounds__(BLOCK) void k_st_marks(int32_t n, const int64_t *row_ptr, int64_t nnz,
+                                                    uint32_t *mark) {
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t u = 1 + (int64_t)blockIdx.x * BLOCK + threadIdx.x; u < n; u += stride) {
+        const int64_t a = row_ptr[u];
+        if (a < nnz) atomicAdd(&mark[a], 1u);
+    }
+}
+__global__ __launch_bounds__(BLOCK) void k_st_rows(int64_t nnz, const uint32_t *mark, const uint32_t *excl,
+                                                   int32_t *erow) {
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < nnz; s += stride)
+        erow[s] = (int32_t)(excl[s] + mark[s]);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_st_iota(int32_t n, int32_t *comp) {
@@ -36,6 +48,43 @@ __device__ __forceinline__ int64_t wave_append(bool take, unsigned long long *cn
     if (lane_id() == leader) base = atomicAdd(cnt, (unsigned long long)__popcll(m));
     base = __shfl(base, leader);
     return (int64_t)base + __popcll(m & ((1ull << lane_id()) - 1ull));
+}
+
+// Row lengths of the vertices a workgroup claimed, into the next level's
+// degree sum and maximum (stat[0] sum, stat[1] max): each thread accumulates
+// over its whole grid-stride loop, then one atomic pair per workgroup (every
+// thread calls it once, at the end of the kernel).
+__device__ __forceinline__ void block_degree(unsigned long long sum, unsigned long long mx,
+                                             unsigned long long *stat) {
+    __shared__ unsigned long long s_sum[BLOCK / WAVE], s_max[BLOCK / WAVE];
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        sum += __shfl_xor(sum, o);
+        const unsigned long long y = __shfl_xor(mx, o);
+        mx = y > mx ? y : mx;
+    }
+    if (lane_id() == 0) {
+        s_sum[threadIdx.x / WAVE] = sum;
+        s_max[threadIdx.x / WAVE] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0, m = 0;
+        for (int w = 0; w < BLOCK / WAVE; w++) {
+            t += s_sum[w];
+            m = s_max[w] > m ? s_max[w] : m;
+        }
+        if (t) {
+            atomicAdd(&stat[0], t);
+            if (stat[1] < m) atomicMax(&stat[1], m);
+        }
+    }
+}
+__device__ __forceinline__ void add_degree(bool take, const int64_t *row_ptr, int32_t w, unsigned long long &sum,
+                                           unsigned long long &mx) {
+    if (!take) return;
+    const unsigned long long dg = (unsigned long long)(row_ptr[w + 1] - row_ptr[w]);
+    sum += dg;
+    mx = dg > mx ? dg : mx;
 }
 
 __device__ __forceinline__ int32_t st_root(const int32_t *comp, int32_t x) {
@@ -72,10 +121,11 @@ __global__ __launch_bounds__(BLOCK) void k_st_compress(int32_t n, int32_t *comp)
 }
 
 // roots: level 0, their own parents, the first frontier
-__global__ __launch_bounds__(BLOCK) void k_st_bfs_init(int32_t n, const int32_t *comp, int32_t *level,
-                                                       int32_t *parent, int32_t *front,
-                                                       unsigned long long *fcnt) {
+__global__ __launch_bounds__(BLOCK) void k_st_bfs_init(int32_t n, const int64_t *row_ptr, const int32_t *comp,
+                                                       int32_t *level, int32_t *parent, int32_t *front,
+                                                       unsigned long long *fcnt, unsigned long long *fstat) {
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    unsigned long long dsum = 0, dmax = 0;
     for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < n; base += stride) {
         const int64_t v = base + threadIdx.x;
         const bool root = v < n && comp[v] == (int32_t)v;
@@ -85,7 +135,9 @@ __global__ __launch_bounds__(BLOCK) void k_st_bfs_init(int32_t n, const int32_t 
         }
         const int64_t pos = wave_append(root, fcnt);
         if (root) front[pos] = (int32_t)v;
+        add_degree(root, row_ptr, (int32_t)v, dsum, dmax);
     }
+    block_degree(dsum, dmax, fstat);
 }
 
 // Top-down level from a small frontier: one wave per frontier vertex claims
@@ -93,9 +145,11 @@ __global__ __launch_bounds__(BLOCK) void k_st_bfs_init(int32_t n, const int32_t 
 __global__ __launch_bounds__(BLOCK) void k_st_top_down(const int64_t *row_ptr, const int32_t *col,
                                                        int32_t *level, int32_t *parent, int L,
                                                        const int32_t *front, const unsigned long long *fcnt,
-                                                       int32_t *next, unsigned long long *ncnt) {
+                                                       int32_t *next, unsigned long long *ncnt,
+                                                       unsigned long long *nstat) {
     const int64_t nf = (int64_t)*fcnt;
     const int64_t nw = (int64_t)gridDim.x * (BLOCK / WAVE);
+    unsigned long long dsum = 0, dmax = 0;
     for (int64_t f = (int64_t)blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE; f < nf; f += nw) {
         const int32_t v = front[f];
         const int64_t a = row_ptr[v], b = row_ptr[v + 1];
@@ -110,22 +164,26 @@ __global__ __launch_bounds__(BLOCK) void k_st_top_down(const int64_t *row_ptr, c
             }
             const int64_t pos = wave_append(claim, ncnt);
             if (claim) next[pos] = w;
+            add_degree(claim, row_ptr, w, dsum, dmax);
         }
     }
+    block_degree(dsum, dmax, nstat);
 }
 
-// Edge-parallel level for a large frontier: every slot (u, w) with u on
-// level L claims w.
-__global__ __launch_bounds__(BLOCK) void k_st_edges(int64_t nnz, const int32_t *erow, const int32_t *col,
-                                                    int32_t *level, int32_t *parent, int L, int32_t *next,
-                                                    unsigned long long *ncnt) {
+// Edge-parallel level for a frontier with long rows but few edges: every
+// slot (u, w) with u on level L claims w.
+__global__ __launch_bounds__(BLOCK) void k_st_edges(int64_t nnz, const int64_t *row_ptr, const int32_t *erow,
+                                                    const int32_t *col, int32_t *level, int32_t *parent, int L,
+                                                    int32_t *next, unsigned long long *ncnt,
+                                                    unsigned long long *nstat) {
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    unsigned long long dsum = 0, dmax = 0;
     for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < nnz; base += stride) {
         const int64_t s = base + threadIdx.x;
         bool claim = false;
-        int32_t w = 0, u = 0;
+        int32_t w = 0;
         if (s < nnz) {
-            u = erow[s];
+            const int32_t u = erow[s];
             if (level[u] == L) {
                 w = col[s];
                 claim = level[w] < 0 && atomicCAS(&level[w], -1, L + 1) == -1;
@@ -134,7 +192,40 @@ __global__ __launch_bounds__(BLOCK) void k_st_edges(int64_t nnz, const int32_t *
         }
         const int64_t pos = wave_append(claim, ncnt);
         if (claim) next[pos] = w;
+        add_degree(claim, row_ptr, w, dsum, dmax);
     }
+    block_degree(dsum, dmax, nstat);
+}
+
+// Bottom-up level for a large frontier: every unvisited vertex looks along
+// its row for a neighbour on level L and takes the first it meets as its
+// parent (no atomics: a vertex writes only its own entries; the level L + 1
+// it writes is never mistaken for L).
+__global__ __launch_bounds__(BLOCK) void k_st_bottom_up(int32_t n, const int64_t *row_ptr, const int32_t *col,
+                                                        int32_t *level, int32_t *parent, int L, int32_t *next,
+                                                        unsigned long long *ncnt, unsigned long long *nstat) {
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    unsigned long long dsum = 0, dmax = 0;
+    for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < n; base += stride) {
+        const int64_t v = base + threadIdx.x;
+        bool claim = false;
+        if (v < n && level[v] < 0) {
+            const int64_t b = row_ptr[v + 1];
+            for (int64_t s = row_ptr[v]; s < b; s++) {
+                const int32_t u = col[s];
+                if (level[u] == L) {
+                    parent[v] = u;
+                    level[v] = L + 1;
+                    claim = true;
+                    break;
+                }
+            }
+        }
+        const int64_t pos = wave_append(claim, ncnt);
+        if (claim) next[pos] = (int32_t)v;
+        add_degree(claim, row_ptr, (int32_t)v, dsum, dmax);
+    }
+    block_degree(dsum, dmax, nstat);
 }
 
 }  // namespace
@@ -157,20 +248,30 @@ extern "C" int drsf_static_forest(int32_t n, const int64_t *row_ptr, const int32
         return DRSF_E_DEVICE;
     if (nnz < 0 || (nnz > 0 && !col)) return DRSF_E_ARG;
     int32_t *erow = nullptr, *level = nullptr, *front0 = nullptr, *front1 = nullptr, *flag = nullptr;
+    uint32_t *mark = nullptr;
+    void *stmp = nullptr;
     unsigned long long *cnt = nullptr, *h = nullptr;
     int rc = DRSF_OK;
     auto ok = [&](hipError_t e) {
         if (e != hipSuccess && rc == DRSF_OK) rc = (e == hipErrorOutOfMemory) ? DRSF_E_NOMEM : DRSF_E_DEVICE;
         return e == hipSuccess;
     };
-    if (ok(hipMalloc(&erow, sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1))) &&
+    if (ok(hipMalloc(&erow, sizeof(int32_t) * (size_t)(nnz + 1))) &&
+        ok(hipMalloc(&mark, sizeof(uint32_t) * (size_t)std::max<int64_t>(nnz, 1))) &&
+        ok(hipMalloc(&stmp, scan_tmp_bytes(nnz) + 64)) &&
         ok(hipMalloc(&level, sizeof(int32_t) * (size_t)n)) && ok(hipMalloc(&front0, sizeof(int32_t) * (size_t)n)) &&
         ok(hipMalloc(&front1, sizeof(int32_t) * (size_t)n)) && ok(hipMalloc(&flag, sizeof(int32_t))) &&
-        ok(hipMalloc(&cnt, 3 * sizeof(unsigned long long))) &&
+        ok(hipMalloc(&cnt, 9 * sizeof(unsigned long long))) &&
         ok(hipHostMalloc((void **)&h, 4 * sizeof(unsigned long long)))) {
         int32_t *comp = label_out;
-        const int gv = grid_for(n, BLOCK), ge = grid_for(nnz, BLOCK), gw = grid_for((int64_t)n * WAVE, BLOCK);
-        hipLaunchKernelGGL(k_st_rows, dim3(gw), dim3(BLOCK), 0, s, n, row_ptr, erow);
+        const int gv = grid_for(n, BLOCK), ge = grid_for(nnz, BLOCK);
+        if (nnz > 0) {  // row of every slot (the exclusive sums land in erow itself)
+            launch_fill_i32(reinterpret_cast<int32_t *>(mark), nnz, 0, s);
+            hipLaunchKernelGGL(k_st_marks, dim3(gv), dim3(BLOCK), 0, s, n, row_ptr, nnz, mark);
+            launch_scan_u32(mark, reinterpret_cast<uint32_t *>(erow), cnt, nnz, stmp, s);
+            hipLaunchKernelGGL(k_st_rows, dim3(ge), dim3(BLOCK), 0, s, nnz, mark,
+                               reinterpret_cast<const uint32_t *>(erow), erow);
+        }
         hipLaunchKernelGGL(k_st_iota, dim3(gv), dim3(BLOCK), 0, s, n, comp);
         // hooking rounds until nothing hooks (each round at least halves the
         // roots that still have an edge to another root)
@@ -185,26 +286,37 @@ extern "C" int drsf_static_forest(int32_t n, const int64_t *row_ptr, const int32
             if (round == 63) rc = DRSF_E_DEVICE;
         }
         // breadth-first forest from the roots; cnt[L % 3] holds level L's
-        // frontier size, cnt[(L + 1) % 3] collects the next
-        launch_fill_u64(reinterpret_cast<uint64_t *>(cnt), 3, 0, s);
-        hipLaunchKernelGGL(k_st_bfs_init, dim3(gv), dim3(BLOCK), 0, s, n, comp, level, parent_out, front0,
-                           cnt);
+        // frontier size, cnt[(L + 1) % 3] collects the next, and st[3 x] the
+        // matching row-length sum and maximum
+        unsigned long long *st = cnt + 3;
+        launch_fill_u64(reinterpret_cast<uint64_t *>(cnt), 9, 0, s);
+        hipLaunchKernelGGL(k_st_bfs_init, dim3(gv), dim3(BLOCK), 0, s, n, row_ptr, comp, level, parent_out,
+                           front0, cnt, st);
         int32_t *fa = front0, *fb = front1;
         int L = 0;
         for (; rc == DRSF_OK; L++) {
             unsigned long long *fc = cnt + L % 3, *nc = cnt + (L + 1) % 3;
+            unsigned long long *fs = st + 2 * (L % 3), *ns = st + 2 * ((L + 1) % 3);
             if (!ok(hipMemcpyAsync(h, fc, sizeof(unsigned long long), hipMemcpyDeviceToHost, s)) ||
+                !ok(hipMemcpyAsync(h + 1, fs, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s)) ||
                 !ok(hipStreamSynchronize(s)))
                 break;
             const int64_t nf = (int64_t)h[0];
             if (nf == 0) break;
             launch_fill_u64(reinterpret_cast<uint64_t *>(cnt + (L + 2) % 3), 1, 0, s);
-            if (nf * 4 < n) {  // small frontier: its own rows
+            launch_fill_u64(reinterpret_cast<uint64_t *>(st + 2 * ((L + 2) % 3)), 2, 0, s);
+            // a frontier with few edges: top-down from its own rows (one wave
+            // walks a row) unless a row is long, then one pass over all slots;
+            // a frontier with many edges: bottom-up
+            if ((int64_t)h[1] * 16 < nnz && h[2] <= 4096) {
                 hipLaunchKernelGGL(k_st_top_down, dim3(grid_for(nf * WAVE, BLOCK)), dim3(BLOCK), 0, s, row_ptr,
-                                   col, level, parent_out, L, fa, fc, fb, nc);
+                                   col, level, parent_out, L, fa, fc, fb, nc, ns);
+            } else if ((int64_t)h[1] * 16 < nnz) {
+                hipLaunchKernelGGL(k_st_edges, dim3(ge), dim3(BLOCK), 0, s, nnz, row_ptr, erow, col, level,
+                                   parent_out, L, fb, nc, ns);
             } else {
-                hipLaunchKernelGGL(k_st_edges, dim3(ge), dim3(BLOCK), 0, s, nnz, erow, col, level, parent_out, L,
-                                   fb, nc);
+                hipLaunchKernelGGL(k_st_bottom_up, dim3(gv), dim3(BLOCK), 0, s, n, row_ptr, col, level,
+                                   parent_out, L, fb, nc, ns);
             }
             std::swap(fa, fb);
             if (L > n) rc = DRSF_E_DEVICE;
@@ -214,6 +326,8 @@ extern "C" int drsf_static_forest(int32_t n, const int64_t *row_ptr, const int32
     }
     (void)hipStreamSynchronize(s);
     hipFree(erow);
+    hipFree(mark);
+    hipFree(stmp);
     hipFree(level);
     hipFree(front0);
     hipFree(front1);
