@@ -150,7 +150,7 @@ struct Dev {
 // slots per range of the orphan adjacency scan; a range's cross edges go to
 // the region of x0 with the range's index, so ranges must not outnumber the
 // base-store tiles: the orphan scan is used only when its slots are at most
-// eb / OR_MAX_FRAC (and OR_W * OR_MAX_FRAC <= TILE)
+// eb / OR_MAX_FRAC, and OR_W * OR_MAX_FRAC >= TILE
 constexpr int OR_W = 2048;
 constexpr int OR_MAX_FRAC = 2;
 constexpr int OR_K = OR_W / BLOCK;  // slots per thread per range
