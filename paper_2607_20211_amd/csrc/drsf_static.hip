@@ -50,6 +50,48 @@ __device__ __forceinline__ int64_t wave_append(bool take, unsigned long long *cn
     return (int64_t)base + __popcll(m & ((1ull << lane_id()) - 1ull));
 }
 
+// Frontier appends gathered per workgroup: claims go to an LDS buffer (one
+// LDS atomic per wave and call) and the workgroup reserves its whole run of
+// the next frontier with one global atomic at the end; claims beyond the
+// buffer fall back to a global append per wave.  Every atomic on the one
+// frontier counter costs a serialised round trip, so per-wave appends from
+// thousands of waves were most of a level's time.
+constexpr int APP_BUF = 4096;
+struct Appender {
+    int32_t buf[APP_BUF];
+    int n;
+    unsigned long long base;
+};
+__device__ __forceinline__ void app_begin(Appender &a) {
+    if (threadIdx.x == 0) a.n = 0;
+    __syncthreads();
+}
+// every lane of the wave calls it
+__device__ __forceinline__ void app_push(Appender &a, bool take, int32_t w, int32_t *next,
+                                         unsigned long long *ncnt) {
+    const uint64_t m = __ballot(take);
+    if (!m) return;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane_id() == leader) base = atomicAdd(&a.n, __popcll(m));
+    base = __shfl(base, leader);
+    const int pos = base + __popcll(m & ((1ull << lane_id()) - 1ull));
+    const bool spill = take && pos >= APP_BUF;
+    if (take && !spill) a.buf[pos] = w;
+    if (base + __popcll(m) > APP_BUF) {  // wave-uniform
+        const int64_t g = wave_append(spill, ncnt);
+        if (spill) next[g] = w;
+    }
+}
+// every thread of the workgroup calls it
+__device__ __forceinline__ void app_end(Appender &a, int32_t *next, unsigned long long *ncnt) {
+    __syncthreads();
+    const int k = a.n < APP_BUF ? a.n : APP_BUF;
+    if (threadIdx.x == 0 && k > 0) a.base = atomicAdd(ncnt, (unsigned long long)k);
+    __syncthreads();
+    for (int i = threadIdx.x; i < k; i += BLOCK) next[a.base + i] = a.buf[i];
+}
+
 // Row lengths of the vertices a workgroup claimed, into the next level's
 // degree sum and maximum (stat[0] sum, stat[1] max): each thread accumulates
 // over its whole grid-stride loop, then one atomic pair per workgroup (every
@@ -85,6 +127,24 @@ __device__ __forceinline__ void add_degree(bool take, const int64_t *row_ptr, in
     const unsigned long long dg = (unsigned long long)(row_ptr[w + 1] - row_ptr[w]);
     sum += dg;
     mx = dg > mx ? dg : mx;
+}
+
+// Level counters: three groups of four words, level L's in group L % 3
+// (frontier size, row-length sum, longest row), then the depth word (the
+// number of non-empty levels seen so far).  The kernel of level L reads group
+// L % 3, fills group (L + 1) % 3 and clears group (L + 2) % 3 for the level
+// after, so levels run back to back with no host step between them.
+constexpr int CNT_WORDS = 13;
+constexpr int CNT_DEPTH = 12;
+__device__ __forceinline__ unsigned long long *level_group(unsigned long long *g, int L) { return g + 4 * (L % 3); }
+__device__ __forceinline__ void level_begin(unsigned long long *g, int L, bool nonempty) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        unsigned long long *c = level_group(g, L + 2);
+        c[0] = 0;
+        c[1] = 0;
+        c[2] = 0;
+        if (nonempty) g[CNT_DEPTH] = (unsigned long long)(L + 1);
+    }
 }
 
 __device__ __forceinline__ int32_t st_root(const int32_t *comp, int32_t x) {
@@ -123,8 +183,11 @@ __global__ __launch_bounds__(BLOCK) void k_st_compress(int32_t n, int32_t *comp)
 // roots: level 0, their own parents, the first frontier
 __global__ __launch_bounds__(BLOCK) void k_st_bfs_init(int32_t n, const int64_t *row_ptr, const int32_t *comp,
                                                        int32_t *level, int32_t *parent, int32_t *front,
-                                                       unsigned long long *fcnt, unsigned long long *fstat) {
+                                                       unsigned long long *g) {
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    unsigned long long *fcnt = level_group(g, 0), *fstat = fcnt + 1;
+    __shared__ Appender app;
+    app_begin(app);
     unsigned long long dsum = 0, dmax = 0;
     for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < n; base += stride) {
         const int64_t v = base + threadIdx.x;
@@ -133,40 +196,77 @@ __global__ __launch_bounds__(BLOCK) void k_st_bfs_init(int32_t n, const int64_t 
             level[v] = root ? 0 : -1;
             parent[v] = root ? (int32_t)v : -1;
         }
-        const int64_t pos = wave_append(root, fcnt);
-        if (root) front[pos] = (int32_t)v;
+        app_push(app, root, (int32_t)v, front, fcnt);
         add_degree(root, row_ptr, (int32_t)v, dsum, dmax);
     }
+    app_end(app, front, fcnt);
     block_degree(dsum, dmax, fstat);
 }
 
-// Top-down level from a small frontier: one wave per frontier vertex claims
-// its unvisited neighbours (compare-and-swap on the level).
+// Top-down level from a small frontier: each unvisited neighbour is claimed
+// by a compare-and-swap on its level.  Rows of up to SHORT_ROW slots are
+// walked by four lanes each (sixteen frontier vertices per wave, the wave
+// looping to its longest such row); a longer row is walked by the whole wave.
+constexpr int SHORT_ROW = 32;
+__device__ __forceinline__ bool td_claim(const int32_t *col, int32_t *level, int32_t *parent, int L, int32_t v,
+                                         int64_t s, int32_t &w) {
+    w = col[s];
+    const bool claim = level[w] < 0 && atomicCAS(&level[w], -1, L + 1) == -1;
+    if (claim) parent[w] = v;
+    return claim;
+}
 __global__ __launch_bounds__(BLOCK) void k_st_top_down(const int64_t *row_ptr, const int32_t *col,
                                                        int32_t *level, int32_t *parent, int L,
-                                                       const int32_t *front, const unsigned long long *fcnt,
-                                                       int32_t *next, unsigned long long *ncnt,
-                                                       unsigned long long *nstat) {
-    const int64_t nf = (int64_t)*fcnt;
-    const int64_t nw = (int64_t)gridDim.x * (BLOCK / WAVE);
+                                                       const int32_t *front, int32_t *next, unsigned long long *g) {
+    const int64_t nf = (int64_t)*level_group(g, L);
+    unsigned long long *ncnt = level_group(g, L + 1), *nstat = ncnt + 1;
+    level_begin(g, L, nf > 0);
+    __shared__ Appender app;
+    app_begin(app);
+    const int sub = lane_id() & 3;
+    const int64_t step = (int64_t)gridDim.x * (BLOCK / WAVE) * (WAVE / 4);
     unsigned long long dsum = 0, dmax = 0;
-    for (int64_t f = (int64_t)blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE; f < nf; f += nw) {
-        const int32_t v = front[f];
-        const int64_t a = row_ptr[v], b = row_ptr[v + 1];
-        for (int64_t s0 = a; s0 < b; s0 += WAVE) {
-            const int64_t s = s0 + lane_id();
+    for (int64_t f0 = ((int64_t)blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE) * (WAVE / 4); f0 < nf;
+         f0 += step) {
+        const int64_t f = f0 + (lane_id() >> 2);
+        int32_t v = 0;
+        int64_t a = 0, b = 0;
+        if (f < nf) {
+            v = front[f];
+            a = row_ptr[v];
+            b = row_ptr[v + 1];
+        }
+        const bool big = b - a > SHORT_ROW;
+        int rounds = big ? 0 : (int)((b - a + 3) >> 2);
+        for (int o = WAVE / 2; o > 0; o >>= 1) {
+            const int y = __shfl_xor(rounds, o);
+            rounds = y > rounds ? y : rounds;
+        }
+        for (int r = 0; r < rounds; r++) {
+            const int64_t sl = a + 4 * r + sub;
             bool claim = false;
             int32_t w = 0;
-            if (s < b) {
-                w = col[s];
-                claim = level[w] < 0 && atomicCAS(&level[w], -1, L + 1) == -1;
-                if (claim) parent[w] = v;
-            }
-            const int64_t pos = wave_append(claim, ncnt);
-            if (claim) next[pos] = w;
+            if (!big && sl < b) claim = td_claim(col, level, parent, L, v, sl, w);
+            app_push(app, claim, w, next, ncnt);
             add_degree(claim, row_ptr, w, dsum, dmax);
         }
+        uint64_t bm = __ballot(big && sub == 0);
+        while (bm) {
+            const int l = __ffsll((unsigned long long)bm) - 1;
+            bm &= bm - 1;
+            const int32_t bv = __shfl(v, l);
+            const int64_t ba = __shfl(a, l), bb = __shfl(b, l);
+            for (int64_t s0 = ba; s0 < bb; s0 += WAVE) {
+                const int64_t sl = s0 + lane_id();
+                bool claim = false;
+                int32_t w = 0;
+                if (sl < bb) claim = td_claim(col, level, parent, L, bv, sl, w);
+                app_push(app, claim, w, next, ncnt);
+                add_degree(claim, row_ptr, w, dsum, dmax);
+            }
+        }
     }
+    app_end(app, next, ncnt);
     block_degree(dsum, dmax, nstat);
 }
 
@@ -174,9 +274,12 @@ __global__ __launch_bounds__(BLOCK) void k_st_top_down(const int64_t *row_ptr, c
 // slot (u, w) with u on level L claims w.
 __global__ __launch_bounds__(BLOCK) void k_st_edges(int64_t nnz, const int64_t *row_ptr, const int32_t *erow,
                                                     const int32_t *col, int32_t *level, int32_t *parent, int L,
-                                                    int32_t *next, unsigned long long *ncnt,
-                                                    unsigned long long *nstat) {
+                                                    int32_t *next, unsigned long long *g) {
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    unsigned long long *ncnt = level_group(g, L + 1), *nstat = ncnt + 1;
+    level_begin(g, L, true);
+    __shared__ Appender app;
+    app_begin(app);
     unsigned long long dsum = 0, dmax = 0;
     for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < nnz; base += stride) {
         const int64_t s = base + threadIdx.x;
@@ -190,10 +293,10 @@ __global__ __launch_bounds__(BLOCK) void k_st_edges(int64_t nnz, const int64_t *
                 if (claim) parent[w] = u;
             }
         }
-        const int64_t pos = wave_append(claim, ncnt);
-        if (claim) next[pos] = w;
+        app_push(app, claim, w, next, ncnt);
         add_degree(claim, row_ptr, w, dsum, dmax);
     }
+    app_end(app, next, ncnt);
     block_degree(dsum, dmax, nstat);
 }
 
@@ -203,8 +306,12 @@ __global__ __launch_bounds__(BLOCK) void k_st_edges(int64_t nnz, const int64_t *
 // it writes is never mistaken for L).
 __global__ __launch_bounds__(BLOCK) void k_st_bottom_up(int32_t n, const int64_t *row_ptr, const int32_t *col,
                                                         int32_t *level, int32_t *parent, int L, int32_t *next,
-                                                        unsigned long long *ncnt, unsigned long long *nstat) {
+                                                        unsigned long long *g) {
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    unsigned long long *ncnt = level_group(g, L + 1), *nstat = ncnt + 1;
+    level_begin(g, L, true);
+    __shared__ Appender app;
+    app_begin(app);
     unsigned long long dsum = 0, dmax = 0;
     for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < n; base += stride) {
         const int64_t v = base + threadIdx.x;
@@ -221,10 +328,10 @@ __global__ __launch_bounds__(BLOCK) void k_st_bottom_up(int32_t n, const int64_t
                 }
             }
         }
-        const int64_t pos = wave_append(claim, ncnt);
-        if (claim) next[pos] = (int32_t)v;
+        app_push(app, claim, (int32_t)v, next, ncnt);
         add_degree(claim, row_ptr, (int32_t)v, dsum, dmax);
     }
+    app_end(app, next, ncnt);
     block_degree(dsum, dmax, nstat);
 }
 
@@ -261,8 +368,8 @@ extern "C" int drsf_static_forest(int32_t n, const int64_t *row_ptr, const int32
         ok(hipMalloc(&stmp, scan_tmp_bytes(nnz) + 64)) &&
         ok(hipMalloc(&level, sizeof(int32_t) * (size_t)n)) && ok(hipMalloc(&front0, sizeof(int32_t) * (size_t)n)) &&
         ok(hipMalloc(&front1, sizeof(int32_t) * (size_t)n)) && ok(hipMalloc(&flag, sizeof(int32_t))) &&
-        ok(hipMalloc(&cnt, 9 * sizeof(unsigned long long))) &&
-        ok(hipHostMalloc((void **)&h, 4 * sizeof(unsigned long long)))) {
+        ok(hipMalloc(&cnt, CNT_WORDS * sizeof(unsigned long long))) &&
+        ok(hipHostMalloc((void **)&h, CNT_WORDS * sizeof(unsigned long long)))) {
         int32_t *comp = label_out;
         const int gv = grid_for(n, BLOCK), ge = grid_for(nnz, BLOCK);
         if (nnz > 0) {  // row of every slot (the exclusive sums land in erow itself)
@@ -285,43 +392,56 @@ extern "C" int drsf_static_forest(int32_t n, const int64_t *row_ptr, const int32
             if (*(int32_t *)h == 0) break;
             if (round == 63) rc = DRSF_E_DEVICE;
         }
-        // breadth-first forest from the roots; cnt[L % 3] holds level L's
-        // frontier size, cnt[(L + 1) % 3] collects the next, and st[3 x] the
-        // matching row-length sum and maximum
-        unsigned long long *st = cnt + 3;
-        launch_fill_u64(reinterpret_cast<uint64_t *>(cnt), 9, 0, s);
+        // breadth-first forest from the roots, a level at a time; the host
+        // reads level L's counters and picks the kernel.  While the frontier's
+        // rows are short and their sum is far below the switch point, up to
+        // BATCH_MAX top-down levels are queued at once (the batch length
+        // doubles while this keeps holding), so a deep graph with small
+        // frontiers pays one host read per batch instead of per level; a
+        // top-down level takes its frontier size from the device, so a batch
+        // that outgrows its estimate stays correct, only slower.
+        constexpr int BATCH_MAX = 64;
+        launch_fill_u64(reinterpret_cast<uint64_t *>(cnt), CNT_WORDS, 0, s);
         hipLaunchKernelGGL(k_st_bfs_init, dim3(gv), dim3(BLOCK), 0, s, n, row_ptr, comp, level, parent_out,
-                           front0, cnt, st);
-        int32_t *fa = front0, *fb = front1;
-        int L = 0;
-        for (; rc == DRSF_OK; L++) {
-            unsigned long long *fc = cnt + L % 3, *nc = cnt + (L + 1) % 3;
-            unsigned long long *fs = st + 2 * (L % 3), *ns = st + 2 * ((L + 1) % 3);
-            if (!ok(hipMemcpyAsync(h, fc, sizeof(unsigned long long), hipMemcpyDeviceToHost, s)) ||
-                !ok(hipMemcpyAsync(h + 1, fs, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s)) ||
+                           front0, cnt);
+        int32_t *fr[2] = {front0, front1};
+        int L = 0, batch = 1;
+        while (rc == DRSF_OK) {
+            if (!ok(hipMemcpyAsync(h, cnt, CNT_WORDS * sizeof(unsigned long long), hipMemcpyDeviceToHost, s)) ||
                 !ok(hipStreamSynchronize(s)))
                 break;
-            const int64_t nf = (int64_t)h[0];
+            const unsigned long long *hg = h + 4 * (L % 3);
+            const int64_t nf = (int64_t)hg[0], dsum = (int64_t)hg[1];
+            const uint64_t dmax = hg[2];
             if (nf == 0) break;
-            launch_fill_u64(reinterpret_cast<uint64_t *>(cnt + (L + 2) % 3), 1, 0, s);
-            launch_fill_u64(reinterpret_cast<uint64_t *>(st + 2 * ((L + 2) % 3)), 2, 0, s);
-            // a frontier with few edges: top-down from its own rows (one wave
-            // walks a row) unless a row is long, then one pass over all slots;
-            // a frontier with many edges: bottom-up
-            if ((int64_t)h[1] * 16 < nnz && h[2] <= 4096) {
-                hipLaunchKernelGGL(k_st_top_down, dim3(grid_for(nf * WAVE, BLOCK)), dim3(BLOCK), 0, s, row_ptr,
-                                   col, level, parent_out, L, fa, fc, fb, nc, ns);
-            } else if ((int64_t)h[1] * 16 < nnz) {
-                hipLaunchKernelGGL(k_st_edges, dim3(ge), dim3(BLOCK), 0, s, nnz, row_ptr, erow, col, level,
-                                   parent_out, L, fb, nc, ns);
-            } else {
-                hipLaunchKernelGGL(k_st_bottom_up, dim3(gv), dim3(BLOCK), 0, s, n, row_ptr, col, level,
-                                   parent_out, L, fb, nc, ns);
+            if (L > n) {  // more levels than vertices: the counters are wrong
+                rc = DRSF_E_DEVICE;
+                break;
             }
-            std::swap(fa, fb);
-            if (L > n) rc = DRSF_E_DEVICE;
+            if (dsum * 16 < nnz && dmax <= 4096) {
+                // a frontier with few edges and short rows: top-down from its
+                // own rows (four lanes per vertex; room for twice the frontier
+                // in a batch)
+                const int k = dsum * 256 < nnz ? batch : 1;
+                const int g = (int)std::min<int64_t>(GRID_CAP, grid_for(std::max<int64_t>(2 * nf, 64) * 4, BLOCK));
+                for (int i = 0; i < k; i++, L++)
+                    hipLaunchKernelGGL(k_st_top_down, dim3(g), dim3(BLOCK), 0, s, row_ptr, col, level, parent_out,
+                                       L, fr[L & 1], fr[(L + 1) & 1], cnt);
+                batch = k == batch ? std::min(2 * batch, BATCH_MAX) : 1;
+            } else {
+                // few edges but a long row: one pass over every slot; many
+                // edges: bottom-up
+                batch = 1;
+                if (dsum * 16 < nnz)
+                    hipLaunchKernelGGL(k_st_edges, dim3(ge), dim3(BLOCK), 0, s, nnz, row_ptr, erow, col, level,
+                                       parent_out, L, fr[(L + 1) & 1], cnt);
+                else
+                    hipLaunchKernelGGL(k_st_bottom_up, dim3(gv), dim3(BLOCK), 0, s, n, row_ptr, col, level,
+                                       parent_out, L, fr[(L + 1) & 1], cnt);
+                L++;
+            }
         }
-        if (levels_out) *levels_out = L;
+        if (levels_out) *levels_out = rc == DRSF_OK ? (int32_t)h[CNT_DEPTH] : 0;
         if (rc == DRSF_OK && !ok(hipStreamSynchronize(s))) rc = DRSF_E_DEVICE;
     }
     (void)hipStreamSynchronize(s);
