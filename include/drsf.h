@@ -85,10 +85,11 @@ typedef struct {
                                 orphans' adjacency when it is at most half the
                                 store, else the whole store; 1: always the whole
                                 store (Sec. II-A as written) */
-    int rounds_queued;       /* hooking rounds (Alg. 2, phase 1) placed in the
-                                captured update graph; an update needing more
-                                finishes them with host-driven launches;
-                                0 = 4 */
+    int rounds_queued;       /* full-grid hooking rounds (Alg. 2, phase 1)
+                                placed in the captured update graph; later
+                                rounds run in one workgroup while at most 4096
+                                cross edges are live, else host-driven
+                                launches finish them; 0 = 2 */
     int levels_queued;       /* super-forest search levels placed in the graph;
                                 0 = 4 (max 12) */
     int reverse_mode;        /* path reversal: 0 (default) one thread walks each
@@ -133,9 +134,13 @@ typedef struct {
     int64_t orphan_slots;     /* delete: adjacency entries of those vertices */
     int32_t scan_orphans;     /* delete: 1 if the key-edge scan covered only the
                                  orphans' adjacency, 0 if the whole store */
-    int32_t host_finished;    /* 1 if the update needed more hooking rounds or
-                                 search levels than queued and was finished by
-                                 host-driven launches */
+    int32_t host_finished;    /* 0 if the captured sequence finished the
+                                 update; else host-driven launches finished it:
+                                 bit 0 set when they ran more hooking rounds
+                                 (the live cross edges outgrew the
+                                 one-workgroup rounds), bit 1 when they ran
+                                 more super-forest search levels or the Euler
+                                 tour */
 } drsf_view;
 
 /*

@@ -30,7 +30,7 @@ namespace {
 
 thread_local std::string g_create_error;
 
-constexpr int BOR_FAST = 4;    // default hooking rounds queued in the captured sequence
+constexpr int BOR_FAST = 2;    // default full-grid hooking rounds queued before the one-workgroup tail
 constexpr int BFS_FAST = 4;    // default search levels queued in the captured sequence
 constexpr int BFS_MAX = 12;    // deeper super-trees use the Euler tour instead
 constexpr int BOR_CHUNK = 3;   // rounds per host check in the continuation
@@ -790,7 +790,9 @@ int continue_update(drsf_ctx *c) {
     if ((rc = read_flags(c->bfs_fast))) return rc;
     bool bad = *(int32_t *)f != 0, done = f[1] != 0, bfs_done = f[2] == 0;
     int r = c->round_base + c->bor_fast, lv = c->bfs_fast;
+    int how = 0;  // the bits of drsf_view.host_finished
     if (!bad && !done) {
+        how |= 1;
         while (!done && !bad && r < bor_bound) {
             const int r1 = std::min(r + BOR_CHUNK, bor_bound);
             launch_boruvka(d, r, r1, 4096, s);
@@ -812,6 +814,7 @@ int continue_update(drsf_ctx *c) {
         }
     }
     if (!bad) {
+        if (!bfs_done) how |= 2;
         while (!bfs_done && lv < BFS_MAX) {
             launch_sf_bfs(d, lv, lv + 4, s);
             lv += 4;
@@ -827,6 +830,7 @@ int continue_update(drsf_ctx *c) {
     }
     launch_cleanup(d, s);  // hands the results to the host, then resets
     HIPCHK(c, hipStreamSynchronize(s));
+    c->view.host_finished = how ? how : 1;
     return DRSF_OK;
 }
 

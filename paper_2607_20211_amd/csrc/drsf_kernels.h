@@ -159,6 +159,10 @@ constexpr int OR_K = OR_W / BLOCK;  // slots per thread per range
 constexpr int OR_PAD = OR_W / BLOCK;
 
 constexpr int MAX_ROUNDS = 64;
+// hooking rounds in one workgroup (k_bor_tail): its size, and the longest
+// live cross-edge list it takes on
+constexpr int TAIL_THREADS = 1024;
+constexpr int64_t TAIL_MAX = 4096;
 // extra counter slots: per-round activity flags
 constexpr int C_LR_ROUND = C_COUNT + MAX_ROUNDS;       // [MAX_ROUNDS]
 constexpr int C_BFS_ROUND = C_COUNT + 2 * MAX_ROUNDS;  // [MAX_ROUNDS]

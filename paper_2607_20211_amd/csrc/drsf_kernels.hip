@@ -1274,6 +1274,102 @@ __global__ __launch_bounds__(BLOCK) void k_bor_hook(Dev d, int r) {
     }
 }
 
+// The rounds from r0 on in one workgroup, once few cross edges are live: a
+// round costs three block barriers instead of two launches (each launch on
+// this part costs a few microseconds however little it does).  Each round
+// selects as k_bor_select does, then hooks from the edges: a component that
+// selected hooks from the live edge holding its key, by the same rule as
+// k_bor_hook (a list can hold an edge twice, so the hook is a
+// compare-and-swap from "none" and only its winner records the edge).  The
+// next round's best[] entries are cleared for the ends of this round's live
+// edges, which include every component a later round can reach.  A list
+// longer than TAIL_MAX leaves everything untouched (the full-grid rounds
+// then go on).  Within one workgroup a barrier makes earlier global writes
+// and atomics visible to every thread of it.
+__global__ __launch_bounds__(TAIL_THREADS) void k_bor_tail(Dev d, int r0) {
+    if (*d.status || d.cnt[C_DONE_BOR]) return;
+    int64_t cin = (int64_t)d.cnt[(r0 & 1) ? C_NX0 : C_NX1];
+    if (cin > TAIL_MAX) return;
+    __shared__ int s_nout;
+    const int64_t np = (int64_t)d.cnt[C_NP];
+    for (int r = r0;; r++) {
+        if (r >= MAX_ROUNDS) {
+            if (threadIdx.x == 0) atomicOr(d.status, ST_ROUND_BOUND);
+            return;
+        }
+        const Cross *in = (r & 1) ? d.x0 : d.x1;
+        Cross *out = (r & 1) ? d.x1 : d.x0;
+        uint64_t *best = best_of(d, r), *nbest = best_of(d, r + 1);
+        if (threadIdx.x == 0) s_nout = 0;
+        __syncthreads();
+        for (int64_t base = 0; base < cin; base += TAIL_THREADS) {
+            const int64_t i = base + threadIdx.x;
+            bool live = false;
+            Cross e;
+            e.key = 0;
+            e.pa = e.pb = 0;
+            int32_t ca = 0, cb = 0;
+            if (i < cin) {
+                e = in[i];
+                ca = comp_root(d, e.pa, (uint32_t)r, np);
+                cb = comp_root(d, e.pb, (uint32_t)r, np);
+                live = ca != cb;
+            }
+            select_edge(d, live, e, ca, cb, best);
+            const uint64_t m = __ballot(live);
+            if (m) {
+                const int leader = __ffsll((unsigned long long)m) - 1;
+                int wb = 0;
+                if (lane_id() == leader) wb = atomicAdd(&s_nout, __popcll(m));
+                wb = __shfl(wb, leader);
+                if (live) {
+                    e.pa = ca;
+                    e.pb = cb;
+                    out[wb + lanes_below(m)] = e;
+                }
+            }
+        }
+        __syncthreads();
+        const int64_t nout = s_nout;
+        if (nout == 0) {
+            if (threadIdx.x == 0) d.cnt[C_DONE_BOR] = 1;
+            return;
+        }
+        for (int64_t base = 0; base < nout; base += TAIL_THREADS) {
+            const int64_t i = base + threadIdx.x;
+            bool rec[2] = {false, false};
+            int4 er[2] = {make_int4(0, 0, 0, 0), make_int4(0, 0, 0, 0)};
+            if (i < nout) {
+                const Cross e = out[i];
+                nbest[e.pa] = KEY_INF;
+                nbest[e.pb] = KEY_INF;
+                for (int side = 0; side < 2; side++) {
+                    const int32_t p = side ? e.pb : e.pa, other = side ? e.pa : e.pb;
+                    if (best[p] != e.key) continue;
+                    const int32_t x = key_lo(e.key), y = key_hi(e.key);
+                    const int32_t px = d.tidx[d.rep[x]], py = d.tidx[d.rep[y]];
+                    if (px < 0 || py < 0) {
+                        atomicOr(d.status, ST_WALK_BOUND);
+                        continue;
+                    }
+                    if (best[other] == e.key && p < other) continue;  // both chose it: the smaller stays
+                    if (atomicCAS((unsigned long long *)&d.hook[p], (unsigned long long)HOOK_NONE,
+                                  (unsigned long long)hook_pack(r, other)) == HOOK_NONE) {
+                        rec[side] = true;
+                        er[side] = make_int4(x, y, px, py);
+                    }
+                }
+            }
+            for (int side = 0; side < 2; side++) {
+                const int64_t slot = wave_append(rec[side], &d.cnt[C_NER]);
+                if (rec[side]) d.er[slot] = er[side];
+            }
+        }
+        __syncthreads();
+        cin = nout;
+    }
+}
+
 // ------------------------------------------- a7: super-forest rooting
 
 // Super-root of each merged component: the piece holding its smallest
@@ -1956,6 +2052,8 @@ void launch_boruvka(const Dev &d, int r0, int r1, int64_t units, hipStream_t s) 
             hipLaunchKernelGGL(k_bor_select, dim3(r == 1 ? ge : gp), dim3(BLOCK), 0, s, d, r);
         hipLaunchKernelGGL(k_bor_hook, dim3(gp), dim3(BLOCK), 0, s, d, r);
     }
+    // the tail reads a dense list, which rounds from 2 on have
+    if (r1 >= 2 && r1 > r0) hipLaunchKernelGGL(k_bor_tail, dim3(1), dim3(TAIL_THREADS), 0, s, d, r1);
 }
 void launch_sf_root(const Dev &d, hipStream_t s) {
     const int gp = grid_for(d.pcap, BLOCK, SMALL_CAP);

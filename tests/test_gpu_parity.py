@@ -521,6 +521,7 @@ def test_long_hooking_and_deep_search_continue_on_host():
     ins = gen.insert_batches(n, g.keys, 1, 200_000, gen.seed(4, 1, gen.P_INSERT))[0]
     st, ost = pair.step(ins, drsf.DRSF_INSERT, "continuation insert")
     assert ost["n_repl"] > n // 2
+    assert (st["host_finished"] & 1) != 0, st  # too many live edges for the one-workgroup rounds
     dl = gen.delete_batches(n, pair.keys, pair.parent, 1, 100_000, 50_000, gen.seed(4, 1, gen.P_DELETE))[0]
     pair.step(dl, drsf.DRSF_DELETE, "continuation delete")
     pair.gpu.close()
@@ -568,6 +569,75 @@ def test_launch_schedule_does_not_change_results(tuning):
         dl = gen.delete_batches(n, pair.keys, pair.parent, 1, 8000, min(4000, trees),
                                 gen.seed(6, step, gen.P_DELETE))[0]
         pair.step(dl, drsf.DRSF_DELETE, f"tuning {tuning} delete {step}")
+    pair.gpu.close()
+
+
+def _hooking_rounds(k, rank):
+    """Rounds of lowest-edge hooking on a path of k + 1 pieces whose edge j
+    (between pieces j and j + 1) has weight rank[j]: each round every
+    component takes its lightest edge to another component, and the chosen
+    edges merge components.  Returns the live edge count at the start of
+    every round (a plain model of Boruvka's algorithm, for the test's
+    premise only)."""
+    comp = list(range(k + 1))
+
+    def find(x):
+        while comp[x] != x:
+            comp[x] = comp[comp[x]]
+            x = comp[x]
+        return x
+
+    live_counts = []
+    while True:
+        live = [j for j in range(k) if find(j) != find(j + 1)]
+        live_counts.append(len(live))
+        if not live:
+            return live_counts
+        best = {}
+        for j in live:
+            for c in (find(j), find(j + 1)):
+                if c not in best or rank[j] < rank[best[c]]:
+                    best[c] = j
+        for j in set(best.values()):
+            a, b = find(j), find(j + 1)
+            if a != b:
+                comp[max(a, b)] = min(a, b)
+
+
+def test_hooking_tail_finishes_rounds_in_the_graph():
+    """A chain of k + 1 two-vertex pieces joined by k inserted edges whose
+    keys follow the ruler sequence (edge j weighs the trailing zeros of
+    j + 1): hooking needs about log2 k rounds.  With two full-grid rounds
+    queued, the rest run in the one-workgroup tail inside the captured
+    sequence (host_finished bit 0 clear); the super-tree is a path, far
+    deeper than the queued search levels, so the host finishes the search
+    (bit 1).  Bit-exact against the oracle."""
+    drsf = _lib()
+    _case("hooking tail")
+    k = 2048
+    weight = [((j + 1) & -(j + 1)).bit_length() for j in range(k)]
+    order = sorted(range(k), key=lambda j: (weight[j], j))
+    rank = [0] * k
+    for r, j in enumerate(order):
+        rank[j] = r
+    live = _hooking_rounds(k, rank)
+    assert len(live) - 1 >= 6 and live[1] <= 4096  # the premise: many rounds, short lists
+    # piece j = {u_j, v_j}: u_j has id rank[j] (edge j's low end), v_j id k + j
+    u = np.array(rank + [k + k + 1], np.int64)  # the last piece's u is spare
+    v = np.arange(k, 2 * k + 1, dtype=np.int64)
+    n = 2 * k + 2
+    base = np.sort((np.minimum(u, v).astype(np.uint64) << np.uint64(32)) | np.maximum(u, v).astype(np.uint64))
+    g = gen.make_graph("chain pieces", n, base)
+    pair = Pair(g, max_batch=4096)
+    pair.gpu.set_tuning(2, 4, 0)
+    ins = np.stack([u[:k], v[1:k + 1]], axis=1).astype(np.int32)
+    st, ost = pair.step(ins, drsf.DRSF_INSERT, "tail insert")
+    assert ost["n_repl"] == k
+    assert (st["host_finished"] & 1) == 0, st
+    assert (st["host_finished"] & 2) != 0, st
+    # and deletes of every third piece's own edge, through the same schedule
+    dl = np.stack([u[0:k:3], v[0:k:3]], axis=1).astype(np.int32)
+    pair.step(dl, drsf.DRSF_DELETE, "tail delete")
     pair.gpu.close()
 
 
