@@ -570,9 +570,11 @@ def main():
         "k_rep_chase": (pd["root_finding"] - ev_del, 12 * g.n + g.n // 8,
                         "root finding: read rep and label, write rep (4 B each per vertex), "
                         "orphan bitmap (1 bit per vertex)"),
-        "k_orph_scan": (pd["orphan_scan"] - ev_del, int(8 * sd["orphan_slots"] + 40 * sd["num_orphans"]),
-                        "orphan scan: column and the neighbour's rep per adjacency slot "
-                        "(4 + 4 B), one 40-B list entry per orphan"),
+        "k_orph_scan": (pd["orphan_scan"] - ev_del,
+                        int(4 * sd["orphan_slots"] + g.n // 8 + 40 * sd["num_orphans"]),
+                        "orphan scan: 4-B column per adjacency slot, the orphan bitmap "
+                        "(1 bit per vertex) once, one 40-B list entry per orphan (the rep of "
+                        "orphan neighbours, read only for them, is not counted)"),
     }
     if sd["scan_orphans"] < 0.5:
         kernels["k_sweep_base"] = (pd["store_sweep"] - ev_del, 4 * eb + 4 * (g.n + 1),

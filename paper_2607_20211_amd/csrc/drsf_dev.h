@@ -72,7 +72,7 @@ struct OrphEnt {
     int32_t v, du, dl;
     int32_t pu;     // dense id of the vertex's piece
     int32_t ru;     // root of that piece (rep of the vertex)
-    int32_t pad;
+    int32_t pk;     // dense id of the piece holding the vertex's old root
 };
 
 __device__ __forceinline__ uint64_t mkkey(uint32_t a, uint32_t b) {

@@ -554,7 +554,7 @@ __global__ __launch_bounds__(BLOCK) void k_rep_chase(Dev d) {
             }
         }
         bool orphan[REP_CH];
-        int32_t t[REP_CH];
+        int32_t t[REP_CH], tk[REP_CH];
         uint32_t us[REP_CH], ls[REP_CH];
         int32_t du[REP_CH], dl[REP_CH];
 #pragma unroll
@@ -563,11 +563,12 @@ __global__ __launch_bounds__(BLOCK) void k_rep_chase(Dev d) {
             if (live[k]) d.rep[v[k]] = x[k];
             const uint64_t word = __ballot(orphan[k]);
             if (lane_id() == 0 && live[k]) d.obits[v[k] >> 6] = word;
-            t[k] = NONE;
+            t[k] = tk[k] = NONE;
             us[k] = ls[k] = 0;
             du[k] = dl[k] = 0;
             if (orphan[k]) {
                 t[k] = d.tidx[x[k]];
+                tk[k] = d.tidx[lab[k]];  // the old root: a piece of its own
                 us[k] = d.bptr[v[k]];
                 ls[k] = d.lptr[v[k]];
                 du[k] = (int32_t)d.bptr[v[k] + 1];
@@ -578,7 +579,7 @@ __global__ __launch_bounds__(BLOCK) void k_rep_chase(Dev d) {
         for (int k = 0; k < REP_CH; k++) {
             if (blk[k] < 0) continue;  // uniform over the block
             if (orphan[k]) {
-                if (t[k] < 0) atomicOr(d.status, ST_WALK_BOUND);
+                if (t[k] < 0 || tk[k] < 0) atomicOr(d.status, ST_WALK_BOUND);
                 du[k] -= (int32_t)us[k];
                 dl[k] -= (int32_t)ls[k];
             }
@@ -597,7 +598,7 @@ __global__ __launch_bounds__(BLOCK) void k_rep_chase(Dev d) {
                 o.dl = dl[k];
                 o.pu = t[k];
                 o.ru = x[k];
-                o.pad = 0;
+                o.pk = tk[k];
                 d.ostage[blk[k] * BLOCK + (int64_t)ocnt(off)] = o;
             }
             if (threadIdx.x == 0) {
@@ -1003,21 +1004,29 @@ __global__ __launch_bounds__(BLOCK) void k_orph_scan(Dev d) {
                 col[k] = *src;
                 if (!real) col[k] = TOMB;
             }
+            // A neighbour that is no orphan kept its old root, which is not
+            // the orphan's piece root: the edge is a cross edge to the old
+            // root's piece, known per orphan.  Only orphan neighbours need
+            // their rep and piece gathered (the orphan bitmap, one bit per
+            // vertex, mostly stays in L2; rep and the piece table do not).
+            uint64_t vw[OR_K];
+#pragma unroll
+            for (int k = 0; k < OR_K; k++) vw[k] = d.obits[(col[k] & COLMASK) >> 6];
+            uint32_t onb = 0;
+#pragma unroll
+            for (int k = 0; k < OR_K; k++)
+                if (col[k] >= 0 && ((vw[k] >> (col[k] & 63)) & 1)) onb |= 1u << k;
             int32_t rv[OR_K];
 #pragma unroll
-            for (int k = 0; k < OR_K; k++) rv[k] = d.rep[col[k] & COLMASK];
+            for (int k = 0; k < OR_K; k++) rv[k] = (onb >> k & 1) ? d.rep[col[k]] : 0;
             uint32_t cross = 0;
 #pragma unroll
             for (int k = 0; k < OR_K; k++)
-                if (col[k] >= 0 && rv[k] != s_o[oi[k]].ru) cross |= 1u << k;
+                if (col[k] >= 0 && (!(onb >> k & 1) || rv[k] != s_o[oi[k]].ru)) cross |= 1u << k;
             int32_t pv[OR_K];
-            uint64_t vw[OR_K];
 #pragma unroll
-            for (int k = 0; k < OR_K; k++) {
-                const bool x = cross >> k & 1;
-                pv[k] = d.tidx[x ? rv[k] : 0];
-                vw[k] = d.obits[x ? (col[k] >> 6) : 0];
-            }
+            for (int k = 0; k < OR_K; k++)
+                pv[k] = ((cross & onb) >> k & 1) ? d.tidx[rv[k]] : s_o[oi[k]].pk;
             // count, and the runs of equal piece pairs
             int runs = 0;
             {
@@ -1027,7 +1036,7 @@ __global__ __launch_bounds__(BLOCK) void k_orph_scan(Dev d) {
                     if (!(cross >> k & 1)) continue;
                     const OrphEnt &o = s_o[oi[k]];
                     if (pv[k] < 0 || o.pu < 0) atomicOr(d.status, ST_WALK_BOUND);
-                    if (!((vw[k] >> (col[k] & 63)) & 1) || o.v < col[k]) ncross++;
+                    if (!(onb >> k & 1) || o.v < col[k]) ncross++;
                     const uint64_t pair = ((uint64_t)(uint32_t)o.pu << 32) | (uint32_t)pv[k];
                     if (pair != cur) { runs++; cur = pair; }
                 }
