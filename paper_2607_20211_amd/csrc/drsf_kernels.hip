@@ -495,13 +495,6 @@ __global__ __launch_bounds__(BLOCK) void k_insert_emit(Dev d) {
 
 // ----------------------------------------------- a4: root finding (delete)
 
-
-// rep[v] <- root of v in F-hat.  Each thread chases rep[] upward; entries
-// already finished by other threads are roots, so chains shorten as the
-// sweep proceeds (pointer jumping, Algorithm 1).  Every value read is an
-// ancestor of the vertex, so stale reads only cost extra steps.  Also marks
-// vertices whose root is not their old root (they lie in a piece cut off by
-// the batch) in a bitmap, and the smallest vertex of each such piece.
 // rep[v] <- root of v in F-hat.  Each thread chases rep[] upward; entries
 // already finished by other threads are roots, so chains shorten as the
 // sweep proceeds (pointer jumping, Algorithm 1).  Every value read is an
@@ -511,8 +504,10 @@ __global__ __launch_bounds__(BLOCK) void k_insert_emit(Dev d) {
 // the whole grid is resident, so more chains per thread add no overlap).
 // Marks vertices whose root is not their old root (they lie in a
 // piece cut off by the batch), stages each block's such orphans, compacted
-// at the block's start, with their adjacency runs for the orphan scan, and
-// lowers each orphan piece's smallest vertex.
+// at the block's start, with their adjacency runs, their piece and their
+// old root's piece for the orphan scan, and lowers each orphan piece's
+// smallest vertex.  (Loading the next block's rep and label before the
+// chase of the current one measured slower.)
 #ifndef DRSF_REP_CH
 #define DRSF_REP_CH 1
 #endif
