@@ -107,7 +107,8 @@ struct drsf_ctx {
     // orphan scan
     int64_t nvb = 0;
     int64_t *bvol = nullptr, *bpre = nullptr;
-    unsigned long long *gsum = nullptr, *gpre = nullptr;
+    unsigned long long *gsum = nullptr;
+    int64_t *gpre = nullptr, *gopre = nullptr;
     int32_t *bcnt = nullptr, *opre = nullptr, *rstart = nullptr;
     OrphEnt *olist = nullptr, *ostage = nullptr;
     unsigned long long *xcnt = nullptr;
@@ -251,7 +252,7 @@ Dev make_dev(drsf_ctx *c) {
     d.lptr = c->lptr; d.lcol = c->lcol; d.twin = c->twin; d.ltwin = c->ltwin;
     d.nvb = c->nvb; d.bvol = c->bvol; d.bcnt = c->bcnt; d.bpre = c->bpre; d.opre = c->opre;
     d.olist = c->olist; d.rstart = c->rstart; d.xcnt = c->xcnt;
-    d.gsum = c->gsum; d.gpre = c->gpre; d.ostage = c->ostage;
+    d.gsum = c->gsum; d.gpre = c->gpre; d.gopre = c->gopre; d.ostage = c->ostage;
     d.zrow = c->zrow; d.zptr = c->zptr; d.nz = c->nz; d.tile_k = c->tile_k; d.ntiles = c->ntiles;
     d.dtmax = c->dtmax;
     d.dkey = c->dkey; d.dcap = c->dcap; d.dhash = c->dhash; d.dhpos = c->dhpos; d.dhmask = c->dhmask;
@@ -307,7 +308,7 @@ int alloc_tiles(drsf_ctx *c) {
     if ((rc = dalloc(c, &c->x0, c->xcap))) return rc;
     if ((rc = dalloc(c, &c->x1, c->xcap))) return rc;
     if ((rc = dalloc(c, &c->rcnt, nregmax))) return rc;
-    if ((rc = dalloc(c, &c->rstart, c->ntiles + 1))) return rc;
+    if ((rc = dalloc(c, &c->rstart, 2 * c->ntiles + 1))) return rc;
     if ((rc = dalloc(c, &c->xcnt, c->ntiles + 1))) return rc;
     launch_fill_u64(c->rcnt, nregmax, 0, c->stream);
     if (c->opts.replacement_mode == 1) {  // supergraph scratch, sized by the cross-edge slots
@@ -414,6 +415,7 @@ int alloc_state(drsf_ctx *c) {
     if ((rc = dalloc(c, &c->opre, c->nvb))) return rc;
     if ((rc = dalloc(c, &c->gsum, (c->nvb + BLOCK - 1) / BLOCK))) return rc;
     if ((rc = dalloc(c, &c->gpre, (c->nvb + BLOCK - 1) / BLOCK))) return rc;
+    if ((rc = dalloc(c, &c->gopre, (c->nvb + BLOCK - 1) / BLOCK))) return rc;
     if ((rc = dalloc(c, &c->olist, n))) return rc;
     if ((rc = dalloc(c, &c->ostage, c->nvb * BLOCK))) return rc;
     launch_fill_u64(reinterpret_cast<uint64_t *>(c->bvol), c->nvb, 0, s);
@@ -674,7 +676,7 @@ int sg_reduce(drsf_ctx *c, const Dev &d, hipStream_t s) {
     HIPCHK(c, hipStreamSynchronize(s));
     if (*(int32_t *)f != 0) return DRSF_OK;  // failed already: the rounds skip themselves
     const bool om = f[1] != 0;
-    const int64_t nr_om = om ? ((int64_t)f[2] + OR_W - 1) / OR_W : 0;
+    const int64_t nr_om = om ? or_regions((int64_t)f[2], c->eb) : 0;
     const Ctl &k = *c->h_ctl;
     const int64_t rlo2 = om ? std::max<int64_t>(k.rlo, c->ntiles) : k.rlo;
     const int64_t nreg = nr_om + std::max<int64_t>(k.rhi - rlo2, 0);
@@ -1085,7 +1087,8 @@ int64_t drsf_footprint(int32_t n, int64_t nnz, const drsf_opts *opts) {
     b += 49 * pcap + 40 * pcap + 16 * pcap + 16 * std::max(2 * pcap, N);  // pieces, tour, er, paths
     b += 37 * mb + 8 * bh + 8 * dcap + 12 * dh;                           // batch, tables, inserted list
     b += 32 * xcap + 8 * (xcap / TILE);                                   // cross lists
-    b += 24 * nvb + 40 * N + 40 * nvb * BLOCK + 16 * (ntiles + 1);       // orphan scan
+    b += 24 * nvb + 40 * N + 40 * nvb * BLOCK + 8 * (ntiles + 1) + 4 * (2 * ntiles + 1) +
+         24 * ((nvb + BLOCK - 1) / BLOCK);                                // orphan scan
     return b + (1 << 20);
 }
 

@@ -70,10 +70,11 @@ struct Dev {
     int64_t *bpre;           // [nvb] slots before the block within its group of BLOCK blocks
     int32_t *opre;           // [nvb] orphans before the block within its group
     unsigned long long *gsum;  // [ngroups] packed (slots, orphans) per group
-    unsigned long long *gpre;  // [ngroups] packed prefix over the groups
+    int64_t *gpre;             // [ngroups] slots before the group
+    int64_t *gopre;            // [ngroups] orphans before the group
     OrphEnt *olist;          // [n] every orphan, vertex order
     OrphEnt *ostage;         // [nvb * BLOCK] each block's orphans, compacted at the block's start
-    int32_t *rstart;         // [ntiles + 1]
+    int32_t *rstart;         // [2 ntiles + 1]
     unsigned long long *xcnt;  // [ntiles] cross edges found per range
     // forest.  Between updates rep[v] == label[v]; a delete recomputes rep as
     // the root of v in F-hat.
@@ -147,13 +148,23 @@ struct Dev {
     unsigned long long *cnt; // [C_TOTAL]
 };
 
-// slots per range of the orphan adjacency scan; a range's cross edges go to
-// the region of x0 with the range's index, so ranges must not outnumber the
-// base-store tiles: the orphan scan is used only when its slots are at most
-// eb / OR_MAX_FRAC, and OR_W * OR_MAX_FRAC >= TILE
+// slots per range of the orphan adjacency scan (one workgroup pass).  A
+// region of x0 (TILE entries, one per base-store tile) takes the cross edges
+// of one range, or of two consecutive ranges when the orphans hold more than
+// half as many slots as the base store; the scan is used while they hold at
+// most as many (so the regions never outnumber the tiles), and a range's
+// entries never outnumber its slots.
 constexpr int OR_W = 2048;
-constexpr int OR_MAX_FRAC = 2;
+static_assert(2 * OR_W == TILE, "two orphan ranges fill one x0 region");
 constexpr int OR_K = OR_W / BLOCK;  // slots per thread per range
+// slots per x0 region of the orphan scan, for V orphan slots and eb stored edges
+__host__ __device__ inline int64_t or_region_slots(int64_t V, int64_t eb) {
+    return 2 * V <= eb ? OR_W : 2 * OR_W;
+}
+__host__ __device__ inline int64_t or_regions(int64_t V, int64_t eb) {
+    const int64_t r = or_region_slots(V, eb);
+    return (V + r - 1) / r;
+}
 // every orphan also owns OR_PAD empty slots after its adjacency, so a range
 // meets at most about OR_W / OR_PAD orphans: one LDS window of BLOCK
 constexpr int OR_PAD = OR_W / BLOCK;

@@ -186,7 +186,9 @@ __device__ unsigned long long block_sum64(unsigned long long x) {
 }
 
 // (slots, orphans) packed into one word so that one sum or scan carries both:
-// slots below 2^44, orphans in the bits above
+// slots below 2^44, orphans in the 20 bits above.  Used only within a group
+// of BLOCK vertex blocks (at most 2^16 orphans); the prefixes over the
+// groups keep the two apart (the orphans of a whole graph can pass 2^20).
 __device__ __forceinline__ unsigned long long opack(unsigned long long vol, unsigned long long c) {
     return (c << 44) | vol;
 }
@@ -877,20 +879,25 @@ __global__ __launch_bounds__(BLOCK) void k_orph_total(Dev d) {
     const int64_t per = (ng + BLOCK - 1) / BLOCK;
     const int64_t g0 = (int64_t)threadIdx.x * per;
     const int64_t g1 = g0 + per < ng ? g0 + per : ng;
-    unsigned long long sum = 0;
-    for (int64_t g = g0; g < g1; g++) sum += d.gsum[g];
-    unsigned long long tot;
-    unsigned long long pre = block_excl_scan64(sum, &tot);
+    unsigned long long sv = 0, sc = 0;
     for (int64_t g = g0; g < g1; g++) {
-        const unsigned long long x = d.gsum[g];
-        d.gpre[g] = pre;
-        pre += x;
+        sv += ovol(d.gsum[g]);
+        sc += ocnt(d.gsum[g]);
+    }
+    unsigned long long tv, tc;
+    unsigned long long pv = block_excl_scan64(sv, &tv);
+    unsigned long long pc = block_excl_scan64(sc, &tc);
+    for (int64_t g = g0; g < g1; g++) {
+        d.gpre[g] = (int64_t)pv;
+        d.gopre[g] = (int64_t)pc;
+        pv += ovol(d.gsum[g]);
+        pc += ocnt(d.gsum[g]);
     }
     if (threadIdx.x == 0) {
-        const int64_t V = (int64_t)ovol(tot);
+        const int64_t V = (int64_t)tv;
         d.cnt[C_OVOL] = (unsigned long long)V;
-        d.cnt[C_NORPH] = ocnt(tot);
-        d.cnt[C_OMODE] = (d.ctl->smode != 1 && V * OR_MAX_FRAC <= d.eb) ? 1ull : 0ull;
+        d.cnt[C_NORPH] = tc;
+        d.cnt[C_OMODE] = (d.ctl->smode != 1 && V <= d.eb) ? 1ull : 0ull;
     }
 }
 
@@ -910,9 +917,8 @@ __global__ __launch_bounds__(BLOCK) void k_orph_fill(Dev d) {
         if (blk < 0) break;
         const int32_t nc = d.bcnt[blk];
         if (nc == 0) continue;
-        const unsigned long long gp = d.gpre[blk / BLOCK];
-        const int64_t ob = (int64_t)ocnt(gp) + d.opre[blk];
-        const int64_t vb = (int64_t)ovol(gp) + d.bpre[blk];
+        const int64_t ob = d.gopre[blk / BLOCK] + d.opre[blk];
+        const int64_t vb = d.gpre[blk / BLOCK] + d.bpre[blk];
         for (int32_t i = sub; i < nc; i += FILL_LANES) {
             OrphEnt o = d.ostage[blk * BLOCK + i];
             const int64_t idx = ob + i;
@@ -924,171 +930,217 @@ __global__ __launch_bounds__(BLOCK) void k_orph_fill(Dev d) {
     }
 }
 
-// One workgroup per range of OR_W consecutive slots.  The orphans covering
-// the range are staged in LDS; each thread takes OR_K consecutive slots
-// (one binary search, then a walk), loads their columns from the upper or
-// lower run and tests rep at both ends.  A cross edge (u, v) takes part in
-// the first hooking round's selection for u's piece (an orphan piece, which
-// never holds an old root), and within the thread's run of slots only the
-// lowest key per pair of pieces is kept for the later rounds: a parallel
-// edge with a higher key closes a cycle on which it is the largest, so the
-// lowest-key forest never contains it.  Edges between two orphan pieces are
-// seen from both ends; they are counted once (from the smaller end).
+// One workgroup per region of x0: one range of OR_W consecutive slots, or
+// two when the orphans hold more than half as many slots as the base store.
+// For each range, the orphans covering it are staged in LDS; each thread
+// takes OR_K consecutive slots (one binary search, then a walk), loads their
+// columns from the upper or lower run and tests the neighbour.  A neighbour
+// that is no orphan kept its old root, which is not the orphan's piece
+// root: the edge is a cross edge to the old root's piece (known per
+// orphan), so only orphan neighbours need their rep and piece gathered (the
+// orphan bitmap, one bit per vertex, mostly stays in L2; rep and the piece
+// table do not).  Parallel edges between two pieces close a cycle with the
+// lowest of them, on which they are the largest, so the lowest-key forest
+// holds none of them: the old-root edges of an orphan in a range are kept
+// as their lowest key alone, and the orphan-neighbour edges as the lowest
+// key of each run of equal piece pairs within a thread's slots.  Every cross
+// edge (u, v) also takes part in the first hooking round's selection for
+// u's piece (an orphan piece, which never holds an old root); edges between
+// two orphan pieces are seen from both ends and counted once (from the
+// smaller end).
 __global__ __launch_bounds__(BLOCK) void k_orph_scan(Dev d) {
     if (*d.status || !d.ctl->has_del || !d.cnt[C_OMODE]) return;
     const int64_t V = (int64_t)d.cnt[C_OVOL];
     const int64_t no = (int64_t)d.cnt[C_NORPH];
-    const int64_t nr = (V + OR_W - 1) / OR_W;
+    const int64_t per = or_region_slots(V, d.eb) / OR_W;  // ranges per region
+    const int64_t nreg = or_regions(V, d.eb);
     __shared__ OrphEnt s_o[BLOCK];
     __shared__ int64_t s_pre[BLOCK];
-    __shared__ unsigned long long s_min[BLOCK];  // lowest cross key per staged orphan
-    for (int64_t w = blockIdx.x; w < nr; w += gridDim.x) {
-        const int64_t S1 = (w + 1) * OR_W < V ? (w + 1) * OR_W : V;
-        int64_t pos = w * OR_W;
-        int64_t i0 = d.rstart[w];
+    __shared__ unsigned long long s_min[BLOCK];   // lowest cross key per staged orphan
+    __shared__ unsigned long long s_mink[BLOCK];  // lowest key to the old root's piece
+    for (int64_t w = blockIdx.x; w < nreg; w += gridDim.x) {
+        Cross *const region = d.x0 + w * TILE;
         int64_t emitted = 0;
         int ncross = 0;
-        while (pos < S1) {  // windows of BLOCK orphans; uniform over the block
-            __syncthreads();  // the LDS is free
-            const int64_t ii = i0 + threadIdx.x;
-            if (ii < no) {
-                s_o[threadIdx.x] = d.olist[ii];
-                s_pre[threadIdx.x] = s_o[threadIdx.x].pre;
-            }
-            s_min[threadIdx.x] = KEY_INF;
-            __syncthreads();
-            const int wn = no - i0 < BLOCK ? (int)(no - i0) : BLOCK;
-            int64_t we = S1;
-            if (wn > 0) {
-                const OrphEnt &last = s_o[wn - 1];
-                const int64_t e = last.pre + last.du + last.dl + OR_PAD;
-                we = e < S1 ? e : S1;
-            }
-            if (wn <= 0 || we <= pos || s_pre[0] > pos) {  // inconsistent plan
-                if (threadIdx.x == 0) atomicOr(d.status, ST_WALK_BOUND);
-                break;
-            }
-            // this thread's slots [s0, s0 + cnt)
-            const int64_t s0 = pos + (int64_t)threadIdx.x * OR_K;
-            const int cnt = s0 >= we ? 0 : (we - s0 < OR_K ? (int)(we - s0) : OR_K);
-            int a = 0;
-            if (cnt > 0) {
-                int b = wn - 1;
-                while (a < b) {
-                    const int mid = (a + b + 1) >> 1;
-                    if (s_pre[mid] <= s0) a = mid; else b = mid - 1;
+        for (int64_t rg = w * per; rg < (w + 1) * per && rg * OR_W < V; rg++) {  // uniform
+            const int64_t S1 = (rg + 1) * OR_W < V ? (rg + 1) * OR_W : V;
+            int64_t pos = rg * OR_W;
+            int64_t i0 = d.rstart[rg];
+            while (pos < S1) {  // windows of BLOCK orphans; uniform over the block
+                __syncthreads();  // the LDS is free
+                const int64_t ii = i0 + threadIdx.x;
+                if (ii < no) {
+                    s_o[threadIdx.x] = d.olist[ii];
+                    s_pre[threadIdx.x] = s_o[threadIdx.x].pre;
                 }
-            }
-            int64_t e = cnt > 0 ? s0 - s_pre[a] : 0;
-            int32_t col[OR_K], oi[OR_K];
-#pragma unroll
-            for (int k = 0; k < OR_K; k++) {
-                const int32_t *src = d.bcol;
-                bool real = false;
-                if (k < cnt) {
-                    while (e >= (int64_t)s_o[a].du + s_o[a].dl + OR_PAD && a < wn - 1) {
-                        e -= (int64_t)s_o[a].du + s_o[a].dl + OR_PAD;
-                        a++;
+                s_min[threadIdx.x] = KEY_INF;
+                s_mink[threadIdx.x] = KEY_INF;
+                __syncthreads();
+                const int wn = no - i0 < BLOCK ? (int)(no - i0) : BLOCK;
+                int64_t we = S1;
+                if (wn > 0) {
+                    const OrphEnt &last = s_o[wn - 1];
+                    const int64_t e = last.pre + last.du + last.dl + OR_PAD;
+                    we = e < S1 ? e : S1;
+                }
+                if (wn <= 0 || we <= pos || s_pre[0] > pos) {  // inconsistent plan
+                    if (threadIdx.x == 0) atomicOr(d.status, ST_WALK_BOUND);
+                    break;
+                }
+                // this thread's slots [s0, s0 + cnt)
+                const int64_t s0 = pos + (int64_t)threadIdx.x * OR_K;
+                const int cnt = s0 >= we ? 0 : (we - s0 < OR_K ? (int)(we - s0) : OR_K);
+                int a = 0;
+                if (cnt > 0) {
+                    int b = wn - 1;
+                    while (a < b) {
+                        const int mid = (a + b + 1) >> 1;
+                        if (s_pre[mid] <= s0) a = mid; else b = mid - 1;
                     }
-                    const OrphEnt &o = s_o[a];
-                    real = e < (int64_t)o.du + o.dl;  // else a padding slot
-                    if (real) src = e < o.du ? d.bcol + o.ustart + e : d.lcol + o.lstart + (e - o.du);
-                    e++;
                 }
-                oi[k] = a;
-                col[k] = *src;
-                if (!real) col[k] = TOMB;
-            }
-            // A neighbour that is no orphan kept its old root, which is not
-            // the orphan's piece root: the edge is a cross edge to the old
-            // root's piece, known per orphan.  Only orphan neighbours need
-            // their rep and piece gathered (the orphan bitmap, one bit per
-            // vertex, mostly stays in L2; rep and the piece table do not).
-            uint64_t vw[OR_K];
-#pragma unroll
-            for (int k = 0; k < OR_K; k++) vw[k] = d.obits[(col[k] & COLMASK) >> 6];
-            uint32_t onb = 0;
-#pragma unroll
-            for (int k = 0; k < OR_K; k++)
-                if (col[k] >= 0 && ((vw[k] >> (col[k] & 63)) & 1)) onb |= 1u << k;
-            int32_t rv[OR_K];
-#pragma unroll
-            for (int k = 0; k < OR_K; k++) rv[k] = (onb >> k & 1) ? d.rep[col[k]] : 0;
-            uint32_t cross = 0;
-#pragma unroll
-            for (int k = 0; k < OR_K; k++)
-                if (col[k] >= 0 && (!(onb >> k & 1) || rv[k] != s_o[oi[k]].ru)) cross |= 1u << k;
-            int32_t pv[OR_K];
-#pragma unroll
-            for (int k = 0; k < OR_K; k++)
-                pv[k] = ((cross & onb) >> k & 1) ? d.tidx[rv[k]] : s_o[oi[k]].pk;
-            // count, and the runs of equal piece pairs
-            int runs = 0;
-            {
-                uint64_t cur = ~0ull;
+                int64_t e = cnt > 0 ? s0 - s_pre[a] : 0;
+                int32_t col[OR_K], oi[OR_K];
 #pragma unroll
                 for (int k = 0; k < OR_K; k++) {
-                    if (!(cross >> k & 1)) continue;
-                    const OrphEnt &o = s_o[oi[k]];
-                    if (pv[k] < 0 || o.pu < 0) atomicOr(d.status, ST_WALK_BOUND);
-                    if (!(onb >> k & 1) || o.v < col[k]) ncross++;
-                    const uint64_t pair = ((uint64_t)(uint32_t)o.pu << 32) | (uint32_t)pv[k];
-                    if (pair != cur) { runs++; cur = pair; }
+                    const int32_t *src = d.bcol;
+                    bool real = false;
+                    if (k < cnt) {
+                        while (e >= (int64_t)s_o[a].du + s_o[a].dl + OR_PAD && a < wn - 1) {
+                            e -= (int64_t)s_o[a].du + s_o[a].dl + OR_PAD;
+                            a++;
+                        }
+                        const OrphEnt &o = s_o[a];
+                        real = e < (int64_t)o.du + o.dl;  // else a padding slot
+                        if (real) src = e < o.du ? d.bcol + o.ustart + e : d.lcol + o.lstart + (e - o.du);
+                        e++;
+                    }
+                    oi[k] = a;
+                    col[k] = *src;
+                    if (!real) col[k] = TOMB;
                 }
-            }
-            int rtot;
-            const int roff = block_excl_scan(runs, &rtot);
-            // lowest key of each run: output, and the run's orphan's minimum
-            // in LDS (several threads' runs of one orphan meet there; one
-            // global atomic per orphan and window follows)
-            {
-                Cross *out = d.x0 + w * TILE + emitted + roff;
-                int r = 0;
-                uint64_t cur = ~0ull, mk = 0;
-                int32_t cpu = 0, cpv = 0, ca = 0;
+                uint64_t vw[OR_K];
 #pragma unroll
-                for (int k = 0; k <= OR_K; k++) {
-                    bool flush = k == OR_K;
-                    uint64_t pair = 0, key = 0;
-                    if (!flush && (cross >> k & 1)) {
+                for (int k = 0; k < OR_K; k++) vw[k] = d.obits[(col[k] & COLMASK) >> 6];
+                uint32_t onb = 0;  // the neighbour is an orphan
+#pragma unroll
+                for (int k = 0; k < OR_K; k++)
+                    if (col[k] >= 0 && ((vw[k] >> (col[k] & 63)) & 1)) onb |= 1u << k;
+                int32_t rv[OR_K];
+#pragma unroll
+                for (int k = 0; k < OR_K; k++) rv[k] = (onb >> k & 1) ? d.rep[col[k]] : 0;
+                uint32_t cross = 0;
+#pragma unroll
+                for (int k = 0; k < OR_K; k++)
+                    if (col[k] >= 0 && (!(onb >> k & 1) || rv[k] != s_o[oi[k]].ru)) cross |= 1u << k;
+                const uint32_t xo = cross & onb, xk = cross & ~onb;  // to orphans / to old roots
+                int32_t pv[OR_K];
+#pragma unroll
+                for (int k = 0; k < OR_K; k++) pv[k] = (xo >> k & 1) ? d.tidx[rv[k]] : s_o[oi[k]].pk;
+                // count, and the runs of equal piece pairs among the edges to orphans
+                int runs = 0;
+                {
+                    uint64_t cur = ~0ull;
+#pragma unroll
+                    for (int k = 0; k < OR_K; k++) {
+                        if (!(cross >> k & 1)) continue;
                         const OrphEnt &o = s_o[oi[k]];
-                        pair = ((uint64_t)(uint32_t)o.pu << 32) | (uint32_t)pv[k];
-                        key = mkkey((uint32_t)o.v, (uint32_t)col[k]);
-                        if (pair == cur) {
+                        if (pv[k] < 0 || o.pu < 0) atomicOr(d.status, ST_WALK_BOUND);
+                        if (!(onb >> k & 1) || o.v < col[k]) ncross++;
+                        if (!(xo >> k & 1)) continue;
+                        const uint64_t pair = ((uint64_t)(uint32_t)o.pu << 32) | (uint32_t)pv[k];
+                        if (pair != cur) { runs++; cur = pair; }
+                    }
+                }
+                // edges to old roots: the lowest key per orphan (a thread's
+                // slots meet few orphans, one LDS minimum per orphan met)
+                {
+                    int32_t ca = -1;
+                    uint64_t mk = ~0ull;
+#pragma unroll
+                    for (int k = 0; k <= OR_K; k++) {
+                        const bool in = k < OR_K && (xk >> k & 1);
+                        if (in && oi[k] == ca) {
+                            const uint64_t key = mkkey((uint32_t)s_o[oi[k]].v, (uint32_t)col[k]);
                             mk = key < mk ? key : mk;
                             continue;
                         }
-                        flush = true;
-                    } else if (!flush) {
-                        continue;
-                    }
-                    if (cur != ~0ull) {
-                        Cross xo;
-                        xo.key = mk;
-                        xo.pa = cpu;
-                        xo.pb = cpv;
-                        out[r++] = xo;
-                        if (s_min[ca] > mk) atomicMin(&s_min[ca], (unsigned long long)mk);
-                    }
-                    if (k < OR_K) {
-                        cur = pair;
-                        mk = key;
-                        cpu = (int32_t)(pair >> 32);
-                        cpv = (int32_t)(uint32_t)pair;
-                        ca = oi[k];
+                        if (!in && k < OR_K) continue;
+                        if (ca >= 0 && s_mink[ca] > mk) atomicMin(&s_mink[ca], (unsigned long long)mk);
+                        if (k < OR_K) {
+                            ca = oi[k];
+                            mk = mkkey((uint32_t)s_o[oi[k]].v, (uint32_t)col[k]);
+                        }
                     }
                 }
+                int rtot;
+                const int roff = block_excl_scan(runs, &rtot);
+                // lowest key of each run: output, and the run's orphan's
+                // minimum in LDS (several threads' runs of one orphan meet
+                // there; one global atomic per orphan and window follows)
+                {
+                    Cross *out = region + emitted + roff;
+                    int r = 0;
+                    uint64_t cur = ~0ull, mk = 0;
+                    int32_t cpu = 0, cpv = 0, ca = 0;
+#pragma unroll
+                    for (int k = 0; k <= OR_K; k++) {
+                        bool flush = k == OR_K;
+                        uint64_t pair = 0, key = 0;
+                        if (!flush && (xo >> k & 1)) {
+                            const OrphEnt &o = s_o[oi[k]];
+                            pair = ((uint64_t)(uint32_t)o.pu << 32) | (uint32_t)pv[k];
+                            key = mkkey((uint32_t)o.v, (uint32_t)col[k]);
+                            if (pair == cur) {
+                                mk = key < mk ? key : mk;
+                                continue;
+                            }
+                            flush = true;
+                        } else if (!flush) {
+                            continue;
+                        }
+                        if (cur != ~0ull) {
+                            Cross x;
+                            x.key = mk;
+                            x.pa = cpu;
+                            x.pb = cpv;
+                            out[r++] = x;
+                            if (s_min[ca] > mk) atomicMin(&s_min[ca], (unsigned long long)mk);
+                        }
+                        if (k < OR_K) {
+                            cur = pair;
+                            mk = key;
+                            cpu = (int32_t)(pair >> 32);
+                            cpv = (int32_t)(uint32_t)pair;
+                            ca = oi[k];
+                        }
+                    }
+                }
+                __syncthreads();
+                // per staged orphan: its edge to the old root's piece, and its
+                // lowest cross key into the first round's selection
+                bool ek = false;
+                Cross xk1;
+                xk1.key = 0;
+                xk1.pa = xk1.pb = 0;
+                if (threadIdx.x < wn) {
+                    const unsigned long long mkk = s_mink[threadIdx.x];
+                    const unsigned long long mo = s_min[threadIdx.x];
+                    const unsigned long long m = mkk < mo ? mkk : mo;
+                    const OrphEnt &o = s_o[threadIdx.x];
+                    if (m != KEY_INF && o.pu >= 0 && d.best[o.pu] > m)
+                        atomicMin((unsigned long long *)&d.best[o.pu], m);
+                    ek = mkk != KEY_INF;
+                    xk1.key = mkk;
+                    xk1.pa = o.pu;
+                    xk1.pb = o.pk;
+                }
+                int ktot;
+                const int koff = block_excl_scan(ek ? 1 : 0, &ktot);
+                if (ek) region[emitted + rtot + koff] = xk1;
+                emitted += rtot + ktot;
+                pos = we;
+                i0 += wn;
             }
-            __syncthreads();
-            if (threadIdx.x < wn) {
-                const unsigned long long m = s_min[threadIdx.x];
-                const int32_t pu = s_o[threadIdx.x].pu;
-                if (m != KEY_INF && pu >= 0 && d.best[pu] > m)
-                    atomicMin((unsigned long long *)&d.best[pu], m);
-            }
-            emitted += rtot;
-            pos = we;
-            i0 += wn;
         }
         int ct;
         block_excl_scan(ncross, &ct);
@@ -1163,7 +1215,7 @@ __global__ __launch_bounds__(BLOCK) void k_bor_round0(Dev d) {
         unsigned long long s = 0;
         for (int64_t r = rlo + threadIdx.x; r < rhi; r += BLOCK) s += d.rcnt[r];
         if (om) {
-            const int64_t nr = ((int64_t)d.cnt[C_OVOL] + OR_W - 1) / OR_W;
+            const int64_t nr = or_regions((int64_t)d.cnt[C_OVOL], d.eb);
             for (int64_t r = threadIdx.x; r < nr; r += BLOCK) s += d.xcnt[r];
         }
         for (int o = WAVE / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
@@ -2036,8 +2088,7 @@ void launch_orphan_list(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_orph_fill, dim3(grid_for(d.nvb, BLOCK / 8, GRID_CAP)), dim3(BLOCK), 0, s, d);
 }
 void launch_orphan_scan(const Dev &d, hipStream_t s) {
-    hipLaunchKernelGGL(k_orph_scan, dim3(grid_for((d.ntiles * TILE) / OR_MAX_FRAC, OR_W, GRID_CAP)),
-                       dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_orph_scan, dim3(grid_for(d.ntiles, 1, GRID_CAP)), dim3(BLOCK), 0, s, d);
 }
 void launch_sweep_delta(const Dev &d, hipStream_t s) {
     if (d.dtmax > 0)

@@ -232,6 +232,91 @@ def test_rmat_small(sweep_mode):
     pair.gpu.close()
 
 
+def _subtree_volume(parent, deg, pad):
+    """Per vertex: the adjacency slots (degree + pad) summed over its subtree."""
+    n = len(parent)
+    ids = np.arange(n)
+    depth = np.zeros(n, np.int64)
+    while True:  # depth[v] = depth[parent[v]] + 1 until nothing changes
+        nd = np.where(parent == ids, 0, depth[parent] + 1)
+        if np.array_equal(nd, depth):
+            break
+        depth = nd
+    vol = deg.astype(np.int64) + pad
+    for d in range(int(depth.max()), 0, -1):
+        at = np.flatnonzero(depth == d)
+        np.add.at(vol, parent[at], vol[at])
+    return vol
+
+
+@pytest.mark.parametrize("lo,hi,scan", [(0.55, 0.95, 1), (1.1, 10.0, 0)])
+def test_orphan_scan_volume_bands(lo, hi, scan):
+    """Deletes of tree edges below the root chosen so that the cut-off
+    vertices hold between half and all of the store's slots (the orphan
+    scan runs with two ranges per output region), or more than all of them
+    (the whole-store sweep runs).  Bit-exact against the oracle."""
+    drsf = _lib()
+    _case(f"orphan volume band {lo}-{hi}")
+    keys = gen.rmat(16, 16, 0.57, 0.19, 0.19, gen.seed(2, 9, gen.P_GRAPH))
+    g = gen.make_graph("rmat16", 1 << 16, keys)
+    pair = Pair(g, max_batch=1 << 16)
+    par = pair.parent
+    deg = np.diff(g.row_ptr)
+    pad = 8  # empty slots the scan gives every orphan
+    vol = _subtree_volume(par, deg, pad)
+    root = 0
+    kids = np.flatnonzero((par == root) & (np.arange(g.n) != root))
+    total, chosen = 0, []
+    for c in kids[np.argsort(-vol[kids], kind="stable")]:
+        if total > lo * g.m:
+            break
+        if total + vol[c] <= hi * g.m:
+            total += int(vol[c])
+            chosen.append(int(c))
+    assert lo * g.m < total <= hi * g.m, (total, g.m)  # the premise
+    batch = np.array([(c, root) for c in chosen], np.int32)
+    st, _ = pair.step(batch, drsf.DRSF_DELETE, f"band {lo}-{hi}")
+    assert st["orphan_slots"] + pad * st["num_orphans"] == total
+    assert st["scan_orphans"] == scan, st
+    pair.gpu.close()
+
+
+@pytest.mark.slow
+def test_orphan_count_beyond_2_20():
+    """R-MAT scale 22: one delete of 64,712 tree edges below the root cutting
+    off about 1.1e6 vertices (more than 2^20) whose slots stay below the
+    store's, so the orphan scan runs: the orphan list's prefixes over the
+    whole graph must not wrap.  Orphan count and slots exact; bit-exact
+    against the oracle."""
+    drsf = _lib()
+    _case("rmat22 orphans beyond 2^20")
+    keys = gen.rmat(22, 16, 0.57, 0.19, 0.19, gen.seed(2, 0, gen.P_GRAPH))
+    g = gen.make_graph("rmat22", 1 << 22, keys)
+    pair = Pair(g, max_batch=1 << 17)
+    par = pair.parent
+    pad = 8
+    vol = _subtree_volume(par, np.diff(g.row_ptr), pad)
+    size = _subtree_volume(par, np.zeros(g.n, np.int64), 1)
+    root = 0
+    kids = np.flatnonzero((par == root) & (np.arange(g.n) != root))
+    order = kids[np.argsort(-(size[kids] / vol[kids]), kind="stable")]
+    count, total, chosen = 0, 0, []
+    for c in order:
+        if count > (1 << 20) + 50_000:
+            break
+        if total + vol[c] <= 0.95 * g.m:
+            count += int(size[c])
+            total += int(vol[c])
+            chosen.append(int(c))
+    assert count > (1 << 20) and total <= g.m  # the premise
+    batch = np.array([(c, root) for c in chosen], np.int32)
+    st, _ = pair.step(batch, drsf.DRSF_DELETE, "rmat22 wide cut")
+    assert st["num_orphans"] == count, st
+    assert st["orphan_slots"] + pad * count == total, st
+    assert st["scan_orphans"] == 1, st
+    pair.gpu.close()
+
+
 @pytest.mark.parametrize("workload", ["gnm", "rmat16", "grid", "path", "continuation"])
 def test_euler_tour_reversal(workload):
     """Path reversal by Euler tour (reverse_mode 1, the paper's
