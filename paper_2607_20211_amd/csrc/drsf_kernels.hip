@@ -966,17 +966,20 @@ __global__ __launch_bounds__(BLOCK) void k_orph_scan(Dev d) {
             const int64_t S1 = (rg + 1) * OR_W < V ? (rg + 1) * OR_W : V;
             int64_t pos = rg * OR_W;
             int64_t i0 = d.rstart[rg];
+            // the last orphan that meets this range: the one holding the next
+            // range's first slot (a hub alone covers whole ranges)
+            const int64_t ilast = S1 < V ? d.rstart[rg + 1] : no - 1;
             while (pos < S1) {  // windows of BLOCK orphans; uniform over the block
+                const int64_t lim = ilast - i0 + 1;
+                const int wn = lim < BLOCK ? (int)lim : BLOCK;
                 __syncthreads();  // the LDS is free
-                const int64_t ii = i0 + threadIdx.x;
-                if (ii < no) {
-                    s_o[threadIdx.x] = d.olist[ii];
+                if (threadIdx.x < wn) {
+                    s_o[threadIdx.x] = d.olist[i0 + threadIdx.x];
                     s_pre[threadIdx.x] = s_o[threadIdx.x].pre;
                 }
                 s_min[threadIdx.x] = KEY_INF;
                 s_mink[threadIdx.x] = KEY_INF;
                 __syncthreads();
-                const int wn = no - i0 < BLOCK ? (int)(no - i0) : BLOCK;
                 int64_t we = S1;
                 if (wn > 0) {
                     const OrphEnt &last = s_o[wn - 1];
@@ -1052,23 +1055,38 @@ __global__ __launch_bounds__(BLOCK) void k_orph_scan(Dev d) {
                     }
                 }
                 // edges to old roots: the lowest key per orphan (a thread's
-                // slots meet few orphans, one LDS minimum per orphan met)
+                // slots meet few orphans, one LDS minimum per orphan met; the
+                // last one met is merged across the wave when every lane
+                // ends on the same orphan, as in a hub's ranges)
                 {
                     int32_t ca = -1;
                     uint64_t mk = ~0ull;
 #pragma unroll
-                    for (int k = 0; k <= OR_K; k++) {
-                        const bool in = k < OR_K && (xk >> k & 1);
-                        if (in && oi[k] == ca) {
-                            const uint64_t key = mkkey((uint32_t)s_o[oi[k]].v, (uint32_t)col[k]);
+                    for (int k = 0; k < OR_K; k++) {
+                        if (!(xk >> k & 1)) continue;
+                        const uint64_t key = mkkey((uint32_t)s_o[oi[k]].v, (uint32_t)col[k]);
+                        if (oi[k] == ca) {
                             mk = key < mk ? key : mk;
                             continue;
                         }
-                        if (!in && k < OR_K) continue;
                         if (ca >= 0 && s_mink[ca] > mk) atomicMin(&s_mink[ca], (unsigned long long)mk);
-                        if (k < OR_K) {
-                            ca = oi[k];
-                            mk = mkkey((uint32_t)s_o[oi[k]].v, (uint32_t)col[k]);
+                        ca = oi[k];
+                        mk = key;
+                    }
+                    const bool has = ca >= 0;
+                    const uint64_t hm = __ballot(has);
+                    if (hm) {
+                        const int leader = __ffsll((unsigned long long)hm) - 1;
+                        const int32_t c0 = __shfl(ca, leader);
+                        if (__ballot(has && ca == c0) == hm) {
+                            uint64_t v = has ? mk : ~0ull;
+                            for (int o = WAVE / 2; o > 0; o >>= 1) {
+                                const uint64_t y = __shfl_xor(v, o);
+                                v = y < v ? y : v;
+                            }
+                            if (lane_id() == leader && s_mink[c0] > v) atomicMin(&s_mink[c0], (unsigned long long)v);
+                        } else if (has && s_mink[ca] > mk) {
+                            atomicMin(&s_mink[ca], (unsigned long long)mk);
                         }
                     }
                 }
