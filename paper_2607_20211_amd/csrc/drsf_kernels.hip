@@ -370,8 +370,9 @@ __device__ void rep_init(const Dev &d, int64_t bid, int64_t nblk) {
     typedef int v4i __attribute__((ext_vector_type(4)));
     const int64_t nb = (d.n + BLOCK - 1) / BLOCK;
     const int w = threadIdx.x / WAVE;
+    const int64_t nvl_list = d.ctl->nvl;  // read once: stores below may alias it
     for (int64_t j = bid * (BLOCK / WAVE) + w;; j += nblk * (BLOCK / WAVE)) {
-        const int64_t blk = list_block(d.vlist, d.ctl->nvl, j, nb);
+        const int64_t blk = list_block(d.vlist, nvl_list, j, nb);
         if (blk < 0) break;
         const int64_t v = blk * BLOCK + lane_id() * 4;
         if (v + 4 <= d.n) {
@@ -517,13 +518,14 @@ constexpr int REP_CH = DRSF_REP_CH;
 __global__ __launch_bounds__(BLOCK) void k_rep_chase(Dev d) {
     if (*d.status || !d.ctl->has_del) return;
     const int64_t nb = (d.n + BLOCK - 1) / BLOCK;
+    const int64_t nvl_list = d.ctl->nvl;  // read once: stores below may alias it
     for (int64_t j0 = (int64_t)blockIdx.x * REP_CH;; j0 += (int64_t)gridDim.x * REP_CH) {
         int64_t blk[REP_CH], v[REP_CH];
         int32_t x[REP_CH], lab[REP_CH];
         bool live[REP_CH], act[REP_CH];
 #pragma unroll
         for (int k = 0; k < REP_CH; k++) {
-            blk[k] = list_block(d.vlist, d.ctl->nvl, j0 + k, nb);
+            blk[k] = list_block(d.vlist, nvl_list, j0 + k, nb);
             v[k] = blk[k] >= 0 ? blk[k] * BLOCK + threadIdx.x : d.n;
             live[k] = act[k] = v[k] < d.n;
         }
@@ -645,8 +647,9 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_base(Dev d) {
     __shared__ int32_t s_u[TILE + 1];     // row vertex per local row
     __shared__ int16_t s_wmax[BLOCK / WAVE];
     int16_t *s_row = reinterpret_cast<int16_t *>(s_rowv);
+    const int64_t ntl_list = d.ctl->ntl;  // read once: stores below may alias it
     for (int64_t jt = blockIdx.x;; jt += gridDim.x) {
-        const int64_t tile = list_block(d.tlist, d.ctl->ntl, jt, d.ntiles);
+        const int64_t tile = list_block(d.tlist, ntl_list, jt, d.ntiles);
         if (tile < 0) break;
         __syncthreads();  // the previous tile is finished with the LDS
         const int64_t base = tile * TILE;
@@ -911,9 +914,10 @@ __global__ __launch_bounds__(BLOCK) void k_orph_fill(Dev d) {
     constexpr int FILL_LANES = 8;
     const int64_t per_block = BLOCK / FILL_LANES;
     const int sub = threadIdx.x % FILL_LANES;
+    const int64_t nvl_list = d.ctl->nvl;  // read once: stores below may alias it
     for (int64_t j = (int64_t)blockIdx.x * per_block + threadIdx.x / FILL_LANES;;
          j += (int64_t)gridDim.x * per_block) {
-        const int64_t blk = list_block(d.vlist, d.ctl->nvl, j, d.nvb);
+        const int64_t blk = list_block(d.vlist, nvl_list, j, d.nvb);
         if (blk < 0) break;
         const int32_t nc = d.bcnt[blk];
         if (nc == 0) continue;
@@ -1724,8 +1728,9 @@ __device__ void label_delete(const Dev &d, int64_t bid, int64_t nblk) {
         return;
     }
     const int64_t nb = (d.n + BLOCK - 1) / BLOCK;
+    const int64_t nvl_list = d.ctl->nvl;  // read once: stores below may alias it
     for (int64_t j = bid;; j += nblk) {
-        const int64_t blk = list_block(d.vlist, d.ctl->nvl, j, nb);
+        const int64_t blk = list_block(d.vlist, nvl_list, j, nb);
         if (blk < 0) break;
         const int64_t v = blk * BLOCK + threadIdx.x;
         uint64_t w = 0;
@@ -1759,8 +1764,9 @@ __device__ void label_insert(const Dev &d, int64_t bid, int64_t nblk) {
     const int64_t nb = (d.n + BLOCK - 1) / BLOCK;
     const int w = threadIdx.x / WAVE;
     // one wave per vertex block, four vertices per lane
+    const int64_t nil_list = d.ctl->nil;  // read once: stores below may alias it
     for (int64_t j = bid * (BLOCK / WAVE) + w;; j += nblk * (BLOCK / WAVE)) {
-        const int64_t blk = list_block(d.ilist, d.ctl->nil, j, nb);
+        const int64_t blk = list_block(d.ilist, nil_list, j, nb);
         if (blk < 0) break;
         const int64_t v = blk * BLOCK + lane_id() * 4;
         int32_t lab[4];
@@ -2052,8 +2058,8 @@ __global__ __launch_bounds__(BLOCK) void k_cleanup(Dev d) {
         }
         for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < b; i += stride)
             if (d.bslot[i] != NONE) d.bhash[d.bslot[i]] = HASH_EMPTY;
-        for (int64_t t = d.ctl->rlo + (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < d.ctl->rhi;
-             t += stride)
+        const int64_t rlo = d.ctl->rlo, rhi = d.ctl->rhi;  // read once: the stores may alias them
+        for (int64_t t = rlo + (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < rhi; t += stride)
             d.rcnt[t] = 0;
     }
     if (!last_block_arrives(&d.cnt[C_ARRIVE])) return;
