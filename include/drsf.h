@@ -82,9 +82,10 @@ typedef struct {
                                 O(|E|) work, amortised over the list; 0 = automatic
                                 (max(4 max_batch, |E| / 8, 2^20)) */
     int sweep_mode;          /* delete key-edge scan: 0 (default) per batch, the
-                                orphans' adjacency when it is at most half the
-                                store, else the whole store; 1: always the whole
-                                store (Sec. II-A as written) */
+                                orphans' adjacency (each orphan counted with 8
+                                extra slots) when it holds at most as many
+                                slots as the store, else the whole store; 1:
+                                always the whole store (Sec. II-A as written) */
     int rounds_queued;       /* full-grid hooking rounds (Alg. 2, phase 1)
                                 placed in the captured update graph; later
                                 rounds run in one workgroup while at most 4096
