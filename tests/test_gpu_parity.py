@@ -467,6 +467,32 @@ def test_invalid_batches_leave_state_unchanged():
     f.close()
 
 
+def test_batch_at_capacity_and_tiny_graphs():
+    """Batches of exactly max_batch edges (insert, then delete with half
+    tree edges), and the smallest graphs: one vertex (an empty batch), two
+    vertices joined by their one edge (delete it, insert it back).
+    Bit-exact against the oracle."""
+    drsf = _lib()
+    _case("capacity and tiny graphs")
+    n = 5000
+    g = gen.make_graph("cap", n, gen.gnm(n, 7000, gen.seed(7, 0, gen.P_GRAPH)))
+    pair = Pair(g, max_batch=1024)
+    ins = gen.insert_batches(n, pair.keys, 1, 1024, gen.seed(7, 0, gen.P_INSERT))[0]
+    pair.step(ins, drsf.DRSF_INSERT, "capacity insert")
+    dl = gen.delete_batches(n, pair.keys, pair.parent, 1, 1024, 512, gen.seed(7, 0, gen.P_DELETE))[0]
+    pair.step(dl, drsf.DRSF_DELETE, "capacity delete")
+    pair.gpu.close()
+    one = Pair(gen.make_graph("one vertex", 1, np.zeros(0, np.uint64)), max_batch=4)
+    one.step(np.zeros((0, 2), np.int32), drsf.DRSF_INSERT, "one vertex")
+    one.gpu.close()
+    two = Pair(gen.make_graph("two vertices", 2, np.array([1], np.uint64)), max_batch=4)
+    st, _ = two.step(np.array([[1, 0]], np.int32), drsf.DRSF_DELETE, "two: delete the edge")
+    assert list(two.gpu.label()) == [0, 1]
+    two.step(np.array([[0, 1]], np.int32), drsf.DRSF_INSERT, "two: insert it back")
+    assert list(two.gpu.parent()) == [0, 0]
+    two.gpu.close()
+
+
 def test_repeated_pairs_in_large_batches():
     """A pair repeated anywhere in a large batch (either orientation) is
     rejected and leaves the state unchanged; the same batches without the
