@@ -136,7 +136,9 @@ def served_workload(scale, ntenants, nreq, seed):
 
 def run_served(scale, nreq, loads, log):
     """Served pattern against the plain path (one request at a time in
-    arrival order, same server code in serial mode)."""
+    arrival order, same server code in serial mode), and with coalescing
+    (the same-op requests waiting at the head of a tenant's queue go out as
+    one batch)."""
     from paper_2607_20211_amd import drsf
     t0 = time.time()
     graphs, reqs, win, last = served_workload(scale, 8, nreq, 0)
@@ -148,20 +150,21 @@ def run_served(scale, nreq, loads, log):
     fps = [drsf.drsf_footprint(g.n, len(g.col), opts) for g in graphs]
     budget = fps[0] + sum(sorted(fps[1:])[-3:])
 
-    def serve(serial, rate):
-        srv = drsf.Server(budget, max_batch=100_000, serial=serial)
+    def serve(serial, rate, coalesce=False):
+        srv = drsf.Server(budget, max_batch=100_000, serial=serial, coalesce=coalesce)
         scale_ns = 1e9 / rate if rate else 0.0
         tids = []
         for g, gr in enumerate(graphs):
             a = 0 if g == 0 or not rate else int(win[g][0] * scale_ns)
             tids.append(srv.admit(gr.n, gr.row_ptr, gr.col, gr.parent, arrive_ns=a))
-        for i, (g, e, op, t) in enumerate(reqs):
-            srv.submit(tids[g], e, op, arrive_ns=int(t * scale_ns) if rate else 0)
+        rids = [srv.submit(tids[g], e, op, arrive_ns=int(t * scale_ns) if rate else 0)
+                for g, e, op, t in reqs]
         for g in range(1, len(graphs)):
             srv.release(tids[g])
         srv.start()
         srv.wait_all()
         st = srv.stats()
+        st["batches"] = len({srv.batch(r) for r in rids})
         srv.close()
         return st
 
@@ -173,10 +176,12 @@ def run_served(scale, nreq, loads, log):
         rate = lam * mu
         a = serve(False, rate)
         b = serve(True, rate)
+        c = serve(False, rate, coalesce=True)
         log(f"load {lam}: served p50 {a['p50_ms']:.3f} p99 {a['p99_ms']:.3f} ms "
             f"(service {a['service_p50_ms']:.3f} / {a['service_p99_ms']:.3f}); "
             f"plain p50 {b['p50_ms']:.3f} p99 {b['p99_ms']:.3f} ms "
-            f"(service {b['service_p50_ms']:.3f} / {b['service_p99_ms']:.3f})")
+            f"(service {b['service_p50_ms']:.3f} / {b['service_p99_ms']:.3f}); "
+            f"coalesced p50 {c['p50_ms']:.3f} p99 {c['p99_ms']:.3f} ms in {c['batches']} batches")
         out.append({"load": lam, "offered_requests_per_s": round(rate, 1),
                     "served_p50_ms": round(a["p50_ms"], 4), "served_p99_ms": round(a["p99_ms"], 4),
                     "served_service_p50_ms": round(a["service_p50_ms"], 4),
@@ -186,6 +191,11 @@ def run_served(scale, nreq, loads, log):
                     "plain_service_p50_ms": round(b["service_p50_ms"], 4),
                     "plain_service_p99_ms": round(b["service_p99_ms"], 4),
                     "plain_updates_per_s": round(b["updates_per_s"], 1),
+                    "coalesced_p50_ms": round(c["p50_ms"], 4), "coalesced_p99_ms": round(c["p99_ms"], 4),
+                    "coalesced_service_p50_ms": round(c["service_p50_ms"], 4),
+                    "coalesced_service_p99_ms": round(c["service_p99_ms"], 4),
+                    "coalesced_updates_per_s": round(c["updates_per_s"], 1),
+                    "coalesced_batches": c["batches"],
                     "peak_bytes": a["peak_bytes"]})
     return {"workload": f"resident R-MAT scale {scale} + 8 tenants G(n, 4n), n = 10^U(5,6), "
                         f"staggered; {len(reqs)} requests of 10^U(2,5) edges, Poisson arrivals",

@@ -329,21 +329,30 @@ const char *drsf_version(void);
  * footprint (drsf_footprint) fits the budget, keeps one FIFO per tenant and
  * starts the head request of every ready tenant on that tenant's stream, so
  * updates of different graphs overlap on the device.  Requests of one tenant
- * are applied one at a time in arrival order (never merged), so each
- * request's result is the one drsf_apply would give on that graph.
+ * are applied in arrival order, by default one batch each, so each request's
+ * result is the one drsf_apply would give on that graph.
  *
  * Times are nanoseconds from drsf_server_start.  arrive_ns >= 0 schedules an
  * admission or request at that time (a pre-generated arrival stream); < 0
  * means now.  Requests submitted before their tenant is admitted wait for
  * it.  Flags: DRSF_SERVER_DIGESTS computes drsf_digest-equal digests of
  * parent and label after every request; DRSF_SERVER_SERIAL keeps at most one
- * request in flight over all tenants, in arrival order (the plain path).
+ * request in flight over all tenants, in arrival order (the plain path);
+ * DRSF_SERVER_COALESCE applies the requests of the same op waiting together
+ * at the head of an idle tenant's FIFO as one batch (up to max_batch
+ * edges).  A merged result is that of drsf_apply on the merged batch (the
+ * same components; the replacement edges may differ from one-at-a-time
+ * application, as Kruskal over a union of batches differs from Kruskal in
+ * sequence); drsf_server_batch tells which batch carried a request.  A
+ * merged batch that is rejected changes nothing and its requests are
+ * retried one at a time.
  * All inputs are host memory and are copied.  One thread at a time may call
  * a server's functions, besides its own scheduler thread.
  */
 typedef struct drsf_server drsf_server;
 #define DRSF_SERVER_DIGESTS 1
 #define DRSF_SERVER_SERIAL 2
+#define DRSF_SERVER_COALESCE 4
 int drsf_server_create(int64_t budget_bytes, const drsf_opts *opts, int flags, drsf_server **out);
 /* Errors: DRSF_E_BUDGET when the estimate exceeds the whole budget. */
 int drsf_server_admit(drsf_server *srv, int32_t n, const int64_t *row_ptr, const int32_t *col,
@@ -361,6 +370,13 @@ int drsf_server_wait_all(drsf_server *srv);
  * DRSF_SERVER_DIGESTS).  Any output may be NULL.
  */
 int drsf_server_result(drsf_server *srv, int64_t req, int32_t *status, uint64_t *t_ns, uint64_t *digest);
+/*
+ * Blocks until request req is done; *batch = the id of the first request of
+ * the device batch that carried it (req itself when it went alone; all
+ * requests of one batch complete together with the same status and
+ * digests).
+ */
+int drsf_server_batch(drsf_server *srv, int64_t req, int64_t *batch);
 /*
  * out[8]: completed requests, p50 and p99 of (completion - arrival) in ms,
  * edge updates per second from the first arrival to the last completion,

@@ -10,10 +10,14 @@
 // so updates of different graphs overlap on the device), (4) completes
 // requests whose stream has drained, and (5) destroys released tenants once
 // their FIFO is empty, which frees memory for the admission queue.  Requests
-// of one tenant are applied in arrival order and never merged, so every
-// request's result equals applying the same requests one at a time.  In
-// serial mode at most one request is in flight over all tenants, in global
-// arrival order: the plain one-batch-at-a-time path, for comparison.
+// of one tenant are applied in arrival order.  By default each is its own
+// batch, so every request's result equals applying the same requests one at
+// a time.  In coalescing mode the requests of the same op waiting at the head
+// of an idle tenant's FIFO go out as one batch (up to max_batch edges); a
+// merged batch that is rejected leaves the graph unchanged and its requests
+// are retried one at a time; each request records the batch that carried it.
+// In serial mode at most one request is in flight over all tenants, in
+// global arrival order: the plain one-batch-at-a-time path, for comparison.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -46,6 +50,7 @@ struct Req {
     uint64_t t_arrive = 0, t_start = 0, t_done = 0;  // ns since the server's start
     int32_t status = DRSF_OK;
     uint64_t digest[2] = {0, 0};
+    int64_t batch = -1;  // the first request of the batch that carried it
     bool done = false;
 };
 
@@ -66,6 +71,9 @@ struct Tenant {
     int64_t bytes = 0;
     std::deque<int64_t> fifo;
     int64_t inflight = -1;
+    std::vector<int64_t> group;   // the requests of the batch in flight
+    std::vector<int32_t> merged;  // their edges, when there are several
+    int64_t solo = 0;             // requests to apply alone (after a rejected merge)
     int phase = 0;  // 1 update queued, 2 digest queued
     bool release = false;
     unsigned long long *d_dig = nullptr, *h_dig = nullptr;
@@ -215,9 +223,18 @@ void scheduler(drsf_server *s) {
                 (void)hipGetLastError();
                 continue;
             }
-            Req &r = s->reqs[tn.inflight];
             if (tn.phase == 1) {
                 const int rc = drsf_wait(tn.ctx, nullptr);  // may finish the update on the host
+                if (rc == DRSF_E_BATCH && tn.group.size() > 1) {
+                    // a merged batch was rejected (the graph is unchanged):
+                    // its requests go back, to be applied one at a time
+                    for (auto it = tn.group.rbegin(); it != tn.group.rend(); ++it) tn.fifo.push_front(*it);
+                    tn.solo = (int64_t)tn.group.size();
+                    tn.group.clear();
+                    tn.inflight = -1;
+                    tn.phase = 0;
+                    continue;
+                }
                 if (rc == DRSF_OK && (s->flags & DRSF_SERVER_DIGESTS)) {
                     drsf_view v;
                     drsf_get_view(tn.ctx, &v);
@@ -227,12 +244,18 @@ void scheduler(drsf_server *s) {
                     tn.phase = 2;
                     continue;
                 }
-                complete(s, r, rc, now_ns() - s->t0);
+                const uint64_t td = now_ns() - s->t0;
+                for (int64_t id : tn.group) complete(s, s->reqs[id], rc, td);
             } else {
-                r.digest[0] = tn.h_dig[0];
-                r.digest[1] = tn.h_dig[1];
-                complete(s, r, DRSF_OK, now_ns() - s->t0);
+                const uint64_t td = now_ns() - s->t0;
+                for (int64_t id : tn.group) {
+                    Req &r = s->reqs[id];
+                    r.digest[0] = tn.h_dig[0];
+                    r.digest[1] = tn.h_dig[1];
+                    complete(s, r, DRSF_OK, td);
+                }
             }
+            tn.group.clear();
             tn.inflight = -1;
             tn.phase = 0;
         }
@@ -254,10 +277,44 @@ void scheduler(drsf_server *s) {
             const int64_t id = pick->fifo.front();
             pick->fifo.pop_front();
             Req &r = s->reqs[id];
-            r.t_start = now_ns() - s->t0;
-            const int rc = drsf_apply_async(pick->ctx, r.edges.data(), (int64_t)(r.edges.size() / 2), r.op);
+            pick->group.assign(1, id);
+            const int32_t *edges = r.edges.data();
+            int64_t b = (int64_t)(r.edges.size() / 2);
+            if ((s->flags & DRSF_SERVER_COALESCE) && pick->solo == 0) {
+                // the following requests of the same op, while the batch fits
+                const int64_t cap = s->opts.max_batch > 0 ? s->opts.max_batch : (1 << 20);
+                int64_t tot = b;
+                while (!pick->fifo.empty()) {
+                    const Req &q = s->reqs[pick->fifo.front()];
+                    const int64_t qb = (int64_t)(q.edges.size() / 2);
+                    if (q.op != r.op || tot + qb > cap) break;
+                    pick->group.push_back(q.id);
+                    tot += qb;
+                    pick->fifo.pop_front();
+                }
+                if (pick->group.size() > 1) {
+                    pick->merged.clear();
+                    pick->merged.reserve((size_t)(2 * tot));
+                    for (int64_t gid : pick->group) {
+                        const std::vector<int32_t> &e = s->reqs[gid].edges;
+                        pick->merged.insert(pick->merged.end(), e.begin(), e.end());
+                    }
+                    edges = pick->merged.data();
+                    b = tot;
+                }
+            }
+            if (pick->solo > 0) pick->solo--;
+            const uint64_t ts = now_ns() - s->t0;
+            for (int64_t gid : pick->group) {
+                s->reqs[gid].t_start = ts;
+                s->reqs[gid].batch = id;
+            }
+            // host edges are copied before the call returns
+            const int rc = drsf_apply_async(pick->ctx, edges, b, r.op);
             if (rc != DRSF_OK) {
-                complete(s, r, rc, now_ns() - s->t0);
+                const uint64_t td = now_ns() - s->t0;
+                for (int64_t gid : pick->group) complete(s, s->reqs[gid], rc, td);
+                pick->group.clear();
                 continue;
             }
             pick->inflight = id;
@@ -445,6 +502,16 @@ int drsf_server_result(drsf_server *s, int64_t req, int32_t *status, uint64_t *t
         digest[0] = r.digest[0];
         digest[1] = r.digest[1];
     }
+    return DRSF_OK;
+}
+
+int drsf_server_batch(drsf_server *s, int64_t req, int64_t *batch) {
+    if (!s || !batch) return DRSF_E_ARG;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(req);
+    if (it == s->reqs.end()) return sfail(s, DRSF_E_ARG, "unknown request");
+    s->cv_done.wait(lk, [&] { return it->second.done; });
+    *batch = it->second.batch;
     return DRSF_OK;
 }
 

@@ -19,7 +19,7 @@ DRSF_INSERT, DRSF_DELETE = 0, 1
 DRSF_OK, DRSF_E_ARG, DRSF_E_NOMEM, DRSF_E_FOREST = 0, -1, -2, -3
 DRSF_E_BATCH, DRSF_E_CAPACITY, DRSF_E_DEVICE, DRSF_E_STATE = -4, -5, -6, -7
 DRSF_E_BUDGET = -8
-DRSF_SERVER_DIGESTS, DRSF_SERVER_SERIAL = 1, 2
+DRSF_SERVER_DIGESTS, DRSF_SERVER_SERIAL, DRSF_SERVER_COALESCE = 1, 2, 4
 PHASES = ("validate", "update_graph", "root_finding", "orphan_list", "orphan_scan",
           "store_sweep", "batch_and_inserted_scan", "replacement_edges", "superforest_rooting",
           "reversal_and_labels")
@@ -72,7 +72,7 @@ EXPORTS = ("drsf_default_opts", "drsf_create", "drsf_apply", "drsf_apply_async",
            "drsf_multi_num_edges", "drsf_num_graphs", "drsf_set_tuning", "drsf_digest",
            "drsf_device_bytes", "drsf_footprint", "drsf_server_create", "drsf_server_admit",
            "drsf_server_submit", "drsf_server_release", "drsf_server_start",
-           "drsf_server_wait_all", "drsf_server_result", "drsf_server_stats",
+           "drsf_server_wait_all", "drsf_server_result", "drsf_server_batch", "drsf_server_stats",
            "drsf_server_tenant_state", "drsf_server_error", "drsf_server_destroy",
            "drsf_static_forest")
 
@@ -164,6 +164,8 @@ def load():
     lib.drsf_server_wait_all.restype = c_int
     lib.drsf_server_result.argtypes = [vp, i64, ctypes.POINTER(i32), vp, vp]
     lib.drsf_server_result.restype = c_int
+    lib.drsf_server_batch.argtypes = [vp, i64, ctypes.POINTER(i64)]
+    lib.drsf_server_batch.restype = c_int
     lib.drsf_server_stats.argtypes = [vp, vp]
     lib.drsf_server_stats.restype = c_int
     lib.drsf_server_tenant_state.argtypes = [vp, i32]
@@ -503,11 +505,12 @@ class Server:
     library's scheduler thread (drsf_server_* in include/drsf.h)."""
 
     def __init__(self, budget_bytes: int, *, max_batch: int = 1 << 17, digests: bool = False,
-                 serial: bool = False, sweep_mode: int = 0):
+                 serial: bool = False, coalesce: bool = False, sweep_mode: int = 0):
         o = drsf_default_opts()
         o.max_batch = max_batch
         o.sweep_mode = sweep_mode
-        flags = (DRSF_SERVER_DIGESTS if digests else 0) | (DRSF_SERVER_SERIAL if serial else 0)
+        flags = ((DRSF_SERVER_DIGESTS if digests else 0) | (DRSF_SERVER_SERIAL if serial else 0) |
+                 (DRSF_SERVER_COALESCE if coalesce else 0))
         out = ctypes.c_void_p()
         _scheck(load().drsf_server_create(int(budget_bytes), ctypes.byref(o), flags, ctypes.byref(out)),
                 None)
@@ -546,6 +549,12 @@ class Server:
                                           dg.ctypes.data), self.srv)
         return {"status": st.value, "t_arrive": int(t[0]), "t_start": int(t[1]), "t_done": int(t[2]),
                 "digest": (int(dg[0]), int(dg[1]))}
+
+    def batch(self, req: int) -> int:
+        """Id of the first request of the device batch that carried req."""
+        b = ctypes.c_int64()
+        _scheck(load().drsf_server_batch(self.srv, req, ctypes.byref(b)), self.srv)
+        return b.value
 
     def stats(self) -> dict:
         out = np.zeros(8, dtype=np.float64)

@@ -145,6 +145,59 @@ def test_served_requests_match_oracle(serial):
     assert stats["p50_ms"] <= stats["p99_ms"]
 
 
+def test_coalesced_batches_match_oracle():
+    """Coalescing mode with requests arriving in bursts, so that several wait
+    together: the same-op requests at the head of a tenant's FIFO go out as
+    one batch.  The oracle applies exactly the batches the server reports
+    (drsf_server_batch) and every request's digest equals the oracle's after
+    its batch.  Two invalid requests make their merged batches fail; those
+    requests are then applied one at a time, and only the invalid ones fail."""
+    drsf = _lib()
+    _case("server coalescing")
+    graphs = _tenants(3, 1)
+    reqs = _stream(graphs, 150, 5, bad={20, 77})
+    reqs = [(t, e, op, (k // 12) * 3_000_000) for k, (t, e, op, _) in enumerate(reqs)]  # bursts of 12
+    srv = drsf.Server(1 << 40, max_batch=512, digests=True, coalesce=True)
+    ids = [srv.admit(g.n, g.row_ptr, g.col, g.parent) for g in graphs]
+    rids = [srv.submit(ids[t], e, op, arrive_ns=a) for t, e, op, a in reqs]
+    for tid in ids:
+        srv.release(tid)
+    srv.start()
+    srv.wait_all()
+    res = [srv.result(r) for r in rids]
+    batch = [srv.batch(r) for r in rids]
+    srv.close()
+    pos = {r: k for k, r in enumerate(rids)}
+    groups = {}
+    for k, b in enumerate(batch):
+        groups.setdefault(b, []).append(k)
+    assert max(len(v) for v in groups.values()) > 1, "no requests were merged"
+    for b, ks in groups.items():
+        assert ks[0] == pos[b] and len({reqs[k][0] for k in ks}) == 1 and len({reqs[k][2] for k in ks}) == 1
+    for k in (20, 77):
+        assert groups[batch[k]] == [k], f"invalid request {k} was not retried alone"
+    # replay the batches per tenant, in the order of their first requests
+    st = []
+    for g in graphs:
+        r = oracle.apply(g.n, g.keys, g.parent, np.zeros((0, 2), np.int32), oracle.DELETE)
+        st.append([g.keys, r.parent, r.label])
+    for b in sorted(groups, key=lambda x: pos[x]):
+        ks = groups[b]
+        t, op = reqs[ks[0]][0], reqs[ks[0]][2]
+        e = np.concatenate([reqs[k][1] for k in ks]).reshape(-1, 2)
+        keys, par, lab = st[t]
+        try:
+            r = oracle.apply(graphs[t].n, keys, par, e, oracle.INSERT if op == 0 else oracle.DELETE, label=lab)
+        except oracle.OracleError:
+            assert len(ks) == 1 and res[ks[0]]["status"] == drsf.DRSF_E_BATCH, (b, ks)
+            continue
+        st[t] = [r.keys, r.parent, r.label]
+        dg = digest(r.parent, r.label)
+        for k in ks:
+            assert res[k]["status"] == drsf.DRSF_OK, (k, res[k])
+            assert res[k]["digest"] == dg, f"request {k} (batch {b}): digest differs from the oracle"
+
+
 def test_budget_delays_admission_only():
     """A budget that holds two of the four graphs: the later graphs wait
     for earlier ones to leave; every request still ends as the oracle says."""
