@@ -4,10 +4,11 @@
 // One update is a fixed kernel sequence (drsf_kernels.hip) whose batch shape
 // lives in a small device control block, so the sequence is captured once
 // per context into a HIP graph and replayed for every batch.  The graph
-// queues a few hooking rounds and search levels; when a batch needs more,
-// the kernels after them skip themselves and drsf_wait finishes the update
-// with direct launches (further rounds in short chunks, deeper search or the
-// Euler tour).  With opts.profile the same sequence is launched directly,
+// queues a few full-grid hooking rounds, one workgroup that runs the later
+// rounds while few cross edges are live, and a few search levels; when a
+// batch needs more, the kernels after them skip themselves and drsf_wait
+// finishes the update with direct launches (further rounds in short chunks,
+// deeper search or the Euler tour).  With opts.profile the same sequence is launched directly,
 // with events between the phases (events recorded inside a captured graph
 // cannot be timed on this runtime).
 #include <hip/hip_runtime.h>

@@ -1,10 +1,12 @@
 // D-RSF kernels for gfx950 (CDNA4, wave64).  One batch update follows
 // Algorithm 1 of "Fully Dynamic Rooted Spanning Tree on GPU":
 //   classify/validate -> update the edge store and cut deleted tree edges ->
-//   root finding (delete) -> key-edge sweep -> replacement edges by
-//   hooking rounds (Alg. 2, phase 1) -> super-forest rooting by an Euler
-//   tour with list ranking (Alg. 2, phase 2) -> path reversal and new parents
-//   (ReversePaths, Algorithm 1) -> component labels.
+//   root finding (delete) -> key-edge scan (the orphans' adjacency, or the
+//   whole store, plus the inserted-edge list) -> replacement edges by
+//   hooking rounds (Alg. 2, phase 1) -> super-forest rooting by a
+//   level-synchronous search from the super-roots, or an Euler tour with
+//   list ranking for deep super-trees (Alg. 2, phase 2) -> path reversal and
+//   new parents (ReversePaths, Algorithm 1) -> component labels.
 // All integer work; no MFMA.  Every loop over device-side counts is a
 // grid-stride loop, every pointer chase is bounded by n and reports
 // ST_WALK_BOUND instead of spinning, and every kernel after validation is a
@@ -24,7 +26,6 @@ int grid_for(int64_t items, int64_t per_block, int cap) {
 
 // ------------------------------------------------------------------ helpers
 
-// position of v in the ascending (masked) run bcol[lo, hi), or -1
 // Position of column v in the ascending run col[lo, hi) (tombstone bits
 // ignored), or -1; *raw receives the stored entry.  Each step loads
 // SEARCH_FAN evenly spaced entries at once and keeps the part of the run
