@@ -1,0 +1,71 @@
+"""Randomized parity: seeded small cases through the C ABI against the oracle.
+
+Each case draws a graph family and size (G(n, m) up to 2·10^4 vertices, R-MAT
+scale 6–14, grids with edges removed, paths with chords), a batch capacity,
+the delete scan (per batch or whole store), the path reversal (per path or
+Euler tour), the replacement-edge method (hooking on every cross edge or on
+the supergraph), sometimes a small inserted-edge list (store rebuilds) and a
+random launch schedule, then alternates insert and delete batches of random
+sizes (deletes with a random share of tree edges).  Every batch: parent and
+label arrays bit-exact, checker pass, same replacement-edge count."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import gen
+from test_gpu_parity import Pair, _case, _lib
+
+pytestmark = pytest.mark.gpu
+
+
+def _graph(rng, kind):
+    if kind == "gnm":
+        n = int(rng.integers(2, 20000))
+        m = min(int(rng.integers(0, 4 * n)), n * (n - 1) // 2)
+        return gen.make_graph("gnm", n, gen.gnm(n, m, int(rng.integers(1 << 30))))
+    if kind == "rmat":
+        s = int(rng.integers(6, 15))
+        return gen.make_graph("rmat", 1 << s, gen.rmat(s, int(rng.integers(2, 16)), 0.57, 0.19, 0.19,
+                                                        int(rng.integers(1 << 30))))
+    if kind == "grid":
+        a, b = int(rng.integers(2, 50)), int(rng.integers(2, 50))
+        total = a * (b - 1) + b * (a - 1)
+        return gen.make_graph("grid", a * b, gen.grid(a, b, int(rng.integers(0, total // 3 + 1)),
+                                                      int(rng.integers(1 << 30))))
+    n = int(rng.integers(2, 3000))
+    path = np.array([(i << 32) | (i + 1) for i in range(n - 1)], np.uint64)
+    chords = gen.gnm(n, int(rng.integers(0, n // 4 + 1)), int(rng.integers(1 << 30)))
+    return gen.make_graph("path", n, np.union1d(path, chords))
+
+
+@pytest.mark.parametrize("block", range(4))
+def test_random_cases(block):
+    drsf = _lib()
+    for c in range(block * 100, (block + 1) * 100):
+        rng = np.random.default_rng(7000 + c)
+        kind = ("gnm", "rmat", "grid", "path")[c % 4]
+        g = _graph(rng, kind)
+        mb = int(rng.integers(1, 3000))
+        kw = dict(max_batch=mb, sweep_mode=int(rng.integers(2)), reverse_mode=int(rng.random() < 0.25),
+                  replacement_mode=int(rng.random() < 0.25))
+        if rng.random() < 0.3:
+            kw["delta_capacity"] = int(rng.integers(mb, 3 * mb + 1))  # a batch always fits
+        _case(f"random {c}: {kind} n={g.n} m={g.m} {kw}")
+        pair = Pair(g, **kw)
+        if rng.random() < 0.5:
+            pair.gpu.set_tuning(int(rng.integers(1, 7)), int(rng.integers(1, 9)), int(rng.integers(2)))
+        for step in range(int(rng.integers(2, 8))):
+            b = int(rng.integers(0, mb + 1))
+            bi = min(b, g.n * (g.n - 1) // 2 - len(pair.keys))
+            if bi > 0:
+                ins = gen.insert_batches(g.n, pair.keys, 1, bi, int(rng.integers(1 << 30)))[0]
+                pair.step(ins, drsf.DRSF_INSERT, f"random {c} insert {step}")
+            trees = int((pair.parent != np.arange(g.n)).sum())
+            bd = min(b, len(pair.keys))
+            if bd > 0:
+                nt = min(trees, int(rng.integers(0, bd + 1)))
+                nt = max(nt, bd - (len(pair.keys) - trees))  # the rest must be non-tree edges
+                dl = gen.delete_batches(g.n, pair.keys, pair.parent, 1, bd, nt, int(rng.integers(1 << 30)))[0]
+                pair.step(dl, drsf.DRSF_DELETE, f"random {c} delete {step}")
+        pair.gpu.close()
