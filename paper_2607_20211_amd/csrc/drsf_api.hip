@@ -1200,34 +1200,41 @@ int drsf_multi_apply_async(drsf_ctx *c, const int32_t *edges, const int64_t *b_o
     // per-edge op and graph; vertex-block lists of the deleting and the
     // inserting graphs and the base-store tiles of the deleting ones
     bool any_ins = false, any_del = false;
-    for (int32_t g = 0; g < G; g++)
+    for (int32_t g = 0; g < G; g++) {
         for (int64_t i = b_off[g]; i < b_off[g + 1]; i++) {
             c->h_bop[i] = op[g];
             c->h_bgid[i] = g;
         }
-    int32_t *vl = c->h_lists, *il = c->h_lists + c->nvblk, *tl = c->h_lists + 2 * c->nvblk;
-    int64_t nvl = 0, nil = 0, ntl = 0, lastv = -1, lasti = -1, lastt = -1;
-    for (int32_t g = 0; g < G; g++) {
-        if (b_off[g + 1] == b_off[g] || c->goff_h[g + 1] == c->goff_h[g]) continue;
-        const int64_t v0 = c->goff_h[g] / BLOCK, v1 = (c->goff_h[g + 1] - 1) / BLOCK;
-        if (op[g] == DRSF_DELETE) {
-            any_del = true;
-            for (int64_t j = std::max(v0, lastv + 1); j <= v1; j++) vl[nvl++] = (int32_t)j;
-            lastv = std::max(lastv, v1);
-            if (c->gedge_h[g + 1] > c->gedge_h[g]) {
-                const int64_t t0 = c->gedge_h[g] / TILE, t1 = (c->gedge_h[g + 1] - 1) / TILE;
-                for (int64_t t = std::max(t0, lastt + 1); t <= t1; t++) tl[ntl++] = (int32_t)t;
-                lastt = std::max(lastt, t1);
-            }
-        } else {
-            any_ins = true;
-            for (int64_t j = std::max(v0, lasti + 1); j <= v1; j++) il[nil++] = (int32_t)j;
-            lasti = std::max(lasti, v1);
-        }
+        if (b_off[g + 1] > b_off[g]) (op[g] == DRSF_DELETE ? any_del : any_ins) = true;
     }
     hipStream_t s = c->stream;
-    HIPCHK(c, hipMemcpyAsync(c->lists, c->h_lists, sizeof(int32_t) * (size_t)(2 * c->nvblk + c->ntiles + 1),
-                             hipMemcpyHostToDevice, s));
+    // lists of -1: every vertex block and tile (one graph: the lists, only
+    // allocated for several, would hold them all)
+    int64_t nvl = -1, nil = -1, ntl = -1;
+    if (c->h_lists) {
+        int32_t *vl = c->h_lists, *il = c->h_lists + c->nvblk, *tl = c->h_lists + 2 * c->nvblk;
+        int64_t lastv = -1, lasti = -1, lastt = -1;
+        nvl = nil = ntl = 0;
+        for (int32_t g = 0; g < G; g++) {
+            if (b_off[g + 1] == b_off[g] || c->goff_h[g + 1] == c->goff_h[g]) continue;
+            const int64_t v0 = c->goff_h[g] / BLOCK, v1 = (c->goff_h[g + 1] - 1) / BLOCK;
+            if (op[g] == DRSF_DELETE) {
+                for (int64_t j = std::max(v0, lastv + 1); j <= v1; j++) vl[nvl++] = (int32_t)j;
+                lastv = std::max(lastv, v1);
+                if (c->gedge_h[g + 1] > c->gedge_h[g]) {
+                    const int64_t t0 = c->gedge_h[g] / TILE, t1 = (c->gedge_h[g + 1] - 1) / TILE;
+                    for (int64_t t = std::max(t0, lastt + 1); t <= t1; t++) tl[ntl++] = (int32_t)t;
+                    lastt = std::max(lastt, t1);
+                }
+            } else {
+                for (int64_t j = std::max(v0, lasti + 1); j <= v1; j++) il[nil++] = (int32_t)j;
+                lasti = std::max(lasti, v1);
+            }
+        }
+        HIPCHK(c, hipMemcpyAsync(c->lists, c->h_lists,
+                                 sizeof(int32_t) * (size_t)(2 * c->nvblk + c->ntiles + 1),
+                                 hipMemcpyHostToDevice, s));
+    }
     HIPCHK(c, hipMemcpyAsync(c->bop, c->h_bop, (size_t)b, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(c->bgid, c->h_bgid, sizeof(int32_t) * (size_t)b, hipMemcpyHostToDevice, s));
     if ((rc = stage_edges(c, edges, b))) return rc;

@@ -165,3 +165,23 @@ def test_multi_create_rejects_cross_graph_edge():
     st = f.apply_multi(np.array([[3, 70]], np.int32), np.array([0, 1, 1]), np.array([0, 0], np.int8))
     assert st[0] == drsf.DRSF_E_BATCH and st[1] == drsf.DRSF_OK
     f.close()
+
+
+def test_multi_context_with_one_graph():
+    """A multi-graph context holding a single graph (its block and tile
+    lists are not allocated: every block and tile is in play): inserts and
+    deletes through the multi-graph call, bit-exact with the oracle."""
+    drsf = _lib()
+    _case("multi with one graph")
+    graphs = _graphs([3000], 7)
+    pair = MultiPair(graphs, max_batch=2048)
+    for step in range(3):
+        (n, keys, par), = pair.local_state()
+        ins = gen.insert_batches(n, keys, 1, 500, gen.seed(41, step, gen.P_INSERT))[0]
+        pair.step([ins], np.array([drsf.DRSF_INSERT], np.int8), f"one graph insert {step}")
+        (n, keys, par), = pair.local_state()
+        trees = int((par != np.arange(n)).sum())
+        dl = gen.delete_batches(n, keys, par, 1, 400, min(200, trees), gen.seed(41, step, gen.P_DELETE))[0]
+        pair.step([dl], np.array([drsf.DRSF_DELETE], np.int8), f"one graph delete {step}")
+    pair.step([np.zeros((0, 2), np.int32)], np.array([drsf.DRSF_INSERT], np.int8), "one graph, empty")
+    pair.gpu.close()

@@ -69,3 +69,48 @@ def test_random_cases(block):
                 dl = gen.delete_batches(g.n, pair.keys, pair.parent, 1, bd, nt, int(rng.integers(1 << 30)))[0]
                 pair.step(dl, drsf.DRSF_DELETE, f"random {c} delete {step}")
         pair.gpu.close()
+
+
+def test_random_multi_graph_cases():
+    """The batched pattern: 60 seeded contexts of 1–40 graphs (1–5000
+    vertices each, some edgeless), 3–6 multi-graph updates each with a
+    random op and batch size per graph (empty batches included), now and
+    then an invalid batch for one graph (rejected, that graph unchanged), and
+    a random launch schedule; every graph bit-exact with the oracle run on
+    it alone."""
+    from test_gpu_multi import MultiPair
+    drsf = _lib()
+    for c in range(60):
+        rng = np.random.default_rng(9000 + c)
+        graphs = []
+        for g in range(int(rng.integers(1, 41))):
+            n = int(rng.integers(1, 5000))
+            m = min(int(rng.integers(0, 4 * n + 1)), n * (n - 1) // 2)
+            keys = gen.gnm(n, m, int(rng.integers(1 << 30))) if m > 0 else np.zeros(0, np.uint64)
+            graphs.append(gen.make_graph(f"g{g}", n, keys))
+        mb = int(rng.integers(1, 2000))
+        _case(f"random multi {c}: {len(graphs)} graphs, sum n={sum(g.n for g in graphs)}, max_batch {mb}")
+        pair = MultiPair(graphs, max_batch=mb * len(graphs), sweep_mode=int(rng.integers(2)))
+        if rng.random() < 0.5:
+            pair.gpu.set_tuning(int(rng.integers(1, 7)), int(rng.integers(1, 9)), int(rng.integers(2)))
+        for step in range(int(rng.integers(3, 7))):
+            batches, ops = [], []
+            for g, (n, keys, par) in enumerate(pair.local_state()):
+                op = int(rng.integers(2))
+                b = int(rng.integers(0, mb + 1))
+                if op == drsf.DRSF_INSERT:
+                    b = min(b, n * (n - 1) // 2 - len(keys))
+                    bt = gen.insert_batches(n, keys, 1, b, int(rng.integers(1 << 30)))[0] if b > 0 else \
+                        np.zeros((0, 2), np.int32)
+                else:
+                    b = min(b, len(keys))
+                    trees = int((par != np.arange(n)).sum())
+                    nt = max(min(trees, int(rng.integers(0, b + 1))), b - (len(keys) - trees))
+                    bt = gen.delete_batches(n, keys, par, 1, b, nt, int(rng.integers(1 << 30)))[0] if b > 0 else \
+                        np.zeros((0, 2), np.int32)
+                batches.append(bt)
+                ops.append(op)
+            bad = {int(rng.integers(len(graphs)))} if rng.random() < 0.3 else set()
+            bad = {g for g in bad if len(batches[g]) > 0 and len(batches[g]) < mb}
+            pair.step(batches, np.array(ops, np.int8), f"random multi {c} step {step}", bad=bad)
+        pair.gpu.close()
