@@ -114,3 +114,82 @@ def test_random_multi_graph_cases():
             bad = {g for g in bad if len(batches[g]) > 0 and len(batches[g]) < mb}
             pair.step(batches, np.array(ops, np.int8), f"random multi {c} step {step}", bad=bad)
         pair.gpu.close()
+
+
+def test_random_server_cases():
+    """The serving pattern: 24 seeded servers (1–5 tenants of random size,
+    20–120 requests with some invalid ones, Poisson or bursty arrivals, a
+    budget that sometimes holds only some tenants, and overlapped, serial or
+    coalescing mode).  Every request's status and digests match the oracle
+    applying the batches the server reports (one request each unless
+    coalescing merged them)."""
+    from test_gpu_server import _stream, digest
+    import oracle
+    drsf = _lib()
+    for c in range(24):
+        rng = np.random.default_rng(11000 + c)
+        graphs = []
+        for t in range(int(rng.integers(1, 6))):
+            # the request stream draws n non-edges and needs 1.5 non-tree
+            # edges per tree edge (m >= 3n leaves enough)
+            n = int(rng.integers(50, 6000))
+            m = int(rng.integers(3 * n, 5 * n + 1))
+            graphs.append(gen.make_graph(f"t{t}", n, gen.gnm(n, m, int(rng.integers(1 << 30)))))
+        nreq = int(rng.integers(20, 121))
+        bad = set(int(x) for x in rng.choice(nreq, size=int(rng.integers(0, 4)), replace=False))
+        reqs = _stream(graphs, nreq, int(rng.integers(1 << 20)), bad=bad)
+        if rng.random() < 0.5:  # bursts, so that requests wait together
+            reqs = [(t, e, op, (k // 10) * 2_000_000) for k, (t, e, op, _) in enumerate(reqs)]
+        mode = ("overlap", "serial", "coalesce")[c % 3]
+        fps = [drsf.drsf_footprint(g.n, len(g.col), None) for g in graphs]
+        budget = max(fps) + (sum(fps) if rng.random() < 0.6 else 0)
+        _case(f"random server {c}: {len(graphs)} tenants, {nreq} requests, bad {sorted(bad)}, {mode}, "
+              f"budget {'all' if budget > max(fps) else 'one at a time'}")
+        srv = drsf.Server(budget, max_batch=512, digests=True, serial=mode == "serial",
+                          coalesce=mode == "coalesce", sweep_mode=int(rng.integers(2)))
+        ids = [srv.admit(g.n, g.row_ptr, g.col, g.parent, arrive_ns=int(rng.integers(0, 3_000_000)))
+               for g in graphs]
+        rids = [srv.submit(ids[t], e, op, arrive_ns=a) for t, e, op, a in reqs]
+        for tid in ids:
+            srv.release(tid)
+        srv.start()
+        srv.wait_all()
+        res = [srv.result(r) for r in rids]
+        batch = [srv.batch(r) for r in rids]
+        srv.close()
+        pos = {r: k for k, r in enumerate(rids)}
+        groups = {}
+        for k, b in enumerate(batch):
+            groups.setdefault(b, []).append(k)
+        if mode != "coalesce":
+            assert all(len(v) == 1 for v in groups.values())
+        st = []
+        for g in graphs:
+            r = oracle.apply(g.n, g.keys, g.parent, np.zeros((0, 2), np.int32), oracle.DELETE)
+            st.append([g.keys, r.parent, r.label])
+        for b in sorted(groups, key=lambda x: pos[x]):
+            ks = groups[b]
+            t, op = reqs[ks[0]][0], reqs[ks[0]][2]
+            e = np.concatenate([reqs[k][1] for k in ks]).reshape(-1, 2)
+            keys, par, lab = st[t]
+            try:
+                r = oracle.apply(graphs[t].n, keys, par, e, oracle.INSERT if op == 0 else oracle.DELETE,
+                                 label=lab)
+            except oracle.OracleError:
+                assert len(ks) == 1 and res[ks[0]]["status"] == drsf.DRSF_E_BATCH, (c, b, ks, res[ks[0]])
+                continue
+            st[t] = [r.keys, r.parent, r.label]
+            dg = digest(r.parent, r.label)
+            for k in ks:
+                assert res[k]["status"] == drsf.DRSF_OK, (c, k, res[k])
+                assert res[k]["digest"] == dg, f"server {c}, request {k}: digest differs from the oracle"
+
+
+def test_random_static_rebuilds():
+    """The static rebuild on 40 seeded graphs (the four families, random
+    sizes): labels bit-exact, the forest valid by the oracle's checker and
+    breadth-first."""
+    from test_gpu_static import _run
+    for c in range(40):
+        rng = np.random.default_rng(13000 + c)
+        _run(_graph(rng, ("gnm", "rmat", "grid", "path")[c % 4]), f"random {c}")
