@@ -31,13 +31,23 @@ def _case(msg):
 
 
 class Pair:
-    """The GPU forest and the oracle state, stepped together."""
+    """The GPU forest and the oracle state, stepped together.  device=True
+    hands the graph, the forest and every batch over in device memory (the
+    benchmark's configuration: the first kernel reads the batch in place)."""
 
-    def __init__(self, g: gen.Graph, **kw):
+    def __init__(self, g: gen.Graph, device: bool = False, **kw):
         drsf = _lib()
         self.n = g.n
         self.keys = g.keys
-        self.gpu = drsf.Forest(g.n, g.row_ptr, g.col, g.parent, **kw)
+        self.device = device
+        if device:
+            import torch
+            self.dev = torch.device("cuda:0")
+            t = [torch.from_numpy(np.ascontiguousarray(x)).to(self.dev) for x in (g.row_ptr, g.col, g.parent)]
+            self.gpu = drsf.Forest(g.n, *t, inputs_on_device=True,
+                                   stream=torch.cuda.current_stream().cuda_stream, **kw)
+        else:
+            self.gpu = drsf.Forest(g.n, g.row_ptr, g.col, g.parent, **kw)
         # canonical starting point: the oracle roots each tree at its minimum
         r = oracle.apply(g.n, g.keys, g.parent, np.zeros((0, 2), np.int32), oracle.DELETE)
         self.parent, self.label = r.parent, r.label
@@ -60,7 +70,11 @@ class Pair:
         drsf = _lib()
         opc = oracle.INSERT if op == drsf.DRSF_INSERT else oracle.DELETE
         r = oracle.apply(self.n, self.keys, self.parent, batch, opc, label=self.label)
-        st = self.gpu.apply(batch, op)
+        if self.device:
+            import torch
+            st = self.gpu.apply(torch.from_numpy(np.ascontiguousarray(batch, np.int32)).to(self.dev), op)
+        else:
+            st = self.gpu.apply(batch, op)
         self.keys, self.parent, self.label = r.keys, r.parent, r.label
         self.check_equal(what)
         assert st["num_replacement"] == r.stats["n_repl"], (what, st, r.stats)
@@ -216,13 +230,13 @@ def test_deep_trees_path_and_grid():
     pair.gpu.close()
 
 
-@pytest.mark.parametrize("sweep_mode", [0, 1])
-def test_rmat_small(sweep_mode):
+@pytest.mark.parametrize("sweep_mode,device", [(0, False), (1, False), (0, True)])
+def test_rmat_small(sweep_mode, device):
     drsf = _lib()
-    _case(f"rmat16 sweep_mode={sweep_mode}")
+    _case(f"rmat16 sweep_mode={sweep_mode} device={device}")
     keys = gen.rmat(16, 16, 0.57, 0.19, 0.19, gen.seed(2, 7, gen.P_GRAPH))
     g = gen.make_graph("rmat16", 1 << 16, keys)
-    pair = Pair(g, sweep_mode=sweep_mode)
+    pair = Pair(g, device=device, sweep_mode=sweep_mode)
     for step in range(2):
         ins = gen.insert_batches(g.n, pair.keys, 1, 10000, gen.seed(2, 7 + step, gen.P_INSERT))[0]
         pair.step(ins, drsf.DRSF_INSERT, f"rmat insert {step}")
@@ -579,16 +593,17 @@ def test_determinism_snapshot_restore_export():
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("sweep_mode", [0, 1])
-def test_rmat22_full_size_step(sweep_mode):
+@pytest.mark.parametrize("sweep_mode,device", [(0, True), (1, False)])
+def test_rmat22_full_size_step(sweep_mode, device):
     """R-MAT scale 22 (the headline workload) at batch 1e5: one insert and one
-    delete step in the configuration the benchmark times, compared with the
-    oracle on the full parent and label arrays."""
+    delete step, compared with the oracle on the full parent and label
+    arrays; with the default scan and everything in device memory it is the
+    configuration the benchmark times."""
     drsf = _lib()
-    _case(f"rmat22 full sweep_mode={sweep_mode}")
+    _case(f"rmat22 full sweep_mode={sweep_mode} device={device}")
     keys = gen.rmat(22, 16, 0.57, 0.19, 0.19, gen.seed(2, 0, gen.P_GRAPH))
     g = gen.make_graph("rmat22", 1 << 22, keys)
-    pair = Pair(g, max_batch=1 << 17, sweep_mode=sweep_mode)
+    pair = Pair(g, device=device, max_batch=1 << 17, sweep_mode=sweep_mode)
     ins = gen.insert_batches(g.n, g.keys, 1, 100000, gen.seed(2, 0, gen.P_INSERT))[0]
     pair.step(ins, drsf.DRSF_INSERT, "rmat22 insert")
     dl = gen.delete_batches(g.n, g.keys, g.parent, 1, 100000, 50000, gen.seed(2, 0, gen.P_DELETE))[0]

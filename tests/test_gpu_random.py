@@ -4,10 +4,11 @@ Each case draws a graph family and size (G(n, m) up to 2·10^4 vertices, R-MAT
 scale 6–14, grids with edges removed, paths with chords), a batch capacity,
 the delete scan (per batch or whole store), the path reversal (per path or
 Euler tour), the replacement-edge method (hooking on every cross edge or on
-the supergraph), sometimes a small inserted-edge list (store rebuilds) and a
-random launch schedule, then alternates insert and delete batches of random
+the supergraph), sometimes a small inserted-edge list (store rebuilds), host
+or device-resident inputs and a random launch schedule, then alternates insert and delete batches of random
 sizes (deletes with a random share of tree edges).  Every batch: parent and
-label arrays bit-exact, checker pass, same replacement-edge count."""
+label arrays bit-exact, checker pass, same replacement-edge count.  Further
+tests draw random multi-graph contexts, servers and static rebuilds."""
 from __future__ import annotations
 
 import numpy as np
@@ -51,8 +52,9 @@ def test_random_cases(block):
                   replacement_mode=int(rng.random() < 0.25))
         if rng.random() < 0.3:
             kw["delta_capacity"] = int(rng.integers(mb, 3 * mb + 1))  # a batch always fits
-        _case(f"random {c}: {kind} n={g.n} m={g.m} {kw}")
-        pair = Pair(g, **kw)
+        device = bool(rng.random() < 0.3)
+        _case(f"random {c}: {kind} n={g.n} m={g.m} {kw} device={device}")
+        pair = Pair(g, device=device, **kw)
         if rng.random() < 0.5:
             pair.gpu.set_tuning(int(rng.integers(1, 7)), int(rng.integers(1, 9)), int(rng.integers(2)))
         for step in range(int(rng.integers(2, 8))):
