@@ -58,7 +58,8 @@ typedef enum {
     DRSF_E_BATCH = -4,    /* apply: invalid batch (self-loop, id out of range,
                              repeated edge, insert of an existing edge, delete of a
                              missing edge); nothing was changed */
-    DRSF_E_CAPACITY = -5, /* batch larger than drsf_opts.max_batch, or graph too large */
+    DRSF_E_CAPACITY = -5, /* batch larger than drsf_opts.max_batch, inserts beyond
+                             drsf_opts.delta_capacity in one batch, or graph too large */
     DRSF_E_DEVICE = -6,   /* HIP runtime error, or an internal bound was exceeded */
     DRSF_E_STATE = -7,    /* call not valid in the context's current state */
     DRSF_E_BUDGET = -8    /* server: the graph does not fit the memory budget */
@@ -165,16 +166,22 @@ int drsf_create(int32_t n, const int64_t *row_ptr, const int32_t *col, const int
  * Applies one batch (Algorithm 1): edges holds b pairs (u, v) interleaved,
  * int32[2b], in either orientation; op is DRSF_INSERT or DRSF_DELETE.
  * Blocks until the result is final on the device and fills *out (may be
- * NULL).  b == 0 is a no-op.  Errors: DRSF_E_BATCH (state unchanged),
- * DRSF_E_CAPACITY (b > max_batch), DRSF_E_ARG, DRSF_E_DEVICE.
+ * NULL).  b == 0 is a no-op.  With inputs_on_device the batch is read in
+ * place on the device (see drsf_apply_async).  Errors: DRSF_E_BATCH (state
+ * unchanged), DRSF_E_CAPACITY (b > max_batch, or more inserts than
+ * delta_capacity), DRSF_E_ARG, DRSF_E_DEVICE.
  */
 int drsf_apply(drsf_ctx *ctx, const int32_t *edges, int64_t b, int op, drsf_view *out);
 
 /*
  * Queues the same work as drsf_apply on the context's stream and returns
- * without waiting.  The batch is copied into the context before return.
- * Call drsf_wait before reading results or queueing host reads; device work
- * queued later on the same stream is ordered after it.
+ * without waiting.  A host batch is copied into the context before return.
+ * A device batch (inputs_on_device) is read in place by the update's first
+ * kernel: work queued later on the context's stream is ordered after that
+ * read, but any other writer of that memory (another stream, the host, a
+ * free that lets another stream reuse it) must wait for drsf_wait.  Call
+ * drsf_wait before reading results or queueing host reads; device work
+ * queued later on the same stream is ordered after the update.
  */
 int drsf_apply_async(drsf_ctx *ctx, const int32_t *edges, int64_t b, int op);
 
