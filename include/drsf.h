@@ -208,7 +208,10 @@ int drsf_wait(drsf_ctx *ctx, drsf_view *out);
  *
  * drsf_multi_apply(_async):
  *   edges    int32[2 * b_off[G]] global-id pairs, graph g's batch at
- *            [b_off[g], b_off[g + 1]) (host or device per inputs_on_device)
+ *            [b_off[g], b_off[g + 1]) (host or device per inputs_on_device;
+ *            a host batch is copied before return, a device batch by a copy
+ *            queued on the context's stream, with drsf_apply_async's rule
+ *            for other writers)
  *   b_off    host int64[G + 1], b_off[0] == 0, non-decreasing; b_off[G] <=
  *            max_batch
  *   op       host int8[G], DRSF_INSERT or DRSF_DELETE per graph
