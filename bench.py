@@ -583,7 +583,7 @@ def main():
         "k_orph_scan": (pd["orphan_scan"] - ev_del,
                         int(4 * sd["orphan_slots"] + g.n // 8 + 40 * sd["num_orphans"]),
                         "orphan scan: 4-B column per adjacency slot, the orphan bitmap "
-                        "(1 bit per vertex) once, one 40-B list entry per orphan (the rep of "
+                        "(1 bit per vertex) once, one 40-B list entry per orphan (the piece of "
                         "orphan neighbours, read only for them, is not counted)"),
     }
     if sd["scan_orphans"] < 0.5:

@@ -84,7 +84,7 @@ struct Dev {
     uint64_t *obits;         // [ceil(n/64)] vertex lies in a piece cut off from its old root
     // touched pieces (trees of F-hat incident to the batch), dense ids
     int32_t *tidx;           // [n] piece root vertex -> dense id, NONE when idle
-    int32_t *owner;          // [n] scratch for electing one registrant per piece
+    int32_t *owner;          // [n] scratch: one registrant per piece, then in a delete each orphan's piece
     uint8_t *pkeep;          // [pcap] piece holds its component's old root (delete)
     int32_t *prt;            // [pcap] dense id -> piece root vertex
     int32_t *pmin;           // [pcap] smallest vertex of the piece

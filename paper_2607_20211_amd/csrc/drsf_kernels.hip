@@ -906,8 +906,9 @@ __global__ __launch_bounds__(BLOCK) void k_orph_total(Dev d) {
 }
 
 // Compacted list of all orphans in vertex order (copied from the blocks'
-// staging with global prefixes), and for each range of OR_W slots the list
-// index of the orphan holding its first slot.
+// staging with global prefixes), each orphan's piece in owner[], and for
+// each range of OR_W slots the list index of the orphan holding its first
+// slot.
 __global__ __launch_bounds__(BLOCK) void k_orph_fill(Dev d) {
     if (*d.status || !d.ctl->has_del || !d.cnt[C_OMODE]) return;
     // FILL_LANES lanes per vertex block (blocks hold few orphans), so one
@@ -929,6 +930,7 @@ __global__ __launch_bounds__(BLOCK) void k_orph_fill(Dev d) {
             const int64_t idx = ob + i;
             o.pre += vb;
             d.olist[idx] = o;
+            d.owner[o.v] = o.pu;  // the orphan's piece, for the orphan scan
             const int64_t end = o.pre + o.du + o.dl + OR_PAD;
             for (int64_t w = (o.pre + OR_W - 1) / OR_W; w * OR_W < end; w++) d.rstart[w] = (int32_t)idx;
         }
@@ -942,11 +944,13 @@ __global__ __launch_bounds__(BLOCK) void k_orph_fill(Dev d) {
 // columns from the upper or lower run and tests the neighbour.  A neighbour
 // that is no orphan kept its old root, which is not the orphan's piece
 // root: the edge is a cross edge to the old root's piece (known per
-// orphan), so only orphan neighbours need their rep and piece gathered (the
-// orphan bitmap, one bit per vertex, mostly stays in L2; rep and the piece
-// table do not).  Parallel edges between two pieces close a cycle with the
-// lowest of them, on which they are the largest, so the lowest-key forest
-// holds none of them: the old-root edges of an orphan in a range are kept
+// orphan), so only orphan neighbours need their piece gathered, one load
+// from owner[], where the list fill left each orphan's piece (the orphan
+// bitmap, one bit per vertex, mostly stays in L2; owner[] does not).  Two
+// ends are in one piece iff their piece ids are equal.  Parallel edges
+// between two pieces close a cycle with the lowest of them, on which they
+// are the largest, so the lowest-key forest holds none of them: the
+// old-root edges of an orphan in a range are kept
 // as their lowest key alone, and the orphan-neighbour edges as the lowest
 // key of each run of equal piece pairs within a thread's slots.  Every cross
 // edge (u, v) also takes part in the first hooking round's selection for
@@ -1033,17 +1037,16 @@ __global__ __launch_bounds__(BLOCK) void k_orph_scan(Dev d) {
 #pragma unroll
                 for (int k = 0; k < OR_K; k++)
                     if (col[k] >= 0 && ((vw[k] >> (col[k] & 63)) & 1)) onb |= 1u << k;
-                int32_t rv[OR_K];
+                // the neighbour's piece: an orphan's from owner[] (one
+                // gather), else the old root's
+                int32_t pv[OR_K];
 #pragma unroll
-                for (int k = 0; k < OR_K; k++) rv[k] = (onb >> k & 1) ? d.rep[col[k]] : 0;
+                for (int k = 0; k < OR_K; k++) pv[k] = (onb >> k & 1) ? d.owner[col[k]] : s_o[oi[k]].pk;
                 uint32_t cross = 0;
 #pragma unroll
                 for (int k = 0; k < OR_K; k++)
-                    if (col[k] >= 0 && (!(onb >> k & 1) || rv[k] != s_o[oi[k]].ru)) cross |= 1u << k;
+                    if (col[k] >= 0 && (!(onb >> k & 1) || pv[k] != s_o[oi[k]].pu)) cross |= 1u << k;
                 const uint32_t xo = cross & onb, xk = cross & ~onb;  // to orphans / to old roots
-                int32_t pv[OR_K];
-#pragma unroll
-                for (int k = 0; k < OR_K; k++) pv[k] = (xo >> k & 1) ? d.tidx[rv[k]] : s_o[oi[k]].pk;
                 // count, and the runs of equal piece pairs among the edges to orphans
                 int runs = 0;
                 {
