@@ -1711,13 +1711,14 @@ __global__ __launch_bounds__(BLOCK) void k_reverse_all(Dev d) {
 // rep == label for the next update.
 __device__ void label_delete(const Dev &d, int64_t bid, int64_t nblk) {
     if (d.cnt[C_OMODE]) {
-        // the orphan list holds every orphan: relabel them, clear their
-        // bitmap words and their blocks' figures (idempotent stores)
+        // the orphan list holds every orphan with its piece (rep and the
+        // piece table are unchanged since root finding): relabel them, clear
+        // their bitmap words and their blocks' figures (idempotent stores)
         const int64_t no = (int64_t)d.cnt[C_NORPH];
         const int64_t stride = nblk * BLOCK;
         for (int64_t i = bid * BLOCK + threadIdx.x; i < no; i += stride) {
             const int32_t v = d.olist[i].v;
-            const int32_t p = d.tidx[d.rep[v]];
+            const int32_t p = d.olist[i].pu;
             if (p >= 0) {
                 const int32_t l = d.newlab[d.comp[p]];
                 d.label[v] = l;
