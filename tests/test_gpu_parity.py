@@ -33,7 +33,10 @@ def _case(msg):
 class Pair:
     """The GPU forest and the oracle state, stepped together.  device=True
     hands the graph, the forest and every batch over in device memory (the
-    benchmark's configuration: the first kernel reads the batch in place)."""
+    benchmark's configuration: the first kernel reads the batch in place),
+    produced on the stream the context queues its work on (a torch pool
+    stream, default priority), so that the copies and the library's reads
+    are ordered by the stream itself."""
 
     def __init__(self, g: gen.Graph, device: bool = False, **kw):
         drsf = _lib()
@@ -43,9 +46,10 @@ class Pair:
         if device:
             import torch
             self.dev = torch.device("cuda:0")
-            t = [torch.from_numpy(np.ascontiguousarray(x)).to(self.dev) for x in (g.row_ptr, g.col, g.parent)]
-            self.gpu = drsf.Forest(g.n, *t, inputs_on_device=True,
-                                   stream=torch.cuda.current_stream().cuda_stream, **kw)
+            self.stream = torch.cuda.Stream(self.dev)
+            with torch.cuda.stream(self.stream):
+                t = [torch.from_numpy(np.ascontiguousarray(x)).to(self.dev) for x in (g.row_ptr, g.col, g.parent)]
+            self.gpu = drsf.Forest(g.n, *t, inputs_on_device=True, stream=self.stream.cuda_stream, **kw)
         else:
             self.gpu = drsf.Forest(g.n, g.row_ptr, g.col, g.parent, **kw)
         # canonical starting point: the oracle roots each tree at its minimum
@@ -72,7 +76,9 @@ class Pair:
         r = oracle.apply(self.n, self.keys, self.parent, batch, opc, label=self.label)
         if self.device:
             import torch
-            st = self.gpu.apply(torch.from_numpy(np.ascontiguousarray(batch, np.int32)).to(self.dev), op)
+            with torch.cuda.stream(self.stream):
+                eb = torch.from_numpy(np.ascontiguousarray(batch, np.int32)).to(self.dev)
+            st = self.gpu.apply(eb, op)
         else:
             st = self.gpu.apply(batch, op)
         self.keys, self.parent, self.label = r.keys, r.parent, r.label
