@@ -31,8 +31,17 @@
  *   - outputs exposed through drsf_view are device memory owned by the
  *     context, valid until the next drsf_apply / drsf_restore / drsf_destroy
  *     on that context;
- *   - all device work is queued on drsf_opts.stream (NULL: a stream owned by
- *     the context);
+ *   - all device work, create's included, is queued on drsf_opts.stream.
+ *     NULL: a stream owned by the context, created blocking, so that its
+ *     work is ordered after work queued earlier on the null (legacy
+ *     default) stream — torch's default stream is that stream;
+ *   - device inputs (inputs_on_device) must be fully written before the
+ *     call's first read of them, which is queued on that stream: write them
+ *     with work queued earlier on the same stream (or, for a context-owned
+ *     stream, on the null stream), or finish their writes (synchronise the
+ *     writing stream, or the device) before the call.  Writes on any other
+ *     stream are not waited for.  The library never writes caller inputs;
+ *     when they may be written again is stated per call;
  *   - every call returns a drsf_status; on failure drsf_last_error() gives a
  *     message, and a rejected batch leaves the state unchanged;
  *   - one context must not be used from two host threads at once; distinct
@@ -110,6 +119,21 @@ typedef struct {
                                 kernel by kernel with two host reads of sizes;
                                 needs about 24 bytes per cross-edge slot more
                                 device memory.  Results are identical. */
+    /* Device allocator hooks, so that a caller can route the context's device
+     * memory through its own allocator (torch's caching allocator, a pool):
+     * when dev_alloc is non-NULL every device allocation of the context and
+     * of its snapshots is dev_alloc(bytes, alloc_user) and is released with
+     * dev_free(ptr, alloc_user) (dev_free must then be non-NULL).  dev_alloc
+     * returns device memory on the context's device, aligned to at least
+     * 256 bytes, or NULL on failure, which the calling function reports as
+     * DRSF_E_NOMEM after releasing what it had allocated.  A block is
+     * released only when no queued work of the context uses it any more
+     * (the context's stream has been synchronised), so a stream-ordered
+     * allocator may reuse it at once.  Pinned host staging memory is always
+     * allocated by the library itself.  NULL (default): hipMalloc/hipFree. */
+    void *(*dev_alloc)(size_t bytes, void *alloc_user);
+    void (*dev_free)(void *ptr, void *alloc_user);
+    void *alloc_user;
 } drsf_opts;
 
 /* Fills *opts with the defaults described above. */
@@ -156,6 +180,8 @@ typedef struct {
  *            precondition the insert path of Algorithm 1 relies on
  *   opts     may be NULL (defaults)
  * Trees whose root is not their smallest vertex are re-rooted there.
+ * Device inputs are read on the context's stream (ordering rule above) and
+ * are no longer needed when drsf_create returns.
  * Errors: DRSF_E_ARG (bad CSR), DRSF_E_FOREST (parent invalid; checked when
  * validate_forest is set), DRSF_E_NOMEM, DRSF_E_DEVICE.  *out is NULL on error.
  */

@@ -20,6 +20,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/drsf.h"
@@ -48,6 +49,7 @@ int ceil_log2(int64_t x) {
 }  // namespace
 
 struct drsf_snapshot {
+    drsf_opts opts{};  // allocator hooks of the context it was taken from
     int32_t n = 0;
     int64_t eb = 0, dcap = 0, ndelta_bound = 0, m_live = 0, rebuilds = 0;
     uint64_t dhmask = 0;
@@ -179,6 +181,7 @@ struct drsf_ctx {
     std::vector<size_t> alloc_bytes;
     int64_t bytes = 0, peak_bytes = 0;  // device bytes held now / at most
     int64_t rebuilds = 0;               // store rebuilds so far
+    bool broken = false;                // a store rebuild failed after dropping the old store
 };
 
 namespace {
@@ -200,14 +203,34 @@ int fail(drsf_ctx *c, int code, const char *fmt, ...) {
             return fail((ctx), DRSF_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_));  \
     } while (0)
 
-template <class T>
-int dalloc(drsf_ctx *c, T **p, int64_t count) {
-    const size_t bytes = sizeof(T) * (size_t)(count > 0 ? count : 1);
+// Device memory through the caller's hooks when given, else hipMalloc.
+void *raw_dalloc(const drsf_opts &o, size_t bytes) {
+    if (o.dev_alloc) {
+        void *q = o.dev_alloc(bytes, o.alloc_user);
+        if (q && ((uintptr_t)q & 255u)) {  // the kernels' vector loads need aligned arrays
+            o.dev_free(q, o.alloc_user);
+            q = nullptr;
+        }
+        return q;
+    }
     void *q = nullptr;
     if (hipMalloc(&q, bytes) != hipSuccess) {
         (void)hipGetLastError();
-        return fail(c, DRSF_E_NOMEM, "device allocation of %zu bytes failed", bytes);
+        return nullptr;
     }
+    return q;
+}
+void raw_dfree(const drsf_opts &o, void *p) {
+    if (!p) return;
+    if (o.dev_alloc) o.dev_free(p, o.alloc_user);
+    else (void)hipFree(p);
+}
+
+template <class T>
+int dalloc(drsf_ctx *c, T **p, int64_t count) {
+    const size_t bytes = sizeof(T) * (size_t)(count > 0 ? count : 1);
+    void *q = raw_dalloc(c->opts, bytes);
+    if (!q) return fail(c, DRSF_E_NOMEM, "device allocation of %zu bytes failed", bytes);
     c->allocs.push_back(q);
     c->alloc_bytes.push_back(bytes);
     c->bytes += (int64_t)bytes;
@@ -235,7 +258,7 @@ void dfree(drsf_ctx *c, void *p) {
         c->alloc_bytes.erase(c->alloc_bytes.begin() + (std::ptrdiff_t)k);
         c->allocs.erase(it);
     }
-    (void)hipFree(p);
+    raw_dfree(c->opts, p);
 }
 
 Dev make_dev(drsf_ctx *c) {
@@ -441,7 +464,7 @@ void destroy_ctx(drsf_ctx *c) {
         if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
         if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
     }
-    for (void *p : c->allocs) (void)hipFree(p);
+    for (void *p : c->allocs) raw_dfree(c->opts, p);
     c->allocs.clear();
     void *hosts[] = {c->h_edges, c->h_bop, c->h_bgid, c->h_lists, c->h_ctl, c->h_ret};
     for (void *p : hosts)
@@ -595,8 +618,8 @@ int rebuild_store(drsf_ctx *c) {
     int rc;
     hipStream_t s = c->stream;
     const int32_t n = c->n;
+    HIPCHK(c, hipMemcpyAsync(c->h_ret, c->cnt + C_NDELTA, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
-    HIPCHK(c, hipMemcpy(c->h_ret, c->cnt + C_NDELTA, sizeof(unsigned long long), hipMemcpyDeviceToHost));
     const int64_t nd = (int64_t)c->h_ret[0];
     const int64_t pcap2 = 2 * nd + 2;
     uint64_t *pairs = nullptr, *sorted = nullptr;
@@ -606,20 +629,33 @@ int rebuild_store(drsf_ctx *c) {
     int64_t *rowp = nullptr;
     int32_t *col = nullptr;
     const size_t sbytes = sort_u64_tmp_bytes(pcap2) + 256;
+    // temporaries are released on every return; the old store is kept until
+    // the merged CSR exists, so a failure before that leaves the context as
+    // it was
+    auto release = [&](int code) {
+        for (void *p : {(void *)pairs, (void *)sorted, (void *)npairs, (void *)stmp, (void *)ddeg, (void *)dstart,
+                        (void *)bdeg, (void *)rowp32, (void *)ctmp, (void *)rowp, (void *)col})
+            dfree(c, p);
+        return code;
+    };
     if ((rc = dalloc(c, &pairs, pcap2)) || (rc = dalloc(c, &sorted, pcap2)) || (rc = dalloc(c, &npairs, 2)) ||
         (rc = dalloc(c, &stmp, (int64_t)sbytes)) || (rc = dalloc(c, &ddeg, n)) ||
         (rc = dalloc(c, &dstart, (int64_t)n + 1)) || (rc = dalloc(c, &bdeg, n)) ||
         (rc = dalloc(c, &rowp32, (int64_t)n + 1)) || (rc = dalloc(c, &rowp, (int64_t)n + 1)) ||
-        (rc = dalloc(c, &ctmp, (int64_t)scan_tmp_bytes(n) + 64)))
-        return rc;
+        (rc = dalloc(c, &ctmp, (int64_t)scan_tmp_bytes(n) + 64))) {
+        (void)hipStreamSynchronize(s);
+        return release(rc);
+    }
     dtot = npairs + 1;
     launch_fill_u64(npairs, 2, 0, s);
     launch_rb_pairs(c->dkey, c->cnt + C_NDELTA, pairs, npairs, pcap2, s);
     HIPCHK(c, hipMemcpyAsync(c->h_ret, npairs, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     const int64_t np = (int64_t)c->h_ret[0];
-    if (np > 0 && launch_sort_u64(pairs, sorted, np, stmp, sbytes, s) != 0)
-        return fail(c, DRSF_E_DEVICE, "sort failed during the store rebuild");
+    if (np > 0 && launch_sort_u64(pairs, sorted, np, stmp, sbytes, s) != 0) {
+        (void)hipStreamSynchronize(s);
+        return release(fail(c, DRSF_E_DEVICE, "sort failed during the store rebuild"));
+    }
     launch_fill_i32(reinterpret_cast<int32_t *>(ddeg), n, 0, s);
     launch_rb_pair_deg(sorted, npairs, ddeg, pcap2, s);
     launch_scan_u32(ddeg, dstart, dtot, n, ctmp, s);
@@ -630,15 +666,19 @@ int rebuild_store(drsf_ctx *c) {
     HIPCHK(c, hipStreamSynchronize(s));
     const int64_t nnz = (int64_t)c->h_ret[0];
     if (nnz != 2 * c->m_live)
-        return fail(c, DRSF_E_DEVICE, "store rebuild counted %lld entries, expected %lld", (long long)nnz,
-                    (long long)(2 * c->m_live));
-    if ((rc = dalloc(c, &col, nnz))) return rc;
+        return release(fail(c, DRSF_E_DEVICE, "store rebuild counted %lld entries, expected %lld",
+                            (long long)nnz, (long long)(2 * c->m_live)));
+    if ((rc = dalloc(c, &col, nnz))) return release(rc);
     launch_u32_to_i64(rowp32, rowp, (int64_t)n + 1, s);
     launch_rb_fill(n, c->bptr, c->bcol, c->lptr, c->lcol, sorted, dstart, ddeg, rowp, col, s);
-    HIPCHK(c, hipStreamSynchronize(s));
+    if (hipStreamSynchronize(s) != hipSuccess)
+        return release(fail(c, DRSF_E_DEVICE, "store rebuild: %s", hipGetErrorString(hipGetLastError())));
     for (void *p : {(void *)pairs, (void *)sorted, (void *)npairs, (void *)stmp, (void *)ddeg, (void *)dstart,
                     (void *)bdeg, (void *)rowp32, (void *)ctmp})
         dfree(c, p);
+    // past this point a failure leaves no store: the context only answers
+    // reads of its forest (parent, label) until destroyed
+    c->broken = true;
     for (void *p : {(void *)c->bptr, (void *)c->bcol, (void *)c->lptr, (void *)c->lcol, (void *)c->twin,
                     (void *)c->ltwin, (void *)c->zrow, (void *)c->zptr, (void *)c->tile_k})
         dfree(c, p);
@@ -657,6 +697,7 @@ int rebuild_store(drsf_ctx *c) {
     c->ndelta_bound = 0;
     c->rebuilds++;
     HIPCHK(c, hipStreamSynchronize(s));
+    c->broken = false;
     for (int k = 0; k < 4; k++) {
         if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
         if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
@@ -953,6 +994,10 @@ static int create_impl(int32_t G, const int32_t *n_off, int32_t n, const int64_t
         fail(c, DRSF_E_ARG, "replacement_mode must be 0 or 1");
         return bail(DRSF_E_ARG);
     }
+    if (c->opts.dev_alloc && !c->opts.dev_free) {
+        fail(c, DRSF_E_ARG, "dev_alloc needs dev_free");
+        return bail(DRSF_E_ARG);
+    }
     {
         const hipError_t e = hipGetDevice(&c->dev);
         if (e != hipSuccess) {
@@ -963,7 +1008,10 @@ static int create_impl(int32_t G, const int32_t *n_off, int32_t n, const int64_t
     if (c->opts.stream) {
         c->stream = (hipStream_t)c->opts.stream;
     } else {
-        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+        // a blocking stream: its work is ordered after work queued earlier
+        // on the null stream, where a caller without a stream of its own
+        // (torch's default stream is the null stream) produces device inputs
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamDefault) != hipSuccess) {
             fail(c, DRSF_E_DEVICE, "stream creation failed");
             return bail(DRSF_E_DEVICE);
         }
@@ -972,19 +1020,22 @@ static int create_impl(int32_t G, const int32_t *n_off, int32_t n, const int64_t
     c->ret_words = 1 + C_TOTAL + (G + 1) / 2;
     if ((rc = halloc(c, &c->h_ret, c->ret_words + 8))) return bail(rc);
     c->h_gstat = reinterpret_cast<int32_t *>(c->h_ret + 1 + C_TOTAL);
-    for (auto &e : c->ev)
-        if (hipEventCreate(&e) != hipSuccess) {
-            fail(c, DRSF_E_DEVICE, "event creation failed");
-            return bail(DRSF_E_DEVICE);
-        }
+    if (c->opts.profile)  // phase events exist only for the profiled launch path
+        for (auto &e : c->ev)
+            if (hipEventCreate(&e) != hipSuccess) {
+                fail(c, DRSF_E_DEVICE, "event creation failed");
+                return bail(DRSF_E_DEVICE);
+            }
     if ((rc = dalloc(c, &c->ctlmem, c->ret_words))) return bail(rc);
     c->status = reinterpret_cast<int32_t *>(c->ctlmem);
     c->cnt = c->ctlmem + 1;
     c->gstat = reinterpret_cast<int32_t *>(c->ctlmem + 1 + C_TOTAL);
     launch_fill_u64(c->ctlmem, c->ret_words, 0, c->stream);
     if ((rc = dalloc(c, &c->goff, (int64_t)G + 1))) return bail(rc);
-    if (hipMemcpy(c->goff, c->goff_h.data(), sizeof(int32_t) * ((size_t)G + 1), hipMemcpyHostToDevice) !=
-        hipSuccess) {
+    // every copy of create runs on the context's stream, after the work the
+    // caller queued there (or, for a context-owned stream, on the null stream)
+    if (hipMemcpyAsync(c->goff, c->goff_h.data(), sizeof(int32_t) * ((size_t)G + 1), hipMemcpyHostToDevice,
+                       c->stream) != hipSuccess) {
         fail(c, DRSF_E_DEVICE, "cannot copy graph offsets");
         return bail(DRSF_E_DEVICE);
     }
@@ -994,12 +1045,17 @@ static int create_impl(int32_t G, const int32_t *n_off, int32_t n, const int64_t
     const int64_t *rp = row_ptr;
     if (c->opts.inputs_on_device) {
         hrow.resize((size_t)n + 1);
-        if (hipMemcpy(hrow.data(), row_ptr, sizeof(int64_t) * hrow.size(), hipMemcpyDeviceToHost) !=
-            hipSuccess) {
+        if (hipMemcpyAsync(hrow.data(), row_ptr, sizeof(int64_t) * hrow.size(), hipMemcpyDeviceToHost,
+                           c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess) {
+            (void)hipGetLastError();
             fail(c, DRSF_E_ARG, "cannot read row_ptr");
             return bail(DRSF_E_ARG);
         }
         rp = hrow.data();
+    } else if (hipStreamSynchronize(c->stream) != hipSuccess) {  // goff's pageable source
+        fail(c, DRSF_E_DEVICE, "cannot copy graph offsets");
+        return bail(DRSF_E_DEVICE);
     }
     if (rp[0] != 0) {
         fail(c, DRSF_E_ARG, "row_ptr[0] must be 0");
@@ -1114,10 +1170,17 @@ int drsf_set_tuning(drsf_ctx *c, int rounds_queued, int levels_queued, int sweep
     return DRSF_OK;
 }
 
+static int check_usable(drsf_ctx *c) {
+    return c->broken ? fail(c, DRSF_E_STATE, "a failed store rebuild left the context without its graph; "
+                                              "only its forest can be read")
+                     : DRSF_OK;
+}
+
 int drsf_apply_async(drsf_ctx *c, const int32_t *edges, int64_t b, int op) {
     if (!c) return DRSF_E_ARG;
     int rc;
     if ((rc = finish_pending(c))) return rc;
+    if ((rc = check_usable(c))) return rc;
     if (c->ngraph != 1) return fail(c, DRSF_E_STATE, "the context holds several graphs: use drsf_multi_apply");
     if (op != DRSF_INSERT && op != DRSF_DELETE) return fail(c, DRSF_E_ARG, "op must be insert or delete");
     if (b < 0 || (b > 0 && !edges)) return fail(c, DRSF_E_ARG, "bad batch");
@@ -1164,6 +1227,7 @@ int drsf_multi_apply_async(drsf_ctx *c, const int32_t *edges, const int64_t *b_o
     if (!c) return DRSF_E_ARG;
     int rc;
     if ((rc = finish_pending(c))) return rc;
+    if ((rc = check_usable(c))) return rc;
     if (!b_off || !op) return fail(c, DRSF_E_ARG, "b_off and op must be non-NULL");
     const int32_t G = c->ngraph;
     const int64_t b = b_off[G];
@@ -1408,6 +1472,7 @@ int drsf_export_edges(drsf_ctx *c, uint64_t *keys, int64_t capacity, int64_t *m_
     if (!c || !keys || !m_out) return DRSF_E_ARG;
     int rc = finish_pending(c);
     if (rc) return rc;
+    if ((rc = check_usable(c))) return rc;
     std::vector<uint32_t> bptr((size_t)c->n + 1);
     std::vector<int32_t> bcol((size_t)c->eb);
     unsigned long long nd = 0;
@@ -1447,20 +1512,22 @@ int drsf_snapshot_take(drsf_ctx *c, drsf_snapshot **out) {
     if (!c || !out) return DRSF_E_ARG;
     int rc = finish_pending(c);
     if (rc) return rc;
+    if ((rc = check_usable(c))) return rc;
     drsf_snapshot *s = new drsf_snapshot();
     s->n = c->n; s->eb = c->eb; s->dcap = c->dcap; s->dhmask = c->dhmask;
     s->ndelta_bound = c->ndelta_bound; s->m_live = c->m_live; s->rebuilds = c->rebuilds;
     s->gm = c->gm_h;
     const size_t dh = (size_t)c->dhmask + 1;
-    const bool ok = hipMalloc(&s->parent, 4 * (size_t)c->n) == hipSuccess &&
-                    hipMalloc(&s->label, 4 * (size_t)c->n) == hipSuccess &&
-                    hipMalloc(&s->bcol, 4 * (size_t)std::max<int64_t>(c->eb, 1)) == hipSuccess &&
-                    hipMalloc(&s->lcol, 4 * (size_t)std::max<int64_t>(c->eb, 1)) == hipSuccess &&
-                    hipMalloc(&s->dkey, 8 * (size_t)c->dcap) == hipSuccess &&
-                    hipMalloc(&s->dhash, 8 * dh) == hipSuccess &&
-                    hipMalloc(&s->dhpos, 4 * dh) == hipSuccess;
+    s->opts = c->opts;
+    auto get = [&](auto **p, size_t bytes) {
+        *p = static_cast<std::remove_reference_t<decltype(**p)> *>(raw_dalloc(s->opts, bytes));
+        return *p != nullptr;
+    };
+    const bool ok = get(&s->parent, 4 * (size_t)c->n) && get(&s->label, 4 * (size_t)c->n) &&
+                    get(&s->bcol, 4 * (size_t)std::max<int64_t>(c->eb, 1)) &&
+                    get(&s->lcol, 4 * (size_t)std::max<int64_t>(c->eb, 1)) &&
+                    get(&s->dkey, 8 * (size_t)c->dcap) && get(&s->dhash, 8 * dh) && get(&s->dhpos, 4 * dh);
     if (!ok) {
-        (void)hipGetLastError();
         drsf_snapshot_free(s);
         return fail(c, DRSF_E_NOMEM, "snapshot allocation failed");
     }
@@ -1483,6 +1550,7 @@ int drsf_snapshot_restore(drsf_ctx *c, const drsf_snapshot *s) {
     if (!c || !s) return DRSF_E_ARG;
     int rc = finish_pending(c);
     if (rc) return rc;
+    if ((rc = check_usable(c))) return rc;
     if (s->n != c->n || s->eb != c->eb || s->dcap != c->dcap || s->dhmask != c->dhmask ||
         s->gm.size() != c->gm_h.size() || s->rebuilds != c->rebuilds)
         return fail(c, DRSF_E_STATE, "snapshot does not match the context's layout (taken before a "
@@ -1509,13 +1577,9 @@ int drsf_snapshot_restore(drsf_ctx *c, const drsf_snapshot *s) {
 
 void drsf_snapshot_free(drsf_snapshot *s) {
     if (!s) return;
-    (void)hipFree(s->parent);
-    (void)hipFree(s->label);
-    (void)hipFree(s->bcol);
-    (void)hipFree(s->lcol);
-    (void)hipFree(s->dkey);
-    (void)hipFree(s->dhash);
-    (void)hipFree(s->dhpos);
+    for (void *p : {(void *)s->parent, (void *)s->label, (void *)s->bcol, (void *)s->lcol, (void *)s->dkey,
+                    (void *)s->dhash, (void *)s->dhpos})
+        raw_dfree(s->opts, p);
     delete s;
 }
 

@@ -39,7 +39,15 @@ class drsf_opts(ctypes.Structure):
                 ("rounds_queued", ctypes.c_int),
                 ("levels_queued", ctypes.c_int),
                 ("reverse_mode", ctypes.c_int),
-                ("replacement_mode", ctypes.c_int)]
+                ("replacement_mode", ctypes.c_int),
+                ("dev_alloc", ctypes.c_void_p),
+                ("dev_free", ctypes.c_void_p),
+                ("alloc_user", ctypes.c_void_p)]
+
+
+# device allocator hooks of drsf_opts
+DEV_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+DEV_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class drsf_view(ctypes.Structure):
@@ -185,6 +193,106 @@ def _ptr(x):
     if hasattr(x, "data_ptr"):
         return x.data_ptr()
     return x.ctypes.data
+
+
+_TORCH_DTYPE_NAMES = {np.dtype(np.int8): "torch.int8", np.dtype(np.int32): "torch.int32",
+                      np.dtype(np.int64): "torch.int64"}
+
+
+def _arr(x, dtype, on_device: bool, what: str, count: int | None = None):
+    """Checks that an input is what the library will read through its
+    pointer — the element type, C-contiguous memory, at least `count`
+    elements, and host memory (numpy array, CPU tensor) for a context whose
+    inputs are host memory or a GPU tensor for one whose inputs are device
+    memory — and returns the pointer; raises DrsfError (DRSF_E_ARG) before
+    any library call otherwise.  Nothing is converted."""
+    dtype = np.dtype(dtype)
+    if hasattr(x, "data_ptr") and hasattr(x, "is_cuda"):  # torch tensor
+        if str(x.dtype) != _TORCH_DTYPE_NAMES[dtype]:
+            raise DrsfError(DRSF_E_ARG, f"{what}: dtype {x.dtype}, expected {_TORCH_DTYPE_NAMES[dtype]}")
+        if not x.is_contiguous():
+            raise DrsfError(DRSF_E_ARG, f"{what}: tensor is not contiguous")
+        if bool(x.is_cuda) != bool(on_device):
+            raise DrsfError(DRSF_E_ARG, f"{what}: a {'GPU' if x.is_cuda else 'CPU'} tensor given to a context "
+                                        f"whose inputs are {'device' if on_device else 'host'} memory")
+        size = x.numel()
+    elif isinstance(x, np.ndarray):
+        if on_device:
+            raise DrsfError(DRSF_E_ARG, f"{what}: a host (numpy) array given to a context whose inputs are "
+                                        "device memory")
+        if x.dtype != dtype:
+            raise DrsfError(DRSF_E_ARG, f"{what}: dtype {x.dtype}, expected {dtype}")
+        if not x.flags.c_contiguous:
+            raise DrsfError(DRSF_E_ARG, f"{what}: array is not C-contiguous")
+        size = x.size
+    else:
+        raise DrsfError(DRSF_E_ARG, f"{what}: expected a numpy array or a torch tensor, got {type(x).__name__}")
+    if count is not None and size < count:
+        raise DrsfError(DRSF_E_ARG, f"{what}: {size} elements, needs {count}")
+    return x.data_ptr() if hasattr(x, "data_ptr") else x.ctypes.data
+
+
+def _host_input(x, dtype):
+    """Host-memory input of a host-input context: numpy arrays are converted
+    (values, not bytes) to the dtype the library reads; tensors pass as they
+    are and are checked by _arr."""
+    if isinstance(x, np.ndarray) or isinstance(x, (list, tuple)):
+        return np.ascontiguousarray(x, dtype=dtype)
+    return x
+
+
+def _batch(x, on_device: bool):
+    """(array, b) of a batch of edge pairs: numpy input of a host-input
+    context is converted to int32 pairs; anything else must already be an
+    int32 array of 2b entries."""
+    if not on_device and (isinstance(x, np.ndarray) or isinstance(x, (list, tuple))):
+        x = np.ascontiguousarray(x, dtype=np.int32).reshape(-1, 2)
+    size = x.numel() if hasattr(x, "numel") else getattr(x, "size", 0)
+    if size % 2:
+        raise DrsfError(DRSF_E_ARG, f"edges: {size} entries, expected pairs")
+    _arr(x, np.int32, on_device, "edges")
+    return x, size // 2
+
+
+class TorchAllocator:
+    """drsf_opts allocator hooks that take the context's device memory from
+    torch's caching allocator (torch.cuda.caching_allocator_alloc / _delete),
+    optionally failing every allocation after the first `limit` (to exercise
+    DRSF_E_NOMEM).  Counts live blocks and bytes.  Must outlive the context
+    and its snapshots."""
+
+    def __init__(self, limit: int | None = None):
+        self.limit = limit
+        self.calls = 0
+        self.live = {}
+        self._alloc = DEV_ALLOC_FN(self._do_alloc)
+        self._free = DEV_FREE_FN(self._do_free)
+
+    def _do_alloc(self, nbytes, user):
+        try:
+            self.calls += 1
+            if self.limit is not None and self.calls > self.limit:
+                return None
+            import torch
+            p = int(torch.cuda.caching_allocator_alloc(int(nbytes)))
+            self.live[p] = int(nbytes)
+            return p
+        except Exception:
+            return None
+
+    def _do_free(self, p, user):
+        try:
+            import torch
+            if p in self.live:
+                del self.live[p]
+                torch.cuda.caching_allocator_delete(int(p))
+        except Exception:
+            pass
+
+    def install(self, o: drsf_opts) -> None:
+        o.dev_alloc = ctypes.cast(self._alloc, ctypes.c_void_p)
+        o.dev_free = ctypes.cast(self._free, ctypes.c_void_p)
+        o.alloc_user = None
 
 
 def _check(rc: int, ctx=None):
@@ -343,11 +451,23 @@ def drsf_version() -> str:
 class Forest:
     """A graph and its rooted spanning forest resident on the GPU."""
 
+    ctx = None
+
     def __init__(self, n: int, row_ptr, col, parent, *, max_batch: int = 1 << 20,
                  stream=None, inputs_on_device: bool = False, validate: bool = True,
                  profile: bool = False, delta_capacity: int = 0, sweep_mode: int = 0,
                  rounds_queued: int = 0, levels_queued: int = 0, reverse_mode: int = 0,
-                 replacement_mode: int = 0):
+                 replacement_mode: int = 0, allocator: TorchAllocator | None = None):
+        self.on_device = bool(inputs_on_device)
+        if not self.on_device:
+            row_ptr = _host_input(row_ptr, np.int64)
+            col = _host_input(col, np.int32)
+            parent = _host_input(parent, np.int32)
+        self.n = n
+        _arr(row_ptr, np.int64, self.on_device, "row_ptr", n + 1)
+        _arr(col, np.int32, self.on_device, "col",
+             None if self.on_device else int(np.asarray(row_ptr)[n]) if n >= 0 else None)
+        _arr(parent, np.int32, self.on_device, "parent", n)
         o = drsf_default_opts()
         o.max_batch = max_batch
         o.inputs_on_device = int(inputs_on_device)
@@ -361,34 +481,28 @@ class Forest:
         o.replacement_mode = replacement_mode
         if stream is not None:
             o.stream = stream
-        if not inputs_on_device:
-            row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
-            col = np.ascontiguousarray(col, dtype=np.int32)
-            parent = np.ascontiguousarray(parent, dtype=np.int32)
-        self.n = n
+        self.allocator = allocator
+        if allocator is not None:
+            allocator.install(o)
         self._keep = (row_ptr, col, parent)
         self.ctx = drsf_create(n, row_ptr, col, parent, o)
         self._keep = None
 
     def apply(self, edges, op: int) -> dict:
-        if hasattr(edges, "data_ptr"):
-            b = edges.numel() // 2
-        else:
-            edges = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
-            b = edges.shape[0]
+        edges, b = _batch(edges, self.on_device)
         v = drsf_apply(self.ctx, edges, b, op)
         return self._stats(v)
 
     def apply_async(self, edges, op: int) -> None:
-        if hasattr(edges, "data_ptr"):
-            b = edges.numel() // 2
-        else:
-            edges = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
-            b = edges.shape[0]
+        edges, b = _batch(edges, self.on_device)
+        self._pending_edges = edges
         drsf_apply_async(self.ctx, edges, b, op)
 
     def wait(self) -> dict:
-        return self._stats(drsf_wait(self.ctx))
+        try:
+            return self._stats(drsf_wait(self.ctx))
+        finally:
+            self._pending_edges = None
 
     @staticmethod
     def _stats(v: drsf_view) -> dict:
@@ -450,7 +564,18 @@ class MultiForest(Forest):
                  stream=None, inputs_on_device: bool = False, validate: bool = True,
                  profile: bool = False, delta_capacity: int = 0, sweep_mode: int = 0,
                  rounds_queued: int = 0, levels_queued: int = 0, reverse_mode: int = 0,
-                 replacement_mode: int = 0):
+                 replacement_mode: int = 0, allocator: TorchAllocator | None = None):
+        self.on_device = bool(inputs_on_device)
+        if not self.on_device:
+            row_ptr = _host_input(row_ptr, np.int64)
+            col = _host_input(col, np.int32)
+            parent = _host_input(parent, np.int32)
+        self.n_off = np.ascontiguousarray(n_off, dtype=np.int32)
+        self.G = len(self.n_off) - 1
+        self.n = int(self.n_off[-1])
+        _arr(row_ptr, np.int64, self.on_device, "row_ptr", self.n + 1)
+        _arr(col, np.int32, self.on_device, "col", None if self.on_device else int(np.asarray(row_ptr)[self.n]))
+        _arr(parent, np.int32, self.on_device, "parent", self.n)
         o = drsf_default_opts()
         o.max_batch = max_batch
         o.inputs_on_device = int(inputs_on_device)
@@ -460,26 +585,32 @@ class MultiForest(Forest):
         o.sweep_mode = sweep_mode
         o.rounds_queued = rounds_queued
         o.levels_queued = levels_queued
+        o.reverse_mode = reverse_mode
+        o.replacement_mode = replacement_mode
         if stream is not None:
             o.stream = stream
-        if not inputs_on_device:
-            row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
-            col = np.ascontiguousarray(col, dtype=np.int32)
-            parent = np.ascontiguousarray(parent, dtype=np.int32)
-        self.n_off = np.ascontiguousarray(n_off, dtype=np.int32)
-        self.G = len(self.n_off) - 1
-        self.n = int(self.n_off[-1])
+        self.allocator = allocator
+        if allocator is not None:
+            allocator.install(o)
         self.ctx = drsf_multi_create(self.G, self.n_off, row_ptr, col, parent, o)
+
+    def _multi_args(self, edges, b_off, op):
+        edges, b = _batch(edges, self.on_device)
+        b_off = np.ascontiguousarray(b_off, dtype=np.int64)
+        op = np.ascontiguousarray(op, dtype=np.int8)
+        if len(b_off) != self.G + 1 or len(op) != self.G:
+            raise DrsfError(DRSF_E_ARG, f"b_off needs {self.G + 1} entries and op {self.G}")
+        if b_off[-1] > b:
+            raise DrsfError(DRSF_E_ARG, f"b_off[G] = {b_off[-1]} but edges hold {b} pairs")
+        return edges, b_off, op
 
     def apply_multi(self, edges, b_off, op) -> np.ndarray:
         """Per-graph status (DRSF_OK or DRSF_E_BATCH)."""
-        if not hasattr(edges, "data_ptr"):
-            edges = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+        edges, b_off, op = self._multi_args(edges, b_off, op)
         return drsf_multi_apply(self.ctx, edges, b_off, op)
 
     def apply_multi_async(self, edges, b_off, op) -> None:
-        if not hasattr(edges, "data_ptr"):
-            edges = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+        edges, b_off, op = self._multi_args(edges, b_off, op)
         self._pending_edges = edges
         drsf_multi_apply_async(self.ctx, edges, b_off, op)
 
