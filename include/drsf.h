@@ -106,9 +106,8 @@ typedef struct {
     int reverse_mode;        /* path reversal: 0 (default) one thread walks each
                                 path; 1: Euler tour of F-hat with list ranking,
                                 start/finish times and the interval test
-                                (Alg. 3, ReversePathsEulerTour), launched kernel
-                                by kernel (it sorts F-hat's child lists with a
-                                library radix sort, kept out of captured graphs);
+                                (Alg. 3, ReversePathsEulerTour; F-hat's child
+                                lists come from this library's radix sort);
                                 needs about 56 bytes per vertex more device
                                 memory.  Results are identical. */
     int replacement_mode;    /* replacement edges: 0 (default) hooking rounds on

@@ -890,9 +890,9 @@ int launch_update(drsf_ctx *c) {
     *(volatile unsigned long long *)(c->h_ret + c->ret_words + 7) = 0;
     c->kind = (c->h_ctl->has_ins ? 1 : 0) | (c->h_ctl->has_del ? 2 : 0);
     if (c->kind == 0) c->kind = 3;  // nothing but rejected or empty batches: run everything
-    // the library sorts of the Euler-tour reversal and of the supergraph are
-    // not captured; the supergraph also reads sizes back
-    if (prof || c->opts.reverse_mode == 1 || c->opts.replacement_mode == 1) {
+    // the supergraph reads sizes back between its kernels, so it is not
+    // captured (the Euler-tour reversal, sort included, is a fixed sequence)
+    if (prof || c->opts.replacement_mode == 1) {
         enqueue_update(c, c->kind, prof);
     } else {
         int rc;

@@ -81,6 +81,8 @@ __device__ __forceinline__ uint64_t mkkey(uint32_t a, uint32_t b) {
 __device__ __forceinline__ int32_t key_lo(uint64_t k) { return (int32_t)(k >> 32); }
 __device__ __forceinline__ int32_t key_hi(uint64_t k) { return (int32_t)(uint32_t)k; }
 
+// 64-bit finalizer of MurmurHash3 (Austin Appleby's published mixing
+// function): spreads keys over the open-addressing tables
 __device__ __forceinline__ uint64_t hmix(uint64_t k) {
     k ^= k >> 33; k *= 0xff51afd7ed558ccdull; k ^= k >> 33;
     k *= 0xc4ceb9fe1a85ec53ull; k ^= k >> 33; return k;
