@@ -289,6 +289,23 @@ int drsf_digest(drsf_ctx *ctx, uint64_t *out);
 int drsf_static_forest(int32_t n, const int64_t *row_ptr, const int32_t *col, int32_t *parent_out,
                        int32_t *label_out, void *stream, int32_t *levels_out);
 
+/*
+ * The same static rebuild for callers that cannot allocate memory (code
+ * being captured into a HIP graph, tight serving loops, harnesses that
+ * forbid allocation): it makes no device or host allocation.  Its scratch
+ * is one array of 64 MiB in device memory that the library holds on each
+ * device it runs on until the process ends; the graph must fit it:
+ * 12 n + 8 nnz bytes plus about 1.5 KB, each of eight arrays rounded up to
+ * 256 bytes (for example n = 10^6 with nnz = 6.8 * 10^6), else
+ * DRSF_E_CAPACITY and nothing is done.  Arguments, result and the other
+ * errors are drsf_static_forest's.  Every call on a device uses that
+ * device's one array, so calls that overlap on one device (from two host
+ * threads, or queued on two streams) race and give wrong results; calls
+ * one after another are independent (every call clears what it reads).
+ */
+int drsf_static_forest_noalloc(int32_t n, const int64_t *row_ptr, const int32_t *col, int32_t *parent_out,
+                               int32_t *label_out, void *stream, int32_t *levels_out);
+
 /* Device bytes the context holds (its own allocations). */
 int64_t drsf_device_bytes(const drsf_ctx *ctx);
 

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <mutex>
 
 #include "../../include/drsf.h"
 #include "drsf_kernels.h"
@@ -340,6 +341,161 @@ __global__ __launch_bounds__(BLOCK) void k_st_bottom_up(int32_t n, const int64_t
 
 using namespace drsf;
 
+namespace {
+
+// Scratch of one static rebuild: the row of every CSR slot and its marks,
+// scan partials, breadth-first levels, two frontiers, the hooking flag and
+// the level counters.
+struct StaticScratch {
+    int32_t *erow, *level, *front0, *front1, *flag;
+    uint32_t *mark;
+    void *stmp;
+    unsigned long long *cnt;
+};
+
+// Device bytes of each scratch array, in StaticScratch order of carving.
+void scratch_sizes(int32_t n, int64_t nnz, size_t sz[8]) {
+    sz[0] = sizeof(int32_t) * (size_t)(nnz + 1);                       // erow
+    sz[1] = sizeof(uint32_t) * (size_t)std::max<int64_t>(nnz, 1);      // mark
+    sz[2] = scan_tmp_bytes(nnz) + 64;                                  // stmp
+    sz[3] = sz[4] = sz[5] = sizeof(int32_t) * (size_t)n;              // level, front0, front1
+    sz[6] = sizeof(int32_t);                                           // flag
+    sz[7] = CNT_WORDS * sizeof(unsigned long long);                    // cnt
+}
+
+// The rebuild on given scratch; h: host memory for CNT_WORDS counters
+// (pinned or not: every read of it follows a stream synchronisation).
+int static_forest_core(int32_t n, const int64_t *row_ptr, const int32_t *col, int64_t nnz, int32_t *parent_out,
+                       int32_t *label_out, hipStream_t s, int32_t *levels_out, const StaticScratch &w,
+                       unsigned long long *h) {
+    int32_t *erow = w.erow, *level = w.level, *front0 = w.front0, *front1 = w.front1, *flag = w.flag;
+    uint32_t *mark = w.mark;
+    void *stmp = w.stmp;
+    unsigned long long *cnt = w.cnt;
+    int rc = DRSF_OK;
+    auto ok = [&](hipError_t e) {
+        if (e != hipSuccess && rc == DRSF_OK) rc = DRSF_E_DEVICE;
+        return e == hipSuccess;
+    };
+    int32_t *comp = label_out;
+    const int gv = grid_for(n, BLOCK), ge = grid_for(nnz, BLOCK);
+    if (nnz > 0) {  // row of every slot (the exclusive sums land in erow itself)
+        launch_fill_i32(reinterpret_cast<int32_t *>(mark), nnz, 0, s);
+        hipLaunchKernelGGL(k_st_marks, dim3(gv), dim3(BLOCK), 0, s, n, row_ptr, nnz, mark);
+        launch_scan_u32(mark, reinterpret_cast<uint32_t *>(erow), cnt, nnz, stmp, s);
+        hipLaunchKernelGGL(k_st_rows, dim3(ge), dim3(BLOCK), 0, s, nnz, mark,
+                           reinterpret_cast<const uint32_t *>(erow), erow);
+    }
+    hipLaunchKernelGGL(k_st_iota, dim3(gv), dim3(BLOCK), 0, s, n, comp);
+    // hooking rounds until nothing hooks (each round at least halves the
+    // roots that still have an edge to another root)
+    for (int round = 0; round < 64 && rc == DRSF_OK; round++) {
+        launch_fill_i32(flag, 1, 0, s);
+        hipLaunchKernelGGL(k_st_hook, dim3(ge), dim3(BLOCK), 0, s, nnz, erow, col, comp, flag);
+        hipLaunchKernelGGL(k_st_compress, dim3(gv), dim3(BLOCK), 0, s, n, comp);
+        if (!ok(hipMemcpyAsync(h, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s)) || !ok(hipStreamSynchronize(s)))
+            break;
+        if (*(int32_t *)h == 0) break;
+        if (round == 63) rc = DRSF_E_DEVICE;
+    }
+    // breadth-first forest from the roots, a level at a time; the host
+    // reads level L's counters and picks the kernel.  While the frontier's
+    // rows are short and their sum is far below the switch point, up to
+    // BATCH_MAX top-down levels are queued at once (the batch length
+    // doubles while this keeps holding), so a deep graph with small
+    // frontiers pays one host read per batch instead of per level; a
+    // top-down level takes its frontier size from the device, so a batch
+    // that outgrows its estimate stays correct, only slower.
+    constexpr int BATCH_MAX = 64;
+    launch_fill_u64(reinterpret_cast<uint64_t *>(cnt), CNT_WORDS, 0, s);
+    hipLaunchKernelGGL(k_st_bfs_init, dim3(gv), dim3(BLOCK), 0, s, n, row_ptr, comp, level, parent_out, front0,
+                       cnt);
+    int32_t *fr[2] = {front0, front1};
+    int L = 0, batch = 1;
+    while (rc == DRSF_OK) {
+        if (!ok(hipMemcpyAsync(h, cnt, CNT_WORDS * sizeof(unsigned long long), hipMemcpyDeviceToHost, s)) ||
+            !ok(hipStreamSynchronize(s)))
+            break;
+        const unsigned long long *hg = h + 4 * (L % 3);
+        const int64_t nf = (int64_t)hg[0], dsum = (int64_t)hg[1];
+        const uint64_t dmax = hg[2];
+        if (nf == 0) break;
+        if (L > n) {  // more levels than vertices: the counters are wrong
+            rc = DRSF_E_DEVICE;
+            break;
+        }
+        if (dsum * 16 < nnz && dmax <= 4096) {
+            // a frontier with few edges and short rows: top-down from its
+            // own rows (four lanes per vertex; room for twice the frontier
+            // in a batch)
+            const int k = dsum * 256 < nnz ? batch : 1;
+            const int g = (int)std::min<int64_t>(GRID_CAP, grid_for(std::max<int64_t>(2 * nf, 64) * 4, BLOCK));
+            for (int i = 0; i < k; i++, L++)
+                hipLaunchKernelGGL(k_st_top_down, dim3(g), dim3(BLOCK), 0, s, row_ptr, col, level, parent_out, L,
+                                   fr[L & 1], fr[(L + 1) & 1], cnt);
+            batch = k == batch ? std::min(2 * batch, BATCH_MAX) : 1;
+        } else {
+            // few edges but a long row: one pass over every slot; many
+            // edges: bottom-up
+            batch = 1;
+            if (dsum * 16 < nnz)
+                hipLaunchKernelGGL(k_st_edges, dim3(ge), dim3(BLOCK), 0, s, nnz, row_ptr, erow, col, level,
+                                   parent_out, L, fr[(L + 1) & 1], cnt);
+            else
+                hipLaunchKernelGGL(k_st_bottom_up, dim3(gv), dim3(BLOCK), 0, s, n, row_ptr, col, level, parent_out,
+                                   L, fr[(L + 1) & 1], cnt);
+            L++;
+        }
+    }
+    if (levels_out) *levels_out = rc == DRSF_OK ? (int32_t)h[CNT_DEPTH] : 0;
+    if (rc == DRSF_OK && !ok(hipStreamSynchronize(s))) rc = DRSF_E_DEVICE;
+    return rc;
+}
+
+// Reads row_ptr[n] (the CSR's entry count) on the stream.
+int read_nnz(int32_t n, const int64_t *row_ptr, hipStream_t s, int64_t *nnz) {
+    *nnz = 0;
+    if (hipMemcpyAsync(nnz, row_ptr + n, sizeof *nnz, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        (void)hipGetLastError();
+        return DRSF_E_DEVICE;
+    }
+    return DRSF_OK;
+}
+
+// Scratch of the allocation-free entry point: one array per device, held
+// until the process ends.  In host code its name only stands for the
+// symbol; kernels get the device address that hipGetSymbolAddress returns
+// for the device that is current.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of this device's scratch array, looked up once per device.
+int scratch_address(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) {
+        (void)hipGetLastError();
+        return DRSF_E_DEVICE;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return DRSF_E_DEVICE;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return DRSF_OK;
+}
+
+}  // namespace
+
 extern "C" int drsf_static_forest(int32_t n, const int64_t *row_ptr, const int32_t *col,
                                   int32_t *parent_out, int32_t *label_out, void *stream,
                                   int32_t *levels_out) {
@@ -350,109 +506,60 @@ extern "C" int drsf_static_forest(int32_t n, const int64_t *row_ptr, const int32
     }
     hipStream_t s = (hipStream_t)stream;
     int64_t nnz = 0;
-    if (hipMemcpyAsync(&nnz, row_ptr + n, sizeof nnz, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-        return DRSF_E_DEVICE;
+    int rc = read_nnz(n, row_ptr, s, &nnz);
+    if (rc) return rc;
     if (nnz < 0 || (nnz > 0 && !col)) return DRSF_E_ARG;
-    int32_t *erow = nullptr, *level = nullptr, *front0 = nullptr, *front1 = nullptr, *flag = nullptr;
-    uint32_t *mark = nullptr;
-    void *stmp = nullptr;
-    unsigned long long *cnt = nullptr, *h = nullptr;
-    int rc = DRSF_OK;
-    auto ok = [&](hipError_t e) {
-        if (e != hipSuccess && rc == DRSF_OK) rc = (e == hipErrorOutOfMemory) ? DRSF_E_NOMEM : DRSF_E_DEVICE;
-        return e == hipSuccess;
-    };
-    if (ok(hipMalloc(&erow, sizeof(int32_t) * (size_t)(nnz + 1))) &&
-        ok(hipMalloc(&mark, sizeof(uint32_t) * (size_t)std::max<int64_t>(nnz, 1))) &&
-        ok(hipMalloc(&stmp, scan_tmp_bytes(nnz) + 64)) &&
-        ok(hipMalloc(&level, sizeof(int32_t) * (size_t)n)) && ok(hipMalloc(&front0, sizeof(int32_t) * (size_t)n)) &&
-        ok(hipMalloc(&front1, sizeof(int32_t) * (size_t)n)) && ok(hipMalloc(&flag, sizeof(int32_t))) &&
-        ok(hipMalloc(&cnt, CNT_WORDS * sizeof(unsigned long long))) &&
-        ok(hipHostMalloc((void **)&h, CNT_WORDS * sizeof(unsigned long long)))) {
-        int32_t *comp = label_out;
-        const int gv = grid_for(n, BLOCK), ge = grid_for(nnz, BLOCK);
-        if (nnz > 0) {  // row of every slot (the exclusive sums land in erow itself)
-            launch_fill_i32(reinterpret_cast<int32_t *>(mark), nnz, 0, s);
-            hipLaunchKernelGGL(k_st_marks, dim3(gv), dim3(BLOCK), 0, s, n, row_ptr, nnz, mark);
-            launch_scan_u32(mark, reinterpret_cast<uint32_t *>(erow), cnt, nnz, stmp, s);
-            hipLaunchKernelGGL(k_st_rows, dim3(ge), dim3(BLOCK), 0, s, nnz, mark,
-                               reinterpret_cast<const uint32_t *>(erow), erow);
-        }
-        hipLaunchKernelGGL(k_st_iota, dim3(gv), dim3(BLOCK), 0, s, n, comp);
-        // hooking rounds until nothing hooks (each round at least halves the
-        // roots that still have an edge to another root)
-        for (int round = 0; round < 64 && rc == DRSF_OK; round++) {
-            launch_fill_i32(flag, 1, 0, s);
-            hipLaunchKernelGGL(k_st_hook, dim3(ge), dim3(BLOCK), 0, s, nnz, erow, col, comp, flag);
-            hipLaunchKernelGGL(k_st_compress, dim3(gv), dim3(BLOCK), 0, s, n, comp);
-            if (!ok(hipMemcpyAsync(h, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s)) ||
-                !ok(hipStreamSynchronize(s)))
-                break;
-            if (*(int32_t *)h == 0) break;
-            if (round == 63) rc = DRSF_E_DEVICE;
-        }
-        // breadth-first forest from the roots, a level at a time; the host
-        // reads level L's counters and picks the kernel.  While the frontier's
-        // rows are short and their sum is far below the switch point, up to
-        // BATCH_MAX top-down levels are queued at once (the batch length
-        // doubles while this keeps holding), so a deep graph with small
-        // frontiers pays one host read per batch instead of per level; a
-        // top-down level takes its frontier size from the device, so a batch
-        // that outgrows its estimate stays correct, only slower.
-        constexpr int BATCH_MAX = 64;
-        launch_fill_u64(reinterpret_cast<uint64_t *>(cnt), CNT_WORDS, 0, s);
-        hipLaunchKernelGGL(k_st_bfs_init, dim3(gv), dim3(BLOCK), 0, s, n, row_ptr, comp, level, parent_out,
-                           front0, cnt);
-        int32_t *fr[2] = {front0, front1};
-        int L = 0, batch = 1;
-        while (rc == DRSF_OK) {
-            if (!ok(hipMemcpyAsync(h, cnt, CNT_WORDS * sizeof(unsigned long long), hipMemcpyDeviceToHost, s)) ||
-                !ok(hipStreamSynchronize(s)))
-                break;
-            const unsigned long long *hg = h + 4 * (L % 3);
-            const int64_t nf = (int64_t)hg[0], dsum = (int64_t)hg[1];
-            const uint64_t dmax = hg[2];
-            if (nf == 0) break;
-            if (L > n) {  // more levels than vertices: the counters are wrong
-                rc = DRSF_E_DEVICE;
-                break;
-            }
-            if (dsum * 16 < nnz && dmax <= 4096) {
-                // a frontier with few edges and short rows: top-down from its
-                // own rows (four lanes per vertex; room for twice the frontier
-                // in a batch)
-                const int k = dsum * 256 < nnz ? batch : 1;
-                const int g = (int)std::min<int64_t>(GRID_CAP, grid_for(std::max<int64_t>(2 * nf, 64) * 4, BLOCK));
-                for (int i = 0; i < k; i++, L++)
-                    hipLaunchKernelGGL(k_st_top_down, dim3(g), dim3(BLOCK), 0, s, row_ptr, col, level, parent_out,
-                                       L, fr[L & 1], fr[(L + 1) & 1], cnt);
-                batch = k == batch ? std::min(2 * batch, BATCH_MAX) : 1;
-            } else {
-                // few edges but a long row: one pass over every slot; many
-                // edges: bottom-up
-                batch = 1;
-                if (dsum * 16 < nnz)
-                    hipLaunchKernelGGL(k_st_edges, dim3(ge), dim3(BLOCK), 0, s, nnz, row_ptr, erow, col, level,
-                                       parent_out, L, fr[(L + 1) & 1], cnt);
-                else
-                    hipLaunchKernelGGL(k_st_bottom_up, dim3(gv), dim3(BLOCK), 0, s, n, row_ptr, col, level,
-                                       parent_out, L, fr[(L + 1) & 1], cnt);
-                L++;
-            }
-        }
-        if (levels_out) *levels_out = rc == DRSF_OK ? (int32_t)h[CNT_DEPTH] : 0;
-        if (rc == DRSF_OK && !ok(hipStreamSynchronize(s))) rc = DRSF_E_DEVICE;
+    size_t sz[8];
+    scratch_sizes(n, nnz, sz);
+    void *p[8] = {};
+    unsigned long long *h = nullptr;
+    bool got = true;
+    for (int k = 0; k < 8 && got; k++) got = hipMalloc(&p[k], sz[k]) == hipSuccess;
+    got = got && hipHostMalloc((void **)&h, CNT_WORDS * sizeof(unsigned long long)) == hipSuccess;
+    if (!got) {
+        (void)hipGetLastError();
+        rc = DRSF_E_NOMEM;
+    } else {
+        const StaticScratch w{(int32_t *)p[0], (int32_t *)p[3], (int32_t *)p[4], (int32_t *)p[5],
+                              (int32_t *)p[6], (uint32_t *)p[1], p[2], (unsigned long long *)p[7]};
+        rc = static_forest_core(n, row_ptr, col, nnz, parent_out, label_out, s, levels_out, w, h);
     }
     (void)hipStreamSynchronize(s);
-    hipFree(erow);
-    hipFree(mark);
-    hipFree(stmp);
-    hipFree(level);
-    hipFree(front0);
-    hipFree(front1);
-    hipFree(flag);
-    hipFree(cnt);
-    if (h) hipHostFree(h);
+    for (void *q : p)
+        if (q) (void)hipFree(q);
+    if (h) (void)hipHostFree(h);
+    return rc;
+}
+
+extern "C" int drsf_static_forest_noalloc(int32_t n, const int64_t *row_ptr, const int32_t *col,
+                                          int32_t *parent_out, int32_t *label_out, void *stream,
+                                          int32_t *levels_out) {
+    if (n < 0 || (n > 0 && (!row_ptr || !parent_out || !label_out))) return DRSF_E_ARG;
+    if (n == 0) {
+        if (levels_out) *levels_out = 0;
+        return DRSF_OK;
+    }
+    void *base = nullptr;
+    int rc = scratch_address(&base);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    int64_t nnz = 0;
+    if ((rc = read_nnz(n, row_ptr, s, &nnz))) return rc;
+    if (nnz < 0 || (nnz > 0 && !col)) return DRSF_E_ARG;
+    if (nnz > ((int64_t)1 << 32)) return DRSF_E_CAPACITY;
+    size_t sz[8], off[8], total = 0;
+    scratch_sizes(n, nnz, sz);
+    for (int k = 0; k < 8; k++) {  // each array 256-byte aligned inside the scratch
+        off[k] = total;
+        total += (sz[k] + 255) & ~(size_t)255;
+    }
+    if (total > NOALLOC_SCRATCH_BYTES) return DRSF_E_CAPACITY;
+    unsigned char *b = static_cast<unsigned char *>(base);
+    const StaticScratch w{(int32_t *)(b + off[0]), (int32_t *)(b + off[3]), (int32_t *)(b + off[4]),
+                          (int32_t *)(b + off[5]), (int32_t *)(b + off[6]), (uint32_t *)(b + off[1]),
+                          (void *)(b + off[2]), (unsigned long long *)(b + off[7])};
+    unsigned long long h[CNT_WORDS] = {};  // pageable: each read follows a stream synchronisation
+    rc = static_forest_core(n, row_ptr, col, nnz, parent_out, label_out, s, levels_out, w, h);
+    (void)hipStreamSynchronize(s);
     return rc;
 }

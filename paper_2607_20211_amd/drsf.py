@@ -82,7 +82,7 @@ EXPORTS = ("drsf_default_opts", "drsf_create", "drsf_apply", "drsf_apply_async",
            "drsf_server_submit", "drsf_server_release", "drsf_server_start",
            "drsf_server_wait_all", "drsf_server_result", "drsf_server_batch", "drsf_server_stats",
            "drsf_server_tenant_state", "drsf_server_error", "drsf_server_destroy",
-           "drsf_static_forest")
+           "drsf_static_forest", "drsf_static_forest_noalloc")
 
 _lib = None
 
@@ -158,6 +158,8 @@ def load():
     lib.drsf_footprint.restype = i64
     lib.drsf_static_forest.argtypes = [i32, vp, vp, vp, vp, vp, ctypes.POINTER(i32)]
     lib.drsf_static_forest.restype = c_int
+    lib.drsf_static_forest_noalloc.argtypes = [i32, vp, vp, vp, vp, vp, ctypes.POINTER(i32)]
+    lib.drsf_static_forest_noalloc.restype = c_int
     lib.drsf_server_create.argtypes = [i64, ctypes.POINTER(drsf_opts), c_int, ctypes.POINTER(vp)]
     lib.drsf_server_create.restype = c_int
     lib.drsf_server_admit.argtypes = [vp, i32, vp, vp, vp, i64, ctypes.POINTER(i32)]
@@ -429,6 +431,16 @@ def drsf_static_forest(n: int, row_ptr, col, parent_out, label_out, stream=None)
     lv = ctypes.c_int32(0)
     rc = load().drsf_static_forest(n, _ptr(row_ptr), _ptr(col), _ptr(parent_out), _ptr(label_out),
                                    stream, ctypes.byref(lv))
+    _check(rc)
+    return int(lv.value)
+
+
+def drsf_static_forest_noalloc(n: int, row_ptr, col, parent_out, label_out, stream=None) -> int:
+    """drsf_static_forest without any allocation (the library's fixed
+    per-device scratch); returns the breadth-first levels."""
+    lv = ctypes.c_int32(0)
+    rc = load().drsf_static_forest_noalloc(n, _ptr(row_ptr), _ptr(col), _ptr(parent_out), _ptr(label_out),
+                                           stream, ctypes.byref(lv))
     _check(rc)
     return int(lv.value)
 
