@@ -71,77 +71,105 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def served_workload(scale, ntenants, nreq, seed):
-    """Serving workload: a resident R-MAT graph plus tenants G(n_t, 4 n_t),
-    n_t = round(10^U(5,6)), arriving staggered over the stream and leaving
-    after their last request.  Requests: target uniform over the graphs live
-    at the request's (unit-rate) arrival time, op ~ Bernoulli(1/2), size
-    round(10^U(2,5)); inserts are initial non-edges and deletes initial edges
-    of the target, distinct across requests, so every request is valid in
-    any interleaving of graphs.  Arrival gaps are unit-mean exponentials,
-    scaled per offered load."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def pct(xs, q):
+    return float(np.percentile(np.asarray(xs, np.float64), q))
+
+
+# this build's phases grouped as the paper's breakdown (Sec. V results):
+# deletion compaction, finding oriented replacement edges (root finding,
+# key-edge scans, hooking, super-forest orientation, and any host-driven
+# continuation of those), path reversal (here with the new labels)
+PAPER_GROUPS = {"validation (not in the paper)": ["validate"],
+                "compaction": ["update_graph"],
+                "oriented_replacement_edges": ["root_finding", "orphan_list", "orphan_scan", "store_sweep",
+                                               "batch_and_inserted_scan", "replacement_edges",
+                                               "superforest_rooting", "host_continuation"],
+                "path_reversal": ["reversal_and_labels"]}
+
+
+def paper_shares(phases, bracket):
+    """Shares of the profiled device time per group of PAPER_GROUPS (phase
+    times less the event bracket; phases that launched nothing count 0)."""
+    t = {k: max(v - bracket, 0.0) if (v > 0 and k != "host_continuation") else v for k, v in phases.items()}
+    tot = sum(t.values())
+    return {grp: round(sum(t.get(k, 0.0) for k in ks) / tot, 3) if tot > 0 else 0.0
+            for grp, ks in PAPER_GROUPS.items()}
+
+
+def run_instances(scale, b, g0, ninst, runs, dev, stream, log):
+    """The paper's protocol (Sec. V: several graph instances, several runs
+    each): instances 0..ninst-1 of the headline workload (instance 0 is the
+    headline graph, the others R-MAT graphs of the same recipe on other
+    seeds), each with 2 warm-up steps and `runs` timed steps of one insert
+    and one delete batch of b; per-op updates/s as median, mean, p10 and
+    p90 over all instance-runs, and per instance."""
+    import torch
     import gen
-    keys = gen.rmat(scale, 16, 0.57, 0.19, 0.19, gen.seed(5, 0, gen.P_GRAPH))
-    graphs = [gen.make_graph(f"rmat{scale}", 1 << scale, keys)]
-    u = gen.uniform(gen.seed(5, 1, gen.P_GRAPH), ntenants)
-    for t in range(ntenants):
-        n = int(round(10 ** (5 + u[t])))
-        graphs.append(gen.make_graph(f"t{t}", n, gen.gnm(n, 4 * n, gen.seed(5, 2 + t, gen.P_GRAPH))))
-    r = gen.uniform(gen.seed(5, 0, gen.P_STREAM), 4 * nreq).reshape(4, nreq)
-    gaps = -np.log1p(-r[0])                  # unit-mean exponential gaps
-    t_arr = np.cumsum(gaps)
-    span = t_arr[-1]
-    # tenant k is live on [k, k + 4) eighths of the stream (staggered, finite)
-    win = [(0.0, np.inf)] + [(span * t / (ntenants + 4), span * (t + 4) / (ntenants + 4))
-                             for t in range(ntenants)]
-    pools = []
-    sizes = np.rint(10 ** (2 + 3 * r[2])).astype(np.int64)
-    ops = (r[3] < 0.5).astype(np.int64)
-    live_idx = [[g for g, (a, b) in enumerate(win) if a <= t < b] for t in t_arr]
-    demand = np.zeros((len(graphs), 2), np.int64)
-    target = np.zeros(nreq, np.int64)
-    for k in range(nreq):
-        lv = live_idx[k]
-        target[k] = lv[min(int(r[1][k] * len(lv)), len(lv) - 1)]
-        demand[target[k], ops[k]] += sizes[k]
-    for g, gr in enumerate(graphs):
-        ni = int(min(demand[g, 0], gr.n * 2))
-        nd = int(min(demand[g, 1], gr.m))
-        trees = int((gr.parent != np.arange(gr.n)).sum())
-        nt = min(trees, nd // 2)
-        nn = min(nd - nt, gr.m - trees)
-        nt = min(trees, nd - nn)
-        ins = gen.insert_batches(gr.n, gr.keys, 1, ni, gen.seed(5, g, gen.P_INSERT))[0] if ni else \
-            np.zeros((0, 2), np.int32)
-        dl = gen.delete_batches(gr.n, gr.keys, gr.parent, 1, nt + nn, nt,
-                                gen.seed(5, g, gen.P_DELETE))[0] if nt + nn else np.zeros((0, 2), np.int32)
-        # tree and non-tree edges interleaved so every request mixes both
-        dl = dl[np.argsort(gen.uniform(gen.seed(5, g, gen.P_STREAM), len(dl)), kind="stable")]
-        pools.append([ins, 0, dl, 0])
-    reqs = []
-    for k in range(nreq):
-        g, op, b = int(target[k]), int(ops[k]), int(sizes[k])
-        pool = pools[g]
-        src, at = (pool[0], 1) if op == 0 else (pool[2], 3)
-        e = src[pool[at]:pool[at] + b]
-        pool[at] += len(e)
-        if len(e) == 0:
-            continue
-        reqs.append((g, np.ascontiguousarray(e), op, float(t_arr[k])))
-    last = {}
-    for i, (g, _, _, _) in enumerate(reqs):
-        last[g] = i
-    return graphs, reqs, win, last
+    from paper_2607_20211_amd import drsf
+    ins_rates, del_rates, per = [], [], []
+    for inst in range(ninst):
+        t0 = time.time()
+        if inst == 0:
+            g = g0
+        else:
+            g = gen.make_graph(f"rmat{scale}", 1 << scale,
+                               gen.rmat(scale, 16, 0.57, 0.19, 0.19, gen.seed(2, inst, gen.P_GRAPH)))
+        ins = torch.from_numpy(gen.insert_batches(g.n, g.keys, 2 + runs, b, gen.seed(2, inst, gen.P_INSERT) + 7)).to(dev)
+        dl = torch.from_numpy(gen.delete_batches(g.n, g.keys, g.parent, 2 + runs, b, b // 2,
+                                                 gen.seed(2, inst, gen.P_DELETE) + 7)).to(dev)
+        f = drsf.Forest(g.n, torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col).to(dev),
+                        torch.from_numpy(g.parent).to(dev), max_batch=b, stream=stream.cuda_stream,
+                        inputs_on_device=True, delta_capacity=(2 + runs) * b + (1 << 20))
+        ri, rd = [], []
+        for i in range(2 + runs):
+            ta = time.perf_counter()
+            f.apply(ins[i], drsf.DRSF_INSERT)
+            tb = time.perf_counter()
+            f.apply(dl[i], drsf.DRSF_DELETE)
+            tc = time.perf_counter()
+            if i >= 2:
+                ri.append(b / (tb - ta))
+                rd.append(b / (tc - tb))
+        f.close()
+        ins_rates += ri
+        del_rates += rd
+        per.append({"instance": inst, "m": g.m, "insert_median": round(float(np.median(ri)), 1),
+                    "delete_median": round(float(np.median(rd)), 1)})
+        log(f"instance {inst}: m={g.m} insert {np.median(ri):.3e} delete {np.median(rd):.3e} updates/s "
+            f"({time.time() - t0:.1f}s)")
+
+    def summ(x):
+        return {"median": round(float(np.median(x)), 1), "mean": round(float(np.mean(x)), 1),
+                "p10": round(pct(x, 10), 1), "p90": round(pct(x, 90), 1)}
+    return {"instances": ninst, "runs_per_instance": runs, "batch": b,
+            "insert_updates_per_s": summ(ins_rates), "delete_updates_per_s": summ(del_rates),
+            "per_instance": per,
+            "how": "instance 0 = the headline graph; others: the same R-MAT recipe on other seeds; each "
+                   "run = one insert batch then one delete batch, host-observed latency per apply"}
 
 
 def run_served(scale, nreq, loads, log):
     """Served pattern against the plain path (one request at a time in
     arrival order, same server code in serial mode), and with coalescing
     (the same-op requests waiting at the head of a tenant's queue go out as
-    one batch)."""
+    one batch).  Every request's status is collected and failures are
+    counted; a verification pass (outside the timed runs) serves the whole
+    stream at once in overlapped and in serial mode with digests on and
+    compares every request's digests of parent and label between the two."""
+    import gen
     from paper_2607_20211_amd import drsf
     t0 = time.time()
-    graphs, reqs, win, last = served_workload(scale, 8, nreq, 0)
+    graphs, reqs, win, last = gen.served_workload(scale, 8, nreq, 0)
     ups = sum(len(e) for _, e, _, _ in reqs)
     log(f"served workload: {len(graphs)} graphs, {len(reqs)} requests, {ups} updates "
         f"({time.time() - t0:.1f}s)")
@@ -150,8 +178,8 @@ def run_served(scale, nreq, loads, log):
     fps = [drsf.drsf_footprint(g.n, len(g.col), opts) for g in graphs]
     budget = fps[0] + sum(sorted(fps[1:])[-3:])
 
-    def serve(serial, rate, coalesce=False):
-        srv = drsf.Server(budget, max_batch=100_000, serial=serial, coalesce=coalesce)
+    def serve(serial, rate, coalesce=False, digests=False):
+        srv = drsf.Server(budget, max_batch=100_000, serial=serial, coalesce=coalesce, digests=digests)
         scale_ns = 1e9 / rate if rate else 0.0
         tids = []
         for g, gr in enumerate(graphs):
@@ -164,44 +192,64 @@ def run_served(scale, nreq, loads, log):
         srv.start()
         srv.wait_all()
         st = srv.stats()
+        res = [srv.result(r) for r in rids]
+        st["failed"] = sum(r["status"] != drsf.DRSF_OK for r in res)
         st["batches"] = len({srv.batch(r) for r in rids})
+        st["digests"] = [r["digest"] for r in res] if digests else None
         srv.close()
         return st
 
     sat = serve(True, None)  # plain path, every request queued at once: its service rate
     mu = sat["completed"] / (sat["completed"] and (ups / sat["updates_per_s"]))
-    log(f"plain path service rate {mu:.1f} requests/s ({sat['updates_per_s']:.3e} updates/s)")
+    log(f"plain path service rate {mu:.1f} requests/s ({sat['updates_per_s']:.3e} updates/s), "
+        f"{sat['failed']} failed")
     out = []
+    failed = sat["failed"]
     for lam in loads:
         rate = lam * mu
         a = serve(False, rate)
-        b = serve(True, rate)
+        bb = serve(True, rate)
         c = serve(False, rate, coalesce=True)
+        failed += a["failed"] + bb["failed"] + c["failed"]
         log(f"load {lam}: served p50 {a['p50_ms']:.3f} p99 {a['p99_ms']:.3f} ms "
             f"(service {a['service_p50_ms']:.3f} / {a['service_p99_ms']:.3f}); "
-            f"plain p50 {b['p50_ms']:.3f} p99 {b['p99_ms']:.3f} ms "
-            f"(service {b['service_p50_ms']:.3f} / {b['service_p99_ms']:.3f}); "
-            f"coalesced p50 {c['p50_ms']:.3f} p99 {c['p99_ms']:.3f} ms in {c['batches']} batches")
+            f"plain p50 {bb['p50_ms']:.3f} p99 {bb['p99_ms']:.3f} ms "
+            f"(service {bb['service_p50_ms']:.3f} / {bb['service_p99_ms']:.3f}); "
+            f"coalesced p50 {c['p50_ms']:.3f} p99 {c['p99_ms']:.3f} ms in {c['batches']} batches; "
+            f"failed {a['failed']}/{bb['failed']}/{c['failed']}")
         out.append({"load": lam, "offered_requests_per_s": round(rate, 1),
                     "served_p50_ms": round(a["p50_ms"], 4), "served_p99_ms": round(a["p99_ms"], 4),
                     "served_service_p50_ms": round(a["service_p50_ms"], 4),
                     "served_service_p99_ms": round(a["service_p99_ms"], 4),
                     "served_updates_per_s": round(a["updates_per_s"], 1),
-                    "plain_p50_ms": round(b["p50_ms"], 4), "plain_p99_ms": round(b["p99_ms"], 4),
-                    "plain_service_p50_ms": round(b["service_p50_ms"], 4),
-                    "plain_service_p99_ms": round(b["service_p99_ms"], 4),
-                    "plain_updates_per_s": round(b["updates_per_s"], 1),
+                    "plain_p50_ms": round(bb["p50_ms"], 4), "plain_p99_ms": round(bb["p99_ms"], 4),
+                    "plain_service_p50_ms": round(bb["service_p50_ms"], 4),
+                    "plain_service_p99_ms": round(bb["service_p99_ms"], 4),
+                    "plain_updates_per_s": round(bb["updates_per_s"], 1),
                     "coalesced_p50_ms": round(c["p50_ms"], 4), "coalesced_p99_ms": round(c["p99_ms"], 4),
                     "coalesced_service_p50_ms": round(c["service_p50_ms"], 4),
                     "coalesced_service_p99_ms": round(c["service_p99_ms"], 4),
                     "coalesced_updates_per_s": round(c["updates_per_s"], 1),
                     "coalesced_batches": c["batches"],
+                    "failed": {"served": a["failed"], "plain": bb["failed"], "coalesced": c["failed"]},
                     "peak_bytes": a["peak_bytes"]})
+    # verification pass: per-request digests, overlapped against serial
+    va = serve(False, None, digests=True)
+    vb = serve(True, None, digests=True)
+    same = va["digests"] == vb["digests"]
+    log(f"served verification: {len(reqs)} requests, digests equal overlapped vs serial: {same}; "
+        f"failed {va['failed']}/{vb['failed']}")
+    assert failed == 0 and va["failed"] == 0 and vb["failed"] == 0, "served requests failed"
+    assert same, "served digests differ from the plain path"
     return {"workload": f"resident R-MAT scale {scale} + 8 tenants G(n, 4n), n = 10^U(5,6), "
                         f"staggered; {len(reqs)} requests of 10^U(2,5) edges, Poisson arrivals",
             "requests": len(reqs), "updates": ups, "budget_bytes": budget,
             "plain_service_requests_per_s": round(mu, 1),
             "plain_saturated_updates_per_s": round(sat["updates_per_s"], 1),
+            "failed_requests": int(failed),
+            "verified": {"requests": len(reqs), "served_equals_plain_digests": bool(same),
+                         "how": "every request's parent and label digests, overlapped against serial, "
+                                "whole stream at once"},
             "loads": out}
 
 
@@ -221,35 +269,52 @@ def time_op(f, snap, batch, op, reps, drsf):
 METHODS = {"hs_paths": (0, 0), "hs_et": (0, 1), "sg_paths": (1, 0), "sg_et": (1, 1)}
 
 
-def methods_ab(n, row, col, par, batches, max_batch, stream, drsf):
+def methods_ab(n, row, col, par, batches, max_batch, stream, drsf, reps=3):
     """The same updates with each replacement-edge method and each path
-    reversal (the paper's SG/HS x ET variants beside this build's defaults),
-    all launched kernel by kernel (the library sorts of SG and ET are never
-    captured): per step the host-observed update time and the replacement
-    and reversal phases (less the event bracket), and whether every method
-    ends in the same forest (digest)."""
+    reversal (the paper's SG/HS x ET variants beside this build's defaults).
+    Wall time per update: median of reps applies from the same state on a
+    context in the production configuration (captured update graph; the
+    supergraph reads sizes back between its kernels, so it is launched
+    directly).  Phase times: the same updates on a profiled context (kernels
+    launched one by one with events), less the event bracket.  Whether every
+    method ends in the same forest: digests."""
     res = {}
     for name, (rm, vm) in METHODS.items():
         f = drsf.Forest(n, row, col, par, max_batch=max_batch, stream=stream.cuda_stream,
-                        inputs_on_device=True, profile=True, replacement_mode=rm, reverse_mode=vm)
-        steps = []
+                        inputs_on_device=True, replacement_mode=rm, reverse_mode=vm)
+        snap = f.snapshot()
+        walls = []
         for edges, op in batches:
-            t0 = time.perf_counter()
-            st = f.apply(edges, op)
-            wall = time.perf_counter() - t0
-            t = f.phase_times()
+            state = f.snapshot()
+            ts = []
+            for _ in range(reps):
+                f.restore(state)
+                t0 = time.perf_counter()
+                f.apply(edges, op)
+                ts.append(time.perf_counter() - t0)
+            walls.append(float(np.median(ts)))
+            drsf.drsf_snapshot_free(state)
+        digest = [int(x) for x in f.digest()]
+        drsf.drsf_snapshot_free(snap)
+        f.close()
+        fp = drsf.Forest(n, row, col, par, max_batch=max_batch, stream=stream.cuda_stream,
+                         inputs_on_device=True, profile=True, replacement_mode=rm, reverse_mode=vm)
+        steps = []
+        for (edges, op), wall in zip(batches, walls):
+            st = fp.apply(edges, op)
+            t = fp.phase_times()
             br = t.pop(drsf.EVENT_BRACKET, 0.0)
-            # an update that needed more hooking rounds or search levels than
-            # queued finishes on the host: that work is outside the phases,
-            # but inside the wall time
             steps.append({"op": "insert" if op == drsf.DRSF_INSERT else "delete",
                           "cross_edges": st["num_key_cross"], "paths": st["num_paths"],
+                          "host_finished": st["host_finished"],
                           "replacement_phase_ms": round(t["replacement_edges"] - br, 4),
                           "reversal_and_labels_phase_ms": round(t["reversal_and_labels"] - br, 4),
+                          "host_continuation_ms": round(t["host_continuation"], 4),
                           "update_wall_ms": round(wall * 1e3, 4)})
-        res[name] = {"steps": steps, "digest": [int(x) for x in f.digest()]}
-        f.close()
-    res["same_result"] = len({tuple(v["digest"]) for v in res.values()}) == 1
+        assert [int(x) for x in fp.digest()] == digest
+        fp.close()
+        res[name] = {"steps": steps, "digest": digest, "captured": rm == 0}
+    res["same_result"] = len({tuple(v["digest"]) for k, v in res.items() if k in METHODS}) == 1
     return res
 
 
@@ -276,6 +341,51 @@ def static_rebuild(n, keys, dev, stream, drsf, reps=3):
 def edge_keys(batch):
     u, v = batch[:, 0].astype(np.uint64), batch[:, 1].astype(np.uint64)
     return (np.minimum(u, v) << np.uint64(32)) | np.maximum(u, v)
+
+
+def store_rebuild(g, dev, stream, log, drsf, b=100_000, reps=3):
+    """Cost of merging the inserted-edge list into the base store (the
+    off-path O(|E|) rebuild): an insert batch that overflows a list of b
+    entries (rebuild + insert) against the same batch on a context whose
+    list has room, both from the same state; amortised over the insert
+    batches that fill the default list."""
+    import torch
+    import gen
+    keys2 = gen.insert_batches(g.n, g.keys, 2, b, gen.seed(2, 3, gen.P_INSERT))
+    d0, d1 = (torch.from_numpy(k).to(dev) for k in keys2)
+    times = {}
+    for cap in (b, 4 * b):
+        f = drsf.Forest(g.n, torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col).to(dev),
+                        torch.from_numpy(g.parent).to(dev), max_batch=b, stream=stream.cuda_stream,
+                        inputs_on_device=True, delta_capacity=cap)
+        f.apply(d0, drsf.DRSF_INSERT)  # fills the list when cap == b
+        ts = []
+        for _ in range(reps):
+            snap = f.snapshot()
+            t0 = time.perf_counter()
+            f.apply(d1, drsf.DRSF_INSERT)
+            ts.append(time.perf_counter() - t0)
+            if cap == b:  # the rebuild changed the layout: start again from a fresh context
+                drsf.drsf_snapshot_free(snap)
+                f.close()
+                f = drsf.Forest(g.n, torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col).to(dev),
+                                torch.from_numpy(g.parent).to(dev), max_batch=b, stream=stream.cuda_stream,
+                                inputs_on_device=True, delta_capacity=cap)
+                f.apply(d0, drsf.DRSF_INSERT)
+            else:
+                f.restore(snap)
+                drsf.drsf_snapshot_free(snap)
+        f.close()
+        times[cap] = float(np.median(ts))
+    rb = times[b] - times[4 * b]
+    dcap = max(4 * b, g.m // 8, 1 << 20)  # the default inserted-edge list at max_batch b
+    out = {"rebuild_ms": round(rb * 1e3, 3), "insert_with_rebuild_ms": round(times[b] * 1e3, 3),
+           "insert_ms": round(times[4 * b] * 1e3, 3), "default_list_entries": dcap,
+           "insert_batches_per_rebuild": dcap // b,
+           "amortised_ms_per_insert_batch": round(rb * 1e3 / (dcap // b), 4),
+           "what": f"R-MAT 22 with {2 * b} inserted edges merged into the base store"}
+    log(f"store rebuild: {out}")
+    return out
 
 
 def run_configs(g, dev, stream, log, reps=3):
@@ -311,6 +421,7 @@ def run_configs(g, dev, stream, log, reps=3):
     drsf.drsf_snapshot_free(snap)
     f.close()
     out["rmat22_from_initial_state"] = sweep
+    out["store_rebuild_rmat22"] = store_rebuild(g, dev, stream, log, drsf)
     # replacement-edge and path-reversal methods (rows f1, f2) on the headline
     # workload: insert then delete 1e5
     ins = torch.from_numpy(gen.insert_batches(g.n, g.keys, 1, 100_000, gen.seed(2, 2, gen.P_INSERT))[0]).to(dev)
@@ -378,11 +489,17 @@ def run_configs(g, dev, stream, log, reps=3):
     return out
 
 
-def run_batched(nsteps, dev, stream, log, tune):
+def run_batched(nsteps, dev, stream, log, tune, small=None):
     """Batched pattern: 256 independent G(n, 4n) graphs (n = 10^U(3,6)) with
     one batch per graph per step (op and size per graph), all graphs updated
-    by one multi-graph apply per step; against the same batches applied one
-    graph at a time through 256 single-graph contexts."""
+    by one multi-graph apply per step.  The schedule is autotuned: the LDS
+    threshold of the small-graph engine (graphs up to it updated whole by one
+    workgroup each, beside the kernel sequence for the others; 0 = every
+    graph through the kernel sequence), its workgroup size and count, then
+    the queued rounds/levels and scan mode.  A/B: the same steps through the
+    kernel sequence alone (threshold 0, its schedule tuned the same way);
+    both end in the same forest (digests).  Against the same batches applied
+    one graph at a time through 256 single-graph contexts."""
     import torch
     import gen
     from paper_2607_20211_amd import drsf
@@ -390,6 +507,7 @@ def run_batched(nsteps, dev, stream, log, tune):
     wl = gen.batched_workload(256, 2 + nsteps, gen.seed(4, 0, gen.P_GRAPH))
     mg = wl.mg
     ups = int(wl.steps[0][1][-1])
+    cap = max(int(e[1][-1]) for e in wl.steps)
     log(f"batched workload: {mg.G} graphs, n={mg.n} m={len(mg.col) // 2}, {ups} updates/step "
         f"({time.time() - t0:.1f}s)")
     d_row = torch.from_numpy(mg.row_ptr).to(dev)
@@ -397,27 +515,51 @@ def run_batched(nsteps, dev, stream, log, tune):
     d_par = torch.from_numpy(mg.parent).to(dev)
     d_steps = [torch.from_numpy(e).to(dev) for e, _, _ in wl.steps]
     torch.cuda.synchronize()
-    f = drsf.MultiForest(mg.n_off, d_row, d_col, d_par, max_batch=ups, stream=stream.cuda_stream,
-                         inputs_on_device=True, delta_capacity=(2 + nsteps) * ups + (1 << 20))
-    del d_row, d_col
-    tuning = None
-    if tune:
-        from paper_2607_20211_amd import autotune
 
-        def sample(fr):
-            fr.apply_multi(d_steps[0], wl.steps[0][1], wl.steps[0][2])
-        tuning = autotune.tune(f, sample, "batched_256_gnm", use_cache=False)
-        log(f"batched tuning: {tuning}")
-    for i in range(2):
-        st = f.apply_multi(d_steps[i], wl.steps[i][1], wl.steps[i][2])
-        assert (st == 0).all()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for i in range(2, 2 + nsteps):
-        f.apply_multi(d_steps[i], wl.steps[i][1], wl.steps[i][2])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t1
+    def make(th):
+        return drsf.MultiForest(mg.n_off, d_row, d_col, d_par, max_batch=cap, stream=stream.cuda_stream,
+                                inputs_on_device=True, delta_capacity=(2 + nsteps) * cap + (1 << 20),
+                                small_graph_vertices=th)
+
+    def sample(fr):
+        fr.apply_multi(d_steps[0], wl.steps[0][1], wl.steps[0][2])
+
+    def run(f):
+        for i in range(2):
+            st = f.apply_multi(d_steps[i], wl.steps[i][1], wl.steps[i][2])
+            assert (st == 0).all()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sts = []
+        for i in range(2, 2 + nsteps):
+            sts.append(f.apply_multi(d_steps[i], wl.steps[i][1], wl.steps[i][2]))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t1
+        rejected = int(sum(int((s != 0).sum()) for s in sts))
+        assert rejected == 0, f"batched: {rejected} graph batches rejected"
+        return wall, [int(x) for x in f.digest()]
+
+    from paper_2607_20211_amd import autotune
+    t0 = time.time()
+    if small is not None:
+        f, tuning = make(small), {"small_graph_vertices": small, "forced": True}
+    elif tune:
+        f, tuning = autotune.tune_batched(make, sample, "batched_256_gnm")
+    else:
+        f, tuning = make(4096), None
+    log(f"batched tuning ({time.time() - t0:.1f}s): {tuning}")
+    wall, dig = run(f)
+    small_graphs = sum(1 for g in mg.graphs if 1 <= g.n <= (tuning or {}).get("small_graph_vertices", 4096))
     f.close()
+    # A/B: the kernel sequence alone
+    fc = make(0)
+    chain_tuning = autotune.tune(fc, sample, "batched_256_gnm_chain", use_cache=False) if tune else None
+    wall_chain, dig_chain = run(fc)
+    fc.close()
+    del d_row, d_col
+    log(f"batched: {nsteps} steps in {wall * 1e3:.2f} ms (chain alone {wall_chain * 1e3:.2f} ms), "
+        f"same forest: {dig == dig_chain}")
+    assert dig == dig_chain, "batched: the small-graph engine and the chain alone end in different forests"
     # the same batches one graph at a time (the plain path), on the first steps
     plain_steps = min(nsteps, 2)
     singles = []
@@ -449,9 +591,14 @@ def run_batched(nsteps, dev, stream, log, tune):
             "updates_per_step": ups, "steps": nsteps,
             "value": round(ups * nsteps / wall, 1), "unit": "edge updates/s",
             "ms_per_step": round(wall / nsteps * 1e3, 4),
+            "small_graphs": small_graphs,
+            "chain_alone_ms_per_step": round(wall_chain / nsteps * 1e3, 4),
+            "chain_alone_value": round(ups * nsteps / wall_chain, 1),
+            "same_forest_as_chain_alone": dig == dig_chain,
             "plain_ms_per_step": round(wall_plain / nsteps * 1e3, 4),
             "plain_value": round(ups * nsteps / wall_plain, 1),
-            "speedup_vs_plain": round(wall_plain / wall, 2), "tuning": tuning}
+            "speedup_vs_plain": round(wall_plain / wall, 2), "tuning": tuning,
+            "chain_alone_tuning": chain_tuning}
 
 
 def main():
@@ -465,12 +612,18 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-pattern measurement (256 graphs per launch)")
     ap.add_argument("--batched-steps", type=int, default=6)
+    ap.add_argument("--batched-small", type=int, default=None,
+                    help="small-graph threshold of the batched context instead of the tuned one")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the per-op rates at other batch sizes and the deep grid")
     ap.add_argument("--no-served", action="store_true",
                     help="skip the served-pattern measurement")
     ap.add_argument("--served-scale", type=int, default=24)
-    ap.add_argument("--served-requests", type=int, default=2000)
+    ap.add_argument("--served-requests", type=int, default=10_000)
+    ap.add_argument("--no-instances", action="store_true",
+                    help="skip the several-instance protocol (median, mean, p10/p90)")
+    ap.add_argument("--instances", type=int, default=5)
+    ap.add_argument("--instance-runs", type=int, default=5)
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch schedule instead of autotuning it first")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -599,8 +752,19 @@ def main():
                            "avg_launch_ms": round(ms, 4), "bytes": what,
                            "timing": "HIP events around the kernel on its stream, mean over the "
                                      "profiled steps, less an empty two-event bracket"}
+    # per-launch medians beside the means (one heavy step can pull a mean up)
+    med_del = {k: float(np.median([p[k] - p.get(drsf.EVENT_BRACKET, 0.0) for p in phases_del]))
+               for k in phases_del[0]}
+    for name, ph in (("k_rep_chase", "root_finding"), ("k_orph_scan", "orphan_scan"),
+                     ("k_sweep_base", "store_sweep")):
+        if name in rooflines:
+            rooflines[name]["median_launch_ms"] = round(med_del[ph], 4)
     dom = max(rooflines, key=lambda k: rooflines[k]["avg_launch_ms"])
     roofline = rooflines[dom]
+    phase_share = {"insert": paper_shares(pi, ev_ins), "delete": paper_shares(pd, ev_del),
+                   "paper": {"compaction": "10-15% (delete)", "oriented_replacement_edges": "~50%",
+                             "path_reversal": "~30% (except SG inserts)"},
+                   "mapping": PAPER_GROUPS}
 
     if args.copy_calibration:
         src = torch.empty(128 << 20, dtype=torch.int32, device=dev).fill_(1)
@@ -613,23 +777,34 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        t1 = time.perf_counter()
-        r1 = oracle.apply(g.n, g.keys, g.parent, ins[0], oracle.INSERT)
-        t2 = time.perf_counter()
-        oracle.apply(g.n, r1.keys, r1.parent, dl[0], oracle.DELETE)
-        t3 = time.perf_counter()
+        # the oracle is single-threaded C; this thread is pinned to one core
+        # for the sample (in-process, no re-exec) and unpinned afterwards
+        aff = os.sched_getaffinity(0)
+        core = min(aff)
+        os.sched_setaffinity(0, {core})
+        try:
+            t1 = time.perf_counter()
+            r1 = oracle.apply(g.n, g.keys, g.parent, ins[0], oracle.INSERT)
+            t2 = time.perf_counter()
+            oracle.apply(g.n, r1.keys, r1.parent, dl[0], oracle.DELETE)
+            t3 = time.perf_counter()
+        finally:
+            os.sched_setaffinity(0, aff)
         cpu = {"value": round(2 * b / (t3 - t1), 1), "unit": "edge updates/s", "cores": 1,
                "kind": "oracle",
                "sample": f"one insert batch and one delete batch of {b} on the same R-MAT "
                          f"scale {scale} graph (insert {t2 - t1:.2f}s, delete {t3 - t2:.2f}s), "
-                         f"single-threaded C oracle"}
+                         f"single-threaded C oracle pinned to core {core}",
+               "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
+    protocol = None if args.no_instances else run_instances(scale, b, g, args.instances, args.instance_runs,
+                                                             dev, stream, log)
     configs = None if args.no_configs else run_configs(g, dev, stream, log)
     batched = None if args.no_batched else run_batched(args.batched_steps, dev, stream, log,
-                                                       not args.no_tune)
+                                                       not args.no_tune, args.batched_small)
 
     served = None if args.no_served else run_served(args.served_scale, args.served_requests,
-                                                     (0.5, 0.95, 1.5), log)
+                                                     (0.5, 0.8, 0.95, 1.5), log)
 
     total_updates = 2 * b * K
     out = {
@@ -666,9 +841,11 @@ def main():
         "phase_ms_insert": {k: round(v, 4) for k, v in pi.items()},
         "phase_ms_delete": {k: round(v, 4) for k, v in pd.items()},
         "event_bracket_ms": {"insert": round(ev_ins, 4), "delete": round(ev_del, 4)},
+        "phase_share_vs_paper": phase_share,
         "tuning": tuning,
         "roofline": roofline,
         "rooflines": rooflines,
+        "protocol": protocol,
         "configs": configs,
         "batched": batched,
         "served": served,

@@ -327,3 +327,88 @@ def batched_workload(G: int, nsteps: int, s: int, log_n=(3.0, 6.0), log_b=(1.0, 
         steps.append((np.concatenate(parts).astype(np.int32), np.array(b_off, np.int64),
                       ops[st].copy()))
     return BatchedWorkload(mg, steps, b_eff)
+
+
+def served_workload(scale, ntenants, nreq, instance=0):
+    """Serving workload: a resident R-MAT graph plus tenants G(n_t, 4 n_t),
+    n_t = round(10^U(5,6)), arriving staggered over the stream and leaving
+    after their last request.  Requests: target uniform over the graphs live
+    at the request's (unit-rate) arrival time, op ~ Bernoulli(1/2), size
+    round(10^U(2,5)).  Each graph's requests are filled in arrival order:
+    inserts take uniform non-edges of the initial graph, distinct across the
+    stream; deletes take initial edges (half tree, half non-tree edges,
+    interleaved), and once those run out, edges inserted by the graph's
+    earlier requests, oldest first.  So every request is valid in any
+    interleaving of graphs that keeps each graph's arrival order; a request
+    left empty is dropped.  Arrival gaps are unit-mean exponentials, scaled
+    per offered load.  Instance 0 is the benchmark's workload; other
+    instances draw everything from other seeds."""
+    cfg = 5 if instance == 0 else 500 + int(instance)
+    keys = rmat(scale, 16, 0.57, 0.19, 0.19, seed(cfg, 0, P_GRAPH))
+    graphs = [make_graph(f"rmat{scale}", 1 << scale, keys)]
+    u = uniform(seed(cfg, 1, P_GRAPH), ntenants)
+    for t in range(ntenants):
+        n = int(round(10 ** (5 + u[t])))
+        graphs.append(make_graph(f"t{t}", n, gnm(n, 4 * n, seed(cfg, 2 + t, P_GRAPH))))
+    r = uniform(seed(cfg, 0, P_STREAM), 4 * nreq).reshape(4, nreq)
+    gaps = -np.log1p(-r[0])                  # unit-mean exponential gaps
+    t_arr = np.cumsum(gaps)
+    span = t_arr[-1]
+    # tenant k is live on [k, k + 4) eighths of the stream (staggered, finite)
+    win = [(0.0, np.inf)] + [(span * t / (ntenants + 4), span * (t + 4) / (ntenants + 4))
+                             for t in range(ntenants)]
+    pools = []
+    sizes = np.rint(10 ** (2 + 3 * r[2])).astype(np.int64)
+    ops = (r[3] < 0.5).astype(np.int64)
+    live_idx = [[g for g, (a, b) in enumerate(win) if a <= t < b] for t in t_arr]
+    demand = np.zeros((len(graphs), 2), np.int64)
+    target = np.zeros(nreq, np.int64)
+    for k in range(nreq):
+        lv = live_idx[k]
+        target[k] = lv[min(int(r[1][k] * len(lv)), len(lv) - 1)]
+        demand[target[k], ops[k]] += sizes[k]
+    for g, gr in enumerate(graphs):
+        ni = int(min(demand[g, 0], gr.n * (gr.n - 1) // 2 - gr.m))
+        nd = int(min(demand[g, 1], gr.m))
+        trees = int((gr.parent != np.arange(gr.n)).sum())
+        nt = min(trees, nd // 2)
+        nn = min(nd - nt, gr.m - trees)
+        nt = min(trees, nd - nn)
+        ins = insert_batches(gr.n, gr.keys, 1, ni, seed(cfg, g, P_INSERT))[0] if ni else \
+            np.zeros((0, 2), np.int32)
+        dl = delete_batches(gr.n, gr.keys, gr.parent, 1, nt + nn, nt,
+                            seed(cfg, g, P_DELETE))[0] if nt + nn else np.zeros((0, 2), np.int32)
+        # tree and non-tree edges interleaved so every request mixes both
+        dl = dl[np.argsort(uniform(seed(cfg, g, P_STREAM), len(dl)), kind="stable")]
+        pools.append([ins, 0, dl, 0, []])  # [inserts, next, initial deletes, next, inserted runs alive]
+    reqs = []
+    for k in range(nreq):
+        g, op, b = int(target[k]), int(ops[k]), int(sizes[k])
+        pool = pools[g]
+        if op == 0:
+            e = pool[0][pool[1]:pool[1] + b]
+            pool[1] += len(e)
+            if len(e):
+                pool[4].append(e)
+        else:
+            e = pool[2][pool[3]:pool[3] + b]
+            pool[3] += len(e)
+            parts = [e]
+            need = b - len(e)
+            while need > 0 and pool[4]:  # edges inserted by earlier requests of this graph
+                run = pool[4][0]
+                take, rest = run[:need], run[need:]
+                parts.append(take)
+                need -= len(take)
+                if len(rest):
+                    pool[4][0] = rest
+                else:
+                    pool[4].pop(0)
+            e = np.concatenate(parts) if len(parts) > 1 else e
+        if len(e) == 0:
+            continue
+        reqs.append((g, np.ascontiguousarray(e, np.int32), op, float(t_arr[k])))
+    last = {}
+    for i, (g, _, _, _) in enumerate(reqs):
+        last[g] = i
+    return graphs, reqs, win, last

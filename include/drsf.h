@@ -133,6 +133,16 @@ typedef struct {
     void *(*dev_alloc)(size_t bytes, void *alloc_user);
     void (*dev_free)(void *ptr, void *alloc_user);
     void *alloc_user;
+    int small_graph_vertices;  /* multi-graph contexts: graphs with at most
+                                this many vertices (<= 16384; 0 = none, the
+                                default) are kept apart from the edge store
+                                and updated whole by one workgroup each, with
+                                the forest held in LDS, taken from a device
+                                work queue by a persistent kernel that runs
+                                beside the kernel sequence updating the other
+                                graphs.  Results are identical. */
+    int small_threads;       /* workgroup size of that kernel: 256, 512 or
+                                1024; 0 = 512 */
 } drsf_opts;
 
 /* Fills *opts with the defaults described above. */
@@ -325,6 +335,16 @@ int64_t drsf_footprint(int32_t n, int64_t nnz, const drsf_opts *opts);
  */
 int drsf_set_tuning(drsf_ctx *ctx, int rounds_queued, int levels_queued, int sweep_mode);
 
+/*
+ * The launch schedule of the small-graph kernel of a multi-graph context
+ * (drsf_opts.small_graph_vertices): threads per workgroup (256, 512 or
+ * 1024; 0 = keep) and workgroups (0 = as many as fit on the device at once,
+ * at most one per small graph).  Results do not depend on it.  The next
+ * apply captures its update graph again.  Used by the autotuner.  Errors:
+ * DRSF_E_ARG.
+ */
+int drsf_set_small_schedule(drsf_ctx *ctx, int threads, int workgroups);
+
 /* Copies parent and/or label (either may be NULL) to host int32[n]. */
 int drsf_copy_out(drsf_ctx *ctx, int32_t *parent_host, int32_t *label_host);
 
@@ -349,19 +369,22 @@ void drsf_snapshot_free(drsf_snapshot *snap);
 
 /*
  * Per-phase device times of the last apply in milliseconds (needs
- * opts.profile), 10 phases: validate; update-graph (cut, store update, piece
- * registration, and for deletes the start of root finding, rep = parent);
- * root finding (pointer chase, orphan bitmap, orphan staging); orphan list;
- * orphan adjacency scan; whole-store sweep; cross edges of the batch and of
- * the inserted-edge list; replacement edges (the hooking rounds queued with
- * the update); super-forest rooting; path reversal with the new labels (one
- * launch).  Work that an update finishes on the host (extra rounds) is not
- * in these times; a phase that launches nothing for the batch's kind (the
- * delete-only phases of an insert batch) reads 0.  Each phase time includes
- * the fixed cost of one event record; an 11th entry (written when cap > 10)
- * is the time of an empty bracket, two events recorded back to back before
- * the update, which measures that cost.  Returns the number of entries
- * written (<= cap).
+ * opts.profile), 11 entries: validate; update-graph (cut, store update,
+ * piece registration, and for deletes the start of root finding, rep =
+ * parent); root finding (pointer chase, orphan bitmap, orphan staging);
+ * orphan list; orphan adjacency scan; whole-store sweep; cross edges of the
+ * batch and of the inserted-edge list; replacement edges (the hooking
+ * rounds queued with the update); super-forest rooting; path reversal with
+ * the new labels (one launch); and the host-driven continuation: when the
+ * queued rounds or search levels did not finish the update
+ * (drsf_view.host_finished), the time from the first continuation launch to
+ * the end of its cleanup, host round trips between launches included (0
+ * otherwise; the queued phases then hold only what ran before it).  A phase
+ * that launches nothing for the batch's kind (the delete-only phases of an
+ * insert batch) reads 0.  Each phase time includes the fixed cost of one
+ * event record; a 12th entry (written when cap > 11) is the time of an
+ * empty bracket, two events recorded back to back before the update, which
+ * measures that cost.  Returns the number of entries written (<= cap).
  */
 int drsf_phase_times(drsf_ctx *ctx, float *ms, int cap);
 
@@ -440,6 +463,16 @@ int drsf_server_batch(drsf_server *srv, int64_t req, int64_t *batch);
 int drsf_server_stats(drsf_server *srv, double *out);
 /* 0 waiting to arrive, 1 queued for admission, 2 live, 3 released, 4 failed. */
 int32_t drsf_server_tenant_state(drsf_server *srv, int32_t tenant);
+/*
+ * Copies a live tenant's parent and label arrays (host int32[n] each;
+ * either may be NULL) once every request submitted for it so far is done:
+ * blocks until then, while the scheduler goes on with other tenants.  The
+ * arrays are the result of all of those requests, as drsf_copy_out on the
+ * tenant's context.  Errors: DRSF_E_ARG (unknown tenant), DRSF_E_STATE (the
+ * tenant is not live: not yet admitted, released or failed; a released
+ * tenant is destroyed once its queue is empty), or the copy's error.
+ */
+int drsf_server_copy_out(drsf_server *srv, int32_t tenant, int32_t *parent_host, int32_t *label_host);
 const char *drsf_server_error(const drsf_server *srv);
 /* Waits for submitted requests, then frees everything. */
 void drsf_server_destroy(drsf_server *srv);

@@ -9,6 +9,13 @@ is measured: every candidate (rounds queued, levels queued, delete scan mode)
 replays the same sample updates from the same snapshot, and the fastest is
 kept and cached on disk under a key describing the workload.  Results never
 depend on the choice (tests check bit-exact results for every setting).
+
+For the batched pattern (multi-graph contexts) tune_batched also searches
+the small-graph engine: the LDS threshold (graphs of at most that many
+vertices are updated whole by one workgroup each; a threshold needs its own
+context, since it decides where each graph's edges live), then the
+engine's workgroup size and number of persistent workgroups on the best
+threshold's context, then the schedule above.
 """
 from __future__ import annotations
 
@@ -86,3 +93,74 @@ def tune(forest, sample, key: str, *, candidates=CANDIDATES, repeats: int = 2,
         cache[key] = best
         _store_cache(path, cache)
     return dict(best, cached=False, tried=len(results))
+
+
+THRESHOLDS = (0, 1024, 2048, 4096, 8192)
+SMALL_SCHEDULES = [(t, w) for t in (256, 512, 1024) for w in (0, 128, 512)]
+
+
+def _time(forest, snap, sample, repeats, sync):
+    t_best = None
+    for _ in range(repeats):
+        forest.restore(snap)
+        if sync:
+            sync()
+        t0 = time.perf_counter()
+        sample(forest)
+        if sync:
+            sync()
+        t = time.perf_counter() - t0
+        t_best = t if t_best is None else min(t_best, t)
+    forest.restore(snap)
+    return t_best
+
+
+def tune_batched(make, sample, key: str, *, thresholds=THRESHOLDS, small_schedules=SMALL_SCHEDULES,
+                 candidates=CANDIDATES, repeats: int = 2, sync=None):
+    """Pick the batched pattern's schedule.  make(threshold) builds a
+    MultiForest with that small_graph_vertices; sample(forest) applies the
+    sample updates.  Returns (forest, choice): the best threshold's context,
+    left with the best small-graph schedule and launch schedule active and
+    its state as created, and {"small_graph_vertices", "small_threads",
+    "small_workgroups", "rounds_queued", "levels_queued", "sweep_mode",
+    "ms", "tried"}."""
+    from .drsf import drsf_snapshot_free
+    best_t, best_f, best_ms, tried = None, None, None, 0
+    per_threshold = {}
+    for th in thresholds:
+        f = make(th)
+        snap = f.snapshot()
+        try:
+            t = _time(f, snap, sample, repeats, sync)
+        finally:
+            drsf_snapshot_free(snap)
+        per_threshold[th] = round(t * 1e3, 4)
+        tried += 1
+        if best_ms is None or t < best_ms:
+            if best_f is not None:
+                best_f.close()
+            best_t, best_f, best_ms = th, f, t
+        else:
+            f.close()
+    f = best_f
+    snap = f.snapshot()
+    sched = (0, 0)
+    try:
+        if best_t:
+            res = []
+            for th, wg in small_schedules:
+                f.set_small_schedule(th, wg)
+                res.append((_time(f, snap, sample, repeats, sync), th, wg))
+                tried += 1
+            t, th, wg = min(res)
+            sched = (th, wg)
+            f.set_small_schedule(th, wg)
+    finally:
+        drsf_snapshot_free(snap)
+    inner = tune(f, sample, key, candidates=candidates, repeats=repeats, use_cache=False, sync=sync)
+    choice = {"small_graph_vertices": best_t, "small_threads": sched[0] or 512,
+              "small_workgroups": sched[1], "rounds_queued": inner["rounds_queued"],
+              "levels_queued": inner["levels_queued"], "sweep_mode": inner["sweep_mode"],
+              "ms": inner["ms"], "tried": tried + inner["tried"],
+              "threshold_ms": per_threshold}
+    return f, choice

@@ -7,7 +7,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdrsf.so")
-SOURCES = ["drsf_kernels.hip", "drsf_api.hip", "drsf_server.hip", "drsf_sort.hip", "drsf_static.hip"]
+SOURCES = ["drsf_kernels.hip", "drsf_api.hip", "drsf_server.hip", "drsf_sort.hip", "drsf_static.hip",
+           "drsf_small.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]

@@ -57,6 +57,11 @@ struct drsf_snapshot {
     std::vector<int64_t> gm;
     int32_t *parent = nullptr, *label = nullptr, *bcol = nullptr, *lcol = nullptr, *dhpos = nullptr;
     uint64_t *dkey = nullptr, *dhash = nullptr;
+    // small graphs: their key pool, live counts and current buffers
+    int64_t pool_keys = 0;
+    int32_t nsg = 0;
+    uint32_t *pool = nullptr;
+    int32_t *sm = nullptr, *sbuf = nullptr;
 };
 
 struct drsf_ctx {
@@ -172,9 +177,12 @@ struct drsf_ctx {
     int last_op = 0;
     int last_rc = DRSF_OK;
     drsf_view view{};
-    hipEvent_t ev[PH_N + 3]{};  // phase boundaries, then an empty bracket
+    // phase boundaries [0, PH_N], an empty bracket, then the bracket of the
+    // host-driven continuation
+    hipEvent_t ev[PH_N + 5]{};
     bool ph_on[PH_N + 1]{};     // the phase recorded its event in the last enqueued update
-    float phase_ms[PH_N + 1]{}; // phases, then the empty bracket
+    float phase_ms[PH_N + 2]{}; // phases, the host-driven continuation, the empty bracket
+    bool cont_timed = false;    // the continuation of the last update recorded its events
     bool have_phases = false;
     std::string err;
     std::vector<void *> allocs;
@@ -182,6 +190,22 @@ struct drsf_ctx {
     int64_t bytes = 0, peak_bytes = 0;  // device bytes held now / at most
     int64_t rebuilds = 0;               // store rebuilds so far
     bool broken = false;                // a store rebuild failed after dropping the old store
+    // small graphs of a multi-graph context (drsf_opts.small_graph_vertices):
+    // updated whole by one workgroup each, beside the chain, on stream s2
+    int32_t nsg = 0, small_T = 0, small_threads = 512, small_grid = 0;
+    std::vector<int32_t> g2s;            // graph -> small graph index, or -1
+    std::vector<int32_t> sgid_h;
+    std::vector<int64_t> scap_h, soff_h, svoff_h;
+    int64_t pool_keys = 0, nsv = 0;
+    int32_t *sgid = nullptr, *sm = nullptr, *sbuf = nullptr, *sok = nullptr;
+    int64_t *soff = nullptr, *scap = nullptr, *svoff = nullptr;
+    uint32_t *pool = nullptr, *xk = nullptr, *bsort0 = nullptr, *bsort1 = nullptr;
+    int32_t *spar = nullptr, *slab = nullptr;
+    int2 *ser = nullptr;
+    int4 *stasks = nullptr, *h_stasks = nullptr;
+    unsigned int *qhead = nullptr;
+    hipStream_t s2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace {
@@ -306,6 +330,37 @@ Dev make_dev(drsf_ctx *c) {
     d.et_finish = c->et_finish; d.et_support = c->et_support;
     d.status = c->status; d.cnt = c->cnt;
     return d;
+}
+
+SmallDev make_small(drsf_ctx *c) {
+    SmallDev sd;
+    memset(&sd, 0, sizeof sd);
+    sd.nsg = c->nsg;
+    sd.T = c->small_T;
+    sd.sgid = c->sgid;
+    sd.soff = c->soff;
+    sd.scap = c->scap;
+    sd.svoff = c->svoff;
+    sd.sm = c->sm;
+    sd.sbuf = c->sbuf;
+    sd.sok = c->sok;
+    sd.pool = c->pool;
+    sd.xk = c->xk;
+    sd.spar = c->spar;
+    sd.slab = c->slab;
+    sd.er = c->ser;
+    sd.bsort0 = c->bsort0;
+    sd.bsort1 = c->bsort1;
+    sd.tasks = c->stasks;
+    sd.qhead = c->qhead;
+    return sd;
+}
+
+// live edges of the graphs in the edge store (the small graphs keep theirs apart)
+int64_t store_edges(const drsf_ctx *c) {
+    int64_t m = c->m_live;
+    for (int32_t g = 0; g < c->nsg; g++) m -= c->gm_h[c->sgid_h[g]];
+    return m;
 }
 
 int read_status(drsf_ctx *c, int32_t *st) {
@@ -460,6 +515,7 @@ int alloc_state(drsf_ctx *c) {
 void destroy_ctx(drsf_ctx *c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->s2) (void)hipStreamSynchronize(c->s2);
     for (int k = 0; k < 4; k++) {
         if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
         if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
@@ -471,6 +527,10 @@ void destroy_ctx(drsf_ctx *c) {
         if (p) (void)hipHostFree(p);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
+    if (c->h_stasks) (void)hipHostFree(c->h_stasks);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->s2) (void)hipStreamDestroy(c->s2);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -501,7 +561,7 @@ int build_store(drsf_ctx *c, const int64_t *row_ptr_in, const int32_t *col_in, i
     if ((rc = dalloc(c, &c->bptr, (int64_t)n + 1))) return rc;
     unsigned long long *dtotal = (unsigned long long *)(tmp + scan_tmp_bytes(n));
     launch_fill_i32(c->status, 1, 0, s);
-    launch_csr_check(n, drow, dcol, ucnt, c->status, c->ngraph > 1 ? c->goff : nullptr, c->ngraph, s);
+    launch_csr_check(n, drow, dcol, nnz, ucnt, c->status, c->ngraph > 1 ? c->goff : nullptr, c->ngraph, s);
     launch_scan_u32(ucnt, c->bptr, dtotal, n, tmp, s);
     HIPCHK(c, hipMemcpyAsync(c->h_ret, dtotal, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(c->h_ret + 1, c->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -518,18 +578,18 @@ int build_store(drsf_ctx *c, const int64_t *row_ptr_in, const int32_t *col_in, i
     // padded to whole sweep tiles with deleted entries
     if ((rc = dalloc(c, &c->bcol, c->ntiles * TILE))) return rc;
     launch_fill_i32(c->bcol + c->eb, c->ntiles * TILE - c->eb, TOMB, s);
-    launch_upper_fill(n, drow, dcol, c->bptr, c->bcol, s);
+    launch_upper_fill(n, drow, dcol, c->bptr, c->bcol, c->eb, s);
     // lower half (row v holds u < v), for the orphan scan
     launch_lower_counts(n, drow, c->bptr, ucnt, s);
     if ((rc = dalloc(c, &c->lptr, (int64_t)n + 1))) return rc;
     launch_scan_u32(ucnt, c->lptr, dtotal, n, tmp, s);
     if ((rc = dalloc(c, &c->lcol, c->eb))) return rc;
-    launch_lower_fill(n, drow, dcol, c->lptr, c->lcol, s);
+    launch_lower_fill(n, drow, dcol, c->lptr, c->lcol, c->eb, s);
     if ((rc = dalloc(c, &c->twin, c->eb))) return rc;
     if ((rc = dalloc(c, &c->ltwin, c->eb))) return rc;
     // every lower entry finds its mirror in the upper half: with equal halves
     // this is the symmetry check
-    launch_twin(n, c->bptr, c->bcol, c->lptr, c->lcol, c->twin, c->ltwin, c->status, s);
+    launch_twin(n, c->bptr, c->bcol, c->lptr, c->lcol, c->twin, c->ltwin, c->status, c->eb, s);
     {
         int32_t st2;
         if ((rc = read_status(c, &st2))) return rc;
@@ -561,6 +621,123 @@ int build_store(drsf_ctx *c, const int64_t *row_ptr_in, const int32_t *col_in, i
     dfree(c, tmp);
     if (!dev_in) { dfree(c, drow); dfree(c, dcol); }
     c->m_live = c->eb;
+    return DRSF_OK;
+}
+
+// Small graphs of a multi-graph context: graphs with at most small_T
+// vertices move out of the edge store into key arrays of their own (see
+// drsf_small.hip); their entries in the store are marked deleted.
+int setup_small(drsf_ctx *c) {
+    int rc;
+    hipStream_t s = c->stream;
+    c->g2s.assign((size_t)c->ngraph, -1);
+    for (int32_t g = 0; g < c->ngraph; g++) {
+        const int32_t ng = c->goff_h[g + 1] - c->goff_h[g];
+        if (ng >= 1 && ng <= c->small_T) {
+            c->g2s[g] = (int32_t)c->sgid_h.size();
+            c->sgid_h.push_back(g);
+        }
+    }
+    c->nsg = (int32_t)c->sgid_h.size();
+    if (c->nsg == 0) return DRSF_OK;
+    c->scap_h.resize((size_t)c->nsg);
+    c->soff_h.resize((size_t)c->nsg);
+    c->svoff_h.resize((size_t)c->nsg);
+    int64_t off = 0, voff = 0;
+    for (int32_t k = 0; k < c->nsg; k++) {
+        const int32_t g = c->sgid_h[k];
+        const int64_t m = c->gm_h[g];
+        c->scap_h[k] = std::max<int64_t>(2 * m, m + 1024);  // room for inserts before the pool grows
+        c->soff_h[k] = off;
+        off += 2 * c->scap_h[k];
+        c->svoff_h[k] = voff;
+        voff += c->goff_h[g + 1] - c->goff_h[g];
+    }
+    c->pool_keys = off;
+    c->nsv = voff;
+    if ((rc = dalloc(c, &c->sgid, c->nsg)) || (rc = dalloc(c, &c->sm, c->nsg)) || (rc = dalloc(c, &c->sbuf, c->nsg)) ||
+        (rc = dalloc(c, &c->sok, c->nsg)) || (rc = dalloc(c, &c->soff, c->nsg)) ||
+        (rc = dalloc(c, &c->scap, c->nsg)) || (rc = dalloc(c, &c->svoff, c->nsg)) ||
+        (rc = dalloc(c, &c->pool, c->pool_keys)) || (rc = dalloc(c, &c->xk, c->pool_keys / 2)) ||
+        (rc = dalloc(c, &c->spar, c->nsv)) || (rc = dalloc(c, &c->slab, c->nsv)) ||
+        (rc = dalloc(c, &c->ser, c->nsv)) || (rc = dalloc(c, &c->bsort0, c->max_batch)) ||
+        (rc = dalloc(c, &c->bsort1, c->max_batch)) || (rc = dalloc(c, &c->stasks, c->nsg)) ||
+        (rc = dalloc(c, &c->qhead, 1)))
+        return rc;
+    if ((rc = halloc(c, &c->h_stasks, c->nsg))) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->sgid, c->sgid_h.data(), 4 * (size_t)c->nsg, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->soff, c->soff_h.data(), 8 * (size_t)c->nsg, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->scap, c->scap_h.data(), 8 * (size_t)c->nsg, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->svoff, c->svoff_h.data(), 8 * (size_t)c->nsg, hipMemcpyHostToDevice, s));
+    launch_fill_i32(reinterpret_cast<int32_t *>(c->qhead), 1, 0, s);
+    launch_small_init(make_dev(c), make_small(c), s);
+    HIPCHK(c, hipStreamSynchronize(s));  // the pageable metadata sources
+    if (hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, DRSF_E_DEVICE, "stream or event creation failed");
+    }
+    return DRSF_OK;
+}
+
+// Workgroups of the small-graph kernel: as many as fit on the device at once
+// (by its LDS), at most one per small graph.
+int small_grid_for(drsf_ctx *c) {
+    int cus = 256, lds_cu = 160 * 1024;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->dev);
+    (void)hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c->dev);
+    const int64_t per = (int64_t)small_lds_bytes(c->small_T) + 18 * 1024;
+    const int64_t fit = std::max<int64_t>(1, lds_cu / per) * cus;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(fit, c->nsg));
+}
+
+// Makes room for more keys in the small graphs' buffers (an insert would
+// not fit): each graph in need gets a larger capacity, the live keys move to
+// a new pool, and the captured update graphs (which hold the old pool) are
+// dropped; snapshots taken before cannot be restored.
+int small_grow(drsf_ctx *c, const std::vector<int64_t> &need) {
+    int rc;
+    hipStream_t s = c->stream;
+    HIPCHK(c, hipStreamSynchronize(s));
+    std::vector<int32_t> sm((size_t)c->nsg), sb((size_t)c->nsg);
+    HIPCHK(c, hipMemcpyAsync(sm.data(), c->sm, 4 * sm.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(sb.data(), c->sbuf, 4 * sb.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    std::vector<int64_t> cap = c->scap_h, off((size_t)c->nsg);
+    int64_t tot = 0;
+    for (int32_t k = 0; k < c->nsg; k++) {
+        if (need[k] > cap[k]) cap[k] = std::max<int64_t>(need[k], 2 * cap[k]);
+        off[k] = tot;
+        tot += 2 * cap[k];
+    }
+    uint32_t *np = nullptr, *nx = nullptr;
+    if ((rc = dalloc(c, &np, tot)) || (rc = dalloc(c, &nx, tot / 2))) {
+        dfree(c, np);
+        return rc;
+    }
+    for (int32_t k = 0; k < c->nsg; k++)
+        if (sm[k] > 0)
+            HIPCHK(c, hipMemcpyAsync(np + off[k], c->pool + c->soff_h[k] + (int64_t)sb[k] * c->scap_h[k],
+                                     4 * (size_t)sm[k], hipMemcpyDeviceToDevice, s));
+    launch_fill_i32(c->sbuf, c->nsg, 0, s);
+    HIPCHK(c, hipMemcpyAsync(c->soff, off.data(), 8 * off.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->scap, cap.data(), 8 * cap.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    dfree(c, c->pool);
+    dfree(c, c->xk);
+    c->pool = np;
+    c->xk = nx;
+    c->scap_h = cap;
+    c->soff_h = off;
+    c->pool_keys = tot;
+    c->rebuilds++;
+    for (int k = 0; k < 4; k++) {
+        if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+        if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+        c->gexec[k] = nullptr;
+        c->graph[k] = nullptr;
+    }
     return DRSF_OK;
 }
 
@@ -625,7 +802,9 @@ int rebuild_store(drsf_ctx *c) {
     uint64_t *pairs = nullptr, *sorted = nullptr;
     unsigned long long *npairs = nullptr, *dtot = nullptr;
     uint32_t *ddeg = nullptr, *dstart = nullptr, *bdeg = nullptr, *rowp32 = nullptr;
-    char *stmp = nullptr, *ctmp = nullptr;
+    uint32_t *flag = nullptr, *LS = nullptr, *US = nullptr;  // live prefix counts of the two halves
+    char *stmp = nullptr, *ctmp = nullptr, *etmp = nullptr;
+    const int64_t eb = c->eb;
     int64_t *rowp = nullptr;
     int32_t *col = nullptr;
     const size_t sbytes = sort_u64_tmp_bytes(pcap2) + 256;
@@ -634,7 +813,8 @@ int rebuild_store(drsf_ctx *c) {
     // it was
     auto release = [&](int code) {
         for (void *p : {(void *)pairs, (void *)sorted, (void *)npairs, (void *)stmp, (void *)ddeg, (void *)dstart,
-                        (void *)bdeg, (void *)rowp32, (void *)ctmp, (void *)rowp, (void *)col})
+                        (void *)bdeg, (void *)rowp32, (void *)ctmp, (void *)rowp, (void *)col, (void *)flag,
+                        (void *)LS, (void *)US, (void *)etmp})
             dfree(c, p);
         return code;
     };
@@ -642,7 +822,9 @@ int rebuild_store(drsf_ctx *c) {
         (rc = dalloc(c, &stmp, (int64_t)sbytes)) || (rc = dalloc(c, &ddeg, n)) ||
         (rc = dalloc(c, &dstart, (int64_t)n + 1)) || (rc = dalloc(c, &bdeg, n)) ||
         (rc = dalloc(c, &rowp32, (int64_t)n + 1)) || (rc = dalloc(c, &rowp, (int64_t)n + 1)) ||
-        (rc = dalloc(c, &ctmp, (int64_t)scan_tmp_bytes(n) + 64))) {
+        (rc = dalloc(c, &ctmp, (int64_t)scan_tmp_bytes(n) + 64)) || (rc = dalloc(c, &flag, eb)) ||
+        (rc = dalloc(c, &LS, eb + 1)) || (rc = dalloc(c, &US, eb + 1)) ||
+        (rc = dalloc(c, &etmp, (int64_t)scan_tmp_bytes(eb) + 64))) {
         (void)hipStreamSynchronize(s);
         return release(rc);
     }
@@ -659,22 +841,27 @@ int rebuild_store(drsf_ctx *c) {
     launch_fill_i32(reinterpret_cast<int32_t *>(ddeg), n, 0, s);
     launch_rb_pair_deg(sorted, npairs, ddeg, pcap2, s);
     launch_scan_u32(ddeg, dstart, dtot, n, ctmp, s);
-    launch_rb_counts(n, c->bptr, c->bcol, c->lptr, c->lcol, bdeg, s);
-    launch_add_u32(bdeg, ddeg, bdeg, n, s);
+    launch_rb_live(c->lcol, eb, flag, s);
+    launch_scan_u32(flag, LS, dtot, eb, etmp, s);
+    launch_rb_live(c->bcol, eb, flag, s);
+    launch_scan_u32(flag, US, dtot, eb, etmp, s);
+    launch_rb_row_count(n, c->bptr, c->lptr, LS, US, ddeg, bdeg, s);
     launch_scan_u32(bdeg, rowp32, dtot, n, ctmp, s);
     HIPCHK(c, hipMemcpyAsync(c->h_ret, dtot, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     const int64_t nnz = (int64_t)c->h_ret[0];
-    if (nnz != 2 * c->m_live)
+    if (nnz != 2 * store_edges(c))
         return release(fail(c, DRSF_E_DEVICE, "store rebuild counted %lld entries, expected %lld",
-                            (long long)nnz, (long long)(2 * c->m_live)));
+                            (long long)nnz, (long long)(2 * store_edges(c))));
     if ((rc = dalloc(c, &col, nnz))) return release(rc);
     launch_u32_to_i64(rowp32, rowp, (int64_t)n + 1, s);
-    launch_rb_fill(n, c->bptr, c->bcol, c->lptr, c->lcol, sorted, dstart, ddeg, rowp, col, s);
+    launch_rb_fill(n, eb, c->bptr, c->bcol, c->lptr, c->lcol, LS, US, sorted, npairs, pcap2, dstart, ddeg, rowp,
+                   col, s);
     if (hipStreamSynchronize(s) != hipSuccess)
         return release(fail(c, DRSF_E_DEVICE, "store rebuild: %s", hipGetErrorString(hipGetLastError())));
     for (void *p : {(void *)pairs, (void *)sorted, (void *)npairs, (void *)stmp, (void *)ddeg, (void *)dstart,
-                    (void *)bdeg, (void *)rowp32, (void *)ctmp})
+                    (void *)bdeg, (void *)rowp32, (void *)ctmp, (void *)flag, (void *)LS, (void *)US,
+                    (void *)etmp})
         dfree(c, p);
     // past this point a failure leaves no store: the context only answers
     // reads of its forest (parent, label) until destroyed
@@ -759,6 +946,14 @@ void enqueue_update(drsf_ctx *c, int kind, bool profile) {
         (void)hipEventRecord(c->ev[PH_N + 1], s);
         (void)hipEventRecord(c->ev[PH_N + 2], s);
     }
+    const bool small = c->nsg > 0;
+    if (small) {  // the small graphs' kernel on its own branch
+        (void)hipEventRecord(c->ev_fork, s);
+        (void)hipStreamWaitEvent(c->s2, c->ev_fork, 0);
+        if (launch_small_update(d, make_small(c), c->small_threads, c->small_grid, c->s2))
+            launch_fill_i32(c->status, 1, ST_ROUND_BOUND, c->s2);
+        (void)hipEventRecord(c->ev_join, c->s2);
+    }
     mark(PH_VALIDATE);
     launch_classify(d, s);
     launch_dedupe(d, s);
@@ -796,6 +991,10 @@ void enqueue_update(drsf_ctx *c, int kind, bool profile) {
         launch_fill_i32(c->status, 1, ST_ROUND_BOUND, s);  // the library sort failed
     launch_finish(d, ins, del, !et, s);
     mark(PH_N);
+    if (small) {
+        (void)hipStreamWaitEvent(s, c->ev_join, 0);
+        launch_small_commit(d, make_small(c), grid_for(c->nsg, 1, GRID_CAP), s);
+    }
     launch_cleanup(d, s);  // also hands the results to the host
 }
 
@@ -835,6 +1034,9 @@ int continue_update(drsf_ctx *c) {
     bool bad = *(int32_t *)f != 0, done = f[1] != 0, bfs_done = f[2] == 0;
     int r = c->round_base + c->bor_fast, lv = c->bfs_fast;
     int how = 0;  // the bits of drsf_view.host_finished
+    // profiled contexts time the continuation, host round trips included
+    c->cont_timed = c->have_phases;
+    if (c->cont_timed) (void)hipEventRecord(c->ev[PH_N + 3], s);
     if (!bad && !done) {
         how |= 1;
         while (!done && !bad && r < bor_bound) {
@@ -873,6 +1075,7 @@ int continue_update(drsf_ctx *c) {
         launch_finish(d, c->kind & 1, c->kind & 2, !et, s);
     }
     launch_cleanup(d, s);  // hands the results to the host, then resets
+    if (c->cont_timed) (void)hipEventRecord(c->ev[PH_N + 4], s);
     HIPCHK(c, hipStreamSynchronize(s));
     c->view.host_finished = how ? how : 1;
     return DRSF_OK;
@@ -998,6 +1201,14 @@ static int create_impl(int32_t G, const int32_t *n_off, int32_t n, const int64_t
         fail(c, DRSF_E_ARG, "dev_alloc needs dev_free");
         return bail(DRSF_E_ARG);
     }
+    if (c->opts.small_graph_vertices < 0 || c->opts.small_graph_vertices > 16384 ||
+        (c->opts.small_threads != 0 && c->opts.small_threads != 256 && c->opts.small_threads != 512 &&
+         c->opts.small_threads != 1024)) {
+        fail(c, DRSF_E_ARG, "small_graph_vertices must be in [0, 16384] and small_threads 0, 256, 512 or 1024");
+        return bail(DRSF_E_ARG);
+    }
+    c->small_T = G > 1 ? c->opts.small_graph_vertices : 0;
+    if (c->opts.small_threads) c->small_threads = c->opts.small_threads;
     {
         const hipError_t e = hipGetDevice(&c->dev);
         if (e != hipSuccess) {
@@ -1081,6 +1292,22 @@ static int create_impl(int32_t G, const int32_t *n_off, int32_t n, const int64_t
     }
     if ((rc = alloc_state(c))) return bail(rc);
     if ((rc = canonicalise_forest(c))) return bail(rc);
+    if (c->small_T > 0) {
+        int lds_blk = 64 * 1024;
+        (void)hipDeviceGetAttribute(&lds_blk, hipDeviceAttributeMaxSharedMemoryPerBlock, c->dev);
+        if ((int64_t)small_lds_bytes(c->small_T) + 18 * 1024 > lds_blk) {
+            fail(c, DRSF_E_ARG, "small_graph_vertices %d needs more LDS than a workgroup may hold (%d bytes)",
+                 c->small_T, lds_blk);
+            return bail(DRSF_E_ARG);
+        }
+        if (small_prepare(c->small_T)) {
+            (void)hipGetLastError();
+            fail(c, DRSF_E_DEVICE, "cannot give the small-graph kernel %zu bytes of LDS", small_lds_bytes(c->small_T));
+            return bail(DRSF_E_DEVICE);
+        }
+        if ((rc = setup_small(c))) return bail(rc);
+        c->small_grid = small_grid_for(c);
+    }
     c->view.parent = c->parent;
     c->view.label = c->label;
     c->view.n = n;
@@ -1176,6 +1403,24 @@ static int check_usable(drsf_ctx *c) {
                      : DRSF_OK;
 }
 
+int drsf_set_small_schedule(drsf_ctx *c, int threads, int workgroups) {
+    if (!c) return DRSF_E_ARG;
+    if ((threads != 0 && threads != 256 && threads != 512 && threads != 1024) || workgroups < 0)
+        return fail(c, DRSF_E_ARG, "threads must be 0, 256, 512 or 1024 and workgroups >= 0");
+    const int rc = finish_pending(c);
+    if (rc) return rc;
+    if (threads) c->small_threads = threads;
+    if (c->nsg) c->small_grid = workgroups ? std::min(workgroups, c->nsg) : small_grid_for(c);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < 4; k++) {
+        if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+        if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+        c->gexec[k] = nullptr;
+        c->graph[k] = nullptr;
+    }
+    return DRSF_OK;
+}
+
 int drsf_apply_async(drsf_ctx *c, const int32_t *edges, int64_t b, int op) {
     if (!c) return DRSF_E_ARG;
     int rc;
@@ -1238,9 +1483,22 @@ int drsf_multi_apply_async(drsf_ctx *c, const int32_t *edges, const int64_t *b_o
     if (b > c->max_batch)
         return fail(c, DRSF_E_CAPACITY, "batch of %lld exceeds max_batch %lld", (long long)b,
                     (long long)c->max_batch);
+    // inserts into the edge store's list (small graphs keep their own arrays,
+    // which grow when an insert would not fit)
     int64_t nins = 0;
-    for (int32_t g = 0; g < G; g++)
-        if (op[g] == DRSF_INSERT) nins += b_off[g + 1] - b_off[g];
+    std::vector<int64_t> need;
+    for (int32_t g = 0; g < G; g++) {
+        if (op[g] != DRSF_INSERT) continue;
+        const int64_t bg = b_off[g + 1] - b_off[g];
+        const int32_t k = c->nsg ? c->g2s[g] : -1;
+        if (k < 0) {
+            nins += bg;
+        } else if (c->gm_h[g] + bg > c->scap_h[k]) {
+            if (need.empty()) need.assign((size_t)c->nsg, 0);
+            need[k] = c->gm_h[g] + bg;
+        }
+    }
+    if (!need.empty() && (rc = small_grow(c, need))) return rc;
     if (c->ndelta_bound + nins > c->dcap) {
         if (nins > c->dcap)
             return fail(c, DRSF_E_CAPACITY, "batch of %lld inserts exceeds delta_capacity %lld",
@@ -1264,12 +1522,18 @@ int drsf_multi_apply_async(drsf_ctx *c, const int32_t *edges, const int64_t *b_o
     // per-edge op and graph; vertex-block lists of the deleting and the
     // inserting graphs and the base-store tiles of the deleting ones
     bool any_ins = false, any_del = false;
+    int32_t nsmall = 0;
     for (int32_t g = 0; g < G; g++) {
+        const int32_t k = c->nsg ? c->g2s[g] : -1;
+        // op 2: the edge belongs to a small graph, whose own kernel takes it
+        const int8_t eo = k < 0 ? op[g] : (int8_t)2;
         for (int64_t i = b_off[g]; i < b_off[g + 1]; i++) {
-            c->h_bop[i] = op[g];
+            c->h_bop[i] = eo;
             c->h_bgid[i] = g;
         }
-        if (b_off[g + 1] > b_off[g]) (op[g] == DRSF_DELETE ? any_del : any_ins) = true;
+        if (b_off[g + 1] == b_off[g]) continue;
+        if (k < 0) (op[g] == DRSF_DELETE ? any_del : any_ins) = true;
+        else c->h_stasks[nsmall++] = make_int4(k, (int)b_off[g], (int)(b_off[g + 1] - b_off[g]), op[g]);
     }
     hipStream_t s = c->stream;
     // lists of -1: every vertex block and tile (one graph: the lists, only
@@ -1281,6 +1545,7 @@ int drsf_multi_apply_async(drsf_ctx *c, const int32_t *edges, const int64_t *b_o
         nvl = nil = ntl = 0;
         for (int32_t g = 0; g < G; g++) {
             if (b_off[g + 1] == b_off[g] || c->goff_h[g + 1] == c->goff_h[g]) continue;
+            if (c->nsg && c->g2s[g] >= 0) continue;  // a small graph: not in the lists
             const int64_t v0 = c->goff_h[g] / BLOCK, v1 = (c->goff_h[g + 1] - 1) / BLOCK;
             if (op[g] == DRSF_DELETE) {
                 for (int64_t j = std::max(v0, lastv + 1); j <= v1; j++) vl[nvl++] = (int32_t)j;
@@ -1299,6 +1564,8 @@ int drsf_multi_apply_async(drsf_ctx *c, const int32_t *edges, const int64_t *b_o
                                  sizeof(int32_t) * (size_t)(2 * c->nvblk + c->ntiles + 1),
                                  hipMemcpyHostToDevice, s));
     }
+    if (nsmall)
+        HIPCHK(c, hipMemcpyAsync(c->stasks, c->h_stasks, sizeof(int4) * (size_t)nsmall, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(c->bop, c->h_bop, (size_t)b, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(c->bgid, c->h_bgid, sizeof(int32_t) * (size_t)b, hipMemcpyHostToDevice, s));
     if ((rc = stage_edges(c, edges, b))) return rc;
@@ -1314,6 +1581,7 @@ int drsf_multi_apply_async(drsf_ctx *c, const int32_t *edges, const int64_t *b_o
     k.nvl = nvl;
     k.nil = nil;
     k.ntl = ntl;
+    k.nsmall = nsmall;
     c->ndelta_bound += nins;
     set_regions(c, k);
     return launch_update(c);
@@ -1343,6 +1611,7 @@ int drsf_wait(drsf_ctx *c, drsf_view *out) {
         const unsigned long long *k = c->h_ret + 1;
         int32_t st = *(int32_t *)c->h_ret;
         c->view.host_finished = 0;
+        c->cont_timed = false;
         if (st == 0 && !k[C_ORIENTED]) {  // the captured rounds did not finish it
             c->view.host_finished = 1;
             const int rc = continue_update(c);
@@ -1350,7 +1619,13 @@ int drsf_wait(drsf_ctx *c, drsf_view *out) {
             st = *(int32_t *)c->h_ret;
         }
         if (c->have_phases &&
-            hipEventElapsedTime(&c->phase_ms[PH_N], c->ev[PH_N + 1], c->ev[PH_N + 2]) != hipSuccess) {
+            hipEventElapsedTime(&c->phase_ms[PH_N + 1], c->ev[PH_N + 1], c->ev[PH_N + 2]) != hipSuccess) {
+            (void)hipGetLastError();
+            c->have_phases = false;
+        }
+        c->phase_ms[PH_N] = 0.f;
+        if (c->have_phases && c->cont_timed &&
+            hipEventElapsedTime(&c->phase_ms[PH_N], c->ev[PH_N + 3], c->ev[PH_N + 4]) != hipSuccess) {
             (void)hipGetLastError();
             c->have_phases = false;
         }
@@ -1368,10 +1643,10 @@ int drsf_wait(drsf_ctx *c, drsf_view *out) {
         if (st != 0) {
             c->last_rc = fail(c, DRSF_E_DEVICE, "internal bound exceeded (status %d)", st);
         } else {
-            c->view.num_key_cross = (int64_t)k[C_NCROSS];
-            c->view.num_replacement = (int64_t)k[C_NER];
+            c->view.num_key_cross = (int64_t)(k[C_NCROSS] + k[C_SNCROSS]);
+            c->view.num_replacement = (int64_t)(k[C_NER] + k[C_SNER]);
             c->view.num_pieces = (int64_t)k[C_NP];
-            c->view.num_paths = (int64_t)k[C_NR];
+            c->view.num_paths = (int64_t)(k[C_NR] + k[C_SNR]);
             c->view.scan_orphans = (int32_t)k[C_OMODE];
             c->view.num_orphans = (int64_t)k[C_NORPH];
             c->view.orphan_slots = (int64_t)k[C_OVOL] - (int64_t)OR_PAD * (int64_t)k[C_NORPH];
@@ -1380,7 +1655,8 @@ int drsf_wait(drsf_ctx *c, drsf_view *out) {
                 for (int32_t g = 0; g < c->ngraph; g++) {
                     const int64_t bg = c->last_bg[g];
                     if (c->h_gstat[g]) {
-                        if (c->last_opg[g] == DRSF_INSERT) c->ndelta_bound -= bg;
+                        const bool in_store = c->g2s.empty() || c->g2s[g] < 0;
+                        if (c->last_opg[g] == DRSF_INSERT && in_store) c->ndelta_bound -= bg;
                     } else {
                         const int64_t dm = c->last_opg[g] == DRSF_INSERT ? bg : -bg;
                         c->gm_h[g] += dm;
@@ -1501,6 +1777,22 @@ int drsf_export_edges(drsf_ctx *c, uint64_t *keys, int64_t capacity, int64_t *m_
             if (w >= capacity) return fail(c, DRSF_E_CAPACITY, "export buffer too small");
             keys[w++] = k;
         }
+    if (c->nsg) {  // small graphs: their own key arrays, in local ids
+        std::vector<int32_t> sm((size_t)c->nsg), sb((size_t)c->nsg);
+        std::vector<uint32_t> pk((size_t)c->pool_keys);
+        HIPCHK(c, hipMemcpyAsync(sm.data(), c->sm, 4 * sm.size(), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(sb.data(), c->sbuf, 4 * sb.size(), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(pk.data(), c->pool, 4 * pk.size(), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int32_t k = 0; k < c->nsg; k++) {
+            const uint64_t o = (uint64_t)c->goff_h[c->sgid_h[k]];
+            const uint32_t *E = pk.data() + c->soff_h[k] + (int64_t)sb[k] * c->scap_h[k];
+            for (int32_t j = 0; j < sm[k]; j++) {
+                if (w >= capacity) return fail(c, DRSF_E_CAPACITY, "export buffer too small");
+                keys[w++] = ((o + (E[j] >> 16)) << 32) | (o + (E[j] & 0xffffu));
+            }
+        }
+    }
     std::sort(keys, keys + w);
     *m_out = w;
     return DRSF_OK;
@@ -1526,7 +1818,11 @@ int drsf_snapshot_take(drsf_ctx *c, drsf_snapshot **out) {
     const bool ok = get(&s->parent, 4 * (size_t)c->n) && get(&s->label, 4 * (size_t)c->n) &&
                     get(&s->bcol, 4 * (size_t)std::max<int64_t>(c->eb, 1)) &&
                     get(&s->lcol, 4 * (size_t)std::max<int64_t>(c->eb, 1)) &&
-                    get(&s->dkey, 8 * (size_t)c->dcap) && get(&s->dhash, 8 * dh) && get(&s->dhpos, 4 * dh);
+                    get(&s->dkey, 8 * (size_t)c->dcap) && get(&s->dhash, 8 * dh) && get(&s->dhpos, 4 * dh) &&
+                    (c->nsg == 0 || (get(&s->pool, 4 * (size_t)c->pool_keys) && get(&s->sm, 4 * (size_t)c->nsg) &&
+                                     get(&s->sbuf, 4 * (size_t)c->nsg)));
+    s->pool_keys = c->pool_keys;
+    s->nsg = c->nsg;
     if (!ok) {
         drsf_snapshot_free(s);
         return fail(c, DRSF_E_NOMEM, "snapshot allocation failed");
@@ -1539,6 +1835,11 @@ int drsf_snapshot_take(drsf_ctx *c, drsf_snapshot **out) {
     HIPCHK(c, hipMemcpyAsync(s->dkey, c->dkey, 8 * (size_t)c->dcap, hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipMemcpyAsync(s->dhash, c->dhash, 8 * dh, hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipMemcpyAsync(s->dhpos, c->dhpos, 4 * dh, hipMemcpyDeviceToDevice, st));
+    if (c->nsg) {
+        HIPCHK(c, hipMemcpyAsync(s->pool, c->pool, 4 * (size_t)c->pool_keys, hipMemcpyDeviceToDevice, st));
+        HIPCHK(c, hipMemcpyAsync(s->sm, c->sm, 4 * (size_t)c->nsg, hipMemcpyDeviceToDevice, st));
+        HIPCHK(c, hipMemcpyAsync(s->sbuf, c->sbuf, 4 * (size_t)c->nsg, hipMemcpyDeviceToDevice, st));
+    }
     HIPCHK(c, hipMemcpyAsync(c->h_ret, c->cnt + C_NDELTA, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     s->ndelta = c->h_ret[0];
@@ -1552,7 +1853,8 @@ int drsf_snapshot_restore(drsf_ctx *c, const drsf_snapshot *s) {
     if (rc) return rc;
     if ((rc = check_usable(c))) return rc;
     if (s->n != c->n || s->eb != c->eb || s->dcap != c->dcap || s->dhmask != c->dhmask ||
-        s->gm.size() != c->gm_h.size() || s->rebuilds != c->rebuilds)
+        s->gm.size() != c->gm_h.size() || s->rebuilds != c->rebuilds || s->nsg != c->nsg ||
+        s->pool_keys != c->pool_keys)
         return fail(c, DRSF_E_STATE, "snapshot does not match the context's layout (taken before a "
                                      "store rebuild?)");
     hipStream_t st = c->stream;
@@ -1565,6 +1867,11 @@ int drsf_snapshot_restore(drsf_ctx *c, const drsf_snapshot *s) {
     HIPCHK(c, hipMemcpyAsync(c->dkey, s->dkey, 8 * (size_t)c->dcap, hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipMemcpyAsync(c->dhash, s->dhash, 8 * dh, hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipMemcpyAsync(c->dhpos, s->dhpos, 4 * dh, hipMemcpyDeviceToDevice, st));
+    if (c->nsg) {
+        HIPCHK(c, hipMemcpyAsync(c->pool, s->pool, 4 * (size_t)c->pool_keys, hipMemcpyDeviceToDevice, st));
+        HIPCHK(c, hipMemcpyAsync(c->sm, s->sm, 4 * (size_t)c->nsg, hipMemcpyDeviceToDevice, st));
+        HIPCHK(c, hipMemcpyAsync(c->sbuf, s->sbuf, 4 * (size_t)c->nsg, hipMemcpyDeviceToDevice, st));
+    }
     c->h_ret[0] = s->ndelta;
     HIPCHK(c, hipMemcpyAsync(c->cnt + C_NDELTA, c->h_ret, sizeof(unsigned long long), hipMemcpyHostToDevice, st));
     HIPCHK(c, hipStreamSynchronize(st));
@@ -1578,7 +1885,7 @@ int drsf_snapshot_restore(drsf_ctx *c, const drsf_snapshot *s) {
 void drsf_snapshot_free(drsf_snapshot *s) {
     if (!s) return;
     for (void *p : {(void *)s->parent, (void *)s->label, (void *)s->bcol, (void *)s->lcol, (void *)s->dkey,
-                    (void *)s->dhash, (void *)s->dhpos})
+                    (void *)s->dhash, (void *)s->dhpos, (void *)s->pool, (void *)s->sm, (void *)s->sbuf})
         raw_dfree(s->opts, p);
     delete s;
 }
@@ -1587,7 +1894,7 @@ int drsf_phase_times(drsf_ctx *c, float *ms, int cap) {
     if (!c || !ms) return 0;
     if (finish_pending(c)) return 0;
     if (!c->have_phases) return 0;
-    const int k = std::min(cap, (int)PH_N + 1);
+    const int k = std::min(cap, (int)PH_N + 2);
     for (int i = 0; i < k; i++) ms[i] = c->phase_ms[i];
     return k;
 }

@@ -23,6 +23,8 @@ struct Ctl {
     int32_t smode;    // delete sweep: 0 chosen per batch, 1 always the full store
     const int32_t *edges;  // the batch in the caller's device memory, or null: staged copy
     uint64_t seq;          // update number, written to the completion word when done
+    int32_t nsmall;        // small graphs with a batch in this update (SmallDev::tasks)
+    int32_t pad;
 };
 
 // All device pointers one apply needs; passed by value to every kernel.
@@ -148,6 +150,34 @@ struct Dev {
     unsigned long long *cnt; // [C_TOTAL]
 };
 
+// Small graphs of a multi-graph context, updated whole by one workgroup each
+// (drsf_small.hip).  Each keeps its edges as an ascending array of 32-bit
+// keys u << 16 | v (u < v, local ids) in one of two buffers of scap keys at
+// pool + soff; per-vertex scratch at svoff (the graph's first local vertex).
+struct SmallDev {
+    int32_t nsg;             // small graphs in the context
+    int32_t T;               // vertex capacity of the LDS arrays (every small graph's n <= T)
+    const int32_t *sgid;     // [nsg] graph id
+    const int64_t *soff;     // [nsg] first key of the graph's two buffers
+    const int64_t *scap;     // [nsg] keys per buffer
+    const int64_t *svoff;    // [nsg] first entry of the graph's per-vertex scratch
+    int32_t *sm;             // [nsg] live edges
+    int32_t *sbuf;           // [nsg] buffer holding them
+    int32_t *sok;            // [nsg] 1: the last update of the graph is staged for commit
+    uint32_t *pool;          // edge keys
+    uint32_t *xk;            // cross edges, graph s at soff[s] / 2 (scap keys)
+    int32_t *spar, *slab;    // staged parents and labels (global ids), per vertex
+    int2 *er;                // replacement edges (local ids), per vertex slot
+    uint32_t *bsort0, *bsort1;  // [max_b] batch keys, sorted in place (graph's batch range)
+    const int4 *tasks;       // [nsmall] (small graph, batch start, batch length, op)
+    unsigned int *qhead;     // work queue: next task (reset by the commit kernel)
+};
+size_t small_lds_bytes(int T);
+int small_prepare(int T);  // allows the kernel its LDS (once, before any launch or capture)
+int launch_small_update(const Dev &d, const SmallDev &s, int threads, int grid, hipStream_t st);
+void launch_small_commit(const Dev &d, const SmallDev &s, int grid, hipStream_t st);
+void launch_small_init(const Dev &d, const SmallDev &s, hipStream_t st);
+
 // slots per range of the orphan adjacency scan (one workgroup pass).  A
 // region of x0 (TILE entries, one per base-store tile) takes the cross edges
 // of one range, or of two consecutive ranges when the orphans hold more than
@@ -178,6 +208,11 @@ constexpr int64_t TAIL_MAX = 4096;
 constexpr int C_LR_ROUND = C_COUNT + MAX_ROUNDS;       // [MAX_ROUNDS]
 constexpr int C_BFS_ROUND = C_COUNT + 2 * MAX_ROUNDS;  // [MAX_ROUNDS]
 constexpr int C_TOTAL = C_COUNT + 3 * MAX_ROUNDS;
+// statistics of the small-graph engine (it runs beside the chain, whose
+// kernels use C_NER and C_NR as list lengths)
+constexpr int C_SNER = C_COUNT + 8;
+constexpr int C_SNCROSS = C_COUNT + 9;
+constexpr int C_SNR = C_COUNT + 10;
 
 // Grid sizes.  Workgroups are dispatched at about 200-270 per microsecond
 // across the chip, so a kernel of many short workgroups is bound by
@@ -251,20 +286,23 @@ int launch_sg_reduce(const Dev &d, int64_t nr_om, int64_t rlo2, int64_t nreg, in
                      const SgScratch &g, hipStream_t s);
 void launch_cleanup(const Dev &d, hipStream_t s);
 
-// store rebuild: live degrees of the base store, the inserted edges as
-// directed pairs (x << 32 | y, both directions), their per-row counts, and
-// the merged symmetric CSR
-void launch_rb_counts(int32_t n, const uint32_t *bptr, const int32_t *bcol, const uint32_t *lptr,
-                      const int32_t *lcol, uint32_t *deg, hipStream_t s);
+// store rebuild: live flags of the base store's halves (scanned into
+// prefix counts), the inserted edges as directed pairs (x << 32 | y, both
+// directions), their per-row counts, the merged rows' sizes, and the merged
+// symmetric CSR
+void launch_rb_live(const int32_t *col, int64_t eb, uint32_t *flag, hipStream_t s);
+void launch_rb_row_count(int32_t n, const uint32_t *bptr, const uint32_t *lptr, const uint32_t *LS,
+                         const uint32_t *US, const uint32_t *ddeg, uint32_t *deg, hipStream_t s);
 void launch_rb_pairs(const uint64_t *dkey, const unsigned long long *ndelta, uint64_t *pairs,
                      unsigned long long *npairs, int64_t cap, hipStream_t s);
 void launch_rb_pair_deg(const uint64_t *pairs, const unsigned long long *npairs, uint32_t *ddeg,
                         int64_t cap, hipStream_t s);
 void launch_add_u32(const uint32_t *a, const uint32_t *b, uint32_t *out, int64_t count, hipStream_t s);
 void launch_u32_to_i64(const uint32_t *in, int64_t *out, int64_t count, hipStream_t s);
-void launch_rb_fill(int32_t n, const uint32_t *bptr, const int32_t *bcol, const uint32_t *lptr,
-                    const int32_t *lcol, const uint64_t *pairs, const uint32_t *dstart,
-                    const uint32_t *ddeg, const int64_t *row_ptr, int32_t *col, hipStream_t s);
+void launch_rb_fill(int32_t n, int64_t eb, const uint32_t *bptr, const int32_t *bcol, const uint32_t *lptr,
+                    const int32_t *lcol, const uint32_t *LS, const uint32_t *US, const uint64_t *pairs,
+                    const unsigned long long *npairs, int64_t cap, const uint32_t *dstart, const uint32_t *ddeg,
+                    const int64_t *row_ptr, int32_t *col, hipStream_t s);
 size_t sort_u64_tmp_bytes(int64_t count);
 size_t sort_pairs_u64_tmp_bytes(int64_t count);
 int launch_sort_pairs_u64(const uint64_t *kin, uint64_t *kout, const uint64_t *vin, uint64_t *vout,
@@ -282,7 +320,9 @@ void launch_fill_u64(uint64_t *p, int64_t count, uint64_t v, hipStream_t s);
 inline void launch_fill_u64(unsigned long long *p, int64_t count, uint64_t v, hipStream_t s) {
     launch_fill_u64(reinterpret_cast<uint64_t *>(p), count, v, s);
 }
-void launch_csr_check(int32_t n, const int64_t *row_ptr, const int32_t *col, uint32_t *ucnt,
+// entries checked (ids, self-loops, ascending rows) and each row's entries
+// above the diagonal counted into ucnt
+void launch_csr_check(int32_t n, const int64_t *row_ptr, const int32_t *col, int64_t nnz, uint32_t *ucnt,
                       int32_t *status, const int32_t *goff, int32_t ngraph, hipStream_t s);
 void launch_csr_symmetric(int32_t n, const int64_t *row_ptr, const int32_t *col,
                           int32_t *status, hipStream_t s);
@@ -291,14 +331,15 @@ void launch_scan_u32(const uint32_t *in, uint32_t *out, unsigned long long *tota
                      void *tmp, hipStream_t s);
 size_t scan_tmp_bytes(int64_t n);
 void launch_upper_fill(int32_t n, const int64_t *row_ptr, const int32_t *col,
-                       const uint32_t *bptr, int32_t *bcol, hipStream_t s);
+                       const uint32_t *bptr, int32_t *bcol, int64_t eb, hipStream_t s);
 // lower half: counts (row length minus upper count), then the row prefixes
 void launch_lower_counts(int32_t n, const int64_t *row_ptr, const uint32_t *bptr, uint32_t *lcnt,
                          hipStream_t s);
 void launch_lower_fill(int32_t n, const int64_t *row_ptr, const int32_t *col,
-                       const uint32_t *lptr, int32_t *lcol, hipStream_t s);
+                       const uint32_t *lptr, int32_t *lcol, int64_t eb, hipStream_t s);
 void launch_twin(int32_t n, const uint32_t *bptr, const int32_t *bcol, const uint32_t *lptr,
-                 const int32_t *lcol, uint32_t *twin, uint32_t *ltwin, int32_t *status, hipStream_t s);
+                 const int32_t *lcol, uint32_t *twin, uint32_t *ltwin, int32_t *status, int64_t eb,
+                 hipStream_t s);
 // non-empty row index: flags -> (scan) -> zrow/zptr, then tile_k
 void launch_nonempty_flags(int32_t n, const uint32_t *bptr, uint32_t *flag, hipStream_t s);
 void launch_nonempty_fill(int32_t n, const uint32_t *bptr, const uint32_t *zpos, int32_t *zrow,

@@ -106,6 +106,20 @@ __device__ void dhash_insert(const Dev &d, uint64_t k, int32_t pos) {
     atomicOr(d.status, ST_CAPACITY);
 }
 
+// Row holding slot j of a CSR with offsets ptr[0..n]: the largest u with
+// ptr[u] <= j (empty rows share their start with the next row, so the
+// largest such u is the row that holds j).
+template <class P>
+__device__ __forceinline__ int32_t row_of(const P *ptr, int32_t n, int64_t j) {
+    int32_t a = 0, b = n - 1;
+    while (a < b) {
+        const int32_t mid = a + ((b - a + 1) >> 1);
+        if ((int64_t)ptr[mid] <= j) a = mid;
+        else b = mid - 1;
+    }
+    return a;
+}
+
 __device__ __forceinline__ bool obit(const uint64_t *bits, int32_t v) {
     return (bits[v >> 6] >> (v & 63)) & 1;
 }
@@ -264,12 +278,16 @@ __global__ __launch_bounds__(BLOCK) void k_classify(Dev d) {
     const int32_t *be = hc->edges ? hc->edges : d.bedges;  // caller's device batch, or the staged one
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < b; i += stride) {
-        const int32_t u = be[2 * i], v = be[2 * i + 1];
-        const int32_t g = edge_graph(d, i);
-        const int32_t lo_ok = d.goff ? d.goff[g] : 0, hi_ok = d.goff ? d.goff[g + 1] : d.n;
         d.bslot[i] = NONE;
         d.bchild[i] = NONE;
         d.bloc[i] = 0;
+        if (opm == 2 && d.bop[i] == 2) {  // a small graph's edge: its own kernel takes it
+            d.bkey[i] = 0;
+            continue;
+        }
+        const int32_t u = be[2 * i], v = be[2 * i + 1];
+        const int32_t g = edge_graph(d, i);
+        const int32_t lo_ok = d.goff ? d.goff[g] : 0, hi_ok = d.goff ? d.goff[g + 1] : d.n;
         if (u < lo_ok || v < lo_ok || u >= hi_ok || v >= hi_ok || u == v) {
             atomicOr(&d.gstat[g], ST_BAD_PAIR);
             d.bkey[i] = 0;
@@ -394,7 +412,7 @@ __global__ __launch_bounds__(BLOCK) void k_prepare(Dev d, int gb) {
     const int64_t stride = (int64_t)gb * BLOCK;
     for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < b; base += stride) {
         const int64_t i = base + threadIdx.x;
-        const bool valid = i < b && edge_ok(d, i);
+        const bool valid = i < b && edge_op(d, i) != 2 && edge_ok(d, i);
         const int op = valid ? edge_op(d, i) : -1;
         if (op == 1) {
             const int64_t loc = d.bloc[i];
@@ -442,7 +460,7 @@ __global__ __launch_bounds__(BLOCK) void k_register(Dev d) {
         const int64_t i = base + threadIdx.x;
         int32_t a = NONE, c2 = NONE;
         bool del = false;
-        if (i < b && edge_ok(d, i)) {
+        if (i < b && edge_op(d, i) != 2 && edge_ok(d, i)) {
             del = edge_op(d, i) == 1;
             if (del) {
                 const int32_t c = d.bchild[i];
@@ -478,7 +496,7 @@ __global__ __launch_bounds__(BLOCK) void k_insert_emit(Dev d) {
     bool cross = false;
     uint64_t k = 0;
     int32_t la = 0, lb = 0;
-    if (i < b && edge_ok(d, i) && edge_op(d, i) == 0) {
+    if (i < b && edge_op(d, i) == 0 && edge_ok(d, i)) {
         k = d.bkey[i];
         la = d.label[key_lo(k)];
         lb = d.label[key_hi(k)];
@@ -2229,26 +2247,6 @@ void launch_cleanup(const Dev &d, hipStream_t s) {
 
 // ------------------------------------------------------ store rebuild
 
-// live entries of each row (upper and lower halves), one wave per row
-__global__ __launch_bounds__(BLOCK) void k_rb_counts(int32_t n, const uint32_t *bptr, const int32_t *bcol,
-                                                     const uint32_t *lptr, const int32_t *lcol,
-                                                     uint32_t *deg) {
-    const int64_t nw = (int64_t)gridDim.x * (BLOCK / WAVE);
-    const int lane = lane_id();
-    for (int64_t u = (int64_t)blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE; u < n; u += nw) {
-        uint32_t c = 0;
-        for (int64_t j = (int64_t)bptr[u] + lane; j < (int64_t)bptr[u + 1]; j += WAVE) c += bcol[j] >= 0;
-        for (int64_t j = (int64_t)lptr[u] + lane; j < (int64_t)lptr[u + 1]; j += WAVE) c += lcol[j] >= 0;
-        for (int o = WAVE / 2; o > 0; o >>= 1) c += __shfl_xor(c, o);
-        if (lane == 0) deg[u] = c;
-    }
-}
-void launch_rb_counts(int32_t n, const uint32_t *bptr, const int32_t *bcol, const uint32_t *lptr,
-                      const int32_t *lcol, uint32_t *deg, hipStream_t s) {
-    hipLaunchKernelGGL(k_rb_counts, dim3(grid_for((int64_t)n * WAVE, BLOCK, GRID_CAP)), dim3(BLOCK), 0, s,
-                       n, bptr, bcol, lptr, lcol, deg);
-}
-
 // live inserted edges as directed pairs in both directions
 __global__ __launch_bounds__(BLOCK) void k_rb_pairs(const uint64_t *dkey, const unsigned long long *ndelta,
                                                     uint64_t *pairs, unsigned long long *npairs,
@@ -2301,47 +2299,99 @@ void launch_u32_to_i64(const uint32_t *in, int64_t *out, int64_t count, hipStrea
     hipLaunchKernelGGL(k_u32_to_i64, dim3(grid_for(count, BLOCK, GRID_CAP)), dim3(BLOCK), 0, s, in, out, count);
 }
 
-// Row u of the merged symmetric CSR: its live lower entries, then its live
+// The merged symmetric CSR is written slot-parallel (a hub row holds
+// hundreds of thousands of entries; a thread or a wave per row leaves it to
+// one lane).  Row u of the merge is its live lower entries, then its live
 // upper entries (together ascending), merged with its inserted neighbours
-// (ascending in the sorted pairs).  One thread per row.
-__global__ void k_rb_fill(int32_t n, const uint32_t *bptr, const int32_t *bcol, const uint32_t *lptr,
-                          const int32_t *lcol, const uint64_t *pairs, const uint32_t *dstart,
-                          const uint32_t *ddeg, const int64_t *row_ptr, int32_t *col) {
+// (ascending in the sorted pairs).  With LS / US the exclusive prefix counts
+// of live entries over the lower / upper halves, a live base entry's place
+// is its live rank in the row plus the inserted neighbours below it, and an
+// inserted neighbour's place is its rank among the row's inserted ones plus
+// the live base entries below it.
+__global__ void k_rb_live(const int32_t *col, int64_t eb, uint32_t *flag) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
-        int64_t w = row_ptr[u];
-        uint64_t a = lptr[u];
-        const uint64_t ae = lptr[u + 1], bs = bptr[u], be = bptr[u + 1];
-        uint64_t b = bs;
-        uint64_t q = dstart[u];
-        const uint64_t qe = q + ddeg[u];
-        while (true) {
-            // next live base entry (lower run first, then upper run)
-            int32_t x = -1;
-            while (a < ae && lcol[a] < 0) a++;
-            if (a < ae) {
-                x = lcol[a];
-            } else {
-                while (b < be && bcol[b] < 0) b++;
-                if (b < be) x = bcol[b];
-            }
-            const int32_t y = q < qe ? (int32_t)(uint32_t)pairs[q] : -1;
-            if (x < 0 && y < 0) break;
-            if (y < 0 || (x >= 0 && x < y)) {
-                col[w++] = x;
-                if (a < ae) a++; else b++;
-            } else {
-                col[w++] = y;
-                q++;
-            }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < eb; i += stride) flag[i] = col[i] >= 0;
+}
+// live base entries per row plus its inserted neighbours
+__global__ void k_rb_row_count(int32_t n, const uint32_t *bptr, const uint32_t *lptr, const uint32_t *LS,
+                               const uint32_t *US, const uint32_t *ddeg, uint32_t *deg) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride)
+        deg[u] = (LS[lptr[u + 1]] - LS[lptr[u]]) + (US[bptr[u + 1]] - US[bptr[u]]) + ddeg[u];
+}
+// number of keys in the row's sorted inserted neighbours pairs[q0, q0 + cnt) below x
+__device__ __forceinline__ uint32_t ins_below(const uint64_t *pairs, uint64_t q0, uint32_t cnt, int32_t x) {
+    uint32_t a = 0, b = cnt;
+    while (a < b) {
+        const uint32_t mid = (a + b) >> 1;
+        if ((int32_t)(uint32_t)pairs[q0 + mid] < x) a = mid + 1;
+        else b = mid;
+    }
+    return a;
+}
+// live entries of col[lo, hi) (ascending by id, deleted ones included) below y
+__device__ __forceinline__ uint32_t live_below(const int32_t *col, const uint32_t *S, uint32_t lo, uint32_t hi,
+                                               int32_t y) {
+    uint32_t a = lo, b = hi;
+    while (a < b) {
+        const uint32_t mid = (a + b) >> 1;
+        if ((col[mid] & COLMASK) < y) a = mid + 1;
+        else b = mid;
+    }
+    return S[a] - S[lo];
+}
+__global__ void k_rb_fill_base(int32_t n, int64_t eb, const uint32_t *bptr, const int32_t *bcol,
+                               const uint32_t *lptr, const int32_t *lcol, const uint32_t *LS, const uint32_t *US,
+                               const uint64_t *pairs, const uint32_t *dstart, const uint32_t *ddeg,
+                               const int64_t *row_ptr, int32_t *col) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < 2 * eb; t += stride) {
+        const bool lower = t < eb;
+        const int64_t j = lower ? t : t - eb;
+        const int32_t x = lower ? lcol[j] : bcol[j];
+        if (x < 0) continue;  // deleted
+        int32_t u;
+        uint32_t rank;
+        if (lower) {
+            u = row_of(lptr, n, j);
+            rank = LS[j] - LS[lptr[u]];
+        } else {
+            u = row_of(bptr, n, j);
+            rank = (LS[lptr[u + 1]] - LS[lptr[u]]) + (US[j] - US[bptr[u]]);
         }
+        col[row_ptr[u] + rank + ins_below(pairs, dstart[u], ddeg[u], x)] = x;
     }
 }
-void launch_rb_fill(int32_t n, const uint32_t *bptr, const int32_t *bcol, const uint32_t *lptr,
-                    const int32_t *lcol, const uint64_t *pairs, const uint32_t *dstart,
-                    const uint32_t *ddeg, const int64_t *row_ptr, int32_t *col, hipStream_t s) {
-    hipLaunchKernelGGL(k_rb_fill, dim3(grid_for(n, BLOCK, GRID_CAP)), dim3(BLOCK), 0, s, n, bptr, bcol, lptr,
-                       lcol, pairs, dstart, ddeg, row_ptr, col);
+__global__ void k_rb_fill_ins(int32_t n, const uint32_t *bptr, const int32_t *bcol, const uint32_t *lptr,
+                              const int32_t *lcol, const uint32_t *LS, const uint32_t *US, const uint64_t *pairs,
+                              const unsigned long long *npairs, int64_t cap, const uint32_t *dstart,
+                              const int64_t *row_ptr, int32_t *col) {
+    const int64_t np = (int64_t)*npairs < cap ? (int64_t)*npairs : cap;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < np; q += stride) {
+        const int32_t u = (int32_t)(pairs[q] >> 32), y = (int32_t)(uint32_t)pairs[q];
+        const uint32_t below = live_below(lcol, LS, lptr[u], lptr[u + 1], y) +
+                               live_below(bcol, US, bptr[u], bptr[u + 1], y);
+        col[row_ptr[u] + (q - (int64_t)dstart[u]) + below] = y;
+    }
+}
+void launch_rb_live(const int32_t *col, int64_t eb, uint32_t *flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_rb_live, dim3(grid_for(eb, BLOCK, 1 << 16)), dim3(BLOCK), 0, s, col, eb, flag);
+}
+void launch_rb_row_count(int32_t n, const uint32_t *bptr, const uint32_t *lptr, const uint32_t *LS,
+                         const uint32_t *US, const uint32_t *ddeg, uint32_t *deg, hipStream_t s) {
+    hipLaunchKernelGGL(k_rb_row_count, dim3(grid_for(n, BLOCK, 1 << 14)), dim3(BLOCK), 0, s, n, bptr, lptr, LS,
+                       US, ddeg, deg);
+}
+void launch_rb_fill(int32_t n, int64_t eb, const uint32_t *bptr, const int32_t *bcol, const uint32_t *lptr,
+                    const int32_t *lcol, const uint32_t *LS, const uint32_t *US, const uint64_t *pairs,
+                    const unsigned long long *npairs, int64_t cap, const uint32_t *dstart, const uint32_t *ddeg,
+                    const int64_t *row_ptr, int32_t *col, hipStream_t s) {
+    if (eb > 0)
+        hipLaunchKernelGGL(k_rb_fill_base, dim3(grid_for(2 * eb, BLOCK, 1 << 16)), dim3(BLOCK), 0, s, n, eb, bptr,
+                           bcol, lptr, lcol, LS, US, pairs, dstart, ddeg, row_ptr, col);
+    hipLaunchKernelGGL(k_rb_fill_ins, dim3(grid_for(cap, BLOCK, 1 << 14)), dim3(BLOCK), 0, s, n, bptr, bcol, lptr,
+                       lcol, LS, US, pairs, npairs, cap, dstart, row_ptr, col);
 }
 
 // ------------------------------------------------------------ digests
@@ -2388,17 +2438,20 @@ void launch_fill_u64(uint64_t *p, int64_t count, uint64_t v, hipStream_t s) {
         hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(count, BLOCK, GRID_CAP)), dim3(BLOCK), 0, s, p, count, v);
 }
 
-// One wave per row: ids in range (inside the row's graph when several graphs
-// share the context), no self-loop, strictly ascending; count the entries
-// above the diagonal (the upper half keeps each edge once).
-__global__ __launch_bounds__(BLOCK) void k_csr_check(int32_t n, const int64_t *row_ptr,
-                                                     const int32_t *col, uint32_t *ucnt,
-                                                     int32_t *status, const int32_t *goff,
+// Create-time kernels walk the CSR's entries, not its rows, one thread per
+// entry (its row by a search in the offsets): a power-law graph's hub rows
+// hold hundreds of thousands of entries, and a wave per row left one wave
+// walking a hub alone while the rest of the device idled.
+
+// Every entry: id in range (of the row's graph), no self-loop, row strictly
+// ascending.
+__global__ __launch_bounds__(BLOCK) void k_csr_check(int32_t n, const int64_t *row_ptr, const int32_t *col,
+                                                     int64_t nnz, int32_t *status, const int32_t *goff,
                                                      int32_t ngraph) {
-    const int64_t nw = (int64_t)gridDim.x * (BLOCK / WAVE);
-    const int lane = lane_id();
-    for (int64_t u = (int64_t)blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE; u < n; u += nw) {
-        const int64_t s = row_ptr[u], e = row_ptr[u + 1];
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    int bad = 0;
+    for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j < nnz; j += stride) {
+        const int32_t u = row_of(row_ptr, n, j);
         int32_t lo = 0, hi = n;
         if (goff) {  // graph of row u: largest g with goff[g] <= u
             int32_t a = 0, b = ngraph - 1;
@@ -2409,28 +2462,34 @@ __global__ __launch_bounds__(BLOCK) void k_csr_check(int32_t n, const int64_t *r
             lo = goff[a];
             hi = goff[a + 1];
         }
-        int bad = 0;
-        int64_t above = 0;
-        for (int64_t j = s + lane; j < e; j += WAVE) {
-            const int32_t c = col[j];
-            if (c < lo || c >= hi || c == u) bad = 1;
-            if (j + 1 < e && col[j + 1] <= c) bad = 1;
-            above += c > u;
+        const int32_t c = col[j];
+        if (c < lo || c >= hi || c == u) bad = 1;
+        if (j + 1 < row_ptr[u + 1] && col[j + 1] <= c) bad = 1;
+    }
+    if (__ballot(bad) && lane_id() == 0) atomicOr(status, 1);
+}
+// Entries above the diagonal per row (rows ascending: one search each).
+__global__ __launch_bounds__(BLOCK) void k_upper_counts(int32_t n, const int64_t *row_ptr, const int32_t *col,
+                                                        uint32_t *ucnt) {
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t u = (int64_t)blockIdx.x * BLOCK + threadIdx.x; u < n; u += stride) {
+        int64_t a = row_ptr[u], b = row_ptr[u + 1];
+        const int64_t e = b;
+        while (a < b) {  // first entry > u
+            const int64_t mid = (a + b) >> 1;
+            if (col[mid] <= (int32_t)u) a = mid + 1;
+            else b = mid;
         }
-        for (int o = WAVE / 2; o > 0; o >>= 1) {
-            above += __shfl_xor(above, o);
-            bad |= __shfl_xor(bad, o);
-        }
-        if (lane == 0) {
-            if (bad) atomicOr(status, 1);
-            ucnt[u] = (uint32_t)above;
-        }
+        ucnt[u] = (uint32_t)(e - a);
     }
 }
-void launch_csr_check(int32_t n, const int64_t *row_ptr, const int32_t *col, uint32_t *ucnt,
+void launch_csr_check(int32_t n, const int64_t *row_ptr, const int32_t *col, int64_t nnz, uint32_t *ucnt,
                       int32_t *status, const int32_t *goff, int32_t ngraph, hipStream_t s) {
-    hipLaunchKernelGGL(k_csr_check, dim3(grid_for((int64_t)n * WAVE, BLOCK, GRID_CAP)), dim3(BLOCK),
-                       0, s, n, row_ptr, col, ucnt, status, goff, ngraph);
+    if (nnz > 0)
+        hipLaunchKernelGGL(k_csr_check, dim3(grid_for(nnz, BLOCK, 1 << 16)), dim3(BLOCK), 0, s, n, row_ptr, col,
+                           nnz, status, goff, ngraph);
+    hipLaunchKernelGGL(k_upper_counts, dim3(grid_for(n, BLOCK, 1 << 14)), dim3(BLOCK), 0, s, n, row_ptr, col,
+                       ucnt);
 }
 
 // Every entry (u, c) must have its mirror (c, u).
@@ -2539,23 +2598,22 @@ void launch_scan_u32(const uint32_t *in, uint32_t *out, unsigned long long *tota
                        n, bsum, total);
 }
 
-// copy the upper-half suffix of every (ascending) row
+// copy the upper-half suffix of every (ascending) row, one thread per stored entry
 __global__ __launch_bounds__(BLOCK) void k_upper_fill(int32_t n, const int64_t *row_ptr,
                                                       const int32_t *col, const uint32_t *bptr,
-                                                      int32_t *bcol) {
-    const int64_t nw = (int64_t)gridDim.x * (BLOCK / WAVE);
-    const int lane = lane_id();
-    for (int64_t u = (int64_t)blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE; u < n; u += nw) {
-        const int64_t e = row_ptr[u + 1];
+                                                      int32_t *bcol, int64_t eb) {
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < eb; p += stride) {
+        const int32_t u = row_of(bptr, n, p);
         const int64_t cntu = (int64_t)bptr[u + 1] - bptr[u];
-        const int64_t s = e - cntu;
-        for (int64_t j = lane; j < cntu; j += WAVE) bcol[bptr[u] + j] = col[s + j];
+        bcol[p] = col[row_ptr[u + 1] - cntu + (p - (int64_t)bptr[u])];
     }
 }
 void launch_upper_fill(int32_t n, const int64_t *row_ptr, const int32_t *col, const uint32_t *bptr,
-                       int32_t *bcol, hipStream_t s) {
-    hipLaunchKernelGGL(k_upper_fill, dim3(grid_for((int64_t)n * WAVE, BLOCK, GRID_CAP)), dim3(BLOCK),
-                       0, s, n, row_ptr, col, bptr, bcol);
+                       int32_t *bcol, int64_t eb, hipStream_t s) {
+    if (eb > 0)
+        hipLaunchKernelGGL(k_upper_fill, dim3(grid_for(eb, BLOCK, 1 << 16)), dim3(BLOCK), 0, s, n, row_ptr, col,
+                           bptr, bcol, eb);
 }
 
 // lower half: the prefix of every ascending row below the diagonal
@@ -2572,45 +2630,43 @@ void launch_lower_counts(int32_t n, const int64_t *row_ptr, const uint32_t *bptr
 }
 __global__ __launch_bounds__(BLOCK) void k_lower_fill(int32_t n, const int64_t *row_ptr,
                                                       const int32_t *col, const uint32_t *lptr,
-                                                      int32_t *lcol) {
-    const int64_t nw = (int64_t)gridDim.x * (BLOCK / WAVE);
-    const int lane = lane_id();
-    for (int64_t u = (int64_t)blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE; u < n; u += nw) {
-        const int64_t s = row_ptr[u];
-        const int64_t cntu = (int64_t)lptr[u + 1] - lptr[u];
-        for (int64_t j = lane; j < cntu; j += WAVE) lcol[lptr[u] + j] = col[s + j];
+                                                      int32_t *lcol, int64_t eb) {
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x; q < eb; q += stride) {
+        const int32_t v = row_of(lptr, n, q);
+        lcol[q] = col[row_ptr[v] + (q - (int64_t)lptr[v])];
     }
 }
 void launch_lower_fill(int32_t n, const int64_t *row_ptr, const int32_t *col, const uint32_t *lptr,
-                       int32_t *lcol, hipStream_t s) {
-    hipLaunchKernelGGL(k_lower_fill, dim3(grid_for((int64_t)n * WAVE, BLOCK, GRID_CAP)), dim3(BLOCK),
-                       0, s, n, row_ptr, col, lptr, lcol);
+                       int32_t *lcol, int64_t eb, hipStream_t s) {
+    if (eb > 0)
+        hipLaunchKernelGGL(k_lower_fill, dim3(grid_for(eb, BLOCK, 1 << 16)), dim3(BLOCK), 0, s, n, row_ptr, col,
+                           lptr, lcol, eb);
 }
 // twin[p]: position in the lower half of the mirror of upper entry p (one
-// wave per row v walks its lower entries u and finds v in upper row u)
+// thread per lower entry q = (v, u), u < v, finds v in upper row u)
 __global__ __launch_bounds__(BLOCK) void k_twin(int32_t n, const uint32_t *bptr, const int32_t *bcol,
                                                 const uint32_t *lptr, const int32_t *lcol,
-                                                uint32_t *twin, uint32_t *ltwin, int32_t *status) {
-    const int64_t nw = (int64_t)gridDim.x * (BLOCK / WAVE);
-    const int lane = lane_id();
-    for (int64_t v = (int64_t)blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE; v < n; v += nw) {
-        for (int64_t q = (int64_t)lptr[v] + lane; q < (int64_t)lptr[v + 1]; q += WAVE) {
-            const int32_t u = lcol[q];
-            int32_t raw;
-            const int64_t p = find_in_row(bcol, bptr[u], bptr[u + 1], (int32_t)v, &raw);
-            if (p < 0) {
-                atomicOr(status, 2);
-            } else {
-                twin[p] = (uint32_t)q;
-                ltwin[q] = (uint32_t)p;
-            }
+                                                uint32_t *twin, uint32_t *ltwin, int32_t *status, int64_t eb) {
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x; q < eb; q += stride) {
+        const int32_t v = row_of(lptr, n, q);
+        const int32_t u = lcol[q];
+        int32_t raw;
+        const int64_t p = find_in_row(bcol, bptr[u], bptr[u + 1], v, &raw);
+        if (p < 0) {
+            atomicOr(status, 2);
+        } else {
+            twin[p] = (uint32_t)q;
+            ltwin[q] = (uint32_t)p;
         }
     }
 }
 void launch_twin(int32_t n, const uint32_t *bptr, const int32_t *bcol, const uint32_t *lptr,
-                 const int32_t *lcol, uint32_t *twin, uint32_t *ltwin, int32_t *status, hipStream_t s) {
-    hipLaunchKernelGGL(k_twin, dim3(grid_for((int64_t)n * WAVE, BLOCK, GRID_CAP)), dim3(BLOCK), 0, s,
-                       n, bptr, bcol, lptr, lcol, twin, ltwin, status);
+                 const int32_t *lcol, uint32_t *twin, uint32_t *ltwin, int32_t *status, int64_t eb, hipStream_t s) {
+    if (eb > 0)
+        hipLaunchKernelGGL(k_twin, dim3(grid_for(eb, BLOCK, 1 << 16)), dim3(BLOCK), 0, s, n, bptr, bcol, lptr,
+                           lcol, twin, ltwin, status, eb);
 }
 
 // Non-empty-row index of the upper-half store (used by the sweep).
@@ -2704,19 +2760,21 @@ void launch_roots_check(int32_t n, const int32_t *parent, const int32_t *root, i
                        root, status);
 }
 
-// no edge of G may join two trees (trees span components)
+// no edge of G may join two trees (trees span components); one thread per
+// stored entry
 __global__ __launch_bounds__(BLOCK) void k_span_check(Dev d, const int32_t *root) {
-    const int64_t nw = (int64_t)gridDim.x * (BLOCK / WAVE);
-    const int lane = lane_id();
-    for (int64_t u = (int64_t)blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE; u < d.n; u += nw) {
-        const int32_t ru = root[u];
-        for (int64_t j = (int64_t)d.bptr[u] + lane; j < (int64_t)d.bptr[u + 1]; j += WAVE)
-            if (root[d.bcol[j]] != ru) atomicOr(d.status, 8);
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    int bad = 0;
+    for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < d.eb; p += stride) {
+        const int32_t c = d.bcol[p];
+        if (c < 0) continue;  // deleted (padding)
+        if (root[c] != root[row_of(d.bptr, d.n, p)]) bad = 1;
     }
+    if (__ballot(bad) && lane_id() == 0) atomicOr(d.status, 8);
 }
 void launch_span_check(const Dev &d, const int32_t *root, hipStream_t s) {
-    hipLaunchKernelGGL(k_span_check, dim3(grid_for((int64_t)d.n * WAVE, BLOCK, GRID_CAP)), dim3(BLOCK),
-                       0, s, d, root);
+    if (d.eb > 0)
+        hipLaunchKernelGGL(k_span_check, dim3(grid_for(d.eb, BLOCK, 1 << 16)), dim3(BLOCK), 0, s, d, root);
 }
 
 // label[r] <- smallest vertex of r's tree (label pre-filled with INT32_MAX),

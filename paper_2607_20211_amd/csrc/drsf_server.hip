@@ -546,6 +546,28 @@ int32_t drsf_server_tenant_state(drsf_server *s, int32_t tenant) {
     return (int32_t)s->tenants[tenant].state;
 }
 
+int drsf_server_copy_out(drsf_server *s, int32_t tenant, int32_t *parent_host, int32_t *label_host) {
+    if (!s) return DRSF_E_ARG;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (tenant < 0 || tenant >= (int32_t)s->tenants.size()) return sfail(s, DRSF_E_ARG, "unknown tenant");
+    // the scheduler uses a tenant's context only while holding the lock, so
+    // an idle tenant's context is free while the lock is held here
+    auto idle = [&] {
+        const Tenant &t = s->tenants[tenant];
+        if (t.state != T_LIVE) return true;
+        if (t.inflight >= 0 || !t.fifo.empty()) return false;
+        for (auto &fr : s->future_reqs)
+            if (s->reqs[fr.second].tenant == tenant) return false;
+        return true;
+    };
+    if (s->started) s->cv_done.wait(lk, idle);
+    Tenant &t = s->tenants[tenant];
+    if (t.state != T_LIVE || !t.ctx) return sfail(s, DRSF_E_STATE, "the tenant is not live");
+    const int rc = drsf_copy_out(t.ctx, parent_host, label_host);
+    if (rc != DRSF_OK) return sfail(s, rc, drsf_last_error(t.ctx));
+    return DRSF_OK;
+}
+
 void drsf_server_destroy(drsf_server *s) {
     if (!s) return;
     {

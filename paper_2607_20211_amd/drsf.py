@@ -22,7 +22,7 @@ DRSF_E_BUDGET = -8
 DRSF_SERVER_DIGESTS, DRSF_SERVER_SERIAL, DRSF_SERVER_COALESCE = 1, 2, 4
 PHASES = ("validate", "update_graph", "root_finding", "orphan_list", "orphan_scan",
           "store_sweep", "batch_and_inserted_scan", "replacement_edges", "superforest_rooting",
-          "reversal_and_labels")
+          "reversal_and_labels", "host_continuation")
 # the entry after the phases in drsf_phase_times: two events back to back (the fixed cost
 # of the event record that every phase time includes)
 EVENT_BRACKET = "event_bracket"
@@ -42,7 +42,9 @@ class drsf_opts(ctypes.Structure):
                 ("replacement_mode", ctypes.c_int),
                 ("dev_alloc", ctypes.c_void_p),
                 ("dev_free", ctypes.c_void_p),
-                ("alloc_user", ctypes.c_void_p)]
+                ("alloc_user", ctypes.c_void_p),
+                ("small_graph_vertices", ctypes.c_int),
+                ("small_threads", ctypes.c_int)]
 
 
 # device allocator hooks of drsf_opts
@@ -77,11 +79,12 @@ EXPORTS = ("drsf_default_opts", "drsf_create", "drsf_apply", "drsf_apply_async",
            "drsf_snapshot_take", "drsf_snapshot_restore", "drsf_snapshot_free",
            "drsf_phase_times", "drsf_destroy", "drsf_last_error", "drsf_version",
            "drsf_multi_create", "drsf_multi_apply", "drsf_multi_apply_async", "drsf_multi_wait",
-           "drsf_multi_num_edges", "drsf_num_graphs", "drsf_set_tuning", "drsf_digest",
+           "drsf_multi_num_edges", "drsf_num_graphs", "drsf_set_tuning", "drsf_set_small_schedule",
+           "drsf_digest",
            "drsf_device_bytes", "drsf_footprint", "drsf_server_create", "drsf_server_admit",
            "drsf_server_submit", "drsf_server_release", "drsf_server_start",
            "drsf_server_wait_all", "drsf_server_result", "drsf_server_batch", "drsf_server_stats",
-           "drsf_server_tenant_state", "drsf_server_error", "drsf_server_destroy",
+           "drsf_server_tenant_state", "drsf_server_copy_out", "drsf_server_error", "drsf_server_destroy",
            "drsf_static_forest", "drsf_static_forest_noalloc")
 
 _lib = None
@@ -150,6 +153,8 @@ def load():
     lib.drsf_num_graphs.restype = c_int
     lib.drsf_set_tuning.argtypes = [vp, c_int, c_int, c_int]
     lib.drsf_set_tuning.restype = c_int
+    lib.drsf_set_small_schedule.argtypes = [vp, c_int, c_int]
+    lib.drsf_set_small_schedule.restype = c_int
     lib.drsf_digest.argtypes = [vp, vp]
     lib.drsf_digest.restype = c_int
     lib.drsf_device_bytes.argtypes = [vp]
@@ -180,6 +185,8 @@ def load():
     lib.drsf_server_stats.restype = c_int
     lib.drsf_server_tenant_state.argtypes = [vp, i32]
     lib.drsf_server_tenant_state.restype = i32
+    lib.drsf_server_copy_out.argtypes = [vp, i32, vp, vp]
+    lib.drsf_server_copy_out.restype = c_int
     lib.drsf_server_error.argtypes = [vp]
     lib.drsf_server_error.restype = ctypes.c_char_p
     lib.drsf_server_destroy.argtypes = [vp]
@@ -415,6 +422,10 @@ def drsf_set_tuning(ctx, rounds_queued: int = 0, levels_queued: int = 0, sweep_m
     _check(load().drsf_set_tuning(ctx, rounds_queued, levels_queued, sweep_mode), ctx)
 
 
+def drsf_set_small_schedule(ctx, threads: int = 0, workgroups: int = 0) -> None:
+    _check(load().drsf_set_small_schedule(ctx, threads, workgroups), ctx)
+
+
 def drsf_digest(ctx) -> tuple:
     out = np.zeros(2, dtype=np.uint64)
     _check(load().drsf_digest(ctx, out.ctypes.data), ctx)
@@ -576,7 +587,8 @@ class MultiForest(Forest):
                  stream=None, inputs_on_device: bool = False, validate: bool = True,
                  profile: bool = False, delta_capacity: int = 0, sweep_mode: int = 0,
                  rounds_queued: int = 0, levels_queued: int = 0, reverse_mode: int = 0,
-                 replacement_mode: int = 0, allocator: TorchAllocator | None = None):
+                 replacement_mode: int = 0, allocator: TorchAllocator | None = None,
+                 small_graph_vertices: int = 0, small_threads: int = 0):
         self.on_device = bool(inputs_on_device)
         if not self.on_device:
             row_ptr = _host_input(row_ptr, np.int64)
@@ -599,6 +611,8 @@ class MultiForest(Forest):
         o.levels_queued = levels_queued
         o.reverse_mode = reverse_mode
         o.replacement_mode = replacement_mode
+        o.small_graph_vertices = small_graph_vertices
+        o.small_threads = small_threads
         if stream is not None:
             o.stream = stream
         self.allocator = allocator
@@ -633,6 +647,9 @@ class MultiForest(Forest):
 
     def num_edges(self) -> np.ndarray:
         return drsf_multi_num_edges(self.ctx, self.G)
+
+    def set_small_schedule(self, threads: int = 0, workgroups: int = 0) -> None:
+        drsf_set_small_schedule(self.ctx, threads, workgroups)
 
 
 # ---- serving ------------------------------------------------------------------
@@ -708,6 +725,13 @@ class Server:
 
     def tenant_state(self, tenant: int) -> int:
         return int(load().drsf_server_tenant_state(self.srv, tenant))
+
+    def copy_out(self, tenant: int, n: int):
+        """(parent, label) of a live tenant once its submitted requests are done."""
+        p = np.empty(n, dtype=np.int32)
+        lab = np.empty(n, dtype=np.int32)
+        _scheck(load().drsf_server_copy_out(self.srv, tenant, p.ctypes.data, lab.ctypes.data), self.srv)
+        return p, lab
 
     def close(self) -> None:
         if self.srv is not None:

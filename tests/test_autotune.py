@@ -43,3 +43,45 @@ def test_tune_picks_fastest_and_caches(tmp_path, monkeypatch):
     f2 = FakeForest(lambda s: 5.0)
     r2 = autotune.tune(f2, sample, "k1")
     assert r2["cached"] and f2.setting == best and f2.restores == 0
+
+
+class FakeMulti(FakeForest):
+    def __init__(self, th, cost):
+        super().__init__(cost)
+        self.th = th
+        self.small = (0, 0)
+        self.closed = False
+
+    def set_small_schedule(self, t, w):
+        self.small = (t, w)
+
+    def close(self):
+        self.closed = True
+
+
+def test_tune_batched_searches_threshold_schedule_and_rounds(monkeypatch):
+    monkeypatch.setattr("paper_2607_20211_amd.drsf.drsf_snapshot_free", lambda s: None)
+    clock = [0.0]
+    monkeypatch.setattr(autotune.time, "perf_counter", lambda: clock[0])
+    made = []
+
+    def cost(f):
+        c = {0: 5.0, 1024: 4.0, 2048: 3.0, 4096: 3.5, 8192: 6.0}[f.th]
+        c -= 0.5 if f.small == (1024, 128) else 0.0
+        c -= 0.25 if f.setting == (4, 2, 0) else 0.0
+        return c
+
+    def make(th):
+        f = FakeMulti(th, None)
+        made.append(f)
+        return f
+
+    def sample(fr):
+        clock[0] += cost(fr)
+
+    f, ch = autotune.tune_batched(make, sample, "b")
+    assert f.th == 2048 and not f.closed
+    assert all(m.closed for m in made if m is not f)
+    assert (ch["small_threads"], ch["small_workgroups"]) == (1024, 128) and f.small == (1024, 128)
+    assert (ch["rounds_queued"], ch["levels_queued"], ch["sweep_mode"]) == (4, 2, 0)
+    assert ch["small_graph_vertices"] == 2048

@@ -657,6 +657,13 @@ def test_long_hooking_and_deep_search_continue_on_host():
     dl = gen.delete_batches(n, pair.keys, pair.parent, 1, 100_000, 50_000, gen.seed(4, 1, gen.P_DELETE))[0]
     pair.step(dl, drsf.DRSF_DELETE, "continuation delete")
     pair.gpu.close()
+    # profiled: the host-driven continuation has a phase time of its own
+    prof = Pair(g, max_batch=1 << 18, profile=True)
+    st, _ = prof.step(ins, drsf.DRSF_INSERT, "continuation insert, profiled")
+    assert st["host_finished"] != 0
+    t = prof.gpu.phase_times()
+    assert t["host_continuation"] > 0, t
+    prof.gpu.close()
 
 
 def test_profile_mode_direct_launches():
@@ -677,9 +684,11 @@ def test_profile_mode_direct_launches():
                                           "store_sweep"))
         assert t["validate"] > 0 and t[drsf.EVENT_BRACKET] >= 0
         dl = gen.delete_batches(n, pair.keys, pair.parent, 1, 4000, 2000, gen.seed(5, step, gen.P_DELETE))[0]
-        pair.step(dl, drsf.DRSF_DELETE, f"profile delete {step}")
+        st, _ = pair.step(dl, drsf.DRSF_DELETE, f"profile delete {step}")
         t = pair.gpu.phase_times()
         assert all(v >= 0 for v in t.values())
+        if st["host_finished"] == 0:
+            assert t["host_continuation"] == 0.0
     pair.gpu.close()
 
 

@@ -77,9 +77,10 @@ def test_random_multi_graph_cases():
     """The batched pattern: 60 seeded contexts of 1–40 graphs (1–5000
     vertices each, some edgeless), 3–6 multi-graph updates each with a
     random op and batch size per graph (empty batches included), now and
-    then an invalid batch for one graph (rejected, that graph unchanged), and
-    a random launch schedule; every graph bit-exact with the oracle run on
-    it alone."""
+    then an invalid batch for one graph (rejected, that graph unchanged), a
+    random launch schedule and a random small-graph threshold and workgroup
+    size (graphs up to it go to the one-workgroup engine); every graph
+    bit-exact with the oracle run on it alone."""
     from test_gpu_multi import MultiPair
     drsf = _lib()
     for c in range(60):
@@ -91,10 +92,16 @@ def test_random_multi_graph_cases():
             keys = gen.gnm(n, m, int(rng.integers(1 << 30))) if m > 0 else np.zeros(0, np.uint64)
             graphs.append(gen.make_graph(f"g{g}", n, keys))
         mb = int(rng.integers(1, 2000))
-        _case(f"random multi {c}: {len(graphs)} graphs, sum n={sum(g.n for g in graphs)}, max_batch {mb}")
-        pair = MultiPair(graphs, max_batch=mb * len(graphs), sweep_mode=int(rng.integers(2)))
+        small = int(rng.choice([0, 0, 300, 2000, 5000]))  # graphs up to this size: the one-workgroup engine
+        threads = int(rng.choice([256, 512, 1024]))
+        _case(f"random multi {c}: {len(graphs)} graphs, sum n={sum(g.n for g in graphs)}, max_batch {mb}, "
+              f"small graphs up to {small} ({threads} threads)")
+        pair = MultiPair(graphs, max_batch=mb * len(graphs), sweep_mode=int(rng.integers(2)),
+                         small_graph_vertices=small, small_threads=threads)
         if rng.random() < 0.5:
             pair.gpu.set_tuning(int(rng.integers(1, 7)), int(rng.integers(1, 9)), int(rng.integers(2)))
+        if small and rng.random() < 0.5:
+            pair.gpu.set_small_schedule(0, int(rng.integers(1, 9)))
         for step in range(int(rng.integers(3, 7))):
             batches, ops = [], []
             for g, (n, keys, par) in enumerate(pair.local_state()):
