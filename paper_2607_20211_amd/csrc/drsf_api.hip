@@ -199,7 +199,7 @@ struct drsf_ctx {
     int64_t pool_keys = 0, nsv = 0;
     int32_t *sgid = nullptr, *sm = nullptr, *sbuf = nullptr, *sok = nullptr;
     int64_t *soff = nullptr, *scap = nullptr, *svoff = nullptr;
-    uint32_t *pool = nullptr, *xk = nullptr, *bsort0 = nullptr, *bsort1 = nullptr;
+    uint32_t *pool = nullptr, *xk = nullptr, *bkeys = nullptr, *htab = nullptr;
     int32_t *spar = nullptr, *slab = nullptr;
     int2 *ser = nullptr;
     int4 *stasks = nullptr, *h_stasks = nullptr;
@@ -349,8 +349,8 @@ SmallDev make_small(drsf_ctx *c) {
     sd.spar = c->spar;
     sd.slab = c->slab;
     sd.er = c->ser;
-    sd.bsort0 = c->bsort0;
-    sd.bsort1 = c->bsort1;
+    sd.bkeys = c->bkeys;
+    sd.htab = c->htab;
     sd.tasks = c->stasks;
     sd.qhead = c->qhead;
     return sd;
@@ -658,10 +658,10 @@ int setup_small(drsf_ctx *c) {
     if ((rc = dalloc(c, &c->sgid, c->nsg)) || (rc = dalloc(c, &c->sm, c->nsg)) || (rc = dalloc(c, &c->sbuf, c->nsg)) ||
         (rc = dalloc(c, &c->sok, c->nsg)) || (rc = dalloc(c, &c->soff, c->nsg)) ||
         (rc = dalloc(c, &c->scap, c->nsg)) || (rc = dalloc(c, &c->svoff, c->nsg)) ||
-        (rc = dalloc(c, &c->pool, c->pool_keys)) || (rc = dalloc(c, &c->xk, c->pool_keys / 2)) ||
+        (rc = dalloc(c, &c->pool, c->pool_keys)) || (rc = dalloc(c, &c->xk, c->pool_keys)) ||
         (rc = dalloc(c, &c->spar, c->nsv)) || (rc = dalloc(c, &c->slab, c->nsv)) ||
-        (rc = dalloc(c, &c->ser, c->nsv)) || (rc = dalloc(c, &c->bsort0, c->max_batch)) ||
-        (rc = dalloc(c, &c->bsort1, c->max_batch)) || (rc = dalloc(c, &c->stasks, c->nsg)) ||
+        (rc = dalloc(c, &c->ser, c->nsv)) || (rc = dalloc(c, &c->bkeys, c->max_batch)) ||
+        (rc = dalloc(c, &c->htab, 2 * c->max_batch + 4 * (int64_t)c->nsg)) || (rc = dalloc(c, &c->stasks, c->nsg)) ||
         (rc = dalloc(c, &c->qhead, 1)))
         return rc;
     if ((rc = halloc(c, &c->h_stasks, c->nsg))) return rc;
@@ -687,7 +687,7 @@ int small_grid_for(drsf_ctx *c) {
     int cus = 256, lds_cu = 160 * 1024;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->dev);
     (void)hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c->dev);
-    const int64_t per = (int64_t)small_lds_bytes(c->small_T) + 18 * 1024;
+    const int64_t per = (int64_t)(small_lds_bytes(c->small_T) + small_static_lds());
     const int64_t fit = std::max<int64_t>(1, lds_cu / per) * cus;
     return (int)std::max<int64_t>(1, std::min<int64_t>(fit, c->nsg));
 }
@@ -712,7 +712,7 @@ int small_grow(drsf_ctx *c, const std::vector<int64_t> &need) {
         tot += 2 * cap[k];
     }
     uint32_t *np = nullptr, *nx = nullptr;
-    if ((rc = dalloc(c, &np, tot)) || (rc = dalloc(c, &nx, tot / 2))) {
+    if ((rc = dalloc(c, &np, tot)) || (rc = dalloc(c, &nx, tot))) {
         dfree(c, np);
         return rc;
     }
@@ -1295,7 +1295,7 @@ static int create_impl(int32_t G, const int32_t *n_off, int32_t n, const int64_t
     if (c->small_T > 0) {
         int lds_blk = 64 * 1024;
         (void)hipDeviceGetAttribute(&lds_blk, hipDeviceAttributeMaxSharedMemoryPerBlock, c->dev);
-        if ((int64_t)small_lds_bytes(c->small_T) + 18 * 1024 > lds_blk) {
+        if ((int64_t)(small_lds_bytes(c->small_T) + small_static_lds()) > lds_blk) {
             fail(c, DRSF_E_ARG, "small_graph_vertices %d needs more LDS than a workgroup may hold (%d bytes)",
                  c->small_T, lds_blk);
             return bail(DRSF_E_ARG);

@@ -165,14 +165,16 @@ struct SmallDev {
     int32_t *sbuf;           // [nsg] buffer holding them
     int32_t *sok;            // [nsg] 1: the last update of the graph is staged for commit
     uint32_t *pool;          // edge keys
-    uint32_t *xk;            // cross edges, graph s at soff[s] / 2 (scap keys)
+    uint32_t *xk;            // cross edges, graph s at soff[s]: two halves of scap keys
     int32_t *spar, *slab;    // staged parents and labels (global ids), per vertex
     int2 *er;                // replacement edges (local ids), per vertex slot
-    uint32_t *bsort0, *bsort1;  // [max_b] batch keys, sorted in place (graph's batch range)
+    uint32_t *bkeys;         // [max_b] batch keys (a graph's batch range)
+    uint32_t *htab;          // [2 max_b + 4 nsg] hash sets of batch keys too large for LDS
     const int4 *tasks;       // [nsmall] (small graph, batch start, batch length, op)
     unsigned int *qhead;     // work queue: next task (reset by the commit kernel)
 };
-size_t small_lds_bytes(int T);
+size_t small_lds_bytes(int T);  // dynamic LDS of the small-graph kernel for T vertices
+size_t small_static_lds();      // and its static LDS
 int small_prepare(int T);  // allows the kernel its LDS (once, before any launch or capture)
 int launch_small_update(const Dev &d, const SmallDev &s, int threads, int grid, hipStream_t st);
 void launch_small_commit(const Dev &d, const SmallDev &s, int grid, hipStream_t st);

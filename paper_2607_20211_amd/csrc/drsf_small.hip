@@ -11,23 +11,28 @@
 // since the chain's per-vertex kernels read the parents of every vertex in
 // the blocks they visit.
 //
-// A small graph keeps its edges as one ascending array of 32-bit keys
-// (u << 16 | v, u < v, local ids) in one of two buffers; an update writes
-// the new array into the other buffer (merge for inserts, filter for
-// deletes) and flips.  Steps per graph (local ids):
-//   1. parents into LDS; the batch normalised to keys, sorted (LSD radix,
-//      8-bit digits, stable wave-ballot ranking), checked: ids in range, no
-//      self-loop, no repeated pair, insert of an absent / delete of a
-//      present edge (binary search) — a rejected batch changes nothing;
-//   2. new edge array (merge / filter);
+// A small graph keeps its edges as an array of 32-bit keys (u << 16 | v,
+// u < v, local ids; n <= 16384, so bit 31 is free) in no particular order,
+// in one of two buffers: an insert appends the batch in place, a delete
+// writes the surviving keys into the other buffer and flips.  Steps per
+// graph (local ids):
+//   1. parents into LDS; the batch normalised to keys; ids in range and no
+//      self-loop;
+//   2. validation against a hash set of the batch keys (open addressing in
+//      LDS, or in HBM when the batch is too large for it): no repeated pair,
+//      insert of an absent / delete of a present edge, found by one pass
+//      over the edge array that also drops the deleted keys — a rejected
+//      batch changes nothing;
 //   3. deletes: cut (parent[c] = c for the child end of a deleted tree edge);
 //   4. pieces: roots of F-hat by pointer jumping in LDS;
-//   5. cross edges: the batch (insert) or every surviving edge (delete)
-//      whose ends lie in different pieces (Sec. II-A);
-//   6. replacement edges: Boruvka rounds over components with LDS atomic
+//   5-6. replacement edges: Boruvka rounds over components with LDS atomic
 //      minima of the edge keys (lowest key leaving each component; a mutual
 //      pair is recorded once), hooks applied after every selection, then
-//      pointer jumping — the Kruskal forest, as in the chain;
+//      pointer jumping — the Kruskal forest, as in the chain.  The first
+//      round reads the candidates, the batch (insert) or every surviving
+//      edge (delete), and keeps those whose ends lie in different pieces
+//      (the cross edges, Sec. II-A); every round keeps the edges still
+//      leaving a component for the next;
 //   7. labels: smallest vertex per final component;
 //   8. orientation: the super-forest of pieces over the replacement edges
 //      is searched level by level from each component's super-root piece
@@ -44,6 +49,8 @@ namespace {
 
 constexpr uint32_t SK_INF = 0xffffffffu;
 constexpr int MAX_WAVES = 16;  // up to 1024 threads per workgroup
+constexpr int UNROLL = 8;      // edge-array loads a thread keeps in flight
+constexpr int ER_REGS = 4;     // replacement edges a thread holds in registers during the level search
 
 __device__ __forceinline__ int nthreads() { return (int)blockDim.x; }
 
@@ -53,44 +60,16 @@ __device__ __forceinline__ uint32_t skey(int32_t a, int32_t b) {
 __device__ __forceinline__ int32_t sk_lo(uint32_t k) { return (int32_t)(k >> 16); }
 __device__ __forceinline__ int32_t sk_hi(uint32_t k) { return (int32_t)(k & 0xffffu); }
 
-// lanes of this wave holding the same 8-bit digit (among lanes with valid)
-__device__ __forceinline__ uint64_t same_digit(uint32_t dgt, bool valid) {
-    uint64_t same = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; b++) {
-        const uint64_t bal = __ballot((dgt >> b) & 1u);
-        same &= ((dgt >> b) & 1u) ? bal : ~bal;
-    }
-    return same;
-}
+// dynamic LDS for T vertices: P, C, H (int16) then B (uint32, 4-byte aligned)
+__host__ __device__ constexpr size_t lds_bytes_for(int T) { return 6 * (size_t)((T + 1) & ~1) + 4 * (size_t)T; }
 
 struct Shared {
     int32_t err;  // a bound was exceeded (corrupt forest): the update fails
-    uint32_t hist[256];
-    uint32_t wcnt[MAX_WAVES][256];
     uint32_t wsum[MAX_WAVES];
     int32_t task;
     int32_t flag;
     uint32_t word[4];
 };
-
-// Exclusive count of set flags over the block (in thread order); every
-// thread calls it.  Returns this thread's position; *total = all set flags.
-__device__ uint32_t block_rank(bool f, Shared &sh, uint32_t *total) {
-    const uint64_t m = __ballot(f);
-    const int w = threadIdx.x / WAVE, nw = nthreads() / WAVE;
-    if (lane_id() == 0) sh.wsum[w] = (uint32_t)__popcll(m);
-    __syncthreads();
-    uint32_t before = 0, tot = 0;
-    for (int k = 0; k < nw; k++) {
-        const uint32_t c = sh.wsum[k];
-        before += k < w ? c : 0;
-        tot += c;
-    }
-    __syncthreads();
-    *total = tot;
-    return before + (uint32_t)lanes_below(m);
-}
 
 // Exclusive sum of one count per thread over the block, in thread order;
 // every thread calls it.  *total = the sum of all counts.
@@ -114,112 +93,66 @@ __device__ uint32_t block_excl_sum(uint32_t x, Shared &sh, uint32_t *total) {
     return before + inc - x;
 }
 
-// Keeps, in order, the keys of src[0, cnt) that `keep` accepts, written to
-// dst (dst may be src: every key is read before a key lands at or below
-// it); returns how many.  Each thread takes one contiguous share, counts,
-// and writes after one block-wide sum (two barriers in all, where a pass
-// per block-sized chunk costs two per chunk).  Every thread calls it.
-template <class F>
-__device__ uint32_t block_compact(const uint32_t *src, uint32_t *dst, int cnt, F keep, Shared &sh) {
-    const int nt = nthreads();
-    const int s0 = (int)((int64_t)cnt * threadIdx.x / nt), s1 = (int)((int64_t)cnt * (threadIdx.x + 1) / nt);
-    uint32_t k = 0;
-    for (int j = s0; j < s1; j++) k += keep(src[j]) ? 1u : 0u;
-    uint32_t tot;
-    uint32_t w = block_excl_sum(k, sh, &tot);
-    for (int j = s0; j < s1; j++) {
-        const uint32_t x = src[j];
-        if (keep(x)) dst[w++] = x;
-    }
-    __syncthreads();
-    return tot;
+// Appends the keys of this wave's lanes that have `keep` set to out at
+// positions claimed from the counter *cnt (one LDS atomic per wave), in no
+// particular order.
+__device__ __forceinline__ void wave_append(bool keep, uint32_t k, uint32_t *out, uint32_t *cnt) {
+    const uint64_t m = __ballot(keep);
+    if (m == 0) return;
+    uint32_t base = 0;
+    if (lane_id() == 0) base = atomicAdd(cnt, (uint32_t)__popcll(m));
+    base = __shfl(base, 0);
+    if (keep) out[base + lanes_below(m)] = k;
 }
 
-// Stable LSD radix sort of a[0, cnt) by the low `bits` bits, 8 bits a pass,
-// with b as the other buffer; returns the buffer holding the result.  A
-// pass takes the keys in chunks of SORT_ITEMS per thread: each wave ranks a
-// contiguous run of its chunk 64 keys at a time (lanes with the same digit
-// found by ballots, per-wave digit counts in LDS carrying the order from
-// round to round), then a prefix over the waves gives each (wave, digit)
-// its output base.
-constexpr int SORT_ITEMS = 8;
-__device__ uint32_t *block_sort(uint32_t *a, uint32_t *b, int cnt, int bits, Shared &sh) {
-    const int nt = nthreads(), w = threadIdx.x / WAVE, nw = nt / WAVE;
-    const uint64_t lt = (1ull << lane_id()) - 1ull;
-    const int chunk = nt * SORT_ITEMS;
-    for (int shift = 0; shift < bits; shift += 8) {
-        for (int k = threadIdx.x; k < 256; k += nt) sh.hist[k] = 0;
-        __syncthreads();
-        for (int i = threadIdx.x; i < cnt; i += nt) atomicAdd(&sh.hist[(a[i] >> shift) & 255u], 1u);
-        __syncthreads();
-        {  // exclusive prefix of the 256 digit counts (every thread calls the sum)
-            const uint32_t c = threadIdx.x < 256 ? sh.hist[threadIdx.x] : 0u;
-            uint32_t tot;
-            const uint32_t e = block_excl_sum(c, sh, &tot);
-            if (threadIdx.x < 256) sh.hist[threadIdx.x] = e;
-        }
-        for (int c0 = 0; c0 < cnt; c0 += chunk) {
-            for (int k = threadIdx.x; k < MAX_WAVES * 256; k += nt) (&sh.wcnt[0][0])[k] = 0;
-            __syncthreads();
-            const int run0 = c0 + w * WAVE * SORT_ITEMS;
-            uint32_t key[SORT_ITEMS], dr[SORT_ITEMS];  // digit << 16 | rank within the wave's run
-#pragma unroll
-            for (int r = 0; r < SORT_ITEMS; r++) {
-                const int i = run0 + r * WAVE + lane_id();
-                const bool valid = i < cnt;
-                key[r] = valid ? a[i] : 0u;
-                const uint32_t dg = (key[r] >> shift) & 255u;
-                const uint64_t same = same_digit(dg, valid);
-                const uint32_t before = sh.wcnt[w][dg];  // read by the group before its leader writes
-                if (valid && (same & lt) == 0) sh.wcnt[w][dg] = before + (uint32_t)__popcll(same);
-                dr[r] = valid ? (dg << 16) | (before + (uint32_t)__popcll(same & lt)) : 0xffffffffu;
-            }
-            __syncthreads();
-            for (int k = threadIdx.x; k < 256; k += nt) {  // digit k: bases per wave, in wave order
-                uint32_t run = sh.hist[k];
-                for (int q = 0; q < nw; q++) {
-                    const uint32_t c = sh.wcnt[q][k];
-                    sh.wcnt[q][k] = run;
-                    run += c;
-                }
-                sh.hist[k] = run;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int r = 0; r < SORT_ITEMS; r++)
-                if (dr[r] != 0xffffffffu) b[sh.wcnt[w][dr[r] >> 16] + (dr[r] & 0xffffu)] = key[r];
-            __syncthreads();
-        }
-        uint32_t *t = a;
-        a = b;
-        b = t;
-    }
-    return a;
+// Hash set of edge keys by open addressing over nch chunks of 4 slots
+// (16-byte aligned): a key's probe sequence starts at the first slot of its
+// home chunk (the high half of mix(k) * nch) and runs on slot by slot, so a
+// lookup reads whole chunks with one 16-byte load and stops at the first
+// chunk that holds the key or an empty slot.  Whole chunks keep the probe
+// count of a wave (its slowest lane) low at half load.  The mix is the
+// "lowbias32" integer hash (C. Wellons, hash-prospector).  A slot holds
+// HS_EMPTY or a key; bit 31 marks the key as found.
+constexpr uint32_t HS_EMPTY = 0xffffffffu, HS_FOUND = 0x80000000u, HS_KEY = 0x7fffffffu;
+__device__ __forceinline__ uint32_t hs_home(uint32_t k, uint32_t nch) {
+    k ^= k >> 16;
+    k *= 0x7feb352du;
+    k ^= k >> 15;
+    k *= 0x846ca68bu;
+    k ^= k >> 16;
+    return (uint32_t)(((uint64_t)k * nch) >> 32);
 }
-
-// First position in a[0, m) holding a key >= k.
-__device__ __forceinline__ int lower_bound(const uint32_t *a, int m, uint32_t k) {
-    int lo = 0, hi = m;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (a[mid] < k) lo = mid + 1;
-        else hi = mid;
+// Adds k; false when k is already there.  The table never fills (at most
+// half its slots are used), so the probe ends; 4 nch probes bound it anyway.
+__device__ __forceinline__ bool hs_add(uint32_t *tab, uint32_t nch, uint32_t k) {
+    uint32_t h = 4 * hs_home(k, nch);
+    for (uint32_t p = 0; p < 4 * nch; p++) {
+        const uint32_t old = atomicCAS(&tab[h], HS_EMPTY, k);
+        if (old == HS_EMPTY) return true;
+        if ((old & HS_KEY) == k) return false;
+        h = h + 1 == 4 * nch ? 0 : h + 1;
     }
-    return lo;
+    return true;
 }
-
-// Root of v under the component links C (16-bit local ids); at most n
-// steps (more means a cycle, reported through err).
-__device__ __forceinline__ int32_t cfind(const int16_t *C, int32_t v, int n, Shared &sh) {
-    int32_t r = C[v];
-    for (int k = 0; C[r] != r; k++) {
-        if (k > n) {
-            sh.err = 1;
-            break;
-        }
-        r = C[r];
+// Slot holding k, or -1 (the table is not written meanwhile).  A chunk is
+// tested without branches (selects, and a max for "holds an empty slot"):
+// the loop body is a few instructions, run by the wave until its slowest
+// lane is done.
+__device__ __forceinline__ int hs_find(const uint32_t *tab, uint32_t nch, uint32_t k) {
+    uint32_t c = hs_home(k, nch);
+    int at = -1;
+    for (uint32_t p = 0; p < nch; p++) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(tab + 4 * c);
+        const int base = (int)(4 * c);
+        at = (q.w & HS_KEY) == k ? base + 3 : -1;
+        at = (q.z & HS_KEY) == k ? base + 2 : at;
+        at = (q.y & HS_KEY) == k ? base + 1 : at;
+        at = (q.x & HS_KEY) == k ? base : at;
+        const uint32_t mx = max(max(q.x, q.y), max(q.z, q.w));  // HS_EMPTY is the largest word
+        if (at >= 0 || mx == HS_EMPTY) break;
+        c = c + 1 == nch ? 0 : c + 1;
     }
-    return r;
+    return at;
 }
 
 // Pointer jumping on X[0, n) until every entry is a root (X[X[v]] == X[v]);
@@ -250,9 +183,10 @@ __device__ void jump_all(int16_t *X, int n, Shared &sh) {
 }
 
 // One graph's update (see the file comment).  Every thread of the block
-// calls it.
-__device__ void small_task(const Dev &d, const SmallDev &s, const int4 tk, Shared &sh, int16_t *P, int16_t *C,
-                           int16_t *H, uint32_t *B) {
+// calls it.  tab_lds: 16-byte aligned LDS after P (lds_chunks chunks of 4
+// words), free until step 4; t: the task's position in the queue.
+__device__ void small_task(const Dev &d, const SmallDev &s, const int t, const int4 tk, Shared &sh, int16_t *P,
+                           int16_t *C, int16_t *H, uint32_t *B, uint32_t *tab_lds, uint32_t lds_chunks) {
     const int sidx = tk.x, op = tk.w;
     const int64_t bstart = tk.y;
     const int blen = tk.z;
@@ -263,24 +197,21 @@ __device__ void small_task(const Dev &d, const SmallDev &s, const int4 tk, Share
     const int64_t cap = s.scap[sidx];
     const int cur = s.sbuf[sidx];
     const int m = s.sm[sidx];
-    const uint32_t *E = s.pool + s.soff[sidx] + (int64_t)cur * cap;
+    uint32_t *E = s.pool + s.soff[sidx] + (int64_t)cur * cap;
     uint32_t *E2 = s.pool + s.soff[sidx] + (int64_t)(1 - cur) * cap;
-    uint32_t *X = s.xk + s.soff[sidx] / 2;
+    uint32_t *X = s.xk + s.soff[sidx], *Y = X + cap;  // surviving candidate edges, two lists
     const int64_t vo = s.svoff[sidx];
     int2 *ER = s.er + vo;
     const Ctl *hc = d.hctl;
     const int32_t *be = hc->edges ? hc->edges : d.bedges;
-    uint32_t *ka = s.bsort0 + bstart, *kb = s.bsort1 + bstart;
-    // key bits: v in [0, lb), u in [16, 16 + lb)
-    int lb = 1;
-    while ((1 << lb) < n) lb++;
-    const int bits = 16 + lb;
+    uint32_t *ka = s.bkeys + bstart;
 
-    // 1. parents, batch keys, validation
+    // 1. parents, batch keys, range checks
     for (int v = threadIdx.x; v < n; v += nt) P[v] = (int16_t)(d.parent[o + v] - o);
     if (threadIdx.x == 0) {
         sh.flag = 0;
         sh.err = 0;
+        sh.word[0] = 0;
     }
     __syncthreads();
     int bad = 0;
@@ -295,77 +226,62 @@ __device__ void small_task(const Dev &d, const SmallDev &s, const int4 tk, Share
     }
     if (bad) atomicOr(&sh.flag, bad);
     __syncthreads();
-    // the batch sorted, then merged with the edge array (merge path: each
-    // thread takes an equal share of the merged order, found by one search,
-    // and walks it; ties put the edge array's key first).  Walking the
-    // merged order gives, with each key's neighbours there: repeated batch
-    // pairs, inserts of present edges, deletes of absent ones, and the new
-    // array (insert: the merged order; delete: the edge array's keys that
-    // have no equal batch key next to them).
-    const uint32_t *K = ka;
-    if (sh.flag == 0) K = block_sort(ka, kb, blen, bits, sh);
-    const int64_t L = (int64_t)m + blen;
-    const int64_t d0 = L * threadIdx.x / nt, d1 = L * (threadIdx.x + 1) / nt;
-    auto tE = [&](int i) { return (uint64_t)E[i] << 1; };
-    auto tK = [&](int j) { return ((uint64_t)K[j] << 1) | 1u; };
-    int i0 = 0;
-    if (sh.flag == 0) {  // co-rank of d0: the edge-array keys among the first d0 of the merged order
-        int lo = (int)(d0 - blen > 0 ? d0 - blen : 0), hi = (int)(d0 < m ? d0 : m);
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (tE(mid) < tK((int)(d0 - mid) - 1)) lo = mid + 1;
-            else hi = mid;
-        }
-        i0 = lo;
-    }
-    // one walk of the share; pass 0 checks and counts, pass 1 (deletes) writes
-    uint32_t kept = 0, keep_before = 0;
-    for (int pass = 0; pass < 2; pass++) {
-        if (sh.flag != 0) break;  // uniform: set before the last barrier
-        if (pass == 1 && op == 0) break;
-        int a = i0, c = (int)(d0 - i0);
-        uint64_t prev = ~0ull;  // the element before the share in the merged order
-        if (d0 > 0) {
-            const uint64_t pe = a > 0 ? tE(a - 1) : 0, pk = c > 0 ? tK(c - 1) : 0;
-            prev = pe > pk ? pe : pk;
-        }
-        bad = 0;
-        uint32_t w = keep_before;
-        for (int64_t dd = d0; dd < d1; dd++) {
-            const bool fromE = c >= blen || (a < m && tE(a) < tK(c));
-            const uint64_t x = fromE ? tE(a) : tK(c);
-            if (fromE) a++; else c++;
-            uint64_t nx = ~0ull;  // the element after x
-            if (a < m || c < blen) {
-                const uint64_t ne = a < m ? tE(a) : ~0ull, nk = c < blen ? tK(c) : ~0ull;
-                nx = ne < nk ? ne : nk;
-            }
-            const bool eq_next = nx != ~0ull && (nx >> 1) == (x >> 1);
-            const bool eq_prev = prev != ~0ull && (prev >> 1) == (x >> 1);
-            if (pass == 0) {
-                if (!fromE && eq_next && (nx & 1)) bad |= ST_DUPLICATE;
+
+    // 2. validation with a hash set of the batch keys: in LDS when twice
+    // the batch fits, else in the task's 2 blen + 4 words of the HBM table
+    // (two inlined copies, so that the LDS one uses LDS instructions)
+    auto validate = [&](uint32_t *tab, const uint32_t nch) {
+        const uint32_t S = 4 * nch;
+        for (uint32_t k = threadIdx.x; k < S; k += nt) tab[k] = HS_EMPTY;
+        __syncthreads();
+        int bad2 = 0;
+        for (int i = threadIdx.x; i < blen; i += nt)
+            if (!hs_add(tab, nch, ka[i])) bad2 |= ST_DUPLICATE;
+        if (bad2) atomicOr(&sh.flag, bad2);
+        __syncthreads();
+        // one pass over the edge array: inserts must meet no batch key;
+        // deletes mark the batch keys they meet and keep the other keys
+        bad2 = 0;
+        const int span = nt * UNROLL;
+        const int mm = (m + span - 1) / span * span;  // whole block rounds: the waves append together
+        for (int j0 = threadIdx.x; j0 < mm; j0 += span) {
+            uint32_t kk[UNROLL];  // loads issued together, then used
+#pragma unroll
+            for (int r = 0; r < UNROLL; r++) kk[r] = j0 + r * nt < m ? E[j0 + r * nt] : HS_EMPTY;
+#pragma unroll
+            for (int r = 0; r < UNROLL; r++) {
+                const bool in = j0 + r * nt < m;
+                const int at = in ? hs_find(tab, nch, kk[r]) : -1;
                 if (op == 0) {
-                    if (fromE && eq_next) bad |= ST_EXISTS;  // a batch key equal to an edge: right after it
-                    E2[dd] = (uint32_t)(x >> 1);
+                    if (at >= 0) bad2 |= ST_EXISTS;
                 } else {
-                    if (!fromE && !(eq_prev && !(prev & 1))) bad |= ST_MISSING;
-                    if (fromE && !eq_next) kept++;
+                    if (at >= 0) atomicOr(&tab[at], HS_FOUND);
+                    wave_append(in && at < 0, kk[r], E2, &sh.word[0]);
                 }
-            } else if (fromE && !eq_next) {
-                E2[w++] = (uint32_t)(x >> 1);
             }
-            prev = x;
         }
-        if (pass == 0) {
-            if (bad) atomicOr(&sh.flag, bad);
-            uint32_t tot;  // the kept counts summed in thread order (barriers inside)
-            keep_before = block_excl_sum(kept, sh, &tot);
-            if (threadIdx.x == 0) sh.word[0] = tot;
+        if (bad2) atomicOr(&sh.flag, bad2);
+        __syncthreads();
+        if (op == 1) {  // every batch key must have been met
+            bad2 = 0;
+            for (uint32_t k = threadIdx.x; k < S; k += nt) {
+                const uint32_t x = tab[k];
+                if (x != HS_EMPTY && !(x & HS_FOUND)) bad2 |= ST_MISSING;
+            }
+            if (bad2) atomicOr(&sh.flag, bad2);
             __syncthreads();
+        }
+    };
+    if (sh.flag == 0 && blen > 0) {
+        if (2 * (int64_t)blen <= 4 * (int64_t)lds_chunks) {
+            validate(tab_lds, lds_chunks);
+        } else {  // words [2 bstart + 4 t, 2 (bstart + blen) + 4 (t + 1)) are the task's: tasks come in batch order
+            const int64_t w0 = (2 * bstart + 4 * (int64_t)t + 3) & ~(int64_t)3;  // 16-byte aligned
+            validate(s.htab + w0, (uint32_t)((2 * (bstart + blen) + 4 * ((int64_t)t + 1) - w0) / 4));
         }
     }
     const int status = sh.flag;
-    const int m2 = op == 0 ? (int)L : (int)sh.word[0];
+    const int m2 = op == 0 ? m + blen : (blen > 0 ? (int)sh.word[0] : m);
     __syncthreads();
     if (status) {
         if (threadIdx.x == 0) {
@@ -375,33 +291,44 @@ __device__ void small_task(const Dev &d, const SmallDev &s, const int4 tk, Share
         __syncthreads();
         return;
     }
-    __syncthreads();
+    if (op == 0 && (int64_t)m + blen > cap) {  // the host grows the buffers first: a corrupt count
+        if (threadIdx.x == 0) {
+            atomicOr(d.status, ST_WALK_BOUND);
+            s.sok[sidx] = 0;
+        }
+        __syncthreads();
+        return;
+    }
+    // the new edge array: inserts append the batch in place; an empty
+    // delete keeps the array where it is
+    const bool flip = op == 1 && blen > 0;
+    if (op == 0)
+        for (int i = threadIdx.x; i < blen; i += nt) E[m + i] = ka[i];
 
     // 3. cut the deleted tree edges
     if (op == 1) {
         for (int i = threadIdx.x; i < blen; i += nt) {
-            const int32_t u = sk_lo(K[i]), v = sk_hi(K[i]);
+            const int32_t u = sk_lo(ka[i]), v = sk_hi(ka[i]);
             if (P[u] == v) P[u] = (int16_t)u;
             else if (P[v] == u) P[v] = (int16_t)v;
         }
-        __syncthreads();
     }
+    __syncthreads();
 
     // 4. pieces: C = root of each vertex in F-hat
     for (int v = threadIdx.x; v < n; v += nt) C[v] = P[v];
     __syncthreads();
     jump_all(C, n, sh);
 
-    // 5. cross edges into X
-    const uint32_t *src = op == 0 ? K : E2;
-    const int ns = op == 0 ? blen : m2;
-    const uint32_t nx =
-        block_compact(src, X, ns, [&](uint32_t k) { return C[sk_lo(k)] != C[sk_hi(k)]; }, sh);
-
-    // 6. replacement edges: Boruvka rounds (C holds component links; piece
-    // roots are the initial components)
-    uint32_t ner = 0;
-    int live = (int)nx;
+    // 5-6. replacement edges: Boruvka rounds (C holds component links,
+    // every entry a root at the start of a round; piece roots are the
+    // initial components).  A round reads list L, keeps the edges whose
+    // ends lie in different components (appended to `out`, the next
+    // round's L) and takes each component's lowest such key.
+    uint32_t ner = 0, nx = 0;
+    const uint32_t *L = op == 0 ? ka : (flip ? E2 : E);
+    int live = op == 0 ? blen : m2;
+    uint32_t *out = X, *spare = Y;
     for (int round = 0;; round++) {
         // each round at least halves the components with a live edge; err is
         // read by every thread before any can set it again
@@ -412,24 +339,36 @@ __device__ void small_task(const Dev &d, const SmallDev &s, const int4 tk, Share
             break;
         }
         for (int v = threadIdx.x; v < n; v += nt) B[v] = SK_INF;
-        if (threadIdx.x == 0) sh.flag = 0;
+        if (threadIdx.x == 0) sh.word[1] = 0;
         __syncthreads();
-        for (int j = threadIdx.x; j < live; j += nt) {
-            const uint32_t k = X[j];
-            const int32_t cu = cfind(C, sk_lo(k), n, sh), cv = cfind(C, sk_hi(k), n, sh);
-            if (cu != cv) {
-                atomicMin(&B[cu], k);
-                atomicMin(&B[cv], k);
+        const int span = nt * UNROLL;
+        const int lr = (live + span - 1) / span * span;
+        for (int j0 = threadIdx.x; j0 < lr; j0 += span) {
+            uint32_t kk[UNROLL];
+#pragma unroll
+            for (int r = 0; r < UNROLL; r++) kk[r] = j0 + r * nt < live ? L[j0 + r * nt] : 0u;
+#pragma unroll
+            for (int r = 0; r < UNROLL; r++) {
+                const uint32_t k = kk[r];
+                const int32_t cu = C[sk_lo(k)], cv = C[sk_hi(k)];
+                const bool keep = j0 + r * nt < live && cu != cv;
+                if (keep) {
+                    atomicMin(&B[cu], k);
+                    atomicMin(&B[cv], k);
+                }
+                wave_append(keep, k, out, &sh.word[1]);
             }
         }
         __syncthreads();
+        live = (int)sh.word[1];
+        if (round == 0) nx = (uint32_t)live;
         // select: H[c] = component c hooks onto (or c); record each chosen edge once
         uint32_t got = 0;
         for (int c = threadIdx.x; c < n; c += nt) {
             H[c] = (int16_t)c;
             const uint32_t k = B[c];
             if (k == SK_INF || C[c] != c) continue;
-            const int32_t cx = cfind(C, sk_lo(k), n, sh), cy = cfind(C, sk_hi(k), n, sh);
+            const int32_t cx = C[sk_lo(k)], cy = C[sk_hi(k)];
             const int32_t other = cx == c ? cy : cx;
             const bool mutual = B[other] == k;
             if (!mutual || c > other) H[c] = (int16_t)other;
@@ -441,7 +380,7 @@ __device__ void small_task(const Dev &d, const SmallDev &s, const int4 tk, Share
         for (int c = threadIdx.x; c < n; c += nt) {
             const uint32_t k = B[c];
             if (k == SK_INF || C[c] != c) continue;
-            const int32_t cx = cfind(C, sk_lo(k), n, sh), cy = cfind(C, sk_hi(k), n, sh);
+            const int32_t cx = C[sk_lo(k)], cy = C[sk_hi(k)];
             const int32_t other = cx == c ? cy : cx;
             if (!(B[other] == k) || c < other) ER[ner + before++] = make_int2(sk_lo(k), sk_hi(k));
         }
@@ -452,8 +391,9 @@ __device__ void small_task(const Dev &d, const SmallDev &s, const int4 tk, Share
             if (H[c] != c) C[c] = H[c];
         __syncthreads();
         jump_all(C, n, sh);
-        // drop edges inside one component
-        live = (int)block_compact(X, X, live, [&](uint32_t k) { return C[sk_lo(k)] != C[sk_hi(k)]; }, sh);
+        L = out;
+        out = spare;
+        spare = const_cast<uint32_t *>(L);
     }
 
     // 7. labels: smallest vertex of each final component (B[root])
@@ -481,26 +421,50 @@ __device__ void small_task(const Dev &d, const SmallDev &s, const int4 tk, Share
     int16_t *PE = C;
     for (int v = threadIdx.x; v < n; v += nt) LV[v] = H[v] < 0 ? 0 : -1;
     __syncthreads();
+    // the piece pair of each of this thread's first ER_REGS replacement
+    // edges, held in registers across the levels (0: used up)
+    auto piece_pair = [&](int e) {
+        const int2 xy = ER[e];
+        int32_t pa = H[xy.x], pb = H[xy.y];
+        if (pa < 0) pa = -pa - 1;
+        if (pb < 0) pb = -pb - 1;
+        return ((uint32_t)pa << 16) | (uint32_t)pb | 0x80000000u;
+    };
+    uint32_t pp[ER_REGS];
+#pragma unroll
+    for (int r = 0; r < ER_REGS; r++) {
+        const int e = threadIdx.x + r * nt;
+        pp[r] = e < (int)ner ? piece_pair(e) : 0u;
+    }
+    // one level: an edge with one end at level lvl and the other unreached
+    // attaches the other end's piece
+    auto visit = [&](uint32_t q, int e, int lvl) {
+        const int32_t pa = (int32_t)((q >> 16) & 0x7fffu), pb = (int32_t)(q & 0xffffu);
+        const int32_t la = LV[pa], lb = LV[pb];
+        if (la == lvl && lb < 0) {
+            LV[pb] = lvl + 1;
+            PE[pb] = (int16_t)e;  // attach vertex y, new parent x
+            return true;
+        }
+        if (lb == lvl && la < 0) {
+            LV[pa] = lvl + 1;
+            PE[pa] = (int16_t)(-e - 1);  // attach vertex x, new parent y
+            return true;
+        }
+        return false;
+    };
     for (int lvl = 0; lvl <= n; lvl++) {  // a super-tree has fewer levels than vertices
         if (threadIdx.x == 0) sh.flag = 0;
         __syncthreads();
         bool any = false;
-        for (int e = threadIdx.x; e < (int)ner; e += nt) {
-            const int2 xy = ER[e];
-            int32_t pa = H[xy.x], pb = H[xy.y];
-            if (pa < 0) pa = -pa - 1;
-            if (pb < 0) pb = -pb - 1;
-            const int32_t la = LV[pa], lb = LV[pb];
-            if (la == lvl && lb < 0) {
-                LV[pb] = lvl + 1;
-                PE[pb] = (int16_t)e;  // attach vertex y, new parent x
-                any = true;
-            } else if (lb == lvl && la < 0) {
-                LV[pa] = lvl + 1;
-                PE[pa] = (int16_t)(-e - 1);  // attach vertex x, new parent y
+#pragma unroll
+        for (int r = 0; r < ER_REGS; r++)
+            if (pp[r] && visit(pp[r], threadIdx.x + r * nt, lvl)) {
+                pp[r] = 0;  // an edge attaches one piece, once
                 any = true;
             }
-        }
+        for (int e = threadIdx.x + ER_REGS * nt; e < (int)ner; e += nt)
+            if (visit(piece_pair(e), e, lvl)) any = true;
         if (any) sh.flag = 1;
         __syncthreads();
         const int f = sh.flag;
@@ -555,7 +519,7 @@ __device__ void small_task(const Dev &d, const SmallDev &s, const int4 tk, Share
     if (threadIdx.x == 0) {
         s.sok[sidx] = 1;
         s.sm[sidx] = m2;
-        s.sbuf[sidx] = 1 - cur;
+        s.sbuf[sidx] = flip ? 1 - cur : cur;
         atomicAdd(&d.cnt[C_SNER], (unsigned long long)ner);
         atomicAdd(&d.cnt[C_SNCROSS], (unsigned long long)nx);
     }
@@ -570,6 +534,10 @@ __global__ __launch_bounds__(1024) void k_small_update(Dev d, SmallDev s) {
     int16_t *C = P + T;
     int16_t *H = C + T;
     uint32_t *B = reinterpret_cast<uint32_t *>(smem + 6 * (size_t)((T + 1) & ~1));
+    // after P, 16-byte aligned: C, H and B, free until the pieces are formed
+    const size_t tab0 = (2 * (size_t)T + 15) & ~(size_t)15;
+    uint32_t *tab = reinterpret_cast<uint32_t *>(smem + tab0);
+    const uint32_t tab_chunks = (uint32_t)((lds_bytes_for(T) - tab0) / 16);
     const int ntask = d.hctl->nsmall;
     while (true) {
         if (threadIdx.x == 0) sh.task = (int32_t)atomicAdd(s.qhead, 1u);
@@ -577,7 +545,7 @@ __global__ __launch_bounds__(1024) void k_small_update(Dev d, SmallDev s) {
         const int t = sh.task;
         __syncthreads();
         if (t >= ntask) break;
-        small_task(d, s, s.tasks[t], sh, P, C, H, B);
+        small_task(d, s, t, s.tasks[t], sh, P, C, H, B, tab, tab_chunks);
     }
 }
 
@@ -632,7 +600,8 @@ __global__ __launch_bounds__(BLOCK) void k_small_init(Dev d, SmallDev s) {
 
 }  // namespace
 
-size_t small_lds_bytes(int T) { return 6 * (size_t)((T + 1) & ~1) + 4 * (size_t)T; }
+size_t small_lds_bytes(int T) { return lds_bytes_for(T); }
+size_t small_static_lds() { return sizeof(Shared); }
 
 int small_prepare(int T) {
     return hipFuncSetAttribute((const void *)k_small_update, hipFuncAttributeMaxDynamicSharedMemorySize,

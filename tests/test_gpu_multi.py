@@ -47,24 +47,48 @@ class MultiPair:
             assert np.array_equal(gp, par), f"{what}: graph {g} parent mismatch"
             assert m[g] == len(keys), f"{what}: graph {g} edge count {m[g]} != {len(keys)}"
 
+    def _spoil(self, g, bt, op, kind):
+        """bt with one invalid entry of the given kind appended: "dup" a
+        repeated pair, "exists" an insert of a present edge, "missing" a
+        delete of an absent pair, "self" a self-loop, "range" an id outside
+        the graph (local id n)."""
+        n, keys = self.state[g][0], self.state[g][1]
+        if kind == "dup":
+            extra = bt[:1]
+        elif kind == "exists":
+            assert op == 0 and len(keys)
+            k = int(keys[len(keys) // 2])
+            extra = np.array([[k >> 32, k & 0xffffffff]])
+        elif kind == "missing":
+            assert op == 1
+            have = set(int(k) for k in keys) | set((int(u) << 32) | int(v) for u, v in np.sort(bt, axis=1))
+            extra = next(np.array([[u, v]]) for u in range(n) for v in range(u + 1, n) if (u << 32 | v) not in have)
+        elif kind == "self":
+            extra = np.array([[n - 1, n - 1]])
+        else:
+            extra = np.array([[0, n]])
+        return np.concatenate([bt, extra.astype(np.int32)])
+
     def step(self, batches, ops, what, bad=()):
         """batches in local ids; graphs in `bad` get an invalid batch (a
-        repeated pair) and must come back rejected and unchanged."""
+        repeated pair, or the kind `bad` maps them to, see _spoil) and must
+        come back rejected and unchanged."""
         drsf = _lib()
+        kinds = bad if isinstance(bad, dict) else {g: "dup" for g in bad}
         glob = []
         b_off = [0]
         for g, bt in enumerate(batches):
             o = int(self.mg.n_off[g])
             bt = np.asarray(bt, np.int32).reshape(-1, 2)
-            if g in bad:
-                bt = np.concatenate([bt, bt[:1]]) if len(bt) else bt
+            if g in kinds and (len(bt) or kinds[g] != "dup"):
+                bt = self._spoil(g, bt, int(ops[g]), kinds[g])
             glob.append(bt + o)
             b_off.append(b_off[-1] + len(bt))
         edges = np.concatenate(glob) if glob else np.zeros((0, 2), np.int32)
         st = self.gpu.apply_multi(edges.astype(np.int32), np.array(b_off, np.int64), ops)
         for g, bt in enumerate(batches):
-            if g in bad and len(bt):
-                assert st[g] == drsf.DRSF_E_BATCH, f"{what}: graph {g} not rejected"
+            if g in kinds and (len(bt) or kinds[g] != "dup"):
+                assert st[g] == drsf.DRSF_E_BATCH, f"{what}: graph {g} not rejected ({kinds[g]})"
                 continue
             assert st[g] == drsf.DRSF_OK, f"{what}: graph {g} status {st[g]}"
             n, keys, par, label = self.state[g]

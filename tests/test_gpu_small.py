@@ -3,8 +3,9 @@ small_graph_vertices): graphs up to that many vertices are updated whole by
 one workgroup each (forest in LDS, taken from a device work queue) beside
 the kernel sequence that updates the others.  Every graph bit-exact with
 the oracle run on it alone after every call, for several thresholds and
-workgroup sizes: mixed ops, empty and invalid batches, deep trees, pools
-that grow, all graphs small, snapshots and exports."""
+workgroup sizes: mixed ops, empty and invalid batches (each kind, with the
+batch's hash set in LDS and in HBM), deep trees, pools that grow, all graphs
+small, snapshots and exports."""
 from __future__ import annotations
 
 import numpy as np
@@ -91,4 +92,29 @@ def test_small_graph_deep_trees_and_pool_growth():
         pair.gpu.restore(snap)
     assert e.value.code == drsf.DRSF_E_STATE
     drsf.drsf_snapshot_free(snap)
+    pair.gpu.close()
+
+
+@pytest.mark.parametrize("T", [300, 4096])
+def test_small_graph_rejections(T):
+    """Each kind of invalid batch sent to small graphs, with batches small
+    enough for the LDS hash set and too large for it (more than half the
+    LDS words after the parents): the graph comes back rejected and
+    unchanged, the others in the same call are applied."""
+    drsf = _lib()
+    _case(f"small rejections T={T}")
+    ns = [T, T // 2, T, 3 * T // 4, 20000]
+    graphs = _graphs(ns, 11)
+    pair = MultiPair(graphs, max_batch=1 << 16, small_graph_vertices=T)
+    lds_words = ((T + 1) & ~1) + T
+    sizes = [5, lds_words // 2 + 7]  # hash set in LDS / in HBM
+    plan = [("dup", 0), ("exists", 0), ("missing", 1), ("self", 0), ("range", 1), ("dup", 1), ("self", 1)]
+    for step, (kind, op_bad) in enumerate(plan):
+        for size in sizes:
+            ops = np.array([op_bad, 1 - op_bad, op_bad, 0, step % 2], np.int8)
+            bs = np.array([size, size // 3, size, 40, 300])
+            batches, ops = gen.multi_step_batches(pair.local_state(), ops, bs,
+                                                  gen.seed(48, step * 4 + size, gen.P_INSERT))
+            bad = {0: kind, 2: kind} if len(batches[2]) else {0: kind}
+            pair.step(batches, ops, f"rejection {kind} size {size}", bad=bad)
     pair.gpu.close()
