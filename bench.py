@@ -310,6 +310,8 @@ def methods_ab(n, row, col, par, batches, max_batch, stream, drsf, reps=3):
                           "replacement_phase_ms": round(t["replacement_edges"] - br, 4),
                           "reversal_and_labels_phase_ms": round(t["reversal_and_labels"] - br, 4),
                           "host_continuation_ms": round(t["host_continuation"], 4),
+                          "phases_ms": {k: round(max(v - br, 0.0) if (v > 0 and k != "host_continuation")
+                                                 else v, 4) for k, v in t.items()},
                           "update_wall_ms": round(wall * 1e3, 4)})
         assert [int(x) for x in fp.digest()] == digest
         fp.close()

@@ -100,9 +100,12 @@ typedef struct {
                                 placed in the captured update graph; later
                                 rounds run in one workgroup while at most 4096
                                 cross edges are live, else host-driven
-                                launches finish them; 0 = 2 */
+                                launches finish them; 0 = chosen by the
+                                library: 2, raised (up to 12) to what an
+                                update that the host had to finish needed */
     int levels_queued;       /* super-forest search levels placed in the graph;
-                                0 = 4 (max 12) */
+                                0 = chosen by the library: 4, raised (up to
+                                12) likewise (max 12) */
     int reverse_mode;        /* path reversal: 0 (default) one thread walks each
                                 path; 1: Euler tour of F-hat with list ranking,
                                 start/finish times and the interval test

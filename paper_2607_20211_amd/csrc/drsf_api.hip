@@ -36,6 +36,7 @@ constexpr int BOR_FAST = 2;    // default full-grid hooking rounds queued before
 constexpr int BFS_FAST = 4;    // default search levels queued in the captured sequence
 constexpr int BFS_MAX = 12;    // deeper super-trees use the Euler tour instead
 constexpr int BOR_CHUNK = 3;   // rounds per host check in the continuation
+constexpr int AUTO_ROUNDS_MAX = 12;  // queued rounds the library may grow to by itself
 
 enum Phase { PH_VALIDATE, PH_UPDATE, PH_ROOT, PH_ORPH_LIST, PH_ORPH_SCAN, PH_SWEEP, PH_SWEEP_DELTA,
              PH_REPL, PH_ROOTING, PH_FINISH, PH_N };
@@ -206,6 +207,11 @@ struct drsf_ctx {
     unsigned int *qhead = nullptr;
     hipStream_t s2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // branch of a delete's update that sweeps the edge store and the
+    // inserted-edge list beside the orphan scan (made on first use)
+    hipStream_t s3 = nullptr;
+    hipEvent_t ev_fork3 = nullptr, ev_join3 = nullptr;
+    bool s3_failed = false;
 };
 
 namespace {
@@ -512,10 +518,22 @@ int alloc_state(drsf_ctx *c) {
     return DRSF_OK;
 }
 
+// Drops the captured update sequences (the next update captures anew with
+// the context's current round and level counts and buffers).
+void drop_graphs(drsf_ctx *c) {
+    for (int k = 0; k < 4; k++) {
+        if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+        if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+        c->gexec[k] = nullptr;
+        c->graph[k] = nullptr;
+    }
+}
+
 void destroy_ctx(drsf_ctx *c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     if (c->s2) (void)hipStreamSynchronize(c->s2);
+    if (c->s3) (void)hipStreamSynchronize(c->s3);
     for (int k = 0; k < 4; k++) {
         if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
         if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
@@ -531,6 +549,9 @@ void destroy_ctx(drsf_ctx *c) {
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->s2) (void)hipStreamDestroy(c->s2);
+    if (c->ev_fork3) (void)hipEventDestroy(c->ev_fork3);
+    if (c->ev_join3) (void)hipEventDestroy(c->ev_join3);
+    if (c->s3) (void)hipStreamDestroy(c->s3);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -732,12 +753,7 @@ int small_grow(drsf_ctx *c, const std::vector<int64_t> &need) {
     c->soff_h = off;
     c->pool_keys = tot;
     c->rebuilds++;
-    for (int k = 0; k < 4; k++) {
-        if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
-        if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
-        c->gexec[k] = nullptr;
-        c->graph[k] = nullptr;
-    }
+    drop_graphs(c);
     return DRSF_OK;
 }
 
@@ -885,12 +901,7 @@ int rebuild_store(drsf_ctx *c) {
     c->rebuilds++;
     HIPCHK(c, hipStreamSynchronize(s));
     c->broken = false;
-    for (int k = 0; k < 4; k++) {
-        if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
-        if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
-        c->gexec[k] = nullptr;
-        c->graph[k] = nullptr;
-    }
+    drop_graphs(c);
     return DRSF_OK;
 }
 
@@ -930,6 +941,26 @@ int sg_reduce(drsf_ctx *c, const Dev &d, hipStream_t s) {
     return DRSF_OK;
 }
 
+// The sweep branch's stream and events, made once (outside any capture);
+// false if they cannot be made (the update then stays on one stream).
+bool ensure_branch(drsf_ctx *c) {
+    if (c->s3) return true;
+    if (c->s3_failed) return false;
+    if (hipStreamCreateWithFlags(&c->s3, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork3, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join3, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        if (c->ev_fork3) (void)hipEventDestroy(c->ev_fork3);
+        if (c->ev_join3) (void)hipEventDestroy(c->ev_join3);
+        if (c->s3) (void)hipStreamDestroy(c->s3);
+        c->s3 = nullptr;
+        c->ev_fork3 = c->ev_join3 = nullptr;
+        c->s3_failed = true;
+        return false;
+    }
+    return true;
+}
+
 // The update sequence (see the file comment) for batches with inserts
 // (kind bit 1) and/or deletes (kind bit 2); with events when profiling.
 void enqueue_update(drsf_ctx *c, int kind, bool profile) {
@@ -963,14 +994,31 @@ void enqueue_update(drsf_ctx *c, int kind, bool profile) {
     mark(PH_ROOT, del);
     if (del) launch_rep_chase(d, s);
     mark(PH_ORPH_LIST, del);
-    if (del) launch_orphan_list(d, s);
+    if (del) launch_orphan_plan(d, s);
+    // deletes: the sweeps of the inserted-edge list and of the store (a
+    // no-op when the orphan scan runs) need only root finding and the scan
+    // mode; they write other regions of x0 than the orphan list and scan, so
+    // they run on a branch beside them (not when profiling: phases are
+    // timed in order)
+    const bool fork = del && !profile && c->s3;
+    if (fork) {
+        (void)hipEventRecord(c->ev_fork3, s);
+        (void)hipStreamWaitEvent(c->s3, c->ev_fork3, 0);
+        launch_sweep_delta(d, c->s3);
+        launch_sweep_base(d, c->s3);
+    }
+    if (del) launch_orphan_fill(d, s);
     mark(PH_ORPH_SCAN, del);
     if (del) launch_orphan_scan(d, s);
     mark(PH_SWEEP, del);
-    if (del) launch_sweep_base(d, s);
+    if (del && !fork) launch_sweep_base(d, s);
     mark(PH_SWEEP_DELTA);
     if (ins) launch_insert_emit(d, s);
-    if (del) launch_sweep_delta(d, s);
+    if (del && !fork) launch_sweep_delta(d, s);
+    if (fork) {
+        (void)hipEventRecord(c->ev_join3, c->s3);
+        (void)hipStreamWaitEvent(s, c->ev_join3, 0);
+    }
     mark(PH_REPL);
     const int64_t units = (ins ? insert_regions(c->max_batch) : 0) + (del ? c->ntiles + c->dtmax : 0);
     if (c->opts.replacement_mode == 1) {  // supergraph, then its rounds
@@ -1078,6 +1126,22 @@ int continue_update(drsf_ctx *c) {
     if (c->cont_timed) (void)hipEventRecord(c->ev[PH_N + 4], s);
     HIPCHK(c, hipStreamSynchronize(s));
     c->view.host_finished = how ? how : 1;
+    // counts left to the library (tuning 0): later updates queue the rounds
+    // and levels this one needed, so that updates like it finish on the
+    // device (each queued round or level that finds nothing costs one
+    // dispatch); bounded so that one outlier cannot make every update slow
+    if (!bad) {
+        bool grew = false;
+        if ((how & 1) && c->opts.rounds_queued <= 0 && r - c->round_base > c->bor_fast) {
+            c->bor_fast = std::min(r - c->round_base, AUTO_ROUNDS_MAX);
+            grew = true;
+        }
+        if ((how & 2) && bfs_done && c->opts.levels_queued <= 0 && lv > c->bfs_fast) {
+            c->bfs_fast = std::min(lv, BFS_MAX);
+            grew = true;
+        }
+        if (grew) drop_graphs(c);
+    }
     return DRSF_OK;
 }
 
@@ -1093,6 +1157,7 @@ int launch_update(drsf_ctx *c) {
     *(volatile unsigned long long *)(c->h_ret + c->ret_words + 7) = 0;
     c->kind = (c->h_ctl->has_ins ? 1 : 0) | (c->h_ctl->has_del ? 2 : 0);
     if (c->kind == 0) c->kind = 3;  // nothing but rejected or empty batches: run everything
+    if ((c->kind & 2) && !prof) (void)ensure_branch(c);
     // the supergraph reads sizes back between its kernels, so it is not
     // captured (the Euler-tour reversal, sort included, is a fixed sequence)
     if (prof || c->opts.replacement_mode == 1) {
@@ -1388,12 +1453,7 @@ int drsf_set_tuning(drsf_ctx *c, int rounds_queued, int levels_queued, int sweep
     c->opts.sweep_mode = sweep_mode;
     // the captured sequences hold the old round counts
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (int k = 0; k < 4; k++) {
-        if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
-        if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
-        c->gexec[k] = nullptr;
-        c->graph[k] = nullptr;
-    }
+    drop_graphs(c);
     return DRSF_OK;
 }
 
@@ -1412,12 +1472,7 @@ int drsf_set_small_schedule(drsf_ctx *c, int threads, int workgroups) {
     if (threads) c->small_threads = threads;
     if (c->nsg) c->small_grid = workgroups ? std::min(workgroups, c->nsg) : small_grid_for(c);
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (int k = 0; k < 4; k++) {
-        if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
-        if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
-        c->gexec[k] = nullptr;
-        c->graph[k] = nullptr;
-    }
+    drop_graphs(c);
     return DRSF_OK;
 }
 

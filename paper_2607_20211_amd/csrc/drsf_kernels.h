@@ -70,7 +70,8 @@ struct Dev {
     int64_t *bvol;           // [nvb] slots of the block's orphans (zero between updates)
     int32_t *bcnt;           // [nvb] listed orphans of the block (zero between updates)
     int64_t *bpre;           // [nvb] slots before the block within its group of BLOCK blocks
-    int32_t *opre;           // [nvb] orphans before the block within its group
+                             // (or within the whole list, the group prefixes then 0)
+    int32_t *opre;           // [nvb] orphans before the block within its group (likewise)
     unsigned long long *gsum;  // [ngroups] packed (slots, orphans) per group
     int64_t *gpre;             // [ngroups] slots before the group
     int64_t *gopre;            // [ngroups] orphans before the group
@@ -256,7 +257,8 @@ void launch_register(const Dev &d, hipStream_t s);
 void launch_insert_emit(const Dev &d, hipStream_t s);
 void launch_rep_chase(const Dev &d, hipStream_t s);
 void launch_sweep_base(const Dev &d, hipStream_t s);
-void launch_orphan_list(const Dev &d, hipStream_t s);  // plan, totals and mode, list
+void launch_orphan_plan(const Dev &d, hipStream_t s);  // block prefixes, totals and scan mode
+void launch_orphan_fill(const Dev &d, hipStream_t s);  // the orphan list
 void launch_orphan_scan(const Dev &d, hipStream_t s);
 void launch_sweep_delta(const Dev &d, hipStream_t s);
 // units: regions of x0 the first two rounds may read (sizes their grids)

@@ -666,6 +666,42 @@ def test_long_hooking_and_deep_search_continue_on_host():
     prof.gpu.close()
 
 
+def test_queued_rounds_grow_after_a_continuation():
+    """A context left to choose its own round and level counts: an update
+    that the host had to finish (more hooking rounds, deeper search than
+    queued) makes later updates queue what it needed.  The same batch
+    applied again from the same state then finishes in the captured
+    sequence; both results bit-exact, and a context with counts set by the
+    caller keeps them."""
+    drsf = _lib()
+    _case("queued rounds grow")
+    n = 100_000
+    g = gen.make_graph("edgeless", n, np.zeros(0, np.uint64))
+    # a random batch on an edgeless graph: many rounds with long live lists
+    pair = Pair(g, max_batch=1 << 18)
+    ins = gen.insert_batches(n, g.keys, 1, 200_000, gen.seed(4, 1, gen.P_INSERT))[0]
+    snap = pair.gpu.snapshot()
+    st1, _ = pair.step(ins, drsf.DRSF_INSERT, "grow: first apply")
+    first = pair.parent.copy(), pair.label.copy()
+    pair.gpu.restore(snap)
+    st2 = pair.gpu.apply(ins, drsf.DRSF_INSERT)
+    assert np.array_equal(pair.gpu.parent(), first[0]) and np.array_equal(pair.gpu.label(), first[1])
+    assert (st1["host_finished"] & 1) != 0, st1  # the premise: the host ran more rounds
+    assert (st2["host_finished"] & 1) == 0, (st1, st2)  # now queued in the captured sequence
+    drsf.drsf_snapshot_free(snap)
+    pair.gpu.close()
+    # counts set by the caller stay as set
+    fixed = Pair(g, max_batch=1 << 18)
+    fixed.gpu.set_tuning(2, 4, 0)
+    snap = fixed.gpu.snapshot()
+    a, _ = fixed.step(ins, drsf.DRSF_INSERT, "fixed counts: first apply")
+    fixed.gpu.restore(snap)
+    b = fixed.gpu.apply(ins, drsf.DRSF_INSERT)
+    assert (a["host_finished"] & 3) == (b["host_finished"] & 3), (a, b)
+    drsf.drsf_snapshot_free(snap)
+    fixed.gpu.close()
+
+
 def test_profile_mode_direct_launches():
     """opts.profile launches the same kernels directly with events between
     the phases; the results are the same and every phase has a time."""
