@@ -699,8 +699,41 @@ def main():
         lat_del.append(tc - tb)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
+    digest_timed = [int(x) for x in f.digest()]
     f.close()
     log(f"timed {K} steps in {wall * 1e3:.2f} ms")
+
+    # the same steps with batch validation off (drsf_opts.validate_batches =
+    # 0: the caller guarantees valid batches, as these are): the same forest
+    # (digests), and the latency without the checks
+    fu = drsf.Forest(g.n, d_row, d_col, d_par, max_batch=b, stream=stream.cuda_stream, inputs_on_device=True,
+                     delta_capacity=max(nsteps * b + b, 1 << 20), validate_batches=False)
+    if tuning:
+        fu.set_tuning(tuning["rounds_queued"], tuning["levels_queued"], tuning["sweep_mode"])
+    for i in range(W):
+        fu.apply(d_ins[i], drsf.DRSF_INSERT)
+        fu.apply(d_del[i], drsf.DRSF_DELETE)
+    torch.cuda.synchronize()
+    lu_ins, lu_del = [], []
+    tu0 = time.perf_counter()
+    for i in range(W, W + K):
+        ta = time.perf_counter()
+        fu.apply(d_ins[i], drsf.DRSF_INSERT)
+        tb = time.perf_counter()
+        fu.apply(d_del[i], drsf.DRSF_DELETE)
+        lu_ins.append(tb - ta)
+        lu_del.append(time.perf_counter() - tb)
+    torch.cuda.synchronize()
+    wall_u = time.perf_counter() - tu0
+    same_u = [int(x) for x in fu.digest()] == digest_timed
+    fu.close()
+    assert same_u, "validate_batches=0 ended in a different forest"
+    unvalidated = {"value": round(2 * b * K / wall_u, 1), "ms_per_step": round(wall_u / K * 1e3, 4),
+                   "insert_ms_mean": round(float(np.mean(lu_ins)) * 1e3, 4),
+                   "delete_ms_mean": round(float(np.mean(lu_del)) * 1e3, 4), "same_forest": same_u,
+                   "what": "the timed steps on a context with validate_batches = 0 (no repeated-pair check, "
+                           "no presence search for inserts; the batches are valid)"}
+    log(f"unvalidated: {unvalidated}")
 
     # profiled pass: the same steps on a fresh context that launches the same
     # kernels one by one with an event between phases, on the stream the
@@ -845,6 +878,7 @@ def main():
         "event_bracket_ms": {"insert": round(ev_ins, 4), "delete": round(ev_del, 4)},
         "phase_share_vs_paper": phase_share,
         "tuning": tuning,
+        "unvalidated": unvalidated,
         "roofline": roofline,
         "rooflines": rooflines,
         "protocol": protocol,

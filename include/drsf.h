@@ -146,6 +146,19 @@ typedef struct {
                                 graphs.  Results are identical. */
     int small_threads;       /* workgroup size of that kernel: 256, 512 or
                                 1024; 0 = 512 */
+    int validate_batches;    /* 1 (default): every batch is checked (ids in
+                                range, no self-loop, no repeated pair, insert
+                                of an absent / delete of a present edge) and a
+                                graph whose batch fails is rejected unchanged
+                                (DRSF_E_BATCH).  0: the caller guarantees
+                                valid batches; the repeated-pair check and the
+                                inserts' presence search are skipped (ids are
+                                still range-checked and self-loops and deletes
+                                of absent edges still rejected, so no input
+                                can make a kernel read out of bounds); an
+                                invalid batch then leaves the context in an
+                                unspecified but safe state.  The small-graph
+                                engine checks its batches either way. */
 } drsf_opts;
 
 /* Fills *opts with the defaults described above. */

@@ -295,6 +295,7 @@ Dev make_dev(drsf_ctx *c) {
     Dev d;
     memset(&d, 0, sizeof d);
     d.n = c->n;
+    d.validate = c->opts.validate_batches != 0;
     d.ctl = c->ctl;
     d.ctlw = c->ctl;
     d.hctl = c->h_ctl;
@@ -987,7 +988,7 @@ void enqueue_update(drsf_ctx *c, int kind, bool profile) {
     }
     mark(PH_VALIDATE);
     launch_classify(d, s);
-    launch_dedupe(d, s);
+    if (c->opts.validate_batches) launch_dedupe(d, s);
     mark(PH_UPDATE);
     launch_prepare(d, del, s);
     launch_register(d, s);
@@ -1220,6 +1221,7 @@ void drsf_default_opts(drsf_opts *o) {
     if (!o) return;
     memset(o, 0, sizeof *o);
     o->validate_forest = 1;
+    o->validate_batches = 1;
     o->max_batch = 1 << 20;
 }
 

@@ -30,6 +30,7 @@ struct Ctl {
 // All device pointers one apply needs; passed by value to every kernel.
 struct Dev {
     int32_t n;
+    int32_t validate;        // 0: batches guaranteed valid (no repeat check, no insert presence search)
     const Ctl *ctl;          // device copy, written by the first kernel of an update
     Ctl *ctlw;               // the same, writable
     const Ctl *hctl;         // host copy (pinned), read by the first kernel only
@@ -70,8 +71,7 @@ struct Dev {
     int64_t *bvol;           // [nvb] slots of the block's orphans (zero between updates)
     int32_t *bcnt;           // [nvb] listed orphans of the block (zero between updates)
     int64_t *bpre;           // [nvb] slots before the block within its group of BLOCK blocks
-                             // (or within the whole list, the group prefixes then 0)
-    int32_t *opre;           // [nvb] orphans before the block within its group (likewise)
+    int32_t *opre;           // [nvb] orphans before the block within its group
     unsigned long long *gsum;  // [ngroups] packed (slots, orphans) per group
     int64_t *gpre;             // [ngroups] slots before the group
     int64_t *gopre;            // [ngroups] orphans before the group

@@ -295,6 +295,7 @@ __global__ __launch_bounds__(BLOCK) void k_classify(Dev d) {
         }
         const uint64_t k = mkkey((uint32_t)u, (uint32_t)v);
         d.bkey[i] = k;
+        if (!d.validate && (opm == 2 ? (int)d.bop[i] : opm) == 0) continue;  // an absent pair, by contract
         const int32_t lo = key_lo(k), hi = key_hi(k);
         // loads that do not depend on the probes below, issued first (the
         // parents only where the batch holds deletes)
@@ -306,7 +307,7 @@ __global__ __launch_bounds__(BLOCK) void k_classify(Dev d) {
             phi = d.parent[hi];
         }
         // repeated pairs: every edge stamps its slot (checked by k_dedupe)
-        d.dslot[hmix(k) & d.dsmask] = (int32_t)i;
+        if (d.validate) d.dslot[hmix(k) & d.dsmask] = (int32_t)i;
         // presence: the edge sits in upper row lo and in lower row hi (with
         // mirrored tombstones); search the shorter and map a lower hit up
         int64_t pos;
@@ -927,64 +928,6 @@ __global__ __launch_bounds__(BLOCK) void k_orph_total(Dev d) {
         d.cnt[C_OVOL] = (unsigned long long)V;
         d.cnt[C_NORPH] = tc;
         d.cnt[C_OMODE] = (d.ctl->smode != 1 && V <= d.eb) ? 1ull : 0ull;
-    }
-}
-
-// Both of the above in one workgroup, for up to PLAN1_MAX vertex blocks:
-// thread t takes a contiguous run of blocks, sums it, a scan over the
-// threads gives each run its start, and the run's blocks get prefixes over
-// the whole list (the group prefixes are then 0).
-constexpr int PLAN1_THREADS = 1024;
-constexpr int64_t PLAN1_MAX = (int64_t)PLAN1_THREADS * 128;
-__global__ __launch_bounds__(PLAN1_THREADS) void k_orph_plan1(Dev d) {
-    if (*d.status || !d.ctl->has_del) return;
-    __shared__ unsigned long long s_v[PLAN1_THREADS / WAVE], s_c[PLAN1_THREADS / WAVE];
-    const int64_t per = (d.nvb + PLAN1_THREADS - 1) / PLAN1_THREADS;
-    const int64_t b0 = (int64_t)threadIdx.x * per < d.nvb ? (int64_t)threadIdx.x * per : d.nvb;
-    const int64_t b1 = b0 + per < d.nvb ? b0 + per : d.nvb;
-    unsigned long long sv = 0, sc = 0;
-    for (int64_t b = b0; b < b1; b++) {
-        sv += (unsigned long long)d.bvol[b];
-        sc += (unsigned long long)d.bcnt[b];
-    }
-    // exclusive scans of both sums over the threads
-    unsigned long long iv = sv, ic = sc;
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-        const unsigned long long yv = __shfl_up(iv, o), yc = __shfl_up(ic, o);
-        if (lane_id() >= o) {
-            iv += yv;
-            ic += yc;
-        }
-    }
-    const int w = threadIdx.x / WAVE;
-    if (lane_id() == WAVE - 1) {
-        s_v[w] = iv;
-        s_c[w] = ic;
-    }
-    __syncthreads();
-    unsigned long long pv = iv - sv, pc = ic - sc, tv = 0, tc = 0;
-    for (int q = 0; q < PLAN1_THREADS / WAVE; q++) {
-        pv += q < w ? s_v[q] : 0;
-        pc += q < w ? s_c[q] : 0;
-        tv += s_v[q];
-        tc += s_c[q];
-    }
-    for (int64_t b = b0; b < b1; b++) {
-        d.bpre[b] = (int64_t)pv;
-        d.opre[b] = (int32_t)pc;
-        pv += (unsigned long long)d.bvol[b];
-        pc += (unsigned long long)d.bcnt[b];
-    }
-    const int64_t ng = (d.nvb + BLOCK - 1) / BLOCK;
-    for (int64_t g = threadIdx.x; g < ng; g += PLAN1_THREADS) {
-        d.gpre[g] = 0;
-        d.gopre[g] = 0;
-    }
-    if (threadIdx.x == 0) {
-        d.cnt[C_OVOL] = tv;
-        d.cnt[C_NORPH] = tc;
-        d.cnt[C_OMODE] = (d.ctl->smode != 1 && (int64_t)tv <= d.eb) ? 1ull : 0ull;
     }
 }
 
@@ -2195,10 +2138,6 @@ void launch_sweep_base(const Dev &d, hipStream_t s) {
         hipLaunchKernelGGL(k_sweep_base, dim3(grid_for(d.ntiles, 1, 6 * 256)), dim3(BLOCK), 0, s, d);
 }
 void launch_orphan_plan(const Dev &d, hipStream_t s) {
-    if (d.nvb <= PLAN1_MAX) {  // one dispatch
-        hipLaunchKernelGGL(k_orph_plan1, dim3(1), dim3(PLAN1_THREADS), 0, s, d);
-        return;
-    }
     hipLaunchKernelGGL(k_orph_plan, dim3(grid_for(d.nvb, BLOCK, 1 << 30)), dim3(BLOCK), 0, s, d);
     hipLaunchKernelGGL(k_orph_total, dim3(1), dim3(BLOCK), 0, s, d);
 }

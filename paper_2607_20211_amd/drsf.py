@@ -44,7 +44,8 @@ class drsf_opts(ctypes.Structure):
                 ("dev_free", ctypes.c_void_p),
                 ("alloc_user", ctypes.c_void_p),
                 ("small_graph_vertices", ctypes.c_int),
-                ("small_threads", ctypes.c_int)]
+                ("small_threads", ctypes.c_int),
+                ("validate_batches", ctypes.c_int)]
 
 
 # device allocator hooks of drsf_opts
@@ -480,7 +481,8 @@ class Forest:
                  stream=None, inputs_on_device: bool = False, validate: bool = True,
                  profile: bool = False, delta_capacity: int = 0, sweep_mode: int = 0,
                  rounds_queued: int = 0, levels_queued: int = 0, reverse_mode: int = 0,
-                 replacement_mode: int = 0, allocator: TorchAllocator | None = None):
+                 replacement_mode: int = 0, allocator: TorchAllocator | None = None,
+                 validate_batches: bool = True):
         self.on_device = bool(inputs_on_device)
         if not self.on_device:
             row_ptr = _host_input(row_ptr, np.int64)
@@ -502,6 +504,7 @@ class Forest:
         o.levels_queued = levels_queued
         o.reverse_mode = reverse_mode
         o.replacement_mode = replacement_mode
+        o.validate_batches = int(validate_batches)
         if stream is not None:
             o.stream = stream
         self.allocator = allocator
@@ -588,7 +591,7 @@ class MultiForest(Forest):
                  profile: bool = False, delta_capacity: int = 0, sweep_mode: int = 0,
                  rounds_queued: int = 0, levels_queued: int = 0, reverse_mode: int = 0,
                  replacement_mode: int = 0, allocator: TorchAllocator | None = None,
-                 small_graph_vertices: int = 0, small_threads: int = 0):
+                 small_graph_vertices: int = 0, small_threads: int = 0, validate_batches: bool = True):
         self.on_device = bool(inputs_on_device)
         if not self.on_device:
             row_ptr = _host_input(row_ptr, np.int64)
@@ -613,6 +616,7 @@ class MultiForest(Forest):
         o.replacement_mode = replacement_mode
         o.small_graph_vertices = small_graph_vertices
         o.small_threads = small_threads
+        o.validate_batches = int(validate_batches)
         if stream is not None:
             o.stream = stream
         self.allocator = allocator

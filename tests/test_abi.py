@@ -39,3 +39,25 @@ def test_binding_has_no_cpu_fallback():
     """The binding routes every call to libdrsf.so and never imports the oracle."""
     src = open(os.path.join(ROOT, "paper_2607_20211_amd", "drsf.py")).read()
     assert "import oracle" not in src and "from oracle" not in src
+
+
+def test_default_opts_layout_matches_the_header():
+    """drsf_default_opts (host code, no device call) fills the C struct; the
+    binding's ctypes mirror must read every field where the library wrote
+    it: the documented defaults, up to the last field."""
+    from paper_2607_20211_amd import drsf
+    if not os.path.exists(drsf.LIB_PATH):
+        pytest.skip("libdrsf.so not built")
+    o = drsf.drsf_default_opts()
+    assert o.validate_forest == 1 and o.profile == 0 and o.inputs_on_device == 0
+    assert o.max_batch == 1 << 20 and o.delta_capacity == 0 and o.sweep_mode == 0
+    assert o.rounds_queued == 0 and o.levels_queued == 0
+    assert o.reverse_mode == 0 and o.replacement_mode == 0
+    assert not o.dev_alloc and not o.dev_free and not o.alloc_user
+    assert o.small_graph_vertices == 0 and o.small_threads == 0
+    assert o.validate_batches == 1
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = text[text.index("typedef struct {", text.index("typedef struct drsf_ctx")):]
+    body = body[:body.index("} drsf_opts;")]
+    fields = re.findall(r"\b(\w+)\s*;", body) + re.findall(r"\(\*(\w+)\)", body)
+    assert set(fields) == {f for f, _ in drsf.drsf_opts._fields_}

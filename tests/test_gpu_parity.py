@@ -702,6 +702,53 @@ def test_queued_rounds_grow_after_a_continuation():
     fixed.gpu.close()
 
 
+@pytest.mark.parametrize("device", [False, True])
+def test_unvalidated_batches(device):
+    """validate_batches = 0 (the caller guarantees valid batches): the same
+    bit-exact results on valid batches, R-MAT and G(n, m), inserts and
+    deletes.  Then the checks it keeps: ids out of range, self-loops and
+    deletes of absent edges are still rejected with the graph unchanged;
+    a repeated pair in an insert batch is not checked, and the context
+    stays usable (its forest spans the graph it holds by the checker)."""
+    drsf = _lib()
+    _case(f"unvalidated batches device={device}")
+    for g in (gen.make_graph("rmat", 1 << 13, gen.rmat(13, 8, 0.57, 0.19, 0.19, gen.seed(8, 0, gen.P_GRAPH))),
+              gen.make_graph("gnm", 20000, gen.gnm(20000, 50000, gen.seed(8, 1, gen.P_GRAPH)))):
+        pair = Pair(g, device=device, max_batch=8192, validate_batches=False)
+        for step in range(4):
+            ins = gen.insert_batches(g.n, pair.keys, 1, 3000, gen.seed(8, step, gen.P_INSERT))[0]
+            pair.step(ins, drsf.DRSF_INSERT, f"unvalidated insert {step}")
+            trees = int((pair.parent != np.arange(g.n)).sum())
+            dl = gen.delete_batches(g.n, pair.keys, pair.parent, 1, 3000, min(1500, trees),
+                                    gen.seed(8, step, gen.P_DELETE))[0]
+            pair.step(dl, drsf.DRSF_DELETE, f"unvalidated delete {step}")
+        before = pair.gpu.parent(), pair.gpu.label(), pair.gpu.edges()
+        absent = gen.insert_batches(g.n, pair.keys, 1, 1, gen.seed(8, 9, gen.P_INSERT))[0]
+        for bad, op in (([[0, g.n]], drsf.DRSF_INSERT), ([[5, 5]], drsf.DRSF_INSERT),
+                        (absent, drsf.DRSF_DELETE), ([[-1, 3]], drsf.DRSF_DELETE)):
+            bad = np.asarray(bad, np.int32)
+            if device:
+                import torch
+                with torch.cuda.stream(pair.stream):
+                    bad = torch.from_numpy(bad).to(pair.dev)
+            with pytest.raises(drsf.DrsfError) as e:
+                pair.gpu.apply(bad, op)
+            assert e.value.code == drsf.DRSF_E_BATCH
+            assert np.array_equal(pair.gpu.parent(), before[0]) and np.array_equal(pair.gpu.label(), before[1])
+            assert np.array_equal(pair.gpu.edges(), before[2])
+        # an unchecked repeated pair: applied, and the forest still spans the held graph
+        rep = np.concatenate([absent, absent]).astype(np.int32)
+        if device:
+            import torch
+            with torch.cuda.stream(pair.stream):
+                rep = torch.from_numpy(rep).to(pair.dev)
+        pair.gpu.apply(rep, drsf.DRSF_INSERT)
+        keys = np.unique(pair.gpu.edges())
+        rc, msg = oracle.check_forest(g.n, keys, pair.gpu.parent(), pair.gpu.label())
+        assert rc == 0, msg
+        pair.gpu.close()
+
+
 def test_profile_mode_direct_launches():
     """opts.profile launches the same kernels directly with events between
     the phases; the results are the same and every phase has a time."""
