@@ -603,6 +603,56 @@ def run_batched(nsteps, dev, stream, log, tune, small=None):
             "chain_alone_tuning": chain_tuning}
 
 
+def run_batched_small(nsteps, dev, stream, log, G=1024):
+    """The batched pattern on small graphs only: G graphs G(n, 4n) with
+    n = 10^U(2, 3.5) (up to 3162 vertices), batches of 10^U(1,3) edges, op
+    per graph and step.  A/B: the small-graph engine alone (threshold 4096:
+    every graph updated whole by one workgroup, no kernel sequence) against
+    the kernel sequence alone (threshold 0), same steps, both launch
+    schedules at their defaults; both end in the same forest (digests)."""
+    import torch
+    import gen
+    from paper_2607_20211_amd import drsf
+    t0 = time.time()
+    wl = gen.batched_workload(G, 2 + nsteps, gen.seed(4, 1, gen.P_GRAPH), log_n=(2.0, 3.5), log_b=(1.0, 3.0))
+    mg = wl.mg
+    cap = max(int(e[1][-1]) for e in wl.steps)
+    ups = [int(e[1][-1]) for e in wl.steps]
+    log(f"batched small graphs: {mg.G} graphs, n={mg.n} m={len(mg.col) // 2}, {ups[0]} updates in the first step "
+        f"({time.time() - t0:.1f}s)")
+    d_row, d_col, d_par = (torch.from_numpy(x).to(dev) for x in (mg.row_ptr, mg.col, mg.parent))
+    d_steps = [torch.from_numpy(e).to(dev) for e, _, _ in wl.steps]
+    torch.cuda.synchronize()
+    res = {}
+    for name, th in (("engine", 4096), ("chain", 0)):
+        f = drsf.MultiForest(mg.n_off, d_row, d_col, d_par, max_batch=cap, stream=stream.cuda_stream,
+                             inputs_on_device=True, delta_capacity=(2 + nsteps) * cap + (1 << 20),
+                             small_graph_vertices=th)
+        for i in range(2):
+            assert (f.apply_multi(d_steps[i], wl.steps[i][1], wl.steps[i][2]) == 0).all()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sts = [f.apply_multi(d_steps[i], wl.steps[i][1], wl.steps[i][2]) for i in range(2, 2 + nsteps)]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t1
+        assert all((x == 0).all() for x in sts), f"batched small graphs ({name}): batches rejected"
+        res[name] = (wall, [int(x) for x in f.digest()])
+        f.close()
+    same = res["engine"][1] == res["chain"][1]
+    assert same, "batched small graphs: the engine and the kernel sequence end in different forests"
+    tot = sum(ups[2:])
+    out = {"workload": f"{G} graphs G(n, 4n), n = 10^U(2,3.5), b = 10^U(1,3) per graph, op per graph and step",
+           "graphs": G, "n_total": mg.n, "m_total": len(mg.col) // 2, "updates_per_step": round(tot / nsteps),
+           "steps": nsteps, "engine_ms_per_step": round(res["engine"][0] / nsteps * 1e3, 4),
+           "engine_updates_per_s": round(tot / res["engine"][0], 1),
+           "chain_ms_per_step": round(res["chain"][0] / nsteps * 1e3, 4),
+           "chain_updates_per_s": round(tot / res["chain"][0], 1),
+           "speedup": round(res["chain"][0] / res["engine"][0], 2), "same_forest": same}
+    log(f"batched small graphs: engine {out['engine_ms_per_step']} ms/step, kernel sequence "
+        f"{out['chain_ms_per_step']} ms/step, same forest: {same}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -618,8 +668,12 @@ def main():
                     help="small-graph threshold of the batched context instead of the tuned one")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the per-op rates at other batch sizes and the deep grid")
-    ap.add_argument("--no-served", action="store_true",
-                    help="skip the served-pattern measurement")
+    # the served measurement is opt-in: its overlapped-server run on the full
+    # request stream ended the process with a segmentation fault whose cause
+    # has not been found; the serial run of the same stream completed
+    ap.add_argument("--served", action="store_true",
+                    help="run the served-pattern measurement (off by default)")
+    ap.add_argument("--no-served", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--served-scale", type=int, default=24)
     ap.add_argument("--served-requests", type=int, default=10_000)
     ap.add_argument("--no-instances", action="store_true",
@@ -835,10 +889,11 @@ def main():
     protocol = None if args.no_instances else run_instances(scale, b, g, args.instances, args.instance_runs,
                                                              dev, stream, log)
     configs = None if args.no_configs else run_configs(g, dev, stream, log)
+    batched_small = None if args.no_batched else run_batched_small(args.batched_steps, dev, stream, log)
     batched = None if args.no_batched else run_batched(args.batched_steps, dev, stream, log,
                                                        not args.no_tune, args.batched_small)
 
-    served = None if args.no_served else run_served(args.served_scale, args.served_requests,
+    served = None if (args.no_served or not args.served) else run_served(args.served_scale, args.served_requests,
                                                      (0.5, 0.8, 0.95, 1.5), log)
 
     total_updates = 2 * b * K
@@ -884,6 +939,7 @@ def main():
         "protocol": protocol,
         "configs": configs,
         "batched": batched,
+        "batched_small_graphs": batched_small,
         "served": served,
         "cpu_baseline": cpu,
     }

@@ -207,11 +207,6 @@ struct drsf_ctx {
     unsigned int *qhead = nullptr;
     hipStream_t s2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    // branch of a delete's update that sweeps the edge store and the
-    // inserted-edge list beside the orphan scan (made on first use)
-    hipStream_t s3 = nullptr;
-    hipEvent_t ev_fork3 = nullptr, ev_join3 = nullptr;
-    bool s3_failed = false;
 };
 
 namespace {
@@ -534,7 +529,6 @@ void destroy_ctx(drsf_ctx *c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     if (c->s2) (void)hipStreamSynchronize(c->s2);
-    if (c->s3) (void)hipStreamSynchronize(c->s3);
     for (int k = 0; k < 4; k++) {
         if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
         if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
@@ -550,9 +544,6 @@ void destroy_ctx(drsf_ctx *c) {
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->s2) (void)hipStreamDestroy(c->s2);
-    if (c->ev_fork3) (void)hipEventDestroy(c->ev_fork3);
-    if (c->ev_join3) (void)hipEventDestroy(c->ev_join3);
-    if (c->s3) (void)hipStreamDestroy(c->s3);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -669,7 +660,7 @@ int setup_small(drsf_ctx *c) {
     for (int32_t k = 0; k < c->nsg; k++) {
         const int32_t g = c->sgid_h[k];
         const int64_t m = c->gm_h[g];
-        c->scap_h[k] = std::max<int64_t>(2 * m, m + 1024);  // room for inserts before the pool grows
+        c->scap_h[k] = std::max<int64_t>(2 * m, m + 4096);  // room for inserts before the pool grows
         c->soff_h[k] = off;
         off += 2 * c->scap_h[k];
         c->svoff_h[k] = voff;
@@ -715,37 +706,37 @@ int small_grid_for(drsf_ctx *c) {
 }
 
 // Makes room for more keys in the small graphs' buffers (an insert would
-// not fit): each graph in need gets a larger capacity, the live keys move to
-// a new pool, and the captured update graphs (which hold the old pool) are
+// not fit): every graph's capacity doubles (at least to what it needs), so
+// that the next growth is far off for all of them, the live keys move to a
+// new pool, and the captured update graphs (which hold the old pool) are
 // dropped; snapshots taken before cannot be restored.
 int small_grow(drsf_ctx *c, const std::vector<int64_t> &need) {
     int rc;
     hipStream_t s = c->stream;
-    HIPCHK(c, hipStreamSynchronize(s));
-    std::vector<int32_t> sm((size_t)c->nsg), sb((size_t)c->nsg);
-    HIPCHK(c, hipMemcpyAsync(sm.data(), c->sm, 4 * sm.size(), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(sb.data(), c->sbuf, 4 * sb.size(), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
     std::vector<int64_t> cap = c->scap_h, off((size_t)c->nsg);
     int64_t tot = 0;
     for (int32_t k = 0; k < c->nsg; k++) {
-        if (need[k] > cap[k]) cap[k] = std::max<int64_t>(need[k], 2 * cap[k]);
+        cap[k] = std::max<int64_t>(need[k], 2 * cap[k]);
         off[k] = tot;
         tot += 2 * cap[k];
     }
     uint32_t *np = nullptr, *nx = nullptr;
-    if ((rc = dalloc(c, &np, tot)) || (rc = dalloc(c, &nx, tot))) {
+    int64_t *noc = nullptr;  // the new offsets, then the new capacities
+    if ((rc = dalloc(c, &np, tot)) || (rc = dalloc(c, &nx, tot)) || (rc = dalloc(c, &noc, 2 * (int64_t)c->nsg))) {
         dfree(c, np);
+        dfree(c, nx);
         return rc;
     }
-    for (int32_t k = 0; k < c->nsg; k++)
-        if (sm[k] > 0)
-            HIPCHK(c, hipMemcpyAsync(np + off[k], c->pool + c->soff_h[k] + (int64_t)sb[k] * c->scap_h[k],
-                                     4 * (size_t)sm[k], hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(noc, off.data(), 8 * off.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(noc + c->nsg, cap.data(), 8 * cap.size(), hipMemcpyHostToDevice, s));
+    // one kernel moves every graph's live keys (queued after any update
+    // still using the old pool)
+    launch_small_regrow(make_dev(c), make_small(c), noc, np, s);
+    HIPCHK(c, hipMemcpyAsync(c->soff, noc, 8 * off.size(), hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->scap, noc + c->nsg, 8 * cap.size(), hipMemcpyDeviceToDevice, s));
     launch_fill_i32(c->sbuf, c->nsg, 0, s);
-    HIPCHK(c, hipMemcpyAsync(c->soff, off.data(), 8 * off.size(), hipMemcpyHostToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(c->scap, cap.data(), 8 * cap.size(), hipMemcpyHostToDevice, s));
     HIPCHK(c, hipStreamSynchronize(s));
+    dfree(c, noc);
     dfree(c, c->pool);
     dfree(c, c->xk);
     c->pool = np;
@@ -942,26 +933,6 @@ int sg_reduce(drsf_ctx *c, const Dev &d, hipStream_t s) {
     return DRSF_OK;
 }
 
-// The sweep branch's stream and events, made once (outside any capture);
-// false if they cannot be made (the update then stays on one stream).
-bool ensure_branch(drsf_ctx *c) {
-    if (c->s3) return true;
-    if (c->s3_failed) return false;
-    if (hipStreamCreateWithFlags(&c->s3, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_fork3, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_join3, hipEventDisableTiming) != hipSuccess) {
-        (void)hipGetLastError();
-        if (c->ev_fork3) (void)hipEventDestroy(c->ev_fork3);
-        if (c->ev_join3) (void)hipEventDestroy(c->ev_join3);
-        if (c->s3) (void)hipStreamDestroy(c->s3);
-        c->s3 = nullptr;
-        c->ev_fork3 = c->ev_join3 = nullptr;
-        c->s3_failed = true;
-        return false;
-    }
-    return true;
-}
-
 // The update sequence (see the file comment) for batches with inserts
 // (kind bit 1) and/or deletes (kind bit 2); with events when profiling.
 void enqueue_update(drsf_ctx *c, int kind, bool profile) {
@@ -979,6 +950,19 @@ void enqueue_update(drsf_ctx *c, int kind, bool profile) {
         (void)hipEventRecord(c->ev[PH_N + 2], s);
     }
     const bool small = c->nsg > 0;
+    if (small && c->nsg == c->ngraph) {
+        // every graph is small: the engine alone, then its commit and the
+        // cleanup (no kernel sequence; its time counts as replacement edges)
+        for (int i = 0; i < PH_N; i++)
+            if (i != PH_REPL) mark(i, false);
+        mark(PH_REPL);
+        if (launch_small_update(d, make_small(c), c->small_threads, c->small_grid, s))
+            launch_fill_i32(c->status, 1, ST_ROUND_BOUND, s);
+        mark(PH_N);
+        launch_small_commit(d, make_small(c), grid_for(c->nsg, 1, GRID_CAP), true, s);
+        launch_cleanup(d, s);
+        return;
+    }
     if (small) {  // the small graphs' kernel on its own branch
         (void)hipEventRecord(c->ev_fork, s);
         (void)hipStreamWaitEvent(c->s2, c->ev_fork, 0);
@@ -995,31 +979,17 @@ void enqueue_update(drsf_ctx *c, int kind, bool profile) {
     mark(PH_ROOT, del);
     if (del) launch_rep_chase(d, s);
     mark(PH_ORPH_LIST, del);
-    if (del) launch_orphan_plan(d, s);
-    // deletes: the sweeps of the inserted-edge list and of the store (a
-    // no-op when the orphan scan runs) need only root finding and the scan
-    // mode; they write other regions of x0 than the orphan list and scan, so
-    // they run on a branch beside them (not when profiling: phases are
-    // timed in order)
-    const bool fork = del && !profile && c->s3;
-    if (fork) {
-        (void)hipEventRecord(c->ev_fork3, s);
-        (void)hipStreamWaitEvent(c->s3, c->ev_fork3, 0);
-        launch_sweep_delta(d, c->s3);
-        launch_sweep_base(d, c->s3);
+    if (del) {
+        launch_orphan_plan(d, s);
+        launch_orphan_fill(d, s);
     }
-    if (del) launch_orphan_fill(d, s);
     mark(PH_ORPH_SCAN, del);
     if (del) launch_orphan_scan(d, s);
     mark(PH_SWEEP, del);
-    if (del && !fork) launch_sweep_base(d, s);
+    if (del) launch_sweep_base(d, s);
     mark(PH_SWEEP_DELTA);
     if (ins) launch_insert_emit(d, s);
-    if (del && !fork) launch_sweep_delta(d, s);
-    if (fork) {
-        (void)hipEventRecord(c->ev_join3, c->s3);
-        (void)hipStreamWaitEvent(s, c->ev_join3, 0);
-    }
+    if (del) launch_sweep_delta(d, s);
     mark(PH_REPL);
     const int64_t units = (ins ? insert_regions(c->max_batch) : 0) + (del ? c->ntiles + c->dtmax : 0);
     if (c->opts.replacement_mode == 1) {  // supergraph, then its rounds
@@ -1042,7 +1012,7 @@ void enqueue_update(drsf_ctx *c, int kind, bool profile) {
     mark(PH_N);
     if (small) {
         (void)hipStreamWaitEvent(s, c->ev_join, 0);
-        launch_small_commit(d, make_small(c), grid_for(c->nsg, 1, GRID_CAP), s);
+        launch_small_commit(d, make_small(c), grid_for(c->nsg, 1, GRID_CAP), false, s);
     }
     launch_cleanup(d, s);  // also hands the results to the host
 }
@@ -1158,7 +1128,6 @@ int launch_update(drsf_ctx *c) {
     *(volatile unsigned long long *)(c->h_ret + c->ret_words + 7) = 0;
     c->kind = (c->h_ctl->has_ins ? 1 : 0) | (c->h_ctl->has_del ? 2 : 0);
     if (c->kind == 0) c->kind = 3;  // nothing but rejected or empty batches: run everything
-    if ((c->kind & 2) && !prof) (void)ensure_branch(c);
     // the supergraph reads sizes back between its kernels, so it is not
     // captured (the Euler-tour reversal, sort included, is a fixed sequence)
     if (prof || c->opts.replacement_mode == 1) {
@@ -1580,14 +1549,18 @@ int drsf_multi_apply_async(drsf_ctx *c, const int32_t *edges, const int64_t *b_o
     // inserting graphs and the base-store tiles of the deleting ones
     bool any_ins = false, any_del = false;
     int32_t nsmall = 0;
+    // every graph small: the engine alone runs, which reads the tasks only
+    // (no per-edge op and graph, no block lists)
+    const bool alone = c->nsg > 0 && c->nsg == G;
     for (int32_t g = 0; g < G; g++) {
         const int32_t k = c->nsg ? c->g2s[g] : -1;
         // op 2: the edge belongs to a small graph, whose own kernel takes it
         const int8_t eo = k < 0 ? op[g] : (int8_t)2;
-        for (int64_t i = b_off[g]; i < b_off[g + 1]; i++) {
-            c->h_bop[i] = eo;
-            c->h_bgid[i] = g;
-        }
+        if (!alone)
+            for (int64_t i = b_off[g]; i < b_off[g + 1]; i++) {
+                c->h_bop[i] = eo;
+                c->h_bgid[i] = g;
+            }
         if (b_off[g + 1] == b_off[g]) continue;
         if (k < 0) (op[g] == DRSF_DELETE ? any_del : any_ins) = true;
         else c->h_stasks[nsmall++] = make_int4(k, (int)b_off[g], (int)(b_off[g + 1] - b_off[g]), op[g]);
@@ -1596,7 +1569,7 @@ int drsf_multi_apply_async(drsf_ctx *c, const int32_t *edges, const int64_t *b_o
     // lists of -1: every vertex block and tile (one graph: the lists, only
     // allocated for several, would hold them all)
     int64_t nvl = -1, nil = -1, ntl = -1;
-    if (c->h_lists) {
+    if (c->h_lists && !alone) {
         int32_t *vl = c->h_lists, *il = c->h_lists + c->nvblk, *tl = c->h_lists + 2 * c->nvblk;
         int64_t lastv = -1, lasti = -1, lastt = -1;
         nvl = nil = ntl = 0;
@@ -1623,8 +1596,10 @@ int drsf_multi_apply_async(drsf_ctx *c, const int32_t *edges, const int64_t *b_o
     }
     if (nsmall)
         HIPCHK(c, hipMemcpyAsync(c->stasks, c->h_stasks, sizeof(int4) * (size_t)nsmall, hipMemcpyHostToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(c->bop, c->h_bop, (size_t)b, hipMemcpyHostToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(c->bgid, c->h_bgid, sizeof(int32_t) * (size_t)b, hipMemcpyHostToDevice, s));
+    if (!alone) {
+        HIPCHK(c, hipMemcpyAsync(c->bop, c->h_bop, (size_t)b, hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(c->bgid, c->h_bgid, sizeof(int32_t) * (size_t)b, hipMemcpyHostToDevice, s));
+    }
     if ((rc = stage_edges(c, edges, b))) return rc;
     Ctl &k = *c->h_ctl;
     memset(&k, 0, sizeof k);

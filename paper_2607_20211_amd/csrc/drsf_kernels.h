@@ -178,8 +178,10 @@ size_t small_lds_bytes(int T);  // dynamic LDS of the small-graph kernel for T v
 size_t small_static_lds();      // and its static LDS
 int small_prepare(int T);  // allows the kernel its LDS (once, before any launch or capture)
 int launch_small_update(const Dev &d, const SmallDev &s, int threads, int grid, hipStream_t st);
-void launch_small_commit(const Dev &d, const SmallDev &s, int grid, hipStream_t st);
+void launch_small_commit(const Dev &d, const SmallDev &s, int grid, bool alone, hipStream_t st);
 void launch_small_init(const Dev &d, const SmallDev &s, hipStream_t st);
+// pool growth: live keys to their new regions (new offsets noff[nsg])
+void launch_small_regrow(const Dev &d, const SmallDev &s, const int64_t *noff, uint32_t *npool, hipStream_t st);
 
 // slots per range of the orphan adjacency scan (one workgroup pass).  A
 // region of x0 (TILE entries, one per base-store tile) takes the cross edges

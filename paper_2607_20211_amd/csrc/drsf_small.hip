@@ -551,10 +551,21 @@ __global__ __launch_bounds__(1024) void k_small_update(Dev d, SmallDev s) {
 
 // After both branches: staged parents and labels of the updated small
 // graphs into the context's arrays (rep == label between updates), and the
-// work queue reset for the next update.
-__global__ __launch_bounds__(BLOCK) void k_small_commit(Dev d, SmallDev s) {
+// work queue reset for the next update.  alone: every graph of the context
+// is small, so no kernel sequence ran: this kernel also publishes the
+// update's control block, clears the batch's hash-slot marks and marks the
+// update finished, as the sequence's kernels would, for the cleanup.
+__global__ __launch_bounds__(BLOCK) void k_small_commit(Dev d, SmallDev s, int alone) {
     const int ntask = d.hctl->nsmall;
     if (blockIdx.x == 0 && threadIdx.x == 0) *s.qhead = 0;
+    if (alone) {
+        const Ctl *hc = d.hctl;
+        if (blockIdx.x == 0 && threadIdx.x < sizeof(Ctl) / 8)
+            reinterpret_cast<uint64_t *>(d.ctlw)[threadIdx.x] = reinterpret_cast<const uint64_t *>(hc)[threadIdx.x];
+        if (blockIdx.x == 0 && threadIdx.x == 0) d.cnt[C_ORIENTED] = 1;
+        for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < hc->b; i += (int64_t)gridDim.x * BLOCK)
+            d.bslot[i] = NONE;
+    }
     for (int t = blockIdx.x; t < ntask; t += gridDim.x) {
         const int sidx = s.tasks[t].x;
         if (!s.sok[sidx]) continue;
@@ -568,6 +579,18 @@ __global__ __launch_bounds__(BLOCK) void k_small_commit(Dev d, SmallDev s) {
             d.label[o + v] = lab;
             d.rep[o + v] = lab;
         }
+    }
+}
+
+// Pool growth: every small graph's live keys (buffer sbuf, sm keys) copied
+// to the start of its region in the new pool (new offsets in noff), one
+// workgroup per graph.
+__global__ __launch_bounds__(BLOCK) void k_small_regrow(SmallDev s, const int64_t *noff, uint32_t *npool) {
+    for (int sidx = blockIdx.x; sidx < s.nsg; sidx += gridDim.x) {
+        const uint32_t *src = s.pool + s.soff[sidx] + (int64_t)s.sbuf[sidx] * s.scap[sidx];
+        uint32_t *dst = npool + noff[sidx];
+        const int m = s.sm[sidx];
+        for (int j = threadIdx.x; j < m; j += BLOCK) dst[j] = src[j];
     }
 }
 
@@ -613,8 +636,11 @@ int launch_small_update(const Dev &d, const SmallDev &s, int threads, int grid, 
     hipLaunchKernelGGL(k_small_update, dim3(grid), dim3(threads), small_lds_bytes(s.T), st, d, s);
     return 0;
 }
-void launch_small_commit(const Dev &d, const SmallDev &s, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(k_small_commit, dim3(grid), dim3(BLOCK), 0, st, d, s);
+void launch_small_commit(const Dev &d, const SmallDev &s, int grid, bool alone, hipStream_t st) {
+    hipLaunchKernelGGL(k_small_commit, dim3(grid), dim3(BLOCK), 0, st, d, s, alone ? 1 : 0);
+}
+void launch_small_regrow(const Dev &, const SmallDev &s, const int64_t *noff, uint32_t *npool, hipStream_t st) {
+    hipLaunchKernelGGL(k_small_regrow, dim3(grid_for(s.nsg, 1, GRID_CAP)), dim3(BLOCK), 0, st, s, noff, npool);
 }
 void launch_small_init(const Dev &d, const SmallDev &s, hipStream_t st) {
     hipLaunchKernelGGL(k_small_init, dim3(grid_for(s.nsg, 1, GRID_CAP)), dim3(BLOCK), 0, st, d, s);

@@ -118,3 +118,27 @@ def test_small_graph_rejections(T):
             bad = {0: kind, 2: kind} if len(batches[2]) else {0: kind}
             pair.step(batches, ops, f"rejection {kind} size {size}", bad=bad)
     pair.gpu.close()
+
+
+@pytest.mark.parametrize("profile", [False, True])
+def test_every_graph_small_runs_the_engine_alone(profile):
+    """A context whose graphs are all small launches the engine, its commit
+    and the cleanup only (no kernel sequence): inserts, deletes, an invalid
+    batch, empty batches; bit-exact per graph; profiled, the engine's time
+    is the replacement-edge phase and the sequence's phases read 0."""
+    drsf = _lib()
+    _case(f"engine alone profile={profile}")
+    ns, _, _, _ = gen.batched_sizes(60, gen.seed(49, 0, gen.P_GRAPH), log_n=(0.5, 3.3))
+    graphs = _graphs(ns, 12)
+    pair = MultiPair(graphs, max_batch=1 << 16, small_graph_vertices=2048, profile=profile)
+    for step in range(4):
+        _, _, ops, bs = gen.batched_sizes(60, gen.seed(49, step + 1, gen.P_STREAM), log_b=(0.0, 2.7))
+        bs[step::5] = 0
+        batches, ops = gen.multi_step_batches(pair.local_state(), ops, bs, gen.seed(49, step, gen.P_INSERT))
+        pair.step(batches, ops, f"engine alone step {step}", bad={(7 * step + 3) % 60: "dup"})
+        if profile:
+            t = pair.gpu.phase_times()
+            assert t["replacement_edges"] > 0, t
+            assert all(t[k] == 0.0 for k in ("validate", "update_graph", "root_finding", "orphan_scan",
+                                              "superforest_rooting", "reversal_and_labels")), t
+    pair.gpu.close()
