@@ -988,17 +988,20 @@ void enqueue_update(drsf_ctx *c, int kind, bool profile) {
     mark(PH_SWEEP, del);
     if (del) launch_sweep_base(d, s);
     mark(PH_SWEEP_DELTA);
-    if (ins) launch_insert_emit(d, s);
+    // the supergraph reads the insert regions before the rounds; otherwise
+    // the first round emits them itself
+    const bool sg = c->opts.replacement_mode == 1;
+    if (ins && sg) launch_insert_emit(d, s);
     if (del) launch_sweep_delta(d, s);
     mark(PH_REPL);
     const int64_t units = (ins ? insert_regions(c->max_batch) : 0) + (del ? c->ntiles + c->dtmax : 0);
-    if (c->opts.replacement_mode == 1) {  // supergraph, then its rounds
+    if (sg) {  // supergraph, then its rounds
         c->round_base = SG_ROUND0;
         if (sg_reduce(c, d, s)) launch_fill_i32(c->status, 1, ST_ROUND_BOUND, s);
-        launch_boruvka(d, SG_ROUND0, SG_ROUND0 + c->bor_fast, units, s);
+        launch_boruvka(d, SG_ROUND0, SG_ROUND0 + c->bor_fast, units, false, s);
     } else {
         c->round_base = 0;
-        launch_boruvka(d, 0, c->bor_fast, units, s);
+        launch_boruvka(d, 0, c->bor_fast, units, ins, s);
     }
     mark(PH_ROOTING);
     launch_sf_root(d, s);
@@ -1060,7 +1063,7 @@ int continue_update(drsf_ctx *c) {
         how |= 1;
         while (!done && !bad && r < bor_bound) {
             const int r1 = std::min(r + BOR_CHUNK, bor_bound);
-            launch_boruvka(d, r, r1, 4096, s);
+            launch_boruvka(d, r, r1, 4096, false, s);
             r = r1;
             if ((rc = read_flags(lv))) return rc;
             bad = *(int32_t *)f != 0;

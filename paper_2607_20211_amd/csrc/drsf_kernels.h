@@ -264,7 +264,9 @@ void launch_orphan_fill(const Dev &d, hipStream_t s);  // the orphan list
 void launch_orphan_scan(const Dev &d, hipStream_t s);
 void launch_sweep_delta(const Dev &d, hipStream_t s);
 // units: regions of x0 the first two rounds may read (sizes their grids)
-void launch_boruvka(const Dev &d, int r0, int r1, int64_t units, hipStream_t s);
+// rounds [r0, r1); emit: round 0 also emits the insert cross edges
+// (k_insert_emit not launched)
+void launch_boruvka(const Dev &d, int r0, int r1, int64_t units, bool emit, hipStream_t s);
 void launch_sf_root(const Dev &d, hipStream_t s);
 void launch_sf_bfs(const Dev &d, int l0, int l1, hipStream_t s);
 void launch_orient_bfs(const Dev &d, int levels, hipStream_t s);

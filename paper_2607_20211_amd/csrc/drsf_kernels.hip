@@ -486,13 +486,11 @@ __global__ __launch_bounds__(BLOCK) void k_register(Dev d) {
 }
 
 // insert: key edges M = B; cross edges join two different trees (labels).
-// Workgroup t takes batch entries [t * BLOCK, (t + 1) * BLOCK) and writes
-// region ibase + t of x0.
-__global__ __launch_bounds__(BLOCK) void k_insert_emit(Dev d) {
-    if (*d.status || !d.ctl->has_ins) return;
+// Batch entries [t * BLOCK, (t + 1) * BLOCK) go to region ibase + t of x0;
+// every thread of the workgroup calls it.  Returns the thread's edge (live
+// when it is a cross edge) and, through *total, the region's count.
+__device__ bool insert_emit_block(const Dev &d, int64_t t, Cross *e, int *total) {
     const int64_t b = d.ctl->b;
-    const int64_t t = blockIdx.x;
-    if (t * BLOCK >= b) return;
     const int64_t i = t * BLOCK + threadIdx.x;
     bool cross = false;
     uint64_t k = 0;
@@ -503,17 +501,28 @@ __global__ __launch_bounds__(BLOCK) void k_insert_emit(Dev d) {
         lb = d.label[key_hi(k)];
         cross = la != lb;
     }
-    int total;
-    const int off = block_excl_scan(cross ? 1 : 0, &total);
+    const int off = block_excl_scan(cross ? 1 : 0, total);
     const int64_t reg = d.ctl->ibase + t;
-    if (threadIdx.x == 0) d.rcnt[reg] = (unsigned long long)total;
+    if (threadIdx.x == 0) d.rcnt[reg] = (unsigned long long)*total;
+    e->key = k;
+    e->pa = e->pb = 0;
     if (cross) {
-        Cross e;
-        e.key = k;
-        e.pa = d.tidx[la];
-        e.pb = d.tidx[lb];
-        d.x0[reg * TILE + off] = e;
+        e->pa = d.tidx[la];
+        e->pb = d.tidx[lb];
+        d.x0[reg * TILE + off] = *e;
     }
+    return cross;
+}
+
+// The insert emit on its own (the supergraph reads the regions before the
+// first round); in the default mode the first hooking round does it.
+__global__ __launch_bounds__(BLOCK) void k_insert_emit(Dev d) {
+    if (*d.status || !d.ctl->has_ins) return;
+    const int64_t t = blockIdx.x;
+    if (t * BLOCK >= d.ctl->b) return;
+    Cross e;
+    int total;
+    (void)insert_emit_block(d, t, &e, &total);
 }
 
 // ----------------------------------------------- a4: root finding (delete)
@@ -1241,16 +1250,29 @@ __device__ __forceinline__ void select_edge(const Dev &d, bool live, const Cross
 }
 
 // Round 0: every cross edge is live and every component is a single piece.
-// Workgroups take the regions [rlo, rhi) of x0 in turn.  Workgroup 0 also
-// sums the region lengths (the number of cross edges found).
-__global__ __launch_bounds__(BLOCK) void k_bor_round0(Dev d) {
+// Workgroups take the regions [rlo, rhi) of x0 in turn.  With emit, the
+// insert regions are not filled yet: a workgroup taking one runs the insert
+// emit for its batch entries (writing the region for the next round) and
+// selects on the edges it found, and adds its count to the statistic.
+// Workgroup 0 sums the other region lengths (the cross edges found).
+__global__ __launch_bounds__(BLOCK) void k_bor_round0(Dev d, int emit) {
     if (*d.status) return;
     // regions below ntiles hold the orphan scan's output when it ran: those
     // edges took part in this round's selection already
     const bool om = d.cnt[C_OMODE] != 0;
     const int64_t rhi = d.ctl->rhi;
     const int64_t rlo = om ? (d.ctl->rlo > d.ntiles ? d.ctl->rlo : d.ntiles) : d.ctl->rlo;
+    const bool ins_here = emit && d.ctl->has_ins;
+    const int64_t ib = d.ctl->ibase, ie = ins_here ? ib + (d.ctl->b + BLOCK - 1) / BLOCK : ib;
     for (int64_t t = rlo + blockIdx.x; t < rhi; t += gridDim.x) {
+        if (t >= ib && t < ie) {  // uniform over the workgroup
+            Cross e;
+            int total;
+            const bool live = insert_emit_block(d, t - ib, &e, &total);
+            select_edge(d, live, e, e.pa, e.pb, d.best);
+            if (threadIdx.x == 0 && total) atomicAdd(&d.cnt[C_NCROSS], (unsigned long long)total);
+            continue;
+        }
         const int64_t cntr = (int64_t)d.rcnt[t];
         const Cross *in = d.x0 + t * TILE;
         for (int64_t base = 0; base < cntr; base += BLOCK) {
@@ -1265,7 +1287,8 @@ __global__ __launch_bounds__(BLOCK) void k_bor_round0(Dev d) {
     }
     if (blockIdx.x == 0) {
         unsigned long long s = 0;
-        for (int64_t r = rlo + threadIdx.x; r < rhi; r += BLOCK) s += d.rcnt[r];
+        for (int64_t r = rlo + threadIdx.x; r < rhi; r += BLOCK)
+            if (r < ib || r >= ie) s += d.rcnt[r];
         if (om) {
             const int64_t nr = or_regions((int64_t)d.cnt[C_OVOL], d.eb);
             for (int64_t r = threadIdx.x; r < nr; r += BLOCK) s += d.xcnt[r];
@@ -2154,12 +2177,12 @@ void launch_sweep_delta(const Dev &d, hipStream_t s) {
 // The hooking, rooting and reversal kernels index pieces, arcs and paths
 // (at most 2 max_batch): grids of one workgroup per CU, grid-stride, so a
 // round that finds nothing to do costs little dispatch.
-void launch_boruvka(const Dev &d, int r0, int r1, int64_t units, hipStream_t s) {
+void launch_boruvka(const Dev &d, int r0, int r1, int64_t units, bool emit, hipStream_t s) {
     const int ge = grid_for(units, 1, EDGE_CAP);
     const int gp = grid_for(d.pcap, BLOCK, SMALL_CAP);
     for (int r = r0; r < r1; r++) {
         if (r == 0)
-            hipLaunchKernelGGL(k_bor_round0, dim3(ge), dim3(BLOCK), 0, s, d);
+            hipLaunchKernelGGL(k_bor_round0, dim3(ge), dim3(BLOCK), 0, s, d, emit ? 1 : 0);
         else
             hipLaunchKernelGGL(k_bor_select, dim3(r == 1 ? ge : gp), dim3(BLOCK), 0, s, d, r);
         hipLaunchKernelGGL(k_bor_hook, dim3(gp), dim3(BLOCK), 0, s, d, r);
