@@ -59,14 +59,19 @@ class Pair:
 
     def check_equal(self, what):
         p, lab = self.gpu.parent(), self.gpu.label()
-        if not np.array_equal(lab, self.label):
-            bad = np.flatnonzero(lab != self.label)[:10]
-            raise AssertionError(f"{what}: label mismatch at {bad.tolist()} "
-                                 f"gpu={lab[bad].tolist()} oracle={self.label[bad].tolist()}")
-        if not np.array_equal(p, self.parent):
-            bad = np.flatnonzero(p != self.parent)[:10]
-            raise AssertionError(f"{what}: parent mismatch at {bad.tolist()} "
-                                 f"gpu={p[bad].tolist()} oracle={self.parent[bad].tolist()}")
+        for name, got, want in (("label", lab, self.label), ("parent", p, self.parent)):
+            # one snapshot of the copied array, so that the report shows the
+            # values that failed the comparison
+            snap = np.array(got, copy=True)
+            if np.array_equal(snap, want):
+                continue
+            bad = np.flatnonzero(snap != want)[:10] if snap.shape == want.shape else np.zeros(0, np.int64)
+            again = getattr(self.gpu, name)()
+            raise AssertionError(
+                f"{what}: {name} mismatch at {bad.tolist()} gpu={snap[bad].tolist()} "
+                f"oracle={want[bad].tolist()} (shapes {snap.shape} {want.shape}, dtypes {snap.dtype} "
+                f"{want.dtype}; the returned array now {'equals' if np.array_equal(got, want) else 'differs from'} "
+                f"the oracle's, a second copy {'equals' if np.array_equal(again, want) else 'differs from'} it)")
         rc, msg = oracle.check_forest(self.n, self.keys, p, lab)
         assert rc == 0, f"{what}: checker: {msg}"
 
