@@ -13,12 +13,12 @@ device memory before the timed region starts.
 
 Prints one JSON line: value = edge updates per second of the whole timed
 job (insert + delete) in the production configuration (each update replays
-the context's captured HIP graph); insert and delete latencies as seen by
-the host; per-phase device times and the roofline of the dominant kernel
-(the key-edge sweep of the base edge store) from a second pass over the
-same steps that launches the kernels one by one with events between the
-phases on the stream the kernels run on; and the CPU oracle timed on a
-bounded sample.
+the context's captured HIP graph, queued behind the one before it so that
+two are in flight); insert and delete latencies as seen by the host from a
+pass over the same steps one update at a time; per-phase device times and
+the rooflines of the dominant kernels from a pass that launches the kernels
+one by one with events between the phases on the stream the kernels run
+on; and the CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -723,7 +723,8 @@ def main():
                            inputs_on_device=True, profile=profile,
                            delta_capacity=max(nsteps * b + b, 1 << 20))
 
-    # timed pass: the production configuration (captured update graph, no events)
+    # timed pass: the production configuration (captured update graphs, two
+    # updates in flight, no events)
     f = make(0)
     torch.cuda.synchronize()
     log(f"context created ({time.time() - t0:.1f}s)")
@@ -741,21 +742,59 @@ def main():
         f.apply(d_ins[i], drsf.DRSF_INSERT)
         f.apply(d_del[i], drsf.DRSF_DELETE)
     torch.cuda.synchronize()
-    lat_ins, lat_del, st_ins, st_del = [], [], [], []
-    t_start = time.perf_counter()
-    for i in range(W, W + K):
-        ta = time.perf_counter()
-        st_ins.append(f.apply(d_ins[i], drsf.DRSF_INSERT))
-        tb = time.perf_counter()
-        st_del.append(f.apply(d_del[i], drsf.DRSF_DELETE))
-        tc = time.perf_counter()
-        lat_ins.append(tb - ta)
-        lat_del.append(tc - tb)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
+    # the batches as views, taken before the clock starts
+    v_ins = [d_ins[i] for i in range(W + K)]
+    v_del = [d_del[i] for i in range(W + K)]
+
+    def run_queued(fr):
+        """The K steps with each batch queued behind the one before it (two
+        in flight: drsf_apply_async, then drsf_wait for the older); returns
+        the wall time and the per-batch statistics."""
+        si, sd = [], []
+        t = time.perf_counter()
+        fr.apply_async(v_ins[W], drsf.DRSF_INSERT)
+        for i in range(W, W + K):
+            fr.apply_async(v_del[i], drsf.DRSF_DELETE)
+            si.append(fr.wait())
+            if i + 1 < W + K:
+                fr.apply_async(v_ins[i + 1], drsf.DRSF_INSERT)
+            sd.append(fr.wait())
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, si, sd
+
+    wall, st_ins, st_del = run_queued(f)
     digest_timed = [int(x) for x in f.digest()]
     f.close()
     log(f"timed {K} steps in {wall * 1e3:.2f} ms")
+
+    # the same steps one update at a time (drsf_apply: each waits for the
+    # last), on a fresh context: the per-op latencies, and the same forest
+    fs = make(0)
+    if tuning:
+        fs.set_tuning(tuning["rounds_queued"], tuning["levels_queued"], tuning["sweep_mode"])
+    for i in range(W):
+        fs.apply(v_ins[i], drsf.DRSF_INSERT)
+        fs.apply(v_del[i], drsf.DRSF_DELETE)
+    torch.cuda.synchronize()
+    lat_ins, lat_del = [], []
+    ts0 = time.perf_counter()
+    for i in range(W, W + K):
+        ta = time.perf_counter()
+        fs.apply(v_ins[i], drsf.DRSF_INSERT)
+        tb = time.perf_counter()
+        fs.apply(v_del[i], drsf.DRSF_DELETE)
+        lat_ins.append(tb - ta)
+        lat_del.append(time.perf_counter() - tb)
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - ts0
+    same_s = [int(x) for x in fs.digest()] == digest_timed
+    fs.close()
+    assert same_s, "one update at a time ended in a different forest"
+    sequential = {"value": round(2 * b * K / wall_s, 1), "ms_per_step": round(wall_s / K * 1e3, 4),
+                  "same_forest": same_s,
+                  "what": "the timed steps applied one at a time (each update waits for the one before; "
+                          "the per-op latencies below come from this pass)"}
+    log(f"sequential: {sequential}")
 
     # the same steps with batch validation off (drsf_opts.validate_batches =
     # 0: the caller guarantees valid batches, as these are): the same forest
@@ -768,25 +807,14 @@ def main():
         fu.apply(d_ins[i], drsf.DRSF_INSERT)
         fu.apply(d_del[i], drsf.DRSF_DELETE)
     torch.cuda.synchronize()
-    lu_ins, lu_del = [], []
-    tu0 = time.perf_counter()
-    for i in range(W, W + K):
-        ta = time.perf_counter()
-        fu.apply(d_ins[i], drsf.DRSF_INSERT)
-        tb = time.perf_counter()
-        fu.apply(d_del[i], drsf.DRSF_DELETE)
-        lu_ins.append(tb - ta)
-        lu_del.append(time.perf_counter() - tb)
-    torch.cuda.synchronize()
-    wall_u = time.perf_counter() - tu0
+    wall_u, _, _ = run_queued(fu)
     same_u = [int(x) for x in fu.digest()] == digest_timed
     fu.close()
     assert same_u, "validate_batches=0 ended in a different forest"
     unvalidated = {"value": round(2 * b * K / wall_u, 1), "ms_per_step": round(wall_u / K * 1e3, 4),
-                   "insert_ms_mean": round(float(np.mean(lu_ins)) * 1e3, 4),
-                   "delete_ms_mean": round(float(np.mean(lu_del)) * 1e3, 4), "same_forest": same_u,
-                   "what": "the timed steps on a context with validate_batches = 0 (no repeated-pair check, "
-                           "no presence search for inserts; the batches are valid)"}
+                   "same_forest": same_u,
+                   "what": "the timed steps, queued as timed, on a context with validate_batches = 0 (no "
+                           "repeated-pair check, no presence search for inserts; the batches are valid)"}
     log(f"unvalidated: {unvalidated}")
 
     # profiled pass: the same steps on a fresh context that launches the same
@@ -933,6 +961,9 @@ def main():
         "event_bracket_ms": {"insert": round(ev_ins, 4), "delete": round(ev_del, 4)},
         "phase_share_vs_paper": phase_share,
         "tuning": tuning,
+        "timed_as": "each batch queued behind the one before it (two updates in flight); per-op "
+                    "latencies from the sequential pass",
+        "sequential": sequential,
         "unvalidated": unvalidated,
         "roofline": roofline,
         "rooflines": rooflines,

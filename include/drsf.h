@@ -233,10 +233,23 @@ int drsf_apply(drsf_ctx *ctx, const int32_t *edges, int64_t b, int op, drsf_view
  * free that lets another stream reuse it) must wait for drsf_wait.  Call
  * drsf_wait before reading results or queueing host reads; device work
  * queued later on the same stream is ordered after the update.
+ *
+ * Two updates may be in flight: on a one-graph context with
+ * inputs_on_device, without profiling and with the default replacement and
+ * reversal modes, a batch is queued behind the one still running, so that
+ * the device starts it as soon as the first is done (the host's round trip
+ * between them is hidden; the result is the same as applying them one after
+ * the other).  A third call first waits for the oldest; an empty batch, one
+ * that needs a store rebuild, and every other context wait for all queued
+ * updates first.  If the running update needs the host to finish it (see
+ * drsf_view.host_finished), the one queued behind it does nothing on the
+ * device until drsf_wait has finished the first, then runs.  A status the
+ * call itself returns belongs to an earlier update that it waited for.
  */
 int drsf_apply_async(drsf_ctx *ctx, const int32_t *edges, int64_t b, int op);
 
-/* Waits for queued work and returns the status of the last queued apply. */
+/* Waits for the oldest queued update and returns its status; with none
+ * queued, returns the status of the last update waited for. */
 int drsf_wait(drsf_ctx *ctx, drsf_view *out);
 
 /*

@@ -159,18 +159,29 @@ struct drsf_ctx {
     int8_t *h_bop = nullptr;              // [max_batch]
     int32_t *h_bgid = nullptr;            // [max_batch]
     int32_t *h_lists = nullptr;           // vlist | ilist | tlist
+    // Two slots of control block and returned words: an update can be
+    // queued while the one before it runs.  Update number q uses slot q & 1;
+    // h_ctl, h_ret and h_gstat point into the slot in use.
+    Ctl *h_ctl_ring = nullptr;
+    unsigned long long *h_ret_ring = nullptr;
+    int slot = 0;
     Ctl *h_ctl = nullptr;
     unsigned long long *h_ret = nullptr;  // copy of ctlmem, then scratch words; the last is the
                                           // completion word (seq of the finished update)
     uint64_t seq = 0;                     // updates launched
     int32_t *h_gstat = nullptr;           // [ngraph] inside h_ret
-    // captured update sequences, by kind (1 inserts, 2 deletes, 3 both)
-    hipGraph_t graph[4] = {};
-    hipGraphExec_t gexec[4] = {};
-    int kind = 0;  // of the pending update
+    // captured update sequences, by slot and kind (1 inserts, 2 deletes, 3 both)
+    hipGraph_t graph[2][4] = {};
+    hipGraphExec_t gexec[2][4] = {};
+    int kind = 0;  // of the update being waited for
     int bor_fast = BOR_FAST, bfs_fast = BFS_FAST;
-    // last apply
-    bool pending = false;
+    // queued updates not yet waited for (the oldest is number seq - npend + 1)
+    struct Pend {
+        uint64_t seq;
+        int kind, op;
+        int64_t b;
+    } pend[2] = {};
+    int npend = 0;
     bool multi_last = false;
     std::vector<int64_t> last_bg;  // per-graph batch sizes of the last apply
     std::vector<int8_t> last_opg;  // per-graph op of the last apply
@@ -190,7 +201,8 @@ struct drsf_ctx {
     std::vector<size_t> alloc_bytes;
     int64_t bytes = 0, peak_bytes = 0;  // device bytes held now / at most
     int64_t rebuilds = 0;               // store rebuilds so far
-    bool broken = false;                // a store rebuild failed after dropping the old store
+    bool broken = false;                // a store rebuild failed after dropping the old store, or a
+                                        // host continuation failed with an update held behind it
     // small graphs of a multi-graph context (drsf_opts.small_graph_vertices):
     // updated whole by one workgroup each, beside the chain, on stream s2
     int32_t nsg = 0, small_T = 0, small_threads = 512, small_grid = 0;
@@ -291,6 +303,7 @@ Dev make_dev(drsf_ctx *c) {
     memset(&d, 0, sizeof d);
     d.n = c->n;
     d.validate = c->opts.validate_batches != 0;
+    d.gate = 1;
     d.ctl = c->ctl;
     d.ctlw = c->ctl;
     d.hctl = c->h_ctl;
@@ -375,6 +388,16 @@ int read_status(drsf_ctx *c, int32_t *st) {
 // Arrays sized by the base store's tiles: cross-edge regions (base-store
 // tiles, inserted-edge tiles, batch regions), orphan-scan ranges and, with
 // several graphs, the block and tile lists.  Called again after a rebuild.
+// Points h_ctl, h_ret and h_gstat at slot q.
+void select_slot(drsf_ctx *c, int q) {
+    c->slot = q;
+    if (c->h_ctl_ring) c->h_ctl = c->h_ctl_ring + q;
+    if (c->h_ret_ring) {
+        c->h_ret = c->h_ret_ring + (size_t)q * (size_t)(c->ret_words + 8);
+        c->h_gstat = reinterpret_cast<int32_t *>(c->h_ret + 1 + C_TOTAL);
+    }
+}
+
 int alloc_tiles(drsf_ctx *c) {
     int rc;
     dfree(c, c->x0); dfree(c, c->x1); dfree(c, c->rcnt); dfree(c, c->rstart); dfree(c, c->xcnt);
@@ -504,7 +527,8 @@ int alloc_state(drsf_ctx *c) {
     if ((rc = halloc(c, &c->h_edges, 2 * mb))) return rc;
     if ((rc = halloc(c, &c->h_bop, mb))) return rc;
     if ((rc = halloc(c, &c->h_bgid, mb))) return rc;
-    if ((rc = halloc(c, &c->h_ctl, 1))) return rc;
+    if ((rc = halloc(c, &c->h_ctl_ring, 2))) return rc;
+    select_slot(c, c->slot);
     launch_fill_i32(c->tidx, n, NONE, s);
     launch_fill_i32(c->level, c->pcap, -1, s);  // the search state is reset by each update's cleanup
     launch_fill_i32(c->parc, c->pcap, NONE, s);
@@ -517,25 +541,23 @@ int alloc_state(drsf_ctx *c) {
 // Drops the captured update sequences (the next update captures anew with
 // the context's current round and level counts and buffers).
 void drop_graphs(drsf_ctx *c) {
-    for (int k = 0; k < 4; k++) {
-        if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
-        if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
-        c->gexec[k] = nullptr;
-        c->graph[k] = nullptr;
-    }
+    for (int q = 0; q < 2; q++)
+        for (int k = 0; k < 4; k++) {
+            if (c->gexec[q][k]) (void)hipGraphExecDestroy(c->gexec[q][k]);
+            if (c->graph[q][k]) (void)hipGraphDestroy(c->graph[q][k]);
+            c->gexec[q][k] = nullptr;
+            c->graph[q][k] = nullptr;
+        }
 }
 
 void destroy_ctx(drsf_ctx *c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     if (c->s2) (void)hipStreamSynchronize(c->s2);
-    for (int k = 0; k < 4; k++) {
-        if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
-        if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
-    }
+    drop_graphs(c);
     for (void *p : c->allocs) raw_dfree(c->opts, p);
     c->allocs.clear();
-    void *hosts[] = {c->h_edges, c->h_bop, c->h_bgid, c->h_lists, c->h_ctl, c->h_ret};
+    void *hosts[] = {c->h_edges, c->h_bop, c->h_bgid, c->h_lists, c->h_ctl_ring, c->h_ret_ring};
     for (void *p : hosts)
         if (p) (void)hipHostFree(p);
     for (auto &e : c->ev)
@@ -935,7 +957,9 @@ int sg_reduce(drsf_ctx *c, const Dev &d, hipStream_t s) {
 
 // The update sequence (see the file comment) for batches with inserts
 // (kind bit 1) and/or deletes (kind bit 2); with events when profiling.
-void enqueue_update(drsf_ctx *c, int kind, bool profile) {
+// kc: the control block, passed with the first kernel when the sequence is
+// launched kernel by kernel (null while capturing: read from pinned memory).
+void enqueue_update(drsf_ctx *c, int kind, bool profile, const Ctl *kc) {
     const Dev d = make_dev(c);
     hipStream_t s = c->stream;
     const bool ins = kind & 1, del = kind & 2;
@@ -971,7 +995,7 @@ void enqueue_update(drsf_ctx *c, int kind, bool profile) {
         (void)hipEventRecord(c->ev_join, c->s2);
     }
     mark(PH_VALIDATE);
-    launch_classify(d, s);
+    launch_classify(d, kc, s);
     if (c->opts.validate_batches) launch_dedupe(d, s);
     mark(PH_UPDATE);
     launch_prepare(d, del, s);
@@ -1021,13 +1045,14 @@ void enqueue_update(drsf_ctx *c, int kind, bool profile) {
 }
 
 int capture_graph(drsf_ctx *c, int kind) {
-    if (c->gexec[kind]) return DRSF_OK;
+    const int q = c->slot;
+    if (c->gexec[q][kind]) return DRSF_OK;
     HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    enqueue_update(c, kind, false);
+    enqueue_update(c, kind, false, nullptr);
     hipGraph_t g = nullptr;
     HIPCHK(c, hipStreamEndCapture(c->stream, &g));
-    c->graph[kind] = g;
-    HIPCHK(c, hipGraphInstantiate(&c->gexec[kind], g, nullptr, nullptr, 0));
+    c->graph[q][kind] = g;
+    HIPCHK(c, hipGraphInstantiate(&c->gexec[q][kind], g, nullptr, nullptr, 0));
     return DRSF_OK;
 }
 
@@ -1035,7 +1060,8 @@ int capture_graph(drsf_ctx *c, int kind) {
 // hooking rounds in short chunks, deeper search or the Euler tour, then
 // reversal, labels and cleanup.
 int continue_update(drsf_ctx *c) {
-    const Dev d = make_dev(c);
+    Dev d = make_dev(c);
+    d.gate = 0;  // runs while the update's cleanup holds any update queued behind it
     hipStream_t s = c->stream;
     unsigned long long *f = c->h_ret + c->ret_words;  // [0] status, [1] rounds done, [2] level active
     auto read_flags = [&](int levels) -> int {
@@ -1125,25 +1151,50 @@ int launch_update(drsf_ctx *c) {
     hipStream_t s = c->stream;
     // the control block is read from h_ctl by the first kernel (no copy)
     const bool prof = c->opts.profile != 0;
-    c->h_ctl->seq = ++c->seq;
+    c->h_ctl->seq = ++c->seq;  // the caller filled slot seq & 1
     // clear the completion word: pinned memory may hold any value (a freed
     // context's, or scratch), and the wait must only see this update's
     *(volatile unsigned long long *)(c->h_ret + c->ret_words + 7) = 0;
     c->kind = (c->h_ctl->has_ins ? 1 : 0) | (c->h_ctl->has_del ? 2 : 0);
     if (c->kind == 0) c->kind = 3;  // nothing but rejected or empty batches: run everything
     // the supergraph reads sizes back between its kernels, so it is not
-    // captured (the Euler-tour reversal, sort included, is a fixed sequence)
-    if (prof || c->opts.replacement_mode == 1) {
-        enqueue_update(c, c->kind, prof);
+    // captured (the Euler-tour reversal, sort included, is a fixed sequence).
+    // An update queued behind a running one is launched kernel by kernel:
+    // the device then goes from one update to the next as from one kernel
+    // to the next, where a graph launch starts some microseconds after the
+    // work before it
+    if (prof || c->opts.replacement_mode == 1 || c->npend > 0) {
+        enqueue_update(c, c->kind, prof, c->h_ctl);
     } else {
         int rc;
         if ((rc = capture_graph(c, c->kind))) return rc;
-        HIPCHK(c, hipGraphLaunch(c->gexec[c->kind], s));
+        HIPCHK(c, hipGraphLaunch(c->gexec[c->slot][c->kind], s));
     }
     HIPCHK(c, hipGetLastError());
-    c->pending = true;
+    c->pend[c->slot] = drsf_ctx::Pend{c->seq, c->kind, c->last_op, c->last_b};
+    c->npend++;
     c->have_phases = prof;
     return DRSF_OK;
+}
+
+// Queues again an update whose first launch stood still behind an
+// unfinished one (its control block is unchanged in its slot).
+int relaunch_update(drsf_ctx *c, int q) {
+    select_slot(c, q);
+    c->kind = c->pend[q].kind;
+    int rc;
+    if ((rc = capture_graph(c, c->kind))) return rc;
+    HIPCHK(c, hipGraphLaunch(c->gexec[q][c->kind], c->stream));
+    HIPCHK(c, hipGetLastError());
+    return DRSF_OK;
+}
+
+// An update may be queued behind a running one (two in flight) when it is
+// launched as a captured graph of a one-graph context reading its batch in
+// place; otherwise the queue is drained first.
+bool can_queue(const drsf_ctx *c) {
+    return c->ngraph == 1 && c->opts.inputs_on_device && !c->opts.profile && c->opts.replacement_mode == 0 &&
+           c->opts.reverse_mode == 0 && c->nsg == 0;
 }
 
 // Regions of x0 the first hooking rounds read (see Dev::x0).
@@ -1178,9 +1229,11 @@ int stage_edges(drsf_ctx *c, const int32_t *edges, int64_t b) {
 }
 
 int finish_pending(drsf_ctx *c) {
-    if (!c->pending) return DRSF_OK;
-    const int rc = drsf_wait(c, nullptr);
-    return (rc == DRSF_OK || rc == DRSF_E_BATCH) ? DRSF_OK : rc;
+    while (c->npend > 0) {
+        const int rc = drsf_wait(c, nullptr);
+        if (rc != DRSF_OK && rc != DRSF_E_BATCH) return rc;
+    }
+    return DRSF_OK;
 }
 
 }  // namespace
@@ -1268,8 +1321,8 @@ static int create_impl(int32_t G, const int32_t *n_off, int32_t n, const int64_t
         c->own_stream = true;
     }
     c->ret_words = 1 + C_TOTAL + (G + 1) / 2;
-    if ((rc = halloc(c, &c->h_ret, c->ret_words + 8))) return bail(rc);
-    c->h_gstat = reinterpret_cast<int32_t *>(c->h_ret + 1 + C_TOTAL);
+    if ((rc = halloc(c, &c->h_ret_ring, 2 * (c->ret_words + 8)))) return bail(rc);
+    select_slot(c, 0);
     if (c->opts.profile)  // phase events exist only for the profiled launch path
         for (auto &e : c->ev)
             if (hipEventCreate(&e) != hipSuccess) {
@@ -1432,8 +1485,8 @@ int drsf_set_tuning(drsf_ctx *c, int rounds_queued, int levels_queued, int sweep
 }
 
 static int check_usable(drsf_ctx *c) {
-    return c->broken ? fail(c, DRSF_E_STATE, "a failed store rebuild left the context without its graph; "
-                                              "only its forest can be read")
+    return c->broken ? fail(c, DRSF_E_STATE, "a failed store rebuild (or host continuation) left the "
+                                              "context unusable; only its forest can be read")
                      : DRSF_OK;
 }
 
@@ -1453,7 +1506,16 @@ int drsf_set_small_schedule(drsf_ctx *c, int threads, int workgroups) {
 int drsf_apply_async(drsf_ctx *c, const int32_t *edges, int64_t b, int op) {
     if (!c) return DRSF_E_ARG;
     int rc;
-    if ((rc = finish_pending(c))) return rc;
+    // queued behind at most one running update; an empty batch or one that
+    // fills the inserted-edge list (a store rebuild) drains the queue
+    const bool queue = can_queue(c) && b > 0 &&
+                       !(op == DRSF_INSERT && c->ndelta_bound + b > c->dcap);
+    if (!queue) {
+        if ((rc = finish_pending(c))) return rc;
+    } else if (c->npend >= 2) {
+        rc = drsf_wait(c, nullptr);
+        if (rc != DRSF_OK && rc != DRSF_E_BATCH) return rc;
+    }
     if ((rc = check_usable(c))) return rc;
     if (c->ngraph != 1) return fail(c, DRSF_E_STATE, "the context holds several graphs: use drsf_multi_apply");
     if (op != DRSF_INSERT && op != DRSF_DELETE) return fail(c, DRSF_E_ARG, "op must be insert or delete");
@@ -1481,6 +1543,7 @@ int drsf_apply_async(drsf_ctx *c, const int32_t *edges, int64_t b, int op) {
     if (!c->opts.inputs_on_device && (rc = stage_edges(c, edges, b))) return rc;
     c->last_b = b;
     c->last_op = op;
+    select_slot(c, (int)((c->seq + 1) & 1));
     Ctl &k = *c->h_ctl;
     memset(&k, 0, sizeof k);
     if (c->opts.inputs_on_device) k.edges = edges;
@@ -1536,6 +1599,7 @@ int drsf_multi_apply_async(drsf_ctx *c, const int32_t *edges, const int64_t *b_o
     }
     c->have_phases = false;
     c->multi_last = true;
+    select_slot(c, (int)((c->seq + 1) & 1));
     c->last_b = b;
     c->last_bg.assign((size_t)G, 0);
     c->last_opg.assign(op, op + G);
@@ -1624,8 +1688,15 @@ int drsf_multi_apply_async(drsf_ctx *c, const int32_t *edges, const int64_t *b_o
 
 int drsf_wait(drsf_ctx *c, drsf_view *out) {
     if (!c) return DRSF_E_ARG;
-    if (c->pending) {
-        c->pending = false;
+    if (c->npend > 0) {
+        // the oldest queued update, in its slot
+        const uint64_t myseq = c->seq - (uint64_t)c->npend + 1;
+        const int q = (int)(myseq & 1);
+        select_slot(c, q);
+        c->kind = c->pend[q].kind;
+        c->last_b = c->pend[q].b;
+        c->last_op = c->pend[q].op;
+        c->npend--;
         // the last kernel writes the completion word once the results in
         // h_ret are final: poll it (a stream synchronisation wakes up later),
         // asking the stream now and then so that a failed or idle stream ends
@@ -1634,7 +1705,7 @@ int drsf_wait(drsf_ctx *c, drsf_view *out) {
         bool seen = false;
         if (!c->have_phases) {
             for (uint32_t it = 1;; it++) {
-                if (*done == c->seq) {
+                if (*done == myseq) {
                     seen = true;
                     break;
                 }
@@ -1642,15 +1713,26 @@ int drsf_wait(drsf_ctx *c, drsf_view *out) {
             }
             std::atomic_thread_fence(std::memory_order_acquire);
         }
-        if (!seen || *done != c->seq) HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (!seen || *done != myseq) HIPCHK(c, hipStreamSynchronize(c->stream));
         const unsigned long long *k = c->h_ret + 1;
         int32_t st = *(int32_t *)c->h_ret;
         c->view.host_finished = 0;
         c->cont_timed = false;
         if (st == 0 && !k[C_ORIENTED]) {  // the captured rounds did not finish it
             c->view.host_finished = 1;
-            const int rc = continue_update(c);
-            if (rc) return c->last_rc = rc;
+            int rc = continue_update(c);
+            if (!rc && c->npend > 0) {
+                // the update queued behind it stood still: queue it again
+                rc = relaunch_update(c, 1 - q);
+                select_slot(c, q);
+                c->kind = c->pend[q].kind;
+            }
+            if (rc) {
+                // a held update would stay held: the context is not usable
+                c->npend = 0;
+                c->broken = true;
+                return c->last_rc = rc;
+            }
             st = *(int32_t *)c->h_ret;
         }
         if (c->have_phases &&

@@ -31,6 +31,8 @@ struct Ctl {
 struct Dev {
     int32_t n;
     int32_t validate;        // 0: batches guaranteed valid (no repeat check, no insert presence search)
+    int32_t gate;            // 1: an update's own kernels, which stand still while the hold word
+                             // is set; 0: the host's continuation of the update that set it
     const Ctl *ctl;          // device copy, written by the first kernel of an update
     Ctl *ctlw;               // the same, writable
     const Ctl *hctl;         // host copy (pinned), read by the first kernel only
@@ -147,7 +149,11 @@ struct Dev {
     int32_t *et_start, *et_finish;  // [n] Euler-tour times of each vertex
     int32_t *et_support;            // [n] support[r] = x for a path (x, r), else NONE
     // control
-    int32_t *status;         // internal errors (bounds exceeded)
+    int32_t *status;         // internal errors (bounds exceeded); status[1], the other half of
+                             // its 8-byte word, is the hold word: set by the cleanup of an
+                             // update left unfinished for the host, cleared by the cleanup of
+                             // its continuation, so that an update queued behind it on the
+                             // stream does nothing in between (the host queues it again)
     unsigned long long *cnt; // [C_TOTAL]
 };
 
@@ -252,7 +258,9 @@ int64_t insert_regions(int64_t b);
 
 // launchers of the update path (drsf_kernels.hip); grids are sized from the
 // context's maxima so that a captured sequence fits every batch
-void launch_classify(const Dev &d, hipStream_t s);
+// kc: the control block passed with the launch (a kernel-by-kernel launch),
+// or null: read from pinned host memory (a captured one)
+void launch_classify(const Dev &d, const Ctl *kc, hipStream_t s);
 void launch_dedupe(const Dev &d, hipStream_t s);  // repeated pairs inside the batch
 void launch_prepare(const Dev &d, bool del, hipStream_t s);  // with rep <- parent when del
 void launch_register(const Dev &d, hipStream_t s);

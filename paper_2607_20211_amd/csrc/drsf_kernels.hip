@@ -241,6 +241,17 @@ __device__ bool last_block_arrives(unsigned long long *arrive) {
     return s_last;
 }
 
+// The update has failed, or it is queued behind one that the host has yet
+// to finish: status and hold word in one load.
+__device__ __forceinline__ uint64_t status_word(const Dev &d) {
+    return *reinterpret_cast<const uint64_t *>(d.status);
+}
+__device__ __forceinline__ bool held(const Dev &d) { return d.gate && (status_word(d) >> 32) != 0; }
+__device__ __forceinline__ bool stopped(const Dev &d) {
+    const uint64_t w = status_word(d);
+    return (uint32_t)w != 0 || (d.gate && (w >> 32) != 0);
+}
+
 __device__ __forceinline__ int edge_op(const Dev &d, int64_t i) {
     return d.ctl->op == 2 ? (int)d.bop[i] : d.ctl->op;
 }
@@ -266,16 +277,29 @@ __device__ __forceinline__ int64_t list_block(const int32_t *list, int64_t cnt, 
 // the child endpoint of a tree edge (parent[u] == v or parent[v] == u;
 // Algorithm 1, the cut step).  Errors mark the edge's graph as rejected;
 // nothing but batch scratch is written.
-__global__ __launch_bounds__(BLOCK) void k_classify(Dev d) {
-    // the update's control block comes from pinned host memory; the first
+__global__ __launch_bounds__(BLOCK) void k_classify(Dev d, Ctl kc, int from_arg) {
+    if (held(d)) return;  // the device copy of the control block still serves the held update
+    // the update's control block comes from pinned host memory (a captured
+    // launch) or with the launch (a kernel-by-kernel one); the first
     // workgroup publishes it for the later kernels, which read the device copy
-    const Ctl *hc = d.hctl;
-    if (blockIdx.x == 0 && threadIdx.x < sizeof(Ctl) / 8)
-        reinterpret_cast<uint64_t *>(d.ctlw)[threadIdx.x] =
-            reinterpret_cast<const uint64_t *>(hc)[threadIdx.x];
-    const int64_t b = hc->b;
-    const int opm = hc->op;
-    const int32_t *be = hc->edges ? hc->edges : d.bedges;  // caller's device batch, or the staged one
+    int64_t b;
+    int opm;
+    const int32_t *edges;
+    if (from_arg) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *d.ctlw = kc;
+        b = kc.b;
+        opm = kc.op;
+        edges = kc.edges;
+    } else {
+        const Ctl *hc = d.hctl;
+        if (blockIdx.x == 0 && threadIdx.x < sizeof(Ctl) / 8)
+            reinterpret_cast<uint64_t *>(d.ctlw)[threadIdx.x] =
+                reinterpret_cast<const uint64_t *>(hc)[threadIdx.x];
+        b = hc->b;
+        opm = hc->op;
+        edges = hc->edges;
+    }
+    const int32_t *be = edges ? edges : d.bedges;  // caller's device batch, or the staged one
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < b; i += stride) {
         d.bslot[i] = NONE;
@@ -347,6 +371,7 @@ __global__ __launch_bounds__(BLOCK) void k_classify(Dev d) {
 // claim their key in a table with compare-and-swap, where repeats among them
 // meet.  Only the colliding edges (about 1 in 16) pay for an atomic.
 __global__ __launch_bounds__(BLOCK) void k_dedupe(Dev d) {
+    if (held(d)) return;
     const int64_t b = d.ctl->b;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < b; i += stride) {
@@ -404,7 +429,7 @@ __device__ void rep_init(const Dev &d, int64_t bid, int64_t nblk) {
 }
 
 __global__ __launch_bounds__(BLOCK) void k_prepare(Dev d, int gb) {
-    if (*d.status) return;
+    if (stopped(d)) return;
     if ((int)blockIdx.x >= gb) {
         if (d.ctl->has_del) rep_init(d, (int64_t)blockIdx.x - gb, (int64_t)gridDim.x - gb);
         return;
@@ -454,7 +479,7 @@ __global__ __launch_bounds__(BLOCK) void k_prepare(Dev d, int gb) {
 
 // Dense ids for the nominated pieces: the owning batch entry registers.
 __global__ __launch_bounds__(BLOCK) void k_register(Dev d) {
-    if (*d.status) return;
+    if (stopped(d)) return;
     const int64_t b = d.ctl->b;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < b; base += stride) {
@@ -517,7 +542,7 @@ __device__ bool insert_emit_block(const Dev &d, int64_t t, Cross *e, int *total)
 // The insert emit on its own (the supergraph reads the regions before the
 // first round); in the default mode the first hooking round does it.
 __global__ __launch_bounds__(BLOCK) void k_insert_emit(Dev d) {
-    if (*d.status || !d.ctl->has_ins) return;
+    if (stopped(d) || !d.ctl->has_ins) return;
     const int64_t t = blockIdx.x;
     if (t * BLOCK >= d.ctl->b) return;
     Cross e;
@@ -551,7 +576,7 @@ __global__ __launch_bounds__(BLOCK) void k_insert_emit(Dev d) {
 constexpr int REP_CH = DRSF_REP_CH;
 constexpr int PUBLISH_AFTER = 4;  // steps before a chase publishes its progress (short chains never do)
 __global__ __launch_bounds__(BLOCK) void k_rep_chase(Dev d) {
-    if (*d.status || !d.ctl->has_del) return;
+    if (stopped(d) || !d.ctl->has_del) return;
     const int64_t nb = (d.n + BLOCK - 1) / BLOCK;
     const int64_t nvl_list = d.ctl->nvl;  // read once: stores below may alias it
     for (int64_t j0 = (int64_t)blockIdx.x * REP_CH;; j0 += (int64_t)gridDim.x * REP_CH) {
@@ -676,7 +701,7 @@ __global__ __launch_bounds__(BLOCK) void k_rep_chase(Dev d) {
 // rep for the flagged edges.  Cross edges go to the
 // tile's own region of x0.
 __global__ __launch_bounds__(BLOCK) void k_sweep_base(Dev d) {
-    if (*d.status || !d.ctl->has_del || d.cnt[C_OMODE]) return;
+    if (stopped(d) || !d.ctl->has_del || d.cnt[C_OMODE]) return;
     typedef int v4i __attribute__((ext_vector_type(4)));
     typedef short v4s __attribute__((ext_vector_type(4)));
     __shared__ v4i s_rowv[TILE / 8];      // int16 local row index per edge
@@ -827,7 +852,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_base(Dev d) {
 // entries [t * TILE, (t + 1) * TILE) and writes region ntiles + t.  Lane
 // layout and gathers as in k_sweep_base.
 __global__ __launch_bounds__(BLOCK) void k_sweep_delta(Dev d) {
-    if (*d.status || !d.ctl->has_del) return;
+    if (stopped(d) || !d.ctl->has_del) return;
     const int64_t nd = (int64_t)d.cnt[C_NDELTA];
     const int64_t t = blockIdx.x;
     if (t * TILE >= nd) return;
@@ -898,7 +923,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_delta(Dev d) {
 // blocks are taken in two levels: within groups of BLOCK blocks here, then
 // over the groups in k_orph_total.
 __global__ __launch_bounds__(BLOCK) void k_orph_plan(Dev d) {
-    if (*d.status || !d.ctl->has_del) return;
+    if (stopped(d) || !d.ctl->has_del) return;
     const int64_t b = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     const unsigned long long x =
         b < d.nvb ? opack((unsigned long long)d.bvol[b], (unsigned long long)d.bcnt[b]) : 0;
@@ -913,7 +938,7 @@ __global__ __launch_bounds__(BLOCK) void k_orph_plan(Dev d) {
 
 // Prefix over the groups, the totals and the choice of scan.
 __global__ __launch_bounds__(BLOCK) void k_orph_total(Dev d) {
-    if (*d.status || !d.ctl->has_del) return;
+    if (stopped(d) || !d.ctl->has_del) return;
     const int64_t ng = (d.nvb + BLOCK - 1) / BLOCK;
     const int64_t per = (ng + BLOCK - 1) / BLOCK;
     const int64_t g0 = (int64_t)threadIdx.x * per;
@@ -945,7 +970,7 @@ __global__ __launch_bounds__(BLOCK) void k_orph_total(Dev d) {
 // each range of OR_W slots the list index of the orphan holding its first
 // slot.
 __global__ __launch_bounds__(BLOCK) void k_orph_fill(Dev d) {
-    if (*d.status || !d.ctl->has_del || !d.cnt[C_OMODE]) return;
+    if (stopped(d) || !d.ctl->has_del || !d.cnt[C_OMODE]) return;
     // FILL_LANES lanes per vertex block (blocks hold few orphans), so one
     // wave covers WAVE / FILL_LANES blocks with all its loads in flight
     constexpr int FILL_LANES = 8;
@@ -993,7 +1018,7 @@ __global__ __launch_bounds__(BLOCK) void k_orph_fill(Dev d) {
 // two orphan pieces are seen from both ends and counted once (from the
 // smaller end).
 __global__ __launch_bounds__(BLOCK) void k_orph_scan(Dev d) {
-    if (*d.status || !d.ctl->has_del || !d.cnt[C_OMODE]) return;
+    if (stopped(d) || !d.ctl->has_del || !d.cnt[C_OMODE]) return;
     const int64_t V = (int64_t)d.cnt[C_OVOL];
     const int64_t no = (int64_t)d.cnt[C_NORPH];
     const int64_t per = or_region_slots(V, d.eb) / OR_W;  // ranges per region
@@ -1256,7 +1281,7 @@ __device__ __forceinline__ void select_edge(const Dev &d, bool live, const Cross
 // selects on the edges it found, and adds its count to the statistic.
 // Workgroup 0 sums the other region lengths (the cross edges found).
 __global__ __launch_bounds__(BLOCK) void k_bor_round0(Dev d, int emit) {
-    if (*d.status) return;
+    if (stopped(d)) return;
     // regions below ntiles hold the orphan scan's output when it ran: those
     // edges took part in this round's selection already
     const bool om = d.cnt[C_OMODE] != 0;
@@ -1302,7 +1327,7 @@ __global__ __launch_bounds__(BLOCK) void k_bor_round0(Dev d, int emit) {
 // compact the survivors into a dense list.  Round 1 reads the regions of x0;
 // later rounds alternate dense lists (out: x1 on odd rounds, x0 on even).
 __global__ __launch_bounds__(BLOCK) void k_bor_select(Dev d, int r) {
-    if (*d.status || d.cnt[C_DONE_BOR]) return;
+    if (stopped(d) || d.cnt[C_DONE_BOR]) return;
     Cross *out = (r & 1) ? d.x1 : d.x0;
     unsigned long long *cout = &d.cnt[(r & 1) ? C_NX1 : C_NX0];
     const int64_t np = (int64_t)d.cnt[C_NP];
@@ -1362,7 +1387,7 @@ __global__ __launch_bounds__(BLOCK) void k_bor_select(Dev d, int r) {
 // the rounds when its select found no live edge.  Also clears the other
 // buffer of best[] for the next round's selection.
 __global__ __launch_bounds__(BLOCK) void k_bor_hook(Dev d, int r) {
-    if (*d.status || d.cnt[C_DONE_BOR]) return;
+    if (stopped(d) || d.cnt[C_DONE_BOR]) return;
     if (r >= 1) {
         const int64_t nout = (int64_t)d.cnt[(r & 1) ? C_NX1 : C_NX0];
         if (nout == 0) {
@@ -1418,7 +1443,7 @@ __global__ __launch_bounds__(BLOCK) void k_bor_hook(Dev d, int r) {
 // then go on).  Within one workgroup a barrier makes earlier global writes
 // and atomics visible to every thread of it.
 __global__ __launch_bounds__(TAIL_THREADS) void k_bor_tail(Dev d, int r0) {
-    if (*d.status || d.cnt[C_DONE_BOR]) return;
+    if (stopped(d) || d.cnt[C_DONE_BOR]) return;
     int64_t cin = (int64_t)d.cnt[(r0 & 1) ? C_NX0 : C_NX1];
     if (cin > TAIL_MAX) return;
     __shared__ int s_nout;
@@ -1508,7 +1533,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_bor_tail(Dev d, int r0) {
 // kept the old root when present, since that root is the component's
 // minimum).  Runs only once the hooking rounds have finished.
 __global__ __launch_bounds__(BLOCK) void k_sf_root(Dev d) {
-    if (*d.status || !d.cnt[C_DONE_BOR]) return;
+    if (stopped(d) || !d.cnt[C_DONE_BOR]) return;
     const int64_t np = (int64_t)d.cnt[C_NP];
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < np; base += stride) {
@@ -1532,7 +1557,7 @@ __device__ __forceinline__ bool is_super_root(const Dev &d, int32_t p) {
 // piece's level and parent arc have a single writer.  A level that reaches no
 // new piece ends the search.
 __global__ __launch_bounds__(BLOCK) void k_sf_bfs(Dev d, int L) {
-    if (*d.status || !d.cnt[C_DONE_BOR]) return;
+    if (stopped(d) || !d.cnt[C_DONE_BOR]) return;
     if (L > 0 && d.cnt[C_BFS_ROUND + L - 1] == 0) return;
     const int64_t na = 2 * (int64_t)d.cnt[C_NER];
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
@@ -1567,7 +1592,7 @@ __global__ __launch_bounds__(BLOCK) void k_sf_bfs(Dev d, int L) {
 // R and new parents).  A super-root piece whose root is not the component's
 // smallest vertex m is re-rooted at m; m is the component's new label.
 __global__ __launch_bounds__(BLOCK) void k_orient_bfs(Dev d, int levels) {
-    if (*d.status || !d.cnt[C_DONE_BOR] || d.cnt[C_BFS_ROUND + levels - 1] != 0) return;
+    if (stopped(d) || !d.cnt[C_DONE_BOR] || d.cnt[C_BFS_ROUND + levels - 1] != 0) return;
     const int64_t np = (int64_t)d.cnt[C_NP];
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     if (blockIdx.x == 0 && threadIdx.x == 0) d.cnt[C_ORIENTED] = 1;
@@ -1607,7 +1632,7 @@ __global__ __launch_bounds__(BLOCK) void k_orient_bfs(Dev d, int levels) {
 // Fallback for deep super-trees: Euler tour of the super-forest and list
 // ranking (Alg. 2, Eulerian tour step).  Arc lists per piece:
 __global__ __launch_bounds__(BLOCK) void k_sf_arcs(Dev d) {
-    if (*d.status) return;
+    if (stopped(d)) return;
     const int64_t ner = (int64_t)d.cnt[C_NER];
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < ner; base += stride) {
@@ -1623,7 +1648,7 @@ __global__ __launch_bounds__(BLOCK) void k_sf_arcs(Dev d) {
 // Euler tour successor: after arc P->Q comes the arc following Q->P in Q's
 // cyclic arc list.  The tour of each component is cut open at its super-root.
 __global__ __launch_bounds__(BLOCK) void k_sf_succ(Dev d) {
-    if (*d.status) return;
+    if (stopped(d)) return;
     const int64_t na = 2 * (int64_t)d.cnt[C_NER];
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t a = (int64_t)blockIdx.x * BLOCK + threadIdx.x; a < na; a += stride) {
@@ -1642,7 +1667,7 @@ __global__ __launch_bounds__(BLOCK) void k_sf_succ(Dev d) {
 // List ranking by pointer jumping (Wyllie): rank = arcs left until the end
 // of the tour.  Double-buffered; round r reads buffer r&1.
 __global__ __launch_bounds__(BLOCK) void k_lr_round(Dev d, int r) {
-    if (*d.status || d.cnt[C_DONE_LR]) return;
+    if (stopped(d) || d.cnt[C_DONE_LR]) return;
     if (r > 0 && d.cnt[C_LR_ROUND + r - 1] == 0) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             d.cnt[C_LR_FINAL] = (unsigned long long)(r & 1);
@@ -1676,7 +1701,7 @@ __global__ __launch_bounds__(BLOCK) void k_lr_round(Dev d, int r) {
 // met first (larger rank) points from parent piece to child piece; the rest
 // as in k_orient_bfs.
 __global__ __launch_bounds__(BLOCK) void k_orient_lr(Dev d, int lr_rounds) {
-    if (*d.status) return;
+    if (stopped(d)) return;
     const int64_t ner = (int64_t)d.cnt[C_NER];
     const int64_t np = (int64_t)d.cnt[C_NP];
     int fin;
@@ -1749,7 +1774,7 @@ __device__ void reverse_paths(const Dev &d, int64_t bid, int64_t nblk) {
     }
 }
 __global__ __launch_bounds__(BLOCK) void k_reverse_all(Dev d) {
-    if (*d.status) return;
+    if (stopped(d)) return;
     reverse_paths(d, blockIdx.x, gridDim.x);
 }
 
@@ -1850,7 +1875,7 @@ __device__ void label_insert(const Dev &d, int64_t bid, int64_t nblk) {
 // rep and the orphan scratch), so one launch does both: workgroups below
 // grev reverse paths, the rest relabel (lab: 1 inserts, 2 deletes).
 __global__ __launch_bounds__(BLOCK) void k_finish(Dev d, int lab, int grev) {
-    if (*d.status || !d.cnt[C_ORIENTED]) return;
+    if (stopped(d) || !d.cnt[C_ORIENTED]) return;
     if ((int)blockIdx.x < grev) {
         reverse_paths(d, blockIdx.x, grev);
     } else {
@@ -1862,7 +1887,7 @@ __global__ __launch_bounds__(BLOCK) void k_finish(Dev d, int lab, int grev) {
 
 // The insert labels of a mixed batch, after the delete labels.
 __global__ __launch_bounds__(BLOCK) void k_label_insert(Dev d) {
-    if (*d.status || !d.cnt[C_ORIENTED] || !d.ctl->has_ins) return;
+    if (stopped(d) || !d.cnt[C_ORIENTED] || !d.ctl->has_ins) return;
     label_insert(d, blockIdx.x, gridDim.x);
 }
 
@@ -1882,7 +1907,7 @@ __device__ __forceinline__ int64_t sg_region(int64_t i, int64_t nr_om, int64_t r
 // cross edges per region, and the cross-edge count statistic (as round 0)
 __global__ __launch_bounds__(BLOCK) void k_sg_count(Dev d, int64_t nr_om, int64_t rlo2, int64_t nreg,
                                                     uint32_t *rcount) {
-    if (*d.status) return;
+    if (stopped(d)) return;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     unsigned long long st = 0;
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < nreg; i += stride) {
@@ -1898,7 +1923,7 @@ __global__ __launch_bounds__(BLOCK) void k_sg_count(Dev d, int64_t nr_om, int64_
 // densely (one workgroup per region)
 __global__ __launch_bounds__(BLOCK) void k_sg_gather(Dev d, int64_t nr_om, int64_t rlo2, int64_t nreg,
                                                      const uint32_t *rpos, uint64_t *keys, uint64_t *vals) {
-    if (*d.status) return;
+    if (stopped(d)) return;
     for (int64_t i = blockIdx.x; i < nreg; i += gridDim.x) {
         const int64_t t = sg_region(i, nr_om, rlo2);
         const int64_t c = (int64_t)d.rcnt[t], base = rpos[i];
@@ -1933,7 +1958,7 @@ __global__ __launch_bounds__(BLOCK) void k_sg_min(int64_t total, const uint32_t 
 __global__ __launch_bounds__(BLOCK) void k_sg_emit(Dev d, int64_t total, const uint64_t *skeys,
                                                    const uint32_t *flag, const uint32_t *segid,
                                                    const uint64_t *smin, const unsigned long long *nseg) {
-    if (*d.status) return;
+    if (stopped(d)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         d.cnt[C_NX0] = *nseg;
         d.cnt[C_NX1] = 0;
@@ -1963,7 +1988,7 @@ __global__ __launch_bounds__(BLOCK) void k_sg_emit(Dev d, int64_t total, const u
 
 // keys for the child lists, and the F-hat parents
 __global__ __launch_bounds__(BLOCK) void k_et_keys(Dev d) {
-    if (*d.status || !d.cnt[C_ORIENTED]) return;
+    if (stopped(d) || !d.cnt[C_ORIENTED]) return;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < d.n; v += stride) {
         const int32_t p = d.parent[v];
@@ -1976,7 +2001,7 @@ __global__ __launch_bounds__(BLOCK) void k_et_keys(Dev d) {
 
 // first child and next sibling from the sorted keys
 __global__ __launch_bounds__(BLOCK) void k_et_links(Dev d) {
-    if (*d.status || !d.cnt[C_ORIENTED]) return;
+    if (stopped(d) || !d.cnt[C_ORIENTED]) return;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j < d.n; j += stride) {
         const uint64_t k = d.et_sorted[j];
@@ -1991,7 +2016,7 @@ __global__ __launch_bounds__(BLOCK) void k_et_links(Dev d) {
 
 // successor of every arc, and the ranking's start (1 arc after, or 0 at the end)
 __global__ __launch_bounds__(BLOCK) void k_et_succ(Dev d) {
-    if (*d.status || !d.cnt[C_ORIENTED]) return;
+    if (stopped(d) || !d.cnt[C_ORIENTED]) return;
     const int64_t na = 2 * (int64_t)d.n;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t a = (int64_t)blockIdx.x * BLOCK + threadIdx.x; a < na; a += stride) {
@@ -2015,7 +2040,7 @@ __global__ __launch_bounds__(BLOCK) void k_et_succ(Dev d) {
 // jumps past it
 __global__ __launch_bounds__(BLOCK) void k_et_round(Dev d, const int32_t *nin, const int32_t *din,
                                                     int32_t *nout, int32_t *dout) {
-    if (*d.status || !d.cnt[C_ORIENTED]) return;
+    if (stopped(d) || !d.cnt[C_ORIENTED]) return;
     const int64_t na = 2 * (int64_t)d.n;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t a = (int64_t)blockIdx.x * BLOCK + threadIdx.x; a < na; a += stride) {
@@ -2034,7 +2059,7 @@ __global__ __launch_bounds__(BLOCK) void k_et_round(Dev d, const int32_t *nin, c
 // a root the rank of its first arc and its tour's length; any other vertex
 // the rank of the down arc to its first child and of its own up arc
 __global__ __launch_bounds__(BLOCK) void k_et_times(Dev d, const int32_t *dst) {
-    if (*d.status || !d.cnt[C_ORIENTED]) return;
+    if (stopped(d) || !d.cnt[C_ORIENTED]) return;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < d.n; v += stride) {
         const int32_t r = d.rep[v];  // root of v's tree of F-hat
@@ -2058,7 +2083,7 @@ __global__ __launch_bounds__(BLOCK) void k_et_times(Dev d, const int32_t *dst) {
 
 // support[r] = x for each path (x, r) of R (at most one path per tree of F-hat)
 __global__ __launch_bounds__(BLOCK) void k_et_support(Dev d) {
-    if (*d.status || !d.cnt[C_ORIENTED]) return;
+    if (stopped(d) || !d.cnt[C_ORIENTED]) return;
     const int64_t nr = (int64_t)d.cnt[C_NR];
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < nr; i += stride) {
@@ -2072,7 +2097,7 @@ __global__ __launch_bounds__(BLOCK) void k_et_support(Dev d) {
 // parent[old parent of u] = u.  Then each path's start hangs below its new
 // parent (its own parent edge is not on any path, so no write collides).
 __global__ __launch_bounds__(BLOCK) void k_et_reverse(Dev d) {
-    if (*d.status || !d.cnt[C_ORIENTED]) return;
+    if (stopped(d) || !d.cnt[C_ORIENTED]) return;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t u = (int64_t)blockIdx.x * BLOCK + threadIdx.x; u < d.n; u += stride) {
         const int32_t pu = d.et_opar[u];
@@ -2099,6 +2124,7 @@ __global__ __launch_bounds__(BLOCK) void k_et_reverse(Dev d) {
 // unfinished and the host continues it) and resets them once the update has
 // finished.
 __global__ __launch_bounds__(BLOCK) void k_cleanup(Dev d) {
+    if (held(d)) return;  // queued behind an unfinished update: no handoff, no reset
     const bool fin = d.cnt[C_ORIENTED] || *d.status;  // else unfinished: the host continues
     if (fin) {
         const int64_t np = (int64_t)d.cnt[C_NP];
@@ -2120,6 +2146,11 @@ __global__ __launch_bounds__(BLOCK) void k_cleanup(Dev d) {
     for (int64_t t = threadIdx.x; t < d.ret_words; t += BLOCK) d.hret[t] = d.ctlmem[t];
     __threadfence_system();
     __syncthreads();  // every thread has copied before the completion word and any reset
+    if (!fin) {
+        // later updates on the stream wait for the host's continuation
+        if (threadIdx.x == 0) d.status[1] = 1;
+        __syncthreads();
+    }
     if (threadIdx.x == 0)
         __hip_atomic_store(d.hdone, (unsigned long long)d.ctl->seq, __ATOMIC_RELEASE,
                            __HIP_MEMORY_SCOPE_SYSTEM);
@@ -2127,7 +2158,10 @@ __global__ __launch_bounds__(BLOCK) void k_cleanup(Dev d) {
     const int t = threadIdx.x;
     if (t < C_TOTAL && t != C_NDELTA) d.cnt[t] = 0;
     for (int64_t g = threadIdx.x; g < d.ctl->ngraph; g += BLOCK) d.gstat[g] = 0;
-    if (t == 0) *d.status = 0;
+    if (t == 0) {
+        d.status[0] = 0;
+        d.status[1] = 0;  // the hold word
+    }
 }
 
 // ------------------------------------------------------------ launchers
@@ -2135,8 +2169,10 @@ __global__ __launch_bounds__(BLOCK) void k_cleanup(Dev d) {
 int64_t delta_tiles(int64_t count) { return (count + TILE - 1) / TILE; }
 int64_t insert_regions(int64_t b) { return (b + BLOCK - 1) / BLOCK; }
 
-void launch_classify(const Dev &d, hipStream_t s) {
-    hipLaunchKernelGGL(k_classify, dim3(grid_for(d.max_b, BLOCK)), dim3(BLOCK), 0, s, d);
+void launch_classify(const Dev &d, const Ctl *kc, hipStream_t s) {
+    const Ctl none{};
+    hipLaunchKernelGGL(k_classify, dim3(grid_for(d.max_b, BLOCK)), dim3(BLOCK), 0, s, d, kc ? *kc : none,
+                       kc ? 1 : 0);
 }
 void launch_dedupe(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_dedupe, dim3(grid_for(d.max_b, BLOCK)), dim3(BLOCK), 0, s, d);

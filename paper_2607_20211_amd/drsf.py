@@ -520,15 +520,23 @@ class Forest:
         return self._stats(v)
 
     def apply_async(self, edges, op: int) -> None:
+        """Queues an update (up to two run back to back on a device-input
+        context; see drsf_apply_async); the batch is kept alive until its
+        wait."""
         edges, b = _batch(edges, self.on_device)
-        self._pending_edges = edges
+        if not hasattr(self, "_pending_edges"):
+            self._pending_edges = []
         drsf_apply_async(self.ctx, edges, b, op)
+        self._pending_edges.append(edges)
+        del self._pending_edges[:-2]  # the library keeps at most two queued
 
     def wait(self) -> dict:
+        """Waits for the oldest queued update and returns its statistics."""
         try:
             return self._stats(drsf_wait(self.ctx))
         finally:
-            self._pending_edges = None
+            if getattr(self, "_pending_edges", None):
+                self._pending_edges.pop(0)
 
     @staticmethod
     def _stats(v: drsf_view) -> dict:
@@ -641,12 +649,12 @@ class MultiForest(Forest):
 
     def apply_multi_async(self, edges, b_off, op) -> None:
         edges, b_off, op = self._multi_args(edges, b_off, op)
-        self._pending_edges = edges
+        self._pending_multi = edges
         drsf_multi_apply_async(self.ctx, edges, b_off, op)
 
     def wait_multi(self) -> np.ndarray:
         st = drsf_multi_wait(self.ctx, self.G)
-        self._pending_edges = None
+        self._pending_multi = None
         return st
 
     def num_edges(self) -> np.ndarray:
