@@ -159,6 +159,15 @@ typedef struct {
                                 invalid batch then leaves the context in an
                                 unspecified but safe state.  The small-graph
                                 engine checks its batches either way. */
+    int launch_mode;         /* 0 (default): an update's kernels are launched
+                                one by one, its control block passed with the
+                                first; 1: the update replays a HIP graph
+                                captured once per update kind (less host time
+                                per update, a few microseconds more on the
+                                device between updates).  An update queued
+                                behind a running one, a profiled one and one
+                                on the supergraph are always launched kernel
+                                by kernel.  Results are identical. */
 } drsf_opts;
 
 /* Fills *opts with the defaults described above. */

@@ -1163,7 +1163,7 @@ int launch_update(drsf_ctx *c) {
     // the device then goes from one update to the next as from one kernel
     // to the next, where a graph launch starts some microseconds after the
     // work before it
-    if (prof || c->opts.replacement_mode == 1 || c->npend > 0) {
+    if (prof || c->opts.replacement_mode == 1 || c->npend > 0 || c->opts.launch_mode == 0) {
         enqueue_update(c, c->kind, prof, c->h_ctl);
     } else {
         int rc;
@@ -1182,9 +1182,13 @@ int launch_update(drsf_ctx *c) {
 int relaunch_update(drsf_ctx *c, int q) {
     select_slot(c, q);
     c->kind = c->pend[q].kind;
-    int rc;
-    if ((rc = capture_graph(c, c->kind))) return rc;
-    HIPCHK(c, hipGraphLaunch(c->gexec[q][c->kind], c->stream));
+    if (c->opts.launch_mode == 0) {
+        enqueue_update(c, c->kind, false, c->h_ctl);
+    } else {
+        int rc;
+        if ((rc = capture_graph(c, c->kind))) return rc;
+        HIPCHK(c, hipGraphLaunch(c->gexec[q][c->kind], c->stream));
+    }
     HIPCHK(c, hipGetLastError());
     return DRSF_OK;
 }
@@ -1247,6 +1251,7 @@ void drsf_default_opts(drsf_opts *o) {
     memset(o, 0, sizeof *o);
     o->validate_forest = 1;
     o->validate_batches = 1;
+    o->launch_mode = 0;
     o->max_batch = 1 << 20;
 }
 
@@ -1287,6 +1292,10 @@ static int create_impl(int32_t G, const int32_t *n_off, int32_t n, const int64_t
     }
     if (c->opts.replacement_mode < 0 || c->opts.replacement_mode > 1) {
         fail(c, DRSF_E_ARG, "replacement_mode must be 0 or 1");
+        return bail(DRSF_E_ARG);
+    }
+    if (c->opts.launch_mode < 0 || c->opts.launch_mode > 1) {
+        fail(c, DRSF_E_ARG, "launch_mode must be 0 or 1");
         return bail(DRSF_E_ARG);
     }
     if (c->opts.dev_alloc && !c->opts.dev_free) {

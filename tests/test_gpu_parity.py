@@ -646,7 +646,7 @@ def test_deep_super_tree_uses_euler_tour_fallback():
 
 def test_long_hooking_and_deep_search_continue_on_host():
     """An edgeless graph receiving a large random batch: the hooking rounds
-    run past the few queued in the captured update sequence and the
+    run past the few queued in the update's kernel sequence and the
     super-trees are deep, so the host finishes the update with further
     rounds and the Euler tour.  Then a delete of half tree, half non-tree
     edges on the result."""
@@ -675,7 +675,7 @@ def test_queued_rounds_grow_after_a_continuation():
     """A context left to choose its own round and level counts: an update
     that the host had to finish (more hooking rounds, deeper search than
     queued) makes later updates queue what it needed.  The same batch
-    applied again from the same state then finishes in the captured
+    applied again from the same state then finishes in the queued
     sequence; both results bit-exact, and a context with counts set by the
     caller keeps them."""
     drsf = _lib()
@@ -692,7 +692,7 @@ def test_queued_rounds_grow_after_a_continuation():
     st2 = pair.gpu.apply(ins, drsf.DRSF_INSERT)
     assert np.array_equal(pair.gpu.parent(), first[0]) and np.array_equal(pair.gpu.label(), first[1])
     assert (st1["host_finished"] & 1) != 0, st1  # the premise: the host ran more rounds
-    assert (st2["host_finished"] & 1) == 0, (st1, st2)  # now queued in the captured sequence
+    assert (st2["host_finished"] & 1) == 0, (st1, st2)  # now queued in the update's sequence
     drsf.drsf_snapshot_free(snap)
     pair.gpu.close()
     # counts set by the caller stay as set
@@ -783,8 +783,8 @@ def test_profile_mode_direct_launches():
 @pytest.mark.parametrize("tuning", [(1, 1, 0), (2, 2, 1), (6, 6, 0)])
 def test_launch_schedule_does_not_change_results(tuning):
     """Few or many queued hooking rounds / search levels, either delete scan:
-    the same bit-exact results (only the split of work between the captured
-    graph and host-driven launches changes)."""
+    the same bit-exact results (only the split of work between the queued
+    kernel sequence and host-driven launches changes)."""
     drsf = _lib()
     _case(f"tuning {tuning}")
     n = 50000
@@ -837,7 +837,7 @@ def test_hooking_tail_finishes_rounds_in_the_graph():
     """A chain of k + 1 two-vertex pieces joined by k inserted edges whose
     keys follow the ruler sequence (edge j weighs the trailing zeros of
     j + 1): hooking needs about log2 k rounds.  With two full-grid rounds
-    queued, the rest run in the one-workgroup tail inside the captured
+    queued, the rest run in the one-workgroup tail inside the queued
     sequence (host_finished bit 0 clear); the super-tree is a path, far
     deeper than the queued search levels, so the host finishes the search
     (bit 1).  Bit-exact against the oracle."""

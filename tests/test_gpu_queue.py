@@ -48,8 +48,9 @@ def _plan(g, nbatch, mb, rng):
     return out
 
 
+@pytest.mark.parametrize("launch_mode", [0, 1])
 @pytest.mark.parametrize("host_finished", [False, True])
-def test_queued_updates_match_the_oracle(host_finished):
+def test_queued_updates_match_the_oracle(host_finished, launch_mode):
     import torch
     drsf = _lib()
     dev = torch.device("cuda:0")
@@ -57,12 +58,14 @@ def test_queued_updates_match_the_oracle(host_finished):
     g = gen.make_graph("rmat13", 1 << 13, gen.rmat(13, 8, 0.57, 0.19, 0.19, 4242))
     mb = 1500
     plan = _plan(g, 24, mb, rng)
-    _case(f"queued updates: R-MAT 13, {len(plan)} batches up to {mb}, host-finished {host_finished}")
+    _case(f"queued updates: R-MAT 13, {len(plan)} batches up to {mb}, host-finished {host_finished}, "
+          f"launch mode {launch_mode}")
     stream = torch.cuda.Stream(dev)
     with torch.cuda.stream(stream):
         t = [torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (g.row_ptr, g.col, g.parent)]
         dbat = [torch.from_numpy(np.ascontiguousarray(b, np.int32)).to(dev) for b, *_ in plan]
-    f = drsf.Forest(g.n, *t, inputs_on_device=True, stream=stream.cuda_stream, max_batch=mb)
+    f = drsf.Forest(g.n, *t, inputs_on_device=True, stream=stream.cuda_stream, max_batch=mb,
+                    launch_mode=launch_mode)
     if host_finished:
         f.set_tuning(1, 1, 0)  # one queued round and level: the host finishes most updates
     op_of = {oracle.INSERT: drsf.DRSF_INSERT, oracle.DELETE: drsf.DRSF_DELETE}

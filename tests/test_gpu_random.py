@@ -53,6 +53,8 @@ def test_random_cases(block):
         if rng.random() < 0.3:
             kw["delta_capacity"] = int(rng.integers(mb, 3 * mb + 1))  # a batch always fits
         device = bool(rng.random() < 0.3)
+        # captured graphs now and then (its own draw: the cases stay as they were)
+        kw["launch_mode"] = int(np.random.default_rng(70000 + c).random() < 0.3)
         _case(f"random {c}: {kind} n={g.n} m={g.m} {kw} device={device}")
         pair = Pair(g, device=device, **kw)
         if rng.random() < 0.5:
