@@ -159,12 +159,14 @@ typedef struct {
                                 invalid batch then leaves the context in an
                                 unspecified but safe state.  The small-graph
                                 engine checks its batches either way. */
-    int launch_mode;         /* 0 (default): an update's kernels are launched
+    int launch_mode;         /* 1: an update replays a HIP graph captured
+                                once per update kind (less host time per
+                                update, a few microseconds more on the device
+                                between updates); 2: its kernels are launched
                                 one by one, its control block passed with the
-                                first; 1: the update replays a HIP graph
-                                captured once per update kind (less host time
-                                per update, a few microseconds more on the
-                                device between updates).  An update queued
+                                first; 0 (default): 2 for a one-graph context,
+                                1 for several graphs (whose updates launch
+                                more, shorter kernels).  An update queued
                                 behind a running one, a profiled one and one
                                 on the supergraph are always launched kernel
                                 by kernel.  Results are identical. */
@@ -226,7 +228,8 @@ int drsf_create(int32_t n, const int64_t *row_ptr, const int32_t *col, const int
  * Applies one batch (Algorithm 1): edges holds b pairs (u, v) interleaved,
  * int32[2b], in either orientation; op is DRSF_INSERT or DRSF_DELETE.
  * Blocks until the result is final on the device and fills *out (may be
- * NULL).  b == 0 is a no-op.  With inputs_on_device the batch is read in
+ * NULL); updates still queued are waited for first and their results
+ * dropped.  b == 0 is a no-op.  With inputs_on_device the batch is read in
  * place on the device (see drsf_apply_async).  Errors: DRSF_E_BATCH (state
  * unchanged), DRSF_E_CAPACITY (b > max_batch, or more inserts than
  * delta_capacity), DRSF_E_ARG, DRSF_E_DEVICE.
@@ -252,13 +255,18 @@ int drsf_apply(drsf_ctx *ctx, const int32_t *edges, int64_t b, int op, drsf_view
  * that needs a store rebuild, and every other context wait for all queued
  * updates first.  If the running update needs the host to finish it (see
  * drsf_view.host_finished), the one queued behind it does nothing on the
- * device until drsf_wait has finished the first, then runs.  A status the
- * call itself returns belongs to an earlier update that it waited for.
+ * device until drsf_wait has finished the first, then runs.  An error this
+ * call returns other than DRSF_E_CAPACITY or DRSF_E_ARG may belong to an
+ * earlier update that it waited for.
  */
 int drsf_apply_async(drsf_ctx *ctx, const int32_t *edges, int64_t b, int op);
 
-/* Waits for the oldest queued update and returns its status; with none
- * queued, returns the status of the last update waited for. */
+/* Returns the status and figures of the oldest queued update not yet
+ * returned, waiting for it if it is still running: one call per
+ * drsf_apply_async, in order.  An update that another call of the library
+ * waited for on the caller's behalf (a drain before a call that needs the
+ * queue empty) keeps its result for this call (the two newest are kept).
+ * With none left, returns the status of the last update waited for. */
 int drsf_wait(drsf_ctx *ctx, drsf_view *out);
 
 /*

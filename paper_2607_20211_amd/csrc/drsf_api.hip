@@ -160,12 +160,15 @@ struct drsf_ctx {
     int32_t *h_bgid = nullptr;            // [max_batch]
     int32_t *h_lists = nullptr;           // vlist | ilist | tlist
     // Two slots of control block and returned words: an update can be
-    // queued while the one before it runs.  Update number q uses slot q & 1;
-    // h_ctl, h_ret and h_gstat point into the slot in use.
+    // queued while the one before it runs.  Queued updates alternate between
+    // the slots, others use slot 0; h_ctl, h_ret and h_gstat point into the
+    // slot in use.
     Ctl *h_ctl_ring = nullptr;
     unsigned long long *h_ret_ring = nullptr;
     int slot = 0;
+    int last_slot = 1;  // of the last update launched
     Ctl *h_ctl = nullptr;
+    uint8_t *h_stage = nullptr;           // pinned staging of device-to-host copies (STAGE_BYTES)
     unsigned long long *h_ret = nullptr;  // copy of ctlmem, then scratch words; the last is the
                                           // completion word (seq of the finished update)
     uint64_t seq = 0;                     // updates launched
@@ -182,6 +185,14 @@ struct drsf_ctx {
         int64_t b;
     } pend[2] = {};
     int npend = 0;
+    // results of updates that a call of the library waited for on the
+    // caller's behalf (a drain before a call that needs the queue empty),
+    // oldest first, until drsf_wait returns them (the two newest are kept)
+    struct Done {
+        int rc;
+        drsf_view view;
+    } done[2] = {};
+    int ndone = 0;
     bool multi_last = false;
     std::vector<int64_t> last_bg;  // per-graph batch sizes of the last apply
     std::vector<int8_t> last_opg;  // per-graph op of the last apply
@@ -286,6 +297,26 @@ int halloc(drsf_ctx *c, T **p, int64_t count) {
     return DRSF_OK;
 }
 
+// Copies device memory to host memory that need not be pinned (a caller's
+// array, a std::vector) through pinned staging, a chunk at a time: each
+// chunk is complete in the pinned buffer once the stream is, and reaches the
+// destination by a host copy after that.  No pageable destination is handed
+// to the copy engine, so nothing can land in it after this returns.
+constexpr size_t STAGE_BYTES = (size_t)1 << 20;
+int d2h(drsf_ctx *c, void *dst, const void *src, size_t bytes) {
+    if (bytes == 0) return DRSF_OK;
+    int rc;
+    if (!c->h_stage && (rc = halloc(c, &c->h_stage, (int64_t)STAGE_BYTES))) return rc;
+    for (size_t off = 0; off < bytes; off += STAGE_BYTES) {
+        const size_t len = std::min(STAGE_BYTES, bytes - off);
+        HIPCHK(c, hipMemcpyAsync(c->h_stage, static_cast<const char *>(src) + off, len, hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        memcpy(static_cast<char *>(dst) + off, c->h_stage, len);
+    }
+    return DRSF_OK;
+}
+
 void dfree(drsf_ctx *c, void *p) {
     if (!p) return;
     auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
@@ -304,6 +335,8 @@ Dev make_dev(drsf_ctx *c) {
     d.n = c->n;
     d.validate = c->opts.validate_batches != 0;
     d.gate = 1;
+    d.lb = c->max_batch;
+    d.ltiles = c->dtmax;
     d.ctl = c->ctl;
     d.ctlw = c->ctl;
     d.hctl = c->h_ctl;
@@ -557,7 +590,7 @@ void destroy_ctx(drsf_ctx *c) {
     drop_graphs(c);
     for (void *p : c->allocs) raw_dfree(c->opts, p);
     c->allocs.clear();
-    void *hosts[] = {c->h_edges, c->h_bop, c->h_bgid, c->h_lists, c->h_ctl_ring, c->h_ret_ring};
+    void *hosts[] = {c->h_edges, c->h_bop, c->h_bgid, c->h_lists, c->h_ctl_ring, c->h_ret_ring, c->h_stage};
     for (void *p : hosts)
         if (p) (void)hipHostFree(p);
     for (auto &e : c->ev)
@@ -645,7 +678,7 @@ int build_store(drsf_ctx *c, const int64_t *row_ptr_in, const int32_t *col_in, i
     launch_tile_k(c->zptr, c->nz, c->eb, c->tile_k, c->ntiles, s);
     // base-store offsets of each graph's rows (host copy, for the tile lists)
     std::vector<uint32_t> bp((size_t)n + 1);
-    HIPCHK(c, hipMemcpyAsync(bp.data(), c->bptr, sizeof(uint32_t) * bp.size(), hipMemcpyDeviceToHost, s));
+    if ((rc = d2h(c, bp.data(), c->bptr, sizeof(uint32_t) * bp.size()))) return rc;
     HIPCHK(c, hipStreamSynchronize(s));
     c->gedge_h.assign((size_t)c->ngraph + 1, 0);
     c->gm_h.assign((size_t)c->ngraph, 0);
@@ -960,7 +993,11 @@ int sg_reduce(drsf_ctx *c, const Dev &d, hipStream_t s) {
 // kc: the control block, passed with the first kernel when the sequence is
 // launched kernel by kernel (null while capturing: read from pinned memory).
 void enqueue_update(drsf_ctx *c, int kind, bool profile, const Ctl *kc) {
-    const Dev d = make_dev(c);
+    Dev d = make_dev(c);
+    if (kc) {  // launched kernel by kernel: grids sized for this batch and list
+        d.lb = std::max<int64_t>(kc->b, 1);
+        d.ltiles = delta_tiles(c->ndelta_bound);
+    }
     hipStream_t s = c->stream;
     const bool ins = kind & 1, del = kind & 2;
     // a phase that launches nothing for this kind records no event (an
@@ -1018,7 +1055,7 @@ void enqueue_update(drsf_ctx *c, int kind, bool profile, const Ctl *kc) {
     if (ins && sg) launch_insert_emit(d, s);
     if (del) launch_sweep_delta(d, s);
     mark(PH_REPL);
-    const int64_t units = (ins ? insert_regions(c->max_batch) : 0) + (del ? c->ntiles + c->dtmax : 0);
+    const int64_t units = (ins ? insert_regions(d.lb) : 0) + (del ? c->ntiles + d.ltiles : 0);
     if (sg) {  // supergraph, then its rounds
         c->round_base = SG_ROUND0;
         if (sg_reduce(c, d, s)) launch_fill_i32(c->status, 1, ST_ROUND_BOUND, s);
@@ -1062,6 +1099,8 @@ int capture_graph(drsf_ctx *c, int kind) {
 int continue_update(drsf_ctx *c) {
     Dev d = make_dev(c);
     d.gate = 0;  // runs while the update's cleanup holds any update queued behind it
+    d.lb = std::max<int64_t>(c->last_b, 1);
+    d.ltiles = delta_tiles(c->ndelta_bound);
     hipStream_t s = c->stream;
     unsigned long long *f = c->h_ret + c->ret_words;  // [0] status, [1] rounds done, [2] level active
     auto read_flags = [&](int levels) -> int {
@@ -1145,13 +1184,19 @@ int continue_update(drsf_ctx *c) {
     return DRSF_OK;
 }
 
+// Updates replay captured graphs (launch_mode 1, or 0 with several graphs)
+// rather than launching kernel by kernel.
+bool graph_launch(const drsf_ctx *c) {
+    return c->opts.launch_mode == 1 || (c->opts.launch_mode == 0 && c->ngraph > 1);
+}
+
 // Queues one update whose batch is in the device batch buffers and whose
 // control block is in h_ctl.
 int launch_update(drsf_ctx *c) {
     hipStream_t s = c->stream;
     // the control block is read from h_ctl by the first kernel (no copy)
     const bool prof = c->opts.profile != 0;
-    c->h_ctl->seq = ++c->seq;  // the caller filled slot seq & 1
+    c->h_ctl->seq = ++c->seq;  // the caller filled the slot in use
     // clear the completion word: pinned memory may hold any value (a freed
     // context's, or scratch), and the wait must only see this update's
     *(volatile unsigned long long *)(c->h_ret + c->ret_words + 7) = 0;
@@ -1163,7 +1208,7 @@ int launch_update(drsf_ctx *c) {
     // the device then goes from one update to the next as from one kernel
     // to the next, where a graph launch starts some microseconds after the
     // work before it
-    if (prof || c->opts.replacement_mode == 1 || c->npend > 0 || c->opts.launch_mode == 0) {
+    if (prof || c->opts.replacement_mode == 1 || c->npend > 0 || !graph_launch(c)) {
         enqueue_update(c, c->kind, prof, c->h_ctl);
     } else {
         int rc;
@@ -1172,6 +1217,7 @@ int launch_update(drsf_ctx *c) {
     }
     HIPCHK(c, hipGetLastError());
     c->pend[c->slot] = drsf_ctx::Pend{c->seq, c->kind, c->last_op, c->last_b};
+    c->last_slot = c->slot;
     c->npend++;
     c->have_phases = prof;
     return DRSF_OK;
@@ -1182,7 +1228,7 @@ int launch_update(drsf_ctx *c) {
 int relaunch_update(drsf_ctx *c, int q) {
     select_slot(c, q);
     c->kind = c->pend[q].kind;
-    if (c->opts.launch_mode == 0) {
+    if (!graph_launch(c)) {
         enqueue_update(c, c->kind, false, c->h_ctl);
     } else {
         int rc;
@@ -1232,9 +1278,23 @@ int stage_edges(drsf_ctx *c, const int32_t *edges, int64_t b) {
     return DRSF_OK;
 }
 
+int wait_oldest(drsf_ctx *c);
+
+// Keeps the result in last_rc and view for a later drsf_wait.
+void keep_done(drsf_ctx *c, int rc) {
+    if (c->ndone == 2) {
+        c->done[0] = c->done[1];
+        c->ndone = 1;
+    }
+    c->done[c->ndone++] = drsf_ctx::Done{rc, c->view};
+}
+
+// Waits for every queued update, keeping their results for drsf_wait;
+// returns an error other than a rejected batch.
 int finish_pending(drsf_ctx *c) {
     while (c->npend > 0) {
-        const int rc = drsf_wait(c, nullptr);
+        const int rc = wait_oldest(c);
+        keep_done(c, rc);
         if (rc != DRSF_OK && rc != DRSF_E_BATCH) return rc;
     }
     return DRSF_OK;
@@ -1294,8 +1354,8 @@ static int create_impl(int32_t G, const int32_t *n_off, int32_t n, const int64_t
         fail(c, DRSF_E_ARG, "replacement_mode must be 0 or 1");
         return bail(DRSF_E_ARG);
     }
-    if (c->opts.launch_mode < 0 || c->opts.launch_mode > 1) {
-        fail(c, DRSF_E_ARG, "launch_mode must be 0 or 1");
+    if (c->opts.launch_mode < 0 || c->opts.launch_mode > 2) {
+        fail(c, DRSF_E_ARG, "launch_mode must be 0, 1 or 2");
         return bail(DRSF_E_ARG);
     }
     if (c->opts.dev_alloc && !c->opts.dev_free) {
@@ -1357,9 +1417,7 @@ static int create_impl(int32_t G, const int32_t *n_off, int32_t n, const int64_t
     const int64_t *rp = row_ptr;
     if (c->opts.inputs_on_device) {
         hrow.resize((size_t)n + 1);
-        if (hipMemcpyAsync(hrow.data(), row_ptr, sizeof(int64_t) * hrow.size(), hipMemcpyDeviceToHost,
-                           c->stream) != hipSuccess ||
-            hipStreamSynchronize(c->stream) != hipSuccess) {
+        if (d2h(c, hrow.data(), row_ptr, sizeof(int64_t) * hrow.size()) != DRSF_OK) {
             (void)hipGetLastError();
             fail(c, DRSF_E_ARG, "cannot read row_ptr");
             return bail(DRSF_E_ARG);
@@ -1522,7 +1580,8 @@ int drsf_apply_async(drsf_ctx *c, const int32_t *edges, int64_t b, int op) {
     if (!queue) {
         if ((rc = finish_pending(c))) return rc;
     } else if (c->npend >= 2) {
-        rc = drsf_wait(c, nullptr);
+        rc = wait_oldest(c);
+        keep_done(c, rc);
         if (rc != DRSF_OK && rc != DRSF_E_BATCH) return rc;
     }
     if ((rc = check_usable(c))) return rc;
@@ -1539,6 +1598,8 @@ int drsf_apply_async(drsf_ctx *c, const int32_t *edges, int64_t b, int op) {
         c->view.num_key_cross = c->view.num_replacement = c->view.num_pieces = c->view.num_paths = 0;
         c->view.num_orphans = c->view.orphan_slots = 0;
         c->view.scan_orphans = 0;
+        c->view.host_finished = 0;
+        keep_done(c, DRSF_OK);
         return DRSF_OK;
     }
     if (op == DRSF_INSERT && c->ndelta_bound + b > c->dcap) {
@@ -1552,7 +1613,9 @@ int drsf_apply_async(drsf_ctx *c, const int32_t *edges, int64_t b, int op) {
     if (!c->opts.inputs_on_device && (rc = stage_edges(c, edges, b))) return rc;
     c->last_b = b;
     c->last_op = op;
-    select_slot(c, (int)((c->seq + 1) & 1));
+    // queued updates alternate between the two slots; one waited for alone
+    // keeps to slot 0 (and to the graphs captured there)
+    select_slot(c, queue ? 1 - c->last_slot : 0);
     Ctl &k = *c->h_ctl;
     memset(&k, 0, sizeof k);
     if (c->opts.inputs_on_device) k.edges = edges;
@@ -1608,7 +1671,7 @@ int drsf_multi_apply_async(drsf_ctx *c, const int32_t *edges, const int64_t *b_o
     }
     c->have_phases = false;
     c->multi_last = true;
-    select_slot(c, (int)((c->seq + 1) & 1));
+    select_slot(c, 0);
     c->last_b = b;
     c->last_bg.assign((size_t)G, 0);
     c->last_opg.assign(op, op + G);
@@ -1619,6 +1682,8 @@ int drsf_multi_apply_async(drsf_ctx *c, const int32_t *edges, const int64_t *b_o
         c->view.num_key_cross = c->view.num_replacement = c->view.num_pieces = c->view.num_paths = 0;
         c->view.num_orphans = c->view.orphan_slots = 0;
         c->view.scan_orphans = 0;
+        c->view.host_finished = 0;
+        keep_done(c, DRSF_OK);
         return DRSF_OK;
     }
     // per-edge op and graph; vertex-block lists of the deleting and the
@@ -1695,121 +1760,141 @@ int drsf_multi_apply_async(drsf_ctx *c, const int32_t *edges, const int64_t *b_o
     return launch_update(c);
 }
 
-int drsf_wait(drsf_ctx *c, drsf_view *out) {
-    if (!c) return DRSF_E_ARG;
-    if (c->npend > 0) {
-        // the oldest queued update, in its slot
-        const uint64_t myseq = c->seq - (uint64_t)c->npend + 1;
-        const int q = (int)(myseq & 1);
-        select_slot(c, q);
-        c->kind = c->pend[q].kind;
-        c->last_b = c->pend[q].b;
-        c->last_op = c->pend[q].op;
-        c->npend--;
-        // the last kernel writes the completion word once the results in
-        // h_ret are final: poll it (a stream synchronisation wakes up later),
-        // asking the stream now and then so that a failed or idle stream ends
-        // the wait; profiling waits for the stream (its events)
-        const volatile unsigned long long *done = c->h_ret + c->ret_words + 7;
-        bool seen = false;
-        if (!c->have_phases) {
-            for (uint32_t it = 1;; it++) {
-                if (*done == myseq) {
-                    seen = true;
-                    break;
+}  // extern "C"
+
+namespace {
+
+// Waits for the oldest queued update and finishes it: its status in
+// last_rc (returned), its figures in view.
+int wait_oldest(drsf_ctx *c) {
+    // the oldest queued update, in its slot
+    const uint64_t myseq = c->seq - (uint64_t)c->npend + 1;
+    const int q = c->pend[0].seq == myseq ? 0 : 1;
+    select_slot(c, q);
+    c->kind = c->pend[q].kind;
+    c->last_b = c->pend[q].b;
+    c->last_op = c->pend[q].op;
+    c->npend--;
+    // the last kernel writes the completion word once the results in
+    // h_ret are final: poll it (a stream synchronisation wakes up later),
+    // asking the stream now and then so that a failed or idle stream ends
+    // the wait; profiling waits for the stream (its events)
+    const volatile unsigned long long *done = c->h_ret + c->ret_words + 7;
+    bool seen = false;
+    if (!c->have_phases) {
+        for (uint32_t it = 1;; it++) {
+            if (*done == myseq) {
+                seen = true;
+                break;
+            }
+            if ((it & 1023) == 0 && hipStreamQuery(c->stream) != hipErrorNotReady) break;
+        }
+        std::atomic_thread_fence(std::memory_order_acquire);
+    }
+    if (!seen || *done != myseq) HIPCHK(c, hipStreamSynchronize(c->stream));
+    const unsigned long long *k = c->h_ret + 1;
+    int32_t st = *(int32_t *)c->h_ret;
+    c->view.host_finished = 0;
+    c->cont_timed = false;
+    if (st == 0 && !k[C_ORIENTED]) {  // the captured rounds did not finish it
+        c->view.host_finished = 1;
+        int rc = continue_update(c);
+        if (!rc && c->npend > 0) {
+            // the update queued behind it stood still: queue it again
+            rc = relaunch_update(c, 1 - q);
+            select_slot(c, q);
+            c->kind = c->pend[q].kind;
+        }
+        if (rc) {
+            // a held update would stay held: the context is not usable
+            c->npend = 0;
+            c->broken = true;
+            return c->last_rc = rc;
+        }
+        st = *(int32_t *)c->h_ret;
+    }
+    if (c->have_phases &&
+        hipEventElapsedTime(&c->phase_ms[PH_N + 1], c->ev[PH_N + 1], c->ev[PH_N + 2]) != hipSuccess) {
+        (void)hipGetLastError();
+        c->have_phases = false;
+    }
+    c->phase_ms[PH_N] = 0.f;
+    if (c->have_phases && c->cont_timed &&
+        hipEventElapsedTime(&c->phase_ms[PH_N], c->ev[PH_N + 3], c->ev[PH_N + 4]) != hipSuccess) {
+        (void)hipGetLastError();
+        c->have_phases = false;
+    }
+    if (c->have_phases)
+        for (int i = 0; i < PH_N; i++) {
+            c->phase_ms[i] = 0.f;
+            if (!c->ph_on[i]) continue;
+            int j = i + 1;
+            while (j < PH_N && !c->ph_on[j]) j++;
+            if (hipEventElapsedTime(&c->phase_ms[i], c->ev[i], c->ev[j]) != hipSuccess) {
+                (void)hipGetLastError();
+                c->have_phases = false;
+            }
+        }
+    if (st != 0) {
+        c->last_rc = fail(c, DRSF_E_DEVICE, "internal bound exceeded (status %d)", st);
+    } else {
+        c->view.num_key_cross = (int64_t)(k[C_NCROSS] + k[C_SNCROSS]);
+        c->view.num_replacement = (int64_t)(k[C_NER] + k[C_SNER]);
+        c->view.num_pieces = (int64_t)k[C_NP];
+        c->view.num_paths = (int64_t)(k[C_NR] + k[C_SNR]);
+        c->view.scan_orphans = (int32_t)k[C_OMODE];
+        c->view.num_orphans = (int64_t)k[C_NORPH];
+        c->view.orphan_slots = (int64_t)k[C_OVOL] - (int64_t)OR_PAD * (int64_t)k[C_NORPH];
+        c->last_rc = DRSF_OK;
+        if (c->multi_last) {
+            for (int32_t g = 0; g < c->ngraph; g++) {
+                const int64_t bg = c->last_bg[g];
+                if (c->h_gstat[g]) {
+                    const bool in_store = c->g2s.empty() || c->g2s[g] < 0;
+                    if (c->last_opg[g] == DRSF_INSERT && in_store) c->ndelta_bound -= bg;
+                } else {
+                    const int64_t dm = c->last_opg[g] == DRSF_INSERT ? bg : -bg;
+                    c->gm_h[g] += dm;
+                    c->m_live += dm;
                 }
-                if ((it & 1023) == 0 && hipStreamQuery(c->stream) != hipErrorNotReady) break;
             }
-            std::atomic_thread_fence(std::memory_order_acquire);
-        }
-        if (!seen || *done != myseq) HIPCHK(c, hipStreamSynchronize(c->stream));
-        const unsigned long long *k = c->h_ret + 1;
-        int32_t st = *(int32_t *)c->h_ret;
-        c->view.host_finished = 0;
-        c->cont_timed = false;
-        if (st == 0 && !k[C_ORIENTED]) {  // the captured rounds did not finish it
-            c->view.host_finished = 1;
-            int rc = continue_update(c);
-            if (!rc && c->npend > 0) {
-                // the update queued behind it stood still: queue it again
-                rc = relaunch_update(c, 1 - q);
-                select_slot(c, q);
-                c->kind = c->pend[q].kind;
-            }
-            if (rc) {
-                // a held update would stay held: the context is not usable
-                c->npend = 0;
-                c->broken = true;
-                return c->last_rc = rc;
-            }
-            st = *(int32_t *)c->h_ret;
-        }
-        if (c->have_phases &&
-            hipEventElapsedTime(&c->phase_ms[PH_N + 1], c->ev[PH_N + 1], c->ev[PH_N + 2]) != hipSuccess) {
-            (void)hipGetLastError();
-            c->have_phases = false;
-        }
-        c->phase_ms[PH_N] = 0.f;
-        if (c->have_phases && c->cont_timed &&
-            hipEventElapsedTime(&c->phase_ms[PH_N], c->ev[PH_N + 3], c->ev[PH_N + 4]) != hipSuccess) {
-            (void)hipGetLastError();
-            c->have_phases = false;
-        }
-        if (c->have_phases)
-            for (int i = 0; i < PH_N; i++) {
-                c->phase_ms[i] = 0.f;
-                if (!c->ph_on[i]) continue;
-                int j = i + 1;
-                while (j < PH_N && !c->ph_on[j]) j++;
-                if (hipEventElapsedTime(&c->phase_ms[i], c->ev[i], c->ev[j]) != hipSuccess) {
-                    (void)hipGetLastError();
-                    c->have_phases = false;
-                }
-            }
-        if (st != 0) {
-            c->last_rc = fail(c, DRSF_E_DEVICE, "internal bound exceeded (status %d)", st);
+        } else if (c->h_gstat[0]) {
+            const int32_t bs = c->h_gstat[0];
+            if (c->last_op == DRSF_INSERT) c->ndelta_bound -= c->last_b;
+            c->last_rc = fail(c, DRSF_E_BATCH, "invalid batch:%s%s%s%s",
+                              bs & ST_BAD_PAIR ? " self-loop or id out of range;" : "",
+                              bs & ST_DUPLICATE ? " repeated edge;" : "",
+                              bs & ST_EXISTS ? " insert of an existing edge;" : "",
+                              bs & ST_MISSING ? " delete of a missing edge;" : "");
         } else {
-            c->view.num_key_cross = (int64_t)(k[C_NCROSS] + k[C_SNCROSS]);
-            c->view.num_replacement = (int64_t)(k[C_NER] + k[C_SNER]);
-            c->view.num_pieces = (int64_t)k[C_NP];
-            c->view.num_paths = (int64_t)(k[C_NR] + k[C_SNR]);
-            c->view.scan_orphans = (int32_t)k[C_OMODE];
-            c->view.num_orphans = (int64_t)k[C_NORPH];
-            c->view.orphan_slots = (int64_t)k[C_OVOL] - (int64_t)OR_PAD * (int64_t)k[C_NORPH];
-            c->last_rc = DRSF_OK;
-            if (c->multi_last) {
-                for (int32_t g = 0; g < c->ngraph; g++) {
-                    const int64_t bg = c->last_bg[g];
-                    if (c->h_gstat[g]) {
-                        const bool in_store = c->g2s.empty() || c->g2s[g] < 0;
-                        if (c->last_opg[g] == DRSF_INSERT && in_store) c->ndelta_bound -= bg;
-                    } else {
-                        const int64_t dm = c->last_opg[g] == DRSF_INSERT ? bg : -bg;
-                        c->gm_h[g] += dm;
-                        c->m_live += dm;
-                    }
-                }
-            } else if (c->h_gstat[0]) {
-                const int32_t bs = c->h_gstat[0];
-                if (c->last_op == DRSF_INSERT) c->ndelta_bound -= c->last_b;
-                c->last_rc = fail(c, DRSF_E_BATCH, "invalid batch:%s%s%s%s",
-                                  bs & ST_BAD_PAIR ? " self-loop or id out of range;" : "",
-                                  bs & ST_DUPLICATE ? " repeated edge;" : "",
-                                  bs & ST_EXISTS ? " insert of an existing edge;" : "",
-                                  bs & ST_MISSING ? " delete of a missing edge;" : "");
-            } else {
-                const int64_t dm = c->last_op == DRSF_INSERT ? c->last_b : -c->last_b;
-                c->m_live += dm;
-                c->gm_h[0] += dm;
-            }
+            const int64_t dm = c->last_op == DRSF_INSERT ? c->last_b : -c->last_b;
+            c->m_live += dm;
+            c->gm_h[0] += dm;
         }
     }
     c->view.parent = c->parent;
     c->view.label = c->label;
     c->view.n = c->n;
     c->view.num_edges = c->m_live;
-    if (out) *out = c->view;
     return c->last_rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int drsf_wait(drsf_ctx *c, drsf_view *out) {
+    if (!c) return DRSF_E_ARG;
+    if (c->ndone > 0) {  // waited for on the caller's behalf by an earlier call
+        const drsf_ctx::Done d = c->done[0];
+        c->done[0] = c->done[1];
+        c->ndone--;
+        if (out) *out = d.view;
+        return d.rc;
+    }
+    const int rc = c->npend > 0 ? wait_oldest(c) : c->last_rc;
+    if (out) *out = c->view;
+    return rc;
 }
 
 int drsf_multi_wait(drsf_ctx *c, int32_t *status) {
@@ -1823,8 +1908,11 @@ int drsf_multi_wait(drsf_ctx *c, int32_t *status) {
 
 int drsf_multi_apply(drsf_ctx *c, const int32_t *edges, const int64_t *b_off, const int8_t *op,
                      int32_t *status) {
-    const int rc = drsf_multi_apply_async(c, edges, b_off, op);
-    if (rc != DRSF_OK) return rc;
+    if (!c) return DRSF_E_ARG;
+    int rc = finish_pending(c);  // results of earlier queued updates are dropped
+    if (rc) return rc;
+    c->ndone = 0;
+    if ((rc = drsf_multi_apply_async(c, edges, b_off, op)) != DRSF_OK) return rc;
     return drsf_multi_wait(c, status);
 }
 
@@ -1837,8 +1925,11 @@ int drsf_multi_num_edges(drsf_ctx *c, int64_t *m) {
 }
 
 int drsf_apply(drsf_ctx *c, const int32_t *edges, int64_t b, int op, drsf_view *out) {
-    const int rc = drsf_apply_async(c, edges, b, op);
-    if (rc != DRSF_OK) return rc;
+    if (!c) return DRSF_E_ARG;
+    int rc = finish_pending(c);  // results of earlier queued updates are dropped
+    if (rc) return rc;
+    c->ndone = 0;
+    if ((rc = drsf_apply_async(c, edges, b, op)) != DRSF_OK) return rc;
     return drsf_wait(c, out);
 }
 
@@ -1852,15 +1943,10 @@ int drsf_get_view(drsf_ctx *c, drsf_view *out) {
 
 int drsf_copy_out(drsf_ctx *c, int32_t *parent_host, int32_t *label_host) {
     if (!c) return DRSF_E_ARG;
-    const int rc = finish_pending(c);
+    int rc = finish_pending(c);
     if (rc) return rc;
-    if (parent_host)
-        HIPCHK(c, hipMemcpyAsync(parent_host, c->parent, sizeof(int32_t) * (size_t)c->n,
-                                 hipMemcpyDeviceToHost, c->stream));
-    if (label_host)
-        HIPCHK(c, hipMemcpyAsync(label_host, c->label, sizeof(int32_t) * (size_t)c->n,
-                                 hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (parent_host && (rc = d2h(c, parent_host, c->parent, sizeof(int32_t) * (size_t)c->n))) return rc;
+    if (label_host && (rc = d2h(c, label_host, c->label, sizeof(int32_t) * (size_t)c->n))) return rc;
     return DRSF_OK;
 }
 
@@ -1879,18 +1965,12 @@ int drsf_export_edges(drsf_ctx *c, uint64_t *keys, int64_t capacity, int64_t *m_
     std::vector<int32_t> bcol((size_t)c->eb);
     unsigned long long nd = 0;
     HIPCHK(c, hipMemcpyAsync(c->h_ret, c->cnt + C_NDELTA, sizeof nd, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(bptr.data(), c->bptr, sizeof(uint32_t) * bptr.size(), hipMemcpyDeviceToHost,
-                             c->stream));
-    if (c->eb)
-        HIPCHK(c, hipMemcpyAsync(bcol.data(), c->bcol, sizeof(int32_t) * bcol.size(),
-                                 hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     nd = c->h_ret[0];
+    if ((rc = d2h(c, bptr.data(), c->bptr, sizeof(uint32_t) * bptr.size()))) return rc;
+    if (c->eb && (rc = d2h(c, bcol.data(), c->bcol, sizeof(int32_t) * bcol.size()))) return rc;
     std::vector<uint64_t> dk((size_t)nd);
-    if (nd) {
-        HIPCHK(c, hipMemcpyAsync(dk.data(), c->dkey, sizeof(uint64_t) * nd, hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-    }
+    if (nd && (rc = d2h(c, dk.data(), c->dkey, sizeof(uint64_t) * nd))) return rc;
     int64_t w = 0;
     for (int32_t u = 0; u < c->n; u++)
         for (uint32_t j = bptr[u]; j < bptr[u + 1]; j++)
@@ -1906,10 +1986,9 @@ int drsf_export_edges(drsf_ctx *c, uint64_t *keys, int64_t capacity, int64_t *m_
     if (c->nsg) {  // small graphs: their own key arrays, in local ids
         std::vector<int32_t> sm((size_t)c->nsg), sb((size_t)c->nsg);
         std::vector<uint32_t> pk((size_t)c->pool_keys);
-        HIPCHK(c, hipMemcpyAsync(sm.data(), c->sm, 4 * sm.size(), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipMemcpyAsync(sb.data(), c->sbuf, 4 * sb.size(), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipMemcpyAsync(pk.data(), c->pool, 4 * pk.size(), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if ((rc = d2h(c, sm.data(), c->sm, 4 * sm.size())) || (rc = d2h(c, sb.data(), c->sbuf, 4 * sb.size())) ||
+            (rc = d2h(c, pk.data(), c->pool, 4 * pk.size())))
+            return rc;
         for (int32_t k = 0; k < c->nsg; k++) {
             const uint64_t o = (uint64_t)c->goff_h[c->sgid_h[k]];
             const uint32_t *E = pk.data() + c->soff_h[k] + (int64_t)sb[k] * c->scap_h[k];

@@ -31,6 +31,10 @@ struct Ctl {
 struct Dev {
     int32_t n;
     int32_t validate;        // 0: batches guaranteed valid (no repeat check, no insert presence search)
+    int64_t lb;              // batch size the launch grids are sized for: the batch itself when
+                             // launched kernel by kernel, max_batch in a captured graph
+    int64_t ltiles;          // tiles of the inserted-edge list the launch covers (at least the
+                             // list's length; its capacity in a captured graph)
     int32_t gate;            // 1: an update's own kernels, which stand still while the hold word
                              // is set; 0: the host's continuation of the update that set it
     const Ctl *ctl;          // device copy, written by the first kernel of an update

@@ -2169,24 +2169,28 @@ __global__ __launch_bounds__(BLOCK) void k_cleanup(Dev d) {
 int64_t delta_tiles(int64_t count) { return (count + TILE - 1) / TILE; }
 int64_t insert_regions(int64_t b) { return (b + BLOCK - 1) / BLOCK; }
 
+// Pieces an update can register: two per batch edge (a grid over them is
+// grid-stride; its size only sets how many workgroups share the work).
+static int64_t piece_bound(const Dev &d) { return std::min<int64_t>(d.pcap, 2 * d.lb + 16); }
+
 void launch_classify(const Dev &d, const Ctl *kc, hipStream_t s) {
     const Ctl none{};
-    hipLaunchKernelGGL(k_classify, dim3(grid_for(d.max_b, BLOCK)), dim3(BLOCK), 0, s, d, kc ? *kc : none,
+    hipLaunchKernelGGL(k_classify, dim3(grid_for(d.lb, BLOCK)), dim3(BLOCK), 0, s, d, kc ? *kc : none,
                        kc ? 1 : 0);
 }
 void launch_dedupe(const Dev &d, hipStream_t s) {
-    hipLaunchKernelGGL(k_dedupe, dim3(grid_for(d.max_b, BLOCK)), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_dedupe, dim3(grid_for(d.lb, BLOCK)), dim3(BLOCK), 0, s, d);
 }
 void launch_prepare(const Dev &d, bool del, hipStream_t s) {
-    const int gb = grid_for(d.max_b, BLOCK);
+    const int gb = grid_for(d.lb, BLOCK);
     const int gi = del ? grid_for(d.nvb, BLOCK / WAVE, COPY_CAP) : 0;
     hipLaunchKernelGGL(k_prepare, dim3(gb + gi), dim3(BLOCK), 0, s, d, gb);
 }
 void launch_register(const Dev &d, hipStream_t s) {
-    hipLaunchKernelGGL(k_register, dim3(grid_for(d.max_b, BLOCK)), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_register, dim3(grid_for(d.lb, BLOCK)), dim3(BLOCK), 0, s, d);
 }
 void launch_insert_emit(const Dev &d, hipStream_t s) {
-    hipLaunchKernelGGL(k_insert_emit, dim3((unsigned)insert_regions(d.max_b)), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_insert_emit, dim3((unsigned)insert_regions(d.lb)), dim3(BLOCK), 0, s, d);
 }
 void launch_rep_chase(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_rep_chase, dim3(grid_for(d.nvb, REP_CH, GRID_CAP)), dim3(BLOCK), 0, s, d);
@@ -2207,15 +2211,15 @@ void launch_orphan_scan(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_orph_scan, dim3(grid_for(d.ntiles, 1, GRID_CAP)), dim3(BLOCK), 0, s, d);
 }
 void launch_sweep_delta(const Dev &d, hipStream_t s) {
-    if (d.dtmax > 0)
-        hipLaunchKernelGGL(k_sweep_delta, dim3((unsigned)d.dtmax), dim3(BLOCK), 0, s, d);
+    if (d.ltiles > 0)
+        hipLaunchKernelGGL(k_sweep_delta, dim3((unsigned)d.ltiles), dim3(BLOCK), 0, s, d);
 }
 // The hooking, rooting and reversal kernels index pieces, arcs and paths
 // (at most 2 max_batch): grids of one workgroup per CU, grid-stride, so a
 // round that finds nothing to do costs little dispatch.
 void launch_boruvka(const Dev &d, int r0, int r1, int64_t units, bool emit, hipStream_t s) {
     const int ge = grid_for(units, 1, EDGE_CAP);
-    const int gp = grid_for(d.pcap, BLOCK, SMALL_CAP);
+    const int gp = grid_for(piece_bound(d), BLOCK, SMALL_CAP);
     for (int r = r0; r < r1; r++) {
         if (r == 0)
             hipLaunchKernelGGL(k_bor_round0, dim3(ge), dim3(BLOCK), 0, s, d, emit ? 1 : 0);
@@ -2227,15 +2231,16 @@ void launch_boruvka(const Dev &d, int r0, int r1, int64_t units, bool emit, hipS
     if (r1 >= 2 && r1 > r0) hipLaunchKernelGGL(k_bor_tail, dim3(1), dim3(TAIL_THREADS), 0, s, d, r1);
 }
 void launch_sf_root(const Dev &d, hipStream_t s) {
-    const int gp = grid_for(d.pcap, BLOCK, SMALL_CAP);
+    const int gp = grid_for(piece_bound(d), BLOCK, SMALL_CAP);
     hipLaunchKernelGGL(k_sf_root, dim3(gp), dim3(BLOCK), 0, s, d);
 }
 void launch_sf_bfs(const Dev &d, int l0, int l1, hipStream_t s) {
-    const int ga = grid_for(2 * d.ercap, BLOCK, SMALL_CAP);
+    const int ga = grid_for(2 * std::min<int64_t>(d.ercap, piece_bound(d)), BLOCK, SMALL_CAP);
     for (int L = l0; L < l1; L++) hipLaunchKernelGGL(k_sf_bfs, dim3(ga), dim3(BLOCK), 0, s, d, L);
 }
 void launch_orient_bfs(const Dev &d, int levels, hipStream_t s) {
-    hipLaunchKernelGGL(k_orient_bfs, dim3(grid_for(d.pcap, BLOCK, SMALL_CAP)), dim3(BLOCK), 0, s, d, levels);
+    hipLaunchKernelGGL(k_orient_bfs, dim3(grid_for(piece_bound(d), BLOCK, SMALL_CAP)), dim3(BLOCK), 0, s, d,
+                       levels);
 }
 void launch_superforest_lr(const Dev &d, int lr_rounds, hipStream_t s) {
     const int ga = grid_for(2 * d.ercap, BLOCK, SMALL_CAP);
@@ -2251,7 +2256,8 @@ void launch_reverse_all(const Dev &d, hipStream_t s) {
 }
 void launch_finish(const Dev &d, bool ins, bool del, bool rev, hipStream_t s) {
     // an update reverses at most one path per piece and per replacement edge
-    const int grev = rev ? grid_for(d.ercap + d.pcap, BLOCK, FINISH_CAP) : 0;
+    const int grev = rev ? grid_for(std::min<int64_t>(d.ercap, piece_bound(d)) + piece_bound(d), BLOCK, FINISH_CAP)
+                         : 0;
     // deletes relabel per vertex block or per listed orphan, inserts one wave
     // per vertex block
     const int glab = del ? grid_for(d.n, BLOCK, FINISH_CAP) : grid_for(d.nvb, BLOCK / WAVE, FINISH_CAP);
@@ -2309,7 +2315,7 @@ int launch_et_reverse(const Dev &d, void *tmp, size_t tmp_bytes, hipStream_t s) 
     return 0;
 }
 void launch_cleanup(const Dev &d, hipStream_t s) {
-    int64_t m = d.pcap > d.max_b ? d.pcap : d.max_b;
+    const int64_t m = std::max<int64_t>(piece_bound(d), d.lb);
     // few workgroups: each arrives once on one counter (serialised atomics)
     hipLaunchKernelGGL(k_cleanup, dim3(grid_for(m, BLOCK, CLEANUP_CAP)), dim3(BLOCK), 0, s, d);
 }

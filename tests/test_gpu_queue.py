@@ -6,7 +6,9 @@ next one runs on the unchanged state), and at every drain the parent and
 label arrays are bit-exact with the oracle's.  With one queued hooking round
 and one search level most updates are finished by the host, so the update
 queued behind each of them first stands still on the device and is then
-queued again."""
+queued again.  With a short inserted-edge list every few inserts rebuild the
+store, and such an insert waits for the queue and is applied alone between
+queued ones."""
 from __future__ import annotations
 
 import numpy as np
@@ -48,9 +50,10 @@ def _plan(g, nbatch, mb, rng):
     return out
 
 
+@pytest.mark.parametrize("short_list", [False, True])
 @pytest.mark.parametrize("launch_mode", [0, 1])
 @pytest.mark.parametrize("host_finished", [False, True])
-def test_queued_updates_match_the_oracle(host_finished, launch_mode):
+def test_queued_updates_match_the_oracle(host_finished, launch_mode, short_list):
     import torch
     drsf = _lib()
     dev = torch.device("cuda:0")
@@ -59,13 +62,13 @@ def test_queued_updates_match_the_oracle(host_finished, launch_mode):
     mb = 1500
     plan = _plan(g, 24, mb, rng)
     _case(f"queued updates: R-MAT 13, {len(plan)} batches up to {mb}, host-finished {host_finished}, "
-          f"launch mode {launch_mode}")
+          f"launch mode {launch_mode}, short inserted-edge list {short_list}")
     stream = torch.cuda.Stream(dev)
     with torch.cuda.stream(stream):
         t = [torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (g.row_ptr, g.col, g.parent)]
         dbat = [torch.from_numpy(np.ascontiguousarray(b, np.int32)).to(dev) for b, *_ in plan]
     f = drsf.Forest(g.n, *t, inputs_on_device=True, stream=stream.cuda_stream, max_batch=mb,
-                    launch_mode=launch_mode)
+                    launch_mode=launch_mode, delta_capacity=2 * mb if short_list else 0)
     if host_finished:
         f.set_tuning(1, 1, 0)  # one queued round and level: the host finishes most updates
     op_of = {oracle.INSERT: drsf.DRSF_INSERT, oracle.DELETE: drsf.DRSF_DELETE}

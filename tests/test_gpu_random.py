@@ -54,7 +54,7 @@ def test_random_cases(block):
             kw["delta_capacity"] = int(rng.integers(mb, 3 * mb + 1))  # a batch always fits
         device = bool(rng.random() < 0.3)
         # captured graphs now and then (its own draw: the cases stay as they were)
-        kw["launch_mode"] = int(np.random.default_rng(70000 + c).random() < 0.3)
+        kw["launch_mode"] = int(np.random.default_rng(70000 + c).integers(3))
         _case(f"random {c}: {kind} n={g.n} m={g.m} {kw} device={device}")
         pair = Pair(g, device=device, **kw)
         if rng.random() < 0.5:
@@ -99,7 +99,8 @@ def test_random_multi_graph_cases():
         _case(f"random multi {c}: {len(graphs)} graphs, sum n={sum(g.n for g in graphs)}, max_batch {mb}, "
               f"small graphs up to {small} ({threads} threads)")
         pair = MultiPair(graphs, max_batch=mb * len(graphs), sweep_mode=int(rng.integers(2)),
-                         small_graph_vertices=small, small_threads=threads)
+                         small_graph_vertices=small, small_threads=threads,
+                         launch_mode=int(np.random.default_rng(90000 + c).integers(3)))
         if rng.random() < 0.5:
             pair.gpu.set_tuning(int(rng.integers(1, 7)), int(rng.integers(1, 9)), int(rng.integers(2)))
         if small and rng.random() < 0.5:
