@@ -12,9 +12,9 @@ every surviving forest edge.  Graph, forest and every batch are resident in
 device memory before the timed region starts.
 
 Prints one JSON line: value = edge updates per second of the whole timed
-job (insert + delete) in the production configuration (each update replays
-the context's captured HIP graph, queued behind the one before it so that
-two are in flight); insert and delete latencies as seen by the host from a
+job (insert + delete) in the production configuration (each update launches
+the context's kernel sequence, queued behind the one before it so that two
+are in flight); insert and delete latencies as seen by the host from a
 pass over the same steps one update at a time; per-phase device times and
 the rooflines of the dominant kernels from a pass that launches the kernels
 one by one with events between the phases on the stream the kernels run
@@ -273,9 +273,8 @@ def methods_ab(n, row, col, par, batches, max_batch, stream, drsf, reps=3):
     """The same updates with each replacement-edge method and each path
     reversal (the paper's SG/HS x ET variants beside this build's defaults).
     Wall time per update: median of reps applies from the same state on a
-    context in the production configuration (captured update graph; the
-    supergraph reads sizes back between its kernels, so it is launched
-    directly).  Phase times: the same updates on a profiled context (kernels
+    context in the production configuration (the supergraph reads sizes
+    back between its kernels, so it is always launched kernel by kernel).  Phase times: the same updates on a profiled context (kernels
     launched one by one with events), less the event bracket.  Whether every
     method ends in the same forest: digests."""
     res = {}
@@ -315,7 +314,7 @@ def methods_ab(n, row, col, par, batches, max_batch, stream, drsf, reps=3):
                           "update_wall_ms": round(wall * 1e3, 4)})
         assert [int(x) for x in fp.digest()] == digest
         fp.close()
-        res[name] = {"steps": steps, "digest": digest, "captured": rm == 0}
+        res[name] = {"steps": steps, "digest": digest}
     res["same_result"] = len({tuple(v["digest"]) for k, v in res.items() if k in METHODS}) == 1
     return res
 
@@ -411,7 +410,7 @@ def run_configs(g, dev, stream, log, reps=3):
         ins = torch.from_numpy(gen.insert_batches(g.n, g.keys, 1, b, gen.seed(2, 1, gen.P_INSERT))[0]).to(dev)
         dl = torch.from_numpy(gen.delete_batches(g.n, g.keys, g.parent, 1, b, b // 2,
                                                  gen.seed(2, 1, gen.P_DELETE))[0]).to(dev)
-        f.apply(ins, drsf.DRSF_INSERT)  # warm (captures the graphs)
+        f.apply(ins, drsf.DRSF_INSERT)  # warm
         f.restore(snap)
         f.apply(dl, drsf.DRSF_DELETE)
         ti = time_op(f, snap, ins, drsf.DRSF_INSERT, reps, drsf)
@@ -723,8 +722,8 @@ def main():
                            inputs_on_device=True, profile=profile,
                            delta_capacity=max(nsteps * b + b, 1 << 20))
 
-    # timed pass: the production configuration (captured update graphs, two
-    # updates in flight, no events)
+    # timed pass: the production configuration (two updates in flight, no
+    # events)
     f = make(0)
     torch.cuda.synchronize()
     log(f"context created ({time.time() - t0:.1f}s)")

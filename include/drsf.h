@@ -83,8 +83,7 @@ typedef struct {
     int validate_forest;     /* create: 1 (default) checks that parent[] is a rooted
                                 spanning forest whose trees span G's components */
     int profile;             /* 1: launch the update's kernels one by one with an
-                                event between phases (drsf_phase_times) instead of
-                                replaying the captured update graph */
+                                event between phases (drsf_phase_times) */
     int64_t max_batch;       /* largest batch accepted by apply; 0 = 1 << 20 */
     int64_t delta_capacity;  /* inserted edges held in the inserted-edge list; an
                                 insert that would overflow it first merges the list
@@ -97,7 +96,7 @@ typedef struct {
                                 slots as the store, else the whole store; 1:
                                 always the whole store (Sec. II-A as written) */
     int rounds_queued;       /* full-grid hooking rounds (Alg. 2, phase 1)
-                                placed in the captured update graph; later
+                                queued in the update's kernel sequence; later
                                 rounds run in one workgroup while at most 4096
                                 cross edges are live, else host-driven
                                 launches finish them; 0 = chosen by the
@@ -196,7 +195,7 @@ typedef struct {
     int64_t orphan_slots;     /* delete: adjacency entries of those vertices */
     int32_t scan_orphans;     /* delete: 1 if the key-edge scan covered only the
                                  orphans' adjacency, 0 if the whole store */
-    int32_t host_finished;    /* 0 if the captured sequence finished the
+    int32_t host_finished;    /* 0 if the queued kernel sequence finished the
                                  update; else host-driven launches finished it:
                                  bit 0 set when they ran more hooking rounds
                                  (the live cross edges outgrew the
@@ -374,9 +373,9 @@ int64_t drsf_footprint(int32_t n, int64_t nnz, const drsf_opts *opts);
 
 /*
  * Changes the tunables of drsf_opts (rounds_queued, levels_queued,
- * sweep_mode; 0 = default for the first two) on a live context; the next
- * apply captures its update graph again.  Results do not depend on them
- * (only the split between captured and host-driven work does).  Used by the
+ * sweep_mode; 0 = default for the first two) on a live context (captured
+ * update graphs are dropped).  Results do not depend on them (only the split
+ * between queued and host-driven work does).  Used by the
  * autotuner.  Errors: DRSF_E_ARG.
  */
 int drsf_set_tuning(drsf_ctx *ctx, int rounds_queued, int levels_queued, int sweep_mode);
@@ -385,8 +384,8 @@ int drsf_set_tuning(drsf_ctx *ctx, int rounds_queued, int levels_queued, int swe
  * The launch schedule of the small-graph kernel of a multi-graph context
  * (drsf_opts.small_graph_vertices): threads per workgroup (256, 512 or
  * 1024; 0 = keep) and workgroups (0 = as many as fit on the device at once,
- * at most one per small graph).  Results do not depend on it.  The next
- * apply captures its update graph again.  Used by the autotuner.  Errors:
+ * at most one per small graph).  Results do not depend on it; captured
+ * update graphs are dropped.  Used by the autotuner.  Errors:
  * DRSF_E_ARG.
  */
 int drsf_set_small_schedule(drsf_ctx *ctx, int threads, int workgroups);

@@ -1,7 +1,8 @@
 """Autotuner for the update path's launch schedule.
 
-An update replays a captured HIP graph that queues a fixed number of hooking
-rounds and super-forest search levels; batches that need more finish on the
+An update launches a fixed kernel sequence (kernel by kernel, or as a
+captured HIP graph) that queues a fixed number of hooking rounds and
+super-forest search levels; batches that need more finish on the
 host (extra launches and synchronisations), batches that need fewer pay for
 launches that find nothing to do.  Which split is cheapest depends on the
 workload (batch size, graph shape, how many graphs share a context), so it
