@@ -264,8 +264,10 @@ int drsf_apply_async(drsf_ctx *ctx, const int32_t *edges, int64_t b, int op);
  * returned, waiting for it if it is still running: one call per
  * drsf_apply_async, in order.  An update that another call of the library
  * waited for on the caller's behalf (a drain before a call that needs the
- * queue empty) keeps its result for this call (the two newest are kept).
- * With none left, returns the status of the last update waited for. */
+ * queue empty) keeps its result for this call (the two newest are kept;
+ * a multi-graph apply drops them, since it overwrites the per-graph
+ * statuses).  With none left, returns the status of the last update waited
+ * for. */
 int drsf_wait(drsf_ctx *ctx, drsf_view *out);
 
 /*

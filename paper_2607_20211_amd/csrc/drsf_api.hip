@@ -1636,6 +1636,9 @@ int drsf_multi_apply_async(drsf_ctx *c, const int32_t *edges, const int64_t *b_o
     if (!c) return DRSF_E_ARG;
     int rc;
     if ((rc = finish_pending(c))) return rc;
+    // per-graph statuses live in the returned words, which this update
+    // overwrites: results not yet returned are dropped
+    c->ndone = 0;
     if ((rc = check_usable(c))) return rc;
     if (!b_off || !op) return fail(c, DRSF_E_ARG, "b_off and op must be non-NULL");
     const int32_t G = c->ngraph;

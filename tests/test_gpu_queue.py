@@ -100,3 +100,62 @@ def test_queued_updates_match_the_oracle(host_finished, launch_mode, short_list)
     if host_finished:
         assert finished_by_host >= len(plan) // 3, f"only {finished_by_host} updates needed the host"
     f.close()
+
+
+def test_results_come_back_in_submission_order():
+    """A drain on the caller's behalf (a copy-out, an empty batch) keeps the
+    drained updates' results for drsf_wait, which returns them in the order
+    the batches were queued: a rejected delete, then a valid insert queued
+    while that result waits, then an empty batch, each with its own
+    status."""
+    import torch
+    drsf = _lib()
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(77)
+    g = gen.make_graph("rmat11", 1 << 11, gen.rmat(11, 8, 0.57, 0.19, 0.19, 99))
+    plan = _plan(g, 4, 300, rng)  # batch 3 is a rejected delete
+    _case("queued results in order: R-MAT 11")
+    stream = torch.cuda.Stream(dev)
+    with torch.cuda.stream(stream):
+        t = [torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (g.row_ptr, g.col, g.parent)]
+        dbat = [torch.from_numpy(np.ascontiguousarray(b, np.int32)).to(dev) for b, *_ in plan]
+        empty = torch.zeros((0, 2), dtype=torch.int32, device=dev)
+    f = drsf.Forest(g.n, *t, inputs_on_device=True, stream=stream.cuda_stream, max_batch=300)
+    op_of = {oracle.INSERT: drsf.DRSF_INSERT, oracle.DELETE: drsf.DRSF_DELETE}
+    for j in range(3):
+        f.apply(dbat[j], op_of[plan[j][1]])
+    f.apply_async(dbat[3], op_of[plan[3][1]])   # rejected
+    f.label()                                   # drains it on the caller's behalf
+    # an insert of pairs that are still non-edges after the rejected delete
+    ins = gen.insert_batches(g.n, _keys_after(g, plan[:3]), 1, 200, 5)[0]
+    with torch.cuda.stream(stream):
+        dins = torch.from_numpy(np.ascontiguousarray(ins, np.int32)).to(dev)
+    got = []
+
+    def wait():
+        try:
+            f.wait()
+            got.append(drsf.DRSF_OK)
+        except drsf.DrsfError as e:
+            got.append(e.code)
+
+    f.apply_async(dins, drsf.DRSF_INSERT)
+    wait()                                      # the rejected delete's result, kept by the drain
+    f.apply_async(empty, drsf.DRSF_DELETE)      # drains the insert, then nothing to launch
+    wait()
+    wait()
+    assert got == [drsf.DRSF_E_BATCH, drsf.DRSF_OK, drsf.DRSF_OK], got
+    r = oracle.apply(g.n, _keys_after(g, plan[:3]), plan[2][3], ins, oracle.INSERT, label=plan[2][4])
+    assert np.array_equal(f.parent(), r.parent) and np.array_equal(f.label(), r.label)
+    f.close()
+
+
+def _keys_after(g, part):
+    """Edge keys after the valid batches of part (replayed on the oracle)."""
+    r = oracle.apply(g.n, g.keys, g.parent, np.zeros((0, 2), np.int32), oracle.DELETE)
+    keys, par, lab = g.keys, r.parent, r.label
+    for batch, op, ok, _, _ in part:
+        if ok:
+            r = oracle.apply(g.n, keys, par, batch, op, label=lab)
+            keys, par, lab = r.keys, r.parent, r.label
+    return keys
