@@ -418,9 +418,6 @@ int read_status(drsf_ctx *c, int32_t *st) {
     return DRSF_OK;
 }
 
-// Arrays sized by the base store's tiles: cross-edge regions (base-store
-// tiles, inserted-edge tiles, batch regions), orphan-scan ranges and, with
-// several graphs, the block and tile lists.  Called again after a rebuild.
 // Points h_ctl, h_ret and h_gstat at slot q.
 void select_slot(drsf_ctx *c, int q) {
     c->slot = q;
@@ -431,6 +428,9 @@ void select_slot(drsf_ctx *c, int q) {
     }
 }
 
+// Arrays sized by the base store's tiles: cross-edge regions (base-store
+// tiles, inserted-edge tiles, batch regions), orphan-scan ranges and, with
+// several graphs, the block and tile lists.  Called again after a rebuild.
 int alloc_tiles(drsf_ctx *c) {
     int rc;
     dfree(c, c->x0); dfree(c, c->x1); dfree(c, c->rcnt); dfree(c, c->rstart); dfree(c, c->xcnt);
@@ -679,7 +679,6 @@ int build_store(drsf_ctx *c, const int64_t *row_ptr_in, const int32_t *col_in, i
     // base-store offsets of each graph's rows (host copy, for the tile lists)
     std::vector<uint32_t> bp((size_t)n + 1);
     if ((rc = d2h(c, bp.data(), c->bptr, sizeof(uint32_t) * bp.size()))) return rc;
-    HIPCHK(c, hipStreamSynchronize(s));
     c->gedge_h.assign((size_t)c->ngraph + 1, 0);
     c->gm_h.assign((size_t)c->ngraph, 0);
     for (int32_t g = 0; g <= c->ngraph; g++) c->gedge_h[g] = bp[c->goff_h[g]];
@@ -1194,7 +1193,8 @@ bool graph_launch(const drsf_ctx *c) {
 // control block is in h_ctl.
 int launch_update(drsf_ctx *c) {
     hipStream_t s = c->stream;
-    // the control block is read from h_ctl by the first kernel (no copy)
+    // the first kernel takes the control block in h_ctl: as its argument
+    // when launched kernel by kernel, from pinned memory in a captured graph
     const bool prof = c->opts.profile != 0;
     c->h_ctl->seq = ++c->seq;  // the caller filled the slot in use
     // clear the completion word: pinned memory may hold any value (a freed
@@ -1239,9 +1239,10 @@ int relaunch_update(drsf_ctx *c, int q) {
     return DRSF_OK;
 }
 
-// An update may be queued behind a running one (two in flight) when it is
-// launched as a captured graph of a one-graph context reading its batch in
-// place; otherwise the queue is drained first.
+// An update may be queued behind a running one (two in flight) in a
+// one-graph context that reads its batches in place, without profiling, on
+// the default replacement and reversal paths; otherwise the queue is drained
+// first.
 bool can_queue(const drsf_ctx *c) {
     return c->ngraph == 1 && c->opts.inputs_on_device && !c->opts.profile && c->opts.replacement_mode == 0 &&
            c->opts.reverse_mode == 0 && c->nsg == 0;
@@ -1799,7 +1800,7 @@ int wait_oldest(drsf_ctx *c) {
     int32_t st = *(int32_t *)c->h_ret;
     c->view.host_finished = 0;
     c->cont_timed = false;
-    if (st == 0 && !k[C_ORIENTED]) {  // the captured rounds did not finish it
+    if (st == 0 && !k[C_ORIENTED]) {  // the queued rounds did not finish it
         c->view.host_finished = 1;
         int rc = continue_update(c);
         if (!rc && c->npend > 0) {
