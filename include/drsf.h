@@ -169,6 +169,16 @@ typedef struct {
                                 behind a running one, a profiled one and one
                                 on the supergraph are always launched kernel
                                 by kernel.  Results are identical. */
+    int walk_limit;          /* path reversal (reverse_mode 0): one thread
+                                walks a path of at most this many steps; a
+                                longer path is turned after the update's
+                                kernel sequence by a pointer-doubling pass
+                                over all vertices that the host launches
+                                (drsf_view.host_finished bit 2), about
+                                log2(path length) kernels, with 13 bytes per
+                                vertex more device memory allocated at the
+                                first such path.  0 = 1024 (default); must be
+                                >= 0.  Results are identical. */
 } drsf_opts;
 
 /* Fills *opts with the defaults described above. */
@@ -201,7 +211,8 @@ typedef struct {
                                  (the live cross edges outgrew the
                                  one-workgroup rounds), bit 1 when they ran
                                  more super-forest search levels or the Euler
-                                 tour */
+                                 tour, bit 2 when they turned paths longer
+                                 than walk_limit */
 } drsf_view;
 
 /*

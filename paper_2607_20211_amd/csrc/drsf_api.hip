@@ -37,6 +37,10 @@ constexpr int BFS_FAST = 4;    // default search levels queued in the captured s
 constexpr int BFS_MAX = 12;    // deeper super-trees use the Euler tour instead
 constexpr int BOR_CHUNK = 3;   // rounds per host check in the continuation
 constexpr int AUTO_ROUNDS_MAX = 12;  // queued rounds the library may grow to by itself
+// default steps one thread walks along a path; a longer path is turned by
+// the doubling pass (a few kernels over all vertices, about as long as a
+// walk of this many dependent reads)
+constexpr int64_t WALK_LIMIT = 1024;
 
 enum Phase { PH_VALIDATE, PH_UPDATE, PH_ROOT, PH_ORPH_LIST, PH_ORPH_SCAN, PH_SWEEP, PH_SWEEP_DELTA,
              PH_REPL, PH_ROOTING, PH_FINISH, PH_N };
@@ -132,6 +136,13 @@ struct drsf_ctx {
     int32_t *arc_nxt = nullptr, *succ0 = nullptr, *succ1 = nullptr, *rank0 = nullptr, *rank1 = nullptr;
     PathReq *paths = nullptr;
     int64_t pathcap = 0;
+    // paths longer than walk_k steps: their list, and the buffers of the
+    // doubling pass that turns them (allocated when such a path first occurs)
+    int32_t *lp_list = nullptr;
+    int64_t lpcap = 0, walk_k = 0;
+    int32_t *lp_p0 = nullptr, *lp_j0 = nullptr, *lp_j1 = nullptr;
+    uint32_t *lp_mark = nullptr;
+    uint32_t lp_epoch = 0;
     // path reversal by Euler tour (reverse_mode 1)
     uint64_t *et_keys = nullptr, *et_sorted = nullptr;
     int32_t *et_fc = nullptr, *et_ns = nullptr, *et_opar = nullptr, *et_nxt0 = nullptr,
@@ -372,6 +383,7 @@ Dev make_dev(drsf_ctx *c) {
     d.er = c->er; d.ercap = c->ercap; d.arc_nxt = c->arc_nxt;
     d.succ0 = c->succ0; d.succ1 = c->succ1; d.rank0 = c->rank0; d.rank1 = c->rank1;
     d.paths = c->paths; d.pathcap = c->pathcap;
+    d.lp_list = c->lp_list; d.lpcap = c->lpcap; d.walk_k = c->walk_k;
     d.et_keys = c->et_keys; d.et_sorted = c->et_sorted; d.et_fc = c->et_fc; d.et_ns = c->et_ns;
     d.et_opar = c->et_opar; d.et_nxt0 = c->et_nxt0; d.et_nxt1 = c->et_nxt1;
     d.et_dst0 = c->et_dst0; d.et_dst1 = c->et_dst1; d.et_start = c->et_start;
@@ -526,6 +538,9 @@ int alloc_state(drsf_ctx *c) {
     if ((rc = dalloc(c, &c->rank1, 2 * c->ercap))) return rc;
     c->pathcap = std::max<int64_t>(c->ercap + c->pcap, n);
     if ((rc = dalloc(c, &c->paths, c->pathcap))) return rc;
+    c->walk_k = c->opts.walk_limit > 0 ? c->opts.walk_limit : WALK_LIMIT;
+    c->lpcap = n / (c->walk_k + 2) + 1;
+    if ((rc = dalloc(c, &c->lp_list, c->lpcap))) return rc;
     if (c->opts.reverse_mode == 1) {  // path reversal by Euler tour
         if ((rc = dalloc(c, &c->et_keys, n))) return rc;
         if ((rc = dalloc(c, &c->et_sorted, n))) return rc;
@@ -803,6 +818,32 @@ int small_grow(drsf_ctx *c, const std::vector<int64_t> &need) {
     return DRSF_OK;
 }
 
+// Turns the paths that an update's walks left to the doubling pass (nlong
+// of them, listed on the device); allocates the pass's buffers the first
+// time.
+int reverse_long_paths(drsf_ctx *c, const Dev &d, int64_t nlong, hipStream_t s) {
+    const int64_t n = c->n;
+    int rc;
+    if (!c->lp_p0 && (rc = dalloc(c, &c->lp_p0, n))) return rc;
+    if (!c->lp_j0 && (rc = dalloc(c, &c->lp_j0, n))) return rc;
+    if (!c->lp_j1 && (rc = dalloc(c, &c->lp_j1, n))) return rc;
+    if (!c->lp_mark) {
+        if ((rc = dalloc(c, &c->lp_mark, n))) return rc;
+        c->lp_epoch = 0;
+        launch_fill_i32((int32_t *)c->lp_mark, n, 0, s);
+    }
+    if (++c->lp_epoch == 0) {  // wrapped: clear the marks so that none equals the epoch
+        launch_fill_i32((int32_t *)c->lp_mark, n, 0, s);
+        c->lp_epoch = 1;
+    }
+    LongPaths b;
+    b.p0 = c->lp_p0; b.j0 = c->lp_j0; b.j1 = c->lp_j1; b.mark = c->lp_mark;
+    b.epoch = c->lp_epoch;
+    b.nlong = std::min(nlong, c->lpcap);  // more were listed only if the update failed
+    launch_long_paths(d, b, s);
+    return DRSF_OK;
+}
+
 // Checks the forest (optional) and roots every tree at its smallest vertex.
 int canonicalise_forest(drsf_ctx *c) {
     const int32_t n = c->n;
@@ -838,6 +879,11 @@ int canonicalise_forest(drsf_ctx *c) {
     launch_tree_min(n, root, c->label, s);
     launch_reroot_requests(d, root, s);
     launch_reverse_all(d, s);
+    // paths too long for one thread's walk: the doubling pass
+    HIPCHK(c, hipMemcpyAsync(c->h_ret + 1, c->cnt + C_NLONG, sizeof(unsigned long long),
+                             hipMemcpyDeviceToHost, s));
+    if ((rc = read_status(c, &st))) return rc;
+    if (!st && c->h_ret[1] > 0 && (rc = reverse_long_paths(c, d, (int64_t)c->h_ret[1], s))) return rc;
     if ((rc = read_status(c, &st))) return rc;
     if (st) return fail(c, DRSF_E_DEVICE, "re-rooting failed (status %d)", st);
     launch_fill_u64(c->cnt, C_TOTAL, 0, s);
@@ -1092,9 +1138,11 @@ int capture_graph(drsf_ctx *c, int kind) {
     return DRSF_OK;
 }
 
-// Finishes an update that the captured sequence left unfinished: more
+// Finishes an update that the queued sequence left unfinished: more
 // hooking rounds in short chunks, deeper search or the Euler tour, then
-// reversal, labels and cleanup.
+// reversal, labels and cleanup; or, when its sequence ran to the end and
+// left only paths too long for one thread's walk, the doubling pass over
+// those and cleanup.
 int continue_update(drsf_ctx *c) {
     Dev d = make_dev(c);
     d.gate = 0;  // runs while the update's cleanup holds any update queued behind it
@@ -1115,15 +1163,24 @@ int continue_update(drsf_ctx *c) {
     // each round at least halves the components that still have a live edge
     const int bor_bound = std::min(c->round_base + ceil_log2(np_max + 2) + 2, MAX_ROUNDS);
     const int lr_rounds = std::min(ceil_log2(2 * np_max + 2) + 2, MAX_ROUNDS);
+    // the counters the update handed over: orientation done means only
+    // long paths are left (the walks ran, and the labels)
+    const unsigned long long *k = c->h_ret + 1;
+    const bool oriented = k[C_ORIENTED] != 0;
+    int64_t nlong = oriented ? (int64_t)k[C_NLONG] : 0;
     int rc;
-    if ((rc = read_flags(c->bfs_fast))) return rc;
-    bool bad = *(int32_t *)f != 0, done = f[1] != 0, bfs_done = f[2] == 0;
-    int r = c->round_base + c->bor_fast, lv = c->bfs_fast;
+    bool bad = false;
     int how = 0;  // the bits of drsf_view.host_finished
     // profiled contexts time the continuation, host round trips included
     c->cont_timed = c->have_phases;
+    if (!oriented) {
+        if ((rc = read_flags(c->bfs_fast))) return rc;
+    }
     if (c->cont_timed) (void)hipEventRecord(c->ev[PH_N + 3], s);
-    if (!bad && !done) {
+    bad = !oriented && *(int32_t *)f != 0;
+    bool done = oriented || f[1] != 0, bfs_done = oriented || f[2] == 0;
+    int r = c->round_base + c->bor_fast, lv = c->bfs_fast;
+    if (!oriented && !bad && !done) {
         how |= 1;
         while (!done && !bad && r < bor_bound) {
             const int r1 = std::min(r + BOR_CHUNK, bor_bound);
@@ -1145,7 +1202,7 @@ int continue_update(drsf_ctx *c) {
             bfs_done = f[2] == 0;
         }
     }
-    if (!bad) {
+    if (!oriented && !bad) {
         if (!bfs_done) how |= 2;
         while (!bfs_done && lv < BFS_MAX) {
             launch_sf_bfs(d, lv, lv + 4, s);
@@ -1159,6 +1216,15 @@ int continue_update(drsf_ctx *c) {
         if (et && launch_et_reverse(d, c->et_tmp, c->et_tmp_bytes, s))
             launch_fill_i32(c->status, 1, ST_ROUND_BOUND, s);
         launch_finish(d, c->kind & 1, c->kind & 2, !et, s);
+        // the walks may have left long paths
+        HIPCHK(c, hipMemcpyAsync(f + 6, c->cnt + C_NLONG, sizeof(unsigned long long),
+                                 hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        nlong = (int64_t)f[6];
+    }
+    if (!bad && nlong > 0) {
+        how |= 4;
+        if ((rc = reverse_long_paths(c, d, nlong, s))) return rc;
     }
     launch_cleanup(d, s);  // hands the results to the host, then resets
     if (c->cont_timed) (void)hipEventRecord(c->ev[PH_N + 4], s);
@@ -1357,6 +1423,10 @@ static int create_impl(int32_t G, const int32_t *n_off, int32_t n, const int64_t
     }
     if (c->opts.launch_mode < 0 || c->opts.launch_mode > 2) {
         fail(c, DRSF_E_ARG, "launch_mode must be 0, 1 or 2");
+        return bail(DRSF_E_ARG);
+    }
+    if (c->opts.walk_limit < 0) {
+        fail(c, DRSF_E_ARG, "walk_limit must be >= 0");
         return bail(DRSF_E_ARG);
     }
     if (c->opts.dev_alloc && !c->opts.dev_free) {
@@ -1800,7 +1870,8 @@ int wait_oldest(drsf_ctx *c) {
     int32_t st = *(int32_t *)c->h_ret;
     c->view.host_finished = 0;
     c->cont_timed = false;
-    if (st == 0 && !k[C_ORIENTED]) {  // the queued rounds did not finish it
+    // the queued rounds and levels did not finish it, or its walks left long paths
+    if (st == 0 && (!k[C_ORIENTED] || k[C_NLONG])) {
         c->view.host_finished = 1;
         int rc = continue_update(c);
         if (!rc && c->npend > 0) {

@@ -50,6 +50,7 @@ enum : int {
     C_NORPH = 13,    // listed orphan vertices (orphans with at least one slot)
     C_ARRIVE = 14,   // workgroups of the running kernel that have finished (zero between kernels)
     C_LR_FINAL = 12, // buffer holding the final list ranks
+    C_NLONG = 15,    // paths longer than the walk limit, left to the host's doubling pass
     C_COUNT = 16,
 };
 

@@ -143,6 +143,13 @@ struct Dev {
     int32_t *rank0, *rank1;  // [2 ercap]
     PathReq *paths;          // [pathcap]
     int64_t pathcap;
+    // paths longer than walk_k steps: one thread does not walk them; their
+    // indices in paths wait here for the pointer-doubling pass the host
+    // launches (vertex-disjoint paths of more than walk_k + 1 vertices, so
+    // at most n / (walk_k + 2) of them)
+    int32_t *lp_list;        // [lpcap]
+    int64_t lpcap;
+    int64_t walk_k;
     // path reversal by Euler tour (reverse_mode 1, else null): arc 2v is the
     // down arc from v's parent into v, arc 2v + 1 the up arc back
     uint64_t *et_keys, *et_sorted;  // [n] (F-hat parent << 32 | child), sorted
@@ -228,6 +235,8 @@ constexpr int C_TOTAL = C_COUNT + 3 * MAX_ROUNDS;
 constexpr int C_SNER = C_COUNT + 8;
 constexpr int C_SNCROSS = C_COUNT + 9;
 constexpr int C_SNR = C_COUNT + 10;
+// the long-path pass: every long path's start has reached its root
+constexpr int C_LP_DONE = C_COUNT + 11;
 
 // Grid sizes.  Workgroups are dispatched at about 200-270 per microsecond
 // across the chip, so a kernel of many short workgroups is bound by
@@ -285,6 +294,18 @@ void launch_orient_bfs(const Dev &d, int levels, hipStream_t s);
 void launch_superforest_lr(const Dev &d, int lr_rounds, hipStream_t s);
 // label kernels of the ops present (delete labels run first)
 void launch_finish(const Dev &d, bool ins, bool del, bool rev, hipStream_t s);  // path reversal and labels
+// Buffers of the pass that turns the paths too long for one thread's walk
+// (allocated when such a path first occurs).
+struct LongPaths {
+    int32_t *p0;        // [n] parents as the pass starts (the orientation to turn)
+    int32_t *j0, *j1;   // [n] the ancestor 2^k steps up, capped at the root (two buffers)
+    uint32_t *mark;     // [n] == epoch: the vertex lies on a long path
+    uint32_t epoch;     // differs from every mark left by an earlier pass
+    int64_t nlong;      // long paths listed in lp_list
+};
+// that pass: rounds of pointer doubling (enough for any path in n vertices),
+// then the reversal and the paths' new parents
+void launch_long_paths(const Dev &d, const LongPaths &b, hipStream_t s);
 // path reversal by Euler tour (Alg. 3); tmp/tmp_bytes: radix-sort scratch
 int launch_et_reverse(const Dev &d, void *tmp, size_t tmp_bytes, hipStream_t s);
 // Supergraph (Sec. III-A): the first round's cross edges reduced to one per

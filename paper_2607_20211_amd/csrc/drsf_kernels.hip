@@ -1756,13 +1756,26 @@ __global__ __launch_bounds__(BLOCK) void k_orient_lr(Dev d, int lr_rounds) {
 // One thread per path.  Paths lie in distinct pieces (at most one per piece:
 // the attach path of a non-root piece or the re-root path of a super-root
 // piece), so the walks touch disjoint vertices; each thread reads a parent
-// before overwriting it (the old orientation is read exactly once).
+// before overwriting it (the old orientation is read exactly once).  A walk
+// first follows its path read-only for at most walk_k steps: a path that
+// does not reach its end by then is listed for the doubling pass below and
+// left untouched (the whole path, its new parent included), so one long
+// path cannot hold the update for its length in dependent reads.
 __device__ void reverse_paths(const Dev &d, int64_t bid, int64_t nblk) {
     const int64_t nr = (int64_t)d.cnt[C_NR];
     const int64_t stride = nblk * BLOCK;
     for (int64_t i = bid * BLOCK + threadIdx.x; i < nr; i += stride) {
         const PathReq q = d.paths[i];
-        int32_t prev = q.newpar, cur = q.start;
+        int32_t cur = q.start;
+        for (int64_t steps = 0; cur != q.stop && steps < d.walk_k; steps++) cur = d.parent[cur];
+        if (cur != q.stop) {
+            const unsigned long long k = atomicAdd(&d.cnt[C_NLONG], 1ull);
+            if ((int64_t)k < d.lpcap) d.lp_list[k] = (int32_t)i;
+            else atomicOr(d.status, ST_CAPACITY);
+            continue;
+        }
+        int32_t prev = q.newpar;
+        cur = q.start;
         for (int64_t steps = 0;; steps++) {
             const int32_t nxt = d.parent[cur];
             d.parent[cur] = prev;
@@ -1776,6 +1789,78 @@ __device__ void reverse_paths(const Dev &d, int64_t bid, int64_t nblk) {
 __global__ __launch_bounds__(BLOCK) void k_reverse_all(Dev d) {
     if (stopped(d)) return;
     reverse_paths(d, blockIdx.x, gridDim.x);
+}
+
+// ----------------------------- a8: long paths by pointer doubling
+//
+// A long path's vertices are the ancestors of its start x up to its piece
+// root r, and r is still a root: the walks above turned only the paths of
+// other pieces, and an attach writes the parent of its own path's start.
+// Marks spread up by doubling.  In round k every vertex's jump pointer goes
+// from the ancestor 2^k steps up to the one 2^(k+1) up (both capped at the
+// root), and every marked vertex marks the ancestor its jump pointer names;
+// so before round k each ancestor of x fewer than 2^k steps up is marked.
+// Only ancestors of a start are ever marked, so a mark that another thread
+// of the same round reads as soon as it is set does no harm.  Once every
+// start's jump pointer names its path's end, the marks are complete: each
+// marked vertex below its root turns its parent edge, parent[p0[u]] = u
+// (distinct targets along a path, read from the snapshot p0, so no write
+// races a read), and each start hangs below its new parent.
+
+__global__ __launch_bounds__(BLOCK) void k_lp_init(Dev d, LongPaths b) {
+    if (stopped(d)) return;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t u = (int64_t)blockIdx.x * BLOCK + threadIdx.x; u < d.n; u += stride) {
+        const int32_t p = d.parent[u];
+        b.p0[u] = p;
+        b.j0[u] = p;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < b.nlong; i += stride)
+        b.mark[d.paths[d.lp_list[i]].start] = b.epoch;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_lp_round(Dev d, LongPaths b, const int32_t *jin, int32_t *jout) {
+    if (stopped(d) || d.cnt[C_LP_DONE]) return;
+    if (blockIdx.x == 0) {
+        // reads jin only, which no thread of this round writes
+        bool reached = true;
+        for (int64_t i = threadIdx.x; i < b.nlong; i += BLOCK) {
+            const PathReq q = d.paths[d.lp_list[i]];
+            reached = reached && jin[q.start] == q.stop;
+        }
+        if (__syncthreads_and(reached)) {
+            if (threadIdx.x == 0) d.cnt[C_LP_DONE] = 1;
+            return;
+        }
+    }
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t u = (int64_t)blockIdx.x * BLOCK + threadIdx.x; u < d.n; u += stride) {
+        const int32_t j = jin[u];
+        jout[u] = jin[j];
+        if (b.mark[u] == b.epoch && b.mark[j] != b.epoch) b.mark[j] = b.epoch;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_lp_reverse(Dev d, LongPaths b) {
+    if (stopped(d)) return;
+    if (!d.cnt[C_LP_DONE]) {  // a start did not reach its path's end: not a forest
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(d.status, ST_WALK_BOUND);
+        return;
+    }
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t u = (int64_t)blockIdx.x * BLOCK + threadIdx.x; u < d.n; u += stride) {
+        if (b.mark[u] != b.epoch) continue;
+        const int32_t p = b.p0[u];
+        if (p != (int32_t)u) d.parent[p] = (int32_t)u;
+    }
+    // the loop above never writes a start's parent: it writes the old
+    // parent of a marked vertex, which lies above it, and a start is the
+    // lowest vertex of its path
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < b.nlong; i += stride) {
+        const PathReq q = d.paths[d.lp_list[i]];
+        d.parent[q.start] = q.newpar;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.cnt[C_NLONG] = 0;  // the update may finish
 }
 
 // ------------------------------------------------------------ a9: labels
@@ -2125,7 +2210,9 @@ __global__ __launch_bounds__(BLOCK) void k_et_reverse(Dev d) {
 // finished.
 __global__ __launch_bounds__(BLOCK) void k_cleanup(Dev d) {
     if (held(d)) return;  // queued behind an unfinished update: no handoff, no reset
-    const bool fin = d.cnt[C_ORIENTED] || *d.status;  // else unfinished: the host continues
+    // else unfinished: the host continues (more rounds or levels, or the
+    // paths too long for one thread)
+    const bool fin = (d.cnt[C_ORIENTED] && !d.cnt[C_NLONG]) || *d.status;
     if (fin) {
         const int64_t np = (int64_t)d.cnt[C_NP];
         const int64_t b = d.ctl->b;
@@ -2253,6 +2340,18 @@ void launch_superforest_lr(const Dev &d, int lr_rounds, hipStream_t s) {
 }
 void launch_reverse_all(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_reverse_all, dim3(grid_for(d.pathcap, BLOCK, 2048)), dim3(BLOCK), 0, s, d);
+}
+void launch_long_paths(const Dev &d, const LongPaths &b, hipStream_t s) {
+    const int gv = grid_for(d.n, BLOCK, GRID_CAP);
+    hipLaunchKernelGGL(k_lp_init, dim3(gv), dim3(BLOCK), 0, s, d, b);
+    // round k finds every start's jump at its path's end once the path has
+    // at most 2^k steps, and a path has fewer than n: rounds 0 .. k with 2^k >= n
+    int rounds = 1;
+    while ((int64_t(1) << (rounds - 1)) < (int64_t)d.n) rounds++;
+    for (int k = 0; k < rounds; k++)
+        hipLaunchKernelGGL(k_lp_round, dim3(gv), dim3(BLOCK), 0, s, d, b, (k & 1) ? b.j1 : b.j0,
+                           (k & 1) ? b.j0 : b.j1);
+    hipLaunchKernelGGL(k_lp_reverse, dim3(gv), dim3(BLOCK), 0, s, d, b);
 }
 void launch_finish(const Dev &d, bool ins, bool del, bool rev, hipStream_t s) {
     // an update reverses at most one path per piece and per replacement edge

@@ -46,7 +46,8 @@ class drsf_opts(ctypes.Structure):
                 ("small_graph_vertices", ctypes.c_int),
                 ("small_threads", ctypes.c_int),
                 ("validate_batches", ctypes.c_int),
-                ("launch_mode", ctypes.c_int)]
+                ("launch_mode", ctypes.c_int),
+                ("walk_limit", ctypes.c_int)]
 
 
 # device allocator hooks of drsf_opts
@@ -483,7 +484,7 @@ class Forest:
                  profile: bool = False, delta_capacity: int = 0, sweep_mode: int = 0,
                  rounds_queued: int = 0, levels_queued: int = 0, reverse_mode: int = 0,
                  replacement_mode: int = 0, allocator: TorchAllocator | None = None,
-                 validate_batches: bool = True, launch_mode: int = 0):
+                 validate_batches: bool = True, launch_mode: int = 0, walk_limit: int = 0):
         self.on_device = bool(inputs_on_device)
         if not self.on_device:
             row_ptr = _host_input(row_ptr, np.int64)
@@ -507,6 +508,7 @@ class Forest:
         o.replacement_mode = replacement_mode
         o.validate_batches = int(validate_batches)
         o.launch_mode = launch_mode
+        o.walk_limit = walk_limit
         if stream is not None:
             o.stream = stream
         self.allocator = allocator
@@ -601,7 +603,8 @@ class MultiForest(Forest):
                  profile: bool = False, delta_capacity: int = 0, sweep_mode: int = 0,
                  rounds_queued: int = 0, levels_queued: int = 0, reverse_mode: int = 0,
                  replacement_mode: int = 0, allocator: TorchAllocator | None = None,
-                 small_graph_vertices: int = 0, small_threads: int = 0, validate_batches: bool = True, launch_mode: int = 0):
+                 small_graph_vertices: int = 0, small_threads: int = 0, validate_batches: bool = True,
+                 launch_mode: int = 0, walk_limit: int = 0):
         self.on_device = bool(inputs_on_device)
         if not self.on_device:
             row_ptr = _host_input(row_ptr, np.int64)
@@ -628,6 +631,7 @@ class MultiForest(Forest):
         o.small_threads = small_threads
         o.validate_batches = int(validate_batches)
         o.launch_mode = launch_mode
+        o.walk_limit = walk_limit
         if stream is not None:
             o.stream = stream
         self.allocator = allocator

@@ -55,7 +55,7 @@ def test_default_opts_layout_matches_the_header():
     assert o.reverse_mode == 0 and o.replacement_mode == 0
     assert not o.dev_alloc and not o.dev_free and not o.alloc_user
     assert o.small_graph_vertices == 0 and o.small_threads == 0
-    assert o.validate_batches == 1 and o.launch_mode == 0
+    assert o.validate_batches == 1 and o.launch_mode == 0 and o.walk_limit == 0
     text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
     body = text[text.index("typedef struct {", text.index("typedef struct drsf_ctx")):]
     body = body[:body.index("} drsf_opts;")]

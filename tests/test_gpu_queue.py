@@ -8,7 +8,9 @@ and one search level most updates are finished by the host, so the update
 queued behind each of them first stands still on the device and is then
 queued again.  With a short inserted-edge list every few inserts rebuild the
 store, and such an insert waits for the queue and is applied alone between
-queued ones."""
+queued ones.  With a walk limit of one step, an update whose paths are
+longer is finished by the host's doubling pass, which also holds the update
+queued behind it."""
 from __future__ import annotations
 
 import numpy as np
@@ -50,10 +52,11 @@ def _plan(g, nbatch, mb, rng):
     return out
 
 
+@pytest.mark.parametrize("walk_limit", [0, 1])
 @pytest.mark.parametrize("short_list", [False, True])
 @pytest.mark.parametrize("launch_mode", [0, 1])
 @pytest.mark.parametrize("host_finished", [False, True])
-def test_queued_updates_match_the_oracle(host_finished, launch_mode, short_list):
+def test_queued_updates_match_the_oracle(host_finished, launch_mode, short_list, walk_limit):
     import torch
     drsf = _lib()
     dev = torch.device("cuda:0")
@@ -62,13 +65,13 @@ def test_queued_updates_match_the_oracle(host_finished, launch_mode, short_list)
     mb = 1500
     plan = _plan(g, 24, mb, rng)
     _case(f"queued updates: R-MAT 13, {len(plan)} batches up to {mb}, host-finished {host_finished}, "
-          f"launch mode {launch_mode}, short inserted-edge list {short_list}")
+          f"launch mode {launch_mode}, short inserted-edge list {short_list}, walk limit {walk_limit}")
     stream = torch.cuda.Stream(dev)
     with torch.cuda.stream(stream):
         t = [torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (g.row_ptr, g.col, g.parent)]
         dbat = [torch.from_numpy(np.ascontiguousarray(b, np.int32)).to(dev) for b, *_ in plan]
     f = drsf.Forest(g.n, *t, inputs_on_device=True, stream=stream.cuda_stream, max_batch=mb,
-                    launch_mode=launch_mode, delta_capacity=2 * mb if short_list else 0)
+                    launch_mode=launch_mode, delta_capacity=2 * mb if short_list else 0, walk_limit=walk_limit)
     if host_finished:
         f.set_tuning(1, 1, 0)  # one queued round and level: the host finishes most updates
     op_of = {oracle.INSERT: drsf.DRSF_INSERT, oracle.DELETE: drsf.DRSF_DELETE}

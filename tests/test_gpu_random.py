@@ -5,7 +5,8 @@ scale 6–14, grids with edges removed, paths with chords), a batch capacity,
 the delete scan (per batch or whole store), the path reversal (per path or
 Euler tour), the replacement-edge method (hooking on every cross edge or on
 the supergraph), sometimes a small inserted-edge list (store rebuilds), host
-or device-resident inputs and a random launch schedule, then alternates insert and delete batches of random
+or device-resident inputs, a random launch schedule and walk limit (paths
+longer than it go to the doubling pass), then alternates insert and delete batches of random
 sizes (deletes with a random share of tree edges).  Every batch: parent and
 label arrays bit-exact, checker pass, same replacement-edge count.  Further
 tests draw random multi-graph contexts, servers and static rebuilds."""
@@ -55,6 +56,8 @@ def test_random_cases(block):
         device = bool(rng.random() < 0.3)
         # captured graphs now and then (its own draw: the cases stay as they were)
         kw["launch_mode"] = int(np.random.default_rng(70000 + c).integers(3))
+        # and now and then a short walk limit (long paths turned by the doubling pass)
+        kw["walk_limit"] = int(np.random.default_rng(80000 + c).choice([0, 0, 0, 1, 2, 5, 40]))
         _case(f"random {c}: {kind} n={g.n} m={g.m} {kw} device={device}")
         pair = Pair(g, device=device, **kw)
         if rng.random() < 0.5:
@@ -80,8 +83,9 @@ def test_random_multi_graph_cases():
     vertices each, some edgeless), 3–6 multi-graph updates each with a
     random op and batch size per graph (empty batches included), now and
     then an invalid batch for one graph (rejected, that graph unchanged), a
-    random launch schedule and a random small-graph threshold and workgroup
-    size (graphs up to it go to the one-workgroup engine); every graph
+    random launch schedule and walk limit, and a random small-graph
+    threshold and workgroup size (graphs up to it go to the one-workgroup
+    engine); every graph
     bit-exact with the oracle run on it alone."""
     from test_gpu_multi import MultiPair
     drsf = _lib()
@@ -100,7 +104,8 @@ def test_random_multi_graph_cases():
               f"small graphs up to {small} ({threads} threads)")
         pair = MultiPair(graphs, max_batch=mb * len(graphs), sweep_mode=int(rng.integers(2)),
                          small_graph_vertices=small, small_threads=threads,
-                         launch_mode=int(np.random.default_rng(90000 + c).integers(3)))
+                         launch_mode=int(np.random.default_rng(90000 + c).integers(3)),
+                         walk_limit=int(np.random.default_rng(95000 + c).choice([0, 0, 1, 3])))
         if rng.random() < 0.5:
             pair.gpu.set_tuning(int(rng.integers(1, 7)), int(rng.integers(1, 9)), int(rng.integers(2)))
         if small and rng.random() < 0.5:
