@@ -213,6 +213,11 @@ typedef struct {
                                  more super-forest search levels or the Euler
                                  tour, bit 2 when they turned paths longer
                                  than walk_limit */
+    int32_t jump_rounds;      /* delete: pointer-jumping rounds before root
+                                 finding's chase that changed an entry; a
+                                 context queues such rounds once a chase has
+                                 found its forest deep (more than 1024
+                                 steps), 0 before */
 } drsf_view;
 
 /*

@@ -157,6 +157,9 @@ struct drsf_ctx {
     uint8_t *sg_scan_tmp = nullptr, *sg_sort_tmp = nullptr;
     size_t sg_sort_bytes = 0;
     int round_base = 0;  // index of the first hooking round of the last update
+    // pointer-jumping rounds queued before root finding's chase: 0 until a
+    // delete finds the forest deep (a chase of more than DEEP_STEPS steps)
+    int jump_rounds = 0;
     // status word, counters and per-graph batch status share one allocation
     // so that one copy returns them: status at word 0, counters from word 1,
     // gstat after the counters
@@ -1083,6 +1086,7 @@ void enqueue_update(drsf_ctx *c, int kind, bool profile, const Ctl *kc) {
     launch_prepare(d, del, s);
     launch_register(d, s);
     mark(PH_ROOT, del);
+    if (del && c->jump_rounds) launch_rep_jump(d, c->jump_rounds, s);
     if (del) launch_rep_chase(d, s);
     mark(PH_ORPH_LIST, del);
     if (del) {
@@ -1669,6 +1673,7 @@ int drsf_apply_async(drsf_ctx *c, const int32_t *edges, int64_t b, int op) {
         c->view.num_key_cross = c->view.num_replacement = c->view.num_pieces = c->view.num_paths = 0;
         c->view.num_orphans = c->view.orphan_slots = 0;
         c->view.scan_orphans = 0;
+        c->view.jump_rounds = 0;
         c->view.host_finished = 0;
         keep_done(c, DRSF_OK);
         return DRSF_OK;
@@ -1756,6 +1761,7 @@ int drsf_multi_apply_async(drsf_ctx *c, const int32_t *edges, const int64_t *b_o
         c->view.num_key_cross = c->view.num_replacement = c->view.num_pieces = c->view.num_paths = 0;
         c->view.num_orphans = c->view.orphan_slots = 0;
         c->view.scan_orphans = 0;
+        c->view.jump_rounds = 0;
         c->view.host_finished = 0;
         keep_done(c, DRSF_OK);
         return DRSF_OK;
@@ -1910,6 +1916,20 @@ int wait_oldest(drsf_ctx *c) {
                 c->have_phases = false;
             }
         }
+    // a deep forest: later deletes queue jumping rounds before the chase,
+    // as many as a path of n vertices needs (rounds after the last one
+    // that changed something exit at once); more if the last queued round
+    // still changed entries
+    if (st == 0) {
+        int want = c->jump_rounds;
+        if (k[C_DEEP] && want == 0) want = std::min(ceil_log2(c->n) + 1, MAX_JUMP);
+        if (want > 0 && k[C_JUMP_ROUND + want - 1]) want = std::min(want + 4, MAX_JUMP);
+        if (want != c->jump_rounds) {
+            (void)hipStreamSynchronize(c->stream);  // a queued update may still run a graph
+            c->jump_rounds = want;
+            drop_graphs(c);
+        }
+    }
     if (st != 0) {
         c->last_rc = fail(c, DRSF_E_DEVICE, "internal bound exceeded (status %d)", st);
     } else {
@@ -1920,6 +1940,8 @@ int wait_oldest(drsf_ctx *c) {
         c->view.scan_orphans = (int32_t)k[C_OMODE];
         c->view.num_orphans = (int64_t)k[C_NORPH];
         c->view.orphan_slots = (int64_t)k[C_OVOL] - (int64_t)OR_PAD * (int64_t)k[C_NORPH];
+        c->view.jump_rounds = 0;
+        for (int r = 0; r < MAX_JUMP; r++) c->view.jump_rounds += k[C_JUMP_ROUND + r] ? 1 : 0;
         c->last_rc = DRSF_OK;
         if (c->multi_last) {
             for (int32_t g = 0; g < c->ngraph; g++) {

@@ -229,7 +229,11 @@ constexpr int64_t TAIL_MAX = 4096;
 // extra counter slots: per-round activity flags
 constexpr int C_LR_ROUND = C_COUNT + MAX_ROUNDS;       // [MAX_ROUNDS]
 constexpr int C_BFS_ROUND = C_COUNT + 2 * MAX_ROUNDS;  // [MAX_ROUNDS]
-constexpr int C_TOTAL = C_COUNT + 3 * MAX_ROUNDS;
+// root finding on deep forests: per-round activity flags of the
+// pointer-jumping rounds queued before the chase (at most 32: 2^32 > n)
+constexpr int MAX_JUMP = 32;
+constexpr int C_JUMP_ROUND = C_COUNT + 3 * MAX_ROUNDS;  // [MAX_JUMP]
+constexpr int C_TOTAL = C_COUNT + 3 * MAX_ROUNDS + MAX_JUMP;
 // statistics of the small-graph engine (it runs beside the chain, whose
 // kernels use C_NER and C_NR as list lengths)
 constexpr int C_SNER = C_COUNT + 8;
@@ -237,6 +241,8 @@ constexpr int C_SNCROSS = C_COUNT + 9;
 constexpr int C_SNR = C_COUNT + 10;
 // the long-path pass: every long path's start has reached its root
 constexpr int C_LP_DONE = C_COUNT + 11;
+// root finding: some chase took more than DEEP_STEPS steps (the forest is deep)
+constexpr int C_DEEP = C_COUNT + 12;
 
 // Grid sizes.  Workgroups are dispatched at about 200-270 per microsecond
 // across the chip, so a kernel of many short workgroups is bound by
@@ -278,6 +284,9 @@ void launch_dedupe(const Dev &d, hipStream_t s);  // repeated pairs inside the b
 void launch_prepare(const Dev &d, bool del, hipStream_t s);  // with rep <- parent when del
 void launch_register(const Dev &d, hipStream_t s);
 void launch_insert_emit(const Dev &d, hipStream_t s);
+// pointer-jumping rounds over rep before the chase (deep forests); a round
+// after one that changed nothing exits at once
+void launch_rep_jump(const Dev &d, int rounds, hipStream_t s);
 void launch_rep_chase(const Dev &d, hipStream_t s);
 void launch_sweep_base(const Dev &d, hipStream_t s);
 void launch_orphan_plan(const Dev &d, hipStream_t s);  // block prefixes, totals and scan mode

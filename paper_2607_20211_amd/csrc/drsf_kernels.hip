@@ -575,6 +575,34 @@ __global__ __launch_bounds__(BLOCK) void k_insert_emit(Dev d) {
 #endif
 constexpr int REP_CH = DRSF_REP_CH;
 constexpr int PUBLISH_AFTER = 4;  // steps before a chase publishes its progress (short chains never do)
+constexpr int64_t DEEP_STEPS = 1024;  // a chase longer than this marks the forest deep
+
+// One round of pointer jumping over the listed vertex blocks (Alg. 1's own
+// root finding), queued before the chase on a forest found deep: rep[v] <-
+// rep[rep[v]], in place (every value read is an ancestor of v, so a value
+// another thread has just written only jumps further).  Round k runs only
+// if round k - 1 changed some entry; after ceil(log2 depth) rounds every
+// entry is a root and the chase takes one step per vertex.
+__global__ __launch_bounds__(BLOCK) void k_rep_jump(Dev d, int k) {
+    if (stopped(d) || !d.ctl->has_del) return;
+    if (k > 0 && !d.cnt[C_JUMP_ROUND + k - 1]) return;
+    const int64_t nb = (d.n + BLOCK - 1) / BLOCK;
+    const int64_t nvl_list = d.ctl->nvl;  // read once: stores below may alias it
+    bool changed = false;
+    for (int64_t j = blockIdx.x;; j += gridDim.x) {
+        const int64_t blk = list_block(d.vlist, nvl_list, j, nb);
+        if (blk < 0) break;
+        const int64_t v = blk * BLOCK + threadIdx.x;
+        if (v >= d.n) continue;
+        const int32_t x = ld_relaxed(&d.rep[v]);
+        const int32_t y = ld_relaxed(&d.rep[x]);
+        if (y != x) {
+            d.rep[v] = y;
+            changed = true;
+        }
+    }
+    if (__ballot(changed) != 0 && lane_id() == 0) d.cnt[C_JUMP_ROUND + k] = 1;
+}
 __global__ __launch_bounds__(BLOCK) void k_rep_chase(Dev d) {
     if (stopped(d) || !d.ctl->has_del) return;
     const int64_t nb = (d.n + BLOCK - 1) / BLOCK;
@@ -595,7 +623,8 @@ __global__ __launch_bounds__(BLOCK) void k_rep_chase(Dev d) {
             x[k] = live[k] ? ld_relaxed(&d.rep[v[k]]) : 0;
             lab[k] = live[k] ? d.label[v[k]] : 0;
         }
-        for (int64_t steps = 0;; steps++) {
+        int64_t steps = 0;
+        for (;; steps++) {
             int32_t y[REP_CH];
 #pragma unroll
             for (int k = 0; k < REP_CH; k++) y[k] = act[k] ? ld_relaxed(&d.rep[x[k]]) : x[k];
@@ -613,6 +642,9 @@ __global__ __launch_bounds__(BLOCK) void k_rep_chase(Dev d) {
                 break;
             }
         }
+        // a long chase tells the host that the forest is deep (one store per
+        // wave, and only then): its later deletes queue jumping rounds first
+        if (__ballot(steps > DEEP_STEPS) != 0 && lane_id() == 0) d.cnt[C_DEEP] = 1;
         bool orphan[REP_CH];
         int32_t t[REP_CH], tk[REP_CH];
         uint32_t us[REP_CH], ls[REP_CH];
@@ -2243,7 +2275,8 @@ __global__ __launch_bounds__(BLOCK) void k_cleanup(Dev d) {
                            __HIP_MEMORY_SCOPE_SYSTEM);
     if (!fin) return;
     const int t = threadIdx.x;
-    if (t < C_TOTAL && t != C_NDELTA) d.cnt[t] = 0;
+    for (int u = t; u < C_TOTAL; u += BLOCK)
+        if (u != C_NDELTA) d.cnt[u] = 0;
     for (int64_t g = threadIdx.x; g < d.ctl->ngraph; g += BLOCK) d.gstat[g] = 0;
     if (t == 0) {
         d.status[0] = 0;
@@ -2278,6 +2311,10 @@ void launch_register(const Dev &d, hipStream_t s) {
 }
 void launch_insert_emit(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_insert_emit, dim3((unsigned)insert_regions(d.lb)), dim3(BLOCK), 0, s, d);
+}
+void launch_rep_jump(const Dev &d, int rounds, hipStream_t s) {
+    for (int k = 0; k < std::min(rounds, MAX_JUMP); k++)
+        hipLaunchKernelGGL(k_rep_jump, dim3(grid_for(d.nvb, 1, GRID_CAP)), dim3(BLOCK), 0, s, d, k);
 }
 void launch_rep_chase(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_rep_chase, dim3(grid_for(d.nvb, REP_CH, GRID_CAP)), dim3(BLOCK), 0, s, d);

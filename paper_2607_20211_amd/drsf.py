@@ -67,7 +67,8 @@ class drsf_view(ctypes.Structure):
                 ("num_orphans", ctypes.c_int64),
                 ("orphan_slots", ctypes.c_int64),
                 ("scan_orphans", ctypes.c_int32),
-                ("host_finished", ctypes.c_int32)]
+                ("host_finished", ctypes.c_int32),
+                ("jump_rounds", ctypes.c_int32)]
 
 
 class DrsfError(RuntimeError):
@@ -548,7 +549,7 @@ class Forest:
                 "num_replacement": v.num_replacement, "num_pieces": v.num_pieces,
                 "num_paths": v.num_paths, "num_orphans": v.num_orphans,
                 "orphan_slots": v.orphan_slots, "scan_orphans": v.scan_orphans,
-                "host_finished": v.host_finished}
+                "host_finished": v.host_finished, "jump_rounds": v.jump_rounds}
 
     def parent(self) -> np.ndarray:
         p = np.empty(self.n, dtype=np.int32)

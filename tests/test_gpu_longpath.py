@@ -128,3 +128,83 @@ def test_create_reroots_a_long_chain():
     for device in (False, True):
         pair = Pair(g, device=device, max_batch=8)  # compares with the oracle's canonical forest
         pair.gpu.close()
+
+
+def _chain_steps(L):
+    """Updates on one chain of L vertices whose chases are long: close the
+    ring, cut it a quarter down, cut the closing edge, close it again,
+    restore the cut edge, cut it halfway."""
+    drsf = _lib()
+    q = L // 4
+    return [("close the ring", drsf.DRSF_INSERT, [(0, L - 1)]),
+            ("cut a quarter down", drsf.DRSF_DELETE, [(q, q + 1)]),
+            ("cut the closing edge", drsf.DRSF_DELETE, [(0, L - 1)]),
+            ("close the ring again", drsf.DRSF_INSERT, [(L - 1, 0)]),
+            ("restore the cut", drsf.DRSF_INSERT, [(q, q + 1)]),
+            ("cut halfway", drsf.DRSF_DELETE, [(L // 2, L // 2 + 1)])]
+
+
+def test_deep_root_finding_queues_jumping_rounds():
+    """Root finding on a chain 2^21 deep: the first delete's chases are long,
+    so the context queues pointer-jumping rounds before the chase of every
+    later delete (drsf_view.jump_rounds > 0); every update bit-exact."""
+    L = 1 << 21
+    g = _chains(1, L)
+    _case(f"deep root finding: one chain of {L}")
+    pair = Pair(g, device=True, max_batch=8)
+    deletes = []
+    for what, op, e in _chain_steps(L):
+        st, _ = pair.step(np.array(e, np.int32), op, what)
+        if op == _lib().DRSF_DELETE:
+            deletes.append(st["jump_rounds"])
+    assert deletes[0] == 0 and all(j > 0 for j in deletes[1:]), deletes
+    pair.gpu.close()
+
+
+def test_deep_chains_queued_two_in_flight():
+    """The same updates queued two deep (drsf_apply_async): the context
+    switches to jumping rounds while an update is queued behind the one
+    that found the forest deep; statuses and final arrays as the oracle's."""
+    import torch
+    import oracle
+    drsf = _lib()
+    dev = torch.device("cuda:0")
+    L = 1 << 20
+    g = _chains(1, L)
+    steps = _chain_steps(L)
+    r = oracle.apply(g.n, g.keys, g.parent, np.zeros((0, 2), np.int32), oracle.DELETE)
+    keys, par, lab = g.keys, r.parent, r.label
+    for _, op, e in steps:
+        r = oracle.apply(g.n, keys, par, np.array(e, np.int32), oracle.INSERT if op == drsf.DRSF_INSERT
+                         else oracle.DELETE, label=lab)
+        keys, par, lab = r.keys, r.parent, r.label
+    _case(f"deep chains queued: one chain of {L}")
+    stream = torch.cuda.Stream(dev)
+    with torch.cuda.stream(stream):
+        t = [torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (g.row_ptr, g.col, g.parent)]
+        dbat = [torch.tensor(e, dtype=torch.int32, device=dev) for _, _, e in steps]
+    f = drsf.Forest(g.n, *t, inputs_on_device=True, stream=stream.cuda_stream, max_batch=8)
+    got = []
+    f.apply_async(dbat[0], steps[0][1])
+    for j in range(1, len(steps)):
+        f.apply_async(dbat[j], steps[j][1])
+        got.append(f.wait())
+    got.append(f.wait())  # each wait raises unless its update succeeded
+    assert np.array_equal(f.label(), lab) and np.array_equal(f.parent(), par)
+    assert got[-1]["jump_rounds"] > 0, got[-1]
+    f.close()
+
+
+def test_deep_chains_in_a_multi_graph_context():
+    """Three chains of 2^19 side by side in one multi-graph context, deleted
+    and re-inserted together: jumping rounds over the deleting graphs'
+    vertex blocks; every graph bit-exact with the oracle run on it alone."""
+    from test_gpu_multi import MultiPair
+    drsf = _lib()
+    L = 1 << 19
+    graphs = [_chains(1, L) for _ in range(3)]
+    _case(f"deep chains, multi-graph: 3 chains of {L}")
+    pair = MultiPair(graphs, max_batch=32, launch_mode=0)
+    for what, op, e in _chain_steps(L):
+        pair.step([np.array(e, np.int32)] * 3, np.full(3, op, np.int8), what)
+    pair.gpu.close()
