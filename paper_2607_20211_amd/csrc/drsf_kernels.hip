@@ -575,7 +575,10 @@ __global__ __launch_bounds__(BLOCK) void k_insert_emit(Dev d) {
 #endif
 constexpr int REP_CH = DRSF_REP_CH;
 constexpr int PUBLISH_AFTER = 4;  // steps before a chase publishes its progress (short chains never do)
-constexpr int64_t DEEP_STEPS = 1024;  // a chase longer than this marks the forest deep
+#ifndef DRSF_DEEP_STEPS
+#define DRSF_DEEP_STEPS 1024
+#endif
+constexpr int64_t DEEP_STEPS = DRSF_DEEP_STEPS;  // a chase longer than this marks the forest deep
 
 // One round of pointer jumping over the listed vertex blocks (Alg. 1's own
 // root finding), queued before the chase on a forest found deep: rep[v] <-
