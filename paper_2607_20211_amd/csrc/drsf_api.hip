@@ -160,6 +160,9 @@ struct drsf_ctx {
     // pointer-jumping rounds queued before root finding's chase: 0 until a
     // delete finds the forest deep (a chase of more than DEEP_STEPS steps)
     int jump_rounds = 0;
+    // the super-forest's Euler tour queued after the search (it skips itself
+    // when the search sufficed): set once an update needed it (tuning 0)
+    bool lr_queued = false;
     // status word, counters and per-graph batch status share one allocation
     // so that one copy returns them: status at word 0, counters from word 1,
     // gstat after the counters
@@ -1036,6 +1039,10 @@ int sg_reduce(drsf_ctx *c, const Dev &d, hipStream_t s) {
     return DRSF_OK;
 }
 
+// List-ranking rounds of the super-forest's Euler tour: enough for a tour
+// of every piece the context can register.
+int tour_rounds(const drsf_ctx *c) { return std::min(ceil_log2(2 * c->pcap + 2) + 2, MAX_ROUNDS); }
+
 // The update sequence (see the file comment) for batches with inserts
 // (kind bit 1) and/or deletes (kind bit 2); with events when profiling.
 // kc: the control block, passed with the first kernel when the sequence is
@@ -1117,6 +1124,7 @@ void enqueue_update(drsf_ctx *c, int kind, bool profile, const Ctl *kc) {
     launch_sf_root(d, s);
     launch_sf_bfs(d, 0, c->bfs_fast, s);
     launch_orient_bfs(d, c->bfs_fast, s);
+    if (c->lr_queued) launch_superforest_lr(d, tour_rounds(c), c->bfs_fast, s);
     mark(PH_FINISH);
     const bool et = c->opts.reverse_mode == 1;
     if (et && launch_et_reverse(d, c->et_tmp, c->et_tmp_bytes, s))
@@ -1166,7 +1174,7 @@ int continue_update(drsf_ctx *c) {
     const int64_t np_max = c->pcap;
     // each round at least halves the components that still have a live edge
     const int bor_bound = std::min(c->round_base + ceil_log2(np_max + 2) + 2, MAX_ROUNDS);
-    const int lr_rounds = std::min(ceil_log2(2 * np_max + 2) + 2, MAX_ROUNDS);
+    const int lr_rounds = tour_rounds(c);
     // the counters the update handed over: orientation done means only
     // long paths are left (the walks ran, and the labels)
     const unsigned long long *k = c->h_ret + 1;
@@ -1215,7 +1223,7 @@ int continue_update(drsf_ctx *c) {
             bfs_done = f[2] == 0;
         }
         if (bfs_done) launch_orient_bfs(d, lv, s);
-        else launch_superforest_lr(d, lr_rounds, s);  // deep super-trees: Euler tour
+        else launch_superforest_lr(d, lr_rounds, lv, s);  // deep super-trees: Euler tour
         const bool et = c->opts.reverse_mode == 1;
         if (et && launch_et_reverse(d, c->et_tmp, c->et_tmp_bytes, s))
             launch_fill_i32(c->status, 1, ST_ROUND_BOUND, s);
@@ -1246,6 +1254,11 @@ int continue_update(drsf_ctx *c) {
         }
         if ((how & 2) && bfs_done && c->opts.levels_queued <= 0 && lv > c->bfs_fast) {
             c->bfs_fast = std::min(lv, BFS_MAX);
+            grew = true;
+        }
+        // deeper than the levels may grow: queue the tour itself
+        if ((how & 2) && !bfs_done && c->opts.levels_queued <= 0 && !c->lr_queued) {
+            c->lr_queued = true;
             grew = true;
         }
         if (grew) drop_graphs(c);

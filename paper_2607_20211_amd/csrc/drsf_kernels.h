@@ -300,7 +300,9 @@ void launch_boruvka(const Dev &d, int r0, int r1, int64_t units, bool emit, hipS
 void launch_sf_root(const Dev &d, hipStream_t s);
 void launch_sf_bfs(const Dev &d, int l0, int l1, hipStream_t s);
 void launch_orient_bfs(const Dev &d, int levels, hipStream_t s);
-void launch_superforest_lr(const Dev &d, int lr_rounds, hipStream_t s);
+// the super-forest's Euler tour when the search of `levels` levels did not
+// finish (skips itself otherwise)
+void launch_superforest_lr(const Dev &d, int lr_rounds, int levels, hipStream_t s);
 // label kernels of the ops present (delete labels run first)
 void launch_finish(const Dev &d, bool ins, bool del, bool rev, hipStream_t s);  // path reversal and labels
 // Buffers of the pass that turns the paths too long for one thread's walk

@@ -1665,9 +1665,17 @@ __global__ __launch_bounds__(BLOCK) void k_orient_bfs(Dev d, int levels) {
 }
 
 // Fallback for deep super-trees: Euler tour of the super-forest and list
-// ranking (Alg. 2, Eulerian tour step).  Arc lists per piece:
-__global__ __launch_bounds__(BLOCK) void k_sf_arcs(Dev d) {
-    if (stopped(d)) return;
+// ranking (Alg. 2, Eulerian tour step).  It runs only when the hooking
+// rounds have finished and the search's last level (levels - 1) was still
+// active (the search did not orient the pieces); the flags it tests do not
+// change while it runs, so it can be queued after the search and skips
+// itself when the search sufficed.
+__device__ __forceinline__ bool tour_needed(const Dev &d, int levels) {
+    return d.cnt[C_DONE_BOR] && d.cnt[C_BFS_ROUND + levels - 1] != 0;
+}
+// Arc lists per piece:
+__global__ __launch_bounds__(BLOCK) void k_sf_arcs(Dev d, int levels) {
+    if (stopped(d) || !tour_needed(d, levels)) return;
     const int64_t ner = (int64_t)d.cnt[C_NER];
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < ner; base += stride) {
@@ -1682,8 +1690,8 @@ __global__ __launch_bounds__(BLOCK) void k_sf_arcs(Dev d) {
 
 // Euler tour successor: after arc P->Q comes the arc following Q->P in Q's
 // cyclic arc list.  The tour of each component is cut open at its super-root.
-__global__ __launch_bounds__(BLOCK) void k_sf_succ(Dev d) {
-    if (stopped(d)) return;
+__global__ __launch_bounds__(BLOCK) void k_sf_succ(Dev d, int levels) {
+    if (stopped(d) || !tour_needed(d, levels)) return;
     const int64_t na = 2 * (int64_t)d.cnt[C_NER];
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
     for (int64_t a = (int64_t)blockIdx.x * BLOCK + threadIdx.x; a < na; a += stride) {
@@ -1701,8 +1709,8 @@ __global__ __launch_bounds__(BLOCK) void k_sf_succ(Dev d) {
 
 // List ranking by pointer jumping (Wyllie): rank = arcs left until the end
 // of the tour.  Double-buffered; round r reads buffer r&1.
-__global__ __launch_bounds__(BLOCK) void k_lr_round(Dev d, int r) {
-    if (stopped(d) || d.cnt[C_DONE_LR]) return;
+__global__ __launch_bounds__(BLOCK) void k_lr_round(Dev d, int r, int levels) {
+    if (stopped(d) || d.cnt[C_DONE_LR] || !tour_needed(d, levels)) return;
     if (r > 0 && d.cnt[C_LR_ROUND + r - 1] == 0) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             d.cnt[C_LR_FINAL] = (unsigned long long)(r & 1);
@@ -1735,8 +1743,8 @@ __global__ __launch_bounds__(BLOCK) void k_lr_round(Dev d, int r) {
 // Orientation from the tour: of the two arcs of a replacement edge the one
 // met first (larger rank) points from parent piece to child piece; the rest
 // as in k_orient_bfs.
-__global__ __launch_bounds__(BLOCK) void k_orient_lr(Dev d, int lr_rounds) {
-    if (stopped(d)) return;
+__global__ __launch_bounds__(BLOCK) void k_orient_lr(Dev d, int lr_rounds, int levels) {
+    if (stopped(d) || !tour_needed(d, levels)) return;
     const int64_t ner = (int64_t)d.cnt[C_NER];
     const int64_t np = (int64_t)d.cnt[C_NP];
     int fin;
@@ -2369,14 +2377,14 @@ void launch_orient_bfs(const Dev &d, int levels, hipStream_t s) {
     hipLaunchKernelGGL(k_orient_bfs, dim3(grid_for(piece_bound(d), BLOCK, SMALL_CAP)), dim3(BLOCK), 0, s, d,
                        levels);
 }
-void launch_superforest_lr(const Dev &d, int lr_rounds, hipStream_t s) {
+void launch_superforest_lr(const Dev &d, int lr_rounds, int levels, hipStream_t s) {
     const int ga = grid_for(2 * d.ercap, BLOCK, SMALL_CAP);
-    hipLaunchKernelGGL(k_sf_arcs, dim3(grid_for(d.ercap, BLOCK, SMALL_CAP)), dim3(BLOCK), 0, s, d);
-    hipLaunchKernelGGL(k_sf_succ, dim3(ga), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_sf_arcs, dim3(grid_for(d.ercap, BLOCK, SMALL_CAP)), dim3(BLOCK), 0, s, d, levels);
+    hipLaunchKernelGGL(k_sf_succ, dim3(ga), dim3(BLOCK), 0, s, d, levels);
     for (int r = 0; r < lr_rounds; r++)
-        hipLaunchKernelGGL(k_lr_round, dim3(ga), dim3(BLOCK), 0, s, d, r);
+        hipLaunchKernelGGL(k_lr_round, dim3(ga), dim3(BLOCK), 0, s, d, r, levels);
     hipLaunchKernelGGL(k_orient_lr, dim3(grid_for(d.ercap + d.pcap, BLOCK, SMALL_CAP)), dim3(BLOCK), 0, s,
-                       d, lr_rounds);
+                       d, lr_rounds, levels);
 }
 void launch_reverse_all(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_reverse_all, dim3(grid_for(d.pathcap, BLOCK, 2048)), dim3(BLOCK), 0, s, d);

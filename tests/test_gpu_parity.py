@@ -622,25 +622,36 @@ def test_rmat22_full_size_step(sweep_mode, device):
     pair.gpu.close()
 
 
-def test_deep_super_tree_uses_euler_tour_fallback():
+@pytest.mark.parametrize("launch_mode", [2, 1])
+def test_deep_super_tree_uses_euler_tour_fallback(launch_mode):
     """A path with skip edges (i, i+2); deleting every 10th path edge leaves a
     chain of pieces joined only through neighbouring pieces, so the
     super-forest is a path ~100 pieces deep: deeper than the breadth-first
-    levels tried first, which exercises the Euler-tour and list-ranking path."""
+    levels tried first, which exercises the Euler-tour and list-ranking path.
+    The first such delete is finished by the host (the tour after the
+    search levels); the context then queues the tour after the search, so a
+    second deep delete (the pieces cut again between their ends) finishes
+    on the device (kernel by kernel or in a captured graph), bit-exact."""
     drsf = _lib()
-    _case("deep super-tree")
+    _case(f"deep super-tree, launch mode {launch_mode}")
     n = 1000
     edges = [(i, i + 1) for i in range(n - 1)] + [(i, i + 2) for i in range(n - 2)]
     keys = np.array(sorted((u << 32) | v for u, v in edges), np.uint64)
     row_ptr, col = gen.keys_to_csr(n, keys)
     parent = np.array([0] + list(range(n - 1)), np.int32)  # the path rooted at 0
     g = gen.Graph("chain", n, keys, row_ptr, col, parent)
-    pair = Pair(g, max_batch=256)
+    pair = Pair(g, max_batch=256, launch_mode=launch_mode)
     batch = np.array([(i, i + 1) for i in range(9, n - 1, 10)], np.int32)
     st, ost = pair.step(batch, drsf.DRSF_DELETE, "chain delete")
     assert ost["n_repl"] == len(batch)
-    # and the reverse direction: re-insert, then delete the skip edges' partners
+    assert st["host_finished"] & 2, st
+    again = np.array([(i, i + 1) for i in range(4, n - 1, 10)], np.int32)
+    st, ost = pair.step(again, drsf.DRSF_DELETE, "chain delete between the cuts")
+    assert ost["n_repl"] == len(again)
+    assert st["host_finished"] == 0, st
+    # and the reverse direction: re-insert both
     pair.step(batch, drsf.DRSF_INSERT, "chain reinsert")
+    pair.step(again, drsf.DRSF_INSERT, "chain reinsert between")
     pair.gpu.close()
 
 
