@@ -104,7 +104,10 @@ typedef struct {
                                 update that the host had to finish needed */
     int levels_queued;       /* super-forest search levels placed in the graph;
                                 0 = chosen by the library: 4, raised (up to
-                                12) likewise (max 12) */
+                                12) likewise, and once an update needed more
+                                than 12 the super-forest's Euler tour is
+                                queued after them (it skips itself when the
+                                search sufficed) (max 12) */
     int reverse_mode;        /* path reversal: 0 (default) one thread walks each
                                 path; 1: Euler tour of F-hat with list ranking,
                                 start/finish times and the interval test
