@@ -161,8 +161,9 @@ struct drsf_ctx {
     // delete finds the forest deep (a chase of more than DEEP_STEPS steps)
     int jump_rounds = 0;
     // the super-forest's Euler tour queued after the search (it skips itself
-    // when the search sufficed): set once an update needed it (tuning 0)
-    bool lr_queued = false;
+    // when the search sufficed), per update kind (bit kind): set once an
+    // update of that kind needed it (tuning 0)
+    unsigned lr_kinds = 0;
     // status word, counters and per-graph batch status share one allocation
     // so that one copy returns them: status at word 0, counters from word 1,
     // gstat after the counters
@@ -1124,7 +1125,7 @@ void enqueue_update(drsf_ctx *c, int kind, bool profile, const Ctl *kc) {
     launch_sf_root(d, s);
     launch_sf_bfs(d, 0, c->bfs_fast, s);
     launch_orient_bfs(d, c->bfs_fast, s);
-    if (c->lr_queued) launch_superforest_lr(d, tour_rounds(c), c->bfs_fast, s);
+    if (c->lr_kinds & (1u << kind)) launch_superforest_lr(d, tour_rounds(c), c->bfs_fast, s);
     mark(PH_FINISH);
     const bool et = c->opts.reverse_mode == 1;
     if (et && launch_et_reverse(d, c->et_tmp, c->et_tmp_bytes, s))
@@ -1257,8 +1258,8 @@ int continue_update(drsf_ctx *c) {
             grew = true;
         }
         // deeper than the levels may grow: queue the tour itself
-        if ((how & 2) && !bfs_done && c->opts.levels_queued <= 0 && !c->lr_queued) {
-            c->lr_queued = true;
+        if ((how & 2) && !bfs_done && c->opts.levels_queued <= 0 && !(c->lr_kinds & (1u << c->kind))) {
+            c->lr_kinds |= 1u << c->kind;
             grew = true;
         }
         if (grew) drop_graphs(c);
