@@ -61,3 +61,38 @@ def test_default_opts_layout_matches_the_header():
     body = body[:body.index("} drsf_opts;")]
     fields = re.findall(r"\b(\w+)\s*;", body) + re.findall(r"\(\*(\w+)\)", body)
     assert set(fields) == {f for f, _ in drsf.drsf_opts._fields_}
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes mirrors of drsf_opts and drsf_view have the C
+    compiler's size and every field at the C offset (a mirror shorter than
+    the C struct would let the library write past the Python buffer)."""
+    import shutil
+    import subprocess
+    from paper_2607_20211_amd import drsf
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "drsf.h"', "int main(void) {"]
+    for st in (drsf.drsf_opts, drsf.drsf_view):
+        name = st.__name__
+        lines.append(f'printf("{name} sizeof %zu\\n", sizeof({name}));')
+        for f, _ in st._fields_:
+            lines.append(f'printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    want = {}
+    for line in out:
+        if line:
+            name, field, val = line.split()
+            want[(name, field)] = int(val)
+    import ctypes
+    for st in (drsf.drsf_opts, drsf.drsf_view):
+        name = st.__name__
+        assert ctypes.sizeof(st) == want[(name, "sizeof")], name
+        for f, _ in st._fields_:
+            assert getattr(st, f).offset == want[(name, f)], (name, f)
