@@ -391,9 +391,10 @@ def store_rebuild(g, dev, stream, log, drsf, b=100_000, reps=3):
 
 def run_configs(g, dev, stream, log, reps=3):
     """Per-op rates from the initial state: R-MAT 22 at b = 1e4, 1e5, 1e6
-    (inserts of uniform non-edges; deletes half tree edges), and the deep
+    (inserts of uniform non-edges; deletes half tree edges), the deep
     4096 x 4096 grid (5% of edges removed): 1e5 tree-edge deletes, then 1e5
-    inserts of uniform vertex pairs that are not edges."""
+    inserts of uniform vertex pairs that are not edges, and deep chains
+    (a long path turned by the pass or walked)."""
     import torch
     import gen
     from paper_2607_20211_amd import drsf
@@ -487,7 +488,50 @@ def run_configs(g, dev, stream, log, reps=3):
     st["speedup_delete"] = round(st["ms"] / (td * 1e3), 1)
     out["static_rebuild_grid4096"] = st
     log(f"static rebuild grid: {st}")
+    out["deep_chains"] = deep_chains(dev, stream, log, drsf)
     return out
+
+
+def deep_chains(dev, stream, log, drsf, n=1 << 22, h=65536):
+    """Deep forests: two chains of n/2 vertices (a path graph's breadth-first
+    forest is the chain itself), each closed into a ring by an insert, then
+    cut so that the far part re-attaches through the closing edge: a path of
+    h steps to turn, and root finding over chains n/2 deep.  The first cut
+    (chain A) flags the forest deep and allocates the long-path pass; the
+    second (chain B) is timed.  Once with the default walk limit (the pass
+    turns the path; pointer-jumping rounds precede the chase) and once
+    with a walk limit above h (one thread walks it); same forest by
+    digests."""
+    import torch
+    import gen
+    L = n // 2
+    i = np.arange(L - 1, dtype=np.uint64)
+    a = (i << np.uint64(32)) | (i + np.uint64(1))
+    g = gen.make_graph("chains", n, np.concatenate([a, a + ((np.uint64(L) << np.uint64(32)) | np.uint64(L))]))
+    q = L - 2 - h
+    res = {"n": n, "path_steps": h, "what": "delete whose attach path has path_steps steps, on a chain n/2 deep"}
+    digests = []
+    for name, limit in (("pass", 0), ("walk", 1 << 30)):
+        with torch.cuda.stream(stream):
+            t = [torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (g.row_ptr, g.col, g.parent)]
+            close = torch.tensor([[0, L - 1], [L, 2 * L - 1]], dtype=torch.int32, device=dev)
+            cut_a = torch.tensor([[q, q + 1]], dtype=torch.int32, device=dev)
+            cut_b = torch.tensor([[L + q, L + q + 1]], dtype=torch.int32, device=dev)
+        f = drsf.Forest(n, *t, inputs_on_device=True, stream=stream.cuda_stream, max_batch=8, walk_limit=limit)
+        f.apply(close, drsf.DRSF_INSERT)
+        first = f.apply(cut_a, drsf.DRSF_DELETE)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = f.apply(cut_b, drsf.DRSF_DELETE)
+        wall = time.perf_counter() - t1
+        digests.append([int(x) for x in f.digest()])
+        f.close()
+        res[name] = {"first_delete_host_finished": first["host_finished"], "delete_ms": round(wall * 1e3, 4),
+                     "host_finished": st["host_finished"], "jump_rounds": st["jump_rounds"]}
+    res["same_result"] = digests[0] == digests[1]
+    assert res["same_result"], "deep chains: the pass and the walk gave different forests"
+    log(f"deep chains: {res}")
+    return res
 
 
 def run_batched(nsteps, dev, stream, log, tune, small=None):
