@@ -41,6 +41,10 @@ constexpr int AUTO_ROUNDS_MAX = 12;  // queued rounds the library may grow to by
 // the doubling pass (a few kernels over all vertices, about as long as a
 // walk of this many dependent reads)
 constexpr int64_t WALK_LIMIT = 1024;
+// a forest handed to create deeper than 2^CREATE_DEEP_LOG starts with
+// jumping rounds before root finding's chase (the 4096 x 4096 grid's
+// breadth-first forest, 8191 deep, is faster without them)
+constexpr int CREATE_DEEP_LOG = 16;
 
 enum Phase { PH_VALIDATE, PH_UPDATE, PH_ROOT, PH_ORPH_LIST, PH_ORPH_SCAN, PH_SWEEP, PH_SWEEP_DELTA,
              PH_REPL, PH_ROOTING, PH_FINISH, PH_N };
@@ -870,6 +874,9 @@ int canonicalise_forest(drsf_ctx *c) {
     for (int r = 0; r < rounds; r++) {
         launch_pointer_jump(n, a, b, s);
         std::swap(a, b);
+        // a tree deeper than 2^16: deletes queue jumping rounds before
+        // root finding's chase from the first one on
+        if (r + 1 == CREATE_DEEP_LOG) launch_deeper_than(n, a, c->cnt + C_DEEP, s);
     }
     int32_t *root = a;
     if (root == c->label) {  // keep roots in rep, labels in label
@@ -889,7 +896,10 @@ int canonicalise_forest(drsf_ctx *c) {
     // paths too long for one thread's walk: the doubling pass
     HIPCHK(c, hipMemcpyAsync(c->h_ret + 1, c->cnt + C_NLONG, sizeof(unsigned long long),
                              hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_ret + 2, c->cnt + C_DEEP, sizeof(unsigned long long),
+                             hipMemcpyDeviceToHost, s));
     if ((rc = read_status(c, &st))) return rc;
+    if (!st && c->h_ret[2]) c->jump_rounds = std::min(ceil_log2(n) + 1, MAX_JUMP);
     if (!st && c->h_ret[1] > 0 && (rc = reverse_long_paths(c, d, (int64_t)c->h_ret[1], s))) return rc;
     if ((rc = read_status(c, &st))) return rc;
     if (st) return fail(c, DRSF_E_DEVICE, "re-rooting failed (status %d)", st);

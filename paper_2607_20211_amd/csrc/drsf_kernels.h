@@ -401,6 +401,8 @@ void launch_tile_k(const uint32_t *zptr, int64_t nz, int64_t eb, int32_t *tile_k
 void launch_forest_check(int32_t n, const uint32_t *bptr, const int32_t *bcol,
                          const int32_t *parent, int32_t *status, int check_edges, hipStream_t s);
 void launch_pointer_jump(int32_t n, const int32_t *in, int32_t *out, hipStream_t s);
+// flag = 1 if some jump[v] is not a root (jump: the ancestors 2^k steps up)
+void launch_deeper_than(int32_t n, const int32_t *jump, unsigned long long *flag, hipStream_t s);
 void launch_roots_check(int32_t n, const int32_t *parent, const int32_t *root,
                         int32_t *status, hipStream_t s);
 void launch_span_check(const Dev &d, const int32_t *root, hipStream_t s);

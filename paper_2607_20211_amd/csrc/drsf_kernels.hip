@@ -2966,6 +2966,22 @@ void launch_pointer_jump(int32_t n, const int32_t *in, int32_t *out, hipStream_t
     hipLaunchKernelGGL(k_pointer_jump, dim3(grid_for(n, BLOCK, GRID_CAP)), dim3(BLOCK), 0, s, n, in, out);
 }
 
+// After k synchronous rounds jump[v] is the ancestor 2^k steps up (capped
+// at the root): some jump[v] that is not a root means a vertex deeper than
+// 2^k (one store per wave that finds one).
+__global__ void k_deeper_than(int32_t n, const int32_t *jump, unsigned long long *flag) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    bool deep = false;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        const int32_t a = jump[v];
+        deep = deep || jump[a] != a;
+    }
+    if (__ballot(deep) != 0 && lane_id() == 0) *flag = 1;
+}
+void launch_deeper_than(int32_t n, const int32_t *jump, unsigned long long *flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_deeper_than, dim3(grid_for(n, BLOCK, GRID_CAP)), dim3(BLOCK), 0, s, n, jump, flag);
+}
+
 // after enough jumping rounds every vertex of a tree points at its root; a
 // vertex on or below a cycle does not
 __global__ void k_roots_check(int32_t n, const int32_t *parent, const int32_t *root,

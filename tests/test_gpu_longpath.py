@@ -145,20 +145,27 @@ def _chain_steps(L):
 
 
 def test_deep_root_finding_queues_jumping_rounds():
-    """Root finding on a chain 2^21 deep: the first delete's chases are long,
-    so the context queues pointer-jumping rounds before the chase of every
-    later delete (drsf_view.jump_rounds > 0); every update bit-exact."""
-    L = 1 << 21
-    g = _chains(1, L)
-    _case(f"deep root finding: one chain of {L}")
-    pair = Pair(g, device=True, max_batch=8)
-    deletes = []
-    for what, op, e in _chain_steps(L):
-        st, _ = pair.step(np.array(e, np.int32), op, what)
-        if op == _lib().DRSF_DELETE:
-            deletes.append(st["jump_rounds"])
-    assert deletes[0] == 0 and all(j > 0 for j in deletes[1:]), deletes
-    pair.gpu.close()
+    """Root finding on deep forests.  A chain 2^21 deep handed to create is
+    found deeper than 2^16 there, so every delete runs pointer-jumping rounds
+    before the chase (drsf_view.jump_rounds > 0).  Chains of 2^16 vertices
+    (depth just below that bound) start without them; a chase of more than
+    1024 steps would add them for later deletes.  Every update is
+    bit-exact."""
+    drsf = _lib()
+    for L, first in ((1 << 21, True), (1 << 16, False)):
+        g = _chains(2, L)
+        _case(f"deep root finding: two chains of {L}")
+        pair = Pair(g, device=True, max_batch=8)
+        deletes = []
+        for what, op, e in _chain_steps(L):
+            e2 = np.array(e + [(u + L, v + L) for u, v in e], np.int32)  # the same on both chains
+            st, _ = pair.step(e2, op, what)
+            if op == drsf.DRSF_DELETE:
+                deletes.append(st["jump_rounds"])
+        assert (deletes[0] > 0) == first, (L, deletes)
+        if first:
+            assert all(j > 0 for j in deletes), deletes
+        pair.gpu.close()
 
 
 def test_deep_chains_queued_two_in_flight():
