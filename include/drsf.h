@@ -220,7 +220,8 @@ typedef struct {
                                  finding's chase that changed an entry; a
                                  context queues such rounds once a chase has
                                  found its forest deep (more than 1024
-                                 steps), 0 before */
+                                 steps) or create found a tree deeper than
+                                 2^16, 0 before */
 } drsf_view;
 
 /*
