@@ -462,6 +462,10 @@ def test_reverse_mode_rejects_unknown_value():
     with pytest.raises(drsf.DrsfError) as ei:
         drsf.Forest(g.n, g.row_ptr, g.col, g.parent, replacement_mode=-1)
     assert ei.value.code == drsf.DRSF_E_ARG
+    for bad in (dict(launch_mode=3), dict(walk_limit=-1)):
+        with pytest.raises(drsf.DrsfError) as ei:
+            drsf.Forest(g.n, g.row_ptr, g.col, g.parent, **bad)
+        assert ei.value.code == drsf.DRSF_E_ARG, bad
 
 
 def test_invalid_batches_leave_state_unchanged():
